@@ -1,0 +1,159 @@
+/*
+ * cfmm -- complex-coordinate fast multipole method on MI355X (gfx950).
+ *
+ * Evaluates the discrete single-layer sum of the complex-coordinate FMM
+ * paper (Sec. 2.3, the M-body sum)
+ *
+ *     u(x_i) = sum_{j != i} G(x_i, x_j) sigma_j ,   i = 0 .. n-1
+ *
+ * at complex points x in C^d (targets = sources, self term excluded), with
+ * the complexified distance r = sqrt(sum_d (x_{i,d} - x_{j,d})^2) on the
+ * principal branch (Sec. 2.1; complex polar / spherical coordinates of
+ * Sec. 3.1).  Kernels:
+ *
+ *     dim 2, CFMM_HELMHOLTZ :  G = (i/4) H0^(1)(kappa r)        (Sec. 4.3)
+ *     dim 3, CFMM_LAPLACE   :  G = 1 / (4 pi r)                 (Sec. 5.2)
+ *     dim 3, CFMM_HELMHOLTZ :  G = exp(i kappa r) / (4 pi r)    (Sec. 5.3)
+ *
+ * The method (Sec. 6): an adaptive level-restricted tree on the real parts of
+ * the points (a Morton sort), complexified box centres, Lists 1-4, and the
+ * eight FMM steps (P2M, M2M, P2P, M2L, M2P, P2L, L2L, L2P) with analytically
+ * continued expansions.  Everything on the hot path runs as HIP kernels.
+ *
+ * Geometry: the imaginary parts must be a Lipschitz function of the real
+ * parts with constant L < 1 (Sec. 4.1, Sec. 5.1); the configurations this
+ * library is validated on have L <= 0.5.
+ *
+ * Memory: all arrays are owned by the caller.  Complex values are complex128
+ * (interleaved re, im doubles, the numpy / torch layout).  A plan copies the
+ * points, so the caller may free them once cfmm_plan returns.  cfmm_eval only
+ * borrows density and potential until the work it enqueued completes
+ * (call cfmm_sync or synchronise the stream).
+ *
+ * Errors: every function returns 0 on success or a negative CFMM_E* code;
+ * nothing throws across this interface.  cfmm_last_error() returns a message
+ * for the calling thread's last failure.
+ *
+ * Threading: one plan is used by one stream at a time; distinct plans may run
+ * concurrently.  Given the same plan and density, cfmm_eval is bitwise
+ * reproducible (no floating-point atomics).
+ */
+#ifndef CFMM_H
+#define CFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CFMM_OK 0
+#define CFMM_EINVAL (-1)     /* bad dim / kernel / kappa / tol / n / pointer */
+#define CFMM_ENOTSUP (-2)    /* combination not supported (e.g. 2D Laplace) */
+#define CFMM_EGEOMETRY (-3)  /* non-finite coordinates, or Re r^2 <= 0 in a near pair */
+#define CFMM_ENOMEM (-4)     /* device allocation failed */
+#define CFMM_EHIP (-5)       /* a HIP runtime call failed (message has the HIP error) */
+#define CFMM_ERANGE (-6)     /* an expansion length beyond the supported maximum */
+
+typedef struct cfmm_plan_s* cfmm_plan_t;
+
+typedef enum { CFMM_LAPLACE = 0, CFMM_HELMHOLTZ = 1 } cfmm_kernel;
+typedef enum { CFMM_FP64 = 0, CFMM_MIXED = 1 } cfmm_precision;
+
+typedef struct {
+    int dim;                   /* 2 or 3 */
+    int kernel;                /* cfmm_kernel */
+    double wavenumber;         /* kappa > 0 for Helmholtz; ignored for Laplace */
+    double tol;                /* requested relative accuracy, 1e-15 < tol < 1 */
+    int64_t n;                 /* number of points, 1 <= n < 2^31 */
+    const void* points;        /* complex128[n][dim], row-major */
+    int points_on_device;      /* 1: device pointer, 0: host pointer */
+    int precision;             /* cfmm_precision: FP64, or FP32 near field (MIXED) */
+    void* stream;              /* hipStream_t for all work; NULL: the null stream */
+    int leaf_size;             /* N_s, max points per leaf (Sec. 6.1); 0: default */
+    int separation;            /* k in {1, 2} (Sec. 6.2, Sec. 6.5); 0: 1 */
+} cfmm_plan_desc;
+
+/* Build a plan: sort, tree, lists, centres, expansion lengths (Sec. 6.1-6.3).
+ * On success *out owns device memory until cfmm_destroy.  Synchronises the
+ * stream once (box and list counts are read back to size allocations). */
+int cfmm_plan(cfmm_plan_t* out, const cfmm_plan_desc* desc);
+
+/* One evaluation (Sec. 6.4 steps 1-8) with densities sigma:
+ *   density   : complex128[n]; potential : complex128[n], overwritten.
+ *   on_device : 1 if both pointers are device pointers (asynchronous on the
+ *               plan's stream), 0 if both are host pointers (synchronous). */
+int cfmm_eval(cfmm_plan_t plan, const void* density, void* potential, int on_device);
+
+/* Wait for all work enqueued on the plan's stream. */
+int cfmm_sync(cfmm_plan_t plan);
+
+/* Free a plan (NULL is accepted).  Synchronises its stream first. */
+int cfmm_destroy(cfmm_plan_t plan);
+
+/* Device bytes held by the plan (the resident footprint used for admission). */
+int64_t cfmm_plan_bytes(cfmm_plan_t plan);
+
+/* Message for the calling thread's last error ("" if none). */
+const char* cfmm_last_error(void);
+
+/* Plan description for tests and reporting.
+ * info[0..15] = { nbox, nleaf, nlevels, top_level, n_list1, n_list2, n_list3,
+ *                 n_list4, p2p_pairs (interactions per eval), m2l_pairs,
+ *                 max_p, dim, kernel, separation, leaf_size, precision } */
+int cfmm_plan_info(cfmm_plan_t plan, int64_t* info16);
+
+/* Expansion length of level l (0 if the level has no expansions). */
+int cfmm_plan_nterms(cfmm_plan_t plan, int level);
+
+/* Copy the integer tree to caller-owned host arrays (any may be NULL):
+ *   perm[n]  (int64: sorted position -> input index), keys[n] (uint64),
+ *   box_level, box_parent, box_child0, box_nchild, box_pbeg, box_pend [nbox]
+ *   (int32), box_prefix[nbox] (uint64). */
+int cfmm_plan_export_tree(cfmm_plan_t plan, int64_t* perm, uint64_t* keys,
+                          int32_t* box_level, int32_t* box_parent, int32_t* box_child0,
+                          int32_t* box_nchild, int32_t* box_pbeg, int32_t* box_pend,
+                          uint64_t* box_prefix);
+
+/* Copy list `which` (1..4) as CSR: offsets[nbox+1] and idx[offsets[nbox]]
+ * (int32, rows sorted).  Either pointer may be NULL; *count receives the
+ * number of entries. */
+int cfmm_plan_export_list(cfmm_plan_t plan, int which, int32_t* offsets, int32_t* idx,
+                          int64_t* count);
+
+/* Complexified box centres, complex128[nbox][dim] (Sec. 6.1). */
+int cfmm_plan_export_centers(cfmm_plan_t plan, void* centers);
+
+/* Per-stage timing: when enabled, cfmm_eval records HIP events around each
+ * stage on the plan's stream; cfmm_stage_ms reads the last evaluation's
+ * times (after cfmm_sync).  Stages: 0 gather, 1 P2M, 2 M2M, 3 M2L+P2L,
+ * 4 L2L, 5 L2P+M2P, 6 P2P (+ scatter), 7 whole eval. */
+int cfmm_set_profiling(cfmm_plan_t plan, int enable);
+int cfmm_stage_ms(cfmm_plan_t plan, int stage, double* ms);
+
+/* ---- host-side planning logic, callable without a GPU (for checking) ----
+ * The integer tree and Lists 1-4 that cfmm_plan builds from the
+ * Morton-sorted keys of the real parts (Sec. 6.1, Sec. 6.2), here from
+ * caller-supplied sorted keys (uint64[n], non-decreasing).  top is the first
+ * level that carries expansions (boxes coarser than top count as near to
+ * everything).  Free the handle with cfmm_htree_free. */
+typedef struct cfmm_htree_s* cfmm_htree_t;
+int cfmm_htree_build(cfmm_htree_t* out, int dim, int64_t n, const uint64_t* sorted_keys,
+                     int leaf_size, int separation, int top);
+/* sizes[0] = nbox, sizes[1..4] = entries of Lists 1..4, sizes[5] = levels */
+int cfmm_htree_sizes(cfmm_htree_t t, int64_t* sizes6);
+int cfmm_htree_export(cfmm_htree_t t, int32_t* box_level, int32_t* box_parent,
+                      int32_t* box_child0, int32_t* box_nchild, int32_t* box_pbeg,
+                      int32_t* box_pend, uint64_t* box_prefix);
+int cfmm_htree_export_list(cfmm_htree_t t, int which, int32_t* offsets, int32_t* idx);
+int cfmm_htree_free(cfmm_htree_t t);
+
+/* Expansion length the plan uses for boxes of width w (Sec. 6.3): the smallest
+ * n >= 1 with |H_n(kappa R) J_n(kappa r)| <= eps at n and n+1, R = (0.5+k) w,
+ * r = sqrt(2)/2 w (2D Helmholtz); pmax + 1 if none up to pmax qualifies. */
+int cfmm_nterms(int dim, int kernel, double kappa, double w, int separation, double eps, int pmax);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFMM_H */

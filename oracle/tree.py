@@ -123,7 +123,7 @@ def _near_units(ca, wa, cb, wb, k) -> bool:
     return all(2 * abs(x - y) <= k * (wa + wb) for x, y in zip(ca, cb))
 
 
-def build_tree(points: np.ndarray, leaf_size: int, sep: int = 1) -> Tree:
+def build_tree(points: np.ndarray, leaf_size: int, sep: int = 1, top_level: int = 0) -> Tree:
     """Adaptive level-restricted tree of complex points (uses Re only)."""
     pts = np.asarray(points)
     dim = pts.shape[1]
@@ -223,16 +223,21 @@ def build_tree(points: np.ndarray, leaf_size: int, sep: int = 1) -> Tree:
 
     t = Tree(dim, B, lo, D, perm, skeys, level, prefix, parent, child0, nchild,
              pbeg, pend, {})
-    t.lists = build_lists(t, sep)
+    t.lists = build_lists(t, sep, top_level)
     return t
 
 
-def build_lists(t: Tree, sep: int) -> dict:
+def build_lists(t: Tree, sep: int, top_level: int = 0) -> dict:
+    """Lists 1-4.  Boxes coarser than `top_level` carry no expansions: for the
+    lists, any pair involving such a box counts as near, so far interactions
+    start at `top_level` (List 2 there holds every non-near box of the level)."""
     nb = t.nbox
     cen = [t.center_units(b) for b in range(nb)]
     wid = [t.width_units(b) for b in range(nb)]
 
     def near(a, b):
+        if t.level[a] < top_level or t.level[b] < top_level:
+            return True
         return _near_units(cen[a], wid[a], cen[b], wid[b], sep)
 
     def kids(a):

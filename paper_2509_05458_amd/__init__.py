@@ -1,0 +1,272 @@
+"""cfmm: complex-coordinate fast multipole method on MI355X (gfx950).
+
+Thin ctypes binding over the C-ABI in include/cfmm.h: argument marshalling
+only, every step of the evaluation runs in the HIP library libcfmm.so.
+PyTorch supplies device memory and streams.  Importing this package without
+the built library raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcfmm.so")
+
+CFMM_OK = 0
+CFMM_EINVAL = -1
+CFMM_ENOTSUP = -2
+CFMM_EGEOMETRY = -3
+CFMM_ENOMEM = -4
+CFMM_EHIP = -5
+CFMM_ERANGE = -6
+
+LAPLACE = 0
+HELMHOLTZ = 1
+FP64 = 0
+MIXED = 1
+
+STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "l2p_m2p", "p2p", "eval")
+
+_ERRNAMES = {CFMM_EINVAL: "EINVAL", CFMM_ENOTSUP: "ENOTSUP", CFMM_EGEOMETRY: "EGEOMETRY",
+             CFMM_ENOMEM: "ENOMEM", CFMM_EHIP: "EHIP", CFMM_ERANGE: "ERANGE"}
+
+
+class CfmmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"cfmm error {_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("kernel", ctypes.c_int), ("wavenumber", ctypes.c_double),
+                ("tol", ctypes.c_double), ("n", ctypes.c_int64), ("points", ctypes.c_void_p),
+                ("points_on_device", ctypes.c_int), ("precision", ctypes.c_int),
+                ("stream", ctypes.c_void_p), ("leaf_size", ctypes.c_int),
+                ("separation", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libcfmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2509_05458_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32p, i64p, u64p = (ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_uint64))
+        L.cfmm_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PlanDesc)]
+        L.cfmm_eval.argtypes = [vp, vp, vp, ctypes.c_int]
+        L.cfmm_sync.argtypes = [vp]
+        L.cfmm_destroy.argtypes = [vp]
+        L.cfmm_plan_bytes.argtypes = [vp]
+        L.cfmm_plan_bytes.restype = i64
+        L.cfmm_last_error.restype = ctypes.c_char_p
+        L.cfmm_plan_info.argtypes = [vp, i64p]
+        L.cfmm_plan_nterms.argtypes = [vp, ctypes.c_int]
+        L.cfmm_plan_export_tree.argtypes = [vp, i64p, u64p, i32p, i32p, i32p, i32p, i32p, i32p, u64p]
+        L.cfmm_plan_export_list.argtypes = [vp, ctypes.c_int, i32p, i32p, i64p]
+        L.cfmm_plan_export_centers.argtypes = [vp, vp]
+        L.cfmm_set_profiling.argtypes = [vp, ctypes.c_int]
+        L.cfmm_stage_ms.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.cfmm_htree_build.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64, u64p, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int]
+        L.cfmm_htree_sizes.argtypes = [vp, i64p]
+        L.cfmm_htree_export.argtypes = [vp, i32p, i32p, i32p, i32p, i32p, i32p, u64p]
+        L.cfmm_htree_export_list.argtypes = [vp, ctypes.c_int, i32p, i32p]
+        L.cfmm_htree_free.argtypes = [vp]
+        L.cfmm_nterms.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int, ctypes.c_double, ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != CFMM_OK:
+        raise CfmmError(rc, lib().cfmm_last_error().decode())
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+class Plan:
+    """A complex-coordinate FMM plan for u_i = sum_{j != i} G(x_i, x_j) sigma_j.
+
+    points: complex128 array [n, dim] (numpy on the host, or a torch CUDA
+    tensor).  Evaluate with ``plan(sigma)`` for any number of densities.
+    """
+
+    def __init__(self, points, kernel: str = "helmholtz", kappa: float = 0.0,
+                 tol: float = 1e-6, precision: str = "fp64", leaf_size: int = 0,
+                 separation: int = 0, stream=None):
+        L = lib()
+        self._handle = ctypes.c_void_p()
+        on_dev = _is_torch(points) and points.is_cuda
+        if on_dev:
+            import torch
+            pts = points.contiguous()
+            assert pts.dtype == torch.complex128
+            n, dim = pts.shape
+            ptr = pts.data_ptr()
+        else:
+            pts = np.ascontiguousarray(points, dtype=np.complex128)
+            n, dim = pts.shape
+            ptr = pts.ctypes.data
+        self._keep = pts
+        if stream is None and on_dev:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        d = PlanDesc(dim=dim, kernel={"laplace": LAPLACE, "helmholtz": HELMHOLTZ}[kernel],
+                     wavenumber=float(kappa), tol=float(tol), n=n, points=ptr,
+                     points_on_device=1 if on_dev else 0,
+                     precision={"fp64": FP64, "mixed": MIXED}[precision],
+                     stream=stream or 0, leaf_size=int(leaf_size), separation=int(separation))
+        _check(L.cfmm_plan(ctypes.byref(self._handle), ctypes.byref(d)))
+        self._keep = None
+        self.n, self.dim, self.kernel, self.kappa, self.tol = n, dim, kernel, kappa, tol
+        self.precision = precision
+        self.stream = stream
+
+    # ----------------------------------------------------------- evaluation
+    def eval_into(self, sigma, out) -> None:
+        """Asynchronous device evaluation: sigma, out are complex128 CUDA tensors [n]."""
+        _check(lib().cfmm_eval(self._handle, sigma.data_ptr(), out.data_ptr(), 1))
+
+    def __call__(self, sigma):
+        L = lib()
+        if _is_torch(sigma):
+            import torch
+            s = sigma.contiguous()
+            assert s.dtype == torch.complex128 and s.is_cuda and s.numel() == self.n
+            out = torch.empty_like(s)
+            _check(L.cfmm_eval(self._handle, s.data_ptr(), out.data_ptr(), 1))
+            return out
+        s = np.ascontiguousarray(sigma, dtype=np.complex128).reshape(-1)
+        assert s.shape[0] == self.n
+        out = np.empty_like(s)
+        _check(L.cfmm_eval(self._handle, s.ctypes.data, out.ctypes.data, 0))
+        return out
+
+    def sync(self):
+        _check(lib().cfmm_sync(self._handle))
+
+    # -------------------------------------------------------------- queries
+    @property
+    def nbytes(self) -> int:
+        return int(lib().cfmm_plan_bytes(self._handle))
+
+    def info(self) -> dict:
+        a = np.zeros(16, dtype=np.int64)
+        _check(lib().cfmm_plan_info(self._handle, _ptr(a, ctypes.c_int64)))
+        keys = ("nbox", "nleaf", "nlevels", "top_level", "n_list1", "n_list2", "n_list3",
+                "n_list4", "p2p_pairs", "m2l_pairs", "max_p", "dim", "kernel", "separation",
+                "leaf_size", "precision")
+        return {k: int(v) for k, v in zip(keys, a)}
+
+    def nterms(self) -> list:
+        return [int(lib().cfmm_plan_nterms(self._handle, l)) for l in range(self.info()["nlevels"])]
+
+    def export_tree(self) -> dict:
+        nb = self.info()["nbox"]
+        out = {"perm": np.zeros(self.n, np.int64), "keys": np.zeros(self.n, np.uint64)}
+        for k in ("level", "parent", "child0", "nchild", "pbeg", "pend"):
+            out[k] = np.zeros(nb, np.int32)
+        out["prefix"] = np.zeros(nb, np.uint64)
+        i32 = ctypes.c_int32
+        _check(lib().cfmm_plan_export_tree(
+            self._handle, _ptr(out["perm"], ctypes.c_int64), _ptr(out["keys"], ctypes.c_uint64),
+            _ptr(out["level"], i32), _ptr(out["parent"], i32), _ptr(out["child0"], i32),
+            _ptr(out["nchild"], i32), _ptr(out["pbeg"], i32), _ptr(out["pend"], i32),
+            _ptr(out["prefix"], ctypes.c_uint64)))
+        return out
+
+    def export_list(self, which: int):
+        nb = self.info()["nbox"]
+        cnt = ctypes.c_int64()
+        _check(lib().cfmm_plan_export_list(self._handle, which, None, None, ctypes.byref(cnt)))
+        off = np.zeros(nb + 1, np.int32)
+        idx = np.zeros(max(1, cnt.value), np.int32)
+        _check(lib().cfmm_plan_export_list(self._handle, which, _ptr(off, ctypes.c_int32),
+                                           _ptr(idx, ctypes.c_int32), None))
+        return off, idx[:cnt.value]
+
+    def export_centers(self) -> np.ndarray:
+        nb = self.info()["nbox"]
+        c = np.zeros((nb, self.dim), np.complex128)
+        _check(lib().cfmm_plan_export_centers(self._handle, c.ctypes.data))
+        return c
+
+    def set_profiling(self, on: bool = True):
+        _check(lib().cfmm_set_profiling(self._handle, 1 if on else 0))
+
+    def stage_ms(self) -> dict:
+        out = {}
+        v = ctypes.c_double()
+        for i, name in enumerate(STAGES):
+            _check(lib().cfmm_stage_ms(self._handle, i, ctypes.byref(v)))
+            out[name] = v.value
+        return out
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            lib().cfmm_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ host logic
+def host_tree(dim: int, sorted_keys: np.ndarray, leaf_size: int, separation: int = 1,
+              top: int = 0) -> dict:
+    """The library's tree and Lists 1-4 from sorted Morton keys (no GPU needed)."""
+    L = lib()
+    keys = np.ascontiguousarray(sorted_keys, dtype=np.uint64)
+    h = ctypes.c_void_p()
+    _check(L.cfmm_htree_build(ctypes.byref(h), dim, keys.shape[0], _ptr(keys, ctypes.c_uint64),
+                              leaf_size, separation, top))
+    try:
+        s = np.zeros(6, np.int64)
+        _check(L.cfmm_htree_sizes(h, _ptr(s, ctypes.c_int64)))
+        nb = int(s[0])
+        out = {k: np.zeros(nb, np.int32) for k in ("level", "parent", "child0", "nchild", "pbeg", "pend")}
+        out["prefix"] = np.zeros(nb, np.uint64)
+        i32 = ctypes.c_int32
+        _check(L.cfmm_htree_export(h, _ptr(out["level"], i32), _ptr(out["parent"], i32),
+                                   _ptr(out["child0"], i32), _ptr(out["nchild"], i32),
+                                   _ptr(out["pbeg"], i32), _ptr(out["pend"], i32),
+                                   _ptr(out["prefix"], ctypes.c_uint64)))
+        for q in range(4):
+            off = np.zeros(nb + 1, np.int32)
+            idx = np.zeros(max(1, int(s[1 + q])), np.int32)
+            _check(L.cfmm_htree_export_list(h, q + 1, _ptr(off, i32), _ptr(idx, i32)))
+            out[f"L{q + 1}"] = (off, idx[:int(s[1 + q])])
+        return out
+    finally:
+        L.cfmm_htree_free(h)
+
+
+def nterms(dim: int, kernel: str, kappa: float, w: float, separation: int, eps: float,
+           pmax: int = 63) -> int:
+    """Expansion length the plan uses for boxes of width w."""
+    rc = lib().cfmm_nterms(dim, {"laplace": LAPLACE, "helmholtz": HELMHOLTZ}[kernel],
+                           float(kappa), float(w), int(separation), float(eps), int(pmax))
+    if rc < 0:
+        _check(rc)
+    return int(rc)

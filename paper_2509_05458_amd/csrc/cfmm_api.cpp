@@ -1,0 +1,630 @@
+// C-ABI of the cfmm library: plan construction (Sec. 6.1-6.3) and one
+// evaluation of the complex-coordinate FMM (the eight steps of Sec. 6.4).
+#include "../../include/cfmm.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "tree_host.hpp"
+
+#pragma clang fp contract(off)
+
+using namespace cfmm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t _e = (expr);                                                           \
+        if (_e != hipSuccess)                                                             \
+            return fail(CFMM_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));    \
+    } while (0)
+
+std::mutex g_init_mu;
+std::set<int> g_inited;
+
+int ensure_device_tables()
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    if (g_inited.count(dev)) return CFMM_OK;
+    HIPCHK(h2d_init_tables(dev));
+    g_inited.insert(dev);
+    return CFMM_OK;
+}
+
+}  // namespace
+
+struct cfmm_plan_s {
+    int dim = 0, kernel = 0, precision = 0, sep = 1, leaf_size = 64;
+    double kappa = 0.0, tol = 0.0;
+    int64_t n = 0;
+    hipStream_t stream = nullptr;
+    HostTree tree;
+    std::vector<uint64_t> keys_h;
+    std::vector<int> P;          // per level (0 below the top level)
+    std::vector<double> rs;      // per level
+    int pmax = 0;
+    double lo[3] = {0, 0, 0}, D = 1.0;
+    std::vector<double> cen_h;   // complex centres after planning: [b][d] (re, im)
+
+    std::vector<void*> allocs;
+    int64_t bytes = 0;
+
+    int* d_perm = nullptr;
+    double *d_xre = nullptr, *d_xim = nullptr, *d_sre = nullptr, *d_sim = nullptr;
+    int *d_pbeg = nullptr, *d_pend = nullptr, *d_level = nullptr, *d_parent = nullptr;
+    int *d_child0 = nullptr, *d_nchild = nullptr, *d_eoff = nullptr, *d_P = nullptr;
+    double *d_cre = nullptr, *d_cim = nullptr, *d_rs = nullptr;
+    int* d_loff[4] = {nullptr, nullptr, nullptr, nullptr};
+    int* d_lidx[4] = {nullptr, nullptr, nullptr, nullptr};
+    int* d_work = nullptr;        // all work lists, concatenated
+    int off_leaves = 0, nleaf = 0, off_p2m = 0, n_p2m = 0, off_m2l = 0, n_m2l = 0;
+    std::vector<int> m2m_off, m2m_cnt, l2l_off, l2l_cnt;   // per level
+    cplx *d_mpole = nullptr, *d_local = nullptr, *d_ufar = nullptr;
+    double *d_io_in = nullptr, *d_io_out = nullptr;       // staging for host pointers
+    int64_t info[16];
+
+    bool prof = false;
+    hipEvent_t ev[8];
+    bool ev_made = false;
+
+    template <class T>
+    int alloc(T** p, size_t count)
+    {
+        *p = nullptr;
+        if (count == 0) count = 1;
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, count * sizeof(T));
+        if (e != hipSuccess)
+            return fail(CFMM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        allocs.push_back(q);
+        bytes += (int64_t)(count * sizeof(T));
+        *p = (T*)q;
+        return CFMM_OK;
+    }
+
+    ~cfmm_plan_s()
+    {
+        if (stream) hipStreamSynchronize(stream);
+        else hipDeviceSynchronize();
+        for (void* q : allocs) hipFree(q);
+        if (ev_made)
+            for (int i = 0; i < 8; ++i) hipEventDestroy(ev[i]);
+    }
+
+    TreeView view() const
+    {
+        TreeView tv;
+        tv.nbox = tree.nbox();
+        tv.pbeg = d_pbeg; tv.pend = d_pend; tv.level = d_level; tv.parent = d_parent;
+        tv.child0 = d_child0; tv.nchild = d_nchild;
+        tv.cre = d_cre; tv.cim = d_cim; tv.eoff = d_eoff; tv.P = d_P; tv.rs = d_rs;
+        tv.l1off = d_loff[0]; tv.l1idx = d_lidx[0];
+        tv.l2off = d_loff[1]; tv.l2idx = d_lidx[1];
+        tv.l3off = d_loff[2]; tv.l3idx = d_lidx[2];
+        tv.l4off = d_loff[3]; tv.l4idx = d_lidx[3];
+        return tv;
+    }
+    PointsView pview() const
+    {
+        PointsView pv;
+        pv.n = n; pv.xre = d_xre; pv.xim = d_xim; pv.sre = d_sre; pv.sim = d_sim;
+        return pv;
+    }
+};
+
+namespace {
+
+template <class T>
+int upload(cfmm_plan_s* p, T** dst, const std::vector<T>& src)
+{
+    int rc = p->alloc(dst, src.size());
+    if (rc) return rc;
+    if (!src.empty())
+        HIPCHK(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, p->stream));
+    return CFMM_OK;
+}
+
+// expansion length of a level: smallest n with |f_n(R) g_n(r)| <= eps at n and
+// n+1 (Sec. 6.3, prefactors dropped), R = (0.5 + k) w, r = sqrt(d)/2 w
+int nterms_level(int dim, int sep, double kappa, double w, double eps, int pmax)
+{
+    double R = (0.5 + sep) * w, r = sqrt((double)dim) * 0.5 * w;
+    double prev = 1e300;
+    for (int m = 1; m <= pmax + 1; ++m) {
+        double c = h2d_nterms_crit(kappa, R, r, m);
+        if (prev <= eps && c <= eps) return m - 1 >= 1 ? m - 1 : 1;
+        prev = c;
+    }
+    return pmax + 1;
+}
+
+int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
+{
+    int rc;
+    int dim = d->dim;
+    int64_t n = d->n;
+    hipStream_t st = p->stream;
+    // -------- points onto the device
+    double* d_pts = nullptr;
+    if ((rc = p->alloc(&d_pts, (size_t)n * dim * 2))) return rc;
+    HIPCHK(hipMemcpyAsync(d_pts, d->points, (size_t)n * dim * 2 * sizeof(double),
+                          d->points_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    // -------- real bounding box (a1)
+    int nbb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    double *d_part = nullptr, *d_bb = nullptr;
+    if ((rc = p->alloc(&d_part, (size_t)nbb * (2 * dim + 1)))) return rc;
+    if ((rc = p->alloc(&d_bb, 2 * dim + 1))) return rc;
+    HIPCHK(launch_bbox(d_pts, n, dim, d_part, nbb, d_bb, st));
+    double bb[7];
+    HIPCHK(hipMemcpyAsync(bb, d_bb, (2 * dim + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bb[2 * dim] != 0.0) return fail(CFMM_EGEOMETRY, "non-finite point coordinates");
+    int B = (dim == 2) ? 31 : 21;
+    double ext = 0.0, mid[3];
+    for (int k = 0; k < dim; ++k) {
+        mid[k] = (bb[k] + bb[dim + k]) * 0.5;
+        ext = std::max(ext, bb[dim + k] - bb[k]);
+    }
+    p->D = ext > 0.0 ? ext * (1.0 + ldexp(1.0, -20)) : 1.0;
+    KeyParams kp;
+    for (int k = 0; k < 3; ++k) kp.lo[k] = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        p->lo[k] = mid[k] - 0.5 * p->D;
+        kp.lo[k] = p->lo[k];
+    }
+    kp.scale = ldexp(1.0, B) / p->D;
+    kp.top = ldexp(1.0, B) - 1.0;
+    // -------- Morton keys and sort (a1, a2)
+    uint64_t *d_keys = nullptr, *d_keys2 = nullptr;
+    int* d_idx2 = nullptr;
+    unsigned char* d_scr = nullptr;
+    if ((rc = p->alloc(&d_keys, n)) || (rc = p->alloc(&d_keys2, n)) || (rc = p->alloc(&p->d_perm, n)) ||
+        (rc = p->alloc(&d_idx2, n)) || (rc = p->alloc(&d_scr, radix_sort_scratch_bytes(n))))
+        return rc;
+    HIPCHK(launch_morton(d_pts, n, dim, kp, d_keys, p->d_perm, st));
+    HIPCHK(launch_radix_sort(d_keys, p->d_perm, d_keys2, d_idx2, n, dim * B, d_scr, st));
+    p->keys_h.resize(n);
+    HIPCHK(hipMemcpyAsync(p->keys_h.data(), d_keys, n * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    // -------- tree (a3)
+    build_topology(p->keys_h.data(), n, dim, p->leaf_size, p->sep, p->tree);
+    HostTree& t = p->tree;
+    int nb = t.nbox(), nlev = t.nlevels();
+    if ((rc = upload(p, &p->d_pbeg, t.pbeg)) || (rc = upload(p, &p->d_pend, t.pend)) ||
+        (rc = upload(p, &p->d_level, t.level)) || (rc = upload(p, &p->d_parent, t.parent)) ||
+        (rc = upload(p, &p->d_child0, t.child0)) || (rc = upload(p, &p->d_nchild, t.nchild)))
+        return rc;
+    // -------- sorted SoA points
+    if ((rc = p->alloc(&p->d_xre, (size_t)dim * n)) || (rc = p->alloc(&p->d_xim, (size_t)dim * n)))
+        return rc;
+    HIPCHK(launch_gather_points(d_pts, p->d_perm, n, dim, p->d_xre, p->d_xim, st));
+    // -------- complexified centres (a4)
+    std::vector<double> cre((size_t)dim * nb);
+    for (int b = 0; b < nb; ++b) {
+        int64_t c[3];
+        box_coords(t, b, c);
+        double h = p->D * ldexp(1.0, -(t.level[b] + 1));
+        for (int k = 0; k < dim; ++k) cre[(size_t)k * nb + b] = p->lo[k] + (2.0 * (double)c[k] + 1.0) * h;
+    }
+    double* d_delta = nullptr;
+    if ((rc = upload(p, &p->d_cre, cre)) || (rc = p->alloc(&p->d_cim, (size_t)dim * nb)) ||
+        (rc = p->alloc(&d_delta, nb)))
+        return rc;
+    HIPCHK(launch_centres(p->d_pbeg, p->d_pend, nb, n, dim, p->d_xim, p->d_cim, d_delta, st));
+    std::vector<double> delta(nb), cim((size_t)dim * nb);
+    HIPCHK(hipMemcpyAsync(delta.data(), d_delta, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(cim.data(), p->d_cim, (size_t)dim * nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    p->cen_h.resize((size_t)nb * dim * 2);
+    for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < dim; ++k) {
+            p->cen_h[((size_t)b * dim + k) * 2] = cre[(size_t)k * nb + b];
+            p->cen_h[((size_t)b * dim + k) * 2 + 1] = cim[(size_t)k * nb + b];
+        }
+    // -------- top level of the far field: the coarsest level (>= 2) whose boxes
+    // keep the imaginary spread small enough that e^{2 kappa delta} times the
+    // FP64 unit roundoff stays below tol/10 (the expansions of boxes with a
+    // large imaginary spread cancel catastrophically)
+    std::vector<double> dmax(nlev, 0.0);
+    for (int b = 0; b < nb; ++b) dmax[t.level[b]] = std::max(dmax[t.level[b]], delta[b]);
+    int top = 2;
+    if (p->kernel == CFMM_HELMHOLTZ) {
+        double tau = 0.5 * log(0.1 * p->tol / 2.2e-16);
+        while (top < nlev && p->kappa * dmax[top] > tau) ++top;
+    }
+    if (top > nlev) top = nlev;
+    // -------- lists (a5)
+    build_lists(t, top);
+    for (int q = 0; q < 4; ++q)
+        if ((rc = upload(p, &p->d_loff[q], t.off[q])) || (rc = upload(p, &p->d_lidx[q], t.idx[q])))
+            return rc;
+    // -------- expansion lengths (a6)
+    p->P.assign(nlev, 0);
+    p->rs.assign(nlev, 1.0);
+    double eps = 0.1 * p->tol;
+    int pmax = 0;
+    for (int l = top; l < nlev; ++l) {
+        double w = p->D * ldexp(1.0, -l);
+        p->rs[l] = std::min(1.0, p->kappa * w);
+        int m = nterms_level(p->dim, p->sep, p->kappa, w, eps, kPMax2D);
+        if (m > kPMax2D)
+            return fail(CFMM_ERANGE, "expansion length above the supported maximum (" +
+                                         std::to_string(kPMax2D) + ") at level " + std::to_string(l) +
+                                         "; the boxes are too many wavelengths wide");
+        p->P[l] = m;
+        pmax = std::max(pmax, m);
+    }
+    p->pmax = pmax;
+    std::vector<int> eoff(nb, -1);
+    int64_t ecount = 0;
+    for (int b = 0; b < nb; ++b)
+        if (t.level[b] >= top) {
+            eoff[b] = (int)ecount;
+            ecount += 2 * p->P[t.level[b]] + 1;
+        }
+    if (ecount > (int64_t)0x7fffffff) return fail(CFMM_ERANGE, "expansion storage above 2^31 entries");
+    if ((rc = upload(p, &p->d_eoff, eoff)) || (rc = upload(p, &p->d_P, p->P)) || (rc = upload(p, &p->d_rs, p->rs)))
+        return rc;
+    // -------- work lists
+    std::vector<int> work;
+    p->off_leaves = (int)work.size();
+    for (int b = 0; b < nb; ++b)
+        if (t.nchild[b] == 0) work.push_back(b);
+    p->nleaf = (int)work.size() - p->off_leaves;
+    p->off_p2m = (int)work.size();
+    for (int b = 0; b < nb; ++b)
+        if (t.nchild[b] == 0 && t.level[b] >= top) work.push_back(b);
+    p->n_p2m = (int)work.size() - p->off_p2m;
+    p->m2m_off.assign(nlev, 0);
+    p->m2m_cnt.assign(nlev, 0);
+    p->l2l_off.assign(nlev, 0);
+    p->l2l_cnt.assign(nlev, 0);
+    for (int l = top; l < nlev; ++l) {
+        p->m2m_off[l] = (int)work.size();
+        for (int b = t.lvl_beg[l]; b < t.lvl_beg[l + 1]; ++b)
+            if (t.nchild[b] > 0) work.push_back(b);
+        p->m2m_cnt[l] = (int)work.size() - p->m2m_off[l];
+    }
+    p->off_m2l = (int)work.size();
+    for (int b = 0; b < nb; ++b)
+        if (t.level[b] >= top) work.push_back(b);
+    p->n_m2l = (int)work.size() - p->off_m2l;
+    for (int l = top + 1; l < nlev; ++l) {
+        p->l2l_off[l] = (int)work.size();
+        for (int b = t.lvl_beg[l]; b < t.lvl_beg[l + 1]; ++b) work.push_back(b);
+        p->l2l_cnt[l] = (int)work.size() - p->l2l_off[l];
+    }
+    if ((rc = upload(p, &p->d_work, work))) return rc;
+    // -------- geometry check on the near pairs
+    int* d_flag = nullptr;
+    if ((rc = p->alloc(&d_flag, 1))) return rc;
+    HIPCHK(hipMemsetAsync(d_flag, 0, sizeof(int), st));
+    HIPCHK(launch_check_near(p->d_work + p->off_leaves, p->nleaf, p->d_pbeg, p->d_pend, p->d_loff[0],
+                             p->d_lidx[0], n, dim, p->d_xre, p->d_xim, d_flag, st));
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (flag)
+        return fail(CFMM_EGEOMETRY, "a near pair has Re(r^2) <= 0: the imaginary parts are not a "
+                                    "Lipschitz function of the real parts with constant below 1");
+    // -------- evaluation buffers
+    if ((rc = p->alloc(&p->d_sre, n)) || (rc = p->alloc(&p->d_sim, n)) ||
+        (rc = p->alloc(&p->d_mpole, ecount)) || (rc = p->alloc(&p->d_local, ecount)) ||
+        (rc = p->alloc(&p->d_ufar, n)))
+        return rc;
+    // -------- release planning scratch
+    HIPCHK(hipStreamSynchronize(st));
+    for (void* q : {(void*)d_pts, (void*)d_part, (void*)d_bb, (void*)d_keys, (void*)d_keys2,
+                    (void*)d_idx2, (void*)d_scr, (void*)d_delta, (void*)d_flag}) {
+        auto it = std::find(p->allocs.begin(), p->allocs.end(), q);
+        if (it != p->allocs.end()) {
+            p->allocs.erase(it);
+            hipFree(q);
+        }
+    }
+    p->bytes = 0;  // recount the resident footprint
+    {
+        int64_t tot = 0;
+        tot += (int64_t)n * (sizeof(int) + 2 * dim * sizeof(double) + 2 * sizeof(double) + sizeof(cplx));
+        tot += (int64_t)nb * (6 * sizeof(int) + 2 * dim * sizeof(double) + sizeof(int));
+        for (int q = 0; q < 4; ++q) tot += (int64_t)(t.off[q].size() + t.idx[q].size()) * sizeof(int);
+        tot += (int64_t)work.size() * sizeof(int) + 2 * ecount * (int64_t)sizeof(cplx);
+        p->bytes = tot;
+    }
+    // -------- description
+    int64_t p2p = 0, m2l = (int64_t)t.idx[1].size();
+    for (int b = 0; b < nb; ++b) {
+        if (t.nchild[b]) continue;
+        int64_t nt = t.pend[b] - t.pbeg[b], ns = 0;
+        for (int e = t.off[0][b]; e < t.off[0][b + 1]; ++e) {
+            int a = t.idx[0][e];
+            ns += t.pend[a] - t.pbeg[a];
+        }
+        p2p += nt * ns - nt;   // the self pairs are skipped
+    }
+    int64_t* I = p->info;
+    I[0] = nb; I[1] = p->nleaf; I[2] = nlev; I[3] = top;
+    for (int q = 0; q < 4; ++q) I[4 + q] = (int64_t)t.idx[q].size();
+    I[8] = p2p; I[9] = m2l; I[10] = pmax; I[11] = dim; I[12] = p->kernel; I[13] = p->sep;
+    I[14] = p->leaf_size; I[15] = p->precision;
+    return CFMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cfmm_plan(cfmm_plan_t* out, const cfmm_plan_desc* d)
+{
+    if (!out) return fail(CFMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(CFMM_EINVAL, "desc is NULL");
+    if (d->dim != 2 && d->dim != 3) return fail(CFMM_EINVAL, "dim must be 2 or 3");
+    if (d->kernel != CFMM_LAPLACE && d->kernel != CFMM_HELMHOLTZ) return fail(CFMM_EINVAL, "unknown kernel");
+    if (d->kernel == CFMM_HELMHOLTZ && !(d->wavenumber > 0.0 && isfinite(d->wavenumber)))
+        return fail(CFMM_EINVAL, "Helmholtz needs a finite wavenumber > 0");
+    if (!(d->tol > 1e-15 && d->tol < 1.0)) return fail(CFMM_EINVAL, "tol must lie in (1e-15, 1)");
+    if (d->n < 1 || d->n > 0x7fffffffLL) return fail(CFMM_EINVAL, "n must lie in [1, 2^31)");
+    if (!d->points) return fail(CFMM_EINVAL, "points is NULL");
+    if (d->precision != CFMM_FP64 && d->precision != CFMM_MIXED) return fail(CFMM_EINVAL, "unknown precision");
+    if (d->leaf_size < 0 || d->leaf_size > 4096) return fail(CFMM_EINVAL, "leaf_size must lie in [0, 4096]");
+    if (d->separation < 0 || d->separation > 2) return fail(CFMM_EINVAL, "separation must be 0, 1 or 2");
+    if (!(d->dim == 2 && d->kernel == CFMM_HELMHOLTZ))
+        return fail(CFMM_ENOTSUP, "supported: dim 2 Helmholtz");
+    int rc = ensure_device_tables();
+    if (rc) return rc;
+    cfmm_plan_s* p = new cfmm_plan_s();
+    p->dim = d->dim;
+    p->kernel = d->kernel;
+    p->kappa = d->kernel == CFMM_HELMHOLTZ ? d->wavenumber : 0.0;
+    p->tol = d->tol;
+    p->n = d->n;
+    p->precision = d->precision;
+    p->sep = d->separation ? d->separation : 1;
+    p->leaf_size = d->leaf_size ? d->leaf_size : 64;
+    p->stream = (hipStream_t)d->stream;
+    rc = plan_impl(p, d);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    g_err.clear();
+    return CFMM_OK;
+}
+
+int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device)
+{
+    if (!p) return fail(CFMM_EINVAL, "plan is NULL");
+    if (!density || !potential) return fail(CFMM_EINVAL, "density or potential is NULL");
+    hipStream_t st = p->stream;
+    int64_t n = p->n;
+    const double* sig = (const double*)density;
+    double* out = (double*)potential;
+    if (!on_device) {
+        if (!p->d_io_in) {
+            int rc;
+            if ((rc = p->alloc(&p->d_io_in, 2 * n)) || (rc = p->alloc(&p->d_io_out, 2 * n))) return rc;
+        }
+        HIPCHK(hipMemcpyAsync(p->d_io_in, density, 2 * n * sizeof(double), hipMemcpyHostToDevice, st));
+        sig = p->d_io_in;
+        out = p->d_io_out;
+    }
+    if (p->prof && !p->ev_made) {
+        for (int i = 0; i < 8; ++i) HIPCHK(hipEventCreate(&p->ev[i]));
+        p->ev_made = true;
+    }
+    auto mark = [&](int i) -> hipError_t { return p->prof ? hipEventRecord(p->ev[i], st) : hipSuccess; };
+    TreeView tv = p->view();
+    PointsView pv = p->pview();
+    const HostTree& t = p->tree;
+    int top = t.top, nlev = t.nlevels();
+    const int* W = p->d_work;
+    HIPCHK(mark(0));
+    HIPCHK(launch_gather_density(sig, p->d_perm, n, p->d_sre, p->d_sim, st));
+    HIPCHK(mark(1));
+    HIPCHK(h2d_p2m(W + p->off_p2m, p->n_p2m, tv, pv, p->kappa, p->d_mpole, st));
+    HIPCHK(mark(2));
+    for (int l = nlev - 2; l >= top; --l)
+        HIPCHK(h2d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], tv, p->kappa, p->d_mpole, st));
+    HIPCHK(mark(3));
+    HIPCHK(h2d_m2l(W + p->off_m2l, p->n_m2l, tv, pv, p->kappa, p->d_mpole, p->d_local, st));
+    HIPCHK(mark(4));
+    for (int l = top + 1; l < nlev; ++l)
+        HIPCHK(h2d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], tv, p->kappa, p->d_local, st));
+    HIPCHK(mark(5));
+    HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, top, std::max(1, p->pmax), tv, pv, p->kappa,
+                        p->d_mpole, p->d_local, p->d_ufar, st));
+    HIPCHK(mark(6));
+    HIPCHK(h2d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out,
+                   p->precision, st));
+    HIPCHK(mark(7));
+    if (!on_device) {
+        HIPCHK(hipMemcpyAsync(potential, p->d_io_out, 2 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    return CFMM_OK;
+}
+
+int cfmm_sync(cfmm_plan_t p)
+{
+    if (!p) return fail(CFMM_EINVAL, "plan is NULL");
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return CFMM_OK;
+}
+
+int cfmm_destroy(cfmm_plan_t p)
+{
+    delete p;
+    return CFMM_OK;
+}
+
+int64_t cfmm_plan_bytes(cfmm_plan_t p) { return p ? p->bytes : 0; }
+
+const char* cfmm_last_error(void) { return g_err.c_str(); }
+
+int cfmm_plan_info(cfmm_plan_t p, int64_t* info16)
+{
+    if (!p || !info16) return fail(CFMM_EINVAL, "NULL argument");
+    memcpy(info16, p->info, sizeof(p->info));
+    return CFMM_OK;
+}
+
+int cfmm_plan_nterms(cfmm_plan_t p, int level)
+{
+    if (!p || level < 0 || level >= (int)p->P.size()) return 0;
+    return p->P[level];
+}
+
+int cfmm_plan_export_tree(cfmm_plan_t p, int64_t* perm, uint64_t* keys, int32_t* box_level,
+                          int32_t* box_parent, int32_t* box_child0, int32_t* box_nchild,
+                          int32_t* box_pbeg, int32_t* box_pend, uint64_t* box_prefix)
+{
+    if (!p) return fail(CFMM_EINVAL, "plan is NULL");
+    const HostTree& t = p->tree;
+    size_t nb = t.level.size();
+    if (perm) {
+        std::vector<int> tmp(p->n);
+        HIPCHK(hipMemcpyAsync(tmp.data(), p->d_perm, p->n * sizeof(int), hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        for (int64_t i = 0; i < p->n; ++i) perm[i] = tmp[i];
+    }
+    if (keys) memcpy(keys, p->keys_h.data(), p->n * sizeof(uint64_t));
+    if (box_level) memcpy(box_level, t.level.data(), nb * 4);
+    if (box_parent) memcpy(box_parent, t.parent.data(), nb * 4);
+    if (box_child0) memcpy(box_child0, t.child0.data(), nb * 4);
+    if (box_nchild) memcpy(box_nchild, t.nchild.data(), nb * 4);
+    if (box_pbeg) memcpy(box_pbeg, t.pbeg.data(), nb * 4);
+    if (box_pend) memcpy(box_pend, t.pend.data(), nb * 4);
+    if (box_prefix) memcpy(box_prefix, t.prefix.data(), nb * 8);
+    return CFMM_OK;
+}
+
+int cfmm_plan_export_list(cfmm_plan_t p, int which, int32_t* offsets, int32_t* idx, int64_t* count)
+{
+    if (!p || which < 1 || which > 4) return fail(CFMM_EINVAL, "bad plan or list number");
+    const HostTree& t = p->tree;
+    if (count) *count = (int64_t)t.idx[which - 1].size();
+    if (offsets) memcpy(offsets, t.off[which - 1].data(), t.off[which - 1].size() * 4);
+    if (idx) memcpy(idx, t.idx[which - 1].data(), t.idx[which - 1].size() * 4);
+    return CFMM_OK;
+}
+
+int cfmm_plan_export_centers(cfmm_plan_t p, void* centers)
+{
+    if (!p || !centers) return fail(CFMM_EINVAL, "NULL argument");
+    memcpy(centers, p->cen_h.data(), p->cen_h.size() * sizeof(double));
+    return CFMM_OK;
+}
+
+}  // extern "C"
+
+struct cfmm_htree_s {
+    HostTree t;
+};
+
+extern "C" {
+
+int cfmm_htree_build(cfmm_htree_t* out, int dim, int64_t n, const uint64_t* keys, int leaf_size,
+                     int separation, int top)
+{
+    if (!out || !keys || (dim != 2 && dim != 3) || n < 1 || leaf_size < 1 || separation < 1 ||
+        separation > 2 || top < 0)
+        return fail(CFMM_EINVAL, "bad argument");
+    for (int64_t i = 1; i < n; ++i)
+        if (keys[i] < keys[i - 1]) return fail(CFMM_EINVAL, "keys are not sorted");
+    cfmm_htree_s* h = new cfmm_htree_s();
+    build_topology(keys, n, dim, leaf_size, separation, h->t);
+    build_lists(h->t, top);
+    *out = h;
+    return CFMM_OK;
+}
+
+int cfmm_htree_sizes(cfmm_htree_t h, int64_t* s)
+{
+    if (!h || !s) return fail(CFMM_EINVAL, "NULL argument");
+    s[0] = h->t.nbox();
+    for (int q = 0; q < 4; ++q) s[1 + q] = (int64_t)h->t.idx[q].size();
+    s[5] = h->t.nlevels();
+    return CFMM_OK;
+}
+
+int cfmm_htree_export(cfmm_htree_t h, int32_t* box_level, int32_t* box_parent, int32_t* box_child0,
+                      int32_t* box_nchild, int32_t* box_pbeg, int32_t* box_pend, uint64_t* box_prefix)
+{
+    if (!h) return fail(CFMM_EINVAL, "NULL argument");
+    const HostTree& t = h->t;
+    size_t nb = t.level.size();
+    if (box_level) memcpy(box_level, t.level.data(), nb * 4);
+    if (box_parent) memcpy(box_parent, t.parent.data(), nb * 4);
+    if (box_child0) memcpy(box_child0, t.child0.data(), nb * 4);
+    if (box_nchild) memcpy(box_nchild, t.nchild.data(), nb * 4);
+    if (box_pbeg) memcpy(box_pbeg, t.pbeg.data(), nb * 4);
+    if (box_pend) memcpy(box_pend, t.pend.data(), nb * 4);
+    if (box_prefix) memcpy(box_prefix, t.prefix.data(), nb * 8);
+    return CFMM_OK;
+}
+
+int cfmm_htree_export_list(cfmm_htree_t h, int which, int32_t* offsets, int32_t* idx)
+{
+    if (!h || which < 1 || which > 4) return fail(CFMM_EINVAL, "bad argument");
+    const HostTree& t = h->t;
+    if (offsets) memcpy(offsets, t.off[which - 1].data(), t.off[which - 1].size() * 4);
+    if (idx) memcpy(idx, t.idx[which - 1].data(), t.idx[which - 1].size() * 4);
+    return CFMM_OK;
+}
+
+int cfmm_htree_free(cfmm_htree_t h)
+{
+    delete h;
+    return CFMM_OK;
+}
+
+int cfmm_nterms(int dim, int kernel, double kappa, double w, int separation, double eps, int pmax)
+{
+    if (dim != 2 || kernel != CFMM_HELMHOLTZ || !(kappa > 0) || !(w > 0) || separation < 1 ||
+        separation > 2 || !(eps > 0) || pmax < 1 || pmax > kPMax2D)
+        return fail(CFMM_EINVAL, "bad argument");
+    return nterms_level(dim, separation, kappa, w, eps, pmax);
+}
+
+int cfmm_set_profiling(cfmm_plan_t p, int enable)
+{
+    if (!p) return fail(CFMM_EINVAL, "plan is NULL");
+    p->prof = enable != 0;
+    return CFMM_OK;
+}
+
+int cfmm_stage_ms(cfmm_plan_t p, int stage, double* ms)
+{
+    if (!p || !ms || stage < 0 || stage > 7) return fail(CFMM_EINVAL, "bad argument");
+    if (!p->ev_made) return fail(CFMM_EINVAL, "profiling was not enabled before the evaluation");
+    float f = 0.0f;
+    if (stage == 7) {
+        HIPCHK(hipEventElapsedTime(&f, p->ev[0], p->ev[7]));
+    } else {
+        HIPCHK(hipEventElapsedTime(&f, p->ev[stage], p->ev[stage + 1]));
+    }
+    *ms = f;
+    return CFMM_OK;
+}
+
+}  // extern "C"

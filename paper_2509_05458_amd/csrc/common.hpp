@@ -1,0 +1,76 @@
+// Shared definitions of the cfmm HIP library: complex arithmetic and limits.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#define CFMM_HD __host__ __device__ inline
+
+namespace cfmm {
+
+constexpr int kPMax2D = 63;          // 2D expansions hold 2P+1 <= 127 coefficients
+constexpr int kNCoef2DMax = 2 * kPMax2D + 1;
+constexpr int kPMax3D = 40;          // 3D expansions hold (P+1)^2 coefficients
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kEuler = 0.57721566490153286060651209008240243;
+constexpr int kGHHalf = 24;          // 48-point Gauss-Hermite rule, positive half
+
+struct cplx {
+    double re, im;
+};
+
+CFMM_HD cplx mk(double r, double i) { return cplx{r, i}; }
+CFMM_HD cplx operator+(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
+CFMM_HD cplx operator-(cplx a, cplx b) { return cplx{a.re - b.re, a.im - b.im}; }
+CFMM_HD cplx operator-(cplx a) { return cplx{-a.re, -a.im}; }
+CFMM_HD cplx operator*(cplx a, cplx b)
+{
+    return cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+CFMM_HD cplx operator*(double s, cplx a) { return cplx{s * a.re, s * a.im}; }
+CFMM_HD cplx operator*(cplx a, double s) { return cplx{s * a.re, s * a.im}; }
+CFMM_HD cplx& operator+=(cplx& a, cplx b) { a.re += b.re; a.im += b.im; return a; }
+CFMM_HD cplx& operator-=(cplx& a, cplx b) { a.re -= b.re; a.im -= b.im; return a; }
+CFMM_HD cplx& operator*=(cplx& a, cplx b) { a = a * b; return a; }
+CFMM_HD cplx& operator*=(cplx& a, double s) { a.re *= s; a.im *= s; return a; }
+CFMM_HD double cabs2(cplx a) { return a.re * a.re + a.im * a.im; }
+CFMM_HD double cabs1(cplx a) { return hypot(a.re, a.im); }
+CFMM_HD cplx conj(cplx a) { return cplx{a.re, -a.im}; }
+CFMM_HD cplx times_i(cplx a) { return cplx{-a.im, a.re}; }
+
+// a / b with scaling (Smith's algorithm)
+CFMM_HD cplx cdiv(cplx a, cplx b)
+{
+    if (fabs(b.re) >= fabs(b.im)) {
+        double r = b.im / b.re, d = b.re + b.im * r;
+        return cplx{(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+    }
+    double r = b.re / b.im, d = b.re * r + b.im;
+    return cplx{(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+}
+CFMM_HD cplx cinv(cplx b) { return cdiv(cplx{1.0, 0.0}, b); }
+
+// principal square root, Re >= 0
+CFMM_HD cplx csqrt_p(cplx a)
+{
+    if (a.re == 0.0 && a.im == 0.0) return cplx{0.0, 0.0};
+    double m = hypot(a.re, a.im);
+    if (a.re >= 0.0) {
+        double t = sqrt(0.5 * (m + a.re));
+        return cplx{t, a.im / (2.0 * t)};
+    }
+    double t = sqrt(0.5 * (m - a.re));
+    return cplx{fabs(a.im) / (2.0 * t), copysign(t, a.im)};
+}
+
+// principal logarithm
+CFMM_HD cplx clog_p(cplx a) { return cplx{log(hypot(a.re, a.im)), atan2(a.im, a.re)}; }
+
+CFMM_HD cplx cexp_(cplx a)
+{
+    double e = exp(a.re), s, c;
+    sincos(a.im, &s, &c);
+    return cplx{e * c, e * s};
+}
+
+}  // namespace cfmm

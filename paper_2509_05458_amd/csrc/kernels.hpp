@@ -1,0 +1,83 @@
+// Launch interfaces of the cfmm kernels (host side).
+#pragma once
+#include "common.hpp"
+
+namespace cfmm {
+
+constexpr int kRsThreads = 256;
+constexpr int kRsRounds = 8;
+constexpr int kRsTile = kRsThreads * kRsRounds;
+
+struct KeyParams {
+    double lo[3];
+    double scale;   // 2^B / D
+    double top;     // 2^B - 1
+};
+
+// tree construction (tree_kernels.hip)
+hipError_t launch_bbox(const double* pts, int64_t n, int dim, double* partial, int nb,
+                       double* out, hipStream_t st);
+hipError_t launch_morton(const double* pts, int64_t n, int dim, const KeyParams& kp,
+                         uint64_t* keys, int* idx, hipStream_t st);
+size_t radix_sort_scratch_bytes(int64_t n);
+hipError_t launch_radix_sort(uint64_t* keys, int* vals, uint64_t* keys_alt, int* vals_alt,
+                             int64_t n, int key_bits, void* scratch, hipStream_t st);
+hipError_t launch_gather_points(const double* pts, const int* perm, int64_t n, int dim,
+                                double* xre, double* xim, hipStream_t st);
+hipError_t launch_gather_density(const double* sig, const int* perm, int64_t n, double* sre,
+                                 double* sim, hipStream_t st);
+hipError_t launch_centres(const int* pbeg, const int* pend, int nbox, int64_t n, int dim,
+                          const double* xim, double* cim, double* delta, hipStream_t st);
+hipError_t launch_check_near(const int* leaves, int nleaf, const int* pbeg, const int* pend,
+                             const int* l1off, const int* l1idx, int64_t n, int dim,
+                             const double* xre, const double* xim, int* flag, hipStream_t st);
+
+// Device views shared by the evaluation kernels.
+struct TreeView {
+    int nbox;
+    const int* pbeg;
+    const int* pend;
+    const int* level;
+    const int* parent;
+    const int* child0;
+    const int* nchild;
+    const double* cre;     // centre real parts, [d * nbox + b]
+    const double* cim;     // centre imaginary parts
+    const int* eoff;       // expansion offset (complex units) per box, -1 if none
+    const int* P;          // expansion length per level
+    const double* rs;      // expansion scaling per level
+    const int* l1off; const int* l1idx;
+    const int* l2off; const int* l2idx;
+    const int* l3off; const int* l3idx;
+    const int* l4off; const int* l4idx;
+};
+
+struct PointsView {
+    int64_t n;
+    const double* xre;     // [d * n + i], sorted order
+    const double* xim;
+    const double* sre;     // densities, sorted order
+    const double* sim;
+};
+
+// 2D Helmholtz evaluation (h2d_kernels.hip)
+hipError_t h2d_init_tables(int device);
+hipError_t h2d_p2m(const int* boxes, int nb, const TreeView& tv, const PointsView& pv,
+                   double kappa, cplx* mpole, hipStream_t st);
+hipError_t h2d_m2m(const int* boxes, int nb, const TreeView& tv, double kappa, cplx* mpole,
+                   hipStream_t st);
+hipError_t h2d_m2l(const int* boxes, int nb, const TreeView& tv, const PointsView& pv,
+                   double kappa, const cplx* mpole, cplx* local, hipStream_t st);
+hipError_t h2d_l2l(const int* boxes, int nb, const TreeView& tv, double kappa, cplx* local,
+                   hipStream_t st);
+hipError_t h2d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const TreeView& tv,
+                        const PointsView& pv, double kappa, const cplx* mpole, const cplx* local,
+                        cplx* ufar, hipStream_t st);
+hipError_t h2d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
+                   double kappa, const cplx* ufar, const int* perm, double* out, int mixed,
+                   hipStream_t st);
+
+// host-side special functions for the expansion-length rule
+double h2d_nterms_crit(double kappa, double R, double r, int n);
+
+}  // namespace cfmm

@@ -1,0 +1,94 @@
+"""CPU checks of the library: it loads, exports every declared symbol, rejects
+invalid arguments before touching a GPU, and its host planning logic (tree,
+Lists 1-4, expansion lengths) equals the oracle's bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2509_05458_amd as cf
+import synth
+from oracle import params
+from oracle import tree as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cfmm.h")).read()
+    return sorted(set(re.findall(r"\b(cfmm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = cf.lib()
+    names = _declared()
+    assert "cfmm_plan" in names and "cfmm_eval" in names and "cfmm_destroy" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("bad", [dict(dim=4), dict(kernel=7), dict(tol=0.0), dict(tol=2.0),
+                                 dict(n=0), dict(wavenumber=-1.0), dict(precision=5),
+                                 dict(separation=3), dict(leaf_size=-2)])
+def test_invalid_arguments_rejected(bad):
+    import ctypes
+    pts = np.zeros((4, 2), np.complex128)
+    kw = dict(dim=2, kernel=cf.HELMHOLTZ, wavenumber=1.0, tol=1e-6, n=4, points=pts.ctypes.data,
+              points_on_device=0, precision=0, stream=None, leaf_size=0, separation=0)
+    kw.update(bad)
+    d = cf.PlanDesc(**kw)
+    h = ctypes.c_void_p()
+    rc = cf.lib().cfmm_plan(ctypes.byref(h), ctypes.byref(d))
+    assert rc == cf.CFMM_EINVAL
+    assert cf.lib().cfmm_last_error().decode() != ""
+    assert not h.value
+
+
+def test_null_arguments_rejected():
+    import ctypes
+    L = cf.lib()
+    assert L.cfmm_plan(None, None) == cf.CFMM_EINVAL
+    h = ctypes.c_void_p()
+    assert L.cfmm_plan(ctypes.byref(h), None) == cf.CFMM_EINVAL
+    assert L.cfmm_eval(None, None, None, 0) == cf.CFMM_EINVAL
+    assert L.cfmm_destroy(None) == cf.CFMM_OK
+
+
+def _cases():
+    from tests.test_tree_oracle import CASES
+    return CASES
+
+
+@pytest.mark.parametrize("top", [0, 2, 3])
+@pytest.mark.parametrize("case", range(6))
+def test_host_tree_and_lists_equal_oracle(case, top):
+    name, make, ns, k = _cases()[case]
+    pts = make()
+    t = T.build_tree(pts, ns, k, top)
+    h = cf.host_tree(pts.shape[1], t.keys, ns, k, top)
+    for key in ("level", "parent", "child0", "nchild", "pbeg", "pend", "prefix"):
+        assert np.array_equal(getattr(t, key).astype(h[key].dtype), h[key]), key
+    for q in range(1, 5):
+        o, i = t.lists[f"L{q}"]
+        ho, hi = h[f"L{q}"]
+        assert np.array_equal(o, ho) and np.array_equal(i, hi), q
+
+
+def test_host_tree_full_size_curve_equals_oracle():
+    c = synth.make_config(1, n=1 << 17)
+    t = T.build_tree(c.points, 64, 1, 3)
+    h = cf.host_tree(2, t.keys, 64, 1, 3)
+    assert np.array_equal(t.pbeg, h["pbeg"]) and np.array_equal(t.level, h["level"])
+    for q in range(1, 5):
+        assert np.array_equal(t.lists[f"L{q}"][1], h[f"L{q}"][1])
+
+
+@pytest.mark.parametrize("eps", [1e-5, 1e-7, 1e-11, 1e-13])
+@pytest.mark.parametrize("w", [1e-3, 0.05, 0.4, 2.0, 5.0])
+@pytest.mark.parametrize("sep", [1, 2])
+def test_nterms_equals_oracle_rule(eps, w, sep):
+    kappa = 10.0
+    got = cf.nterms(2, "helmholtz", kappa, w, sep, eps, 63)
+    ref = params.nterms(2, "helmholtz", kappa, w, sep, eps, 63)
+    assert got == ref
