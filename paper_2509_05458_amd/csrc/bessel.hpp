@@ -21,24 +21,41 @@
 namespace cfmm {
 
 // ---------------------------------------------------------------- H0, H1
+// series coefficients: 1/k^2, 1/(k(k+1)) and the harmonic numbers H_k
+struct SeriesTab {
+    double inv_k2[41], inv_kk1[41], harm[41];
+};
+constexpr SeriesTab make_series_tab()
+{
+    SeriesTab t{};
+    double h = 0.0;
+    for (int k = 1; k < 41; ++k) {
+        t.inv_k2[k] = 1.0 / ((double)k * (double)k);
+        t.inv_kk1[k] = 1.0 / ((double)k * (double)(k + 1));
+        h += 1.0 / (double)k;
+        t.harm[k] = h;
+    }
+    return t;
+}
+
 template <bool WANT_H1>
 CFMM_HD void hankel_small(cplx z, cplx q, cplx half_log_q, cplx* h0, cplx* h1)
 {
     // q = z^2/4, half_log_q = log(z/2)
+    constexpr SeriesTab T = make_series_tab();
     cplx mq = -q;
     cplx t = mk(1.0, 0.0), j0 = t, s0 = mk(0.0, 0.0);
     cplx u = mk(1.0, 0.0), su = u, sh = mk(0.0, 0.0);   // J1 = (z/2) su
     double hk = 0.0;
     double aq = sqrt(cabs2(q));
     for (int k = 1; k < 40; ++k) {
-        double dk = (double)k;
-        t = t * mq * (1.0 / (dk * dk));
-        double hk1 = hk + 1.0 / dk;         // H_k
+        t = t * mq * T.inv_k2[k];
+        double hk1 = T.harm[k];             // H_k
         j0 += t;
         s0 += hk1 * t;
         if (WANT_H1) {
             sh += (hk + hk1) * u;           // (H_{k-1} + H_k) u_{k-1}
-            u = u * mq * (1.0 / (dk * (dk + 1.0)));
+            u = u * mq * T.inv_kk1[k];
             su += u;
         }
         hk = hk1;
@@ -251,8 +268,10 @@ CFMM_HD void hcore2(cplx y1, cplx y2, double kappa, double r, int K, const doubl
     *bm = cdiv(zm, rho);
     cplx riz = r * cinv(z);
     double r2 = r * r;
-    if (z.im >= 0.0) {
-        // H^(1)_k grows with k here: the upward recurrence is stable
+    if (z.im >= -1.0) {
+        // H^(1)_k grows with k for Im z >= 0: the upward recurrence is stable;
+        // for -1 <= Im z < 0 the unwanted H^(2) component can gain at most
+        // about e^(2 |Im z|) relative to H^(1), a few ulps
         cplx hm1 = h0, hk = r * h1;
         seq[0] = h0;
         for (int k = 1; k <= K; ++k) {

@@ -78,6 +78,13 @@ struct cfmm_plan_s {
     int off_leaves = 0, nleaf = 0, off_p2m = 0, n_p2m = 0, off_m2l = 0, n_m2l = 0;
     std::vector<int> m2m_off, m2m_cnt, l2l_off, l2l_cnt;   // per level
     cplx *d_mpole = nullptr, *d_local = nullptr, *d_ufar = nullptr;
+    int off_p2l = 0, n_p2l = 0;
+    // plan-time translation operators (2D Helmholtz)
+    int64_t *d_o_m2l = nullptr, *d_o_tr = nullptr;
+    cplx *d_g_m2l = nullptr, *d_g_m2m = nullptr, *d_g_l2l = nullptr;
+    double* d_pw = nullptr;
+    int64_t* d_poff = nullptr;   // per box: offset of its points' expansion values
+    cplx* d_pvals = nullptr;
     double *d_io_in = nullptr, *d_io_out = nullptr;       // staging for host pointers
     int64_t info[16];
 
@@ -121,6 +128,13 @@ struct cfmm_plan_s {
         tv.l3off = d_loff[2]; tv.l3idx = d_lidx[2];
         tv.l4off = d_loff[3]; tv.l4idx = d_lidx[3];
         return tv;
+    }
+    H2DOps ops() const
+    {
+        H2DOps o;
+        o.g_m2l = d_g_m2l; o.o_m2l = d_o_m2l; o.g_m2m = d_g_m2m; o.g_l2l = d_g_l2l;
+        o.o_tr = d_o_tr; o.pw = d_pw;
+        return o;
     }
     PointsView pview() const
     {
@@ -312,7 +326,55 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         for (int b = t.lvl_beg[l]; b < t.lvl_beg[l + 1]; ++b) work.push_back(b);
         p->l2l_cnt[l] = (int)work.size() - p->l2l_off[l];
     }
+    p->off_p2l = (int)work.size();
+    for (int b = 0; b < nb; ++b)
+        if (t.level[b] >= top && t.off[3][b + 1] > t.off[3][b]) work.push_back(b);
+    p->n_p2l = (int)work.size() - p->off_p2l;
+    int off_tr = (int)work.size();
+    for (int b = 0; b < nb; ++b)
+        if (t.level[b] >= top + 1) work.push_back(b);
+    int n_tr = (int)work.size() - off_tr;
+    int off_pairb = (int)work.size();
+    for (int b = 0; b < nb; ++b)
+        for (int e = t.off[1][b]; e < t.off[1][b + 1]; ++e) work.push_back(b);
+    int npairs = (int)t.idx[1].size();
     if ((rc = upload(p, &p->d_work, work))) return rc;
+    // -------- translation operators (generators of M2L, M2M, L2L)
+    std::vector<int64_t> o_m2l(npairs), o_tr(nb, -1);
+    int64_t gsz = 0;
+    for (int b = 0; b < nb; ++b)
+        for (int e = t.off[1][b]; e < t.off[1][b + 1]; ++e) {
+            o_m2l[e] = gsz;
+            gsz += 4 * p->P[t.level[b]] + 1;
+        }
+    int64_t tsz = 0;
+    for (int b = 0; b < nb; ++b)
+        if (t.level[b] >= top + 1) {
+            o_tr[b] = tsz;
+            tsz += 2 * (p->P[t.level[b]] + p->P[t.level[b] - 1]) + 1;
+        }
+    std::vector<double> pw((size_t)nlev * kPwStride, 0.0);
+    for (int l = 0; l < nlev; ++l)
+        for (int e = 0; e < kPwStride; ++e) pw[(size_t)l * kPwStride + e] = pow(p->rs[l], (double)e);
+    if ((rc = upload(p, &p->d_o_m2l, o_m2l)) || (rc = upload(p, &p->d_o_tr, o_tr)) ||
+        (rc = upload(p, &p->d_pw, pw)) || (rc = p->alloc(&p->d_g_m2l, gsz)) ||
+        (rc = p->alloc(&p->d_g_m2m, tsz)) || (rc = p->alloc(&p->d_g_l2l, tsz)))
+        return rc;
+    std::vector<int64_t> poff(nb, -1);
+    int64_t psz = 0;
+    for (int b = 0; b < nb; ++b)
+        if (t.nchild[b] == 0 && t.level[b] >= top) {
+            poff[b] = psz;
+            psz += (int64_t)(t.pend[b] - t.pbeg[b]) * (2 * p->P[t.level[b]] + 1);
+        }
+    if ((rc = upload(p, &p->d_poff, poff)) || (rc = p->alloc(&p->d_pvals, psz))) return rc;
+    {
+        TreeView tv = p->view();
+        HIPCHK(h2d_gen_pts(p->d_work + p->off_p2m, p->n_p2m, tv, p->pview(), p->kappa, p->d_poff,
+                           p->d_pvals, st));
+        HIPCHK(h2d_gen_ops(p->d_work + off_pairb, npairs, p->d_work + off_tr, n_tr, tv, p->kappa,
+                           p->d_o_m2l, p->d_g_m2l, p->d_o_tr, p->d_g_m2m, p->d_g_l2l, st));
+    }
     // -------- geometry check on the near pairs
     int* d_flag = nullptr;
     if ((rc = p->alloc(&d_flag, 1))) return rc;
@@ -347,6 +409,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         tot += (int64_t)nb * (6 * sizeof(int) + 2 * dim * sizeof(double) + sizeof(int));
         for (int q = 0; q < 4; ++q) tot += (int64_t)(t.off[q].size() + t.idx[q].size()) * sizeof(int);
         tot += (int64_t)work.size() * sizeof(int) + 2 * ecount * (int64_t)sizeof(cplx);
+        tot += (gsz + 2 * tsz + psz) * (int64_t)sizeof(cplx) + (npairs + 2 * nb) * 8 + (int64_t)pw.size() * 8;
         p->bytes = tot;
     }
     // -------- description
@@ -441,18 +504,19 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
     HIPCHK(mark(0));
     HIPCHK(launch_gather_density(sig, p->d_perm, n, p->d_sre, p->d_sim, st));
     HIPCHK(mark(1));
-    HIPCHK(h2d_p2m(W + p->off_p2m, p->n_p2m, tv, pv, p->kappa, p->d_mpole, st));
+    HIPCHK(h2d_p2m(W + p->off_p2m, p->n_p2m, tv, pv, p->d_poff, p->d_pvals, p->d_mpole, st));
     HIPCHK(mark(2));
     for (int l = nlev - 2; l >= top; --l)
-        HIPCHK(h2d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], tv, p->kappa, p->d_mpole, st));
+        HIPCHK(h2d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], tv, p->ops(), p->d_mpole, st));
     HIPCHK(mark(3));
-    HIPCHK(h2d_m2l(W + p->off_m2l, p->n_m2l, tv, pv, p->kappa, p->d_mpole, p->d_local, st));
+    HIPCHK(h2d_m2l(W + p->off_m2l, p->n_m2l, tv, p->ops(), p->d_mpole, p->d_local, st));
+    HIPCHK(h2d_p2l(W + p->off_p2l, p->n_p2l, tv, pv, p->kappa, p->d_local, st));
     HIPCHK(mark(4));
     for (int l = top + 1; l < nlev; ++l)
-        HIPCHK(h2d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], tv, p->kappa, p->d_local, st));
+        HIPCHK(h2d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], tv, p->ops(), p->d_local, st));
     HIPCHK(mark(5));
     HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, top, std::max(1, p->pmax), tv, pv, p->kappa,
-                        p->d_mpole, p->d_local, p->d_ufar, st));
+                        p->d_poff, p->d_pvals, p->d_mpole, p->d_local, p->d_ufar, st));
     HIPCHK(mark(6));
     HIPCHK(h2d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out,
                    p->precision, st));

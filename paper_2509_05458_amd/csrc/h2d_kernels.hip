@@ -57,203 +57,287 @@ __device__ inline int iabs_(int a) { return a < 0 ? -a : a; }
 // ------------------------------------------------------------------ P2M
 constexpr int kChunk = 16;
 
-__global__ __launch_bounds__(128) void k_h2d_p2m(const int* __restrict__ boxes, TreeView tv,
-                                                 PointsView pv, double kappa, cplx* __restrict__ mpole)
+// Per-point expansion values, built once per plan for every point of a leaf
+// that carries expansions (Y = y - c, the leaf's complexified centre):
+//   v[n + P] = J_n(kappa rho_Y) e^{-in phi_Y} / r^|n|,  n = -P..P.
+// P2M is M_n = sum_j sigma_j v_n(j); L2P reuses them since
+// J_n(kappa rho_X) e^{in phi_X} / r^|n| = (-1)^n v_{-n} at the same point.
+__global__ void k_h2d_gen_pts(const int* __restrict__ leaves, int nleaf, TreeView tv, PointsView pv,
+                              double kappa, const int64_t* __restrict__ poff, cplx* __restrict__ vals)
 {
-    __shared__ cplx spos[kChunk][kPMax2D + 1];
-    __shared__ cplx sneg[kChunk][kPMax2D + 1];
-    __shared__ cplx ssig[kChunk];
-    int b = boxes[blockIdx.x];
+    int li = blockIdx.x;
+    if (li >= nleaf) return;
+    int b = leaves[li];
     int l = tv.level[b];
-    int P = tv.P[l];
+    int P = tv.P[l], nc = 2 * P + 1;
     double r = tv.rs[l];
     int nbx = tv.nbox;
     int64_t n = pv.n;
     cplx c1 = mk(tv.cre[b], tv.cim[b]), c2 = mk(tv.cre[nbx + b], tv.cim[nbx + b]);
-    int t = threadIdx.x, ncoef = 2 * P + 1, mm = t - P;
-    cplx acc = mk(0.0, 0.0);
-    int p0 = tv.pbeg[b], p1 = tv.pend[b];
-    for (int j0 = p0; j0 < p1; j0 += kChunk) {
-        int cnt = min(kChunk, p1 - j0);
-        if (t < cnt) {
-            int j = j0 + t;
-            cplx y1 = mk(pv.xre[j] - c1.re, pv.xim[j] - c1.im);
-            cplx y2 = mk(pv.xre[n + j] - c2.re, pv.xim[n + j] - c2.im);
-            jseq2(y1, y2, kappa, r, P, &spos[t][0], &sneg[t][0], 1);
-            ssig[t] = mk(pv.sre[j], pv.sim[j]);
+    for (int j = tv.pbeg[b] + threadIdx.x; j < tv.pend[b]; j += blockDim.x) {
+        cplx y1 = mk(pv.xre[j] - c1.re, pv.xim[j] - c1.im);
+        cplx y2 = mk(pv.xre[n + j] - c2.re, pv.xim[n + j] - c2.im);
+        cplx* v = vals + poff[b] + (int64_t)(j - tv.pbeg[b]) * nc + P;
+        cplx bp, bm;
+        bool fact;
+        // core sequence into v[0..P], then expand: v[n] uses e^{-i phi} (bm), v[-n] e^{+i phi}
+        jcore2(y1, y2, kappa, r, P, v, 1, &bp, &bm, &fact);
+        cplx pp = mk(1.0, 0.0), pm = mk(1.0, 0.0);
+        for (int k = 1; k <= P; ++k) {
+            double f = fact ? 1.0 / k : 1.0;
+            pp = pp * bp * f;
+            pm = pm * bm * f;
+            cplx s = v[k];
+            v[k] = s * pm;
+            cplx w = s * pp;
+            v[-k] = (k & 1) ? -w : w;
         }
-        __syncthreads();
-        if (t < ncoef) {
-            for (int q = 0; q < cnt; ++q) {
-                cplx v = (mm >= 0) ? sneg[q][mm] : ((mm & 1) ? -spos[q][-mm] : spos[q][-mm]);
-                acc += v * ssig[q];
-            }
-        }
-        __syncthreads();
     }
-    if (t < ncoef) mpole[tv.eoff[b] + t] = acc;
+}
+
+// one wavefront per leaf, lane = coefficient
+__global__ __launch_bounds__(256) void k_h2d_p2m(const int* __restrict__ leaves, int nleaf, TreeView tv,
+                                                 PointsView pv, const int64_t* __restrict__ poff,
+                                                 const cplx* __restrict__ vals, cplx* __restrict__ mpole)
+{
+    int lane = threadIdx.x & 63;
+    int li = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (li >= nleaf) return;
+    int b = leaves[li];
+    int P = tv.P[tv.level[b]], nc = 2 * P + 1;
+    int p0 = tv.pbeg[b], p1 = tv.pend[b];
+    const cplx* V = vals + poff[b];
+    for (int m0 = 0; m0 < nc; m0 += 64) {
+        int mi = m0 + lane;
+        if (mi >= nc) break;
+        cplx acc = mk(0.0, 0.0);
+        for (int j = p0; j < p1; ++j) {
+            cplx sg = mk(pv.sre[j], pv.sim[j]);
+            acc += V[(int64_t)(j - p0) * nc + mi] * sg;
+        }
+        mpole[tv.eoff[b] + mi] = acc;
+    }
+}
+
+// ------------------------------------------------------ operator generators
+// Translation generators depend only on the geometry and are built once per
+// plan.  For a List-2 pair (target b, source a), D = c_b - c_a:
+//   gm2l[k + 2P] = H_k(kappa rho_D) e^{ik phi_D} r^|k|,            k = -2P..2P
+// and for each box c with parent p (K = P_p + P_c):
+//   gm2m[k + K] = J_k(kappa rho_D) e^{ik phi_D} / r_c^|k|,  D = c_p - c_c
+//   gl2l[k + K] = J_k(kappa rho_D) e^{ik phi_D} / r_p^|k|,  D = c_c - c_p
+// (negative k from J_{-k} = (-1)^k J_k, H_{-k} = (-1)^k H_k).
+__device__ inline void fill_signed(cplx* g, int K, cplx bp, cplx bm, bool fact)
+{
+    // g[0..K] holds the core sequence; expand to g[-K..K] with the bases
+    cplx pp = mk(1.0, 0.0), pm = mk(1.0, 0.0);
+    for (int k = 1; k <= K; ++k) {
+        double f = fact ? 1.0 / k : 1.0;
+        pp = pp * bp * f;
+        pm = pm * bm * f;
+        cplx s = g[k];
+        g[k] = s * pp;
+        cplx v = s * pm;
+        g[-k] = (k & 1) ? -v : v;
+    }
+}
+
+__global__ void k_h2d_gen_m2l(int npairs, const int* __restrict__ pair_b, TreeView tv, double kappa,
+                              const int64_t* __restrict__ goff, cplx* __restrict__ gen)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= npairs) return;
+    int b = pair_b[e], a = tv.l2idx[e];
+    int l = tv.level[b];
+    int K = 2 * tv.P[l];
+    double r = tv.rs[l];
+    int nbx = tv.nbox;
+    cplx d1 = mk(tv.cre[b] - tv.cre[a], tv.cim[b] - tv.cim[a]);
+    cplx d2 = mk(tv.cre[nbx + b] - tv.cre[nbx + a], tv.cim[nbx + b] - tv.cim[nbx + a]);
+    cplx* g = gen + goff[e] + K;
+    cplx bp, bm;
+    hcore2(d1, d2, kappa, r, K, c_ghx, c_ghw, g, 1, &bp, &bm);
+    fill_signed(g, K, bp, bm, false);
+}
+
+__global__ void k_h2d_gen_tr(const int* __restrict__ boxes, int nb, TreeView tv, double kappa,
+                             const int64_t* __restrict__ toff, cplx* __restrict__ gm2m,
+                             cplx* __restrict__ gl2l)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    int c = boxes[i], p = tv.parent[c];
+    int lc = tv.level[c];
+    int K = tv.P[lc] + tv.P[lc - 1];
+    double rc = tv.rs[lc], rp = tv.rs[lc - 1];
+    int nbx = tv.nbox;
+    cplx d1 = mk(tv.cre[p] - tv.cre[c], tv.cim[p] - tv.cim[c]);
+    cplx d2 = mk(tv.cre[nbx + p] - tv.cre[nbx + c], tv.cim[nbx + p] - tv.cim[nbx + c]);
+    cplx bp, bm;
+    bool fact;
+    cplx* g = gm2m + toff[c] + K;
+    jcore2(d1, d2, kappa, rc, K, g, 1, &bp, &bm, &fact);
+    fill_signed(g, K, bp, bm, fact);
+    g = gl2l + toff[c] + K;
+    jcore2(-d1, -d2, kappa, rp, K, g, 1, &bp, &bm, &fact);
+    fill_signed(g, K, bp, bm, fact);
 }
 
 // ------------------------------------------------------------------ M2M
-__global__ __launch_bounds__(128) void k_h2d_m2m(const int* __restrict__ boxes, TreeView tv,
-                                                 double kappa, cplx* __restrict__ mpole)
+// One wavefront per parent; lane m owns output coefficient m.  Entry (m, n)
+// of child c: gm2m[n - m] r_c^(|n-m| + |n| - |m|) (r_c/r_p)^|m|.
+__global__ __launch_bounds__(256) void k_h2d_m2m(const int* __restrict__ boxes, int nb, TreeView tv,
+                                                 H2DOps ops, cplx* __restrict__ mpole)
 {
-    __shared__ cplx gp[4][2 * kPMax2D + 1];
-    __shared__ cplx gn[4][2 * kPMax2D + 1];
-    __shared__ cplx mc[4][kNCoef2DMax];
-    __shared__ double pw[2 * kPMax2D + 2];
-    __shared__ double rat[kPMax2D + 1];
-    int p = boxes[blockIdx.x];
+    int lane = threadIdx.x & 63;
+    int bi = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (bi >= nb) return;
+    int p = boxes[bi];
     int l = tv.level[p];
     int Pp = tv.P[l], Pc = tv.P[l + 1];
-    double rp = tv.rs[l], rc = tv.rs[l + 1];
+    int K = Pp + Pc, ncoef = 2 * Pp + 1;
+    const double* pwc = ops.pw + (size_t)(l + 1) * kPwStride;
+    double rat = tv.rs[l + 1] / tv.rs[l];
     int c0 = tv.child0[p], nc = tv.nchild[p];
-    int K = Pp + Pc, nbx = tv.nbox, ncc = 2 * Pc + 1;
-    int t = threadIdx.x;
-    if (t < nc) {
-        int c = c0 + t;
-        cplx d1 = mk(tv.cre[p] - tv.cre[c], tv.cim[p] - tv.cim[c]);
-        cplx d2 = mk(tv.cre[nbx + p] - tv.cre[nbx + c], tv.cim[nbx + p] - tv.cim[nbx + c]);
-        jseq2(d1, d2, kappa, rc, K, &gp[t][0], &gn[t][0], 1);
-    }
-    for (int e = t; e <= 2 * Pc; e += blockDim.x) pw[e] = pow(rc, (double)e);
-    for (int j = t; j <= Pp; j += blockDim.x) rat[j] = pow(rc / rp, (double)j);
-    for (int q = t; q < nc * ncc; q += blockDim.x) {
-        int ci = q / ncc, k = q - ci * ncc;
-        mc[ci][k] = mpole[tv.eoff[c0 + ci] + k];
-    }
-    __syncthreads();
-    if (t < 2 * Pp + 1) {
-        int mm = t - Pp, am = iabs_(mm);
+    for (int m0 = 0; m0 < ncoef; m0 += 64) {
+        int mi = m0 + lane;
+        if (mi >= ncoef) break;
+        int mm = mi - Pp, am = mm < 0 ? -mm : mm;
         cplx acc = mk(0.0, 0.0);
         for (int ci = 0; ci < nc; ++ci) {
+            int c = c0 + ci;
+            const cplx* M = mpole + tv.eoff[c] + Pc;
+            const cplx* G = ops.g_m2m + ops.o_tr[c] + K - mm;
             for (int nn = -Pc; nn <= Pc; ++nn) {
                 int k = nn - mm;
-                int e = iabs_(k) + iabs_(nn) - am;
-                acc += (pw[e] * gen_at(gp[ci], gn[ci], k)) * mc[ci][nn + Pc];
+                int e = (k < 0 ? -k : k) + (nn < 0 ? -nn : nn) - am;
+                acc += (pwc[e] * G[nn]) * M[nn];
             }
         }
-        mpole[tv.eoff[p] + t] = rat[am] * acc;
+        mpole[tv.eoff[p] + mi] = pow(rat, (double)am) * acc;
     }
 }
 
-// ------------------------------------------------------------- M2L + P2L
-constexpr int kM2LBatch = 8;
-
-__global__ __launch_bounds__(128) void k_h2d_m2l(const int* __restrict__ boxes, TreeView tv,
-                                                 PointsView pv, double kappa,
-                                                 const cplx* __restrict__ mpole,
+// ------------------------------------------------------------------ M2L
+// One wavefront per target box; lane m owns L_m.  Entry (m, n) of source a:
+// gm2l[n - m] r^(|m| + |n| - |n - m|), i.e. r^(2 min(|m|,|n|)) when m, n have
+// the same sign and 1 otherwise.
+__global__ __launch_bounds__(256) void k_h2d_m2l(const int* __restrict__ boxes, int nb, TreeView tv,
+                                                 H2DOps ops, const cplx* __restrict__ mpole,
                                                  cplx* __restrict__ local)
 {
-    __shared__ cplx gp[kM2LBatch][2 * kPMax2D + 1];
-    __shared__ cplx gn[kM2LBatch][2 * kPMax2D + 1];
-    __shared__ cplx ms[kM2LBatch][kNCoef2DMax];
-    __shared__ double pw[2 * kPMax2D + 2];
+    int lane = threadIdx.x & 63;
+    int bi = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (bi >= nb) return;
+    int b = boxes[bi];
+    int l = tv.level[b];
+    int P = tv.P[l], ncoef = 2 * P + 1;
+    const double* pw = ops.pw + (size_t)l * kPwStride;
+    int e0 = tv.l2off[b], e1 = tv.l2off[b + 1];
+    for (int m0 = 0; m0 < ncoef; m0 += 64) {
+        int mi = m0 + lane;
+        if (mi >= ncoef) break;
+        int mm = mi - P, am = mm < 0 ? -mm : mm;
+        double rm = pw[2 * am];
+        cplx acc = mk(0.0, 0.0);
+        for (int e = e0; e < e1; ++e) {
+            const cplx* M = mpole + tv.eoff[tv.l2idx[e]] + P;
+            const cplx* G = ops.g_m2l + ops.o_m2l[e] + 2 * P - mm;
+            for (int nn = -P; nn <= P; ++nn) {
+                int an = nn < 0 ? -nn : nn;
+                bool same = (nn > 0 && mm > 0) || (nn < 0 && mm < 0);
+                double f = same ? (an <= am ? pw[2 * an] : rm) : 1.0;
+                acc += (f * G[nn]) * M[nn];
+            }
+        }
+        local[tv.eoff[b] + mi] = acc;
+    }
+}
+
+// ------------------------------------------------------------------ P2L
+// Sources of the coarser leaves in List 4 go directly into the local
+// expansion (added after M2L wrote it).
+__global__ __launch_bounds__(128) void k_h2d_p2l(const int* __restrict__ boxes, TreeView tv,
+                                                 PointsView pv, double kappa, cplx* __restrict__ local)
+{
+    __shared__ cplx gp[kChunk][kPMax2D + 1];
+    __shared__ cplx gn[kChunk][kPMax2D + 1];
+    __shared__ cplx ss[kChunk];
     int b = boxes[blockIdx.x];
     int l = tv.level[b];
     int P = tv.P[l];
     double r = tv.rs[l];
     int nbx = tv.nbox, ncoef = 2 * P + 1;
     int64_t n = pv.n;
-    int t = threadIdx.x, mm = t - P, am = iabs_(mm);
-    for (int e = t; e <= 2 * P; e += blockDim.x) pw[e] = pow(r, (double)e);
+    int t = threadIdx.x, mm = t - P;
     cplx acc = mk(0.0, 0.0);
-    int e0 = tv.l2off[b], e1 = tv.l2off[b + 1];
-    for (int eb = e0; eb < e1; eb += kM2LBatch) {
-        int cnt = min(kM2LBatch, e1 - eb);
-        if (t < cnt) {
-            int a = tv.l2idx[eb + t];
-            cplx d1 = mk(tv.cre[b] - tv.cre[a], tv.cim[b] - tv.cim[a]);
-            cplx d2 = mk(tv.cre[nbx + b] - tv.cre[nbx + a], tv.cim[nbx + b] - tv.cim[nbx + a]);
-            hseq2(d1, d2, kappa, r, 2 * P, c_ghx, c_ghw, &gp[t][0], &gn[t][0], 1);
-        }
-        for (int q = t; q < cnt * ncoef; q += blockDim.x) {
-            int ai = q / ncoef, k = q - ai * ncoef;
-            ms[ai][k] = mpole[tv.eoff[tv.l2idx[eb + ai]] + k];
-        }
-        __syncthreads();
-        if (t < ncoef) {
-            for (int ai = 0; ai < cnt; ++ai) {
-                for (int nn = -P; nn <= P; ++nn) {
-                    int k = nn - mm;
-                    int e = am + iabs_(nn) - iabs_(k);
-                    acc += (pw[e] * gen_at(gp[ai], gn[ai], k)) * ms[ai][nn + P];
-                }
-            }
-        }
-        __syncthreads();
-    }
-    // P2L: sources of the coarser leaves in List 4, directly into the local
     cplx cb1 = mk(tv.cre[b], tv.cim[b]), cb2 = mk(tv.cre[nbx + b], tv.cim[nbx + b]);
     for (int e = tv.l4off[b]; e < tv.l4off[b + 1]; ++e) {
         int c = tv.l4idx[e];
         int q0 = tv.pbeg[c], q1 = tv.pend[c];
-        for (int j0 = q0; j0 < q1; j0 += kM2LBatch) {
-            int cnt = min(kM2LBatch, q1 - j0);
+        for (int j0 = q0; j0 < q1; j0 += kChunk) {
+            int cnt = min(kChunk, q1 - j0);
             if (t < cnt) {
                 int j = j0 + t;
                 cplx y1 = mk(pv.xre[j] - cb1.re, pv.xim[j] - cb1.im);
                 cplx y2 = mk(pv.xre[n + j] - cb2.re, pv.xim[n + j] - cb2.im);
                 hseq2(y1, y2, kappa, r, P, c_ghx, c_ghw, &gp[t][0], &gn[t][0], 1);
-                ms[t][0] = mk(pv.sre[j], pv.sim[j]);
+                ss[t] = mk(pv.sre[j], pv.sim[j]);
             }
             __syncthreads();
             if (t < ncoef) {
                 for (int q = 0; q < cnt; ++q) {
                     cplx v = (mm >= 0) ? gn[q][mm] : ((mm & 1) ? -gp[q][-mm] : gp[q][-mm]);
-                    acc += v * ms[q][0];
+                    acc += v * ss[q];
                 }
             }
             __syncthreads();
         }
     }
-    if (t < ncoef) local[tv.eoff[b] + t] = acc;
+    if (t < ncoef) local[tv.eoff[b] + t] += acc;
 }
 
 // ------------------------------------------------------------------ L2L
-__global__ __launch_bounds__(128) void k_h2d_l2l(const int* __restrict__ boxes, TreeView tv,
-                                                 double kappa, cplx* __restrict__ local)
+// One wavefront per child box c; entry (m, n):
+// gl2l[n - m] r_p^(|n-m| + |m| - |n|) (r_c/r_p)^|m|.
+__global__ __launch_bounds__(256) void k_h2d_l2l(const int* __restrict__ boxes, int nb, TreeView tv,
+                                                 H2DOps ops, cplx* __restrict__ local)
 {
-    __shared__ cplx gp[2 * kPMax2D + 1];
-    __shared__ cplx gn[2 * kPMax2D + 1];
-    __shared__ cplx lp[kNCoef2DMax];
-    __shared__ double pw[2 * kPMax2D + 2];
-    __shared__ double rat[kPMax2D + 1];
-    int c = boxes[blockIdx.x];
+    int lane = threadIdx.x & 63;
+    int bi = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (bi >= nb) return;
+    int c = boxes[bi];
     int p = tv.parent[c];
     int lc = tv.level[c];
     int Pc = tv.P[lc], Pp = tv.P[lc - 1];
-    double rc = tv.rs[lc], rp = tv.rs[lc - 1];
-    int K = Pp + Pc, nbx = tv.nbox;
-    int t = threadIdx.x;
-    if (t == 0) {
-        cplx d1 = mk(tv.cre[c] - tv.cre[p], tv.cim[c] - tv.cim[p]);
-        cplx d2 = mk(tv.cre[nbx + c] - tv.cre[nbx + p], tv.cim[nbx + c] - tv.cim[nbx + p]);
-        jseq2(d1, d2, kappa, rp, K, gp, gn, 1);
-    }
-    for (int e = t; e <= 2 * Pc; e += blockDim.x) pw[e] = pow(rp, (double)e);
-    for (int j = t; j <= Pc; j += blockDim.x) rat[j] = pow(rc / rp, (double)j);
-    for (int k = t; k < 2 * Pp + 1; k += blockDim.x) lp[k] = local[tv.eoff[p] + k];
-    __syncthreads();
-    if (t < 2 * Pc + 1) {
-        int mm = t - Pc, am = iabs_(mm);
+    int K = Pp + Pc, ncoef = 2 * Pc + 1;
+    const double* pwp = ops.pw + (size_t)(lc - 1) * kPwStride;
+    double rat = tv.rs[lc] / tv.rs[lc - 1];
+    const cplx* Lp = local + tv.eoff[p] + Pp;
+    for (int m0 = 0; m0 < ncoef; m0 += 64) {
+        int mi = m0 + lane;
+        if (mi >= ncoef) break;
+        int mm = mi - Pc, am = mm < 0 ? -mm : mm;
+        const cplx* G = ops.g_l2l + ops.o_tr[c] + K - mm;
         cplx acc = mk(0.0, 0.0);
         for (int nn = -Pp; nn <= Pp; ++nn) {
             int k = nn - mm;
-            int e = iabs_(k) + am - iabs_(nn);
-            acc += (pw[e] * gen_at(gp, gn, k)) * lp[nn + Pp];
+            int e = (k < 0 ? -k : k) + am - (nn < 0 ? -nn : nn);
+            acc += (pwp[e] * G[nn]) * Lp[nn];
         }
-        local[tv.eoff[c] + t] += rat[am] * acc;
+        local[tv.eoff[c] + mi] += pow(rat, (double)am) * acc;
     }
 }
 
 // ------------------------------------------------------------- L2P + M2P
 __global__ void k_h2d_leaf_far(const int* __restrict__ leaves, int top, TreeView tv, PointsView pv,
-                               double kappa, const cplx* __restrict__ mpole,
+                               double kappa, const int64_t* __restrict__ poff,
+                               const cplx* __restrict__ vals, const cplx* __restrict__ mpole,
                                const cplx* __restrict__ local, cplx* __restrict__ ufar)
 {
-    extern __shared__ cplx rows[];      // rows[k * blockDim.x + thread]
-    int b = leaves[blockIdx.x];
+    extern __shared__ cplx rows[];      // rows[k * blockDim.x + thread], for M2P
+    int li = blockIdx.x;
+    int b = leaves[li];
     int l = tv.level[b];
     int nbx = tv.nbox, st = blockDim.x, t = threadIdx.x;
     int64_t n = pv.n;
@@ -263,36 +347,25 @@ __global__ void k_h2d_leaf_far(const int* __restrict__ leaves, int top, TreeView
         if (i >= p1) break;
         cplx u = mk(0.0, 0.0);
         if (l >= top) {
-            cplx x1 = mk(pv.xre[i], pv.xim[i]), x2 = mk(pv.xre[n + i], pv.xim[n + i]);
-            int P = tv.P[l];
-            double r = tv.rs[l];
-            cplx X1 = x1 - mk(tv.cre[b], tv.cim[b]), X2 = x2 - mk(tv.cre[nbx + b], tv.cim[nbx + b]);
-            cplx bp, bm;
-            bool fact;
-            jcore2(X1, X2, kappa, r, P, rows + t, st, &bp, &bm, &fact);
+            int P = tv.P[l], nc = 2 * P + 1;
+            // L2P: u = sum_n L_n (-1)^n v_{-n}
             const cplx* L = local + tv.eoff[b] + P;
-            cplx pp = mk(1.0, 0.0), pm = mk(1.0, 0.0);
-            for (int k = 0; k <= P; ++k) {
-                cplx term = pp * L[k];
-                if (k > 0) {
-                    cplx v = pm * L[-k];
-                    term += (k & 1) ? -v : v;
-                }
-                u += rows[k * st + t] * term;
-                double f = fact ? 1.0 / (k + 1) : 1.0;
-                pp = pp * bp * f;
-                pm = pm * bm * f;
+            const cplx* V = vals + poff[b] + (int64_t)(i - p0) * nc + P;
+            for (int k = -P; k <= P; ++k) {
+                cplx w = L[k] * V[-k];
+                u += (k & 1) ? -w : w;
             }
+            cplx x1 = mk(pv.xre[i], pv.xim[i]), x2 = mk(pv.xre[n + i], pv.xim[n + i]);
             for (int e = tv.l3off[b]; e < tv.l3off[b + 1]; ++e) {
                 int a = tv.l3idx[e];
                 int la = tv.level[a];
                 int Pa = tv.P[la];
                 double ra = tv.rs[la];
                 cplx Y1 = x1 - mk(tv.cre[a], tv.cim[a]), Y2 = x2 - mk(tv.cre[nbx + a], tv.cim[nbx + a]);
+                cplx bp, bm;
                 hcore2(Y1, Y2, kappa, ra, Pa, c_ghx, c_ghw, rows + t, st, &bp, &bm);
                 const cplx* M = mpole + tv.eoff[a] + Pa;
-                pp = mk(1.0, 0.0);
-                pm = mk(1.0, 0.0);
+                cplx pp = mk(1.0, 0.0), pm = mk(1.0, 0.0);
                 for (int k = 0; k <= Pa; ++k) {
                     cplx term = pp * M[k];
                     if (k > 0) {
@@ -373,41 +446,66 @@ __global__ __launch_bounds__(64) void k_h2d_p2p(const int* __restrict__ leaves, 
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t h2d_p2m(const int* boxes, int nb, const TreeView& tv, const PointsView& pv,
-                   double kappa, cplx* mpole, hipStream_t st)
+hipError_t h2d_gen_pts(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
+                       double kappa, const int64_t* poff, cplx* vals, hipStream_t st)
 {
-    if (nb <= 0) return hipSuccess;
-    k_h2d_p2m<<<nb, 128, 0, st>>>(boxes, tv, pv, kappa, mpole);
+    if (nleaf <= 0) return hipSuccess;
+    k_h2d_gen_pts<<<nleaf, 64, 0, st>>>(leaves, nleaf, tv, pv, kappa, poff, vals);
     return hipGetLastError();
 }
 
-hipError_t h2d_m2m(const int* boxes, int nb, const TreeView& tv, double kappa, cplx* mpole,
+hipError_t h2d_p2m(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
+                   const int64_t* poff, const cplx* vals, cplx* mpole, hipStream_t st)
+{
+    if (nleaf <= 0) return hipSuccess;
+    k_h2d_p2m<<<(nleaf + 3) / 4, 256, 0, st>>>(leaves, nleaf, tv, pv, poff, vals, mpole);
+    return hipGetLastError();
+}
+
+hipError_t h2d_gen_ops(const int* pair_b, int npairs, const int* tr_boxes, int ntr,
+                       const TreeView& tv, double kappa, const int64_t* o_m2l, cplx* g_m2l,
+                       const int64_t* o_tr, cplx* g_m2m, cplx* g_l2l, hipStream_t st)
+{
+    if (npairs > 0) k_h2d_gen_m2l<<<(npairs + 63) / 64, 64, 0, st>>>(npairs, pair_b, tv, kappa, o_m2l, g_m2l);
+    if (ntr > 0) k_h2d_gen_tr<<<(ntr + 63) / 64, 64, 0, st>>>(tr_boxes, ntr, tv, kappa, o_tr, g_m2m, g_l2l);
+    return hipGetLastError();
+}
+
+hipError_t h2d_m2m(const int* boxes, int nb, const TreeView& tv, const H2DOps& ops, cplx* mpole,
                    hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    k_h2d_m2m<<<nb, 128, 0, st>>>(boxes, tv, kappa, mpole);
+    k_h2d_m2m<<<(nb + 3) / 4, 256, 0, st>>>(boxes, nb, tv, ops, mpole);
     return hipGetLastError();
 }
 
-hipError_t h2d_m2l(const int* boxes, int nb, const TreeView& tv, const PointsView& pv,
-                   double kappa, const cplx* mpole, cplx* local, hipStream_t st)
+hipError_t h2d_m2l(const int* boxes, int nb, const TreeView& tv, const H2DOps& ops,
+                   const cplx* mpole, cplx* local, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    k_h2d_m2l<<<nb, 128, 0, st>>>(boxes, tv, pv, kappa, mpole, local);
+    k_h2d_m2l<<<(nb + 3) / 4, 256, 0, st>>>(boxes, nb, tv, ops, mpole, local);
     return hipGetLastError();
 }
 
-hipError_t h2d_l2l(const int* boxes, int nb, const TreeView& tv, double kappa, cplx* local,
+hipError_t h2d_p2l(const int* boxes, int nb, const TreeView& tv, const PointsView& pv, double kappa,
+                   cplx* local, hipStream_t st)
+{
+    if (nb <= 0) return hipSuccess;
+    k_h2d_p2l<<<nb, 128, 0, st>>>(boxes, tv, pv, kappa, local);
+    return hipGetLastError();
+}
+
+hipError_t h2d_l2l(const int* boxes, int nb, const TreeView& tv, const H2DOps& ops, cplx* local,
                    hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    k_h2d_l2l<<<nb, 128, 0, st>>>(boxes, tv, kappa, local);
+    k_h2d_l2l<<<(nb + 3) / 4, 256, 0, st>>>(boxes, nb, tv, ops, local);
     return hipGetLastError();
 }
 
 hipError_t h2d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const TreeView& tv,
-                        const PointsView& pv, double kappa, const cplx* mpole, const cplx* local,
-                        cplx* ufar, hipStream_t st)
+                        const PointsView& pv, double kappa, const int64_t* poff, const cplx* vals,
+                        const cplx* mpole, const cplx* local, cplx* ufar, hipStream_t st)
 {
     if (nleaf <= 0) return hipSuccess;
     int threads = 64;
@@ -416,7 +514,7 @@ hipError_t h2d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const T
         threads /= 2;
         lds = (size_t)threads * (pmax + 1) * sizeof(cplx);
     }
-    k_h2d_leaf_far<<<nleaf, threads, lds, st>>>(leaves, top, tv, pv, kappa, mpole, local, ufar);
+    k_h2d_leaf_far<<<nleaf, threads, lds, st>>>(leaves, top, tv, pv, kappa, poff, vals, mpole, local, ufar);
     return hipGetLastError();
 }
 

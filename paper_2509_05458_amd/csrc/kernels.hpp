@@ -60,19 +60,37 @@ struct PointsView {
     const double* sim;
 };
 
+// Plan-time operator tables of the 2D Helmholtz translations.
+constexpr int kPwStride = 4 * 64;          // per-level powers r^e, e < kPwStride
+struct H2DOps {
+    const cplx* g_m2l;      // per List-2 entry: 4P+1 generator values, k = -2P..2P
+    const int64_t* o_m2l;   // offset of each entry's generator
+    const cplx* g_m2m;      // per box: 2K+1 values, K = P(parent) + P(box)
+    const cplx* g_l2l;
+    const int64_t* o_tr;    // per box offset into g_m2m / g_l2l (-1 if none)
+    const double* pw;       // pw[l * kPwStride + e] = r_l^e
+};
+
 // 2D Helmholtz evaluation (h2d_kernels.hip)
 hipError_t h2d_init_tables(int device);
-hipError_t h2d_p2m(const int* boxes, int nb, const TreeView& tv, const PointsView& pv,
-                   double kappa, cplx* mpole, hipStream_t st);
-hipError_t h2d_m2m(const int* boxes, int nb, const TreeView& tv, double kappa, cplx* mpole,
+hipError_t h2d_gen_ops(const int* pair_b, int npairs, const int* tr_boxes, int ntr,
+                       const TreeView& tv, double kappa, const int64_t* o_m2l, cplx* g_m2l,
+                       const int64_t* o_tr, cplx* g_m2m, cplx* g_l2l, hipStream_t st);
+hipError_t h2d_gen_pts(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
+                       double kappa, const int64_t* poff, cplx* vals, hipStream_t st);
+hipError_t h2d_p2m(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
+                   const int64_t* poff, const cplx* vals, cplx* mpole, hipStream_t st);
+hipError_t h2d_m2m(const int* boxes, int nb, const TreeView& tv, const H2DOps& ops, cplx* mpole,
                    hipStream_t st);
-hipError_t h2d_m2l(const int* boxes, int nb, const TreeView& tv, const PointsView& pv,
-                   double kappa, const cplx* mpole, cplx* local, hipStream_t st);
-hipError_t h2d_l2l(const int* boxes, int nb, const TreeView& tv, double kappa, cplx* local,
+hipError_t h2d_m2l(const int* boxes, int nb, const TreeView& tv, const H2DOps& ops,
+                   const cplx* mpole, cplx* local, hipStream_t st);
+hipError_t h2d_p2l(const int* boxes, int nb, const TreeView& tv, const PointsView& pv, double kappa,
+                   cplx* local, hipStream_t st);
+hipError_t h2d_l2l(const int* boxes, int nb, const TreeView& tv, const H2DOps& ops, cplx* local,
                    hipStream_t st);
 hipError_t h2d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const TreeView& tv,
-                        const PointsView& pv, double kappa, const cplx* mpole, const cplx* local,
-                        cplx* ufar, hipStream_t st);
+                        const PointsView& pv, double kappa, const int64_t* poff, const cplx* vals,
+                        const cplx* mpole, const cplx* local, cplx* ufar, hipStream_t st);
 hipError_t h2d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
                    double kappa, const cplx* ufar, const int* perm, double* out, int mixed,
                    hipStream_t st);
