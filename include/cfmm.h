@@ -124,6 +124,13 @@ int cfmm_plan_export_list(cfmm_plan_t plan, int which, int32_t* offsets, int32_t
 /* Complexified box centres, complex128[nbox][dim] (Sec. 6.1). */
 int cfmm_plan_export_centers(cfmm_plan_t plan, void* centers);
 
+/* Multipole and local expansion coefficients after the last evaluation
+ * (complex128, box b's coefficients start at offsets[b], -1 for boxes without
+ * expansions); *count receives the total.  Any pointer may be NULL.  For
+ * checking the individual translation steps against a reference. */
+int cfmm_plan_export_expansions(cfmm_plan_t plan, void* mpole, void* local, int64_t* offsets,
+                                int64_t* count);
+
 /* Per-stage timing: when enabled, cfmm_eval records HIP events around each
  * stage on the plan's stream; cfmm_stage_ms reads the last evaluation's
  * times (after cfmm_sync).  Stages: 0 gather, 1 P2M, 2 M2M, 3 M2L+P2L,

@@ -75,6 +75,7 @@ def lib():
         L.cfmm_plan_export_tree.argtypes = [vp, i64p, u64p, i32p, i32p, i32p, i32p, i32p, i32p, u64p]
         L.cfmm_plan_export_list.argtypes = [vp, ctypes.c_int, i32p, i32p, i64p]
         L.cfmm_plan_export_centers.argtypes = [vp, vp]
+        L.cfmm_plan_export_expansions.argtypes = [vp, vp, vp, i64p, i64p]
         L.cfmm_set_profiling.argtypes = [vp, ctypes.c_int]
         L.cfmm_stage_ms.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.cfmm_htree_build.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64, u64p, ctypes.c_int,
@@ -208,6 +209,19 @@ class Plan:
         c = np.zeros((nb, self.dim), np.complex128)
         _check(lib().cfmm_plan_export_centers(self._handle, c.ctypes.data))
         return c
+
+    def export_expansions(self):
+        """(mpole, local, offsets) of the last evaluation (complex128 arrays)."""
+        nb = self.info()["nbox"]
+        off = np.zeros(nb, np.int64)
+        cnt = ctypes.c_int64()
+        _check(lib().cfmm_plan_export_expansions(self._handle, None, None,
+                                                 _ptr(off, ctypes.c_int64), ctypes.byref(cnt)))
+        mp = np.zeros(max(1, cnt.value), np.complex128)
+        lc = np.zeros(max(1, cnt.value), np.complex128)
+        _check(lib().cfmm_plan_export_expansions(self._handle, mp.ctypes.data, lc.ctypes.data,
+                                                 None, None))
+        return mp[:cnt.value], lc[:cnt.value], off
 
     def set_profiling(self, on: bool = True):
         _check(lib().cfmm_set_profiling(self._handle, 1 if on else 0))

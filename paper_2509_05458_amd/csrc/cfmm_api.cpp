@@ -170,6 +170,16 @@ int nterms_level(int dim, int sep, double kappa, double w, double eps, int pmax)
     return pmax + 1;
 }
 
+// Laplace expansion length: (r/R)^n <= eps at n and n+1 with R = (0.5 + k) w,
+// r = sqrt(d)/2 w (Sec. 6.3 with the prefactors dropped; scale free)
+int nterms_laplace(int dim, int sep, double eps)
+{
+    double ratio = sqrt((double)dim) * 0.5 / (0.5 + sep);
+    int n = 1;
+    while (pow(ratio, n) > eps && n < 200) ++n;
+    return n;
+}
+
 int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
 {
     int rc;
@@ -271,28 +281,45 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         if ((rc = upload(p, &p->d_loff[q], t.off[q])) || (rc = upload(p, &p->d_lidx[q], t.idx[q])))
             return rc;
     // -------- expansion lengths (a6)
+    bool h2d = dim == 2;
     p->P.assign(nlev, 0);
     p->rs.assign(nlev, 1.0);
-    double eps = 0.1 * p->tol;
     int pmax = 0;
-    for (int l = top; l < nlev; ++l) {
-        double w = p->D * ldexp(1.0, -l);
-        p->rs[l] = std::min(1.0, p->kappa * w);
-        int m = nterms_level(p->dim, p->sep, p->kappa, w, eps, kPMax2D);
-        if (m > kPMax2D)
-            return fail(CFMM_ERANGE, "expansion length above the supported maximum (" +
-                                         std::to_string(kPMax2D) + ") at level " + std::to_string(l) +
-                                         "; the boxes are too many wavelengths wide");
-        p->P[l] = m;
-        pmax = std::max(pmax, m);
+    if (h2d) {
+        double eps = 0.1 * p->tol;
+        for (int l = top; l < nlev; ++l) {
+            double w = p->D * ldexp(1.0, -l);
+            p->rs[l] = std::min(1.0, p->kappa * w);
+            int m = nterms_level(p->dim, p->sep, p->kappa, w, eps, kPMax2D);
+            if (m > kPMax2D)
+                return fail(CFMM_ERANGE, "expansion length above the supported maximum (" +
+                                             std::to_string(kPMax2D) + ") at level " + std::to_string(l) +
+                                             "; the boxes are too many wavelengths wide");
+            p->P[l] = m;
+            pmax = std::max(pmax, m);
+        }
+    } else {
+        // 3D Laplace: (r/R)^n <= tol with R = (0.5 + k) w, r = sqrt(3)/2 w, the same
+        // at every level; coordinates of level l are scaled by 1/w_l
+        int m = nterms_laplace(dim, p->sep, p->tol);
+        int lim = l3d_pmax_supported();
+        if (m > lim)
+            return fail(CFMM_ERANGE, "expansion length " + std::to_string(m) +
+                                         " above the supported maximum " + std::to_string(lim));
+        for (int l = top; l < nlev; ++l) {
+            p->rs[l] = 1.0 / (p->D * ldexp(1.0, -l));
+            p->P[l] = m;
+        }
+        pmax = m;
     }
     p->pmax = pmax;
+    auto ncoef = [&](int l) -> int64_t { return h2d ? 2 * p->P[l] + 1 : (int64_t)(p->P[l] + 1) * (p->P[l] + 1); };
     std::vector<int> eoff(nb, -1);
     int64_t ecount = 0;
     for (int b = 0; b < nb; ++b)
         if (t.level[b] >= top) {
             eoff[b] = (int)ecount;
-            ecount += 2 * p->P[t.level[b]] + 1;
+            ecount += ncoef(t.level[b]);
         }
     if (ecount > (int64_t)0x7fffffff) return fail(CFMM_ERANGE, "expansion storage above 2^31 entries");
     if ((rc = upload(p, &p->d_eoff, eoff)) || (rc = upload(p, &p->d_P, p->P)) || (rc = upload(p, &p->d_rs, p->rs)))
@@ -339,15 +366,15 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         for (int e = t.off[1][b]; e < t.off[1][b + 1]; ++e) work.push_back(b);
     int npairs = (int)t.idx[1].size();
     if ((rc = upload(p, &p->d_work, work))) return rc;
+    int64_t gsz = 0, tsz = 0, psz = 0;
+    if (h2d) {
     // -------- translation operators (generators of M2L, M2M, L2L)
     std::vector<int64_t> o_m2l(npairs), o_tr(nb, -1);
-    int64_t gsz = 0;
     for (int b = 0; b < nb; ++b)
         for (int e = t.off[1][b]; e < t.off[1][b + 1]; ++e) {
             o_m2l[e] = gsz;
             gsz += 4 * p->P[t.level[b]] + 1;
         }
-    int64_t tsz = 0;
     for (int b = 0; b < nb; ++b)
         if (t.level[b] >= top + 1) {
             o_tr[b] = tsz;
@@ -361,7 +388,6 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         (rc = p->alloc(&p->d_g_m2m, tsz)) || (rc = p->alloc(&p->d_g_l2l, tsz)))
         return rc;
     std::vector<int64_t> poff(nb, -1);
-    int64_t psz = 0;
     for (int b = 0; b < nb; ++b)
         if (t.nchild[b] == 0 && t.level[b] >= top) {
             poff[b] = psz;
@@ -375,6 +401,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         HIPCHK(h2d_gen_ops(p->d_work + off_pairb, npairs, p->d_work + off_tr, n_tr, tv, p->kappa,
                            p->d_o_m2l, p->d_g_m2l, p->d_o_tr, p->d_g_m2m, p->d_g_l2l, st));
     }
+    }  // h2d operator tables
     // -------- geometry check on the near pairs
     int* d_flag = nullptr;
     if ((rc = p->alloc(&d_flag, 1))) return rc;
@@ -409,7 +436,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         tot += (int64_t)nb * (6 * sizeof(int) + 2 * dim * sizeof(double) + sizeof(int));
         for (int q = 0; q < 4; ++q) tot += (int64_t)(t.off[q].size() + t.idx[q].size()) * sizeof(int);
         tot += (int64_t)work.size() * sizeof(int) + 2 * ecount * (int64_t)sizeof(cplx);
-        tot += (gsz + 2 * tsz + psz) * (int64_t)sizeof(cplx) + (npairs + 2 * nb) * 8 + (int64_t)pw.size() * 8;
+        tot += (gsz + 2 * tsz + psz) * (int64_t)sizeof(cplx) + (npairs + 2 * nb) * 8 + (int64_t)nlev * kPwStride * 8;
         p->bytes = tot;
     }
     // -------- description
@@ -450,8 +477,8 @@ int cfmm_plan(cfmm_plan_t* out, const cfmm_plan_desc* d)
     if (d->precision != CFMM_FP64 && d->precision != CFMM_MIXED) return fail(CFMM_EINVAL, "unknown precision");
     if (d->leaf_size < 0 || d->leaf_size > 4096) return fail(CFMM_EINVAL, "leaf_size must lie in [0, 4096]");
     if (d->separation < 0 || d->separation > 2) return fail(CFMM_EINVAL, "separation must be 0, 1 or 2");
-    if (!(d->dim == 2 && d->kernel == CFMM_HELMHOLTZ))
-        return fail(CFMM_ENOTSUP, "supported: dim 2 Helmholtz");
+    if (!((d->dim == 2 && d->kernel == CFMM_HELMHOLTZ) || (d->dim == 3 && d->kernel == CFMM_LAPLACE)))
+        return fail(CFMM_ENOTSUP, "supported: dim 2 Helmholtz, dim 3 Laplace");
     int rc = ensure_device_tables();
     if (rc) return rc;
     cfmm_plan_s* p = new cfmm_plan_s();
@@ -461,8 +488,10 @@ int cfmm_plan(cfmm_plan_t* out, const cfmm_plan_desc* d)
     p->tol = d->tol;
     p->n = d->n;
     p->precision = d->precision;
-    p->sep = d->separation ? d->separation : 1;
-    p->leaf_size = d->leaf_size ? d->leaf_size : 64;
+    // default separation: k = 1 in 2D; k = 2 in 3D, where the convergence of the
+    // continued expansions degrades fastest with the Lipschitz constant (Sec. 5.1, 6.5)
+    p->sep = d->separation ? d->separation : (d->dim == 3 ? 2 : 1);
+    p->leaf_size = d->leaf_size ? d->leaf_size : (d->dim == 2 ? 64 : 256);
     p->stream = (hipStream_t)d->stream;
     rc = plan_impl(p, d);
     if (rc) {
@@ -504,22 +533,41 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
     HIPCHK(mark(0));
     HIPCHK(launch_gather_density(sig, p->d_perm, n, p->d_sre, p->d_sim, st));
     HIPCHK(mark(1));
-    HIPCHK(h2d_p2m(W + p->off_p2m, p->n_p2m, tv, pv, p->d_poff, p->d_pvals, p->d_mpole, st));
-    HIPCHK(mark(2));
-    for (int l = nlev - 2; l >= top; --l)
-        HIPCHK(h2d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], tv, p->ops(), p->d_mpole, st));
-    HIPCHK(mark(3));
-    HIPCHK(h2d_m2l(W + p->off_m2l, p->n_m2l, tv, p->ops(), p->d_mpole, p->d_local, st));
-    HIPCHK(h2d_p2l(W + p->off_p2l, p->n_p2l, tv, pv, p->kappa, p->d_local, st));
-    HIPCHK(mark(4));
-    for (int l = top + 1; l < nlev; ++l)
-        HIPCHK(h2d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], tv, p->ops(), p->d_local, st));
-    HIPCHK(mark(5));
-    HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, top, std::max(1, p->pmax), tv, pv, p->kappa,
-                        p->d_poff, p->d_pvals, p->d_mpole, p->d_local, p->d_ufar, st));
-    HIPCHK(mark(6));
-    HIPCHK(h2d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out,
-                   p->precision, st));
+    if (p->dim == 2) {
+        HIPCHK(h2d_p2m(W + p->off_p2m, p->n_p2m, tv, pv, p->d_poff, p->d_pvals, p->d_mpole, st));
+        HIPCHK(mark(2));
+        for (int l = nlev - 2; l >= top; --l)
+            HIPCHK(h2d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], tv, p->ops(), p->d_mpole, st));
+        HIPCHK(mark(3));
+        HIPCHK(h2d_m2l(W + p->off_m2l, p->n_m2l, tv, p->ops(), p->d_mpole, p->d_local, st));
+        HIPCHK(h2d_p2l(W + p->off_p2l, p->n_p2l, tv, pv, p->kappa, p->d_local, st));
+        HIPCHK(mark(4));
+        for (int l = top + 1; l < nlev; ++l)
+            HIPCHK(h2d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], tv, p->ops(), p->d_local, st));
+        HIPCHK(mark(5));
+        HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, top, std::max(1, p->pmax), tv, pv, p->kappa,
+                            p->d_poff, p->d_pvals, p->d_mpole, p->d_local, p->d_ufar, st));
+        HIPCHK(mark(6));
+        HIPCHK(h2d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out,
+                       p->precision, st));
+    } else {
+        int P = p->pmax;
+        HIPCHK(l3d_p2m(W + p->off_p2m, p->n_p2m, P, tv, pv, p->d_mpole, st));
+        HIPCHK(mark(2));
+        for (int l = nlev - 2; l >= top; --l)
+            HIPCHK(l3d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], P, tv, p->d_mpole, st));
+        HIPCHK(mark(3));
+        HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_mpole, p->d_local, st));
+        HIPCHK(l3d_p2l(W + p->off_p2l, p->n_p2l, P, tv, pv, p->d_local, st));
+        HIPCHK(mark(4));
+        for (int l = top + 1; l < nlev; ++l)
+            HIPCHK(l3d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], P, tv, p->d_local, st));
+        HIPCHK(mark(5));
+        HIPCHK(l3d_leaf_far(W + p->off_leaves, p->nleaf, top, tv, pv, p->d_mpole, p->d_local,
+                            p->d_ufar, st));
+        HIPCHK(mark(6));
+        HIPCHK(l3d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->d_ufar, p->d_perm, out, st));
+    }
     HIPCHK(mark(7));
     if (!on_device) {
         HIPCHK(hipMemcpyAsync(potential, p->d_io_out, 2 * n * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -668,6 +716,29 @@ int cfmm_nterms(int dim, int kernel, double kappa, double w, int separation, dou
         separation > 2 || !(eps > 0) || pmax < 1 || pmax > kPMax2D)
         return fail(CFMM_EINVAL, "bad argument");
     return nterms_level(dim, separation, kappa, w, eps, pmax);
+}
+
+int cfmm_plan_export_expansions(cfmm_plan_t p, void* mpole, void* local, int64_t* offsets,
+                                int64_t* count)
+{
+    if (!p) return fail(CFMM_EINVAL, "plan is NULL");
+    const HostTree& t = p->tree;
+    int nb = t.nbox();
+    int64_t tot = 0;
+    for (int b = 0; b < nb; ++b) {
+        int64_t nc = 0;
+        if (t.level[b] >= t.top) {
+            int P = p->P[t.level[b]];
+            nc = p->dim == 2 ? 2 * P + 1 : (int64_t)(P + 1) * (P + 1);
+        }
+        if (offsets) offsets[b] = nc ? tot : -1;
+        tot += nc;
+    }
+    if (count) *count = tot;
+    HIPCHK(hipStreamSynchronize(p->stream));
+    if (mpole && tot) HIPCHK(hipMemcpy(mpole, p->d_mpole, tot * sizeof(cplx), hipMemcpyDeviceToHost));
+    if (local && tot) HIPCHK(hipMemcpy(local, p->d_local, tot * sizeof(cplx), hipMemcpyDeviceToHost));
+    return CFMM_OK;
 }
 
 int cfmm_set_profiling(cfmm_plan_t p, int enable)

@@ -95,6 +95,23 @@ hipError_t h2d_p2p(const int* leaves, int nleaf, const TreeView& tv, const Point
                    double kappa, const cplx* ufar, const int* perm, double* out, int mixed,
                    hipStream_t st);
 
+// 3D Laplace evaluation (l3d_kernels.hip); P is the common expansion length
+hipError_t l3d_p2m(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
+                   cplx* mpole, hipStream_t st);
+hipError_t l3d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
+                   cplx* local, hipStream_t st);
+hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mpole, hipStream_t st);
+hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const cplx* mpole,
+                   cplx* local, hipStream_t st);
+hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st);
+hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& tv,
+                        const PointsView& pv, const cplx* mpole, const cplx* local, cplx* ufar,
+                        hipStream_t st);
+hipError_t l3d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
+                   const cplx* ufar, const int* perm, double* out, hipStream_t st);
+size_t l3d_max_lds_m2l(int P);
+int l3d_pmax_supported();
+
 // host-side special functions for the expansion-length rule
 double h2d_nterms_crit(double kappa, double R, double r, int n);
 
