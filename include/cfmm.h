@@ -49,7 +49,7 @@ extern "C" {
 
 #define CFMM_OK 0
 #define CFMM_EINVAL (-1)     /* bad dim / kernel / kappa / tol / n / pointer */
-#define CFMM_ENOTSUP (-2)    /* combination not supported (e.g. 2D Laplace) */
+#define CFMM_ENOTSUP (-2)    /* combination not supported (2D Laplace) */
 #define CFMM_EGEOMETRY (-3)  /* non-finite coordinates, or Re r^2 <= 0 in a near pair */
 #define CFMM_ENOMEM (-4)     /* device allocation failed */
 #define CFMM_EHIP (-5)       /* a HIP runtime call failed (message has the HIP error) */
@@ -156,8 +156,10 @@ int cfmm_htree_export_list(cfmm_htree_t t, int which, int32_t* offsets, int32_t*
 int cfmm_htree_free(cfmm_htree_t t);
 
 /* Expansion length the plan uses for boxes of width w (Sec. 6.3): the smallest
- * n >= 1 with |H_n(kappa R) J_n(kappa r)| <= eps at n and n+1, R = (0.5+k) w,
- * r = sqrt(2)/2 w (2D Helmholtz); pmax + 1 if none up to pmax qualifies. */
+ * n >= 1 with |H_n(kappa R) J_n(kappa r)| <= eps (dim 2) or
+ * |h_n(kappa R) j_n(kappa r)| <= eps (dim 3) at n and n+1, R = (0.5+k) w,
+ * r = sqrt(dim)/2 w; pmax + 1 if none up to pmax qualifies.  Helmholtz only;
+ * pmax <= 63 (dim 2) or 50 (dim 3). */
 int cfmm_nterms(int dim, int kernel, double kappa, double w, int separation, double eps, int pmax);
 
 #ifdef __cplusplus

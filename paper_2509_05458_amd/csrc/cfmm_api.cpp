@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "h3d_host.hpp"
 #include "kernels.hpp"
 #include "tree_host.hpp"
 
@@ -45,6 +46,7 @@ int ensure_device_tables()
     std::lock_guard<std::mutex> lk(g_init_mu);
     if (g_inited.count(dev)) return CFMM_OK;
     HIPCHK(h2d_init_tables(dev));
+    HIPCHK(h3d_init_tables(dev));
     g_inited.insert(dev);
     return CFMM_OK;
 }
@@ -65,6 +67,7 @@ struct cfmm_plan_s {
     std::vector<double> cen_h;   // complex centres after planning: [b][d] (re, im)
 
     std::vector<void*> allocs;
+    std::vector<size_t> alloc_sz;
     int64_t bytes = 0;
 
     int* d_perm = nullptr;
@@ -86,6 +89,23 @@ struct cfmm_plan_s {
     int64_t* d_poff = nullptr;   // per box: offset of its points' expansion values
     cplx* d_pvals = nullptr;
     double *d_io_in = nullptr, *d_io_out = nullptr;       // staging for host pointers
+    // 3D Helmholtz: per-level kappa w and scale; translation stages and chunks
+    struct H3Chunk {
+        int pair_begin, np, grp_begin, ng, goff_off;
+    };
+    struct H3Stage {
+        int kind, level, Ps, Pt, nq, src_h, trg_h;
+        double ks, sc, rs_s, inv_w;
+        int64_t o_nodes, o_W, o_T;
+        int64_t sFG, sA, sR, sfg, sB, per_pair;
+        std::vector<H3Chunk> chunks;
+    };
+    std::vector<H3Stage> h3;
+    double *d_h3_kw = nullptr, *d_h3_sc = nullptr, *d_h3_tabd = nullptr, *d_h3_eq = nullptr;
+    cplx *d_h3_tabc = nullptr, *d_h3_scr = nullptr;
+    int *d_h3_src = nullptr, *d_h3_dst = nullptr, *d_h3_gdst = nullptr, *d_h3_goff = nullptr;
+    int64_t h3_eq_half = 0;
+    int64_t ecount = 0;
     int64_t info[16];
 
     bool prof = false;
@@ -102,6 +122,7 @@ struct cfmm_plan_s {
         if (e != hipSuccess)
             return fail(CFMM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
         allocs.push_back(q);
+        alloc_sz.push_back(count * sizeof(T));
         bytes += (int64_t)(count * sizeof(T));
         *p = (T*)q;
         return CFMM_OK;
@@ -178,6 +199,174 @@ int nterms_laplace(int dim, int sep, double eps)
     int n = 1;
     while (pow(ratio, n) > eps && n < 200) ++n;
     return n;
+}
+
+// 3D Helmholtz translation stages (Sec. 5.3, point-and-shoot with sampled
+// rotations and coaxial translations): per stage (M2M, M2L or L2L at one
+// level) the pairs grouped by target box, the Gauss-Legendre nodes, the
+// projection weights W, the target radial constants and the chunking of the
+// pairs over a bounded scratch region.
+int plan_h3d(cfmm_plan_s* p, int nlev, int top)
+{
+    const HostTree& t = p->tree;
+    int nb = t.nbox();
+    double kappa = p->kappa;
+    std::vector<double> kw(nlev, 0.0), sc(nlev, 1.0), wl(nlev);
+    for (int l = 0; l < nlev; ++l) {
+        wl[l] = p->D * ldexp(1.0, -l);
+        kw[l] = kappa * wl[l];
+        sc[l] = std::min(1.0, kw[l]);
+    }
+    std::vector<double> tabd;
+    std::vector<cplx> tabc;
+    std::vector<int> psrc, pdst, gdst, goff;
+    const int64_t cap_bytes = (int64_t)512 << 20;
+    int64_t scr = 0;
+    auto add_stage = [&](int kind, int level, const std::vector<int>& groups,
+                         const std::vector<std::vector<int>>& srcs) {
+        cfmm_plan_s::H3Stage S;
+        S.kind = kind;
+        S.level = level;
+        int ls = kind == 0 ? level + 1 : (kind == 1 ? level : level - 1);   // source level
+        S.Ps = p->P[ls];
+        S.Pt = p->P[level];
+        int Pm = std::max(S.Ps, S.Pt);
+        S.nq = std::max((int)(2.5 * Pm), Pm + 2);
+        S.src_h = kind != 2;
+        S.trg_h = kind == 0;
+        S.ks = kw[ls];
+        S.sc = sc[ls];
+        S.inv_w = 1.0 / wl[ls];
+        double rs = kind == 0 ? 1.5 * wl[level] : 0.5 * sqrt(3.0) * wl[level];   // physical radius
+        S.rs_s = rs / wl[ls];
+        // nodes and projection weights
+        S.o_nodes = (int64_t)tabd.size();
+        std::vector<double> gx(S.nq), gw(S.nq);
+        gauss_legendre(S.nq, gx.data(), gw.data());
+        for (int j = 0; j < S.nq; ++j) tabd.push_back(sqrt(std::max(0.0, 1.0 - gx[j] * gx[j])));
+        for (int j = 0; j < S.nq; ++j) tabd.push_back(gx[j]);
+        S.o_W = (int64_t)tabd.size();
+        int ntri = (S.Pt + 1) * (S.Pt + 2) / 2;
+        size_t w0 = tabd.size();
+        tabd.resize(w0 + (size_t)ntri * S.nq);
+        std::vector<double> col(ntri);
+        for (int j = 0; j < S.nq; ++j) {
+            schmidt_column_table(S.Pt, gx[j], sqrt(std::max(0.0, 1.0 - gx[j] * gx[j])), col.data());
+            for (int n = 0; n <= S.Pt; ++n)
+                for (int m = 0; m <= n; ++m) {
+                    int k = n * (n + 1) / 2 + m;
+                    tabd[w0 + (size_t)k * S.nq + j] = 0.5 * (2.0 * n + 1.0) * gw[j] * col[k];
+                }
+        }
+        // target radial function T_n at rs and its derivative in source-scaled units
+        S.o_T = (int64_t)tabc.size();
+        std::vector<double> jj(S.Pt + 1), yy(S.Pt + 1), jd(S.Pt + 1), yd(S.Pt + 1);
+        sph_bessel_real(S.Pt, kappa * rs, jj.data(), yy.data(), jd.data(), yd.data());
+        std::vector<cplx> Tc(S.Pt + 1), Tdc(S.Pt + 1);
+        double sct = sc[level], f = 1.0;
+        for (int n = 0; n <= S.Pt; ++n) {
+            cplx T, Td;
+            if (S.trg_h) {
+                T = mk(jj[n] * f, yy[n] * f);
+                Td = mk(wl[ls] * kappa * jd[n] * f, wl[ls] * kappa * yd[n] * f);
+            } else {
+                T = mk(jj[n] / f, 0.0);
+                Td = mk(wl[ls] * kappa * jd[n] / f, 0.0);
+            }
+            double den = cabs2(T) + cabs2(Td);
+            Tc[n] = conj(T) * (1.0 / den);
+            Tdc[n] = conj(Td) * (1.0 / den);
+            f *= sct;
+        }
+        tabc.insert(tabc.end(), Tc.begin(), Tc.end());
+        tabc.insert(tabc.end(), Tdc.begin(), Tdc.end());
+        // per-pair scratch strides (complex units)
+        int64_t J = 2 * Pm + 1;
+        S.sFG = 2 * (int64_t)(Pm + 1) * J;
+        S.sA = (int64_t)(Pm + 1) * (Pm + 1);
+        S.sR = (int64_t)(S.Ps + 2) * S.nq;
+        S.sfg = 2 * (int64_t)(2 * S.Ps + 1) * S.nq;
+        S.sB = (int64_t)(S.Pt + 1) * (S.Pt + 1);
+        S.per_pair = 10 + S.sFG + S.sA + S.sR + S.sfg + S.sB;
+        int64_t maxg = 1;
+        for (auto& v : srcs) maxg = std::max<int64_t>(maxg, (int64_t)v.size());
+        int64_t cap = std::max<int64_t>(maxg, cap_bytes / (S.per_pair * (int64_t)sizeof(cplx)));
+        // chunks of whole groups
+        size_t g = 0;
+        while (g < groups.size()) {
+            cfmm_plan_s::H3Chunk C;
+            C.pair_begin = (int)psrc.size();
+            C.grp_begin = (int)gdst.size();
+            C.goff_off = (int)goff.size();
+            int np = 0, ng = 0;
+            goff.push_back(0);
+            while (g < groups.size() && np + (int64_t)srcs[g].size() <= cap) {
+                for (int a : srcs[g]) {
+                    psrc.push_back(a);
+                    pdst.push_back(groups[g]);
+                }
+                np += (int)srcs[g].size();
+                gdst.push_back(groups[g]);
+                goff.push_back(np);
+                ++ng;
+                ++g;
+            }
+            C.np = np;
+            C.ng = ng;
+            S.chunks.push_back(C);
+            scr = std::max(scr, (int64_t)np * S.per_pair);
+        }
+        p->h3.push_back(S);
+    };
+    // M2M at parent level l (children at l + 1), l = nlev-2 .. top
+    for (int l = nlev - 2; l >= top; --l) {
+        std::vector<int> groups;
+        std::vector<std::vector<int>> srcs;
+        for (int b = t.lvl_beg[l]; b < t.lvl_beg[l + 1]; ++b)
+            if (t.nchild[b] > 0) {
+                groups.push_back(b);
+                std::vector<int> c;
+                for (int k = 0; k < t.nchild[b]; ++k) c.push_back(t.child0[b] + k);
+                srcs.push_back(c);
+            }
+        if (!groups.empty()) add_stage(0, l, groups, srcs);
+    }
+    // M2L at level l
+    for (int l = top; l < nlev; ++l) {
+        std::vector<int> groups;
+        std::vector<std::vector<int>> srcs;
+        for (int b = t.lvl_beg[l]; b < t.lvl_beg[l + 1]; ++b)
+            if (t.off[1][b + 1] > t.off[1][b]) {
+                groups.push_back(b);
+                srcs.emplace_back(t.idx[1].begin() + t.off[1][b], t.idx[1].begin() + t.off[1][b + 1]);
+            }
+        if (!groups.empty()) add_stage(1, l, groups, srcs);
+    }
+    // L2L into level l from its parents at l - 1
+    for (int l = top + 1; l < nlev; ++l) {
+        std::vector<int> groups;
+        std::vector<std::vector<int>> srcs;
+        for (int b = t.lvl_beg[l]; b < t.lvl_beg[l + 1]; ++b) {
+            groups.push_back(b);
+            srcs.push_back({t.parent[b]});
+        }
+        if (!groups.empty()) add_stage(2, l, groups, srcs);
+    }
+    int pm = 1;
+    for (int l = 0; l < nlev; ++l) pm = std::max(pm, p->P[l]);
+    int ntri = (pm + 1) * (pm + 2) / 2;
+    std::vector<double> eq(2 * (size_t)ntri);
+    equator_table(pm, eq.data(), eq.data() + ntri);
+    p->h3_eq_half = ntri;
+    int rc;
+    if ((rc = upload(p, &p->d_h3_kw, kw)) || (rc = upload(p, &p->d_h3_sc, sc)) ||
+        (rc = upload(p, &p->d_h3_tabd, tabd)) || (rc = upload(p, &p->d_h3_tabc, tabc)) ||
+        (rc = upload(p, &p->d_h3_eq, eq)) || (rc = upload(p, &p->d_h3_src, psrc)) ||
+        (rc = upload(p, &p->d_h3_dst, pdst)) || (rc = upload(p, &p->d_h3_gdst, gdst)) ||
+        (rc = upload(p, &p->d_h3_goff, goff)) || (rc = p->alloc(&p->d_h3_scr, std::max<int64_t>(scr, 1))))
+        return rc;
+    (void)nb;
+    return CFMM_OK;
 }
 
 int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
@@ -298,6 +487,20 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
             p->P[l] = m;
             pmax = std::max(pmax, m);
         }
+    } else if (p->kernel == CFMM_HELMHOLTZ) {
+        // 3D Helmholtz: |h_n(kR) j_n(kr)| <= eps at n and n+1 (Sec. 6.3) with
+        // eps = tol/10, as in 2D; coordinates of level l are scaled by 1/w_l
+        for (int l = top; l < nlev; ++l) {
+            double w = p->D * ldexp(1.0, -l);
+            p->rs[l] = 1.0 / w;
+            int m = h3d_nterms(p->kappa, w, p->sep, 0.1 * p->tol, kPMaxH3);
+            if (m > kPMaxH3)
+                return fail(CFMM_ERANGE, "expansion length above the supported maximum (" +
+                                             std::to_string(kPMaxH3) + ") at level " + std::to_string(l) +
+                                             "; the boxes are too many wavelengths wide");
+            p->P[l] = m;
+            pmax = std::max(pmax, m);
+        }
     } else {
         // 3D Laplace: (r/R)^n <= tol with R = (0.5 + k) w, r = sqrt(3)/2 w, the same
         // at every level; coordinates of level l are scaled by 1/w_l
@@ -322,6 +525,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
             ecount += ncoef(t.level[b]);
         }
     if (ecount > (int64_t)0x7fffffff) return fail(CFMM_ERANGE, "expansion storage above 2^31 entries");
+    p->ecount = ecount;
     if ((rc = upload(p, &p->d_eoff, eoff)) || (rc = upload(p, &p->d_P, p->P)) || (rc = upload(p, &p->d_rs, p->rs)))
         return rc;
     // -------- work lists
@@ -402,6 +606,8 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
                            p->d_o_m2l, p->d_g_m2l, p->d_o_tr, p->d_g_m2m, p->d_g_l2l, st));
     }
     }  // h2d operator tables
+    if (dim == 3 && p->kernel == CFMM_HELMHOLTZ)
+        if ((rc = plan_h3d(p, nlev, top))) return rc;
     // -------- geometry check on the near pairs
     int* d_flag = nullptr;
     if ((rc = p->alloc(&d_flag, 1))) return rc;
@@ -419,25 +625,18 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         (rc = p->alloc(&p->d_mpole, ecount)) || (rc = p->alloc(&p->d_local, ecount)) ||
         (rc = p->alloc(&p->d_ufar, n)))
         return rc;
-    // -------- release planning scratch
+    // -------- release planning scratch; the plan keeps the rest resident
     HIPCHK(hipStreamSynchronize(st));
     for (void* q : {(void*)d_pts, (void*)d_part, (void*)d_bb, (void*)d_keys, (void*)d_keys2,
                     (void*)d_idx2, (void*)d_scr, (void*)d_delta, (void*)d_flag}) {
         auto it = std::find(p->allocs.begin(), p->allocs.end(), q);
         if (it != p->allocs.end()) {
+            size_t k = it - p->allocs.begin();
+            p->bytes -= (int64_t)p->alloc_sz[k];
             p->allocs.erase(it);
+            p->alloc_sz.erase(p->alloc_sz.begin() + k);
             hipFree(q);
         }
-    }
-    p->bytes = 0;  // recount the resident footprint
-    {
-        int64_t tot = 0;
-        tot += (int64_t)n * (sizeof(int) + 2 * dim * sizeof(double) + 2 * sizeof(double) + sizeof(cplx));
-        tot += (int64_t)nb * (6 * sizeof(int) + 2 * dim * sizeof(double) + sizeof(int));
-        for (int q = 0; q < 4; ++q) tot += (int64_t)(t.off[q].size() + t.idx[q].size()) * sizeof(int);
-        tot += (int64_t)work.size() * sizeof(int) + 2 * ecount * (int64_t)sizeof(cplx);
-        tot += (gsz + 2 * tsz + psz) * (int64_t)sizeof(cplx) + (npairs + 2 * nb) * 8 + (int64_t)nlev * kPwStride * 8;
-        p->bytes = tot;
     }
     // -------- description
     int64_t p2p = 0, m2l = (int64_t)t.idx[1].size();
@@ -477,8 +676,8 @@ int cfmm_plan(cfmm_plan_t* out, const cfmm_plan_desc* d)
     if (d->precision != CFMM_FP64 && d->precision != CFMM_MIXED) return fail(CFMM_EINVAL, "unknown precision");
     if (d->leaf_size < 0 || d->leaf_size > 4096) return fail(CFMM_EINVAL, "leaf_size must lie in [0, 4096]");
     if (d->separation < 0 || d->separation > 2) return fail(CFMM_EINVAL, "separation must be 0, 1 or 2");
-    if (!((d->dim == 2 && d->kernel == CFMM_HELMHOLTZ) || (d->dim == 3 && d->kernel == CFMM_LAPLACE)))
-        return fail(CFMM_ENOTSUP, "supported: dim 2 Helmholtz, dim 3 Laplace");
+    if (d->dim == 2 && d->kernel == CFMM_LAPLACE)
+        return fail(CFMM_ENOTSUP, "supported: dim 2 Helmholtz, dim 3 Laplace and Helmholtz");
     int rc = ensure_device_tables();
     if (rc) return rc;
     cfmm_plan_s* p = new cfmm_plan_s();
@@ -550,6 +749,54 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         HIPCHK(mark(6));
         HIPCHK(h2d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out,
                        p->precision, st));
+    } else if (p->kernel == CFMM_HELMHOLTZ) {
+        H3DLevels hl{p->d_h3_kw, p->d_h3_sc};
+        HIPCHK(hipMemsetAsync(p->d_mpole, 0, p->ecount * sizeof(cplx), st));
+        HIPCHK(hipMemsetAsync(p->d_local, 0, p->ecount * sizeof(cplx), st));
+        HIPCHK(h3d_p2m(W + p->off_p2m, p->n_p2m, p->pmax, tv, pv, hl, p->d_mpole, st));
+        HIPCHK(mark(2));
+        auto run = [&](int kind, const cplx* src, cplx* dst) -> int {
+            for (const auto& S : p->h3) {
+                if (S.kind != kind) continue;
+                for (const auto& C : S.chunks) {
+                    H3DTr tr;
+                    tr.np = C.np;
+                    tr.src = p->d_h3_src + C.pair_begin;
+                    tr.dst = p->d_h3_dst + C.pair_begin;
+                    tr.Ps = S.Ps; tr.Pt = S.Pt; tr.nq = S.nq;
+                    tr.src_h = S.src_h; tr.trg_h = S.trg_h;
+                    tr.ks = S.ks; tr.sc = S.sc; tr.rs = S.rs_s; tr.inv_w = S.inv_w;
+                    tr.sth = p->d_h3_tabd + S.o_nodes;
+                    tr.cth = tr.sth + S.nq;
+                    tr.W = p->d_h3_tabd + S.o_W;
+                    tr.Tc = p->d_h3_tabc + S.o_T;
+                    tr.Tdc = tr.Tc + S.Pt + 1;
+                    int64_t np = C.np;
+                    tr.geo = p->d_h3_scr;
+                    tr.FG = tr.geo + 10 * np; tr.sFG = S.sFG;
+                    tr.A = tr.FG + S.sFG * np; tr.sA = S.sA;
+                    tr.R = tr.A + S.sA * np; tr.sR = S.sR;
+                    tr.fg = tr.R + S.sR * np; tr.sfg = S.sfg;
+                    tr.B = tr.fg + S.sfg * np; tr.sB = S.sB;
+                    HIPCHK(h3d_translate(tr, tv, p->d_eoff, src, p->d_h3_gdst + C.grp_begin,
+                                         p->d_h3_goff + C.goff_off, C.ng, p->d_eoff, dst, p->d_h3_eq,
+                                         p->d_h3_eq + p->h3_eq_half, st));
+                }
+            }
+            return CFMM_OK;
+        };
+        int rc;
+        if ((rc = run(0, p->d_mpole, p->d_mpole))) return rc;
+        HIPCHK(mark(3));
+        if ((rc = run(1, p->d_mpole, p->d_local))) return rc;
+        HIPCHK(h3d_p2l(W + p->off_p2l, p->n_p2l, p->pmax, tv, pv, hl, p->d_local, st));
+        HIPCHK(mark(4));
+        if ((rc = run(2, p->d_local, p->d_local))) return rc;
+        HIPCHK(mark(5));
+        HIPCHK(h3d_leaf_far(W + p->off_leaves, p->nleaf, top, std::max(1, p->pmax), tv, pv, hl,
+                            p->d_mpole, p->d_local, p->d_ufar, st));
+        HIPCHK(mark(6));
+        HIPCHK(h3d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out, st));
     } else {
         int P = p->pmax;
         HIPCHK(l3d_p2m(W + p->off_p2m, p->n_p2m, P, tv, pv, p->d_mpole, st));
@@ -712,9 +959,11 @@ int cfmm_htree_free(cfmm_htree_t h)
 
 int cfmm_nterms(int dim, int kernel, double kappa, double w, int separation, double eps, int pmax)
 {
-    if (dim != 2 || kernel != CFMM_HELMHOLTZ || !(kappa > 0) || !(w > 0) || separation < 1 ||
-        separation > 2 || !(eps > 0) || pmax < 1 || pmax > kPMax2D)
+    if ((dim != 2 && dim != 3) || kernel != CFMM_HELMHOLTZ || !(kappa > 0) || !(w > 0) ||
+        separation < 1 || separation > 2 || !(eps > 0) || pmax < 1 ||
+        pmax > (dim == 2 ? kPMax2D : kPMaxH3))
         return fail(CFMM_EINVAL, "bad argument");
+    if (dim == 3) return h3d_nterms(kappa, w, separation, eps, pmax);
     return nterms_level(dim, separation, kappa, w, eps, pmax);
 }
 

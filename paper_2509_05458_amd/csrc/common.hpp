@@ -11,6 +11,7 @@ namespace cfmm {
 constexpr int kPMax2D = 63;          // 2D expansions hold 2P+1 <= 127 coefficients
 constexpr int kNCoef2DMax = 2 * kPMax2D + 1;
 constexpr int kPMax3D = 40;          // 3D expansions hold (P+1)^2 coefficients
+constexpr int kPMaxH3 = 50;          // 3D Helmholtz expansion length limit
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kEuler = 0.57721566490153286060651209008240243;
 constexpr int kGHHalf = 24;          // 48-point Gauss-Hermite rule, positive half

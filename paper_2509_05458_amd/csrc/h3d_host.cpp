@@ -1,0 +1,165 @@
+// Host-side plan-time mathematics of the 3D Helmholtz path.
+#include "h3d_host.hpp"
+
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+namespace cfmm {
+
+namespace {
+
+// j_n for n <= nmax by the power series j_n(x) = x^n/(2n+1)!! sum_k (-x^2/2)^k
+// / (k! prod_{i<=k} (2n+2i+1)) at the two top orders, then downward
+// recurrence (stable for the regular solution); valid while x^2 is small
+// next to 2(2 nmax + 5), so the series has no cancellation.
+void jn_series_down(int nmax, double x, double* j)
+{
+    auto series = [&](int n) {
+        double pref = 1.0;
+        for (int i = 1; i <= n; ++i) pref *= x / (2.0 * i + 1.0);
+        double term = 1.0, sum = 1.0, q = -0.5 * x * x;
+        for (int k = 1; k < 200; ++k) {
+            term *= q / ((double)k * (2.0 * n + 2.0 * k + 1.0));
+            sum += term;
+            if (fabs(term) < 1e-18 * fabs(sum)) break;
+        }
+        return pref * sum;
+    };
+    j[nmax] = series(nmax);
+    if (nmax == 0) return;
+    j[nmax - 1] = series(nmax - 1);
+    for (int n = nmax - 1; n >= 1; --n) j[n - 1] = (2.0 * n + 1.0) / x * j[n] - j[n + 1];
+}
+
+// j_n by Miller's backward recurrence normalised on j_0 and j_1 (least squares
+// on both, so a zero of either costs nothing).
+void jn_miller(int nmax, double x, double* j)
+{
+    int start = nmax + 20 + (int)(x);
+    std::vector<double> t(start + 2, 0.0);
+    t[start + 1] = 0.0;
+    t[start] = 1e-30;
+    for (int n = start; n >= 1; --n) {
+        t[n - 1] = (2.0 * n + 1.0) / x * t[n] - t[n + 1];
+        if (fabs(t[n - 1]) > 1e250) {
+            for (int k = n - 1; k <= start; ++k) t[k] *= 1e-250;
+        }
+    }
+    double j0 = sin(x) / x, j1 = sin(x) / (x * x) - cos(x) / x;
+    double nrm = std::max(fabs(t[0]), fabs(t[1]));
+    double a0 = t[0] / nrm, a1 = t[1] / nrm;
+    double s = (j0 * a0 + j1 * a1) / (a0 * a0 + a1 * a1) / nrm;
+    for (int n = 0; n <= nmax; ++n) j[n] = s * t[n];
+}
+
+}  // namespace
+
+void sph_bessel_real(int nmax, double x, double* j, double* y, double* jd, double* yd)
+{
+    std::vector<double> jj(nmax + 2), yy(nmax + 2);
+    if (x * x < 2.0 * (2.0 * (nmax + 1) + 5.0)) jn_series_down(nmax + 1, x, jj.data());
+    else jn_miller(nmax + 1, x, jj.data());
+    yy[0] = -cos(x) / x;
+    if (nmax + 1 >= 1) yy[1] = -cos(x) / (x * x) - sin(x) / x;
+    for (int n = 1; n <= nmax; ++n) yy[n + 1] = (2.0 * n + 1.0) / x * yy[n] - yy[n - 1];
+    for (int n = 0; n <= nmax; ++n) {
+        if (j) j[n] = jj[n];
+        if (y) y[n] = yy[n];
+        if (jd) jd[n] = n / x * jj[n] - jj[n + 1];
+        if (yd) yd[n] = n / x * yy[n] - yy[n + 1];
+    }
+}
+
+void gauss_legendre(int n, double* x, double* w)
+{
+    for (int i = 0; i < n; ++i) {
+        double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+        double pp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            pp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / pp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        pp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+int h3d_nterms(double kappa, double w, int sep, double eps, int pmax)
+{
+    double R = (0.5 + sep) * w, r = sqrt(3.0) * 0.5 * w;
+    std::vector<double> jR(pmax + 3), yR(pmax + 3), jr(pmax + 3);
+    sph_bessel_real(pmax + 2, kappa * R, jR.data(), yR.data(), nullptr, nullptr);
+    sph_bessel_real(pmax + 2, kappa * r, jr.data(), nullptr, nullptr, nullptr);
+    auto crit = [&](int n) { return hypot(jR[n], yR[n]) * fabs(jr[n]); };
+    for (int n = 1; n <= pmax; ++n)
+        if (crit(n) <= eps && crit(n + 1) <= eps) return n;
+    return pmax + 1;
+}
+
+// Column recurrence of the Schmidt-normalised solid harmonics at a unit vector
+// with w = x + iy real (y = 0): S_m^m = c_m x^m, then
+// S_n^m = ((2n-1) z S_{n-1}^m - sqrt((n+m-1)(n-m-1)) S_{n-2}^m) / sqrt((n-m)(n+m)).
+void schmidt_column_table(int P, double cth, double sth, double* out)
+{
+    double d = 1.0;
+    for (int m = 0; m <= P; ++m) {
+        if (m > 0) d *= sth * sqrt((2.0 * m - 1.0) / (2.0 * m));
+        double a = d;
+        out[m * (m + 1) / 2 + m] = a;
+        if (m + 1 > P) continue;
+        double b = sqrt(2.0 * m + 1.0) * cth * d;
+        out[(m + 1) * (m + 2) / 2 + m] = b;
+        for (int n = m + 2; n <= P; ++n) {
+            double c = ((2.0 * n - 1.0) * cth * b - sqrt((double)(n + m - 1) * (n - m - 1)) * a) /
+                       sqrt((double)(n - m) * (n + m));
+            out[n * (n + 1) / 2 + m] = c;
+            a = b;
+            b = c;
+        }
+    }
+}
+
+// At e_x: z = 0, w = 1; along v = (0, 0, -1): dw = 0, dz = -1 (tangent, so r^2
+// is constant to first order).
+void equator_table(int P, double* p0, double* d0)
+{
+    double d = 1.0;
+    for (int m = 0; m <= P; ++m) {
+        if (m > 0) d *= sqrt((2.0 * m - 1.0) / (2.0 * m));
+        double q0 = 1.0, dq0 = 0.0;
+        p0[m * (m + 1) / 2 + m] = d * q0;
+        d0[m * (m + 1) / 2 + m] = d * dq0;
+        if (m + 1 > P) continue;
+        double q1 = 0.0, dq1 = -sqrt(2.0 * m + 1.0);
+        p0[(m + 1) * (m + 2) / 2 + m] = d * q1;
+        d0[(m + 1) * (m + 2) / 2 + m] = d * dq1;
+        for (int n = m + 2; n <= P; ++n) {
+            double e = sqrt((double)(n + m - 1) * (n - m - 1)), f = sqrt((double)(n - m) * (n + m));
+            double q2 = (0.0 - e * q0) / f;
+            double dq2 = ((2.0 * n - 1.0) * (-1.0 * q1 + 0.0 * dq1) - e * dq0) / f;
+            p0[n * (n + 1) / 2 + m] = d * q2;
+            d0[n * (n + 1) / 2 + m] = d * dq2;
+            q0 = q1; q1 = q2; dq0 = dq1; dq1 = dq2;
+        }
+    }
+}
+
+}  // namespace cfmm

@@ -1,0 +1,790 @@
+// 3D Helmholtz complex-coordinate FMM kernels (Sec. 5.3 and the multilevel
+// steps of Sec. 6.4).
+//
+// Expansions use Schmidt-normalised solid harmonics S_n^m(x) = rho^n Y_n^m,
+// evaluated by their Cartesian column recurrences at complex points
+// (w = x + iy for m >= 0, x - iy for m < 0, c_m = prod_k sqrt((2k-1)/(2k))):
+//   S_|m|^m = c_|m| w^|m|,
+//   S_n^m = ((2n-1) z S_{n-1}^m - sqrt((n+|m|-1)(n-|m|-1)) r2 S_{n-2}^m) / sqrt((n-|m|)(n+|m|)),
+// so that P_n(cos g) = sum_m Y_n^m(x) Y_n^-m(y) and
+//   h_0(k|X - Y|) = sum_n (2n+1) j_n(k rho_Y) h_n(k rho_X) sum_m Y_n^-m(Y) Y_n^m(X).
+// With box width w, kw = kappa w and the level scale sc = min(1, kw), in
+// coordinates scaled by 1/w:
+//   A_n(x) = j_n(kw rho) / (sc rho)^n     (entire in rho^2 = x.x)
+//   B_n(x) = h_n(kw rho) sc^n / rho^n     (principal rho)
+//   P2M  Mhat_n^m = (2n+1) sum sigma A_n(y) S_n^-m(y),   u = (i kappa / 4pi) sum Mhat B_n(x) S_n^m(x)
+//   P2L  Lhat_n^m = (2n+1) sum sigma B_n(y) S_n^-m(y),   u = (i kappa / 4pi) sum Lhat A_n(x) S_n^m(x).
+//
+// Translations (M2M, M2L, L2L) follow the point-and-shoot scheme of Sec. 5.2
+// and Sec. 5.3: rotate the source expansion so that the offset D lies on the
+// z axis, translate coaxially, rotate back.  Both steps are done by sampling
+// and projection:
+//  * rotation: a complex orthogonal Q (Q Q^T = I) with Q e_z = D / rho_D; the
+//    degree-n part f_n = sum_m a_n^m S_n^m is sampled at Q y_j on the equator
+//    y_j = (cos phi_j, sin phi_j, 0), phi_j = 2 pi j / (2P+1), together with its
+//    derivative along -Q e_z (the polar derivative), and a DFT over j returns the
+//    rotated coefficients (divided by S_n^m(e_x) when n+m is even, by its polar
+//    derivative when n+m is odd);
+//  * coaxial translation: the rotated source field is sampled, per azimuthal
+//    order m, at Gauss-Legendre nodes of a sphere of radius rs about the new
+//    centre, together with its radial derivative, and projected on the
+//    associated Legendre functions; T_n and T'_n (the target radial function and
+//    its derivative at rs) combine the two by least squares, so no zero of
+//    j_n ends the translation.
+// Every pair of a level runs the same seven batched kernels (geometry, rotate
+// sample, DFT, radial, coaxial sample, projection, rotate back, accumulate)
+// over a scratch region, and each target box sums its pairs in a fixed order.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace cfmm {
+
+namespace {
+
+constexpr int kT = kPMaxH3 + 3;       // recurrence tables cover n <= kPMaxH3 + 2
+__constant__ double c_ca[kT * kT];    // sqrt((n+m-1)(n-m-1))            [n * kT + m]
+__constant__ double c_cb[kT * kT];    // 1 / sqrt((n-m)(n+m)),  n > m
+__constant__ double c_cs[kT];         // c_m = prod_{k<=m} sqrt((2k-1)/(2k))
+__constant__ double c_ck[kT];         // sqrt((2m-1)/(2m))
+
+__device__ inline int hnm(int n, int m) { return n * n + n + m; }
+__device__ inline int tri(int n, int m) { return n * (n + 1) / 2 + m; }
+
+struct V3 {
+    cplx x, y, z;
+};
+
+__device__ inline cplx dot(const V3& a, const V3& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// One column step: (q0, q1) = (Q_{n-2}, Q_{n-1}) -> Q_n, with its derivative
+// along a direction where z' = dz and (r2)' = dr2.
+__device__ inline void col_step(int n, int am, cplx z, cplx dz, cplx r2, cplx dr2, cplx& q0, cplx& q1,
+                                cplx& dq0, cplx& dq1)
+{
+    double a = c_ca[n * kT + am], b = c_cb[n * kT + am], s = 2.0 * n - 1.0;
+    cplx q2 = (s * (z * q1) - a * (r2 * q0)) * b;
+    cplx dq2 = (s * (dz * q1 + z * dq1) - a * (dr2 * q0 + r2 * dq0)) * b;
+    q0 = q1; q1 = q2; dq0 = dq1; dq1 = dq2;
+}
+
+__device__ inline void col_step_nd(int n, int am, cplx z, cplx r2, cplx& q0, cplx& q1)
+{
+    double a = c_ca[n * kT + am], b = c_cb[n * kT + am], s = 2.0 * n - 1.0;
+    cplx q2 = (s * (z * q1) - a * (r2 * q0)) * b;
+    q0 = q1; q1 = q2;
+}
+
+// Radial functions, written to out[n * stride] for n = 0..N.
+// A_n = j_n(kw rho) / (sc rho)^n: power series at the two top orders and
+// downward recurrence A_{n-1} = (2n+1)(sc/kw) A_n - sc^2 rho^2 A_{n+1} while
+// |z|^2 < 2(2N + 5); otherwise Miller's backward recurrence for j_n(z),
+// normalised on j_0 and j_1 by least squares, then divided by (sc rho)^n.
+__device__ void radial_j(cplx rho2, double kw, double sc, int N, cplx* out, int stride)
+{
+    cplx z2 = (kw * kw) * rho2;
+    if (cabs1(z2) < 2.0 * (2.0 * N + 5.0)) {
+        auto series = [&](int n) {
+            double pref = 1.0, g = kw / sc;
+            for (int i = 1; i <= n; ++i) pref *= g / (2.0 * i + 1.0);
+            cplx term = mk(1.0, 0.0), sum = mk(1.0, 0.0), q = -0.5 * z2;
+            for (int k = 1; k < 400; ++k) {
+                term = term * q * (1.0 / ((double)k * (2.0 * n + 2.0 * k + 1.0)));
+                sum += term;
+                if (cabs2(term) < 1e-36 * cabs2(sum)) break;
+            }
+            return pref * sum;
+        };
+        cplx aN = series(N);
+        out[N * stride] = aN;
+        if (N == 0) return;
+        cplx aN1 = series(N - 1);
+        out[(N - 1) * stride] = aN1;
+        cplx s2r2 = (sc * sc) * rho2;
+        double g = sc / kw;
+        cplx hi = aN, mid = aN1;
+        for (int n = N - 1; n >= 1; --n) {
+            cplx lo = ((2.0 * n + 1.0) * g) * mid - s2r2 * hi;
+            out[(n - 1) * stride] = lo;
+            hi = mid;
+            mid = lo;
+        }
+        return;
+    }
+    cplx rho = csqrt_p(rho2);
+    cplx z = kw * rho;
+    cplx iz = cinv(z);
+    int start = N + 24 + (int)cabs1(z);
+    cplx t1 = mk(0.0, 0.0), t0 = mk(1e-30, 0.0);   // t_{n+1}, t_n at n = start
+    for (int n = start; n >= 1; --n) {
+        cplx tm = ((2.0 * n + 1.0) * iz) * t0 - t1;   // t_{n-1}
+        t1 = t0;
+        t0 = tm;
+        if (n - 1 <= N) out[(n - 1) * stride] = tm;
+        if (cabs2(tm) > 1e200) {
+            t0 *= 1e-150; t1 *= 1e-150;
+            for (int k = n - 1; k <= N; ++k) out[k * stride] *= 1e-150;
+        }
+    }
+    cplx sz, cz;
+    {
+        // sin z, cos z for complex z
+        double s, c;
+        sincos(z.re, &s, &c);
+        double eh = exp(z.im), ehm = exp(-z.im);
+        double ch = 0.5 * (eh + ehm), sh = 0.5 * (eh - ehm);
+        sz = mk(s * ch, c * sh);
+        cz = mk(c * ch, -s * sh);
+    }
+    cplx j0 = sz * iz, j1 = (sz * iz - cz) * iz;
+    cplx m0 = out[0], m1 = (N >= 1) ? out[stride] : t1;
+    double nrm = fmax(cabs1(m0), cabs1(m1));
+    cplx a0 = m0 * (1.0 / nrm), a1 = m1 * (1.0 / nrm);
+    cplx s = cdiv(j0 * conj(a0) + j1 * conj(a1), mk(cabs2(a0) + cabs2(a1), 0.0)) * (1.0 / nrm);
+    cplx f = s, step = cinv(sc * rho);
+    for (int n = 0; n <= N; ++n) {
+        out[n * stride] = out[n * stride] * f;
+        f = f * step;
+    }
+}
+
+// B_n = h_n(kw rho) sc^n / rho^n for n = 0..N.  Forward recurrence
+// B_{n+1} = (2n+1)(sc/kw) B_n / rho^2 - sc^2 B_{n-1} / rho^2 from
+// h_0 = -i e^{iz}/z, h_1 = -e^{iz}(z + i)/z^2 when Im z >= -1; below, the
+// reflection h_n(z) = 2 j_n(z) - conj(h_n(conj z)), whose second term recurs
+// forward stably.
+__device__ void radial_h_fwd(cplx rho, double kw, double sc, int N, cplx* out, int stride, bool accumulate_conj)
+{
+    cplx z = kw * rho;
+    cplx iz = cinv(z);
+    cplx e = cexp_(times_i(z));
+    cplx h0 = times_i(e * iz) * -1.0;                   // -i e^{iz} / z
+    cplx h1 = -(e * (z + mk(0.0, 1.0)) * iz * iz);      // -e^{iz}(z+i)/z^2
+    cplx ir2 = cinv(rho * rho);
+    cplx b0 = h0, b1 = h1 * sc * cinv(rho);
+    auto put = [&](int n, cplx v) {
+        if (accumulate_conj) out[n * stride] = out[n * stride] - conj(v);
+        else out[n * stride] = v;
+    };
+    put(0, b0);
+    if (N == 0) return;
+    put(1, b1);
+    double g = sc / kw;
+    for (int n = 1; n < N; ++n) {
+        cplx b2 = ((2.0 * n + 1.0) * g) * (b1 * ir2) - (sc * sc) * (b0 * ir2);
+        put(n + 1, b2);
+        b0 = b1;
+        b1 = b2;
+    }
+}
+
+__device__ void radial_h(cplx rho2, double kw, double sc, int N, cplx* out, int stride)
+{
+    cplx rho = csqrt_p(rho2);
+    cplx z = kw * rho;
+    if (z.im >= -1.0) {
+        radial_h_fwd(rho, kw, sc, N, out, stride, false);
+        return;
+    }
+    // B_n(rho) = 2 sc^{2n} A_n(rho) - conj(B_n(conj rho))
+    radial_j(rho2, kw, sc, N, out, stride);
+    double f = 2.0;
+    for (int n = 0; n <= N; ++n) {
+        out[n * stride] = out[n * stride] * f;
+        f *= sc * sc;
+    }
+    radial_h_fwd(conj(rho), kw, sc, N, out, stride, true);
+}
+
+// ------------------------------------------------------------------ P2M / P2L
+// One workgroup per box; thread t owns the order m = t - P of the output and
+// sweeps the box's points (or its List-4 boxes' points) in chunks of kPC,
+// whose radial values the first kPC threads compute into LDS.
+constexpr int kPC = 32;
+
+template <bool IRREG>
+__global__ __launch_bounds__(128) void k_h3d_p2x(const int* __restrict__ boxes, TreeView tv, PointsView pv,
+                                                 H3DLevels hl, int useL4, cplx* __restrict__ out)
+{
+    extern __shared__ cplx lds[];
+    int b = boxes[blockIdx.x];
+    int l = tv.level[b];
+    int P = tv.P[l];
+    double iw = tv.rs[l], kw = hl.kw[l], sc = hl.sc[l];
+    int st = blockDim.x;
+    cplx* acc = lds;                               // [(P+1)][st]
+    cplx* rad = acc + (size_t)(P + 1) * st;        // [(P+2)][kPC]
+    cplx* py = rad + (size_t)(P + 2) * kPC;        // [kPC][3]
+    cplx* ps = py + 3 * kPC;                       // [kPC]
+    int t = threadIdx.x, mm = t - P;
+    bool act = t < 2 * P + 1;
+    int am = mm < 0 ? -mm : mm;
+    if (act)
+        for (int n = am; n <= P; ++n) acc[n * st + t] = mk(0.0, 0.0);
+    cplx c[3];
+    int nb = tv.nbox;
+    for (int d = 0; d < 3; ++d) c[d] = mk(tv.cre[d * nb + b], tv.cim[d * nb + b]);
+    int64_t n = pv.n;
+    int e0 = useL4 ? tv.l4off[b] : 0, e1 = useL4 ? tv.l4off[b + 1] : 1;
+    for (int e = e0; e < e1; ++e) {
+        int src = useL4 ? tv.l4idx[e] : b;
+        for (int j0 = tv.pbeg[src]; j0 < tv.pend[src]; j0 += kPC) {
+            int cnt = min(kPC, tv.pend[src] - j0);
+            __syncthreads();
+            if (t < cnt) {
+                int j = j0 + t;
+                cplx y[3];
+                for (int d = 0; d < 3; ++d)
+                    y[d] = mk((pv.xre[d * n + j] - c[d].re) * iw, (pv.xim[d * n + j] - c[d].im) * iw);
+                for (int d = 0; d < 3; ++d) py[3 * t + d] = y[d];
+                ps[t] = mk(pv.sre[j], pv.sim[j]);
+                cplx r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+                if (IRREG) radial_h(r2, kw, sc, P, rad + t, kPC);
+                else radial_j(r2, kw, sc, P, rad + t, kPC);
+            }
+            __syncthreads();
+            if (!act) continue;
+            // order o = -mm of the source side
+            int o = -mm;
+            for (int q = 0; q < cnt; ++q) {
+                cplx x = py[3 * q], yv = py[3 * q + 1], z = py[3 * q + 2];
+                cplx w = o >= 0 ? mk(x.re - yv.im, x.im + yv.re) : mk(x.re + yv.im, x.im - yv.re);
+                cplx r2 = x * x + yv * yv + z * z;
+                cplx D = mk(c_cs[am], 0.0);
+                for (int k = 0; k < am; ++k) D = D * w;
+                D = D * ps[q];
+                cplx q0 = mk(0.0, 0.0), q1 = mk(1.0, 0.0);
+                acc[am * st + t] += D * rad[am * kPC + q];
+                for (int nn = am + 1; nn <= P; ++nn) {
+                    col_step_nd(nn, am, z, r2, q0, q1);
+                    acc[nn * st + t] += (D * q1) * rad[nn * kPC + q];
+                }
+            }
+        }
+    }
+    if (act) {
+        cplx* o = out + tv.eoff[b];
+        for (int nn = am; nn <= P; ++nn) {
+            cplx v = (2.0 * nn + 1.0) * acc[nn * st + t];
+            if (useL4) o[hnm(nn, mm)] += v;
+            else o[hnm(nn, mm)] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ L2P + M2P
+// One wavefront per leaf, one target per thread; each thread's radial values
+// sit in its own LDS column.
+__global__ __launch_bounds__(64) void k_h3d_leaf_far(const int* __restrict__ leaves, int top, int pmax,
+                                                     TreeView tv, PointsView pv, H3DLevels hl,
+                                                     const cplx* __restrict__ mpole,
+                                                     const cplx* __restrict__ local, cplx* __restrict__ ufar)
+{
+    extern __shared__ cplx rad[];   // [(pmax+2)][64]
+    int b = leaves[blockIdx.x];
+    int l = tv.level[b];
+    int t = threadIdx.x;
+    int64_t n = pv.n;
+    int nb = tv.nbox;
+    cplx* my = rad + t;
+    for (int i = tv.pbeg[b] + t; i < tv.pend[b]; i += 64) {
+        cplx u = mk(0.0, 0.0);
+        if (l >= top) {
+            // L2P from the leaf's own local expansion, then M2P over List 3
+            for (int e = tv.l3off[b] - 1; e < tv.l3off[b + 1]; ++e) {
+                int a = e < tv.l3off[b] ? b : tv.l3idx[e];
+                bool loc = a == b && e < tv.l3off[b];
+                int la = tv.level[a];
+                int P = tv.P[la];
+                double iw = tv.rs[la];
+                cplx x[3];
+                for (int d = 0; d < 3; ++d)
+                    x[d] = mk((pv.xre[d * n + i] - tv.cre[d * nb + a]) * iw,
+                              (pv.xim[d * n + i] - tv.cim[d * nb + a]) * iw);
+                cplx r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+                if (loc) radial_j(r2, hl.kw[la], hl.sc[la], P, my, 64);
+                else radial_h(r2, hl.kw[la], hl.sc[la], P, my, 64);
+                const cplx* C = (loc ? local : mpole) + tv.eoff[a];
+                cplx wp = mk(x[0].re - x[1].im, x[0].im + x[1].re);
+                cplx wm = mk(x[0].re + x[1].im, x[0].im - x[1].re);
+                cplx Dp = mk(1.0, 0.0), Dm = mk(1.0, 0.0);
+                for (int am = 0; am <= P; ++am) {
+                    if (am > 0) {
+                        Dp = Dp * wp * c_ck[am];
+                        Dm = Dm * wm * c_ck[am];
+                    }
+                    for (int sgn = 0; sgn < (am ? 2 : 1); ++sgn) {
+                        int m = sgn ? -am : am;
+                        cplx D = sgn ? Dm : Dp;
+                        cplx q0 = mk(0.0, 0.0), q1 = mk(1.0, 0.0);
+                        cplx s = C[hnm(am, m)] * my[am * 64];
+                        for (int nn = am + 1; nn <= P; ++nn) {
+                            col_step_nd(nn, am, x[2], r2, q0, q1);
+                            s += (C[hnm(nn, m)] * q1) * my[nn * 64];
+                        }
+                        u += D * s;
+                    }
+                }
+            }
+        }
+        ufar[i] = u;
+    }
+    (void)pmax;
+}
+
+// ------------------------------------------------------------------ P2P
+// G = e^{i kappa r} / (4 pi r) with the principal r = t + i Im s/(2t),
+// t = sqrt((|s| + Re s)/2): e^{i kappa r}/r = e^{-kappa Im r} (cos + i sin)(kappa Re r) conj(r) / |s|.
+__global__ __launch_bounds__(64) void k_h3d_p2p(const int* __restrict__ leaves, TreeView tv, PointsView pv,
+                                                double kappa, const cplx* __restrict__ ufar,
+                                                const int* __restrict__ perm, double* __restrict__ out)
+{
+    __shared__ double sx[6][64], ss[2][64];
+    int b = leaves[blockIdx.x];
+    int64_t n = pv.n;
+    int t = threadIdx.x;
+    int p0 = tv.pbeg[b], p1 = tv.pend[b];
+    int e0 = tv.l1off[b], e1 = tv.l1off[b + 1];
+    for (int i0 = p0; i0 < p1; i0 += 64) {
+        int i = i0 + t;
+        bool active = i < p1;
+        double xr[3] = {0, 0, 0}, xi[3] = {0, 0, 0};
+        if (active)
+            for (int d = 0; d < 3; ++d) { xr[d] = pv.xre[d * n + i]; xi[d] = pv.xim[d * n + i]; }
+        double ar = 0.0, ai = 0.0;
+        for (int e = e0; e < e1; ++e) {
+            int a = tv.l1idx[e];
+            int q0 = tv.pbeg[a], q1 = tv.pend[a];
+            for (int j0 = q0; j0 < q1; j0 += 64) {
+                int cnt = min(64, q1 - j0);
+                __syncthreads();
+                if (t < cnt) {
+                    int j = j0 + t;
+                    for (int d = 0; d < 3; ++d) { sx[2 * d][t] = pv.xre[d * n + j]; sx[2 * d + 1][t] = pv.xim[d * n + j]; }
+                    ss[0][t] = pv.sre[j];
+                    ss[1][t] = pv.sim[j];
+                }
+                __syncthreads();
+                if (active) {
+                    for (int q = 0; q < cnt; ++q) {
+                        if (j0 + q == i) continue;
+                        double sr = 0.0, si = 0.0;
+                        for (int d = 0; d < 3; ++d) {
+                            double dr = xr[d] - sx[2 * d][q], di = xi[d] - sx[2 * d + 1][q];
+                            sr += dr * dr - di * di;
+                            si += 2.0 * dr * di;
+                        }
+                        if (sr == 0.0 && si == 0.0) continue;
+                        double as = sqrt(sr * sr + si * si);
+                        double tt = sqrt(0.5 * (as + sr));
+                        double rr = tt, ri = 0.5 * si / tt;
+                        double sn, cs;
+                        sincos(kappa * rr, &sn, &cs);
+                        double ex = exp(-kappa * ri) / as;
+                        // (cs + i sn)(rr - i ri) * ex
+                        double gr = (cs * rr + sn * ri) * ex, gi = (sn * rr - cs * ri) * ex;
+                        ar += gr * ss[0][q] - gi * ss[1][q];
+                        ai += gr * ss[1][q] + gi * ss[0][q];
+                    }
+                }
+            }
+        }
+        if (active) {
+            cplx f = ufar[i];
+            double k = 1.0 / (4.0 * kPi);
+            // far field carries the factor i kappa
+            int64_t p = perm[i];
+            out[2 * p] = k * (ar - kappa * f.im);
+            out[2 * p + 1] = k * (ai + kappa * f.re);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ translations
+// K0: per pair, D = (c_dst - c_src) / w_src, rho_D = sqrt(D.D) and a complex
+// orthogonal Q with third column u = D / rho_D, built by Gram-Schmidt in the
+// bilinear form from the coordinate axis e_k with the smallest |u_k|:
+// q1 = (e_k - u_k u) / sqrt(1 - u_k^2), q2 = u x q1, Q = [q1 q2 u].
+__global__ void k_h3d_geo(H3DTr tr, TreeView tv)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tr.np) return;
+    int s = tr.src[i], d = tr.dst[i], nb = tv.nbox;
+    cplx D[3];
+    for (int k = 0; k < 3; ++k)
+        D[k] = mk((tv.cre[k * nb + d] - tv.cre[k * nb + s]) * tr.inv_w,
+                  (tv.cim[k * nb + d] - tv.cim[k * nb + s]) * tr.inv_w);
+    cplx rho = csqrt_p(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    cplx ir = cinv(rho);
+    cplx u[3] = {D[0] * ir, D[1] * ir, D[2] * ir};
+    int k = 0;
+    for (int q = 1; q < 3; ++q)
+        if (cabs2(u[q]) < cabs2(u[k])) k = q;
+    cplx q1[3];
+    for (int q = 0; q < 3; ++q) q1[q] = -(u[k] * u[q]);
+    q1[k] += mk(1.0, 0.0);
+    cplx nrm = cinv(csqrt_p(q1[0] * q1[0] + q1[1] * q1[1] + q1[2] * q1[2]));
+    for (int q = 0; q < 3; ++q) q1[q] = q1[q] * nrm;
+    cplx q2[3] = {u[1] * q1[2] - u[2] * q1[1], u[2] * q1[0] - u[0] * q1[2], u[0] * q1[1] - u[1] * q1[0]};
+    cplx* g = tr.geo + (size_t)i * 10;
+    for (int r = 0; r < 3; ++r) {
+        g[3 * r + 0] = q1[r];
+        g[3 * r + 1] = q2[r];
+        g[3 * r + 2] = u[r];
+    }
+    g[9] = rho;
+}
+
+// K1: rotation samples.  Thread (pair, n-block, node j): x = Q y_j (forward) or
+// Q^T y_j (back), derivative direction v = -Q e_z (or -Q^T e_z); accumulates
+// F_n(j) = sum_m a_n^m S_n^m(x) and G_n(j) = sum_m a_n^m v.grad S_n^m(x) for
+// the n of its block, sweeping the columns m with the diagonal start kept
+// incrementally.  On the unit sphere r2 = 1 and, v being tangent, (r2)' = 0.
+template <int NB>
+__global__ void k_h3d_rot_sample(H3DTr tr, int back, const int* __restrict__ eoff, const cplx* __restrict__ coef)
+{
+    int P = back ? tr.Pt : tr.Ps;
+    int J = 2 * P + 1;
+    int nblk = (P + NB) / NB;
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)tr.np * nblk * J) return;
+    int j = (int)(gid % J);
+    int blk = (int)((gid / J) % nblk);
+    int i = (int)(gid / ((int64_t)J * nblk));
+    const cplx* g = tr.geo + (size_t)i * 10;
+    const cplx* a = back ? tr.B + (size_t)i * tr.sB : coef + eoff[tr.src[i]];
+    double sp, cp;
+    sincospi(2.0 * j / J, &sp, &cp);
+    // x = M y with y = (cp, sp, 0); M = Q or Q^T
+    V3 x, v;
+    if (!back) {
+        x.x = cp * g[0] + sp * g[1]; x.y = cp * g[3] + sp * g[4]; x.z = cp * g[6] + sp * g[7];
+        v.x = -g[2]; v.y = -g[5]; v.z = -g[8];
+    } else {
+        x.x = cp * g[0] + sp * g[3]; x.y = cp * g[1] + sp * g[4]; x.z = cp * g[2] + sp * g[5];
+        v.x = -g[6]; v.y = -g[7]; v.z = -g[8];
+    }
+    int nlo = blk * NB, nhi = min(P, nlo + NB - 1);
+    cplx F[NB], G[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) { F[k] = mk(0.0, 0.0); G[k] = mk(0.0, 0.0); }
+    cplx one = mk(1.0, 0.0), zero = mk(0.0, 0.0);
+    for (int sgn = 0; sgn < 2; ++sgn) {
+        cplx w = sgn ? mk(x.x.re + x.y.im, x.x.im - x.y.re) : mk(x.x.re - x.y.im, x.x.im + x.y.re);
+        cplx dw = sgn ? mk(v.x.re + v.y.im, v.x.im - v.y.re) : mk(v.x.re - v.y.im, v.x.im + v.y.re);
+        cplx D = one, dD = zero;
+        for (int am = 0; am <= nhi; ++am) {
+            if (am > 0) {
+                double ck = c_ck[am];
+                cplx Dn = (D * w) * ck;
+                dD = (dD * w + D * dw) * ck;
+                D = Dn;
+            }
+            if (sgn && am == 0) continue;
+            int m = sgn ? -am : am;
+            const cplx* am_col = a;
+            cplx q0 = zero, q1 = one, dq0 = zero, dq1 = zero;
+            int n = am;
+            // advance to n = nlo - 1 when the column starts below the block
+            while (n < nlo - 1) {
+                ++n;
+                col_step(n, am, x.z, v.z, one, zero, q0, q1, dq0, dq1);
+            }
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                int nn = nlo + k;
+                if (nn > nhi || nn < am) continue;
+                if (nn > n) {
+                    col_step(nn, am, x.z, v.z, one, zero, q0, q1, dq0, dq1);
+                    n = nn;
+                }
+                cplx c = am_col[hnm(nn, m)];
+                F[k] += c * (D * q1);
+                G[k] += c * (dD * q1 + D * dq1);
+            }
+        }
+    }
+    cplx* FG = tr.FG + (size_t)i * tr.sFG;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        int nn = nlo + k;
+        if (nn > nhi) break;
+        FG[(size_t)nn * J + j] = F[k];
+        FG[(size_t)(P + 1) * J + (size_t)nn * J + j] = G[k];
+    }
+}
+
+// K2: DFT over the samples.  Thread (pair, coefficient (n, m)):
+// b_n^m = (1/J) sum_j e^{-i m phi_j} F_n(j) / S_n^m(e_x)  (n+m even)
+//       = (1/J) sum_j e^{-i m phi_j} G_n(j) / d_n^m        (n+m odd).
+__global__ void k_h3d_rot_dft(H3DTr tr, int back, const double* __restrict__ eq_p0,
+                              const double* __restrict__ eq_d0)
+{
+    extern __shared__ double tw[];   // cos, sin of 2 pi k / J
+    int P = back ? tr.Pt : tr.Ps;
+    int J = 2 * P + 1;
+    for (int k = threadIdx.x; k < J; k += blockDim.x) {
+        double s, c;
+        sincospi(2.0 * k / J, &s, &c);
+        tw[2 * k] = c;
+        tw[2 * k + 1] = s;
+    }
+    __syncthreads();
+    int nc = (P + 1) * (P + 1);
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)tr.np * nc) return;
+    int c = (int)(gid % nc);
+    int i = (int)(gid / nc);
+    int n = (int)sqrt((double)c);
+    while (n * n > c) --n;
+    while ((n + 1) * (n + 1) <= c) ++n;
+    int m = c - n * n - n;
+    int am = m < 0 ? -m : m;
+    bool even = ((n + m) & 1) == 0;
+    const cplx* FG = tr.FG + (size_t)i * tr.sFG + (even ? 0 : (size_t)(P + 1) * J) + (size_t)n * J;
+    double sr = 0.0, si = 0.0;
+    int mj = ((m % J) + J) % J, k = 0;
+    for (int j = 0; j < J; ++j) {
+        double cr = tw[2 * k], ci = -tw[2 * k + 1];   // e^{-i m phi_j}
+        cplx f = FG[j];
+        sr += f.re * cr - f.im * ci;
+        si += f.re * ci + f.im * cr;
+        k += mj;
+        if (k >= J) k -= J;
+    }
+    double den = (even ? eq_p0[tri(n, am)] : eq_d0[tri(n, am)]) * J;
+    cplx* o = tr.A + (size_t)i * tr.sA;
+    o[c] = mk(sr / den, si / den);
+}
+
+// K3a: radial functions of the source expansion at the coaxial nodes
+// x_j = (rs sin t_j, 0, rho_D + rs cos t_j) (source-scaled coordinates).
+__global__ void k_h3d_coax_radial(H3DTr tr)
+{
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)tr.np * tr.nq) return;
+    int j = (int)(gid % tr.nq);
+    int i = (int)(gid / tr.nq);
+    cplx t = tr.geo[(size_t)i * 10 + 9];
+    cplx x1 = mk(tr.rs * tr.sth[j], 0.0);
+    cplx x3 = t + mk(tr.rs * tr.cth[j], 0.0);
+    cplx r2 = x1 * x1 + x3 * x3;
+    cplx* R = tr.R + (size_t)i * tr.sR + j;
+    if (tr.src_h) radial_h(r2, tr.ks, tr.sc, tr.Ps + 1, R, tr.nq);
+    else radial_j(r2, tr.ks, tr.sc, tr.Ps + 1, R, tr.nq);
+}
+
+// K3: coaxial samples.  Thread (pair, order m >= 0, node j): the column of
+// order m at x_j (y = 0, so S_n^-m = S_n^m there) with its derivative along
+// s_j = (sin t_j, 0, cos t_j); with F = R_n(rho) S_n^m(x),
+//   dF/drs = fac R_{n+1} (s.x) S_n^m + R_n s.grad S_n^m,
+// fac = -kw sc for the regular A_n and -kw / sc for the singular B_n.
+__global__ void k_h3d_coax_sample(H3DTr tr)
+{
+    int Ps = tr.Ps, nq = tr.nq;
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)tr.np * (Ps + 1) * nq) return;
+    int j = (int)(gid % nq);
+    int am = (int)((gid / nq) % (Ps + 1));
+    int i = (int)(gid / ((int64_t)nq * (Ps + 1)));
+    cplx t = tr.geo[(size_t)i * 10 + 9];
+    double s1 = tr.sth[j], s3 = tr.cth[j];
+    cplx x1 = mk(tr.rs * s1, 0.0);
+    cplx x3 = t + mk(tr.rs * s3, 0.0);
+    cplx r2 = x1 * x1 + x3 * x3;
+    cplx sx = s1 * x1 + s3 * x3;
+    cplx dr2 = 2.0 * sx;
+    const cplx* R = tr.R + (size_t)i * tr.sR + j;
+    const cplx* a = tr.A + (size_t)i * tr.sA;
+    double fac = tr.src_h ? -tr.ks / tr.sc : -tr.ks * tr.sc;
+    // diagonal start c_m x1^m and its derivative c_m m x1^{m-1} s1
+    cplx D = mk(c_cs[am], 0.0), dD = mk(0.0, 0.0);
+    {
+        cplx pw = mk(1.0, 0.0);
+        for (int k = 0; k < am; ++k) {
+            if (k == am - 1) dD = (double)am * c_cs[am] * s1 * pw;
+            pw = pw * x1;
+        }
+        D = c_cs[am] * pw;
+    }
+    cplx fp = mk(0.0, 0.0), fm = fp, gp = fp, gm = fp;
+    cplx q0 = mk(0.0, 0.0), q1 = mk(1.0, 0.0), dq0 = q0, dq1 = q0;
+    cplx z = x3, dz = mk(s3, 0.0);
+    for (int n = am; n <= Ps; ++n) {
+        if (n > am) col_step(n, am, z, dz, r2, dr2, q0, q1, dq0, dq1);
+        cplx S = D * q1, dS = dD * q1 + D * dq1;
+        cplx Rn = R[(size_t)n * nq], Rn1 = R[(size_t)(n + 1) * nq];
+        cplx f = Rn * S;
+        cplx gg = (fac * Rn1) * (sx * S) + Rn * dS;
+        cplx cp = a[hnm(n, am)];
+        fp += cp * f;
+        gp += cp * gg;
+        if (am) {
+            cplx cm = a[hnm(n, -am)];
+            fm += cm * f;
+            gm += cm * gg;
+        }
+    }
+    cplx* f = tr.fg + (size_t)i * tr.sfg;
+    cplx* g = f + (size_t)(2 * Ps + 1) * nq;
+    f[(size_t)(am + Ps) * nq + j] = fp;
+    g[(size_t)(am + Ps) * nq + j] = gp;
+    if (am) {
+        f[(size_t)(Ps - am) * nq + j] = fm;
+        g[(size_t)(Ps - am) * nq + j] = gm;
+    }
+}
+
+// K4: Legendre projection.  Thread (pair, target coefficient (n, m)):
+// b_n^m = Tc_n sum_j W_nm(j) f_m(j) + Tdc_n sum_j W_nm(j) g_m(j).
+__global__ void k_h3d_coax_proj(H3DTr tr)
+{
+    int Pt = tr.Pt, Ps = tr.Ps, nq = tr.nq;
+    int nc = (Pt + 1) * (Pt + 1);
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)tr.np * nc) return;
+    int c = (int)(gid % nc);
+    int i = (int)(gid / nc);
+    int n = (int)sqrt((double)c);
+    while (n * n > c) --n;
+    while ((n + 1) * (n + 1) <= c) ++n;
+    int m = c - n * n - n;
+    int am = m < 0 ? -m : m;
+    cplx* o = tr.B + (size_t)i * tr.sB;
+    if (am > Ps) {
+        o[c] = mk(0.0, 0.0);
+        return;
+    }
+    const cplx* f = tr.fg + (size_t)i * tr.sfg + (size_t)(m + Ps) * nq;
+    const cplx* g = f + (size_t)(2 * Ps + 1) * nq;
+    const double* W = tr.W + (size_t)tri(n, am) * nq;
+    cplx pf = mk(0.0, 0.0), pg = pf;
+    for (int j = 0; j < nq; ++j) {
+        pf += W[j] * f[j];
+        pg += W[j] * g[j];
+    }
+    o[c] = tr.Tc[n] * pf + tr.Tdc[n] * pg;
+}
+
+// K7: each target box adds its pairs' translated expansions, in pair order.
+__global__ void k_h3d_accum(H3DTr tr, const int* __restrict__ gdst, const int* __restrict__ goff, int ng,
+                            const int* __restrict__ eoff, cplx* __restrict__ out)
+{
+    int nc = (tr.Pt + 1) * (tr.Pt + 1);
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)ng * nc) return;
+    int c = (int)(gid % nc);
+    int k = (int)(gid / nc);
+    cplx s = mk(0.0, 0.0);
+    for (int i = goff[k]; i < goff[k + 1]; ++i) s += tr.A[(size_t)i * tr.sA + c];
+    out[eoff[gdst[k]] + c] += s;
+}
+
+inline unsigned blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t h3d_init_tables(int device)
+{
+    (void)device;
+    static double ca[kT * kT], cb[kT * kT], cs[kT], ck[kT];
+    for (int n = 0; n < kT; ++n)
+        for (int m = 0; m < kT; ++m) {
+            double a = (double)(n + m - 1) * (double)(n - m - 1);
+            ca[n * kT + m] = a > 0.0 ? sqrt(a) : 0.0;
+            double b = (double)(n - m) * (double)(n + m);
+            cb[n * kT + m] = b > 0.0 ? 1.0 / sqrt(b) : 0.0;
+        }
+    cs[0] = 1.0;
+    ck[0] = 1.0;
+    for (int m = 1; m < kT; ++m) {
+        ck[m] = sqrt((2.0 * m - 1.0) / (2.0 * m));
+        cs[m] = cs[m - 1] * ck[m];
+    }
+    hipError_t e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_ca), ca, sizeof(ca))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_cb), cb, sizeof(cb))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_cs), cs, sizeof(cs))) != hipSuccess) return e;
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_ck), ck, sizeof(ck));
+}
+
+static size_t p2x_lds(int P, int st)
+{
+    return sizeof(cplx) * ((size_t)(P + 1) * st + (size_t)(P + 2) * kPC + 4 * kPC);
+}
+
+template <bool IRREG>
+static hipError_t launch_p2x(const int* boxes, int nb, int pmax, const TreeView& tv, const PointsView& pv,
+                             const H3DLevels& hl, int useL4, cplx* out, hipStream_t st)
+{
+    if (nb <= 0) return hipSuccess;
+    int threads = 2 * pmax + 1 <= 64 ? 64 : 128;
+    size_t lds = p2x_lds(pmax, threads);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_h3d_p2x<IRREG>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    k_h3d_p2x<IRREG><<<nb, threads, lds, st>>>(boxes, tv, pv, hl, useL4, out);
+    return hipGetLastError();
+}
+
+hipError_t h3d_p2m(const int* boxes, int nb, int pmax, const TreeView& tv, const PointsView& pv,
+                   const H3DLevels& hl, cplx* mpole, hipStream_t st)
+{
+    return launch_p2x<false>(boxes, nb, pmax, tv, pv, hl, 0, mpole, st);
+}
+
+hipError_t h3d_p2l(const int* boxes, int nb, int pmax, const TreeView& tv, const PointsView& pv,
+                   const H3DLevels& hl, cplx* local, hipStream_t st)
+{
+    return launch_p2x<true>(boxes, nb, pmax, tv, pv, hl, 1, local, st);
+}
+
+hipError_t h3d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const TreeView& tv,
+                        const PointsView& pv, const H3DLevels& hl, const cplx* mpole,
+                        const cplx* local, cplx* ufar, hipStream_t st)
+{
+    if (nleaf <= 0) return hipSuccess;
+    size_t lds = sizeof(cplx) * (size_t)(pmax + 3) * 64;
+    k_h3d_leaf_far<<<nleaf, 64, lds, st>>>(leaves, top, pmax, tv, pv, hl, mpole, local, ufar);
+    return hipGetLastError();
+}
+
+hipError_t h3d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv, double kappa,
+                   const cplx* ufar, const int* perm, double* out, hipStream_t st)
+{
+    if (nleaf <= 0) return hipSuccess;
+    k_h3d_p2p<<<nleaf, 64, 0, st>>>(leaves, tv, pv, kappa, ufar, perm, out);
+    return hipGetLastError();
+}
+
+// One chunk of a translation stage: pairs [0, tr.np) of the chunk, target
+// groups [0, ng) with pair ranges goff (chunk-relative).
+hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_src, const cplx* coef_src,
+                         const int* gdst, const int* goff, int ng, const int* eoff_dst, cplx* coef_dst,
+                         const double* eq_p0, const double* eq_d0, hipStream_t st)
+{
+    if (tr.np <= 0) return hipSuccess;
+    const int bs = 256;
+    constexpr int NB = 8;
+    k_h3d_geo<<<blocks(tr.np, bs), bs, 0, st>>>(tr, tv);
+    int Ps = tr.Ps, Pt = tr.Pt;
+    int64_t n1 = (int64_t)tr.np * ((Ps + NB) / NB) * (2 * Ps + 1);
+    k_h3d_rot_sample<NB><<<blocks(n1, bs), bs, 0, st>>>(tr, 0, eoff_src, coef_src);
+    int64_t n2 = (int64_t)tr.np * (Ps + 1) * (Ps + 1);
+    k_h3d_rot_dft<<<blocks(n2, bs), bs, sizeof(double) * 2 * (2 * Ps + 1), st>>>(tr, 0, eq_p0, eq_d0);
+    int64_t n3 = (int64_t)tr.np * tr.nq;
+    k_h3d_coax_radial<<<blocks(n3, bs), bs, 0, st>>>(tr);
+    int64_t n4 = (int64_t)tr.np * (Ps + 1) * tr.nq;
+    k_h3d_coax_sample<<<blocks(n4, bs), bs, 0, st>>>(tr);
+    int64_t n5 = (int64_t)tr.np * (Pt + 1) * (Pt + 1);
+    k_h3d_coax_proj<<<blocks(n5, bs), bs, 0, st>>>(tr);
+    int64_t n6 = (int64_t)tr.np * ((Pt + NB) / NB) * (2 * Pt + 1);
+    k_h3d_rot_sample<NB><<<blocks(n6, bs), bs, 0, st>>>(tr, 1, nullptr, nullptr);
+    k_h3d_rot_dft<<<blocks(n5, bs), bs, sizeof(double) * 2 * (2 * Pt + 1), st>>>(tr, 1, eq_p0, eq_d0);
+    int64_t n7 = (int64_t)ng * (Pt + 1) * (Pt + 1);
+    k_h3d_accum<<<blocks(n7, bs), bs, 0, st>>>(tr, gdst, goff, ng, eoff_dst, coef_dst);
+    return hipGetLastError();
+}
+
+}  // namespace cfmm

@@ -112,6 +112,51 @@ hipError_t l3d_p2p(const int* leaves, int nleaf, const TreeView& tv, const Point
 size_t l3d_max_lds_m2l(int P);
 int l3d_pmax_supported();
 
+// 3D Helmholtz evaluation (h3d_kernels.hip)
+struct H3DLevels {
+    const double* kw;      // kappa * w_l per level
+    const double* sc;      // min(1, kappa * w_l)
+};
+
+// One chunk of a translation stage (M2M, M2L or L2L at one level): its pairs,
+// the per-stage constants and the scratch regions (per-pair strides in
+// complex units).
+struct H3DTr {
+    int np;                 // pairs in the chunk
+    const int* src;         // source box per pair
+    const int* dst;         // target box per pair
+    int Ps, Pt, nq;         // source / target expansion lengths, coaxial nodes
+    int src_h, trg_h;       // 1: singular (multipole) expansion, 0: regular (local)
+    double ks, sc;          // kappa w_src and the source level's scale
+    double rs;              // coaxial sampling radius / w_src
+    double inv_w;           // 1 / w_src
+    const double* sth;      // sin t_j, cos t_j of the Gauss-Legendre nodes
+    const double* cth;
+    const double* W;        // [(n(n+1)/2 + m) * nq + j] = (2n+1)/2 w_j S_n^m(s_j)
+    const cplx* Tc;         // conj(T_n) / (|T_n|^2 + |T'_n|^2)
+    const cplx* Tdc;        // conj(T'_n) / (|T_n|^2 + |T'_n|^2)
+    cplx* geo;  // [np][10]: Q (row major), rho_D
+    cplx* FG;  int64_t sFG;
+    cplx* A;   int64_t sA;
+    cplx* R;   int64_t sR;
+    cplx* fg;  int64_t sfg;
+    cplx* B;   int64_t sB;
+};
+
+hipError_t h3d_init_tables(int device);
+hipError_t h3d_p2m(const int* boxes, int nb, int pmax, const TreeView& tv, const PointsView& pv,
+                   const H3DLevels& hl, cplx* mpole, hipStream_t st);
+hipError_t h3d_p2l(const int* boxes, int nb, int pmax, const TreeView& tv, const PointsView& pv,
+                   const H3DLevels& hl, cplx* local, hipStream_t st);
+hipError_t h3d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const TreeView& tv,
+                        const PointsView& pv, const H3DLevels& hl, const cplx* mpole,
+                        const cplx* local, cplx* ufar, hipStream_t st);
+hipError_t h3d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv, double kappa,
+                   const cplx* ufar, const int* perm, double* out, hipStream_t st);
+hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_src, const cplx* coef_src,
+                         const int* gdst, const int* goff, int ng, const int* eoff_dst, cplx* coef_dst,
+                         const double* eq_p0, const double* eq_d0, hipStream_t st);
+
 // host-side special functions for the expansion-length rule
 double h2d_nterms_crit(double kappa, double R, double r, int n);
 

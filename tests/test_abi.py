@@ -92,3 +92,23 @@ def test_nterms_equals_oracle_rule(eps, w, sep):
     got = cf.nterms(2, "helmholtz", kappa, w, sep, eps, 63)
     ref = params.nterms(2, "helmholtz", kappa, w, sep, eps, 63)
     assert got == ref
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-10, 1e-12])
+@pytest.mark.parametrize("w", [0.01, 0.1875, 0.75, 1.5])
+@pytest.mark.parametrize("sep", [1, 2])
+def test_nterms_3d_helmholtz_equals_oracle_rule(eps, w, sep):
+    kappa = 20.0 * 2.0 * np.pi / 12.0
+    got = cf.nterms(3, "helmholtz", kappa, w, sep, eps, 50)
+    ref = params.nterms(3, "helmholtz", kappa, w, sep, eps, 50)
+    assert got == ref
+
+
+def test_2d_laplace_not_supported():
+    import ctypes
+    pts = np.zeros((4, 2), np.complex128)
+    d = cf.PlanDesc(dim=2, kernel=cf.LAPLACE, wavenumber=0.0, tol=1e-6, n=4, points=pts.ctypes.data,
+                    points_on_device=0, precision=0, stream=None, leaf_size=0, separation=0)
+    h = ctypes.c_void_p()
+    assert cf.lib().cfmm_plan(ctypes.byref(h), ctypes.byref(d)) == cf.CFMM_ENOTSUP
+    assert not h.value
