@@ -7,9 +7,11 @@ Morton sort, tree, centres, lists, expansion lengths) is built once before
 timing, as in the iterative solves the method serves, and its time is
 reported separately.
 
-Workload (default): 2D Helmholtz single layer, N = 2^20 points on the
-complexified curve x(t) = (t + i psi(t), 0.2 exp(-t^2)) scaled by 0.1,
-kappa = 100, tolerance 1e-6, FP64.
+Workload (default, --workload c1): 2D Helmholtz single layer, N = 2^20
+points on the complexified curve x(t) = (t + i psi(t), 0.2 exp(-t^2)) scaled
+by 0.1, kappa = 100, tolerance 1e-6, FP64.  --workload c2: 3D Laplace on the
+1448^2 complexified plane; c3: 3D Helmholtz on the 1000^2 plane with bumps,
+kappa = 20 * 2 pi / 12.
 
 Prints one JSON line.  metric: N^2-equivalent interactions per second,
 N (N - 1) / t_eval.
@@ -28,12 +30,25 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP64 flops of one near-field interaction G(x_i, y_j) sigma_j in
-# the small-argument regime of this workload (|kappa r| < 0.1): squared
-# complex distance 15, complex log 10, five series terms of J0 and Y0 at 12
-# each, assembly 8, complex multiply-accumulate 8; add/mul count 1, FMA 2.
-P2P_FLOPS_PER_INTERACTION = 100.0
+# Algorithmic flops of one near-field interaction G(x_i, y_j) sigma_j, counting
+# add/mul as 1, FMA as 2 and each sqrt, divide, exp or sincos as 1:
+#  * 2D Helmholtz in the small-argument regime of the C1 curve (|kappa r| < 0.1):
+#    squared complex distance 15, complex log 10, five series terms of J0 and Y0
+#    at 12 each, assembly 8, complex multiply-accumulate 8;
+#  * 3D Laplace: squared complex distance 18, principal root and 1/r 9,
+#    complex multiply-accumulate 8;
+#  * 3D Helmholtz: as 3D Laplace plus e^{i kappa r} (exp, sincos, 6) and the
+#    complex product with 1/r (6).
+WORKLOADS = {
+    # name: (config index, dim, kernel, default tol, P2P kernel, flops per interaction)
+    "c1": (1, 2, "helmholtz", 1e-6, "k_h2d_p2p", 100.0),
+    "c2": (2, 3, "laplace", 1e-6, "k_l3d_p2p", 35.0),
+    "c3": (3, 3, "helmholtz", 1e-6, "k_h3d_p2p", 47.0),
+}
+P2P_FLOPS_PER_INTERACTION = WORKLOADS["c1"][5]
 PEAK_FP64_VALU = 78.6e12          # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
+PEAK_FP32_VALU = 157.3e12
+METRIC = "N\u00b2-equiv interactions/s at 1e-6 rel err; served p50/p99 latency vs plain"
 
 
 def parse():
@@ -41,8 +56,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=1 << 20)
-    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--check-targets", type=int, default=64)
@@ -61,21 +77,23 @@ def main():
     import paper_2509_05458_amd as cf
     import synth
 
-    cfg = synth.make_config(1, n=a.n, n_oracle=max(a.check_targets, a.cpu_targets))
+    ci, dim, kern, tol0, p2p_kernel, p2p_flops_unit = WORKLOADS[a.workload]
+    tol = a.tol or tol0
+    cfg = synth.make_config(ci, n=a.n or None, n_oracle=max(a.check_targets, a.cpu_targets))
     n = cfg.n
     dev = torch.device("cuda:0")
     pts = torch.from_numpy(cfg.points).to(dev)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = cf.Plan(pts, "helmholtz", cfg.kappa, a.tol, precision=a.precision, leaf_size=a.leaf,
+    plan = cf.Plan(pts, kern, cfg.kappa, tol, precision=a.precision, leaf_size=a.leaf,
                    stream=stream.cuda_stream)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
     # fresh seeded densities per step, resident in HBM before timing
     nsig = max(1, min(4, a.steps))
-    sigs = [torch.from_numpy(synth.density(n, 2001 + 17 * k)).to(dev) for k in range(nsig)]
+    sigs = [torch.from_numpy(synth.density(n, 2000 + ci + 17 * k)).to(dev) for k in range(nsig)]
     out = torch.empty_like(sigs[0])
     for w in range(a.warmup):
         plan.eval_into(sigs[w % nsig], out)
@@ -102,15 +120,23 @@ def main():
     tg = cfg.oracle_targets[: a.check_targets]
     u_gpu = out.cpu().numpy()
     sig_last = sigs[(a.steps - 1) % nsig].cpu().numpy()
-    u0 = oracle.direct_self(2, "helmholtz", cfg.kappa, cfg.points, sig_last, targets=tg,
+    u0 = oracle.direct_self(dim, kern, cfg.kappa, cfg.points, sig_last, targets=tg,
                             nthreads=min(16, os.cpu_count() or 1))
     rel = oracle.rel_l2(u_gpu[tg], u0)
 
     p2p_ms = stage_avg["p2p"]
-    p2p_flops = P2P_FLOPS_PER_INTERACTION * info["p2p_pairs"]
+    p2p_flops = p2p_flops_unit * info["p2p_pairs"]
     achieved = p2p_flops / (p2p_ms * 1e-3)
+    peak = PEAK_FP64_VALU if a.precision == "fp64" else PEAK_FP32_VALU
+    names = {"c1": f"2D Helmholtz single layer, N={n} complexified curve (C0 curve scaled 0.1), "
+                   f"kappa={cfg.kappa}, tol={tol}, targets=sources",
+             "c2": f"3D Laplace single layer, N={n} complexified plane ({cfg.meta.get('grid')}^2 grid), "
+                   f"tol={tol}, targets=sources",
+             "c3": f"3D Helmholtz single layer, N={n} complexified plane with 8 bumps "
+                   f"({cfg.meta.get('grid')}^2 grid), kappa={cfg.kappa:.4f} (20 wavelengths), tol={tol}, "
+                   f"targets=sources"}
     res = {
-        "metric": "N^2-equivalent interactions/s at 1e-6 relative error",
+        "metric": METRIC,
         "value": value,
         "unit": "interactions/s",
         "n_gpus": 1,
@@ -123,9 +149,8 @@ def main():
         "dtype": "f64" if a.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"2D Helmholtz single layer, N={n} complexified curve (C0 curve scaled 0.1), "
-                        f"kappa={cfg.kappa}, tol={a.tol}, targets=sources",
-            "n": n, "kappa": cfg.kappa, "tol": a.tol, "precision": a.precision,
+            "workload": names[a.workload],
+            "n": n, "kappa": cfg.kappa, "tol": tol, "precision": a.precision,
             "leaf_size": info["leaf_size"], "separation": info["separation"],
             "top_level": info["top_level"], "levels": info["nlevels"], "max_p": info["max_p"],
             "p2p_pairs": info["p2p_pairs"], "m2l_pairs": info["m2l_pairs"],
@@ -134,14 +159,14 @@ def main():
             "step": "one cfmm_eval on a warm plan",
         },
         "roofline": {
-            "kernel": "k_h2d_p2p",
+            "kernel": p2p_kernel,
             "bound": "alu",
             "achieved": achieved / 1e12,
-            "peak": PEAK_FP64_VALU / 1e12,
+            "peak": peak / 1e12,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_VALU,
+            "frac": achieved / peak,
             "traffic": None,
-            "flops_per_interaction": P2P_FLOPS_PER_INTERACTION,
+            "flops_per_interaction": p2p_flops_unit,
         },
     }
     if not a.no_cpu:
@@ -149,7 +174,7 @@ def main():
         ct = cfg.oracle_targets[: a.cpu_targets]
         cores = len(os.sched_getaffinity(0))
         t0 = time.perf_counter()
-        orc.direct_self(2, "helmholtz", cfg.kappa, cfg.points, sig_last, targets=ct, nthreads=cores)
+        orc.direct_self(dim, kern, cfg.kappa, cfg.points, sig_last, targets=ct, nthreads=cores)
         cdt = time.perf_counter() - t0
         res["cpu_baseline"] = {
             "value": len(ct) * (n - 1) / cdt,
