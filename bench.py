@@ -41,7 +41,7 @@ sys.path.insert(0, ROOT)
 #    complex product with 1/r (6).
 WORKLOADS = {
     # name: (config index, dim, kernel, default tol, P2P kernel, flops per interaction)
-    "c1": (1, 2, "helmholtz", 1e-6, "k_h2d_p2p", 100.0),
+    "c1": (1, 2, "helmholtz", 1e-6, "k_h2d_p2p_ser", 100.0),
     "c2": (2, 3, "laplace", 1e-6, "k_l3d_p2p", 35.0),
     "c3": (3, 3, "helmholtz", 1e-6, "k_h3d_p2p", 47.0),
 }

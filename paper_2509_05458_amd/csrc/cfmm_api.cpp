@@ -82,6 +82,8 @@ struct cfmm_plan_s {
     std::vector<int> m2m_off, m2m_cnt, l2l_off, l2l_cnt;   // per level
     cplx *d_mpole = nullptr, *d_local = nullptr, *d_ufar = nullptr;
     int off_p2l = 0, n_p2l = 0;
+    int off_p2p_ser = 0, n_p2p_ser = 0, off_p2p_gen = 0, n_p2p_gen = 0;
+    int* d_p2p_nterm = nullptr;   // series terms per series-only P2P leaf
     // plan-time translation operators (2D Helmholtz)
     int64_t *d_o_m2l = nullptr, *d_o_tr = nullptr;
     cplx *d_g_m2l = nullptr, *d_g_m2m = nullptr, *d_g_l2l = nullptr;
@@ -569,6 +571,50 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     for (int b = 0; b < nb; ++b)
         for (int e = t.off[1][b]; e < t.off[1][b + 1]; ++e) work.push_back(b);
     int npairs = (int)t.idx[1].size();
+    // 2D Helmholtz near field: leaves whose near pairs all have |kappa r| < 3,
+    // by a bound from the box geometry (real half widths plus the imaginary
+    // spreads about the complexified centres), take the series-only P2P with a
+    // per-leaf number of series terms; the rest take the general P2P.
+    std::vector<int> ser_nterm;
+    if (h2d) {
+        double k2 = 0.25 * p->kappa * p->kappa;
+        std::vector<int> gen;
+        p->off_p2p_ser = (int)work.size();
+        for (int b = 0; b < nb; ++b) {
+            if (t.nchild[b]) continue;
+            double qb = 0.0, wb = p->D * ldexp(1.0, -t.level[b]);
+            for (int e = t.off[0][b]; e < t.off[0][b + 1]; ++e) {
+                int a = t.idx[0][e];
+                double wa = p->D * ldexp(1.0, -t.level[a]);
+                double sre = 0.0, sci = 0.0;
+                for (int k = 0; k < dim; ++k) {
+                    double dr = fabs(cre[(size_t)k * nb + b] - cre[(size_t)k * nb + a]) + 0.5 * (wa + wb);
+                    double dc = cim[(size_t)k * nb + b] - cim[(size_t)k * nb + a];
+                    sre += dr * dr;
+                    sci += dc * dc;
+                }
+                double di = delta[a] + delta[b] + sqrt(sci);
+                qb = std::max(qb, k2 * (sre + di * di));
+            }
+            if (qb < 2.25) {
+                int K = 1;
+                double term = qb * qb / 4.0;      // q^(K+1) / ((K+1)!)^2 at K = 1
+                while (term > 1e-17 && K < 39) {
+                    ++K;
+                    term *= qb / ((double)(K + 1) * (K + 1));
+                }
+                work.push_back(b);
+                ser_nterm.push_back(K);
+            } else {
+                gen.push_back(b);
+            }
+        }
+        p->n_p2p_ser = (int)work.size() - p->off_p2p_ser;
+        p->off_p2p_gen = (int)work.size();
+        work.insert(work.end(), gen.begin(), gen.end());
+        p->n_p2p_gen = (int)gen.size();
+        if ((rc = upload(p, &p->d_p2p_nterm, ser_nterm))) return rc;
+    }
     if ((rc = upload(p, &p->d_work, work))) return rc;
     int64_t gsz = 0, tsz = 0, psz = 0;
     if (h2d) {
@@ -747,8 +793,8 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, top, std::max(1, p->pmax), tv, pv, p->kappa,
                             p->d_poff, p->d_pvals, p->d_mpole, p->d_local, p->d_ufar, st));
         HIPCHK(mark(6));
-        HIPCHK(h2d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out,
-                       p->precision, st));
+        HIPCHK(h2d_p2p(W + p->off_p2p_ser, p->n_p2p_ser, p->d_p2p_nterm, W + p->off_p2p_gen, p->n_p2p_gen,
+                       tv, pv, p->kappa, p->d_ufar, p->d_perm, out, p->precision, st));
     } else if (p->kernel == CFMM_HELMHOLTZ) {
         H3DLevels hl{p->d_h3_kw, p->d_h3_sc};
         HIPCHK(hipMemsetAsync(p->d_mpole, 0, p->ecount * sizeof(cplx), st));

@@ -445,6 +445,94 @@ __global__ __launch_bounds__(64) void k_h2d_p2p(const int* __restrict__ leaves, 
     }
 }
 
+// P2P for leaves whose every near pair has |kappa r| < 3 (a plan-time bound
+// from the box geometry): only the power series of H0 is needed, with the
+// leaf's fixed number of terms K (enough for the bound).  With q = kappa^2 s/4,
+// log(z/2) = log(q)/2 and log q = log(kappa^2/4) + log|s| + i arg s (Re s > 0 on
+// every near pair, as the plan checks):
+//   J0 = sum_k (-q)^k/(k!)^2,  Y0 = (2/pi)((log(z/2) + gamma) J0 - sum_k H_k (-q)^k/(k!)^2).
+// The kernel carries none of the other Hankel branches, so it keeps far fewer
+// registers live than the general P2P.
+__global__ __launch_bounds__(64) void k_h2d_p2p_ser(const int* __restrict__ leaves,
+                                                    const int* __restrict__ nterm, TreeView tv,
+                                                    PointsView pv, double kappa,
+                                                    const cplx* __restrict__ ufar,
+                                                    const int* __restrict__ perm, double* __restrict__ out)
+{
+    constexpr SeriesTab T = make_series_tab();
+    __shared__ double s1r[64], s1i[64], s2r[64], s2i[64], ssr[64], ssi[64];
+    int b = leaves[blockIdx.x];
+    int K = nterm[blockIdx.x];
+    int64_t n = pv.n;
+    int t = threadIdx.x;
+    int p0 = tv.pbeg[b], p1 = tv.pend[b];
+    int e0 = tv.l1off[b], e1 = tv.l1off[b + 1];
+    double k2 = 0.25 * kappa * kappa, lk2 = log(k2);
+    for (int i0 = p0; i0 < p1; i0 += 64) {
+        int i = i0 + t;
+        bool active = i < p1;
+        double x1r = 0, x1i = 0, x2r = 0, x2i = 0;
+        if (active) {
+            x1r = pv.xre[i]; x1i = pv.xim[i];
+            x2r = pv.xre[n + i]; x2i = pv.xim[n + i];
+        }
+        double ar = 0.0, ai = 0.0;
+        for (int e = e0; e < e1; ++e) {
+            int a = tv.l1idx[e];
+            int q0 = tv.pbeg[a], q1 = tv.pend[a];
+            for (int j0 = q0; j0 < q1; j0 += 64) {
+                int cnt = min(64, q1 - j0);
+                __syncthreads();
+                if (t < cnt) {
+                    int j = j0 + t;
+                    s1r[t] = pv.xre[j]; s1i[t] = pv.xim[j];
+                    s2r[t] = pv.xre[n + j]; s2i[t] = pv.xim[n + j];
+                    ssr[t] = pv.sre[j]; ssi[t] = pv.sim[j];
+                }
+                __syncthreads();
+                if (active) {
+                    for (int q = 0; q < cnt; ++q) {
+                        if (j0 + q == i) continue;
+                        double d1r = x1r - s1r[q], d1i = x1i - s1i[q];
+                        double d2r = x2r - s2r[q], d2i = x2i - s2i[q];
+                        double sr = d1r * d1r - d1i * d1i + d2r * d2r - d2i * d2i;
+                        double si = 2.0 * (d1r * d1i + d2r * d2i);
+                        if (sr == 0.0 && si == 0.0) continue;
+                        double lm = 0.5 * log(sr * sr + si * si) + lk2;   // log|q|
+                        double ag = atan2(si, sr);                        // arg q
+                        double qr = -k2 * sr, qi = -k2 * si;              // -q
+                        double tr = 1.0, ti = 0.0, jr = 1.0, ji = 0.0, sr0 = 0.0, si0 = 0.0;
+                        for (int k = 1; k <= K; ++k) {
+                            double c = T.inv_k2[k];
+                            double nr = (tr * qr - ti * qi) * c, ni = (tr * qi + ti * qr) * c;
+                            tr = nr;
+                            ti = ni;
+                            jr += tr;
+                            ji += ti;
+                            double h = T.harm[k];
+                            sr0 += h * tr;
+                            si0 += h * ti;
+                        }
+                        double lgr = 0.5 * lm + kEuler, lgi = 0.5 * ag;
+                        double yr = (2.0 / kPi) * (lgr * jr - lgi * ji - sr0);
+                        double yi = (2.0 / kPi) * (lgr * ji + lgi * jr - si0);
+                        double hr = jr - yi, hi = ji + yr;     // J0 + i Y0
+                        ar += hr * ssr[q] - hi * ssi[q];
+                        ai += hr * ssi[q] + hi * ssr[q];
+                    }
+                }
+            }
+        }
+        if (active) {
+            cplx f = ufar[i];
+            double tr = ar + f.re, ti = ai + f.im;
+            int64_t p = perm[i];
+            out[2 * p] = -0.25 * ti;      // (i/4) (tr + i ti)
+            out[2 * p + 1] = 0.25 * tr;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t h2d_gen_pts(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
                        double kappa, const int64_t* poff, cplx* vals, hipStream_t st)
@@ -518,13 +606,13 @@ hipError_t h2d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const T
     return hipGetLastError();
 }
 
-hipError_t h2d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                   double kappa, const cplx* ufar, const int* perm, double* out, int mixed,
-                   hipStream_t st)
+hipError_t h2d_p2p(const int* ser_leaves, int nser, const int* ser_nterm, const int* gen_leaves, int ngen,
+                   const TreeView& tv, const PointsView& pv, double kappa, const cplx* ufar,
+                   const int* perm, double* out, int mixed, hipStream_t st)
 {
     (void)mixed;
-    if (nleaf <= 0) return hipSuccess;
-    k_h2d_p2p<<<nleaf, 64, 0, st>>>(leaves, tv, pv, kappa, ufar, perm, out);
+    if (nser > 0) k_h2d_p2p_ser<<<nser, 64, 0, st>>>(ser_leaves, ser_nterm, tv, pv, kappa, ufar, perm, out);
+    if (ngen > 0) k_h2d_p2p<<<ngen, 64, 0, st>>>(gen_leaves, tv, pv, kappa, ufar, perm, out);
     return hipGetLastError();
 }
 

@@ -91,9 +91,9 @@ hipError_t h2d_l2l(const int* boxes, int nb, const TreeView& tv, const H2DOps& o
 hipError_t h2d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const TreeView& tv,
                         const PointsView& pv, double kappa, const int64_t* poff, const cplx* vals,
                         const cplx* mpole, const cplx* local, cplx* ufar, hipStream_t st);
-hipError_t h2d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                   double kappa, const cplx* ufar, const int* perm, double* out, int mixed,
-                   hipStream_t st);
+hipError_t h2d_p2p(const int* ser_leaves, int nser, const int* ser_nterm, const int* gen_leaves, int ngen,
+                   const TreeView& tv, const PointsView& pv, double kappa, const cplx* ufar,
+                   const int* perm, double* out, int mixed, hipStream_t st);
 
 // 3D Laplace evaluation (l3d_kernels.hip); P is the common expansion length
 hipError_t l3d_p2m(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
