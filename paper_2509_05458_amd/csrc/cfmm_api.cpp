@@ -842,7 +842,8 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         HIPCHK(h3d_leaf_far(W + p->off_leaves, p->nleaf, top, std::max(1, p->pmax), tv, pv, hl,
                             p->d_mpole, p->d_local, p->d_ufar, st));
         HIPCHK(mark(6));
-        HIPCHK(h3d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out, st));
+        HIPCHK(h3d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out,
+                       p->precision, st));
     } else {
         int P = p->pmax;
         HIPCHK(l3d_p2m(W + p->off_p2m, p->n_p2m, P, tv, pv, p->d_mpole, st));
@@ -859,7 +860,7 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         HIPCHK(l3d_leaf_far(W + p->off_leaves, p->nleaf, top, tv, pv, p->d_mpole, p->d_local,
                             p->d_ufar, st));
         HIPCHK(mark(6));
-        HIPCHK(l3d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->d_ufar, p->d_perm, out, st));
+        HIPCHK(l3d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->d_ufar, p->d_perm, out, p->precision, st));
     }
     HIPCHK(mark(7));
     if (!on_device) {

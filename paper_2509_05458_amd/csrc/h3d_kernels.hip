@@ -334,6 +334,9 @@ __global__ __launch_bounds__(64) void k_h3d_leaf_far(const int* __restrict__ lea
 // ------------------------------------------------------------------ P2P
 // G = e^{i kappa r} / (4 pi r) with the principal r = t + i Im s/(2t),
 // t = sqrt((|s| + Re s)/2): e^{i kappa r}/r = e^{-kappa Im r} (cos + i sin)(kappa Re r) conj(r) / |s|.
+// MIXED: differences formed in FP64 and cast to FP32, kernel and products in
+// FP32, each source tile summed in FP32 and the tile sums added in FP64.
+template <bool MIXED>
 __global__ __launch_bounds__(64) void k_h3d_p2p(const int* __restrict__ leaves, TreeView tv, PointsView pv,
                                                 double kappa, const cplx* __restrict__ ufar,
                                                 const int* __restrict__ perm, double* __restrict__ out)
@@ -344,6 +347,7 @@ __global__ __launch_bounds__(64) void k_h3d_p2p(const int* __restrict__ leaves, 
     int t = threadIdx.x;
     int p0 = tv.pbeg[b], p1 = tv.pend[b];
     int e0 = tv.l1off[b], e1 = tv.l1off[b + 1];
+    float kf = (float)kappa;
     for (int i0 = p0; i0 < p1; i0 += 64) {
         int i = i0 + t;
         bool active = i < p1;
@@ -364,7 +368,32 @@ __global__ __launch_bounds__(64) void k_h3d_p2p(const int* __restrict__ leaves, 
                     ss[1][t] = pv.sim[j];
                 }
                 __syncthreads();
-                if (active) {
+                if (!active) continue;
+                if (MIXED) {
+                    float fr = 0.0f, fi = 0.0f;
+                    for (int q = 0; q < cnt; ++q) {
+                        if (j0 + q == i) continue;
+                        float sr = 0.0f, si = 0.0f;
+                        for (int d = 0; d < 3; ++d) {
+                            float dr = (float)(xr[d] - sx[2 * d][q]), di = (float)(xi[d] - sx[2 * d + 1][q]);
+                            sr += dr * dr - di * di;
+                            si += 2.0f * dr * di;
+                        }
+                        if (sr == 0.0f && si == 0.0f) continue;
+                        float as = sqrtf(sr * sr + si * si);
+                        float tt = sqrtf(0.5f * (as + sr));
+                        float rr = tt, ri = 0.5f * si / tt;
+                        float sn, cs;
+                        sincosf(kf * rr, &sn, &cs);
+                        float ex = expf(-kf * ri) / as;
+                        float gr = (cs * rr + sn * ri) * ex, gi = (sn * rr - cs * ri) * ex;
+                        float wr = (float)ss[0][q], wi = (float)ss[1][q];
+                        fr += gr * wr - gi * wi;
+                        fi += gr * wi + gi * wr;
+                    }
+                    ar += (double)fr;
+                    ai += (double)fi;
+                } else {
                     for (int q = 0; q < cnt; ++q) {
                         if (j0 + q == i) continue;
                         double sr = 0.0, si = 0.0;
@@ -751,10 +780,11 @@ hipError_t h3d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const T
 }
 
 hipError_t h3d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv, double kappa,
-                   const cplx* ufar, const int* perm, double* out, hipStream_t st)
+                   const cplx* ufar, const int* perm, double* out, int mixed, hipStream_t st)
 {
     if (nleaf <= 0) return hipSuccess;
-    k_h3d_p2p<<<nleaf, 64, 0, st>>>(leaves, tv, pv, kappa, ufar, perm, out);
+    if (mixed) k_h3d_p2p<true><<<nleaf, 64, 0, st>>>(leaves, tv, pv, kappa, ufar, perm, out);
+    else k_h3d_p2p<false><<<nleaf, 64, 0, st>>>(leaves, tv, pv, kappa, ufar, perm, out);
     return hipGetLastError();
 }
 

@@ -108,7 +108,7 @@ hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& t
                         const PointsView& pv, const cplx* mpole, const cplx* local, cplx* ufar,
                         hipStream_t st);
 hipError_t l3d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                   const cplx* ufar, const int* perm, double* out, hipStream_t st);
+                   const cplx* ufar, const int* perm, double* out, int mixed, hipStream_t st);
 size_t l3d_max_lds_m2l(int P);
 int l3d_pmax_supported();
 
@@ -152,7 +152,7 @@ hipError_t h3d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const T
                         const PointsView& pv, const H3DLevels& hl, const cplx* mpole,
                         const cplx* local, cplx* ufar, hipStream_t st);
 hipError_t h3d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv, double kappa,
-                   const cplx* ufar, const int* perm, double* out, hipStream_t st);
+                   const cplx* ufar, const int* perm, double* out, int mixed, hipStream_t st);
 hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_src, const cplx* coef_src,
                          const int* gdst, const int* goff, int ng, const int* eoff_dst, cplx* coef_dst,
                          const double* eq_p0, const double* eq_d0, hipStream_t st);

@@ -355,7 +355,10 @@ __global__ __launch_bounds__(64) void k_l3d_leaf_far(const int* __restrict__ lea
 
 // ------------------------------------------------------------------ P2P
 // 1/(4 pi r) with the principal root: 1/sqrt(s) = (t - i Im s/(2t)) / |s|,
-// t = sqrt((|s| + Re s)/2).
+// t = sqrt((|s| + Re s)/2).  MIXED: the coordinate differences are formed in
+// FP64 and cast to FP32, the kernel and the products run in FP32, each source
+// tile is summed in FP32 and the tile sums are added in FP64.
+template <bool MIXED>
 __global__ __launch_bounds__(64) void k_l3d_p2p(const int* __restrict__ leaves, TreeView tv,
                                                 PointsView pv, const cplx* __restrict__ ufar,
                                                 const int* __restrict__ perm, double* __restrict__ out)
@@ -386,7 +389,29 @@ __global__ __launch_bounds__(64) void k_l3d_p2p(const int* __restrict__ leaves, 
                     ss[1][t] = pv.sim[j];
                 }
                 __syncthreads();
-                if (active) {
+                if (!active) continue;
+                if (MIXED) {
+                    float fr = 0.0f, fi = 0.0f;
+                    for (int q = 0; q < cnt; ++q) {
+                        if (j0 + q == i) continue;
+                        float sr = 0.0f, si = 0.0f;
+                        for (int d = 0; d < 3; ++d) {
+                            float dr = (float)(xr[d] - sx[2 * d][q]), di = (float)(xi[d] - sx[2 * d + 1][q]);
+                            sr += dr * dr - di * di;
+                            si += 2.0f * dr * di;
+                        }
+                        if (sr == 0.0f && si == 0.0f) continue;
+                        float as = sqrtf(sr * sr + si * si);
+                        float tt = sqrtf(0.5f * (as + sr));
+                        float ias = 1.0f / as;
+                        float gr = tt * ias, gi = -0.5f * si * ias / tt;
+                        float wr = (float)ss[0][q], wi = (float)ss[1][q];
+                        fr += gr * wr - gi * wi;
+                        fi += gr * wi + gi * wr;
+                    }
+                    ar += (double)fr;
+                    ai += (double)fi;
+                } else {
                     for (int q = 0; q < cnt; ++q) {
                         if (j0 + q == i) continue;
                         double sr = 0.0, si = 0.0;
@@ -470,10 +495,11 @@ hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& t
 }
 
 hipError_t l3d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                   const cplx* ufar, const int* perm, double* out, hipStream_t st)
+                   const cplx* ufar, const int* perm, double* out, int mixed, hipStream_t st)
 {
     if (nleaf <= 0) return hipSuccess;
-    k_l3d_p2p<<<nleaf, 64, 0, st>>>(leaves, tv, pv, ufar, perm, out);
+    if (mixed) k_l3d_p2p<true><<<nleaf, 64, 0, st>>>(leaves, tv, pv, ufar, perm, out);
+    else k_l3d_p2p<false><<<nleaf, 64, 0, st>>>(leaves, tv, pv, ufar, perm, out);
     return hipGetLastError();
 }
 
