@@ -83,7 +83,7 @@ struct cfmm_plan_s {
     cplx *d_mpole = nullptr, *d_local = nullptr, *d_ufar = nullptr;
     int off_p2l = 0, n_p2l = 0;
     int off_p2p_ser = 0, n_p2p_ser = 0, off_p2p_gen = 0, n_p2p_gen = 0;
-    int* d_p2p_nterm = nullptr;   // series terms per series-only P2P leaf
+    int* d_p2p_nterm = nullptr;   // per P2P leaf: series terms (2D) or the wide-phase flag (3D Helmholtz)
     // plan-time translation operators (2D Helmholtz)
     int64_t *d_o_m2l = nullptr, *d_o_tr = nullptr;
     cplx *d_g_m2l = nullptr, *d_g_m2m = nullptr, *d_g_l2l = nullptr;
@@ -466,11 +466,6 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         while (top < nlev && p->kappa * dmax[top] > tau) ++top;
     }
     if (top > nlev) top = nlev;
-    // -------- lists (a5)
-    build_lists(t, top);
-    for (int q = 0; q < 4; ++q)
-        if ((rc = upload(p, &p->d_loff[q], t.off[q])) || (rc = upload(p, &p->d_lidx[q], t.idx[q])))
-            return rc;
     // -------- expansion lengths (a6)
     bool h2d = dim == 2;
     p->P.assign(nlev, 0);
@@ -482,6 +477,10 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
             double w = p->D * ldexp(1.0, -l);
             p->rs[l] = std::min(1.0, p->kappa * w);
             int m = nterms_level(p->dim, p->sep, p->kappa, w, eps, kPMax2D);
+            if (m > kPMax2D && l == top && top + 1 < nlev) {
+                ++top;   // boxes this wide stay in the near field of the coarser lists
+                continue;
+            }
             if (m > kPMax2D)
                 return fail(CFMM_ERANGE, "expansion length above the supported maximum (" +
                                              std::to_string(kPMax2D) + ") at level " + std::to_string(l) +
@@ -490,12 +489,20 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
             pmax = std::max(pmax, m);
         }
     } else if (p->kernel == CFMM_HELMHOLTZ) {
-        // 3D Helmholtz: |h_n(kR) j_n(kr)| <= eps at n and n+1 (Sec. 6.3) with
-        // eps = tol/10, as in 2D; coordinates of level l are scaled by 1/w_l
+        // 3D Helmholtz: |h_n(kR) j_n(kr)| <= eps_l at n and n+1 (Sec. 6.3) with
+        // eps_l = (tol/10) e^{-kappa delta_l / 2}: in the oscillatory range the
+        // continued expansion terms of a box whose points spread by delta_l in
+        // the imaginary direction grow with e^{kappa delta_l}; half the exponent
+        // is the empirical margin.  Coordinates of level l are scaled by 1/w_l.
         for (int l = top; l < nlev; ++l) {
             double w = p->D * ldexp(1.0, -l);
             p->rs[l] = 1.0 / w;
-            int m = h3d_nterms(p->kappa, w, p->sep, 0.1 * p->tol, kPMaxH3);
+            double eps = 0.1 * p->tol * exp(-0.5 * p->kappa * dmax[l]);
+            int m = h3d_nterms(p->kappa, w, p->sep, eps, kPMaxH3);
+            if (m > kPMaxH3 && l == top && top + 1 < nlev) {
+                ++top;   // boxes this wide stay in the near field of the coarser lists
+                continue;
+            }
             if (m > kPMaxH3)
                 return fail(CFMM_ERANGE, "expansion length above the supported maximum (" +
                                              std::to_string(kPMaxH3) + ") at level " + std::to_string(l) +
@@ -518,6 +525,11 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         pmax = m;
     }
     p->pmax = pmax;
+    // -------- lists (a5), from the final top level
+    build_lists(t, top);
+    for (int q = 0; q < 4; ++q)
+        if ((rc = upload(p, &p->d_loff[q], t.off[q])) || (rc = upload(p, &p->d_lidx[q], t.idx[q])))
+            return rc;
     auto ncoef = [&](int l) -> int64_t { return h2d ? 2 * p->P[l] + 1 : (int64_t)(p->P[l] + 1) * (p->P[l] + 1); };
     std::vector<int> eoff(nb, -1);
     int64_t ecount = 0;
@@ -614,6 +626,30 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         work.insert(work.end(), gen.begin(), gen.end());
         p->n_p2p_gen = (int)gen.size();
         if ((rc = upload(p, &p->d_p2p_nterm, ser_nterm))) return rc;
+    }
+    // 3D Helmholtz mixed near field: leaves whose near pairs may reach
+    // kappa |r| > 8 form the phase in FP64 (same box bound as above)
+    if (dim == 3 && p->kernel == CFMM_HELMHOLTZ) {
+        std::vector<int> wide;
+        for (int b = 0; b < nb; ++b) {
+            if (t.nchild[b]) continue;
+            double rb = 0.0, wb = p->D * ldexp(1.0, -t.level[b]);
+            for (int e = t.off[0][b]; e < t.off[0][b + 1]; ++e) {
+                int a = t.idx[0][e];
+                double wa = p->D * ldexp(1.0, -t.level[a]);
+                double sre = 0.0, sci = 0.0;
+                for (int k = 0; k < dim; ++k) {
+                    double dr = fabs(cre[(size_t)k * nb + b] - cre[(size_t)k * nb + a]) + 0.5 * (wa + wb);
+                    double dc = cim[(size_t)k * nb + b] - cim[(size_t)k * nb + a];
+                    sre += dr * dr;
+                    sci += dc * dc;
+                }
+                double di = delta[a] + delta[b] + sqrt(sci);
+                rb = std::max(rb, sqrt(sre + di * di));
+            }
+            wide.push_back(p->kappa * rb > 8.0 ? 1 : 0);
+        }
+        if ((rc = upload(p, &p->d_p2p_nterm, wide))) return rc;
     }
     if ((rc = upload(p, &p->d_work, work))) return rc;
     int64_t gsz = 0, tsz = 0, psz = 0;
@@ -842,8 +878,8 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         HIPCHK(h3d_leaf_far(W + p->off_leaves, p->nleaf, top, std::max(1, p->pmax), tv, pv, hl,
                             p->d_mpole, p->d_local, p->d_ufar, st));
         HIPCHK(mark(6));
-        HIPCHK(h3d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out,
-                       p->precision, st));
+        HIPCHK(h3d_p2p(W + p->off_leaves, p->d_p2p_nterm, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm,
+                       out, p->precision, st));
     } else {
         int P = p->pmax;
         HIPCHK(l3d_p2m(W + p->off_p2m, p->n_p2m, P, tv, pv, p->d_mpole, st));

@@ -336,13 +336,18 @@ __global__ __launch_bounds__(64) void k_h3d_leaf_far(const int* __restrict__ lea
 // t = sqrt((|s| + Re s)/2): e^{i kappa r}/r = e^{-kappa Im r} (cos + i sin)(kappa Re r) conj(r) / |s|.
 // MIXED: differences formed in FP64 and cast to FP32, kernel and products in
 // FP32, each source tile summed in FP32 and the tile sums added in FP64.
+// Leaves whose near field reaches kappa r > 8 (flag[] set at plan time) form
+// r and the phase kappa Re r in FP64, reduce it mod 2 pi, and take sincos and
+// exp in FP32, so the phase error stays near FP32 rounding of an angle below pi.
 template <bool MIXED>
-__global__ __launch_bounds__(64) void k_h3d_p2p(const int* __restrict__ leaves, TreeView tv, PointsView pv,
+__global__ __launch_bounds__(64) void k_h3d_p2p(const int* __restrict__ leaves, const int* __restrict__ flag,
+                                                TreeView tv, PointsView pv,
                                                 double kappa, const cplx* __restrict__ ufar,
                                                 const int* __restrict__ perm, double* __restrict__ out)
 {
     __shared__ double sx[6][64], ss[2][64];
     int b = leaves[blockIdx.x];
+    bool wide = MIXED && flag[blockIdx.x] != 0;
     int64_t n = pv.n;
     int t = threadIdx.x;
     int p0 = tv.pbeg[b], p1 = tv.pend[b];
@@ -369,7 +374,34 @@ __global__ __launch_bounds__(64) void k_h3d_p2p(const int* __restrict__ leaves, 
                 }
                 __syncthreads();
                 if (!active) continue;
-                if (MIXED) {
+                if (MIXED && wide) {
+                    float fr = 0.0f, fi = 0.0f;
+                    const double tpi = 2.0 * kPi, itpi = 1.0 / (2.0 * kPi);
+                    for (int q = 0; q < cnt; ++q) {
+                        if (j0 + q == i) continue;
+                        double sr = 0.0, si = 0.0;
+                        for (int d = 0; d < 3; ++d) {
+                            double dr = xr[d] - sx[2 * d][q], di = xi[d] - sx[2 * d + 1][q];
+                            sr += dr * dr - di * di;
+                            si += 2.0 * dr * di;
+                        }
+                        if (sr == 0.0 && si == 0.0) continue;
+                        double as = sqrt(sr * sr + si * si);
+                        double tt = sqrt(0.5 * (as + sr));
+                        double ph = kappa * tt;
+                        ph -= tpi * rint(ph * itpi);
+                        float rr = (float)tt, ri = (float)(0.5 * si / tt);
+                        float sn, cs;
+                        sincosf((float)ph, &sn, &cs);
+                        float ex = expf(-kf * ri) / (float)as;
+                        float gr = (cs * rr + sn * ri) * ex, gi = (sn * rr - cs * ri) * ex;
+                        float wr = (float)ss[0][q], wi = (float)ss[1][q];
+                        fr += gr * wr - gi * wi;
+                        fi += gr * wi + gi * wr;
+                    }
+                    ar += (double)fr;
+                    ai += (double)fi;
+                } else if (MIXED) {
                     float fr = 0.0f, fi = 0.0f;
                     for (int q = 0; q < cnt; ++q) {
                         if (j0 + q == i) continue;
@@ -779,12 +811,12 @@ hipError_t h3d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const T
     return hipGetLastError();
 }
 
-hipError_t h3d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv, double kappa,
-                   const cplx* ufar, const int* perm, double* out, int mixed, hipStream_t st)
+hipError_t h3d_p2p(const int* leaves, const int* wide, int nleaf, const TreeView& tv, const PointsView& pv,
+                   double kappa, const cplx* ufar, const int* perm, double* out, int mixed, hipStream_t st)
 {
     if (nleaf <= 0) return hipSuccess;
-    if (mixed) k_h3d_p2p<true><<<nleaf, 64, 0, st>>>(leaves, tv, pv, kappa, ufar, perm, out);
-    else k_h3d_p2p<false><<<nleaf, 64, 0, st>>>(leaves, tv, pv, kappa, ufar, perm, out);
+    if (mixed) k_h3d_p2p<true><<<nleaf, 64, 0, st>>>(leaves, wide, tv, pv, kappa, ufar, perm, out);
+    else k_h3d_p2p<false><<<nleaf, 64, 0, st>>>(leaves, wide, tv, pv, kappa, ufar, perm, out);
     return hipGetLastError();
 }
 

@@ -151,8 +151,8 @@ hipError_t h3d_p2l(const int* boxes, int nb, int pmax, const TreeView& tv, const
 hipError_t h3d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const TreeView& tv,
                         const PointsView& pv, const H3DLevels& hl, const cplx* mpole,
                         const cplx* local, cplx* ufar, hipStream_t st);
-hipError_t h3d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv, double kappa,
-                   const cplx* ufar, const int* perm, double* out, int mixed, hipStream_t st);
+hipError_t h3d_p2p(const int* leaves, const int* wide, int nleaf, const TreeView& tv, const PointsView& pv,
+                   double kappa, const cplx* ufar, const int* perm, double* out, int mixed, hipStream_t st);
 hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_src, const cplx* coef_src,
                          const int* gdst, const int* goff, int ng, const int* eoff_dst, cplx* coef_dst,
                          const double* eq_p0, const double* eq_d0, hipStream_t st);

@@ -152,26 +152,47 @@ def make_config(i: int, n: int | None = None, n_oracle: int = 4096) -> Config:
 
 @dataclass
 class Request:
+    """One served request: a geometry, a wavenumber and a tolerance, evaluated
+    for `nmat` densities in turn (the matvecs of an iterative solve).  Arrays
+    are drawn on demand from the request's seeds."""
     rid: int
     arrival: float        # seconds after trace start
     dim: int
     kappa: float
     tol: float
-    n: int
-    points: np.ndarray
-    sigmas: list          # list of complex128[n]
-    check_targets: np.ndarray
+    n: int                # number of points (3D: a square grid, n = m^2)
+    scale: float          # geometry scale (keeps kappa * extent in the validated range)
+    nmat: int = 20
+
+    def points(self) -> np.ndarray:
+        if self.dim == 2:
+            return curve2d(self.n, 5000 + self.rid, scale=self.scale)
+        m = int(round(math.sqrt(self.n)))
+        return plane3d_bumps(m, 5000 + self.rid, scale=self.scale)
+
+    def density_factors(self):
+        """(a, b): the m-th density is a * exp(2 pi i m b), a complex Gaussian
+        (seed 6000 + rid), b uniform on [0, 1) (seed 8000 + rid)."""
+        a = density(self.n, 6000 + self.rid)
+        b = np.random.default_rng(8000 + self.rid).uniform(0.0, 1.0, size=self.n)
+        return a, b
+
+    def density(self, m: int) -> np.ndarray:
+        a, b = self.density_factors()
+        return a * np.exp(2j * np.pi * m * b)
+
+    def check_targets(self, k: int = 64) -> np.ndarray:
+        return sample_targets(self.n, min(k, self.n), 7000 + self.rid)
 
 
 def serving_trace(nreq: int = 512, rate: float = 100.0, nmat: int = 20,
-                  nmin_log2: float = 10.0, nmax_log2: float = 18.0,
-                  n_check: int = 256, seed: int = 4000) -> list:
-    """Seeded request trace for the served stream (Poisson arrivals at `rate`/s).
-
-    Geometry of request r uses seed 5000+r, its m-th density 6000+20r+m.
+                  nmin_log2: float = 10.0, nmax_log2: float = 18.0, seed: int = 4000) -> list:
+    """Seeded request trace for the served stream: Poisson arrivals at `rate`/s,
+    sizes log-uniform in [2^nmin_log2, 2^nmax_log2], half 2D and half 3D
+    Helmholtz, kappa log-uniform in [1, 200], tolerance from {1e-4, 1e-6, 1e-10}.
     2D requests use the curve scaled by min(1, 10/kappa); 3D requests the bump
-    plane (n' = round(sqrt n)^2) scaled by min(1, KAPPA_C3/kappa).
-    """
+    plane (n = round(sqrt N)^2) scaled by min(1, KAPPA_C3/kappa), so every
+    request keeps the wavelength count of the validated configurations."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, size=nreq)
     arr = np.cumsum(gaps) - gaps[0]
@@ -183,15 +204,10 @@ def serving_trace(nreq: int = 512, rate: float = 100.0, nmat: int = 20,
     for r in range(nreq):
         n = int(round(2.0 ** logn[r]))
         if dims[r] == 2:
-            s = min(1.0, 10.0 / kap[r])
-            pts = curve2d(n, 5000 + r, scale=s)
+            sc = min(1.0, 10.0 / kap[r])
         else:
             m = max(2, int(round(math.sqrt(n))))
-            s = min(1.0, KAPPA_C3 / kap[r])
-            pts = plane3d_bumps(m, 5000 + r, scale=s)
-        nn = pts.shape[0]
-        sig = [density(nn, 6000 + nmat * r + mm) for mm in range(nmat)]
-        chk = sample_targets(nn, n_check, 7000 + r)
-        out.append(Request(r, float(arr[r]), int(dims[r]), float(kap[r]),
-                           float(tols[r]), nn, pts, sig, chk))
+            n = m * m
+            sc = min(1.0, KAPPA_C3 / kap[r])
+        out.append(Request(r, float(arr[r]), int(dims[r]), float(kap[r]), float(tols[r]), n, sc, nmat))
     return out

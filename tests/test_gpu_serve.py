@@ -1,0 +1,59 @@
+"""GPU checks of the served stream: every request's result is the same alone
+and in the mix, matches the oracle within its tolerance, and admission keeps
+the resident plans within the HBM budget."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2509_05458_amd import serve  # noqa: E402
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+def _prepared(nreq, nmax_log2, seed):
+    return [serve.Prepared(r) for r in synth.serving_trace(nreq, rate=1.0, nmax_log2=nmax_log2, seed=seed)]
+
+
+def test_same_alone_and_in_mix_and_oracle():
+    prep = _prepared(12, 12.5, 4100)
+    for p in prep:
+        p.req.nmat = 3
+    print(f"[gpu] serve mix test: {[(p.req.dim, p.req.n, round(p.req.kappa, 1), p.req.tol) for p in prep]}",
+          flush=True)
+    alone = serve.Server(slots=1, keep_results=True).run(prep, rate_scale=0.0)
+    mix = serve.Server(slots=4, keep_results=True).run(prep, rate_scale=0.0)
+    for k, p in enumerate(prep):
+        a = alone["records"][k]["result"].cpu().numpy()
+        b = mix["records"][k]["result"].cpu().numpy()
+        d = np.linalg.norm(a - b) / np.linalg.norm(a)
+        assert d <= p.req.tol, (k, d)
+        # the last matvec against the oracle on sampled targets
+        r = p.req
+        tg = r.check_targets(48)
+        sig = r.density(r.nmat - 1)
+        u0 = oracle.direct_self(r.dim, "helmholtz", r.kappa, p.points, sig, targets=tg, nthreads=NTHREADS)
+        e = oracle.rel_l2(b[tg], u0)
+        print(f"[gpu] req {r.rid} dim={r.dim} n={r.n} tol={r.tol}: mix-vs-alone {d:.2e}, vs oracle {e:.2e}",
+              flush=True)
+        assert e <= r.tol
+
+
+def test_admission_keeps_budget():
+    prep = _prepared(8, 12.0, 4200)
+    for p in prep:
+        p.req.nmat = 2
+    res = serve.Server(slots=4, hbm_budget=1).run(prep, rate_scale=0.0)
+    single = max(max(rec["bytes"], serve.estimate_bytes(p.req.dim, p.req.n))
+                 for rec, p in zip(res["records"], prep))
+    print(f"[gpu] admission peak {res['peak_bytes']} single max {single}", flush=True)
+    assert res["peak_bytes"] <= single
