@@ -154,6 +154,7 @@ def main():
             "leaf_size": info["leaf_size"], "separation": info["separation"],
             "top_level": info["top_level"], "levels": info["nlevels"], "max_p": info["max_p"],
             "p2p_pairs": info["p2p_pairs"], "m2l_pairs": info["m2l_pairs"],
+            "boxes": info["nbox"], "leaves": info["nleaf"], "list3": info["n_list3"], "list4": info["n_list4"],
             "plan_ms": plan_ms, "stage_ms": stage_avg,
             "rel_l2_err_sampled": rel, "err_targets": int(len(tg)),
             "step": "one cfmm_eval on a warm plan",

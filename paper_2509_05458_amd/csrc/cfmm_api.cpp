@@ -83,6 +83,8 @@ struct cfmm_plan_s {
     cplx *d_mpole = nullptr, *d_local = nullptr, *d_ufar = nullptr;
     int off_p2l = 0, n_p2l = 0;
     int off_p2p_ser = 0, n_p2p_ser = 0, off_p2p_gen = 0, n_p2p_gen = 0;
+    int off_m2p = 0, n_m2p = 0;   // leaves with List-3 boxes
+    std::vector<int> p2l_h;       // host copy of the P2L work list (level order)
     int* d_p2p_nterm = nullptr;   // per P2P leaf: series terms (2D) or the wide-phase flag (3D Helmholtz)
     // plan-time translation operators (2D Helmholtz)
     int64_t *d_o_m2l = nullptr, *d_o_tr = nullptr;
@@ -571,10 +573,15 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         for (int b = t.lvl_beg[l]; b < t.lvl_beg[l + 1]; ++b) work.push_back(b);
         p->l2l_cnt[l] = (int)work.size() - p->l2l_off[l];
     }
+    p->off_m2p = (int)work.size();
+    for (int b = 0; b < nb; ++b)
+        if (t.nchild[b] == 0 && t.level[b] >= top && t.off[2][b + 1] > t.off[2][b]) work.push_back(b);
+    p->n_m2p = (int)work.size() - p->off_m2p;
     p->off_p2l = (int)work.size();
     for (int b = 0; b < nb; ++b)
         if (t.level[b] >= top && t.off[3][b + 1] > t.off[3][b]) work.push_back(b);
     p->n_p2l = (int)work.size() - p->off_p2l;
+    p->p2l_h.assign(work.begin() + p->off_p2l, work.end());
     int off_tr = (int)work.size();
     for (int b = 0; b < nb; ++b)
         if (t.level[b] >= top + 1) work.push_back(b);
@@ -818,16 +825,36 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         HIPCHK(h2d_p2m(W + p->off_p2m, p->n_p2m, tv, pv, p->d_poff, p->d_pvals, p->d_mpole, st));
         HIPCHK(mark(2));
         for (int l = nlev - 2; l >= top; --l)
-            HIPCHK(h2d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], tv, p->ops(), p->d_mpole, st));
+            HIPCHK(h2d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], 2 * p->P[l] + 1, tv, p->ops(), p->d_mpole, st));
         HIPCHK(mark(3));
-        HIPCHK(h2d_m2l(W + p->off_m2l, p->n_m2l, tv, p->ops(), p->d_mpole, p->d_local, st));
-        HIPCHK(h2d_p2l(W + p->off_p2l, p->n_p2l, tv, pv, p->kappa, p->d_local, st));
+        {
+            // the M2L list holds the boxes of levels >= top in level order
+            int nlv = nlev - top, boff[64], cnt[64], nco[64];
+            for (int k = 0; k < nlv && k < 64; ++k) {
+                int l = top + k;
+                boff[k] = t.lvl_beg[l] - t.lvl_beg[top];
+                cnt[k] = t.lvl_beg[l + 1] - t.lvl_beg[l];
+                nco[k] = 2 * p->P[l] + 1;
+            }
+            HIPCHK(h2d_m2l(W + p->off_m2l, std::min(nlv, 64), boff, cnt, nco, tv, p->ops(), p->d_mpole,
+                           p->d_local, st));
+        }
+        {
+            // the P2L list is in level order; one launch per level sizes its LDS by that level's P
+            int k0 = 0;
+            while (k0 < p->n_p2l) {
+                int l = t.level[p->p2l_h[k0]], k1 = k0;
+                while (k1 < p->n_p2l && t.level[p->p2l_h[k1]] == l) ++k1;
+                HIPCHK(h2d_p2l(W + p->off_p2l + k0, k1 - k0, p->P[l], tv, pv, p->kappa, p->d_local, st));
+                k0 = k1;
+            }
+        }
         HIPCHK(mark(4));
         for (int l = top + 1; l < nlev; ++l)
-            HIPCHK(h2d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], tv, p->ops(), p->d_local, st));
+            HIPCHK(h2d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], 2 * p->P[l] + 1, tv, p->ops(), p->d_local, st));
         HIPCHK(mark(5));
-        HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, top, std::max(1, p->pmax), tv, pv, p->kappa,
-                            p->d_poff, p->d_pvals, p->d_mpole, p->d_local, p->d_ufar, st));
+        HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, W + p->off_m2p, p->n_m2p, top, std::max(1, p->pmax), tv,
+                            pv, p->kappa, p->d_poff, p->d_pvals, p->d_mpole, p->d_local, p->d_ufar, st));
         HIPCHK(mark(6));
         HIPCHK(h2d_p2p(W + p->off_p2p_ser, p->n_p2p_ser, p->d_p2p_nterm, W + p->off_p2p_gen, p->n_p2p_gen,
                        tv, pv, p->kappa, p->d_ufar, p->d_perm, out, p->precision, st));

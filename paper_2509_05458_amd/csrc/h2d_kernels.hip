@@ -62,6 +62,7 @@ constexpr int kChunk = 16;
 //   v[n + P] = J_n(kappa rho_Y) e^{-in phi_Y} / r^|n|,  n = -P..P.
 // P2M is M_n = sum_j sigma_j v_n(j); L2P reuses them since
 // J_n(kappa rho_X) e^{in phi_X} / r^|n| = (-1)^n v_{-n} at the same point.
+// Within a leaf the values are stored point-major, v_n(j) at j * (2P+1) + n + P.
 __global__ void k_h2d_gen_pts(const int* __restrict__ leaves, int nleaf, TreeView tv, PointsView pv,
                               double kappa, const int64_t* __restrict__ poff, cplx* __restrict__ vals)
 {
@@ -183,130 +184,183 @@ __global__ void k_h2d_gen_tr(const int* __restrict__ boxes, int nb, TreeView tv,
     fill_signed(g, K, bp, bm, fact);
 }
 
+// Launch shape shared by M2M, M2L and L2L (one launch per level): G lanes own
+// the output coefficients (G >= 2P+1 when possible), S groups of G lanes split
+// the input sum of a box (partial sums reduced through LDS), and 256/(G S)
+// boxes share a 256-thread block.  All boxes of a launch have the same P.
+struct TShape {
+    int G, S;
+};
+
+constexpr int kMaxLv = 32;
+struct LvTable {
+    int n;                          // levels in the launch
+    int first_block[kMaxLv + 1];    // block range of each level
+    int box_off[kMaxLv], nb[kMaxLv], G[kMaxLv], S[kMaxLv];
+};
+
+__device__ inline cplx tsum(cplx acc, cplx* part, int G, int S, int s)
+{
+    if (S == 1) return acc;
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    cplx r = acc;
+    if (s == 0)
+        for (int k = 1; k < S; ++k) r += part[threadIdx.x + k * G];
+    __syncthreads();
+    return r;
+}
+
 // ------------------------------------------------------------------ M2M
-// One wavefront per parent; lane m owns output coefficient m.  Entry (m, n)
-// of child c: gm2m[n - m] r_c^(|n-m| + |n| - |m|) (r_c/r_p)^|m|.
-__global__ __launch_bounds__(256) void k_h2d_m2m(const int* __restrict__ boxes, int nb, TreeView tv,
+// Entry (m, n) of child c: gm2m[n - m] r_c^(|n-m| + |n| - |m|) (r_c/r_p)^|m|.
+__global__ __launch_bounds__(256) void k_h2d_m2m(const int* __restrict__ boxes, int nb, TShape sh, TreeView tv,
                                                  H2DOps ops, cplx* __restrict__ mpole)
 {
-    int lane = threadIdx.x & 63;
-    int bi = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (bi >= nb) return;
-    int p = boxes[bi];
+    __shared__ cplx part[256];
+    int G = sh.G, S = sh.S, per = G * S;
+    int lane = threadIdx.x % G, s = (threadIdx.x / G) % S;
+    int bi = blockIdx.x * (256 / per) + threadIdx.x / per;
+    bool valid = bi < nb;
+    int p = boxes[valid ? bi : 0];
     int l = tv.level[p];
     int Pp = tv.P[l], Pc = tv.P[l + 1];
     int K = Pp + Pc, ncoef = 2 * Pp + 1;
     const double* pwc = ops.pw + (size_t)(l + 1) * kPwStride;
     double rat = tv.rs[l + 1] / tv.rs[l];
     int c0 = tv.child0[p], nc = tv.nchild[p];
-    for (int m0 = 0; m0 < ncoef; m0 += 64) {
+    for (int m0 = 0; m0 < ncoef; m0 += G) {
         int mi = m0 + lane;
-        if (mi >= ncoef) break;
         int mm = mi - Pp, am = mm < 0 ? -mm : mm;
         cplx acc = mk(0.0, 0.0);
-        for (int ci = 0; ci < nc; ++ci) {
-            int c = c0 + ci;
-            const cplx* M = mpole + tv.eoff[c] + Pc;
-            const cplx* G = ops.g_m2m + ops.o_tr[c] + K - mm;
-            for (int nn = -Pc; nn <= Pc; ++nn) {
-                int k = nn - mm;
-                int e = (k < 0 ? -k : k) + (nn < 0 ? -nn : nn) - am;
-                acc += (pwc[e] * G[nn]) * M[nn];
+        if (valid && mi < ncoef) {
+            for (int ci = 0; ci < nc; ++ci) {
+                int c = c0 + ci;
+                const cplx* M = mpole + tv.eoff[c] + Pc;
+                const cplx* Gv = ops.g_m2m + ops.o_tr[c] + K - mm;
+                for (int nn = -Pc + s; nn <= Pc; nn += S) {
+                    int k = nn - mm;
+                    int e = (k < 0 ? -k : k) + (nn < 0 ? -nn : nn) - am;
+                    acc += (pwc[e] * Gv[nn]) * M[nn];
+                }
             }
         }
-        mpole[tv.eoff[p] + mi] = pow(rat, (double)am) * acc;
+        acc = tsum(acc, part, G, S, s);
+        if (valid && mi < ncoef && s == 0) mpole[tv.eoff[p] + mi] = pow(rat, (double)am) * acc;
     }
 }
 
 // ------------------------------------------------------------------ M2L
-// One wavefront per target box; lane m owns L_m.  Entry (m, n) of source a:
-// gm2l[n - m] r^(|m| + |n| - |n - m|), i.e. r^(2 min(|m|,|n|)) when m, n have
-// the same sign and 1 otherwise.
-__global__ __launch_bounds__(256) void k_h2d_m2l(const int* __restrict__ boxes, int nb, TreeView tv,
+// Entry (m, n) of source a: gm2l[n - m] r^(|m| + |n| - |n - m|), i.e.
+// r^(2 min(|m|,|n|)) when m, n have the same sign and 1 otherwise.
+// All levels go in one launch (M2L has no dependence between levels); the
+// block table gives each level its own contiguous block range and shape.
+__global__ __launch_bounds__(256) void k_h2d_m2l(const int* __restrict__ boxes, LvTable lt, TreeView tv,
                                                  H2DOps ops, const cplx* __restrict__ mpole,
                                                  cplx* __restrict__ local)
 {
-    int lane = threadIdx.x & 63;
-    int bi = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (bi >= nb) return;
-    int b = boxes[bi];
+    __shared__ cplx part[256];
+    int k = 0;
+    while (k + 1 < lt.n && (int)blockIdx.x >= lt.first_block[k + 1]) ++k;
+    int G = lt.G[k], S = lt.S[k], per = G * S, nb = lt.nb[k];
+    int lane = threadIdx.x % G, s = (threadIdx.x / G) % S;
+    int bi = (blockIdx.x - lt.first_block[k]) * (256 / per) + threadIdx.x / per;
+    bool valid = bi < nb;
+    int b = boxes[lt.box_off[k] + (valid ? bi : 0)];
     int l = tv.level[b];
     int P = tv.P[l], ncoef = 2 * P + 1;
     const double* pw = ops.pw + (size_t)l * kPwStride;
     int e0 = tv.l2off[b], e1 = tv.l2off[b + 1];
-    for (int m0 = 0; m0 < ncoef; m0 += 64) {
+    for (int m0 = 0; m0 < ncoef; m0 += G) {
         int mi = m0 + lane;
-        if (mi >= ncoef) break;
         int mm = mi - P, am = mm < 0 ? -mm : mm;
-        double rm = pw[2 * am];
         cplx acc = mk(0.0, 0.0);
-        for (int e = e0; e < e1; ++e) {
-            const cplx* M = mpole + tv.eoff[tv.l2idx[e]] + P;
-            const cplx* G = ops.g_m2l + ops.o_m2l[e] + 2 * P - mm;
-            for (int nn = -P; nn <= P; ++nn) {
-                int an = nn < 0 ? -nn : nn;
-                bool same = (nn > 0 && mm > 0) || (nn < 0 && mm < 0);
-                double f = same ? (an <= am ? pw[2 * an] : rm) : 1.0;
-                acc += (f * G[nn]) * M[nn];
+        if (valid && mi < ncoef) {
+            double rm = pw[2 * am];
+            for (int e = e0; e < e1; ++e) {
+                const cplx* M = mpole + tv.eoff[tv.l2idx[e]] + P;
+                const cplx* Gv = ops.g_m2l + ops.o_m2l[e] + 2 * P - mm;
+                for (int nn = -P + s; nn <= P; nn += S) {
+                    int an = nn < 0 ? -nn : nn;
+                    bool same = (nn > 0 && mm > 0) || (nn < 0 && mm < 0);
+                    double f = same ? (an <= am ? pw[2 * an] : rm) : 1.0;
+                    acc += (f * Gv[nn]) * M[nn];
+                }
             }
         }
-        local[tv.eoff[b] + mi] = acc;
+        acc = tsum(acc, part, G, S, s);
+        if (valid && mi < ncoef && s == 0) local[tv.eoff[b] + mi] = acc;
     }
 }
 
 // ------------------------------------------------------------------ P2L
 // Sources of the coarser leaves in List 4 go directly into the local
-// expansion (added after M2L wrote it).
+// expansion (added after M2L wrote it).  Launched per level.  Every thread of
+// the block computes the Hankel sequence of one source of the current chunk
+// into LDS; then thread t accumulates output coefficient t % G over the
+// sources q = t / G (mod S) of the chunk, and the S partial sums are reduced
+// through LDS at the end.
 __global__ __launch_bounds__(128) void k_h2d_p2l(const int* __restrict__ boxes, TreeView tv,
-                                                 PointsView pv, double kappa, cplx* __restrict__ local)
+                                                 PointsView pv, double kappa, int chunk, int pstride,
+                                                 cplx* __restrict__ local)
 {
-    __shared__ cplx gp[kChunk][kPMax2D + 1];
-    __shared__ cplx gn[kChunk][kPMax2D + 1];
-    __shared__ cplx ss[kChunk];
+    extern __shared__ cplx lds[];
+    cplx* gp = lds;                              // [chunk][pstride]
+    cplx* gn = gp + (size_t)chunk * pstride;     // [chunk][pstride]
+    cplx* ss = gn + (size_t)chunk * pstride;     // [chunk]
+    cplx* part = ss + chunk;                     // [128]
     int b = boxes[blockIdx.x];
     int l = tv.level[b];
     int P = tv.P[l];
     double r = tv.rs[l];
     int nbx = tv.nbox, ncoef = 2 * P + 1;
+    int G = ncoef <= 32 ? 32 : (ncoef <= 64 ? 64 : 128), S = 128 / G;
     int64_t n = pv.n;
-    int t = threadIdx.x, mm = t - P;
+    int t = threadIdx.x, mi = t % G, sp = t / G, mm = mi - P;
     cplx acc = mk(0.0, 0.0);
     cplx cb1 = mk(tv.cre[b], tv.cim[b]), cb2 = mk(tv.cre[nbx + b], tv.cim[nbx + b]);
     for (int e = tv.l4off[b]; e < tv.l4off[b + 1]; ++e) {
         int c = tv.l4idx[e];
         int q0 = tv.pbeg[c], q1 = tv.pend[c];
-        for (int j0 = q0; j0 < q1; j0 += kChunk) {
-            int cnt = min(kChunk, q1 - j0);
+        for (int j0 = q0; j0 < q1; j0 += chunk) {
+            int cnt = min(chunk, q1 - j0);
             if (t < cnt) {
                 int j = j0 + t;
                 cplx y1 = mk(pv.xre[j] - cb1.re, pv.xim[j] - cb1.im);
                 cplx y2 = mk(pv.xre[n + j] - cb2.re, pv.xim[n + j] - cb2.im);
-                hseq2(y1, y2, kappa, r, P, c_ghx, c_ghw, &gp[t][0], &gn[t][0], 1);
+                hseq2(y1, y2, kappa, r, P, c_ghx, c_ghw, gp + (size_t)t * pstride, gn + (size_t)t * pstride, 1);
                 ss[t] = mk(pv.sre[j], pv.sim[j]);
             }
             __syncthreads();
-            if (t < ncoef) {
-                for (int q = 0; q < cnt; ++q) {
-                    cplx v = (mm >= 0) ? gn[q][mm] : ((mm & 1) ? -gp[q][-mm] : gp[q][-mm]);
+            if (mi < ncoef) {
+                for (int q = sp; q < cnt; q += S) {
+                    const cplx* pq = gp + (size_t)q * pstride;
+                    const cplx* nq = gn + (size_t)q * pstride;
+                    cplx v = (mm >= 0) ? nq[mm] : ((mm & 1) ? -pq[-mm] : pq[-mm]);
                     acc += v * ss[q];
                 }
             }
             __syncthreads();
         }
     }
-    if (t < ncoef) local[tv.eoff[b] + t] += acc;
+    part[t] = acc;
+    __syncthreads();
+    if (sp == 0 && mi < ncoef) {
+        for (int k = 1; k < S; ++k) acc += part[t + k * G];
+        local[tv.eoff[b] + mi] += acc;
+    }
 }
 
 // ------------------------------------------------------------------ L2L
-// One wavefront per child box c; entry (m, n):
-// gl2l[n - m] r_p^(|n-m| + |m| - |n|) (r_c/r_p)^|m|.
-__global__ __launch_bounds__(256) void k_h2d_l2l(const int* __restrict__ boxes, int nb, TreeView tv,
+// Entry (m, n): gl2l[n - m] r_p^(|n-m| + |m| - |n|) (r_c/r_p)^|m|.
+__global__ __launch_bounds__(256) void k_h2d_l2l(const int* __restrict__ boxes, int nb, TShape sh, TreeView tv,
                                                  H2DOps ops, cplx* __restrict__ local)
 {
-    int lane = threadIdx.x & 63;
-    int bi = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (bi >= nb) return;
-    int c = boxes[bi];
+    __shared__ cplx part[256];
+    int G = sh.G, S = sh.S, per = G * S;
+    int lane = threadIdx.x % G, s = (threadIdx.x / G) % S;
+    int bi = blockIdx.x * (256 / per) + threadIdx.x / per;
+    bool valid = bi < nb;
+    int c = boxes[valid ? bi : 0];
     int p = tv.parent[c];
     int lc = tv.level[c];
     int Pc = tv.P[lc], Pp = tv.P[lc - 1];
@@ -314,71 +368,99 @@ __global__ __launch_bounds__(256) void k_h2d_l2l(const int* __restrict__ boxes, 
     const double* pwp = ops.pw + (size_t)(lc - 1) * kPwStride;
     double rat = tv.rs[lc] / tv.rs[lc - 1];
     const cplx* Lp = local + tv.eoff[p] + Pp;
-    for (int m0 = 0; m0 < ncoef; m0 += 64) {
+    for (int m0 = 0; m0 < ncoef; m0 += G) {
         int mi = m0 + lane;
-        if (mi >= ncoef) break;
         int mm = mi - Pc, am = mm < 0 ? -mm : mm;
-        const cplx* G = ops.g_l2l + ops.o_tr[c] + K - mm;
         cplx acc = mk(0.0, 0.0);
-        for (int nn = -Pp; nn <= Pp; ++nn) {
-            int k = nn - mm;
-            int e = (k < 0 ? -k : k) + am - (nn < 0 ? -nn : nn);
-            acc += (pwp[e] * G[nn]) * Lp[nn];
+        if (valid && mi < ncoef) {
+            const cplx* Gv = ops.g_l2l + ops.o_tr[c] + K - mm;
+            for (int nn = -Pp + s; nn <= Pp; nn += S) {
+                int k = nn - mm;
+                int e = (k < 0 ? -k : k) + am - (nn < 0 ? -nn : nn);
+                acc += (pwp[e] * Gv[nn]) * Lp[nn];
+            }
         }
-        local[tv.eoff[c] + mi] += pow(rat, (double)am) * acc;
+        acc = tsum(acc, part, G, S, s);
+        if (valid && mi < ncoef && s == 0) local[tv.eoff[c] + mi] += pow(rat, (double)am) * acc;
     }
 }
 
-// ------------------------------------------------------------- L2P + M2P
-__global__ void k_h2d_leaf_far(const int* __restrict__ leaves, int top, TreeView tv, PointsView pv,
-                               double kappa, const int64_t* __restrict__ poff,
-                               const cplx* __restrict__ vals, const cplx* __restrict__ mpole,
-                               const cplx* __restrict__ local, cplx* __restrict__ ufar)
+// ------------------------------------------------------------- L2P, M2P
+// L2P writes the far field of every target of a leaf with expansions (0 for
+// leaves coarser than the top level).  The leaf's per-point values are
+// contiguous (point-major), so a chunk of points is staged into LDS with
+// coalesced loads and each thread then reads its own point's row there.
+__global__ __launch_bounds__(64) void k_h2d_l2p(const int* __restrict__ leaves, int top, int chunk_cap,
+                                                TreeView tv, const int64_t* __restrict__ poff,
+                                                const cplx* __restrict__ vals, const cplx* __restrict__ local,
+                                                cplx* __restrict__ ufar)
 {
-    extern __shared__ cplx rows[];      // rows[k * blockDim.x + thread], for M2P
-    int li = blockIdx.x;
-    int b = leaves[li];
+    extern __shared__ cplx rowv[];
+    int b = leaves[blockIdx.x];
     int l = tv.level[b];
-    int nbx = tv.nbox, st = blockDim.x, t = threadIdx.x;
-    int64_t n = pv.n;
     int p0 = tv.pbeg[b], p1 = tv.pend[b];
-    for (int i0 = p0; i0 < p1; i0 += st) {
-        int i = i0 + t;
-        if (i >= p1) break;
-        cplx u = mk(0.0, 0.0);
-        if (l >= top) {
-            int P = tv.P[l], nc = 2 * P + 1;
-            // L2P: u = sum_n L_n (-1)^n v_{-n}
-            const cplx* L = local + tv.eoff[b] + P;
-            const cplx* V = vals + poff[b] + (int64_t)(i - p0) * nc + P;
+    int t = threadIdx.x;
+    if (l < top) {
+        for (int i = p0 + t; i < p1; i += blockDim.x) ufar[i] = mk(0.0, 0.0);
+        return;
+    }
+    int P = tv.P[l], nc = 2 * P + 1;
+    int chunk = min(chunk_cap / nc, (int)blockDim.x);
+    const cplx* L = local + tv.eoff[b] + P;
+    for (int c0 = p0; c0 < p1; c0 += chunk) {
+        int cnt = min(chunk, p1 - c0);
+        const cplx* src = vals + poff[b] + (int64_t)(c0 - p0) * nc;
+        __syncthreads();
+        for (int e = t; e < cnt * nc; e += blockDim.x) rowv[e] = src[e];
+        __syncthreads();
+        if (t < cnt) {
+            // u = sum_n L_n (-1)^n v_{-n}
+            const cplx* V = rowv + t * nc + P;
+            cplx u = mk(0.0, 0.0);
             for (int k = -P; k <= P; ++k) {
                 cplx w = L[k] * V[-k];
                 u += (k & 1) ? -w : w;
             }
-            cplx x1 = mk(pv.xre[i], pv.xim[i]), x2 = mk(pv.xre[n + i], pv.xim[n + i]);
-            for (int e = tv.l3off[b]; e < tv.l3off[b + 1]; ++e) {
-                int a = tv.l3idx[e];
-                int la = tv.level[a];
-                int Pa = tv.P[la];
-                double ra = tv.rs[la];
-                cplx Y1 = x1 - mk(tv.cre[a], tv.cim[a]), Y2 = x2 - mk(tv.cre[nbx + a], tv.cim[nbx + a]);
-                cplx bp, bm;
-                hcore2(Y1, Y2, kappa, ra, Pa, c_ghx, c_ghw, rows + t, st, &bp, &bm);
-                const cplx* M = mpole + tv.eoff[a] + Pa;
-                cplx pp = mk(1.0, 0.0), pm = mk(1.0, 0.0);
-                for (int k = 0; k <= Pa; ++k) {
-                    cplx term = pp * M[k];
-                    if (k > 0) {
-                        cplx v = pm * M[-k];
-                        term += (k & 1) ? -v : v;
-                    }
-                    u += rows[k * st + t] * term;
-                    pp = pp * bp;
-                    pm = pm * bm;
+            ufar[c0 + t] = u;
+        }
+    }
+}
+
+// M2P over List 3, only for the leaves that have List-3 boxes; adds to the
+// far field L2P wrote.  Each thread's Hankel sequence sits in its LDS column.
+__global__ void k_h2d_m2p(const int* __restrict__ leaves, TreeView tv, PointsView pv, double kappa,
+                          const cplx* __restrict__ mpole, cplx* __restrict__ ufar)
+{
+    extern __shared__ cplx rows[];      // rows[k * blockDim.x + thread]
+    int b = leaves[blockIdx.x];
+    int nbx = tv.nbox, st = blockDim.x, t = threadIdx.x;
+    int64_t n = pv.n;
+    int p0 = tv.pbeg[b], p1 = tv.pend[b];
+    for (int i = p0 + t; i < p1; i += st) {
+        cplx u = mk(0.0, 0.0);
+        cplx x1 = mk(pv.xre[i], pv.xim[i]), x2 = mk(pv.xre[n + i], pv.xim[n + i]);
+        for (int e = tv.l3off[b]; e < tv.l3off[b + 1]; ++e) {
+            int a = tv.l3idx[e];
+            int la = tv.level[a];
+            int Pa = tv.P[la];
+            double ra = tv.rs[la];
+            cplx Y1 = x1 - mk(tv.cre[a], tv.cim[a]), Y2 = x2 - mk(tv.cre[nbx + a], tv.cim[nbx + a]);
+            cplx bp, bm;
+            hcore2(Y1, Y2, kappa, ra, Pa, c_ghx, c_ghw, rows + t, st, &bp, &bm);
+            const cplx* M = mpole + tv.eoff[a] + Pa;
+            cplx pp = mk(1.0, 0.0), pm = mk(1.0, 0.0);
+            for (int k = 0; k <= Pa; ++k) {
+                cplx term = pp * M[k];
+                if (k > 0) {
+                    cplx v = pm * M[-k];
+                    term += (k & 1) ? -v : v;
                 }
+                u += rows[k * st + t] * term;
+                pp = pp * bp;
+                pm = pm * bm;
             }
         }
-        ufar[i] = u;
+        ufar[i] += u;
     }
 }
 
@@ -445,6 +527,37 @@ __global__ __launch_bounds__(64) void k_h2d_p2p(const int* __restrict__ leaves, 
     }
 }
 
+// Natural logarithm of a positive, finite, normal x: with x = 2^e m,
+// m in [sqrt(1/2), sqrt(2)), log x = e ln 2 + 2 atanh(t), t = (m - 1)/(m + 1),
+// |t| < 0.1716, and atanh t = t sum_k t^(2k) / (2k + 1), truncated after
+// k = 10 (the next term is below 2^-56 relative).  About 1-2 ulp.
+__device__ inline double log_pos(double x)
+{
+    int e;
+    double m = frexp(x, &e);                 // m in [0.5, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    double t = (m - 1.0) / (m + 1.0);
+    double t2 = t * t;
+    double p = 1.0 / 21.0;
+    p = fma(p, t2, 1.0 / 19.0);
+    p = fma(p, t2, 1.0 / 17.0);
+    p = fma(p, t2, 1.0 / 15.0);
+    p = fma(p, t2, 1.0 / 13.0);
+    p = fma(p, t2, 1.0 / 11.0);
+    p = fma(p, t2, 1.0 / 9.0);
+    p = fma(p, t2, 1.0 / 7.0);
+    p = fma(p, t2, 1.0 / 5.0);
+    p = fma(p, t2, 1.0 / 3.0);
+    p = fma(p, t2, 1.0);
+    // ln 2 split so that e * ln2_hi is exact for |e| < 2^11
+    const double ln2_hi = 0.693147180559890330187045037746;
+    const double ln2_lo = 5.4979230187083711552420206e-14;
+    return (double)e * ln2_hi + ((double)e * ln2_lo + 2.0 * t * p);
+}
+
 // P2P for leaves whose every near pair has |kappa r| < 3 (a plan-time bound
 // from the box geometry): only the power series of H0 is needed, with the
 // leaf's fixed number of terms K (enough for the bound).  With q = kappa^2 s/4,
@@ -498,7 +611,7 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_ser(const int* __restrict__ leav
                         double sr = d1r * d1r - d1i * d1i + d2r * d2r - d2i * d2i;
                         double si = 2.0 * (d1r * d1i + d2r * d2i);
                         if (sr == 0.0 && si == 0.0) continue;
-                        double lm = 0.5 * log(sr * sr + si * si) + lk2;   // log|q|
+                        double lm = 0.5 * log_pos(sr * sr + si * si) + lk2;   // log|q|
                         double ag = atan2(si, sr);                        // arg q
                         double qr = -k2 * sr, qi = -k2 * si;              // -q
                         double tr = 1.0, ti = 0.0, jr = 1.0, ji = 0.0, sr0 = 0.0, si0 = 0.0;
@@ -559,50 +672,86 @@ hipError_t h2d_gen_ops(const int* pair_b, int npairs, const int* tr_boxes, int n
     return hipGetLastError();
 }
 
-hipError_t h2d_m2m(const int* boxes, int nb, const TreeView& tv, const H2DOps& ops, cplx* mpole,
+// G lanes cover the output coefficients; levels with few boxes split the
+// input sum over S = 256 / G groups so that the level still fills the chip.
+static TShape tshape(int ncoef, int nb)
+{
+    TShape sh;
+    sh.G = ncoef <= 32 ? 32 : (ncoef <= 64 ? 64 : 128);
+    sh.S = ((int64_t)nb * sh.G < 256 * 256) ? 256 / sh.G : 1;
+    return sh;
+}
+
+static unsigned tblocks(int nb, TShape sh) { return (unsigned)((nb + 256 / (sh.G * sh.S) - 1) / (256 / (sh.G * sh.S))); }
+
+hipError_t h2d_m2m(const int* boxes, int nb, int ncoef, const TreeView& tv, const H2DOps& ops, cplx* mpole,
                    hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    k_h2d_m2m<<<(nb + 3) / 4, 256, 0, st>>>(boxes, nb, tv, ops, mpole);
+    TShape sh = tshape(ncoef, nb);
+    k_h2d_m2m<<<tblocks(nb, sh), 256, 0, st>>>(boxes, nb, sh, tv, ops, mpole);
     return hipGetLastError();
 }
 
-hipError_t h2d_m2l(const int* boxes, int nb, const TreeView& tv, const H2DOps& ops,
-                   const cplx* mpole, cplx* local, hipStream_t st)
+hipError_t h2d_m2l(const int* boxes, int nlv, const int* box_off, const int* nb, const int* ncoef,
+                   const TreeView& tv, const H2DOps& ops, const cplx* mpole, cplx* local, hipStream_t st)
 {
-    if (nb <= 0) return hipSuccess;
-    k_h2d_m2l<<<(nb + 3) / 4, 256, 0, st>>>(boxes, nb, tv, ops, mpole, local);
-    return hipGetLastError();
-}
-
-hipError_t h2d_p2l(const int* boxes, int nb, const TreeView& tv, const PointsView& pv, double kappa,
-                   cplx* local, hipStream_t st)
-{
-    if (nb <= 0) return hipSuccess;
-    k_h2d_p2l<<<nb, 128, 0, st>>>(boxes, tv, pv, kappa, local);
-    return hipGetLastError();
-}
-
-hipError_t h2d_l2l(const int* boxes, int nb, const TreeView& tv, const H2DOps& ops, cplx* local,
-                   hipStream_t st)
-{
-    if (nb <= 0) return hipSuccess;
-    k_h2d_l2l<<<(nb + 3) / 4, 256, 0, st>>>(boxes, nb, tv, ops, local);
-    return hipGetLastError();
-}
-
-hipError_t h2d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const TreeView& tv,
-                        const PointsView& pv, double kappa, const int64_t* poff, const cplx* vals,
-                        const cplx* mpole, const cplx* local, cplx* ufar, hipStream_t st)
-{
-    if (nleaf <= 0) return hipSuccess;
-    int threads = 64;
-    size_t lds = (size_t)threads * (pmax + 1) * sizeof(cplx);
-    while (lds > 65536 && threads > 8) {
-        threads /= 2;
-        lds = (size_t)threads * (pmax + 1) * sizeof(cplx);
+    LvTable lt;
+    lt.n = 0;
+    int blk = 0;
+    for (int k = 0; k < nlv; ++k) {
+        if (nb[k] <= 0) continue;
+        if (lt.n == kMaxLv) return hipErrorInvalidValue;
+        TShape sh = tshape(ncoef[k], nb[k]);
+        lt.first_block[lt.n] = blk;
+        lt.box_off[lt.n] = box_off[k];
+        lt.nb[lt.n] = nb[k];
+        lt.G[lt.n] = sh.G;
+        lt.S[lt.n] = sh.S;
+        blk += (int)tblocks(nb[k], sh);
+        ++lt.n;
     }
-    k_h2d_leaf_far<<<nleaf, threads, lds, st>>>(leaves, top, tv, pv, kappa, poff, vals, mpole, local, ufar);
+    if (lt.n == 0) return hipSuccess;
+    lt.first_block[lt.n] = blk;
+    k_h2d_m2l<<<blk, 256, 0, st>>>(boxes, lt, tv, ops, mpole, local);
+    return hipGetLastError();
+}
+
+hipError_t h2d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
+                   double kappa, cplx* local, hipStream_t st)
+{
+    if (nb <= 0) return hipSuccess;
+    int pstride = P + 1;
+    int chunk = (int)(48000 / (sizeof(cplx) * (2 * (size_t)pstride + 1)));
+    chunk = chunk > 128 ? 128 : (chunk < 1 ? 1 : chunk);
+    size_t lds = sizeof(cplx) * ((size_t)chunk * (2 * (size_t)pstride + 1) + 128);
+    k_h2d_p2l<<<nb, 128, lds, st>>>(boxes, tv, pv, kappa, chunk, pstride, local);
+    return hipGetLastError();
+}
+
+hipError_t h2d_l2l(const int* boxes, int nb, int ncoef, const TreeView& tv, const H2DOps& ops, cplx* local,
+                   hipStream_t st)
+{
+    if (nb <= 0) return hipSuccess;
+    TShape sh = tshape(ncoef, nb);
+    k_h2d_l2l<<<tblocks(nb, sh), 256, 0, st>>>(boxes, nb, sh, tv, ops, local);
+    return hipGetLastError();
+}
+
+hipError_t h2d_leaf_far(const int* leaves, int nleaf, const int* m2p_leaves, int nm2p, int top, int pmax,
+                        const TreeView& tv, const PointsView& pv, double kappa, const int64_t* poff,
+                        const cplx* vals, const cplx* mpole, const cplx* local, cplx* ufar, hipStream_t st)
+{
+    if (nleaf > 0) {
+        // LDS for at least one point at the largest P, up to 32 KB
+        int cap = 2048 > 2 * pmax + 1 ? 2048 : 2 * pmax + 1;
+        k_h2d_l2p<<<nleaf, 64, sizeof(cplx) * (size_t)cap, st>>>(leaves, top, cap, tv, poff, vals, local, ufar);
+    }
+    if (nm2p > 0) {
+        int threads = 64;
+        size_t lds = (size_t)threads * (pmax + 1) * sizeof(cplx);
+        k_h2d_m2p<<<nm2p, threads, lds, st>>>(m2p_leaves, tv, pv, kappa, mpole, ufar);
+    }
     return hipGetLastError();
 }
 

@@ -80,17 +80,17 @@ hipError_t h2d_gen_pts(const int* leaves, int nleaf, const TreeView& tv, const P
                        double kappa, const int64_t* poff, cplx* vals, hipStream_t st);
 hipError_t h2d_p2m(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
                    const int64_t* poff, const cplx* vals, cplx* mpole, hipStream_t st);
-hipError_t h2d_m2m(const int* boxes, int nb, const TreeView& tv, const H2DOps& ops, cplx* mpole,
+hipError_t h2d_m2m(const int* boxes, int nb, int ncoef, const TreeView& tv, const H2DOps& ops, cplx* mpole,
                    hipStream_t st);
-hipError_t h2d_m2l(const int* boxes, int nb, const TreeView& tv, const H2DOps& ops,
-                   const cplx* mpole, cplx* local, hipStream_t st);
-hipError_t h2d_p2l(const int* boxes, int nb, const TreeView& tv, const PointsView& pv, double kappa,
-                   cplx* local, hipStream_t st);
-hipError_t h2d_l2l(const int* boxes, int nb, const TreeView& tv, const H2DOps& ops, cplx* local,
+hipError_t h2d_m2l(const int* boxes, int nlv, const int* box_off, const int* nb, const int* ncoef,
+                   const TreeView& tv, const H2DOps& ops, const cplx* mpole, cplx* local, hipStream_t st);
+hipError_t h2d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
+                   double kappa, cplx* local, hipStream_t st);
+hipError_t h2d_l2l(const int* boxes, int nb, int ncoef, const TreeView& tv, const H2DOps& ops, cplx* local,
                    hipStream_t st);
-hipError_t h2d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const TreeView& tv,
-                        const PointsView& pv, double kappa, const int64_t* poff, const cplx* vals,
-                        const cplx* mpole, const cplx* local, cplx* ufar, hipStream_t st);
+hipError_t h2d_leaf_far(const int* leaves, int nleaf, const int* m2p_leaves, int nm2p, int top, int pmax,
+                        const TreeView& tv, const PointsView& pv, double kappa, const int64_t* poff,
+                        const cplx* vals, const cplx* mpole, const cplx* local, cplx* ufar, hipStream_t st);
 hipError_t h2d_p2p(const int* ser_leaves, int nser, const int* ser_nterm, const int* gen_leaves, int ngen,
                    const TreeView& tv, const PointsView& pv, double kappa, const cplx* ufar,
                    const int* perm, double* out, int mixed, hipStream_t st);
