@@ -51,6 +51,36 @@ PEAK_FP32_VALU = 157.3e12
 METRIC = "N\u00b2-equiv interactions/s at 1e-6 rel err; served p50/p99 latency vs plain"
 
 
+TRAFFIC_PROFILES = {
+    # workload: counter summary of its P2P kernel (calibrated HBM bytes per launch)
+    "c1": "profiles/helmholtz2d_n1m_p2p_traffic.md",
+}
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the workload's P2P kernel from the committed
+    counter summary, or None when there is none or when the kernel sources
+    have changed since the counters were taken."""
+    import hashlib
+    path = TRAFFIC_PROFILES.get(workload)
+    if not path or not os.path.exists(os.path.join(ROOT, path)):
+        return None
+    fields = {}
+    for line in open(os.path.join(ROOT, path)):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for src in fields["kernel_sources"].split(","):
+            h.update(open(os.path.join(ROOT, src.strip()), "rb").read())
+        if h.hexdigest() != fields["kernel_source_sha256"]:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +94,8 @@ def parse():
     ap.add_argument("--check-targets", type=int, default=64)
     ap.add_argument("--cpu-targets", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 512 MiB device copy (counter calibration for HBM traffic)")
     return ap.parse_args()
 
 
@@ -114,6 +146,14 @@ def main():
     pairs = n * (n - 1)
     value = pairs / (ms_per_step * 1e-3)
     stage_avg = {k: v / a.steps for k, v in stage_tot.items()}
+
+    if a.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # accuracy of the timed configuration on sampled targets (oracle, CPU)
     import oracle
@@ -166,7 +206,7 @@ def main():
             "peak": peak / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": measured_traffic(a.workload) if a.precision == "fp64" else None,
             "flops_per_interaction": p2p_flops_unit,
         },
     }
