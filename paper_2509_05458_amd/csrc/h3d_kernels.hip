@@ -685,45 +685,75 @@ __global__ void k_h3d_coax_sample(H3DTr tr)
             gm += cm * gg;
         }
     }
-    cplx* f = tr.fg + (size_t)i * tr.sfg;
-    cplx* g = f + (size_t)(2 * Ps + 1) * nq;
-    f[(size_t)(am + Ps) * nq + j] = fp;
-    g[(size_t)(am + Ps) * nq + j] = gp;
+    // samples stored pair-fastest for the projection GEMM:
+    // fg[((m + Ps) nq + j) np + i] = (f.re, f.im, g.re, g.im)
+    double* o = (double*)tr.fg;
+    size_t row = ((size_t)(am + Ps) * nq + j) * tr.np + i;
+    o[4 * row + 0] = fp.re; o[4 * row + 1] = fp.im; o[4 * row + 2] = gp.re; o[4 * row + 3] = gp.im;
     if (am) {
-        f[(size_t)(Ps - am) * nq + j] = fm;
-        g[(size_t)(Ps - am) * nq + j] = gm;
+        row = ((size_t)(Ps - am) * nq + j) * tr.np + i;
+        o[4 * row + 0] = fm.re; o[4 * row + 1] = fm.im; o[4 * row + 2] = gm.re; o[4 * row + 3] = gm.im;
     }
 }
 
-// K4: Legendre projection.  Thread (pair, target coefficient (n, m)):
-// b_n^m = Tc_n sum_j W_nm(j) f_m(j) + Tdc_n sum_j W_nm(j) g_m(j).
-__global__ void k_h3d_coax_proj(H3DTr tr)
+// K4: Legendre projection as a dense real GEMM on the FP64 matrix cores.  For
+// each order m the projection matrix W^m (rows n = |m|..Pt, columns the nodes
+// j) is the same for every pair of the stage, so
+//     Out^m[n][(i, c)] = sum_j W^m[n][j] S^m[j][(i, c)],   c in {f.re, f.im, g.re, g.im},
+// over all pairs i of the chunk, and then b_n^m = Tc_n (f) + Tdc_n (g).  One
+// wavefront computes a 16 x 16 tile (16 degrees x 4 pairs) with
+// v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16] and
+// holds D[4v + l/16][l%16], v = 0..3.  Orders |m| > Ps have no samples and
+// give zero coefficients.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_h3d_coax_proj(H3DTr tr)
 {
-    int Pt = tr.Pt, Ps = tr.Ps, nq = tr.nq;
-    int nc = (Pt + 1) * (Pt + 1);
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)tr.np * nc) return;
-    int c = (int)(gid % nc);
-    int i = (int)(gid / nc);
-    int n = (int)sqrt((double)c);
-    while (n * n > c) --n;
-    while ((n + 1) * (n + 1) <= c) ++n;
-    int m = c - n * n - n;
+    __shared__ double tile[4][16][17];
+    int Pt = tr.Pt, Ps = tr.Ps, nq = tr.nq, np = tr.np;
+    int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    int pgroups = (np + 3) / 4;
+    int rt_max = (Pt + 16) / 16;                 // row tiles for m = 0
+    int64_t wid = (int64_t)blockIdx.x * 4 + wave;
+    int64_t nw = (int64_t)(2 * Pt + 1) * rt_max * pgroups;
+    // every wavefront reaches the barrier below; inactive ones only skip work
+    bool live = wid < nw;
+    int pg = live ? (int)(wid % pgroups) : 0;
+    int rt = live ? (int)((wid / pgroups) % rt_max) : 0;
+    int m = live ? (int)(wid / ((int64_t)pgroups * rt_max)) - Pt : 0;
     int am = m < 0 ? -m : m;
-    cplx* o = tr.B + (size_t)i * tr.sB;
-    if (am > Ps) {
-        o[c] = mk(0.0, 0.0);
-        return;
+    int n0 = am + 16 * rt;
+    live = live && n0 <= Pt;
+    bool sampled = am <= Ps;
+    int i0 = pg * 4;
+    int r = l & 15, kq = l >> 4;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    if (live && sampled) {
+        const double* S = (const double*)tr.fg + (size_t)(m + Ps) * nq * np * 4;
+        int na = n0 + r;                          // A row this lane supplies
+        bool arow = na <= Pt;
+        size_t wrow = (size_t)tri(arow ? na : n0, am) * nq;
+        int col = i0 * 4 + r;                     // B column this lane supplies
+        bool bcol = i0 + (r >> 2) < np;
+        for (int k0 = 0; k0 < nq; k0 += 4) {
+            int j = k0 + kq;
+            double a = (arow && j < nq) ? tr.W[wrow + j] : 0.0;
+            double b = (bcol && j < nq) ? S[(size_t)j * np * 4 + col] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
     }
-    const cplx* f = tr.fg + (size_t)i * tr.sfg + (size_t)(m + Ps) * nq;
-    const cplx* g = f + (size_t)(2 * Ps + 1) * nq;
-    const double* W = tr.W + (size_t)tri(n, am) * nq;
-    cplx pf = mk(0.0, 0.0), pg = pf;
-    for (int j = 0; j < nq; ++j) {
-        pf += W[j] * f[j];
-        pg += W[j] * g[j];
+    // gather the four components of each pair through LDS
+    for (int v = 0; v < 4; ++v) tile[wave][4 * v + kq][r] = acc[v];
+    __syncthreads();
+    // lane l: degree row dr = l >> 2 (0..15), pair p = l & 3
+    int dr = l >> 2, p = l & 3;
+    int n = n0 + dr, i = i0 + p;
+    if (live && n <= Pt && i < np) {
+        const double* t = tile[wave][dr];
+        cplx pf = mk(t[4 * p + 0], t[4 * p + 1]), pgv = mk(t[4 * p + 2], t[4 * p + 3]);
+        // orders beyond the source expansion have no samples: zero coefficients
+        tr.B[(size_t)i * tr.sB + hnm(n, m)] = sampled ? tr.Tc[n] * pf + tr.Tdc[n] * pgv : mk(0.0, 0.0);
     }
-    o[c] = tr.Tc[n] * pf + tr.Tdc[n] * pg;
 }
 
 // K7: each target box adds its pairs' translated expansions, in pair order.
@@ -840,7 +870,8 @@ hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_sr
     int64_t n4 = (int64_t)tr.np * (Ps + 1) * tr.nq;
     k_h3d_coax_sample<<<blocks(n4, bs), bs, 0, st>>>(tr);
     int64_t n5 = (int64_t)tr.np * (Pt + 1) * (Pt + 1);
-    k_h3d_coax_proj<<<blocks(n5, bs), bs, 0, st>>>(tr);
+    int64_t nwave = (int64_t)(2 * Pt + 1) * ((Pt + 16) / 16) * ((tr.np + 3) / 4);
+    k_h3d_coax_proj<<<(unsigned)((nwave + 3) / 4), 256, 0, st>>>(tr);
     int64_t n6 = (int64_t)tr.np * ((Pt + NB) / NB) * (2 * Pt + 1);
     k_h3d_rot_sample<NB><<<blocks(n6, bs), bs, 0, st>>>(tr, 1, nullptr, nullptr);
     k_h3d_rot_dft<<<blocks(n5, bs), bs, sizeof(double) * 2 * (2 * Pt + 1), st>>>(tr, 1, eq_p0, eq_d0);
