@@ -103,6 +103,13 @@ const char* cfmm_last_error(void);
  *                 max_p, dim, kernel, separation, leaf_size, precision } */
 int cfmm_plan_info(cfmm_plan_t plan, int64_t* info16);
 
+/* Near-field work of one evaluation: work2[0] = ordered interactions
+ * G(x_i, x_j) sigma_j summed directly (j != i), work2[1] = kernel evaluations
+ * that produce them.  G(x, y) = G(y, x), so a pair of near leaves in the
+ * small-argument regime of the 2D Helmholtz kernel is evaluated once for both
+ * directions and work2[1] < work2[0]; otherwise the two are equal. */
+int cfmm_plan_near_work(cfmm_plan_t plan, int64_t* work2);
+
 /* Expansion length of level l (0 if the level has no expansions). */
 int cfmm_plan_nterms(cfmm_plan_t plan, int level);
 

@@ -72,6 +72,7 @@ def lib():
         L.cfmm_last_error.restype = ctypes.c_char_p
         L.cfmm_plan_info.argtypes = [vp, i64p]
         L.cfmm_plan_nterms.argtypes = [vp, ctypes.c_int]
+        L.cfmm_plan_near_work.argtypes = [vp, i64p]
         L.cfmm_plan_export_tree.argtypes = [vp, i64p, u64p, i32p, i32p, i32p, i32p, i32p, i32p, u64p]
         L.cfmm_plan_export_list.argtypes = [vp, ctypes.c_int, i32p, i32p, i64p]
         L.cfmm_plan_export_centers.argtypes = [vp, vp]
@@ -176,6 +177,12 @@ class Plan:
                 "n_list4", "p2p_pairs", "m2l_pairs", "max_p", "dim", "kernel", "separation",
                 "leaf_size", "precision")
         return {k: int(v) for k, v in zip(keys, a)}
+
+    def near_work(self) -> dict:
+        """Ordered near-field interactions and the kernel evaluations producing them."""
+        a = np.zeros(2, dtype=np.int64)
+        _check(lib().cfmm_plan_near_work(self._handle, _ptr(a, ctypes.c_int64)))
+        return {"interactions": int(a[0]), "evaluations": int(a[1])}
 
     def nterms(self) -> list:
         return [int(lib().cfmm_plan_nterms(self._handle, l)) for l in range(self.info()["nlevels"])]

@@ -82,10 +82,11 @@ struct cfmm_plan_s {
     std::vector<int> m2m_off, m2m_cnt, l2l_off, l2l_cnt;   // per level
     cplx *d_mpole = nullptr, *d_local = nullptr, *d_ufar = nullptr;
     int off_p2l = 0, n_p2l = 0;
-    int off_p2p_ser = 0, n_p2p_ser = 0, off_p2p_gen = 0, n_p2p_gen = 0;
+    H2DNear near2{};              // 2D near-field work items and partial sums
+    int64_t near_evals = -1;      // kernel evaluations per eval (-1: one per ordered pair)
     int off_m2p = 0, n_m2p = 0;   // leaves with List-3 boxes
     std::vector<int> p2l_h;       // host copy of the P2L work list (level order)
-    int* d_p2p_nterm = nullptr;   // per P2P leaf: series terms (2D) or the wide-phase flag (3D Helmholtz)
+    int* d_p2p_nterm = nullptr;   // per P2P leaf: the wide-phase flag (3D Helmholtz)
     // plan-time translation operators (2D Helmholtz)
     int64_t *d_o_m2l = nullptr, *d_o_tr = nullptr;
     cplx *d_g_m2l = nullptr, *d_g_m2m = nullptr, *d_g_l2l = nullptr;
@@ -590,49 +591,97 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     for (int b = 0; b < nb; ++b)
         for (int e = t.off[1][b]; e < t.off[1][b + 1]; ++e) work.push_back(b);
     int npairs = (int)t.idx[1].size();
-    // 2D Helmholtz near field: leaves whose near pairs all have |kappa r| < 3,
-    // by a bound from the box geometry (real half widths plus the imaginary
-    // spreads about the complexified centres), take the series-only P2P with a
-    // per-leaf number of series terms; the rest take the general P2P.
-    std::vector<int> ser_nterm;
+    // 2D Helmholtz near field by List-1 entries e = (target leaf b, source leaf
+    // a).  A pair whose every point pair has |kappa r| < 3 (bound from the box
+    // geometry: real half widths plus the imaginary spreads about the
+    // complexified centres) takes the power series of H0 with a per-pair term
+    // count; such pairs with a < b are evaluated once for both directions.
+    // Diagonal entries and the remaining pairs are row items.
     if (h2d) {
         double k2 = 0.25 * p->kappa * p->kappa;
-        std::vector<int> gen;
-        p->off_p2p_ser = (int)work.size();
-        for (int b = 0; b < nb; ++b) {
-            if (t.nchild[b]) continue;
-            double qb = 0.0, wb = p->D * ldexp(1.0, -t.level[b]);
+        int ne = (int)t.idx[0].size();
+        std::vector<int> row_of(ne), partner(ne, -1), sym, sym_k, diag, diag_k, ser, ser_k, gen;
+        std::vector<int64_t> coff(ne + 1, 0);
+        for (int b = 0; b < nb; ++b)
             for (int e = t.off[0][b]; e < t.off[0][b + 1]; ++e) {
-                int a = t.idx[0][e];
-                double wa = p->D * ldexp(1.0, -t.level[a]);
-                double sre = 0.0, sci = 0.0;
-                for (int k = 0; k < dim; ++k) {
-                    double dr = fabs(cre[(size_t)k * nb + b] - cre[(size_t)k * nb + a]) + 0.5 * (wa + wb);
-                    double dc = cim[(size_t)k * nb + b] - cim[(size_t)k * nb + a];
-                    sre += dr * dr;
-                    sci += dc * dc;
-                }
-                double di = delta[a] + delta[b] + sqrt(sci);
-                qb = std::max(qb, k2 * (sre + di * di));
+                row_of[e] = b;
+                coff[e + 1] = coff[e] + (t.pend[b] - t.pbeg[b]);
             }
-            if (qb < 2.25) {
-                int K = 1;
-                double term = qb * qb / 4.0;      // q^(K+1) / ((K+1)!)^2 at K = 1
-                while (term > 1e-17 && K < 39) {
-                    ++K;
-                    term *= qb / ((double)(K + 1) * (K + 1));
-                }
-                work.push_back(b);
-                ser_nterm.push_back(K);
+        for (int e = 0; e < ne; ++e) {
+            int b = row_of[e], a = t.idx[0][e];
+            const int* r0 = t.idx[0].data() + t.off[0][a];
+            const int* r1 = t.idx[0].data() + t.off[0][a + 1];
+            const int* f = std::lower_bound(r0, r1, b);
+            if (f == r1 || *f != b) return fail(CFMM_EINVAL, "internal: List 1 is not symmetric");
+            partner[e] = (int)(f - t.idx[0].data());
+        }
+        auto bound = [&](int b, int a) {
+            double wb = p->D * ldexp(1.0, -t.level[b]), wa = p->D * ldexp(1.0, -t.level[a]);
+            double sre = 0.0, sci = 0.0;
+            for (int k = 0; k < dim; ++k) {
+                double dr = fabs(cre[(size_t)k * nb + b] - cre[(size_t)k * nb + a]) + 0.5 * (wa + wb);
+                double dc = cim[(size_t)k * nb + b] - cim[(size_t)k * nb + a];
+                sre += dr * dr;
+                sci += dc * dc;
+            }
+            double di = delta[a] + delta[b] + sqrt(sci);
+            return k2 * (sre + di * di);
+        };
+        auto nterms_series = [](double qb) {
+            int K = 1;
+            double term = qb * qb / 4.0;      // q^(K+1) / ((K+1)!)^2 at K = 1
+            while (term > 1e-17 && K < 39) {
+                ++K;
+                term *= qb / ((double)(K + 1) * (K + 1));
+            }
+            return K;
+        };
+        for (int e = 0; e < ne; ++e) {
+            int b = row_of[e], a = t.idx[0][e];
+            if (a > b) continue;                      // the pair is visited from a's row
+            double qb = bound(b, a);
+            bool series = qb < 2.25;
+            if (a == b) {
+                if (series && t.pend[b] - t.pbeg[b] <= 64) { diag.push_back(e); diag_k.push_back(nterms_series(qb)); }
+                else if (series) { ser.push_back(e); ser_k.push_back(nterms_series(qb)); }
+                else gen.push_back(e);
+            } else if (series) {
+                sym.push_back(e);
+                sym_k.push_back(nterms_series(qb));
             } else {
-                gen.push_back(b);
+                gen.push_back(e);
+                gen.push_back(partner[e]);
             }
         }
-        p->n_p2p_ser = (int)work.size() - p->off_p2p_ser;
-        p->off_p2p_gen = (int)work.size();
-        work.insert(work.end(), gen.begin(), gen.end());
-        p->n_p2p_gen = (int)gen.size();
-        if ((rc = upload(p, &p->d_p2p_nterm, ser_nterm))) return rc;
+        int64_t ev = 0;
+        auto cnt = [&](int b) { return (int64_t)(t.pend[b] - t.pbeg[b]); };
+        for (int e : sym) ev += cnt(row_of[e]) * cnt(t.idx[0][e]);
+        for (int e : diag) ev += cnt(row_of[e]) * (cnt(row_of[e]) - 1) / 2;
+        for (int e : ser) ev += cnt(row_of[e]) * (cnt(row_of[e]) - 1);
+        for (int e : gen) {
+            int b = row_of[e], a = t.idx[0][e];
+            ev += a == b ? cnt(b) * (cnt(b) - 1) : cnt(b) * cnt(a);
+        }
+        p->near_evals = ev;
+        p->near2.nsym = (int)sym.size();
+        p->near2.ndiag = (int)diag.size();
+        p->near2.nser = (int)ser.size();
+        p->near2.ngen = (int)gen.size();
+        int* dd[7] = {nullptr};
+        if ((rc = upload(p, &dd[0], sym)) || (rc = upload(p, &dd[1], sym_k)) || (rc = upload(p, &dd[2], ser)) ||
+            (rc = upload(p, &dd[3], ser_k)) || (rc = upload(p, &dd[4], gen)) || (rc = upload(p, &dd[5], row_of)) ||
+            (rc = upload(p, &dd[6], partner)))
+            return rc;
+        int *dg = nullptr, *dgk = nullptr;
+        if ((rc = upload(p, &dg, diag)) || (rc = upload(p, &dgk, diag_k))) return rc;
+        p->near2.diag = dg;
+        p->near2.diag_k = dgk;
+        int64_t* dcoff = nullptr;
+        cplx* dC = nullptr;
+        if ((rc = upload(p, &dcoff, coff)) || (rc = p->alloc(&dC, std::max<int64_t>(coff[ne], 1)))) return rc;
+        p->near2.sym = dd[0]; p->near2.sym_k = dd[1]; p->near2.ser = dd[2]; p->near2.ser_k = dd[3];
+        p->near2.gen = dd[4]; p->near2.row_of = dd[5]; p->near2.partner = dd[6];
+        p->near2.coff = dcoff; p->near2.C = dC;
     }
     // 3D Helmholtz mixed near field: leaves whose near pairs may reach
     // kappa |r| > 8 form the phase in FP64 (same box bound as above)
@@ -856,8 +905,7 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, W + p->off_m2p, p->n_m2p, top, std::max(1, p->pmax), tv,
                             pv, p->kappa, p->d_poff, p->d_pvals, p->d_mpole, p->d_local, p->d_ufar, st));
         HIPCHK(mark(6));
-        HIPCHK(h2d_p2p(W + p->off_p2p_ser, p->n_p2p_ser, p->d_p2p_nterm, W + p->off_p2p_gen, p->n_p2p_gen,
-                       tv, pv, p->kappa, p->d_ufar, p->d_perm, out, p->precision, st));
+        HIPCHK(h2d_p2p(p->near2, W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out, st));
     } else if (p->kernel == CFMM_HELMHOLTZ) {
         H3DLevels hl{p->d_h3_kw, p->d_h3_sc};
         HIPCHK(hipMemsetAsync(p->d_mpole, 0, p->ecount * sizeof(cplx), st));
@@ -954,6 +1002,14 @@ int cfmm_plan_info(cfmm_plan_t p, int64_t* info16)
 {
     if (!p || !info16) return fail(CFMM_EINVAL, "NULL argument");
     memcpy(info16, p->info, sizeof(p->info));
+    return CFMM_OK;
+}
+
+int cfmm_plan_near_work(cfmm_plan_t p, int64_t* work2)
+{
+    if (!p || !work2) return fail(CFMM_EINVAL, "NULL argument");
+    work2[0] = p->info[8];
+    work2[1] = p->near_evals >= 0 ? p->near_evals : p->info[8];
     return CFMM_OK;
 }
 

@@ -464,68 +464,6 @@ __global__ void k_h2d_m2p(const int* __restrict__ leaves, TreeView tv, PointsVie
     }
 }
 
-// ------------------------------------------------------------------ P2P
-// One workgroup (one wavefront) per target leaf; each lane keeps a target in
-// registers while source tiles of the leaves in List 1 are staged in LDS as
-// SoA doubles (coalesced loads, broadcast reads).  Writes
-// u[perm[i]] = (i/4) (near + far) in the caller's order.
-__global__ __launch_bounds__(64) void k_h2d_p2p(const int* __restrict__ leaves, TreeView tv,
-                                                PointsView pv, double kappa,
-                                                const cplx* __restrict__ ufar,
-                                                const int* __restrict__ perm, double* __restrict__ out)
-{
-    __shared__ double s1r[64], s1i[64], s2r[64], s2i[64], ssr[64], ssi[64];
-    int b = leaves[blockIdx.x];
-    int64_t n = pv.n;
-    int t = threadIdx.x;
-    int p0 = tv.pbeg[b], p1 = tv.pend[b];
-    int e0 = tv.l1off[b], e1 = tv.l1off[b + 1];
-    for (int i0 = p0; i0 < p1; i0 += 64) {
-        int i = i0 + t;
-        bool active = i < p1;
-        double x1r = 0, x1i = 0, x2r = 0, x2i = 0;
-        if (active) {
-            x1r = pv.xre[i]; x1i = pv.xim[i];
-            x2r = pv.xre[n + i]; x2i = pv.xim[n + i];
-        }
-        double ar = 0.0, ai = 0.0;
-        for (int e = e0; e < e1; ++e) {
-            int a = tv.l1idx[e];
-            int q0 = tv.pbeg[a], q1 = tv.pend[a];
-            for (int j0 = q0; j0 < q1; j0 += 64) {
-                int cnt = min(64, q1 - j0);
-                __syncthreads();
-                if (t < cnt) {
-                    int j = j0 + t;
-                    s1r[t] = pv.xre[j]; s1i[t] = pv.xim[j];
-                    s2r[t] = pv.xre[n + j]; s2i[t] = pv.xim[n + j];
-                    ssr[t] = pv.sre[j]; ssi[t] = pv.sim[j];
-                }
-                __syncthreads();
-                if (active) {
-                    for (int q = 0; q < cnt; ++q) {
-                        if (j0 + q == i) continue;
-                        double d1r = x1r - s1r[q], d1i = x1i - s1i[q];
-                        double d2r = x2r - s2r[q], d2i = x2i - s2i[q];
-                        cplx s = mk(d1r * d1r - d1i * d1i + d2r * d2r - d2i * d2i,
-                                    2.0 * (d1r * d1i + d2r * d2i));
-                        if (s.re == 0.0 && s.im == 0.0) continue;
-                        cplx h = hankel0_s(s, kappa, c_ghx, c_ghw);
-                        ar += h.re * ssr[q] - h.im * ssi[q];
-                        ai += h.re * ssi[q] + h.im * ssr[q];
-                    }
-                }
-            }
-        }
-        if (active) {
-            cplx f = ufar[i];
-            double tr = ar + f.re, ti = ai + f.im;
-            int64_t p = perm[i];
-            out[2 * p] = -0.25 * ti;      // (i/4) (tr + i ti)
-            out[2 * p + 1] = 0.25 * tr;
-        }
-    }
-}
 
 // Natural logarithm of a positive, finite, normal x: with x = 2^e m,
 // m in [sqrt(1/2), sqrt(2)), log x = e ln 2 + 2 atanh(t), t = (m - 1)/(m + 1),
@@ -558,91 +496,232 @@ __device__ inline double log_pos(double x)
     return (double)e * ln2_hi + ((double)e * ln2_lo + 2.0 * t * p);
 }
 
-// P2P for leaves whose every near pair has |kappa r| < 3 (a plan-time bound
-// from the box geometry): only the power series of H0 is needed, with the
-// leaf's fixed number of terms K (enough for the bound).  With q = kappa^2 s/4,
-// log(z/2) = log(q)/2 and log q = log(kappa^2/4) + log|s| + i arg s (Re s > 0 on
-// every near pair, as the plan checks):
-//   J0 = sum_k (-q)^k/(k!)^2,  Y0 = (2/pi)((log(z/2) + gamma) J0 - sum_k H_k (-q)^k/(k!)^2).
-// The kernel carries none of the other Hankel branches, so it keeps far fewer
-// registers live than the general P2P.
-__global__ __launch_bounds__(64) void k_h2d_p2p_ser(const int* __restrict__ leaves,
-                                                    const int* __restrict__ nterm, TreeView tv,
-                                                    PointsView pv, double kappa,
-                                                    const cplx* __restrict__ ufar,
-                                                    const int* __restrict__ perm, double* __restrict__ out)
+
+// ------------------------------------------------- P2P by leaf pairs
+// The near field as work items over List-1 entries e = (target leaf b, source
+// leaf a).  Each item writes the partial potential of b's targets due to a's
+// sources into C[coff[e] + (i - pbeg[b])]; a final pass adds, per target, the
+// partials of its List-1 entries in list order (deterministic).
+//
+// Symmetric items (a < b, every pair in the small-argument regime): since
+// G(x, y) = G(y, x), one evaluation serves both directions.  A wavefront holds
+// 64 targets of b in its lanes and a tile of 64 sources of a in LDS; at step s
+// lane l pairs its target with source (l + s) mod 64.  The target's row sum
+// stays in the lane, while the source's column sum travels with the source:
+// after each step it moves one lane down, so after 64 steps lane l holds the
+// column sum of source l, which goes to the partner entry e' = (a, b).
+struct P2PMap {
+    const int* row_of;      // target leaf of each List-1 entry
+    const int* partner;     // entry (a, b) for entry (b, a)
+    const int64_t* coff;    // offset of each entry's partial sums in C
+    cplx* C;
+};
+
+// H0(kappa r) from s = r^2 by the power series with K terms (|kappa r| < 3).
+__device__ inline cplx h0_series_s(double sr, double si, double k2, double lk2, int K)
 {
     constexpr SeriesTab T = make_series_tab();
+    double lm = 0.5 * log_pos(sr * sr + si * si) + lk2;   // log|q|
+    double ag = atan2(si, sr);                            // arg q
+    double qr = -k2 * sr, qi = -k2 * si;                  // -q
+    double tr = 1.0, ti = 0.0, jr = 1.0, ji = 0.0, sr0 = 0.0, si0 = 0.0;
+    for (int k = 1; k <= K; ++k) {
+        double c = T.inv_k2[k];
+        double nr = (tr * qr - ti * qi) * c, ni = (tr * qi + ti * qr) * c;
+        tr = nr;
+        ti = ni;
+        jr += tr;
+        ji += ti;
+        double h = T.harm[k];
+        sr0 += h * tr;
+        si0 += h * ti;
+    }
+    double lgr = 0.5 * lm + kEuler, lgi = 0.5 * ag;
+    double yr = (2.0 / kPi) * (lgr * jr - lgi * ji - sr0);
+    double yi = (2.0 / kPi) * (lgr * ji + lgi * jr - si0);
+    return mk(jr - yi, ji + yr);                          // J0 + i Y0
+}
+
+__global__ __launch_bounds__(64) void k_h2d_p2p_sym(const int* __restrict__ items, const int* __restrict__ nterm,
+                                                    P2PMap mp, TreeView tv, PointsView pv, double kappa)
+{
     __shared__ double s1r[64], s1i[64], s2r[64], s2i[64], ssr[64], ssi[64];
-    int b = leaves[blockIdx.x];
-    int K = nterm[blockIdx.x];
+    int e = items[blockIdx.x], K = nterm[blockIdx.x];
+    int b = mp.row_of[e], a = tv.l1idx[e], ep = mp.partner[e];
     int64_t n = pv.n;
     int t = threadIdx.x;
-    int p0 = tv.pbeg[b], p1 = tv.pend[b];
-    int e0 = tv.l1off[b], e1 = tv.l1off[b + 1];
     double k2 = 0.25 * kappa * kappa, lk2 = log(k2);
-    for (int i0 = p0; i0 < p1; i0 += 64) {
+    int pb0 = tv.pbeg[b], pb1 = tv.pend[b], pa0 = tv.pbeg[a], pa1 = tv.pend[a];
+    cplx* Crow = mp.C + mp.coff[e];
+    cplx* Ccol = mp.C + mp.coff[ep];
+    for (int i0 = pb0; i0 < pb1; i0 += 64) {
         int i = i0 + t;
-        bool active = i < p1;
+        bool ti_ok = i < pb1;
+        double x1r = 0, x1i = 0, x2r = 0, x2i = 0, wr = 0, wi = 0;
+        if (ti_ok) {
+            x1r = pv.xre[i]; x1i = pv.xim[i];
+            x2r = pv.xre[n + i]; x2i = pv.xim[n + i];
+            wr = pv.sre[i]; wi = pv.sim[i];
+        }
+        double ar = 0.0, ai = 0.0;
+        for (int j0 = pa0; j0 < pa1; j0 += 64) {
+            int cnt = min(64, pa1 - j0);
+            __syncthreads();
+            if (t < cnt) {
+                int j = j0 + t;
+                s1r[t] = pv.xre[j]; s1i[t] = pv.xim[j];
+                s2r[t] = pv.xre[n + j]; s2i[t] = pv.xim[n + j];
+                ssr[t] = pv.sre[j]; ssi[t] = pv.sim[j];
+            }
+            __syncthreads();
+            double cr = 0.0, ci = 0.0;   // column sum of source (t + step) mod 64
+            for (int step = 0; step < 64; ++step) {
+                int q = (t + step) & 63;
+                if (ti_ok && q < cnt) {
+                    double d1r = x1r - s1r[q], d1i = x1i - s1i[q];
+                    double d2r = x2r - s2r[q], d2i = x2i - s2i[q];
+                    double sr = d1r * d1r - d1i * d1i + d2r * d2r - d2i * d2i;
+                    double si = 2.0 * (d1r * d1i + d2r * d2i);
+                    if (sr != 0.0 || si != 0.0) {
+                        cplx h = h0_series_s(sr, si, k2, lk2, K);
+                        ar += h.re * ssr[q] - h.im * ssi[q];
+                        ai += h.re * ssi[q] + h.im * ssr[q];
+                        cr += h.re * wr - h.im * wi;
+                        ci += h.re * wi + h.im * wr;
+                    }
+                }
+                // hand the column sum to the lane that meets this source next
+                cr = __shfl(cr, (t + 1) & 63, 64);
+                ci = __shfl(ci, (t + 1) & 63, 64);
+            }
+            if (t < cnt) {
+                cplx* cc = Ccol + (j0 - pa0) + t;
+                if (i0 == pb0) *cc = mk(cr, ci);
+                else *cc = *cc + mk(cr, ci);
+            }
+        }
+        if (ti_ok) Crow[i - pb0] = mk(ar, ai);
+    }
+}
+
+// Diagonal items (a == b, at most 64 points, series regime): the same
+// rotation within one tile.  Steps s = 1..32 pair lane l with point (l + s)
+// mod 64, which covers every unordered pair once (at s = 32 only lanes l < 32
+// work, since (l, l + 32) and (l + 32, l) are the same pair); a final shuffle
+// returns each travelling column sum to its own lane.
+__global__ __launch_bounds__(64) void k_h2d_p2p_diag(const int* __restrict__ items, const int* __restrict__ nterm,
+                                                     P2PMap mp, TreeView tv, PointsView pv, double kappa)
+{
+    __shared__ double s1r[64], s1i[64], s2r[64], s2i[64], ssr[64], ssi[64];
+    int e = items[blockIdx.x], K = nterm[blockIdx.x];
+    int b = mp.row_of[e];
+    int64_t n = pv.n;
+    int t = threadIdx.x;
+    double k2 = 0.25 * kappa * kappa, lk2 = log(k2);
+    int p0 = tv.pbeg[b], cnt = tv.pend[b] - p0;
+    bool ok = t < cnt;
+    if (ok) {
+        int j = p0 + t;
+        s1r[t] = pv.xre[j]; s1i[t] = pv.xim[j];
+        s2r[t] = pv.xre[n + j]; s2i[t] = pv.xim[n + j];
+        ssr[t] = pv.sre[j]; ssi[t] = pv.sim[j];
+    }
+    __syncthreads();
+    double x1r = s1r[t & 63], x1i = s1i[t & 63], x2r = s2r[t & 63], x2i = s2i[t & 63];
+    double wr = ssr[t & 63], wi = ssi[t & 63];
+    double ar = 0.0, ai = 0.0, cr = 0.0, ci = 0.0;
+    for (int step = 1; step <= 32; ++step) {
+        // the column sum held here belongs to point (t + step) mod 64
+        int q = (t + step) & 63;
+        if (ok && q < cnt && (step < 32 || t < 32)) {
+            double d1r = x1r - s1r[q], d1i = x1i - s1i[q];
+            double d2r = x2r - s2r[q], d2i = x2i - s2i[q];
+            double sr = d1r * d1r - d1i * d1i + d2r * d2r - d2i * d2i;
+            double si = 2.0 * (d1r * d1i + d2r * d2i);
+            if (sr != 0.0 || si != 0.0) {
+                cplx h = h0_series_s(sr, si, k2, lk2, K);
+                ar += h.re * ssr[q] - h.im * ssi[q];
+                ai += h.re * ssi[q] + h.im * ssr[q];
+                cr += h.re * wr - h.im * wi;
+                ci += h.re * wi + h.im * wr;
+            }
+        }
+        cr = __shfl(cr, (t + 1) & 63, 64);
+        ci = __shfl(ci, (t + 1) & 63, 64);
+    }
+    // after 32 hand-offs lane u holds the sum of point (u + 33) mod 64
+    cr = __shfl(cr, (t + 31) & 63, 64);
+    ci = __shfl(ci, (t + 31) & 63, 64);
+    if (ok) mp.C[mp.coff[e] + t] = mk(ar + cr, ai + ci);
+}
+
+// Row items: one direction of an entry, the small-argument series (SERIES,
+// K terms) or the general Hankel evaluation; a == b skips the self pair.
+template <bool SERIES>
+__global__ __launch_bounds__(64) void k_h2d_p2p_row(const int* __restrict__ items, const int* __restrict__ nterm,
+                                                    P2PMap mp, TreeView tv, PointsView pv, double kappa)
+{
+    __shared__ double s1r[64], s1i[64], s2r[64], s2i[64], ssr[64], ssi[64];
+    int e = items[blockIdx.x];
+    int K = SERIES ? nterm[blockIdx.x] : 0;
+    int b = mp.row_of[e], a = tv.l1idx[e];
+    int64_t n = pv.n;
+    int t = threadIdx.x;
+    double k2 = 0.25 * kappa * kappa, lk2 = log(k2);
+    int pb0 = tv.pbeg[b], pb1 = tv.pend[b], pa0 = tv.pbeg[a], pa1 = tv.pend[a];
+    cplx* Crow = mp.C + mp.coff[e];
+    for (int i0 = pb0; i0 < pb1; i0 += 64) {
+        int i = i0 + t;
+        bool active = i < pb1;
         double x1r = 0, x1i = 0, x2r = 0, x2i = 0;
         if (active) {
             x1r = pv.xre[i]; x1i = pv.xim[i];
             x2r = pv.xre[n + i]; x2i = pv.xim[n + i];
         }
         double ar = 0.0, ai = 0.0;
-        for (int e = e0; e < e1; ++e) {
-            int a = tv.l1idx[e];
-            int q0 = tv.pbeg[a], q1 = tv.pend[a];
-            for (int j0 = q0; j0 < q1; j0 += 64) {
-                int cnt = min(64, q1 - j0);
-                __syncthreads();
-                if (t < cnt) {
-                    int j = j0 + t;
-                    s1r[t] = pv.xre[j]; s1i[t] = pv.xim[j];
-                    s2r[t] = pv.xre[n + j]; s2i[t] = pv.xim[n + j];
-                    ssr[t] = pv.sre[j]; ssi[t] = pv.sim[j];
-                }
-                __syncthreads();
-                if (active) {
-                    for (int q = 0; q < cnt; ++q) {
-                        if (j0 + q == i) continue;
-                        double d1r = x1r - s1r[q], d1i = x1i - s1i[q];
-                        double d2r = x2r - s2r[q], d2i = x2i - s2i[q];
-                        double sr = d1r * d1r - d1i * d1i + d2r * d2r - d2i * d2i;
-                        double si = 2.0 * (d1r * d1i + d2r * d2i);
-                        if (sr == 0.0 && si == 0.0) continue;
-                        double lm = 0.5 * log_pos(sr * sr + si * si) + lk2;   // log|q|
-                        double ag = atan2(si, sr);                        // arg q
-                        double qr = -k2 * sr, qi = -k2 * si;              // -q
-                        double tr = 1.0, ti = 0.0, jr = 1.0, ji = 0.0, sr0 = 0.0, si0 = 0.0;
-                        for (int k = 1; k <= K; ++k) {
-                            double c = T.inv_k2[k];
-                            double nr = (tr * qr - ti * qi) * c, ni = (tr * qi + ti * qr) * c;
-                            tr = nr;
-                            ti = ni;
-                            jr += tr;
-                            ji += ti;
-                            double h = T.harm[k];
-                            sr0 += h * tr;
-                            si0 += h * ti;
-                        }
-                        double lgr = 0.5 * lm + kEuler, lgi = 0.5 * ag;
-                        double yr = (2.0 / kPi) * (lgr * jr - lgi * ji - sr0);
-                        double yi = (2.0 / kPi) * (lgr * ji + lgi * jr - si0);
-                        double hr = jr - yi, hi = ji + yr;     // J0 + i Y0
-                        ar += hr * ssr[q] - hi * ssi[q];
-                        ai += hr * ssi[q] + hi * ssr[q];
-                    }
-                }
+        for (int j0 = pa0; j0 < pa1; j0 += 64) {
+            int cnt = min(64, pa1 - j0);
+            __syncthreads();
+            if (t < cnt) {
+                int j = j0 + t;
+                s1r[t] = pv.xre[j]; s1i[t] = pv.xim[j];
+                s2r[t] = pv.xre[n + j]; s2i[t] = pv.xim[n + j];
+                ssr[t] = pv.sre[j]; ssi[t] = pv.sim[j];
+            }
+            __syncthreads();
+            if (!active) continue;
+            for (int q = 0; q < cnt; ++q) {
+                if (j0 + q == i) continue;
+                double d1r = x1r - s1r[q], d1i = x1i - s1i[q];
+                double d2r = x2r - s2r[q], d2i = x2i - s2i[q];
+                double sr = d1r * d1r - d1i * d1i + d2r * d2r - d2i * d2i;
+                double si = 2.0 * (d1r * d1i + d2r * d2i);
+                if (sr == 0.0 && si == 0.0) continue;
+                cplx h = SERIES ? h0_series_s(sr, si, k2, lk2, K)
+                                : hankel0_s(mk(sr, si), kappa, c_ghx, c_ghw);
+                ar += h.re * ssr[q] - h.im * ssi[q];
+                ai += h.re * ssi[q] + h.im * ssr[q];
             }
         }
-        if (active) {
-            cplx f = ufar[i];
-            double tr = ar + f.re, ti = ai + f.im;
-            int64_t p = perm[i];
-            out[2 * p] = -0.25 * ti;      // (i/4) (tr + i ti)
-            out[2 * p + 1] = 0.25 * tr;
-        }
+        if (active) Crow[i - pb0] = mk(ar, ai);
+    }
+}
+
+// Final pass: u[perm[i]] = (i/4)(near + far), the near field summed over the
+// target's List-1 entries in list order.
+__global__ __launch_bounds__(64) void k_h2d_p2p_final(const int* __restrict__ leaves, P2PMap mp, TreeView tv,
+                                                      const cplx* __restrict__ ufar,
+                                                      const int* __restrict__ perm, double* __restrict__ out)
+{
+    int b = leaves[blockIdx.x];
+    int p0 = tv.pbeg[b], p1 = tv.pend[b];
+    int e0 = tv.l1off[b], e1 = tv.l1off[b + 1];
+    for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+        cplx u = ufar[i];
+        for (int e = e0; e < e1; ++e) u += mp.C[mp.coff[e] + (i - p0)];
+        int64_t p = perm[i];
+        out[2 * p] = -0.25 * u.im;      // (i/4) u
+        out[2 * p + 1] = 0.25 * u.re;
     }
 }
 
@@ -755,13 +834,15 @@ hipError_t h2d_leaf_far(const int* leaves, int nleaf, const int* m2p_leaves, int
     return hipGetLastError();
 }
 
-hipError_t h2d_p2p(const int* ser_leaves, int nser, const int* ser_nterm, const int* gen_leaves, int ngen,
-                   const TreeView& tv, const PointsView& pv, double kappa, const cplx* ufar,
-                   const int* perm, double* out, int mixed, hipStream_t st)
+hipError_t h2d_p2p(const H2DNear& nr, const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
+                   double kappa, const cplx* ufar, const int* perm, double* out, hipStream_t st)
 {
-    (void)mixed;
-    if (nser > 0) k_h2d_p2p_ser<<<nser, 64, 0, st>>>(ser_leaves, ser_nterm, tv, pv, kappa, ufar, perm, out);
-    if (ngen > 0) k_h2d_p2p<<<ngen, 64, 0, st>>>(gen_leaves, tv, pv, kappa, ufar, perm, out);
+    P2PMap mp{nr.row_of, nr.partner, nr.coff, nr.C};
+    if (nr.nsym > 0) k_h2d_p2p_sym<<<nr.nsym, 64, 0, st>>>(nr.sym, nr.sym_k, mp, tv, pv, kappa);
+    if (nr.ndiag > 0) k_h2d_p2p_diag<<<nr.ndiag, 64, 0, st>>>(nr.diag, nr.diag_k, mp, tv, pv, kappa);
+    if (nr.nser > 0) k_h2d_p2p_row<true><<<nr.nser, 64, 0, st>>>(nr.ser, nr.ser_k, mp, tv, pv, kappa);
+    if (nr.ngen > 0) k_h2d_p2p_row<false><<<nr.ngen, 64, 0, st>>>(nr.gen, nullptr, mp, tv, pv, kappa);
+    if (nleaf > 0) k_h2d_p2p_final<<<nleaf, 64, 0, st>>>(leaves, mp, tv, ufar, perm, out);
     return hipGetLastError();
 }
 

@@ -91,9 +91,18 @@ hipError_t h2d_l2l(const int* boxes, int nb, int ncoef, const TreeView& tv, cons
 hipError_t h2d_leaf_far(const int* leaves, int nleaf, const int* m2p_leaves, int nm2p, int top, int pmax,
                         const TreeView& tv, const PointsView& pv, double kappa, const int64_t* poff,
                         const cplx* vals, const cplx* mpole, const cplx* local, cplx* ufar, hipStream_t st);
-hipError_t h2d_p2p(const int* ser_leaves, int nser, const int* ser_nterm, const int* gen_leaves, int ngen,
-                   const TreeView& tv, const PointsView& pv, double kappa, const cplx* ufar,
-                   const int* perm, double* out, int mixed, hipStream_t st);
+// Near-field work of the 2D Helmholtz plan: List-1 entries as work items
+// (symmetric pair items, series row items, general row items) and the
+// partial-sum buffer C they write.
+struct H2DNear {
+    const int* sym; const int* sym_k; int nsym;
+    const int* diag; const int* diag_k; int ndiag;
+    const int* ser; const int* ser_k; int nser;
+    const int* gen; int ngen;
+    const int* row_of; const int* partner; const int64_t* coff; cplx* C;
+};
+hipError_t h2d_p2p(const H2DNear& nr, const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
+                   double kappa, const cplx* ufar, const int* perm, double* out, hipStream_t st);
 
 // 3D Laplace evaluation (l3d_kernels.hip); P is the common expansion length
 hipError_t l3d_p2m(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
