@@ -46,8 +46,8 @@ MAC_FLOPS = 8.0
 WORKLOADS = {
     # name: (config index, dim, kernel, default tol, P2P kernel, flops per interaction)
     "c1": (1, 2, "helmholtz", 1e-6, "P2P stage: k_h2d_p2p_sym + k_h2d_p2p_diag + k_h2d_p2p_row + k_h2d_p2p_final", 100.0),
-    "c2": (2, 3, "laplace", 1e-6, "k_l3d_p2p", 35.0),
-    "c3": (3, 3, "helmholtz", 1e-6, "k_h3d_p2p", 47.0),
+    "c2": (2, 3, "laplace", 1e-6, "P2P stage: k_near3_pair + k_near3_diag + k_near3_final", 35.0),
+    "c3": (3, 3, "helmholtz", 1e-6, "P2P stage: k_near3_pair + k_near3_diag + k_near3_final", 47.0),
 }
 P2P_FLOPS_PER_INTERACTION = WORKLOADS["c1"][5]
 PEAK_FP64_VALU = 78.6e12          # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz

@@ -83,10 +83,10 @@ struct cfmm_plan_s {
     cplx *d_mpole = nullptr, *d_local = nullptr, *d_ufar = nullptr;
     int off_p2l = 0, n_p2l = 0;
     H2DNear near2{};              // 2D near-field work items and partial sums
+    Near3Work near3{};            // 3D near-field work items and partial sums
     int64_t near_evals = -1;      // kernel evaluations per eval (-1: one per ordered pair)
     int off_m2p = 0, n_m2p = 0;   // leaves with List-3 boxes
     std::vector<int> p2l_h;       // host copy of the P2L work list (level order)
-    int* d_p2p_nterm = nullptr;   // per P2P leaf: the wide-phase flag (3D Helmholtz)
     // plan-time translation operators (2D Helmholtz)
     int64_t *d_o_m2l = nullptr, *d_o_tr = nullptr;
     cplx *d_g_m2l = nullptr, *d_g_m2m = nullptr, *d_g_l2l = nullptr;
@@ -683,29 +683,64 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         p->near2.gen = dd[4]; p->near2.row_of = dd[5]; p->near2.partner = dd[6];
         p->near2.coff = dcoff; p->near2.C = dC;
     }
-    // 3D Helmholtz mixed near field: leaves whose near pairs may reach
-    // kappa |r| > 8 form the phase in FP64 (same box bound as above)
-    if (dim == 3 && p->kernel == CFMM_HELMHOLTZ) {
-        std::vector<int> wide;
-        for (int b = 0; b < nb; ++b) {
-            if (t.nchild[b]) continue;
-            double rb = 0.0, wb = p->D * ldexp(1.0, -t.level[b]);
+    // 3D near field by List-1 entries: each pair of near leaves once (a < b),
+    // plus the diagonal entries.  In mixed Helmholtz, pairs whose near field
+    // may reach kappa |r| > 8 (box bound as above) form the phase in FP64.
+    if (dim == 3) {
+        int ne = (int)t.idx[0].size();
+        std::vector<int> row_of(ne), partner(ne, -1), it[4];
+        std::vector<int64_t> coff(ne + 1, 0);
+        for (int b = 0; b < nb; ++b)
             for (int e = t.off[0][b]; e < t.off[0][b + 1]; ++e) {
-                int a = t.idx[0][e];
-                double wa = p->D * ldexp(1.0, -t.level[a]);
-                double sre = 0.0, sci = 0.0;
-                for (int k = 0; k < dim; ++k) {
-                    double dr = fabs(cre[(size_t)k * nb + b] - cre[(size_t)k * nb + a]) + 0.5 * (wa + wb);
-                    double dc = cim[(size_t)k * nb + b] - cim[(size_t)k * nb + a];
-                    sre += dr * dr;
-                    sci += dc * dc;
-                }
-                double di = delta[a] + delta[b] + sqrt(sci);
-                rb = std::max(rb, sqrt(sre + di * di));
+                row_of[e] = b;
+                coff[e + 1] = coff[e] + (t.pend[b] - t.pbeg[b]);
             }
-            wide.push_back(p->kappa * rb > 8.0 ? 1 : 0);
+        for (int e = 0; e < ne; ++e) {
+            int b = row_of[e], a = t.idx[0][e];
+            const int* r0 = t.idx[0].data() + t.off[0][a];
+            const int* r1 = t.idx[0].data() + t.off[0][a + 1];
+            const int* f = std::lower_bound(r0, r1, b);
+            if (f == r1 || *f != b) return fail(CFMM_EINVAL, "internal: List 1 is not symmetric");
+            partner[e] = (int)(f - t.idx[0].data());
         }
-        if ((rc = upload(p, &p->d_p2p_nterm, wide))) return rc;
+        bool wide_split = p->kernel == CFMM_HELMHOLTZ && p->precision == CFMM_MIXED;
+        auto rbound = [&](int b, int a) {
+            double wb = p->D * ldexp(1.0, -t.level[b]), wa = p->D * ldexp(1.0, -t.level[a]);
+            double sre = 0.0, sci = 0.0;
+            for (int k = 0; k < dim; ++k) {
+                double dr = fabs(cre[(size_t)k * nb + b] - cre[(size_t)k * nb + a]) + 0.5 * (wa + wb);
+                double dc = cim[(size_t)k * nb + b] - cim[(size_t)k * nb + a];
+                sre += dr * dr;
+                sci += dc * dc;
+            }
+            double di = delta[a] + delta[b] + sqrt(sci);
+            return sqrt(sre + di * di);
+        };
+        int64_t ev = 0;
+        auto cnt = [&](int b) { return (int64_t)(t.pend[b] - t.pbeg[b]); };
+        for (int e = 0; e < ne; ++e) {
+            int b = row_of[e], a = t.idx[0][e];
+            if (a > b) continue;
+            int w = (wide_split && p->kappa * rbound(b, a) > 8.0) ? 2 : 0;
+            it[w + (a == b ? 1 : 0)].push_back(e);
+            ev += a == b ? cnt(b) * (cnt(b) - 1) / 2 : cnt(b) * cnt(a);
+        }
+        p->near_evals = ev;
+        int* dd[6] = {nullptr};
+        for (int q = 0; q < 4; ++q)
+            if ((rc = upload(p, &dd[q], it[q]))) return rc;
+        if ((rc = upload(p, &dd[4], row_of)) || (rc = upload(p, &dd[5], partner))) return rc;
+        int64_t* dcoff = nullptr;
+        cplx* dC = nullptr;
+        if ((rc = upload(p, &dcoff, coff)) || (rc = p->alloc(&dC, std::max<int64_t>(coff[ne], 1)))) return rc;
+        for (int q = 0; q < 4; ++q) {
+            p->near3.items[q] = dd[q];
+            p->near3.nitems[q] = (int)it[q].size();
+        }
+        p->near3.row_of = dd[4];
+        p->near3.partner = dd[5];
+        p->near3.coff = dcoff;
+        p->near3.C = dC;
     }
     if ((rc = upload(p, &p->d_work, work))) return rc;
     int64_t gsz = 0, tsz = 0, psz = 0;
@@ -953,8 +988,8 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         HIPCHK(h3d_leaf_far(W + p->off_leaves, p->nleaf, top, std::max(1, p->pmax), tv, pv, hl,
                             p->d_mpole, p->d_local, p->d_ufar, st));
         HIPCHK(mark(6));
-        HIPCHK(h3d_p2p(W + p->off_leaves, p->d_p2p_nterm, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm,
-                       out, p->precision, st));
+        HIPCHK(near3_p2p(p->near3, 1, p->precision, W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar,
+                         p->d_perm, out, st));
     } else {
         int P = p->pmax;
         HIPCHK(l3d_p2m(W + p->off_p2m, p->n_p2m, P, tv, pv, p->d_mpole, st));
@@ -971,7 +1006,8 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         HIPCHK(l3d_leaf_far(W + p->off_leaves, p->nleaf, top, tv, pv, p->d_mpole, p->d_local,
                             p->d_ufar, st));
         HIPCHK(mark(6));
-        HIPCHK(l3d_p2p(W + p->off_leaves, p->nleaf, tv, pv, p->d_ufar, p->d_perm, out, p->precision, st));
+        HIPCHK(near3_p2p(p->near3, 0, p->precision, W + p->off_leaves, p->nleaf, tv, pv, 0.0, p->d_ufar,
+                         p->d_perm, out, st));
     }
     HIPCHK(mark(7));
     if (!on_device) {

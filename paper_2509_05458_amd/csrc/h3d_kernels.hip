@@ -331,134 +331,6 @@ __global__ __launch_bounds__(64) void k_h3d_leaf_far(const int* __restrict__ lea
     (void)pmax;
 }
 
-// ------------------------------------------------------------------ P2P
-// G = e^{i kappa r} / (4 pi r) with the principal r = t + i Im s/(2t),
-// t = sqrt((|s| + Re s)/2): e^{i kappa r}/r = e^{-kappa Im r} (cos + i sin)(kappa Re r) conj(r) / |s|.
-// MIXED: differences formed in FP64 and cast to FP32, kernel and products in
-// FP32, each source tile summed in FP32 and the tile sums added in FP64.
-// Leaves whose near field reaches kappa r > 8 (flag[] set at plan time) form
-// r and the phase kappa Re r in FP64, reduce it mod 2 pi, and take sincos and
-// exp in FP32, so the phase error stays near FP32 rounding of an angle below pi.
-template <bool MIXED>
-__global__ __launch_bounds__(64) void k_h3d_p2p(const int* __restrict__ leaves, const int* __restrict__ flag,
-                                                TreeView tv, PointsView pv,
-                                                double kappa, const cplx* __restrict__ ufar,
-                                                const int* __restrict__ perm, double* __restrict__ out)
-{
-    __shared__ double sx[6][64], ss[2][64];
-    int b = leaves[blockIdx.x];
-    bool wide = MIXED && flag[blockIdx.x] != 0;
-    int64_t n = pv.n;
-    int t = threadIdx.x;
-    int p0 = tv.pbeg[b], p1 = tv.pend[b];
-    int e0 = tv.l1off[b], e1 = tv.l1off[b + 1];
-    float kf = (float)kappa;
-    for (int i0 = p0; i0 < p1; i0 += 64) {
-        int i = i0 + t;
-        bool active = i < p1;
-        double xr[3] = {0, 0, 0}, xi[3] = {0, 0, 0};
-        if (active)
-            for (int d = 0; d < 3; ++d) { xr[d] = pv.xre[d * n + i]; xi[d] = pv.xim[d * n + i]; }
-        double ar = 0.0, ai = 0.0;
-        for (int e = e0; e < e1; ++e) {
-            int a = tv.l1idx[e];
-            int q0 = tv.pbeg[a], q1 = tv.pend[a];
-            for (int j0 = q0; j0 < q1; j0 += 64) {
-                int cnt = min(64, q1 - j0);
-                __syncthreads();
-                if (t < cnt) {
-                    int j = j0 + t;
-                    for (int d = 0; d < 3; ++d) { sx[2 * d][t] = pv.xre[d * n + j]; sx[2 * d + 1][t] = pv.xim[d * n + j]; }
-                    ss[0][t] = pv.sre[j];
-                    ss[1][t] = pv.sim[j];
-                }
-                __syncthreads();
-                if (!active) continue;
-                if (MIXED && wide) {
-                    float fr = 0.0f, fi = 0.0f;
-                    const double tpi = 2.0 * kPi, itpi = 1.0 / (2.0 * kPi);
-                    for (int q = 0; q < cnt; ++q) {
-                        if (j0 + q == i) continue;
-                        double sr = 0.0, si = 0.0;
-                        for (int d = 0; d < 3; ++d) {
-                            double dr = xr[d] - sx[2 * d][q], di = xi[d] - sx[2 * d + 1][q];
-                            sr += dr * dr - di * di;
-                            si += 2.0 * dr * di;
-                        }
-                        if (sr == 0.0 && si == 0.0) continue;
-                        double as = sqrt(sr * sr + si * si);
-                        double tt = sqrt(0.5 * (as + sr));
-                        double ph = kappa * tt;
-                        ph -= tpi * rint(ph * itpi);
-                        float rr = (float)tt, ri = (float)(0.5 * si / tt);
-                        float sn, cs;
-                        sincosf((float)ph, &sn, &cs);
-                        float ex = expf(-kf * ri) / (float)as;
-                        float gr = (cs * rr + sn * ri) * ex, gi = (sn * rr - cs * ri) * ex;
-                        float wr = (float)ss[0][q], wi = (float)ss[1][q];
-                        fr += gr * wr - gi * wi;
-                        fi += gr * wi + gi * wr;
-                    }
-                    ar += (double)fr;
-                    ai += (double)fi;
-                } else if (MIXED) {
-                    float fr = 0.0f, fi = 0.0f;
-                    for (int q = 0; q < cnt; ++q) {
-                        if (j0 + q == i) continue;
-                        float sr = 0.0f, si = 0.0f;
-                        for (int d = 0; d < 3; ++d) {
-                            float dr = (float)(xr[d] - sx[2 * d][q]), di = (float)(xi[d] - sx[2 * d + 1][q]);
-                            sr += dr * dr - di * di;
-                            si += 2.0f * dr * di;
-                        }
-                        if (sr == 0.0f && si == 0.0f) continue;
-                        float as = sqrtf(sr * sr + si * si);
-                        float tt = sqrtf(0.5f * (as + sr));
-                        float rr = tt, ri = 0.5f * si / tt;
-                        float sn, cs;
-                        sincosf(kf * rr, &sn, &cs);
-                        float ex = expf(-kf * ri) / as;
-                        float gr = (cs * rr + sn * ri) * ex, gi = (sn * rr - cs * ri) * ex;
-                        float wr = (float)ss[0][q], wi = (float)ss[1][q];
-                        fr += gr * wr - gi * wi;
-                        fi += gr * wi + gi * wr;
-                    }
-                    ar += (double)fr;
-                    ai += (double)fi;
-                } else {
-                    for (int q = 0; q < cnt; ++q) {
-                        if (j0 + q == i) continue;
-                        double sr = 0.0, si = 0.0;
-                        for (int d = 0; d < 3; ++d) {
-                            double dr = xr[d] - sx[2 * d][q], di = xi[d] - sx[2 * d + 1][q];
-                            sr += dr * dr - di * di;
-                            si += 2.0 * dr * di;
-                        }
-                        if (sr == 0.0 && si == 0.0) continue;
-                        double as = sqrt(sr * sr + si * si);
-                        double tt = sqrt(0.5 * (as + sr));
-                        double rr = tt, ri = 0.5 * si / tt;
-                        double sn, cs;
-                        sincos(kappa * rr, &sn, &cs);
-                        double ex = exp(-kappa * ri) / as;
-                        // (cs + i sn)(rr - i ri) * ex
-                        double gr = (cs * rr + sn * ri) * ex, gi = (sn * rr - cs * ri) * ex;
-                        ar += gr * ss[0][q] - gi * ss[1][q];
-                        ai += gr * ss[1][q] + gi * ss[0][q];
-                    }
-                }
-            }
-        }
-        if (active) {
-            cplx f = ufar[i];
-            double k = 1.0 / (4.0 * kPi);
-            // far field carries the factor i kappa
-            int64_t p = perm[i];
-            out[2 * p] = k * (ar - kappa * f.im);
-            out[2 * p + 1] = k * (ai + kappa * f.re);
-        }
-    }
-}
 
 // ------------------------------------------------------------------ translations
 // K0: per pair, D = (c_dst - c_src) / w_src, rho_D = sqrt(D.D) and a complex
@@ -841,14 +713,6 @@ hipError_t h3d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const T
     return hipGetLastError();
 }
 
-hipError_t h3d_p2p(const int* leaves, const int* wide, int nleaf, const TreeView& tv, const PointsView& pv,
-                   double kappa, const cplx* ufar, const int* perm, double* out, int mixed, hipStream_t st)
-{
-    if (nleaf <= 0) return hipSuccess;
-    if (mixed) k_h3d_p2p<true><<<nleaf, 64, 0, st>>>(leaves, wide, tv, pv, kappa, ufar, perm, out);
-    else k_h3d_p2p<false><<<nleaf, 64, 0, st>>>(leaves, wide, tv, pv, kappa, ufar, perm, out);
-    return hipGetLastError();
-}
 
 // One chunk of a translation stage: pairs [0, tr.np) of the chunk, target
 // groups [0, ng) with pair ranges goff (chunk-relative).

@@ -116,8 +116,6 @@ hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* lo
 hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& tv,
                         const PointsView& pv, const cplx* mpole, const cplx* local, cplx* ufar,
                         hipStream_t st);
-hipError_t l3d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                   const cplx* ufar, const int* perm, double* out, int mixed, hipStream_t st);
 size_t l3d_max_lds_m2l(int P);
 int l3d_pmax_supported();
 
@@ -160,11 +158,25 @@ hipError_t h3d_p2l(const int* boxes, int nb, int pmax, const TreeView& tv, const
 hipError_t h3d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const TreeView& tv,
                         const PointsView& pv, const H3DLevels& hl, const cplx* mpole,
                         const cplx* local, cplx* ufar, hipStream_t st);
-hipError_t h3d_p2p(const int* leaves, const int* wide, int nleaf, const TreeView& tv, const PointsView& pv,
-                   double kappa, const cplx* ufar, const int* perm, double* out, int mixed, hipStream_t st);
 hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_src, const cplx* coef_src,
                          const int* gdst, const int* goff, int ng, const int* eoff_dst, cplx* coef_dst,
                          const double* eq_p0, const double* eq_d0, hipStream_t st);
+
+// 3D near field by List-1 entries (near3d.hip)
+struct Near3Map {
+    const int* row_of;      // target leaf of each List-1 entry
+    const int* partner;     // entry (a, b) for entry (b, a)
+    const int64_t* coff;    // offset of each entry's partial sums in C
+    cplx* C;
+};
+struct Near3Work {
+    const int* items[4];    // neighbour, diagonal, neighbour (wide phase), diagonal (wide phase)
+    int nitems[4];
+    const int* row_of; const int* partner; const int64_t* coff; cplx* C;
+};
+hipError_t near3_p2p(const Near3Work& w, int kernel, int mixed, const int* leaves, int nleaf, const TreeView& tv,
+                     const PointsView& pv, double kappa, const cplx* ufar, const int* perm, double* out,
+                     hipStream_t st);
 
 // host-side special functions for the expansion-length rule
 double h2d_nterms_crit(double kappa, double R, double r, int n);

@@ -353,93 +353,6 @@ __global__ __launch_bounds__(64) void k_l3d_leaf_far(const int* __restrict__ lea
     }
 }
 
-// ------------------------------------------------------------------ P2P
-// 1/(4 pi r) with the principal root: 1/sqrt(s) = (t - i Im s/(2t)) / |s|,
-// t = sqrt((|s| + Re s)/2).  MIXED: the coordinate differences are formed in
-// FP64 and cast to FP32, the kernel and the products run in FP32, each source
-// tile is summed in FP32 and the tile sums are added in FP64.
-template <bool MIXED>
-__global__ __launch_bounds__(64) void k_l3d_p2p(const int* __restrict__ leaves, TreeView tv,
-                                                PointsView pv, const cplx* __restrict__ ufar,
-                                                const int* __restrict__ perm, double* __restrict__ out)
-{
-    __shared__ double sx[6][64], ss[2][64];
-    int b = leaves[blockIdx.x];
-    int64_t n = pv.n;
-    int t = threadIdx.x;
-    int p0 = tv.pbeg[b], p1 = tv.pend[b];
-    int e0 = tv.l1off[b], e1 = tv.l1off[b + 1];
-    for (int i0 = p0; i0 < p1; i0 += 64) {
-        int i = i0 + t;
-        bool active = i < p1;
-        double xr[3] = {0, 0, 0}, xi[3] = {0, 0, 0};
-        if (active)
-            for (int d = 0; d < 3; ++d) { xr[d] = pv.xre[d * n + i]; xi[d] = pv.xim[d * n + i]; }
-        double ar = 0.0, ai = 0.0;
-        for (int e = e0; e < e1; ++e) {
-            int a = tv.l1idx[e];
-            int q0 = tv.pbeg[a], q1 = tv.pend[a];
-            for (int j0 = q0; j0 < q1; j0 += 64) {
-                int cnt = min(64, q1 - j0);
-                __syncthreads();
-                if (t < cnt) {
-                    int j = j0 + t;
-                    for (int d = 0; d < 3; ++d) { sx[2 * d][t] = pv.xre[d * n + j]; sx[2 * d + 1][t] = pv.xim[d * n + j]; }
-                    ss[0][t] = pv.sre[j];
-                    ss[1][t] = pv.sim[j];
-                }
-                __syncthreads();
-                if (!active) continue;
-                if (MIXED) {
-                    float fr = 0.0f, fi = 0.0f;
-                    for (int q = 0; q < cnt; ++q) {
-                        if (j0 + q == i) continue;
-                        float sr = 0.0f, si = 0.0f;
-                        for (int d = 0; d < 3; ++d) {
-                            float dr = (float)(xr[d] - sx[2 * d][q]), di = (float)(xi[d] - sx[2 * d + 1][q]);
-                            sr += dr * dr - di * di;
-                            si += 2.0f * dr * di;
-                        }
-                        if (sr == 0.0f && si == 0.0f) continue;
-                        float as = sqrtf(sr * sr + si * si);
-                        float tt = sqrtf(0.5f * (as + sr));
-                        float ias = 1.0f / as;
-                        float gr = tt * ias, gi = -0.5f * si * ias / tt;
-                        float wr = (float)ss[0][q], wi = (float)ss[1][q];
-                        fr += gr * wr - gi * wi;
-                        fi += gr * wi + gi * wr;
-                    }
-                    ar += (double)fr;
-                    ai += (double)fi;
-                } else {
-                    for (int q = 0; q < cnt; ++q) {
-                        if (j0 + q == i) continue;
-                        double sr = 0.0, si = 0.0;
-                        for (int d = 0; d < 3; ++d) {
-                            double dr = xr[d] - sx[2 * d][q], di = xi[d] - sx[2 * d + 1][q];
-                            sr += dr * dr - di * di;
-                            si += 2.0 * dr * di;
-                        }
-                        if (sr == 0.0 && si == 0.0) continue;
-                        double as = sqrt(sr * sr + si * si);
-                        double tt = sqrt(0.5 * (as + sr));
-                        double ias = 1.0 / as;
-                        double gr = tt * ias, gi = -0.5 * si * ias / tt;
-                        ar += gr * ss[0][q] - gi * ss[1][q];
-                        ai += gr * ss[1][q] + gi * ss[0][q];
-                    }
-                }
-            }
-        }
-        if (active) {
-            cplx f = ufar[i];
-            double k = 1.0 / (4.0 * kPi);
-            int64_t p = perm[i];
-            out[2 * p] = k * (ar + f.re);
-            out[2 * p + 1] = k * (ai + f.im);
-        }
-    }
-}
 
 // ---------------------------------------------------------------- launchers
 static size_t lds_bytes(int nelem) { return (size_t)nelem * sizeof(cplx); }
@@ -494,14 +407,6 @@ hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& t
     return hipGetLastError();
 }
 
-hipError_t l3d_p2p(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                   const cplx* ufar, const int* perm, double* out, int mixed, hipStream_t st)
-{
-    if (nleaf <= 0) return hipSuccess;
-    if (mixed) k_l3d_p2p<true><<<nleaf, 64, 0, st>>>(leaves, tv, pv, ufar, perm, out);
-    else k_l3d_p2p<false><<<nleaf, 64, 0, st>>>(leaves, tv, pv, ufar, perm, out);
-    return hipGetLastError();
-}
 
 size_t l3d_max_lds_m2l(int P) { return lds_bytes((2 * P + 1) * (2 * P + 1) + (P + 1) * (P + 1)); }
 

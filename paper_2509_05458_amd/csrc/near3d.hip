@@ -1,0 +1,354 @@
+// 3D near field (P2P, step 3 of Sec. 6.4) for the Laplace kernel 1/(4 pi r)
+// and the Helmholtz kernel e^{i kappa r}/(4 pi r), by List-1 entries.
+//
+// G(x, y) = G(y, x) (the squared complex distance is the same either way), so
+// every pair of near leaves is evaluated once for both directions.  A work
+// item is an entry e = (b, a) with a < b (neighbour item) or a = b (diagonal
+// item).  Each entry e owns the partial sums C[coff[e] + (i - pbeg[b])] of
+// b's targets due to a's sources; a neighbour item writes C[e] (rows) and
+// C[partner e] (columns), a diagonal item writes C[e].  A final pass adds, per
+// target, its entries' partials in list order, so results are reproducible.
+//
+// Inside an item a wavefront holds 64 targets (one per lane) and a tile of 64
+// sources in LDS.  At step s lane l pairs its target with source (l + s) mod
+// 64: the row sum stays in the lane and the source's column sum travels with
+// the source, one lane down per step, so after 64 steps lane l holds the
+// column sum of source l.  A tile against itself takes steps 1..32 only (at
+// step 32 just lanes l < 32), which covers each unordered pair once.
+//
+// Precision: FP64, or MIXED (differences formed in FP64 and cast to FP32, the
+// kernel in FP32, each tile's sums in FP32 and added in FP64).  In MIXED mode a
+// Helmholtz item whose near field can reach kappa r > 8 (flag from the plan)
+// forms r and the phase in FP64, reduced mod 2 pi before the FP32 sincos.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace cfmm {
+
+namespace {
+
+struct Tile {
+    double xr[3][64], xi[3][64], sr[64], si[64];
+};
+
+template <int KIND, int PREC>
+struct Kernel;
+
+// 1/r (principal r): (t - i Im s/(2t)) / |s|, t = sqrt((|s| + Re s)/2)
+template <>
+struct Kernel<0, 0> {
+    __device__ static void eval(const double* dr, const double* di, double, double& gr, double& gi)
+    {
+        double sr = 0.0, si = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            sr += dr[d] * dr[d] - di[d] * di[d];
+            si += 2.0 * dr[d] * di[d];
+        }
+        if (sr == 0.0 && si == 0.0) { gr = gi = 0.0; return; }
+        double as = sqrt(sr * sr + si * si);
+        double tt = sqrt(0.5 * (as + sr));
+        double ias = 1.0 / as;
+        gr = tt * ias;
+        gi = -0.5 * si * ias / tt;
+    }
+};
+template <>
+struct Kernel<0, 1> {
+    __device__ static void eval(const double* dr, const double* di, double, float& gr, float& gi)
+    {
+        float sr = 0.0f, si = 0.0f;
+        for (int d = 0; d < 3; ++d) {
+            float a = (float)dr[d], b = (float)di[d];
+            sr += a * a - b * b;
+            si += 2.0f * a * b;
+        }
+        if (sr == 0.0f && si == 0.0f) { gr = gi = 0.0f; return; }
+        float as = sqrtf(sr * sr + si * si);
+        float tt = sqrtf(0.5f * (as + sr));
+        float ias = 1.0f / as;
+        gr = tt * ias;
+        gi = -0.5f * si * ias / tt;
+    }
+};
+// e^{i kappa r}/r = e^{-kappa Im r}(cos + i sin)(kappa Re r) conj(r)/|s|
+template <>
+struct Kernel<1, 0> {
+    __device__ static void eval(const double* dr, const double* di, double kappa, double& gr, double& gi)
+    {
+        double sr = 0.0, si = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            sr += dr[d] * dr[d] - di[d] * di[d];
+            si += 2.0 * dr[d] * di[d];
+        }
+        if (sr == 0.0 && si == 0.0) { gr = gi = 0.0; return; }
+        double as = sqrt(sr * sr + si * si);
+        double rr = sqrt(0.5 * (as + sr)), ri = 0.5 * si / rr;
+        double sn, cs;
+        sincos(kappa * rr, &sn, &cs);
+        double ex = exp(-kappa * ri) / as;
+        gr = (cs * rr + sn * ri) * ex;
+        gi = (sn * rr - cs * ri) * ex;
+    }
+};
+template <>
+struct Kernel<1, 1> {
+    __device__ static void eval(const double* dr, const double* di, double kappa, float& gr, float& gi)
+    {
+        float sr = 0.0f, si = 0.0f;
+        for (int d = 0; d < 3; ++d) {
+            float a = (float)dr[d], b = (float)di[d];
+            sr += a * a - b * b;
+            si += 2.0f * a * b;
+        }
+        if (sr == 0.0f && si == 0.0f) { gr = gi = 0.0f; return; }
+        float kf = (float)kappa;
+        float as = sqrtf(sr * sr + si * si);
+        float rr = sqrtf(0.5f * (as + sr)), ri = 0.5f * si / rr;
+        float sn, cs;
+        sincosf(kf * rr, &sn, &cs);
+        float ex = expf(-kf * ri) / as;
+        gr = (cs * rr + sn * ri) * ex;
+        gi = (sn * rr - cs * ri) * ex;
+    }
+};
+// mixed, wide phase: r and kappa Re r in FP64, the rest in FP32
+template <>
+struct Kernel<1, 2> {
+    __device__ static void eval(const double* dr, const double* di, double kappa, float& gr, float& gi)
+    {
+        double sr = 0.0, si = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            sr += dr[d] * dr[d] - di[d] * di[d];
+            si += 2.0 * dr[d] * di[d];
+        }
+        if (sr == 0.0 && si == 0.0) { gr = gi = 0.0f; return; }
+        double as = sqrt(sr * sr + si * si);
+        double tt = sqrt(0.5 * (as + sr));
+        double ph = kappa * tt;
+        ph -= (2.0 * kPi) * rint(ph * (1.0 / (2.0 * kPi)));
+        float rr = (float)tt, ri = (float)(0.5 * si / tt);
+        float sn, cs;
+        sincosf((float)ph, &sn, &cs);
+        float ex = expf(-(float)kappa * ri) / (float)as;
+        gr = (cs * rr + sn * ri) * ex;
+        gi = (sn * rr - cs * ri) * ex;
+    }
+};
+
+template <int PREC>
+struct Acc {
+    typedef double T;
+};
+template <>
+struct Acc<1> {
+    typedef float T;
+};
+template <>
+struct Acc<2> {
+    typedef float T;
+};
+
+__device__ inline void load_tile(Tile& sh, const PointsView& pv, int j0, int cnt, int t)
+{
+    int64_t n = pv.n;
+    if (t < cnt) {
+        int j = j0 + t;
+        for (int d = 0; d < 3; ++d) {
+            sh.xr[d][t] = pv.xre[d * n + j];
+            sh.xi[d][t] = pv.xim[d * n + j];
+        }
+        sh.sr[t] = pv.sre[j];
+        sh.si[t] = pv.sim[j];
+    }
+}
+
+// One tile pair by rotation.  `steps` = 64 (distinct tiles) or 32 (a tile
+// against itself).  Row sums (ar, ai) accumulate in the lane; the column sums
+// are returned in (cr, ci) at their home lane.
+template <int KIND, int PREC>
+__device__ inline void tile_pair(const Tile& sh, int cnt_s, bool tok, const double* x, const double* y,
+                                 double wr, double wi, double kappa, int steps, double& ar, double& ai,
+                                 double& cr_out, double& ci_out)
+{
+    typedef typename Acc<PREC>::T T;
+    int t = threadIdx.x;
+    T rr = 0, ri = 0, cr = 0, ci = 0;
+    T fwr = (T)wr, fwi = (T)wi;
+    for (int step = (steps == 32 ? 1 : 0); step < (steps == 32 ? 33 : 64); ++step) {
+        int q = (t + step) & 63;
+        bool on = tok && q < cnt_s && (steps != 32 || step < 32 || t < 32);
+        if (on) {
+            double dr[3], di[3];
+            for (int d = 0; d < 3; ++d) {
+                dr[d] = x[d] - sh.xr[d][q];
+                di[d] = y[d] - sh.xi[d][q];
+            }
+            T gr, gi;
+            Kernel<KIND, PREC>::eval(dr, di, kappa, gr, gi);
+            T sr = (T)sh.sr[q], si = (T)sh.si[q];
+            rr += gr * sr - gi * si;
+            ri += gr * si + gi * sr;
+            cr += gr * fwr - gi * fwi;
+            ci += gr * fwi + gi * fwr;
+        }
+        cr = __shfl(cr, (t + 1) & 63, 64);
+        ci = __shfl(ci, (t + 1) & 63, 64);
+    }
+    if (steps == 32) {
+        // after 32 hand-offs lane u holds the column sum of point (u + 33) mod 64
+        cr = __shfl(cr, (t + 31) & 63, 64);
+        ci = __shfl(ci, (t + 31) & 63, 64);
+    }
+    ar += (double)rr;
+    ai += (double)ri;
+    cr_out = (double)cr;
+    ci_out = (double)ci;
+}
+
+// Neighbour items (a < b): rows into C[e], columns into C[partner e].
+template <int KIND, int PREC>
+__global__ __launch_bounds__(64) void k_near3_pair(const int* __restrict__ items, Near3Map mp, TreeView tv,
+                                                   PointsView pv, double kappa)
+{
+    __shared__ Tile sh;
+    int e = items[blockIdx.x];
+    int b = mp.row_of[e], a = tv.l1idx[e], ep = mp.partner[e];
+    int64_t n = pv.n;
+    int t = threadIdx.x;
+    int pb0 = tv.pbeg[b], pb1 = tv.pend[b], pa0 = tv.pbeg[a], pa1 = tv.pend[a];
+    cplx* Crow = mp.C + mp.coff[e];
+    cplx* Ccol = mp.C + mp.coff[ep];
+    for (int i0 = pb0; i0 < pb1; i0 += 64) {
+        int i = i0 + t;
+        bool tok = i < pb1;
+        double x[3] = {0, 0, 0}, y[3] = {0, 0, 0}, wr = 0, wi = 0;
+        if (tok) {
+            for (int d = 0; d < 3; ++d) { x[d] = pv.xre[d * n + i]; y[d] = pv.xim[d * n + i]; }
+            wr = pv.sre[i];
+            wi = pv.sim[i];
+        }
+        double ar = 0.0, ai = 0.0;
+        for (int j0 = pa0; j0 < pa1; j0 += 64) {
+            int cnt = min(64, pa1 - j0);
+            __syncthreads();
+            load_tile(sh, pv, j0, cnt, t);
+            __syncthreads();
+            double cr, ci;
+            tile_pair<KIND, PREC>(sh, cnt, tok, x, y, wr, wi, kappa, 64, ar, ai, cr, ci);
+            if (t < cnt) {
+                cplx* cc = Ccol + (j0 - pa0) + t;
+                if (i0 == pb0) *cc = mk(cr, ci);
+                else *cc = *cc + mk(cr, ci);
+            }
+        }
+        if (tok) Crow[i - pb0] = mk(ar, ai);
+    }
+}
+
+// Diagonal items (a = b): tile pairs (T, S) with T <= S of the leaf; both
+// rows and columns land in C[e].  The block first clears its region.
+template <int KIND, int PREC>
+__global__ __launch_bounds__(64) void k_near3_diag(const int* __restrict__ items, Near3Map mp, TreeView tv,
+                                                   PointsView pv, double kappa)
+{
+    __shared__ Tile sh;
+    int e = items[blockIdx.x];
+    int b = mp.row_of[e];
+    int64_t n = pv.n;
+    int t = threadIdx.x;
+    int p0 = tv.pbeg[b], p1 = tv.pend[b];
+    cplx* Cb = mp.C + mp.coff[e];
+    for (int i = t; i < p1 - p0; i += 64) Cb[i] = mk(0.0, 0.0);
+    for (int i0 = p0; i0 < p1; i0 += 64) {
+        int i = i0 + t;
+        bool tok = i < p1;
+        double x[3] = {0, 0, 0}, y[3] = {0, 0, 0}, wr = 0, wi = 0;
+        if (tok) {
+            for (int d = 0; d < 3; ++d) { x[d] = pv.xre[d * n + i]; y[d] = pv.xim[d * n + i]; }
+            wr = pv.sre[i];
+            wi = pv.sim[i];
+        }
+        double ar = 0.0, ai = 0.0;
+        for (int j0 = i0; j0 < p1; j0 += 64) {
+            int cnt = min(64, p1 - j0);
+            __syncthreads();
+            load_tile(sh, pv, j0, cnt, t);
+            __syncthreads();
+            double cr, ci;
+            bool self = j0 == i0;
+            tile_pair<KIND, PREC>(sh, cnt, tok, x, y, wr, wi, kappa, self ? 32 : 64, ar, ai, cr, ci);
+            if (self) {
+                ar += cr;   // the column sums of the same tile are this lane's own point
+                ai += ci;
+            } else if (t < cnt) {
+                // written by this wavefront only; earlier tiles' rows never touch it
+                cplx* cc = Cb + (j0 - p0) + t;
+                *cc = *cc + mk(cr, ci);
+            }
+        }
+        if (tok) Cb[i - p0] = Cb[i - p0] + mk(ar, ai);
+    }
+}
+
+// u[perm[i]] = (1/4pi)(near + far), far = ufar (Laplace) or i kappa ufar
+// (Helmholtz, whose expansions carry the factor i kappa / 4pi).
+template <int KIND>
+__global__ __launch_bounds__(64) void k_near3_final(const int* __restrict__ leaves, Near3Map mp, TreeView tv,
+                                                    double kappa, const cplx* __restrict__ ufar,
+                                                    const int* __restrict__ perm, double* __restrict__ out)
+{
+    int b = leaves[blockIdx.x];
+    int p0 = tv.pbeg[b], p1 = tv.pend[b];
+    int e0 = tv.l1off[b], e1 = tv.l1off[b + 1];
+    double k = 1.0 / (4.0 * kPi);
+    for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+        cplx u = mk(0.0, 0.0);
+        for (int e = e0; e < e1; ++e) u += mp.C[mp.coff[e] + (i - p0)];
+        cplx f = ufar[i];
+        if (KIND == 1) f = mk(-kappa * f.im, kappa * f.re);
+        int64_t p = perm[i];
+        out[2 * p] = k * (u.re + f.re);
+        out[2 * p + 1] = k * (u.im + f.im);
+    }
+}
+
+template <int KIND, int PREC>
+void launch_items(const Near3Work& w, int which, const Near3Map& mp, const TreeView& tv, const PointsView& pv,
+                  double kappa, hipStream_t st)
+{
+    const int* it = w.items[which];
+    int nit = w.nitems[which];
+    if (nit <= 0) return;
+    if (which == 0 || which == 2) k_near3_pair<KIND, PREC><<<nit, 64, 0, st>>>(it, mp, tv, pv, kappa);
+    else k_near3_diag<KIND, PREC><<<nit, 64, 0, st>>>(it, mp, tv, pv, kappa);
+}
+
+}  // namespace
+
+// items[0]: neighbour items, items[1]: diagonal items; in MIXED Helmholtz,
+// items[2], items[3]: the same for wide-phase pairs.
+hipError_t near3_p2p(const Near3Work& w, int kernel, int mixed, const int* leaves, int nleaf, const TreeView& tv,
+                     const PointsView& pv, double kappa, const cplx* ufar, const int* perm, double* out,
+                     hipStream_t st)
+{
+    Near3Map mp{w.row_of, w.partner, w.coff, w.C};
+    if (kernel == 0) {
+        if (mixed) { launch_items<0, 1>(w, 0, mp, tv, pv, kappa, st); launch_items<0, 1>(w, 1, mp, tv, pv, kappa, st); }
+        else { launch_items<0, 0>(w, 0, mp, tv, pv, kappa, st); launch_items<0, 0>(w, 1, mp, tv, pv, kappa, st); }
+        if (nleaf > 0) k_near3_final<0><<<nleaf, 64, 0, st>>>(leaves, mp, tv, kappa, ufar, perm, out);
+    } else {
+        if (mixed) {
+            launch_items<1, 1>(w, 0, mp, tv, pv, kappa, st);
+            launch_items<1, 1>(w, 1, mp, tv, pv, kappa, st);
+            launch_items<1, 2>(w, 2, mp, tv, pv, kappa, st);
+            launch_items<1, 2>(w, 3, mp, tv, pv, kappa, st);
+        } else {
+            launch_items<1, 0>(w, 0, mp, tv, pv, kappa, st);
+            launch_items<1, 0>(w, 1, mp, tv, pv, kappa, st);
+        }
+        if (nleaf > 0) k_near3_final<1><<<nleaf, 64, 0, st>>>(leaves, mp, tv, kappa, ufar, perm, out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cfmm
