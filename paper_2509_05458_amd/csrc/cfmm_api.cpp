@@ -13,6 +13,7 @@
 
 #include "h3d_host.hpp"
 #include "kernels.hpp"
+#include "l3d_layout.hpp"
 #include "tree_host.hpp"
 
 #pragma clang fp contract(off)
@@ -110,6 +111,9 @@ struct cfmm_plan_s {
     cplx *d_h3_tabc = nullptr, *d_h3_scr = nullptr;
     int *d_h3_src = nullptr, *d_h3_dst = nullptr, *d_h3_gdst = nullptr, *d_h3_goff = nullptr;
     int64_t h3_eq_half = 0;
+    // 3D Laplace M2L: table row bases and lane slots (l3d_layout.hpp)
+    int* d_l3map = nullptr;
+    int l3_ntab = 0, l3_R = 0;
     int64_t ecount = 0;
     int64_t info[16];
 
@@ -526,6 +530,12 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
             p->P[l] = m;
         }
         pmax = m;
+        L3dM2LLayout lay = l3d_m2l_layout(m);
+        std::vector<int> map(lay.base);
+        map.insert(map.end(), lay.slot.begin(), lay.slot.end());
+        if ((rc = upload(p, &p->d_l3map, map))) return rc;
+        p->l3_ntab = lay.entries;
+        p->l3_R = lay.R;
     }
     p->pmax = pmax;
     // -------- lists (a5), from the final top level
@@ -997,7 +1007,8 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         for (int l = nlev - 2; l >= top; --l)
             HIPCHK(l3d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], P, tv, p->d_mpole, st));
         HIPCHK(mark(3));
-        HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_mpole, p->d_local, st));
+        HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, p->d_mpole, p->d_local,
+                       st));
         HIPCHK(l3d_p2l(W + p->off_p2l, p->n_p2l, P, tv, pv, p->d_local, st));
         HIPCHK(mark(4));
         for (int l = top + 1; l < nlev; ++l)

@@ -34,6 +34,14 @@ CFMM_HD cplx& operator+=(cplx& a, cplx b) { a.re += b.re; a.im += b.im; return a
 CFMM_HD cplx& operator-=(cplx& a, cplx b) { a.re -= b.re; a.im -= b.im; return a; }
 CFMM_HD cplx& operator*=(cplx& a, cplx b) { a = a * b; return a; }
 CFMM_HD cplx& operator*=(cplx& a, double s) { a.re *= s; a.im *= s; return a; }
+// acc += a * b as four fused multiply-adds (no separate product rounding)
+CFMM_HD void cfma(cplx& acc, cplx a, cplx b)
+{
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+}
 CFMM_HD double cabs2(cplx a) { return a.re * a.re + a.im * a.im; }
 CFMM_HD double cabs1(cplx a) { return hypot(a.re, a.im); }
 CFMM_HD cplx conj(cplx a) { return cplx{a.re, -a.im}; }
@@ -72,6 +80,15 @@ CFMM_HD cplx cexp_(cplx a)
     double e = exp(a.re), s, c;
     sincos(a.im, &s, &c);
     return cplx{e * c, e * s};
+}
+
+// Workgroup i of a grid of n is dispatched to XCD i mod 8; this returns a
+// work index such that each XCD takes one contiguous range of [0, n), so that
+// neighbouring work items (which share their inputs) share one L2.
+__device__ inline int xcd_contiguous(int i, int n)
+{
+    int q = n >> 3, r = n & 7, x = i & 7;
+    return x * q + (x < r ? x : r) + (i >> 3);
 }
 
 }  // namespace cfmm

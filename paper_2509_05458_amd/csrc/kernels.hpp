@@ -110,13 +110,13 @@ hipError_t l3d_p2m(const int* boxes, int nb, int P, const TreeView& tv, const Po
 hipError_t l3d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
                    cplx* local, hipStream_t st);
 hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mpole, hipStream_t st);
-hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const cplx* mpole,
-                   cplx* local, hipStream_t st);
+hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const int* map, int ntab, int R,
+                   const cplx* mpole, cplx* local, hipStream_t st);
 hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st);
 hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& tv,
                         const PointsView& pv, const cplx* mpole, const cplx* local, cplx* ufar,
                         hipStream_t st);
-size_t l3d_max_lds_m2l(int P);
+size_t l3d_m2l_lds(int P, int ntab);
 int l3d_pmax_supported();
 
 // 3D Helmholtz evaluation (h3d_kernels.hip)

@@ -25,6 +25,7 @@
 // Coefficient (n, m) is stored at n^2 + n + m.  G = 1/(4 pi r) is applied at the end.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "l3d_layout.hpp"
 
 namespace cfmm {
 
@@ -206,66 +207,106 @@ __global__ __launch_bounds__(256) void k_l3d_m2m(const int* __restrict__ boxes, 
 }
 
 // ------------------------------------------------------------------ M2L
-// One workgroup per target box; per source box the table I_l^q(D / w),
-// l <= 2P, is built by columns (one thread per order q) in LDS.
-__global__ __launch_bounds__(256) void k_l3d_m2l(const int* __restrict__ boxes, TreeView tv,
-                                                 const cplx* __restrict__ mpole,
-                                                 cplx* __restrict__ local)
+// One wavefront per target box.  For each List-2 source box the table
+// I_l^q(D / w), l <= 2P, is built by columns (one lane per order q) in LDS,
+// entry (l, q) at base[l] + q with zero guards (layout in l3d_layout.hpp), and
+// the source multipole is copied beside it.  The outputs are split into groups
+// of four consecutive orders (j, k0..k0+3), k0 = -j + 4g; a lane owns up to R
+// groups, as the layout's lane slots assign them.  Over the source
+// coefficients (n, m), read at one LDS address by the whole wavefront, a group
+// needs I_{j+n}^{m-k0-c}, c = 0..3: at fixed n these four entries slide one
+// place along the row l = j + n per step in m, so each step loads one table
+// entry for four complex multiply-adds, and the sixteen lanes of a quarter
+// wave read sixteen distinct bank slots.  Orders past k = j in the last group
+// of a row read guard or neighbouring entries and are discarded.
+struct alignas(16) cplx16 {
+    double re, im;
+};
+
+template <int R>
+__global__ __launch_bounds__(64) void k_l3d_m2l(const int* __restrict__ boxes, int nboxes, TreeView tv,
+                                                const int* __restrict__ map, int ntab,
+                                                const cplx* __restrict__ mpole,
+                                                cplx* __restrict__ local)
 {
-    extern __shared__ cplx sh[];
-    int b = boxes[blockIdx.x];
+    extern __shared__ cplx16 tab16[];
+    int b = boxes[xcd_contiguous(blockIdx.x, nboxes)];
     int l = tv.level[b];
     int P = tv.P[l];
-    int nc = (P + 1) * (P + 1), ni = (2 * P + 1) * (2 * P + 1);
-    cplx* It = sh;             // ni
-    cplx* Ms = sh + ni;        // nc
+    int nc = (P + 1) * (P + 1);
+    cplx* tab = reinterpret_cast<cplx*>(tab16);
+    cplx* Ms = tab + ntab;
+    int* base = reinterpret_cast<int*>(Ms + nc);
     double s = tv.rs[l];
     int t = threadIdx.x;
-    cplx acc[4];
-    for (int r = 0; r < 4; ++r) acc[r] = mk(0.0, 0.0);
-    int jj[4], kk[4];
-    for (int r = 0; r < 4; ++r) {
-        int o = t + r * blockDim.x;
-        int n = (int)sqrt((double)o);
-        while (n * n > o) --n;
-        while ((n + 1) * (n + 1) <= o) ++n;
-        jj[r] = n;
-        kk[r] = o - n * n - n;
+    int jg[R], kg[R];
+    bool act[R];
+    cplx acc[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int code = map[2 * P + 1 + t + 64 * r];
+        jg[r] = code & 255;
+        kg[r] = -jg[r] + 4 * ((code >> 8) & 255);
+        act[r] = (code >> 16) & 1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = mk(0.0, 0.0);
     }
+    for (int i = t; i < ntab; i += 64) tab[i] = mk(0.0, 0.0);
+    for (int i = t; i <= 2 * P; i += 64) base[i] = map[i];
     cplx cb[3];
     box_centre(tv, b, cb);
     for (int e = tv.l2off[b]; e < tv.l2off[b + 1]; ++e) {
         int a = tv.l2idx[e];
+        cplx ca[3];
+        box_centre(tv, a, ca);
+        Vec3 d;
+        d.x = (cb[0] - ca[0]) * s; d.y = (cb[1] - ca[1]) * s; d.z = (cb[2] - ca[2]) * s;
+        const cplx* M = mpole + tv.eoff[a];
         __syncthreads();
-        if (t < 4 * P + 1) {
-            cplx ca[3];
-            box_centre(tv, a, ca);
-            Vec3 d;
-            d.x = (cb[0] - ca[0]) * s; d.y = (cb[1] - ca[1]) * s; d.z = (cb[2] - ca[2]) * s;
-            int q = t - 2 * P;
-            col_I(d, q, 2 * P, false, [&](int n, cplx v) { It[nm(n, q)] = v; });
-        }
-        for (int i = t; i < nc; i += blockDim.x) Ms[i] = mpole[tv.eoff[a] + i];
+        for (int i = t; i < nc; i += 64) Ms[i] = M[i];
+        for (int q = t - 2 * P; q <= 2 * P; q += 64)
+            col_I(d, q, 2 * P, false, [&](int n, cplx v) { tab[base[n] + q] = v; });
         __syncthreads();
-        for (int r = 0; r < 4; ++r) {
-            int o = t + r * blockDim.x;
-            if (o >= nc) break;
-            int j = jj[r], k = kk[r];
-            cplx a2 = mk(0.0, 0.0);
-            for (int n = 0; n <= P; ++n) {
-                const cplx* Irow = It + (j + n) * (j + n) + (j + n) - k;   // It[nm(j+n, m-k)] = Irow[m]
-                const cplx* Mrow = Ms + n * n + n;
-                for (int m = -n; m <= n; ++m) a2 += Mrow[m] * Irow[m];
+        for (int n = 0; n <= P; ++n) {
+            const cplx* Mn = Ms + n * n + n;
+            const cplx16* row[R];
+            cplx16 w1[R], w2[R], w3[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                row[r] = tab16 + base[jg[r] + n] - kg[r];
+                w1[r] = row[r][-n - 1];
+                w2[r] = row[r][-n - 2];
+                w3[r] = row[r][-n - 3];
             }
-            acc[r] += a2;
+#pragma unroll 4
+            for (int m = -n; m <= n; ++m) {
+                cplx am = Mn[m];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    cplx16 w0 = row[r][m];
+                    cfma(acc[r][0], am, mk(w0.re, w0.im));
+                    cfma(acc[r][1], am, mk(w1[r].re, w1[r].im));
+                    cfma(acc[r][2], am, mk(w2[r].re, w2[r].im));
+                    cfma(acc[r][3], am, mk(w3[r].re, w3[r].im));
+                    w3[r] = w2[r];
+                    w2[r] = w1[r];
+                    w1[r] = w0;
+                }
+            }
         }
     }
-    for (int r = 0; r < 4; ++r) {
-        int o = t + r * blockDim.x;
-        if (o < nc) {
-            cplx v = acc[r];
-            if ((jj[r] + kk[r]) & 1) v = -v;
-            local[tv.eoff[b] + o] = v;
+    cplx* o = local + tv.eoff[b];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!act[r]) continue;
+        int j = jg[r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            int k = kg[r] + c;
+            if (k > j) break;
+            cplx v = acc[r][c];
+            if ((j + k) & 1) v = -v;
+            o[nm(j, k)] = v;
         }
     }
 }
@@ -382,13 +423,37 @@ hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mp
     return hipGetLastError();
 }
 
-hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const cplx* mpole,
-                   cplx* local, hipStream_t st)
+template <int R>
+static hipError_t launch_m2l(const int* boxes, int nb, size_t lds, const TreeView& tv, const int* map, int ntab,
+                             const cplx* mpole, cplx* local, hipStream_t st)
+{
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_l3d_m2l<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    k_l3d_m2l<R><<<nb, 64, lds, st>>>(boxes, nb, tv, map, ntab, mpole, local);
+    return hipGetLastError();
+}
+
+size_t l3d_m2l_lds(int P, int ntab)
+{
+    return (size_t)(ntab + (P + 1) * (P + 1)) * sizeof(cplx) + (size_t)(2 * P + 1) * sizeof(int);
+}
+
+hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const int* map, int ntab, int R,
+                   const cplx* mpole, cplx* local, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    size_t lds = lds_bytes((2 * P + 1) * (2 * P + 1) + (P + 1) * (P + 1));
-    k_l3d_m2l<<<nb, 256, lds, st>>>(boxes, tv, mpole, local);
-    return hipGetLastError();
+    size_t lds = l3d_m2l_lds(P, ntab);
+    switch (R) {
+    case 1: return launch_m2l<1>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
+    case 2: return launch_m2l<2>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
+    case 3: return launch_m2l<3>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
+    case 4: return launch_m2l<4>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
+    case 5: return launch_m2l<5>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st)
@@ -408,20 +473,20 @@ hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& t
 }
 
 
-size_t l3d_max_lds_m2l(int P) { return lds_bytes((2 * P + 1) * (2 * P + 1) + (P + 1) * (P + 1)); }
-
-// Largest P the kernels take: 4 outputs per thread of a 256-thread M2L
-// workgroup ((P+1)^2 <= 1024) and the M2L tables within the device's LDS.
+// Largest P the kernels take: at most 5 output groups per M2L lane (P <= 31),
+// 4 outputs per thread of the 256-thread M2M/L2L workgroups ((P+1)^2 <= 1024),
+// and the M2L table within one workgroup's share of the CU's LDS.
 int l3d_pmax_supported()
 {
     int dev = 0, lds = 65536;
     if (hipGetDevice(&dev) == hipSuccess) {
         int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+            v > lds)
             lds = v;
     }
     int P = 31;
-    while (P > 1 && l3d_max_lds_m2l(P) > (size_t)lds) --P;
+    while (P > 1 && (l3d_m2l_layout(P).R > 5 || l3d_m2l_lds(P, l3d_m2l_layout(P).entries) > (size_t)lds)) --P;
     return P;
 }
 

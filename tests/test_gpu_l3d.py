@@ -31,14 +31,25 @@ def _plan_eval(pts, sig, tol, leaf=0, sep=0):
     return plan, u.cpu().numpy()
 
 
-@pytest.mark.parametrize("m,tol,leaf", [(48, 1e-6, 32), (64, 1e-6, 64), (64, 1e-9, 64), (40, 1e-6, 256), (48, 1e-4, 16)])
-def test_c2_family_full_parity(m, tol, leaf):
+# The expansion lengths span every M2L register-block count: P = 9, 14, 20,
+# 22, 27, 31 with separation 2 and P = 17, 26 with separation 1 hold 1..5
+# groups of four outputs per lane.  With separation 1 the plane's imaginary
+# parts are scaled by `im` (Lipschitz constant 0.5 im): at the full 0.5 the
+# k = 1 lists lie outside the proven 3D convergence region and the error
+# stalls near 1e-4 at tol 1e-6.
+@pytest.mark.parametrize("m,tol,leaf,sep,im", [
+    (48, 1e-6, 32, 0, 1.0), (64, 1e-6, 64, 0, 1.0), (64, 1e-9, 64, 0, 1.0), (40, 1e-6, 256, 0, 1.0),
+    (48, 1e-4, 16, 0, 1.0), (40, 1e-10, 64, 2, 1.0), (40, 1e-12, 64, 2, 1.0), (32, 1e-14, 64, 2, 1.0),
+    (40, 1e-4, 32, 1, 1.0), (32, 1e-6, 32, 1, 0.2)])
+def test_c2_family_full_parity(m, tol, leaf, sep, im):
     cfg = synth.make_config(2, n=m * m)
-    plan, u = _plan_eval(cfg.points, cfg.sigma, tol, leaf)
-    u0 = oracle.direct_self(3, "laplace", 0.0, cfg.points, cfg.sigma, nthreads=NTHREADS)
+    pts = cfg.points.real + 1j * im * cfg.points.imag
+    plan, u = _plan_eval(pts, cfg.sigma, tol, leaf, sep)
+    u0 = oracle.direct_self(3, "laplace", 0.0, pts, cfg.sigma, nthreads=NTHREADS)
     e = oracle.rel_l2(u, u0)
-    _say(f"[gpu] l3d m={m} tol={tol} rel_l2={e:.3e} info={plan.info()}")
-    assert e <= tol
+    _say(f"[gpu] l3d m={m} tol={tol} sep={sep} im={im} rel_l2={e:.3e} info={plan.info()}")
+    # below 1e-12 the FP64 rounding of the translations, not the truncation, sets the error
+    assert e <= max(tol, 1e-12)
 
 
 def test_c3_geometry_laplace_parity_and_tree():
