@@ -48,6 +48,7 @@ int ensure_device_tables()
     if (g_inited.count(dev)) return CFMM_OK;
     HIPCHK(h2d_init_tables(dev));
     HIPCHK(h3d_init_tables(dev));
+    HIPCHK(l3d_init_tables(dev));
     g_inited.insert(dev);
     return CFMM_OK;
 }

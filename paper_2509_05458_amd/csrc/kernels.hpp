@@ -151,6 +151,7 @@ struct H3DTr {
 };
 
 hipError_t h3d_init_tables(int device);
+hipError_t l3d_init_tables(int device);
 hipError_t h3d_p2m(const int* boxes, int nb, int pmax, const TreeView& tv, const PointsView& pv,
                    const H3DLevels& hl, cplx* mpole, hipStream_t st);
 hipError_t h3d_p2l(const int* boxes, int nb, int pmax, const TreeView& tv, const PointsView& pv,

@@ -103,43 +103,175 @@ __device__ inline void col_I(const Vec3& v, int m, int P, bool flip, F f)
     }
 }
 
-// ------------------------------------------------------------ P2M / P2L
-// One workgroup per box; thread t owns order m = t - P and accumulates its
-// column over the box's (or List-4 boxes') points in LDS.
-template <bool IRREGULAR>
-__global__ void k_l3d_p2x(const int* __restrict__ boxes, TreeView tv, PointsView pv, int useL4,
-                          cplx* __restrict__ out)
+// Recurrence constants, n, m <= 31: 1/((n+m)(n-m)) for m < n, 1/(2m), 2n-1 and
+// (n+m-1)(n-m-1).
+constexpr int kLT = 32;
+__constant__ double c_lrr[kLT * kLT];
+__constant__ double c_ldg[kLT];
+__constant__ double c_lodd[kLT];
+__constant__ double c_lka[kLT * kLT];
+
+// sum over n <= P, |m| <= n of C[nm(n, m)] R_n^m(x): the diagonal start of
+// column m is carried from column m - 1, and the columns +m and -m (same
+// recurrence coefficients, starts from w+ and w-) run side by side.
+__device__ inline cplx reg_sum(const Vec3& x, int P, const cplx* __restrict__ C)
 {
-    extern __shared__ cplx acc[];      // acc[n * blockDim.x + t]
+    cplx wp = wplus(x), wm = wminus(x), r2 = dot3(x), z = x.z;
+    cplx dp = mk(1.0, 0.0), dm = mk(1.0, 0.0), acc = mk(0.0, 0.0);
+    for (int m = 0; m <= P; ++m) {
+        if (m > 0) {
+            double f = c_ldg[m];
+            dp = (dp * wp) * f;
+            dm = (dm * wm) * f;
+        }
+        cplx ap = dp, am = (m & 1) ? -dm : dm;
+        cfma(acc, C[nm(m, m)], ap);
+        if (m > 0) cfma(acc, C[nm(m, -m)], am);
+        if (m + 1 > P) continue;
+        cplx bp = z * ap, bm = z * am;
+        cfma(acc, C[nm(m + 1, m)], bp);
+        if (m > 0) cfma(acc, C[nm(m + 1, -m)], bm);
+        for (int n = m + 2; n <= P; ++n) {
+            double o = c_lodd[n], f = c_lrr[n * kLT + m];
+            cplx cp = (o * (z * bp) - r2 * ap) * f;
+            cplx cm = (o * (z * bm) - r2 * am) * f;
+            cfma(acc, C[nm(n, m)], cp);
+            if (m > 0) cfma(acc, C[nm(n, -m)], cm);
+            ap = bp; bp = cp;
+            am = bm; bm = cm;
+        }
+    }
+    return acc;
+}
+
+// sum over n <= P, |m| <= n of C[nm(n, m)] I_n^m(y), principal rho.
+__device__ inline cplx irr_sum(const Vec3& y, int P, const cplx* __restrict__ C)
+{
+    cplx r2 = dot3(y), ir2 = cinv(r2);
+    cplx up = wplus(y) * ir2, um = wminus(y) * ir2, zi = y.z * ir2;
+    cplx dp = cinv(csqrt_p(r2)), dm = dp, acc = mk(0.0, 0.0);
+    for (int m = 0; m <= P; ++m) {
+        if (m > 0) {
+            double f = c_lodd[m];
+            dp = (dp * up) * f;
+            dm = (dm * um) * f;
+        }
+        cplx ap = dp, am = (m & 1) ? -dm : dm;
+        cfma(acc, C[nm(m, m)], ap);
+        if (m > 0) cfma(acc, C[nm(m, -m)], am);
+        if (m + 1 > P) continue;
+        double o1 = c_lodd[m + 1];
+        cplx bp = o1 * (zi * ap), bm = o1 * (zi * am);
+        cfma(acc, C[nm(m + 1, m)], bp);
+        if (m > 0) cfma(acc, C[nm(m + 1, -m)], bm);
+        for (int n = m + 2; n <= P; ++n) {
+            double o = c_lodd[n], k = c_lka[n * kLT + m];
+            cplx cp = o * (zi * bp) - k * (ir2 * ap);
+            cplx cm = o * (zi * bm) - k * (ir2 * am);
+            cfma(acc, C[nm(n, m)], cp);
+            if (m > 0) cfma(acc, C[nm(n, -m)], cm);
+            ap = bp; bp = cp;
+            am = bm; bm = cm;
+        }
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------ P2M / P2L
+// One wavefront per box.  Lane (h, c), c < 2P+1, owns the output order
+// m = c - P for the points h, h + H, ... of each staged chunk (H = 64 / (2P+1)
+// point streams).  The coefficient of order m is (-1)^m X_n^{-m}, i.e. the
+// column of |m| started from w- (m >= 0) or from w+ with the sign (-1)^|m|
+// (m < 0); sigma is folded into the start, so a step of the column recurrence
+// adds its value to the lane's LDS accumulator.  The diagonal start takes |m|
+// steps and the column P - |m|, so every lane takes P steps per point.
+constexpr int kP2XChunk = 64;
+
+template <bool IRREGULAR>
+__global__ __launch_bounds__(64) void k_l3d_p2x(const int* __restrict__ boxes, TreeView tv, PointsView pv, int useL4,
+                                                cplx* __restrict__ out)
+{
+    extern __shared__ cplx sh[];
     int b = boxes[blockIdx.x];
     int l = tv.level[b];
     int P = tv.P[l];
+    int ncol = 2 * P + 1, H = 64 / ncol;
+    double* pts = reinterpret_cast<double*>(sh);          // [8][kP2XChunk]: x,y,z re, x,y,z im, sigma re, im
+    cplx* acc = sh + 4 * kP2XChunk;                      // [H][P+1][ncol]
     double s = tv.rs[l];
-    int t = threadIdx.x, st = blockDim.x, mm = t - P;
-    bool act = t < 2 * P + 1;
-    int am = mm < 0 ? -mm : mm;
-    if (act)
-        for (int n = am; n <= P; ++n) acc[n * st + t] = mk(0.0, 0.0);
+    int t = threadIdx.x, h = t / ncol, col = t % ncol;
+    int m = col - P, am = m < 0 ? -m : m;
+    bool act = h < H;
+    for (int i = t; i < H * (P + 1) * ncol; i += 64) acc[i] = mk(0.0, 0.0);
     cplx c[3];
     box_centre(tv, b, c);
+    double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
     int e0 = useL4 ? tv.l4off[b] : 0, e1 = useL4 ? tv.l4off[b + 1] : 1;
+    int64_t n = pv.n;
     for (int e = e0; e < e1; ++e) {
         int src = useL4 ? tv.l4idx[e] : b;
-        for (int j = tv.pbeg[src]; j < tv.pend[src]; ++j) {
+        for (int j0 = tv.pbeg[src]; j0 < tv.pend[src]; j0 += kP2XChunk) {
+            int cnt = min(kP2XChunk, tv.pend[src] - j0);
+            __syncthreads();
+            if (t < cnt) {
+                int j = j0 + t;
+                for (int d = 0; d < 3; ++d) {
+                    pts[d * kP2XChunk + t] = (pv.xre[d * n + j] - c[d].re) * s;
+                    pts[(3 + d) * kP2XChunk + t] = (pv.xim[d * n + j] - c[d].im) * s;
+                }
+                pts[6 * kP2XChunk + t] = pv.sre[j];
+                pts[7 * kP2XChunk + t] = pv.sim[j];
+            }
+            __syncthreads();
             if (!act) continue;
-            Vec3 y = point_rel(pv, j, c, s);
-            cplx sg = mk(pv.sre[j], pv.sim[j]);
-            // (-1)^m X_n^{-m}(y): order -mm, flipped sign when mm odd
-            auto f = [&](int n, cplx v) { acc[n * st + t] += v * sg; };
-            if (IRREGULAR) col_I(y, -mm, P, (am & 1) != 0, f);
-            else col_R(y, -mm, P, (am & 1) != 0, f);
+            cplx* ac = acc + h * (P + 1) * ncol + col;
+            for (int q = h; q < cnt; q += H) {
+                Vec3 y;
+                y.x = mk(pts[q], pts[3 * kP2XChunk + q]);
+                y.y = mk(pts[kP2XChunk + q], pts[4 * kP2XChunk + q]);
+                y.z = mk(pts[2 * kP2XChunk + q], pts[5 * kP2XChunk + q]);
+                cplx sig = mk(pts[6 * kP2XChunk + q] * sg, pts[7 * kP2XChunk + q] * sg);
+                cplx w = m >= 0 ? wminus(y) : wplus(y);
+                cplx r2 = dot3(y);
+                if (!IRREGULAR) {
+                    cplx a = sig;
+                    for (int k = 1; k <= am; ++k) a = (a * w) * c_ldg[k];
+                    ac[am * ncol] += a;
+                    if (am + 1 > P) continue;
+                    cplx bb = y.z * a;
+                    ac[(am + 1) * ncol] += bb;
+                    for (int nn = am + 2; nn <= P; ++nn) {
+                        cplx cc = (c_lodd[nn] * (y.z * bb) - r2 * a) * c_lrr[nn * kLT + am];
+                        ac[nn * ncol] += cc;
+                        a = bb;
+                        bb = cc;
+                    }
+                } else {
+                    cplx ir2 = cinv(r2), u = w * ir2, zi = y.z * ir2;
+                    cplx a = sig * cinv(csqrt_p(r2));
+                    for (int k = 1; k <= am; ++k) a = (a * u) * c_lodd[k];
+                    ac[am * ncol] += a;
+                    if (am + 1 > P) continue;
+                    cplx bb = c_lodd[am + 1] * (zi * a);
+                    ac[(am + 1) * ncol] += bb;
+                    for (int nn = am + 2; nn <= P; ++nn) {
+                        cplx cc = c_lodd[nn] * (zi * bb) - c_lka[nn * kLT + am] * (ir2 * a);
+                        ac[nn * ncol] += cc;
+                        a = bb;
+                        bb = cc;
+                    }
+                }
+            }
         }
     }
-    if (act) {
+    __syncthreads();
+    if (h == 0) {
         cplx* o = out + tv.eoff[b];
-        for (int n = am; n <= P; ++n) {
-            if (useL4) o[nm(n, mm)] += acc[n * st + t];
-            else o[nm(n, mm)] = acc[n * st + t];
+        for (int nn = am; nn <= P; ++nn) {
+            cplx v = acc[nn * ncol + col];
+            for (int hh = 1; hh < H; ++hh) v += acc[(hh * (P + 1) + nn) * ncol + col];
+            if (useL4) o[nm(nn, m)] += v;
+            else o[nm(nn, m)] = v;
         }
     }
 }
@@ -355,6 +487,8 @@ __global__ __launch_bounds__(256) void k_l3d_l2l(const int* __restrict__ boxes, 
 }
 
 // ------------------------------------------------------------- L2P + M2P
+// One thread per target of a leaf: the leaf's local expansion and the
+// multipoles of its List-3 boxes, summed column by column (reg_sum, irr_sum).
 __global__ __launch_bounds__(64) void k_l3d_leaf_far(const int* __restrict__ leaves, int top,
                                                      TreeView tv, PointsView pv,
                                                      const cplx* __restrict__ mpole,
@@ -370,40 +504,33 @@ __global__ __launch_bounds__(64) void k_l3d_leaf_far(const int* __restrict__ lea
             double s = tv.rs[l];
             cplx c[3];
             box_centre(tv, b, c);
-            Vec3 x = point_rel(pv, i, c, s);
-            const cplx* L = local + tv.eoff[b];
-            cplx ul = mk(0.0, 0.0);
-            for (int m = -P; m <= P; ++m)
-                col_R(x, m, P, false, [&](int n, cplx v) { ul += L[nm(n, m)] * v; });
-            u = s * ul;
+            u = s * reg_sum(point_rel(pv, i, c, s), P, local + tv.eoff[b]);
             for (int e = tv.l3off[b]; e < tv.l3off[b + 1]; ++e) {
                 int a = tv.l3idx[e];
                 int la = tv.level[a];
-                int Pa = tv.P[la];
                 double sa = tv.rs[la];
                 box_centre(tv, a, c);
-                Vec3 y = point_rel(pv, i, c, sa);
-                const cplx* M = mpole + tv.eoff[a];
-                cplx um = mk(0.0, 0.0);
-                for (int m = -Pa; m <= Pa; ++m)
-                    col_I(y, m, Pa, false, [&](int n, cplx v) { um += M[nm(n, m)] * v; });
-                u += sa * um;
+                u += sa * irr_sum(point_rel(pv, i, c, sa), tv.P[la], mpole + tv.eoff[a]);
             }
         }
         ufar[i] = u;
     }
 }
 
-
 // ---------------------------------------------------------------- launchers
 static size_t lds_bytes(int nelem) { return (size_t)nelem * sizeof(cplx); }
+
+static size_t p2x_lds(int P)
+{
+    int ncol = 2 * P + 1;
+    return lds_bytes(4 * kP2XChunk + (64 / ncol) * (P + 1) * ncol);
+}
 
 hipError_t l3d_p2m(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
                    cplx* mpole, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    int th = ((2 * P + 1 + 63) / 64) * 64;
-    k_l3d_p2x<false><<<nb, th, lds_bytes((P + 1) * th), st>>>(boxes, tv, pv, 0, mpole);
+    k_l3d_p2x<false><<<nb, 64, p2x_lds(P), st>>>(boxes, tv, pv, 0, mpole);
     return hipGetLastError();
 }
 
@@ -411,9 +538,27 @@ hipError_t l3d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const Po
                    cplx* local, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    int th = ((2 * P + 1 + 63) / 64) * 64;
-    k_l3d_p2x<true><<<nb, th, lds_bytes((P + 1) * th), st>>>(boxes, tv, pv, 1, local);
+    k_l3d_p2x<true><<<nb, 64, p2x_lds(P), st>>>(boxes, tv, pv, 1, local);
     return hipGetLastError();
+}
+
+hipError_t l3d_init_tables(int device)
+{
+    (void)device;
+    static double rr[kLT * kLT], dg[kLT], odd[kLT], ka[kLT * kLT];
+    for (int n = 0; n < kLT; ++n) {
+        odd[n] = 2.0 * n - 1.0;
+        dg[n] = n > 0 ? 0.5 / n : 0.0;
+        for (int m = 0; m < kLT; ++m) {
+            rr[n * kLT + m] = m < n ? 1.0 / ((double)(n + m) * (double)(n - m)) : 0.0;
+            ka[n * kLT + m] = (double)(n + m - 1) * (double)(n - m - 1);
+        }
+    }
+    hipError_t e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_lrr), rr, sizeof(rr))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_ldg), dg, sizeof(dg))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_lodd), odd, sizeof(odd))) != hipSuccess) return e;
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_lka), ka, sizeof(ka));
 }
 
 hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mpole, hipStream_t st)
