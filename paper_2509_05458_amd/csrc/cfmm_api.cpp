@@ -115,6 +115,12 @@ struct cfmm_plan_s {
     // 3D Laplace M2L: table row bases and lane slots (l3d_layout.hpp)
     int* d_l3map = nullptr;
     int l3_ntab = 0, l3_R = 0;
+    // 3D M2P by List-3 entries: owner leaf, partial-sum offsets and storage
+    int* d_m2p_owner = nullptr;
+    int64_t* d_m2p_poff = nullptr;
+    cplx* d_m2p_part = nullptr;
+    int n_m2p3 = 0;
+    M2PParts m2p_parts() const { return M2PParts{n_m2p3, d_m2p_owner, d_m2p_poff, d_m2p_part}; }
     int64_t ecount = 0;
     int64_t info[16];
 
@@ -589,6 +595,21 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     for (int b = 0; b < nb; ++b)
         if (t.nchild[b] == 0 && t.level[b] >= top && t.off[2][b + 1] > t.off[2][b]) work.push_back(b);
     p->n_m2p = (int)work.size() - p->off_m2p;
+    if (dim == 3 && !t.idx[2].empty()) {
+        int n3 = (int)t.idx[2].size();
+        std::vector<int> owner(n3);
+        std::vector<int64_t> poff(n3 + 1, 0);
+        for (int b = 0; b < nb; ++b)
+            for (int e = t.off[2][b]; e < t.off[2][b + 1]; ++e) {
+                owner[e] = b;
+                poff[e + 1] = t.pend[b] - t.pbeg[b];
+            }
+        for (int e = 0; e < n3; ++e) poff[e + 1] += poff[e];
+        if ((rc = upload(p, &p->d_m2p_owner, owner)) || (rc = upload(p, &p->d_m2p_poff, poff)) ||
+            (rc = p->alloc(&p->d_m2p_part, (size_t)std::max<int64_t>(1, poff[n3]))))
+            return rc;
+        p->n_m2p3 = n3;
+    }
     p->off_p2l = (int)work.size();
     for (int b = 0; b < nb; ++b)
         if (t.level[b] >= top && t.off[3][b + 1] > t.off[3][b]) work.push_back(b);
@@ -997,7 +1018,7 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         if ((rc = run(2, p->d_local, p->d_local))) return rc;
         HIPCHK(mark(5));
         HIPCHK(h3d_leaf_far(W + p->off_leaves, p->nleaf, top, std::max(1, p->pmax), tv, pv, hl,
-                            p->d_mpole, p->d_local, p->d_ufar, st));
+                            p->d_mpole, p->d_local, p->m2p_parts(), p->d_ufar, st));
         HIPCHK(mark(6));
         HIPCHK(near3_p2p(p->near3, 1, p->precision, W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar,
                          p->d_perm, out, st));
@@ -1016,7 +1037,7 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
             HIPCHK(l3d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], P, tv, p->d_local, st));
         HIPCHK(mark(5));
         HIPCHK(l3d_leaf_far(W + p->off_leaves, p->nleaf, top, tv, pv, p->d_mpole, p->d_local,
-                            p->d_ufar, st));
+                            p->m2p_parts(), p->d_ufar, st));
         HIPCHK(mark(6));
         HIPCHK(near3_p2p(p->near3, 0, p->precision, W + p->off_leaves, p->nleaf, tv, pv, 0.0, p->d_ufar,
                          p->d_perm, out, st));

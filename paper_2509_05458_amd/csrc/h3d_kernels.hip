@@ -272,65 +272,82 @@ __global__ __launch_bounds__(128) void k_h3d_p2x(const int* __restrict__ boxes, 
 }
 
 // ------------------------------------------------------------------ L2P + M2P
-// One wavefront per leaf, one target per thread; each thread's radial values
-// sit in its own LDS column.
-__global__ __launch_bounds__(64) void k_h3d_leaf_far(const int* __restrict__ leaves, int top, int pmax,
-                                                     TreeView tv, PointsView pv, H3DLevels hl,
-                                                     const cplx* __restrict__ mpole,
-                                                     const cplx* __restrict__ local, cplx* __restrict__ ufar)
+// Expansion of box a (its local expansion when loc, else its multipole) at
+// point i; `my` is the calling thread's LDS column (stride 64) for the radial
+// values.
+__device__ inline cplx h3d_eval_point(int i, int a, bool loc, const TreeView& tv, const PointsView& pv,
+                                      const H3DLevels& hl, const cplx* __restrict__ coef, cplx* my)
+{
+    int64_t n = pv.n;
+    int nb = tv.nbox;
+    int la = tv.level[a];
+    int P = tv.P[la];
+    double iw = tv.rs[la];
+    cplx x[3];
+    for (int d = 0; d < 3; ++d)
+        x[d] = mk((pv.xre[d * n + i] - tv.cre[d * nb + a]) * iw, (pv.xim[d * n + i] - tv.cim[d * nb + a]) * iw);
+    cplx r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    if (loc) radial_j(r2, hl.kw[la], hl.sc[la], P, my, 64);
+    else radial_h(r2, hl.kw[la], hl.sc[la], P, my, 64);
+    const cplx* C = coef + tv.eoff[a];
+    cplx wp = mk(x[0].re - x[1].im, x[0].im + x[1].re);
+    cplx wm = mk(x[0].re + x[1].im, x[0].im - x[1].re);
+    cplx Dp = mk(1.0, 0.0), Dm = mk(1.0, 0.0), u = mk(0.0, 0.0);
+    for (int am = 0; am <= P; ++am) {
+        if (am > 0) {
+            Dp = Dp * wp * c_ck[am];
+            Dm = Dm * wm * c_ck[am];
+        }
+        for (int sgn = 0; sgn < (am ? 2 : 1); ++sgn) {
+            int m = sgn ? -am : am;
+            cplx D = sgn ? Dm : Dp;
+            cplx q0 = mk(0.0, 0.0), q1 = mk(1.0, 0.0);
+            cplx s = C[hnm(am, m)] * my[am * 64];
+            for (int nn = am + 1; nn <= P; ++nn) {
+                col_step_nd(nn, am, x[2], r2, q0, q1);
+                s += (C[hnm(nn, m)] * q1) * my[nn * 64];
+            }
+            u += D * s;
+        }
+    }
+    return u;
+}
+
+// M2P by List-3 entries: entry e = (leaf owner[e], box l3idx[e]), one
+// wavefront per entry, into part[poff[e] + i - pbeg].
+__global__ __launch_bounds__(64) void k_h3d_m2p_part(const int* __restrict__ owner,
+                                                     const int64_t* __restrict__ poff, TreeView tv,
+                                                     PointsView pv, H3DLevels hl,
+                                                     const cplx* __restrict__ mpole, cplx* __restrict__ part)
+{
+    extern __shared__ cplx rad[];   // [(pmax+2)][64]
+    int e = blockIdx.x;
+    int b = owner[e], a = tv.l3idx[e];
+    cplx* o = part + poff[e] - tv.pbeg[b];
+    for (int i = tv.pbeg[b] + threadIdx.x; i < tv.pend[b]; i += 64)
+        o[i] = h3d_eval_point(i, a, false, tv, pv, hl, mpole, rad + threadIdx.x);
+}
+
+// L2P, one wavefront per leaf and one target per thread, plus the leaf's
+// List-3 parts in list order.
+__global__ __launch_bounds__(64) void k_h3d_leaf_far(const int* __restrict__ leaves, int top, TreeView tv,
+                                                     PointsView pv, H3DLevels hl,
+                                                     const cplx* __restrict__ local,
+                                                     const int64_t* __restrict__ poff,
+                                                     const cplx* __restrict__ part, cplx* __restrict__ ufar)
 {
     extern __shared__ cplx rad[];   // [(pmax+2)][64]
     int b = leaves[blockIdx.x];
     int l = tv.level[b];
-    int t = threadIdx.x;
-    int64_t n = pv.n;
-    int nb = tv.nbox;
-    cplx* my = rad + t;
-    for (int i = tv.pbeg[b] + t; i < tv.pend[b]; i += 64) {
+    for (int i = tv.pbeg[b] + threadIdx.x; i < tv.pend[b]; i += 64) {
         cplx u = mk(0.0, 0.0);
         if (l >= top) {
-            // L2P from the leaf's own local expansion, then M2P over List 3
-            for (int e = tv.l3off[b] - 1; e < tv.l3off[b + 1]; ++e) {
-                int a = e < tv.l3off[b] ? b : tv.l3idx[e];
-                bool loc = a == b && e < tv.l3off[b];
-                int la = tv.level[a];
-                int P = tv.P[la];
-                double iw = tv.rs[la];
-                cplx x[3];
-                for (int d = 0; d < 3; ++d)
-                    x[d] = mk((pv.xre[d * n + i] - tv.cre[d * nb + a]) * iw,
-                              (pv.xim[d * n + i] - tv.cim[d * nb + a]) * iw);
-                cplx r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-                if (loc) radial_j(r2, hl.kw[la], hl.sc[la], P, my, 64);
-                else radial_h(r2, hl.kw[la], hl.sc[la], P, my, 64);
-                const cplx* C = (loc ? local : mpole) + tv.eoff[a];
-                cplx wp = mk(x[0].re - x[1].im, x[0].im + x[1].re);
-                cplx wm = mk(x[0].re + x[1].im, x[0].im - x[1].re);
-                cplx Dp = mk(1.0, 0.0), Dm = mk(1.0, 0.0);
-                for (int am = 0; am <= P; ++am) {
-                    if (am > 0) {
-                        Dp = Dp * wp * c_ck[am];
-                        Dm = Dm * wm * c_ck[am];
-                    }
-                    for (int sgn = 0; sgn < (am ? 2 : 1); ++sgn) {
-                        int m = sgn ? -am : am;
-                        cplx D = sgn ? Dm : Dp;
-                        cplx q0 = mk(0.0, 0.0), q1 = mk(1.0, 0.0);
-                        cplx s = C[hnm(am, m)] * my[am * 64];
-                        for (int nn = am + 1; nn <= P; ++nn) {
-                            col_step_nd(nn, am, x[2], r2, q0, q1);
-                            s += (C[hnm(nn, m)] * q1) * my[nn * 64];
-                        }
-                        u += D * s;
-                    }
-                }
-            }
+            u = h3d_eval_point(i, b, true, tv, pv, hl, local, rad + threadIdx.x);
+            for (int e = tv.l3off[b]; e < tv.l3off[b + 1]; ++e) u += part[poff[e] + i - tv.pbeg[b]];
         }
         ufar[i] = u;
     }
-    (void)pmax;
 }
-
 
 // ------------------------------------------------------------------ translations
 // K0: per pair, D = (c_dst - c_src) / w_src, rho_D = sqrt(D.D) and a complex
@@ -705,11 +722,16 @@ hipError_t h3d_p2l(const int* boxes, int nb, int pmax, const TreeView& tv, const
 
 hipError_t h3d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const TreeView& tv,
                         const PointsView& pv, const H3DLevels& hl, const cplx* mpole,
-                        const cplx* local, cplx* ufar, hipStream_t st)
+                        const cplx* local, const M2PParts& m2p, cplx* ufar, hipStream_t st)
 {
     if (nleaf <= 0) return hipSuccess;
     size_t lds = sizeof(cplx) * (size_t)(pmax + 3) * 64;
-    k_h3d_leaf_far<<<nleaf, 64, lds, st>>>(leaves, top, pmax, tv, pv, hl, mpole, local, ufar);
+    if (m2p.n > 0) {
+        k_h3d_m2p_part<<<m2p.n, 64, lds, st>>>(m2p.owner, m2p.poff, tv, pv, hl, mpole, m2p.part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_h3d_leaf_far<<<nleaf, 64, lds, st>>>(leaves, top, tv, pv, hl, local, m2p.poff, m2p.part, ufar);
     return hipGetLastError();
 }
 

@@ -52,6 +52,15 @@ struct TreeView {
     const int* l4off; const int* l4idx;
 };
 
+// M2P by List-3 entries (3D): per entry its owner leaf and the offset of its
+// per-point partial sums.
+struct M2PParts {
+    int n;                 // List-3 entries
+    const int* owner;      // [n]
+    const int64_t* poff;   // [n + 1]
+    cplx* part;            // [poff[n]]
+};
+
 struct PointsView {
     int64_t n;
     const double* xre;     // [d * n + i], sorted order
@@ -114,8 +123,8 @@ hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const in
                    const cplx* mpole, cplx* local, hipStream_t st);
 hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st);
 hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& tv,
-                        const PointsView& pv, const cplx* mpole, const cplx* local, cplx* ufar,
-                        hipStream_t st);
+                        const PointsView& pv, const cplx* mpole, const cplx* local, const M2PParts& m2p,
+                        cplx* ufar, hipStream_t st);
 size_t l3d_m2l_lds(int P, int ntab);
 int l3d_pmax_supported();
 
@@ -158,7 +167,7 @@ hipError_t h3d_p2l(const int* boxes, int nb, int pmax, const TreeView& tv, const
                    const H3DLevels& hl, cplx* local, hipStream_t st);
 hipError_t h3d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const TreeView& tv,
                         const PointsView& pv, const H3DLevels& hl, const cplx* mpole,
-                        const cplx* local, cplx* ufar, hipStream_t st);
+                        const cplx* local, const M2PParts& m2p, cplx* ufar, hipStream_t st);
 hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_src, const cplx* coef_src,
                          const int* gdst, const int* goff, int ng, const int* eoff_dst, cplx* coef_dst,
                          const double* eq_p0, const double* eq_d0, hipStream_t st);

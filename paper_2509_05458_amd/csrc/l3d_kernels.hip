@@ -487,12 +487,33 @@ __global__ __launch_bounds__(256) void k_l3d_l2l(const int* __restrict__ boxes, 
 }
 
 // ------------------------------------------------------------- L2P + M2P
-// One thread per target of a leaf: the leaf's local expansion and the
-// multipoles of its List-3 boxes, summed column by column (reg_sum, irr_sum).
+// M2P by List-3 entries: entry e = (leaf owner[e], box l3idx[e]) evaluates the
+// box's multipole at the leaf's points into part[poff[e] + i - pbeg], one
+// wavefront per entry, so a leaf with a long List 3 spreads over many
+// wavefronts.
+__global__ __launch_bounds__(64) void k_l3d_m2p_part(const int* __restrict__ owner,
+                                                     const int64_t* __restrict__ poff, TreeView tv,
+                                                     PointsView pv, const cplx* __restrict__ mpole,
+                                                     cplx* __restrict__ part)
+{
+    int e = blockIdx.x;
+    int b = owner[e], a = tv.l3idx[e];
+    int la = tv.level[a];
+    double sa = tv.rs[la];
+    cplx c[3];
+    box_centre(tv, a, c);
+    cplx* o = part + poff[e] - tv.pbeg[b];
+    for (int i = tv.pbeg[b] + threadIdx.x; i < tv.pend[b]; i += blockDim.x)
+        o[i] = sa * irr_sum(point_rel(pv, i, c, sa), tv.P[la], mpole + tv.eoff[a]);
+}
+
+// L2P, one thread per target of a leaf, plus the leaf's List-3 parts in list
+// order.
 __global__ __launch_bounds__(64) void k_l3d_leaf_far(const int* __restrict__ leaves, int top,
                                                      TreeView tv, PointsView pv,
-                                                     const cplx* __restrict__ mpole,
                                                      const cplx* __restrict__ local,
+                                                     const int64_t* __restrict__ poff,
+                                                     const cplx* __restrict__ part,
                                                      cplx* __restrict__ ufar)
 {
     int b = leaves[blockIdx.x];
@@ -505,13 +526,7 @@ __global__ __launch_bounds__(64) void k_l3d_leaf_far(const int* __restrict__ lea
             cplx c[3];
             box_centre(tv, b, c);
             u = s * reg_sum(point_rel(pv, i, c, s), P, local + tv.eoff[b]);
-            for (int e = tv.l3off[b]; e < tv.l3off[b + 1]; ++e) {
-                int a = tv.l3idx[e];
-                int la = tv.level[a];
-                double sa = tv.rs[la];
-                box_centre(tv, a, c);
-                u += sa * irr_sum(point_rel(pv, i, c, sa), tv.P[la], mpole + tv.eoff[a]);
-            }
+            for (int e = tv.l3off[b]; e < tv.l3off[b + 1]; ++e) u += part[poff[e] + i - tv.pbeg[b]];
         }
         ufar[i] = u;
     }
@@ -609,11 +624,16 @@ hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* lo
 }
 
 hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& tv,
-                        const PointsView& pv, const cplx* mpole, const cplx* local, cplx* ufar,
-                        hipStream_t st)
+                        const PointsView& pv, const cplx* mpole, const cplx* local, const M2PParts& m2p,
+                        cplx* ufar, hipStream_t st)
 {
     if (nleaf <= 0) return hipSuccess;
-    k_l3d_leaf_far<<<nleaf, 64, 0, st>>>(leaves, top, tv, pv, mpole, local, ufar);
+    if (m2p.n > 0) {
+        k_l3d_m2p_part<<<m2p.n, 64, 0, st>>>(m2p.owner, m2p.poff, tv, pv, mpole, m2p.part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_l3d_leaf_far<<<nleaf, 64, 0, st>>>(leaves, top, tv, pv, local, m2p.poff, m2p.part, ufar);
     return hipGetLastError();
 }
 
