@@ -89,6 +89,7 @@ struct cfmm_plan_s {
     int64_t near_evals = -1;      // kernel evaluations per eval (-1: one per ordered pair)
     int off_m2p = 0, n_m2p = 0;   // leaves with List-3 boxes
     std::vector<int> p2l_h;       // host copy of the P2L work list (level order)
+    std::vector<int> p2m_h;       // host copy of the P2M work list (level order)
     // plan-time translation operators (2D Helmholtz)
     int64_t *d_o_m2l = nullptr, *d_o_tr = nullptr;
     cplx *d_g_m2l = nullptr, *d_g_m2m = nullptr, *d_g_l2l = nullptr;
@@ -572,6 +573,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     for (int b = 0; b < nb; ++b)
         if (t.nchild[b] == 0 && t.level[b] >= top) work.push_back(b);
     p->n_p2m = (int)work.size() - p->off_p2m;
+    p->p2m_h.assign(work.begin() + p->off_p2m, work.end());
     p->m2m_off.assign(nlev, 0);
     p->m2m_cnt.assign(nlev, 0);
     p->l2l_off.assign(nlev, 0);
@@ -977,7 +979,21 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         H3DLevels hl{p->d_h3_kw, p->d_h3_sc};
         HIPCHK(hipMemsetAsync(p->d_mpole, 0, p->ecount * sizeof(cplx), st));
         HIPCHK(hipMemsetAsync(p->d_local, 0, p->ecount * sizeof(cplx), st));
-        HIPCHK(h3d_p2m(W + p->off_p2m, p->n_p2m, p->pmax, tv, pv, hl, p->d_mpole, st));
+        // the P2M and P2L lists are in level order; one launch per level sizes
+        // its threads and LDS by that level's P
+        auto per_level = [&](const std::vector<int>& h, int off, int cnt, bool p2l) -> int {
+            int k0 = 0;
+            while (k0 < cnt) {
+                int l = t.level[h[k0]], k1 = k0;
+                while (k1 < cnt && t.level[h[k1]] == l) ++k1;
+                if (p2l) HIPCHK(h3d_p2l(W + off + k0, k1 - k0, p->P[l], tv, pv, hl, p->d_local, st));
+                else HIPCHK(h3d_p2m(W + off + k0, k1 - k0, p->P[l], tv, pv, hl, p->d_mpole, st));
+                k0 = k1;
+            }
+            return CFMM_OK;
+        };
+        int rc0;
+        if ((rc0 = per_level(p->p2m_h, p->off_p2m, p->n_p2m, false))) return rc0;
         HIPCHK(mark(2));
         auto run = [&](int kind, const cplx* src, cplx* dst) -> int {
             for (const auto& S : p->h3) {
@@ -1013,7 +1029,7 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         if ((rc = run(0, p->d_mpole, p->d_mpole))) return rc;
         HIPCHK(mark(3));
         if ((rc = run(1, p->d_mpole, p->d_local))) return rc;
-        HIPCHK(h3d_p2l(W + p->off_p2l, p->n_p2l, p->pmax, tv, pv, hl, p->d_local, st));
+        if ((rc0 = per_level(p->p2l_h, p->off_p2l, p->n_p2l, true))) return rc0;
         HIPCHK(mark(4));
         if ((rc = run(2, p->d_local, p->d_local))) return rc;
         HIPCHK(mark(5));
