@@ -384,13 +384,52 @@ __global__ void k_h3d_geo(H3DTr tr, TreeView tv)
     g[9] = rho;
 }
 
+// K1a: coefficients of the polar derivative.  With v = -Q e_z (forward) or
+// -Q^T e_z (back), the derivative of a degree-n field along v is a degree-(n-1)
+// field: for the Schmidt harmonics
+//   d_z S_n^m = sqrt((n-m)(n+m)) S_{n-1}^m,
+//   (d_x + i d_y) S_n^m = -/+ sqrt((n-m)(n-m-1)) S_{n-1}^{m+1}   (- for m >= 0),
+//   (d_x - i d_y) S_n^m = +/- sqrt((n+m)(n+m-1)) S_{n-1}^{m-1}   (+ for m > 0),
+// and v.grad = v_z d_z + (v_x - i v_y)/2 (d_x + i d_y) + (v_x + i v_y)/2 (d_x - i d_y), so
+// G_n = sum_m a_n^m v.grad S_n^m = sum_m' t_{n-1}^m' S_{n-1}^m' with
+//   t_{n-1}^m' = v_z al(n,m') a_n^m' + (v_x - i v_y)/2 be(n,m'-1) a_n^{m'-1}
+//              + (v_x + i v_y)/2 ga(n,m'+1) a_n^{m'+1}.
+// Thread (pair, coefficient (n-1, m')), n = 1..P; written to A, which is free
+// until the DFT that follows the sampling.
+__global__ void k_h3d_rot_prep(H3DTr tr, int back, const int* __restrict__ eoff, const cplx* __restrict__ coef)
+{
+    int P = back ? tr.Pt : tr.Ps;
+    int nc = P * P;
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)tr.np * nc) return;
+    int c = (int)(gid % nc);
+    int i = (int)(gid / nc);
+    int np1 = (int)sqrt((double)c);
+    while (np1 * np1 > c) --np1;
+    while ((np1 + 1) * (np1 + 1) <= c) ++np1;
+    int mp = c - np1 * np1 - np1, n = np1 + 1;
+    const cplx* g = tr.geo + (size_t)i * 10;
+    const cplx* a = back ? tr.B + (size_t)i * tr.sB : coef + eoff[tr.src[i]];
+    cplx vx, vy, vz;
+    if (!back) { vx = -g[2]; vy = -g[5]; vz = -g[8]; }
+    else { vx = -g[6]; vy = -g[7]; vz = -g[8]; }
+    cplx hm = 0.5 * mk(vx.re + vy.im, vx.im - vy.re);   // (v_x - i v_y) / 2
+    cplx hp = 0.5 * mk(vx.re - vy.im, vx.im + vy.re);   // (v_x + i v_y) / 2
+    double al = sqrt((double)(n - mp) * (double)(n + mp));
+    int m1 = mp - 1, m2 = mp + 1;
+    double be = (m1 < 0 ? 1.0 : -1.0) * sqrt((double)(n - m1) * (double)(n - m1 - 1));
+    double ga = (m2 > 0 ? 1.0 : -1.0) * sqrt((double)(n + m2) * (double)(n + m2 - 1));
+    cplx t = (vz * a[hnm(n, mp)]) * al + (hm * a[hnm(n, m1)]) * be + (hp * a[hnm(n, m2)]) * ga;
+    tr.A[(size_t)i * tr.sA + c] = t;
+}
+
 // K1: rotation samples.  Thread (pair, n-block, node j): x = Q y_j (forward) or
-// Q^T y_j (back), derivative direction v = -Q e_z (or -Q^T e_z); accumulates
-// F_n(j) = sum_m a_n^m S_n^m(x) and G_n(j) = sum_m a_n^m v.grad S_n^m(x) for
+// Q^T y_j (back); accumulates F_n(j) = sum_m a_n^m S_n^m(x) and, from the
+// derivative coefficients t of K1a, G_n(j) = sum_m t_{n-1}^m S_{n-1}^m(x) for
 // the n of its block, sweeping the columns m with the diagonal start kept
-// incrementally.  On the unit sphere r2 = 1 and, v being tangent, (r2)' = 0.
+// incrementally and folded into the column.  On the unit sphere r2 = 1.
 template <int NB>
-__global__ void k_h3d_rot_sample(H3DTr tr, int back, const int* __restrict__ eoff, const cplx* __restrict__ coef)
+__global__ __launch_bounds__(256) void k_h3d_rot_sample(H3DTr tr, int back, const int* __restrict__ eoff, const cplx* __restrict__ coef)
 {
     int P = back ? tr.Pt : tr.Ps;
     int J = 2 * P + 1;
@@ -402,16 +441,15 @@ __global__ void k_h3d_rot_sample(H3DTr tr, int back, const int* __restrict__ eof
     int i = (int)(gid / ((int64_t)J * nblk));
     const cplx* g = tr.geo + (size_t)i * 10;
     const cplx* a = back ? tr.B + (size_t)i * tr.sB : coef + eoff[tr.src[i]];
+    const cplx* at = tr.A + (size_t)i * tr.sA;
     double sp, cp;
     sincospi(2.0 * j / J, &sp, &cp);
     // x = M y with y = (cp, sp, 0); M = Q or Q^T
-    V3 x, v;
+    V3 x;
     if (!back) {
         x.x = cp * g[0] + sp * g[1]; x.y = cp * g[3] + sp * g[4]; x.z = cp * g[6] + sp * g[7];
-        v.x = -g[2]; v.y = -g[5]; v.z = -g[8];
     } else {
         x.x = cp * g[0] + sp * g[3]; x.y = cp * g[1] + sp * g[4]; x.z = cp * g[2] + sp * g[5];
-        v.x = -g[6]; v.y = -g[7]; v.z = -g[8];
     }
     int nlo = blk * NB, nhi = min(P, nlo + NB - 1);
     cplx F[NB], G[NB];
@@ -420,36 +458,30 @@ __global__ void k_h3d_rot_sample(H3DTr tr, int back, const int* __restrict__ eof
     cplx one = mk(1.0, 0.0), zero = mk(0.0, 0.0);
     for (int sgn = 0; sgn < 2; ++sgn) {
         cplx w = sgn ? mk(x.x.re + x.y.im, x.x.im - x.y.re) : mk(x.x.re - x.y.im, x.x.im + x.y.re);
-        cplx dw = sgn ? mk(v.x.re + v.y.im, v.x.im - v.y.re) : mk(v.x.re - v.y.im, v.x.im + v.y.re);
-        cplx D = one, dD = zero;
+        cplx D = one;
         for (int am = 0; am <= nhi; ++am) {
-            if (am > 0) {
-                double ck = c_ck[am];
-                cplx Dn = (D * w) * ck;
-                dD = (dD * w + D * dw) * ck;
-                D = Dn;
-            }
+            if (am > 0) D = (D * w) * c_ck[am];
             if (sgn && am == 0) continue;
             int m = sgn ? -am : am;
-            const cplx* am_col = a;
-            cplx q0 = zero, q1 = one, dq0 = zero, dq1 = zero;
+            cplx q0 = zero, q1 = D;
             int n = am;
             // advance to n = nlo - 1 when the column starts below the block
             while (n < nlo - 1) {
                 ++n;
-                col_step(n, am, x.z, v.z, one, zero, q0, q1, dq0, dq1);
+                col_step_nd(n, am, x.z, one, q0, q1);
             }
+            // G of degree nlo takes the column at nlo - 1
+            if (nlo >= 1 && n == nlo - 1) cfma(G[0], at[hnm(n, m)], q1);
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 int nn = nlo + k;
                 if (nn > nhi || nn < am) continue;
                 if (nn > n) {
-                    col_step(nn, am, x.z, v.z, one, zero, q0, q1, dq0, dq1);
+                    col_step_nd(nn, am, x.z, one, q0, q1);
                     n = nn;
                 }
-                cplx c = am_col[hnm(nn, m)];
-                F[k] += c * (D * q1);
-                G[k] += c * (dD * q1 + D * dq1);
+                cfma(F[k], a[hnm(nn, m)], q1);
+                if (k + 1 < NB && nn + 1 <= nhi) cfma(G[k + 1], at[hnm(nn, m)], q1);
             }
         }
     }
@@ -747,6 +779,7 @@ hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_sr
     constexpr int NB = 8;
     k_h3d_geo<<<blocks(tr.np, bs), bs, 0, st>>>(tr, tv);
     int Ps = tr.Ps, Pt = tr.Pt;
+    k_h3d_rot_prep<<<blocks((int64_t)tr.np * Ps * Ps, bs), bs, 0, st>>>(tr, 0, eoff_src, coef_src);
     int64_t n1 = (int64_t)tr.np * ((Ps + NB) / NB) * (2 * Ps + 1);
     k_h3d_rot_sample<NB><<<blocks(n1, bs), bs, 0, st>>>(tr, 0, eoff_src, coef_src);
     int64_t n2 = (int64_t)tr.np * (Ps + 1) * (Ps + 1);
@@ -758,6 +791,7 @@ hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_sr
     int64_t n5 = (int64_t)tr.np * (Pt + 1) * (Pt + 1);
     int64_t nwave = (int64_t)(2 * Pt + 1) * ((Pt + 16) / 16) * ((tr.np + 3) / 4);
     k_h3d_coax_proj<<<(unsigned)((nwave + 3) / 4), 256, 0, st>>>(tr);
+    k_h3d_rot_prep<<<blocks((int64_t)tr.np * Pt * Pt, bs), bs, 0, st>>>(tr, 1, nullptr, nullptr);
     int64_t n6 = (int64_t)tr.np * ((Pt + NB) / NB) * (2 * Pt + 1);
     k_h3d_rot_sample<NB><<<blocks(n6, bs), bs, 0, st>>>(tr, 1, nullptr, nullptr);
     k_h3d_rot_dft<<<blocks(n5, bs), bs, sizeof(double) * 2 * (2 * Pt + 1), st>>>(tr, 1, eq_p0, eq_d0);
