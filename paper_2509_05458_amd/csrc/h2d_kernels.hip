@@ -574,9 +574,12 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_sym(const int* __restrict__ item
                 ssr[t] = pv.sre[j]; ssi[t] = pv.sim[j];
             }
             __syncthreads();
-            double cr = 0.0, ci = 0.0;   // column sum of source (t + step) mod 64
-            for (int step = 0; step < 64; ++step) {
-                int q = (t + step) & 63;
+            // rotation with period L = max(rows, sources): see k_near3 in near3d.hip
+            int R = min(64, pb1 - i0), L = max(R, cnt);
+            int nxt = t < L ? (t + 1 == L ? 0 : t + 1) : t;
+            double cr = 0.0, ci = 0.0;   // column sum of source (t + step) mod L
+            int q = t < L ? t : 0;
+            for (int step = 0; step < L; ++step) {
                 if (ti_ok && q < cnt) {
                     double d1r = x1r - s1r[q], d1i = x1i - s1i[q];
                     double d2r = x2r - s2r[q], d2i = x2i - s2i[q];
@@ -591,8 +594,9 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_sym(const int* __restrict__ item
                     }
                 }
                 // hand the column sum to the lane that meets this source next
-                cr = __shfl(cr, (t + 1) & 63, 64);
-                ci = __shfl(ci, (t + 1) & 63, 64);
+                cr = __shfl(cr, nxt, 64);
+                ci = __shfl(ci, nxt, 64);
+                if (++q >= L) q -= L;
             }
             if (t < cnt) {
                 cplx* cc = Ccol + (j0 - pa0) + t;
@@ -605,10 +609,11 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_sym(const int* __restrict__ item
 }
 
 // Diagonal items (a == b, at most 64 points, series regime): the same
-// rotation within one tile.  Steps s = 1..32 pair lane l with point (l + s)
-// mod 64, which covers every unordered pair once (at s = 32 only lanes l < 32
-// work, since (l, l + 32) and (l + 32, l) are the same pair); a final shuffle
-// returns each travelling column sum to its own lane.
+// rotation within one tile of L points.  Steps s = 1..L/2 pair lane l with
+// point (l + s) mod L, which covers every unordered pair once (at s = L/2,
+// L even, only lanes l < L/2 work, since (l, l + L/2) and (l + L/2, l) are the
+// same pair); a final shuffle returns each travelling column sum to its own
+// lane.
 __global__ __launch_bounds__(64) void k_h2d_p2p_diag(const int* __restrict__ items, const int* __restrict__ nterm,
                                                      P2PMap mp, TreeView tv, PointsView pv, double kappa)
 {
@@ -630,10 +635,11 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_diag(const int* __restrict__ ite
     double x1r = s1r[t & 63], x1i = s1i[t & 63], x2r = s2r[t & 63], x2i = s2i[t & 63];
     double wr = ssr[t & 63], wi = ssi[t & 63];
     double ar = 0.0, ai = 0.0, cr = 0.0, ci = 0.0;
-    for (int step = 1; step <= 32; ++step) {
-        // the column sum held here belongs to point (t + step) mod 64
-        int q = (t + step) & 63;
-        if (ok && q < cnt && (step < 32 || t < 32)) {
+    int L = cnt, nxt = t < L ? (t + 1 == L ? 0 : t + 1) : t;
+    int q = t + 1 < L ? t + 1 : 0;
+    for (int step = 1; 2 * step <= L; ++step) {
+        // the column sum held here belongs to point (t + step) mod L
+        if (ok && (2 * step < L || 2 * t < L)) {
             double d1r = x1r - s1r[q], d1i = x1i - s1i[q];
             double d2r = x2r - s2r[q], d2i = x2i - s2i[q];
             double sr = d1r * d1r - d1i * d1i + d2r * d2r - d2i * d2i;
@@ -646,12 +652,18 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_diag(const int* __restrict__ ite
                 ci += h.re * wi + h.im * wr;
             }
         }
-        cr = __shfl(cr, (t + 1) & 63, 64);
-        ci = __shfl(ci, (t + 1) & 63, 64);
+        cr = __shfl(cr, nxt, 64);
+        ci = __shfl(ci, nxt, 64);
+        if (++q >= L) q -= L;
     }
-    // after 32 hand-offs lane u holds the sum of point (u + 33) mod 64
-    cr = __shfl(cr, (t + 31) & 63, 64);
-    ci = __shfl(ci, (t + 31) & 63, 64);
+    // after L/2 hand-offs lane u holds the sum of point (u + L/2 + 1) mod L
+    int src = t;
+    if (t < L) {
+        src = t - L / 2 - 1;
+        while (src < 0) src += L;
+    }
+    cr = __shfl(cr, src, 64);
+    ci = __shfl(ci, src, 64);
     if (ok) mp.C[mp.coff[e] + t] = mk(ar + cr, ai + ci);
 }
 

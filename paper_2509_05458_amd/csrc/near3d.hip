@@ -9,12 +9,13 @@
 // C[partner e] (columns), a diagonal item writes C[e].  A final pass adds, per
 // target, its entries' partials in list order, so results are reproducible.
 //
-// Inside an item a wavefront holds 64 targets (one per lane) and a tile of 64
-// sources in LDS.  At step s lane l pairs its target with source (l + s) mod
-// 64: the row sum stays in the lane and the source's column sum travels with
-// the source, one lane down per step, so after 64 steps lane l holds the
-// column sum of source l.  A tile against itself takes steps 1..32 only (at
-// step 32 just lanes l < 32), which covers each unordered pair once.
+// Inside an item a wavefront holds up to 64 targets (one per lane) and a tile
+// of up to 64 sources in LDS.  With L the larger of the two counts, at step s
+// lane l pairs its target with source (l + s) mod L: the row sum stays in the
+// lane and the source's column sum travels with the source, one lane down per
+// step, so after L steps lane l holds the column sum of source l.  A tile
+// against itself takes steps 1..L/2 only (at step L/2 just lanes l < L/2 when
+// L is even), which covers each unordered pair once.
 //
 // Precision: FP64, or MIXED (differences formed in FP64 and cast to FP32, the
 // kernel in FP32, each tile's sums in FP32 and added in FP64).  In MIXED mode a
@@ -162,21 +163,30 @@ __device__ inline void load_tile(Tile& sh, const PointsView& pv, int j0, int cnt
     }
 }
 
-// One tile pair by rotation.  `steps` = 64 (distinct tiles) or 32 (a tile
-// against itself).  Row sums (ar, ai) accumulate in the lane; the column sums
-// are returned in (cr, ci) at their home lane.
+// One tile pair by rotation with period L = max(R, C) (R targets in lanes
+// 0..R-1, C sources in the tile): at step s lane l < L pairs its target with
+// source (l + s) mod L and hands its travelling column sum to lane l - 1
+// (mod L), so after L steps lane l holds the column sum of source l.  A tile
+// against itself (R = C = L) takes steps 1..L/2, at step L/2 (L even) only
+// lanes l < L/2, which covers each unordered pair once; a last shuffle
+// returns each column sum to its home lane.  Row sums (ar, ai) accumulate in
+// the lane.
 template <int KIND, int PREC>
-__device__ inline void tile_pair(const Tile& sh, int cnt_s, bool tok, const double* x, const double* y,
-                                 double wr, double wi, double kappa, int steps, double& ar, double& ai,
+__device__ inline void tile_pair(const Tile& sh, int R, int C, bool self, const double* x, const double* y,
+                                 double wr, double wi, double kappa, double& ar, double& ai,
                                  double& cr_out, double& ci_out)
 {
     typedef typename Acc<PREC>::T T;
     int t = threadIdx.x;
+    int L = max(R, C);
+    int nxt = t < L ? (t + 1 == L ? 0 : t + 1) : t;
+    int s0 = self ? 1 : 0, s1 = self ? L / 2 : L - 1;
     T rr = 0, ri = 0, cr = 0, ci = 0;
     T fwr = (T)wr, fwi = (T)wi;
-    for (int step = (steps == 32 ? 1 : 0); step < (steps == 32 ? 33 : 64); ++step) {
-        int q = (t + step) & 63;
-        bool on = tok && q < cnt_s && (steps != 32 || step < 32 || t < 32);
+    int q = t + s0;
+    if (q >= L) q -= L;
+    for (int step = s0; step <= s1; ++step) {
+        bool on = t < R && q < C && (!self || 2 * step < L || 2 * t < L);
         if (on) {
             double dr[3], di[3];
             for (int d = 0; d < 3; ++d) {
@@ -191,13 +201,19 @@ __device__ inline void tile_pair(const Tile& sh, int cnt_s, bool tok, const doub
             cr += gr * fwr - gi * fwi;
             ci += gr * fwi + gi * fwr;
         }
-        cr = __shfl(cr, (t + 1) & 63, 64);
-        ci = __shfl(ci, (t + 1) & 63, 64);
+        cr = __shfl(cr, nxt, 64);
+        ci = __shfl(ci, nxt, 64);
+        if (++q >= L) q -= L;
     }
-    if (steps == 32) {
-        // after 32 hand-offs lane u holds the column sum of point (u + 33) mod 64
-        cr = __shfl(cr, (t + 31) & 63, 64);
-        ci = __shfl(ci, (t + 31) & 63, 64);
+    if (self) {
+        // after L/2 hand-offs lane u holds the column sum of point (u + L/2 + 1) mod L
+        int src = t;
+        if (t < L) {
+            src = t - L / 2 - 1;
+            while (src < 0) src += L;
+        }
+        cr = __shfl(cr, src, 64);
+        ci = __shfl(ci, src, 64);
     }
     ar += (double)rr;
     ai += (double)ri;
@@ -234,7 +250,7 @@ __global__ __launch_bounds__(64) void k_near3_pair(const int* __restrict__ items
             load_tile(sh, pv, j0, cnt, t);
             __syncthreads();
             double cr, ci;
-            tile_pair<KIND, PREC>(sh, cnt, tok, x, y, wr, wi, kappa, 64, ar, ai, cr, ci);
+            tile_pair<KIND, PREC>(sh, min(64, pb1 - i0), cnt, false, x, y, wr, wi, kappa, ar, ai, cr, ci);
             if (t < cnt) {
                 cplx* cc = Ccol + (j0 - pa0) + t;
                 if (i0 == pb0) *cc = mk(cr, ci);
@@ -276,7 +292,7 @@ __global__ __launch_bounds__(64) void k_near3_diag(const int* __restrict__ items
             __syncthreads();
             double cr, ci;
             bool self = j0 == i0;
-            tile_pair<KIND, PREC>(sh, cnt, tok, x, y, wr, wi, kappa, self ? 32 : 64, ar, ai, cr, ci);
+            tile_pair<KIND, PREC>(sh, min(64, p1 - i0), cnt, self, x, y, wr, wi, kappa, ar, ai, cr, ci);
             if (self) {
                 ar += cr;   // the column sums of the same tile are this lane's own point
                 ai += ci;
