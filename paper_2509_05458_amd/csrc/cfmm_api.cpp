@@ -87,7 +87,6 @@ struct cfmm_plan_s {
     H2DNear near2{};              // 2D near-field work items and partial sums
     Near3Work near3{};            // 3D near-field work items and partial sums
     int64_t near_evals = -1;      // kernel evaluations per eval (-1: one per ordered pair)
-    int off_m2p = 0, n_m2p = 0;   // leaves with List-3 boxes
     std::vector<int> p2l_h;       // host copy of the P2L work list (level order)
     std::vector<int> p2m_h;       // host copy of the P2M work list (level order)
     // plan-time translation operators (2D Helmholtz)
@@ -120,7 +119,7 @@ struct cfmm_plan_s {
     int* d_m2p_owner = nullptr;
     int64_t* d_m2p_poff = nullptr;
     cplx* d_m2p_part = nullptr;
-    int n_m2p3 = 0;
+    int n_m2p3 = 0, m2p_pmax = 0;
     M2PParts m2p_parts() const { return M2PParts{n_m2p3, d_m2p_owner, d_m2p_poff, d_m2p_part}; }
     int64_t ecount = 0;
     int64_t info[16];
@@ -593,11 +592,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         for (int b = t.lvl_beg[l]; b < t.lvl_beg[l + 1]; ++b) work.push_back(b);
         p->l2l_cnt[l] = (int)work.size() - p->l2l_off[l];
     }
-    p->off_m2p = (int)work.size();
-    for (int b = 0; b < nb; ++b)
-        if (t.nchild[b] == 0 && t.level[b] >= top && t.off[2][b + 1] > t.off[2][b]) work.push_back(b);
-    p->n_m2p = (int)work.size() - p->off_m2p;
-    if (dim == 3 && !t.idx[2].empty()) {
+    if (!t.idx[2].empty()) {
         int n3 = (int)t.idx[2].size();
         std::vector<int> owner(n3);
         std::vector<int64_t> poff(n3 + 1, 0);
@@ -605,6 +600,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
             for (int e = t.off[2][b]; e < t.off[2][b + 1]; ++e) {
                 owner[e] = b;
                 poff[e + 1] = t.pend[b] - t.pbeg[b];
+                p->m2p_pmax = std::max(p->m2p_pmax, p->P[t.level[t.idx[2][e]]]);
             }
         for (int e = 0; e < n3; ++e) poff[e + 1] += poff[e];
         if ((rc = upload(p, &p->d_m2p_owner, owner)) || (rc = upload(p, &p->d_m2p_poff, poff)) ||
@@ -971,7 +967,7 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         for (int l = top + 1; l < nlev; ++l)
             HIPCHK(h2d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], 2 * p->P[l] + 1, tv, p->ops(), p->d_local, st));
         HIPCHK(mark(5));
-        HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, W + p->off_m2p, p->n_m2p, top, std::max(1, p->pmax), tv,
+        HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, p->m2p_parts(), p->m2p_pmax, top, std::max(1, p->pmax), tv,
                             pv, p->kappa, p->d_poff, p->d_pvals, p->d_mpole, p->d_local, p->d_ufar, st));
         HIPCHK(mark(6));
         HIPCHK(h2d_p2p(p->near2, W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out, st));

@@ -393,6 +393,7 @@ __global__ __launch_bounds__(256) void k_h2d_l2l(const int* __restrict__ boxes, 
 __global__ __launch_bounds__(64) void k_h2d_l2p(const int* __restrict__ leaves, int top, int chunk_cap,
                                                 TreeView tv, const int64_t* __restrict__ poff,
                                                 const cplx* __restrict__ vals, const cplx* __restrict__ local,
+                                                const int64_t* __restrict__ poff3, const cplx* __restrict__ part,
                                                 cplx* __restrict__ ufar)
 {
     extern __shared__ cplx rowv[];
@@ -421,46 +422,46 @@ __global__ __launch_bounds__(64) void k_h2d_l2p(const int* __restrict__ leaves, 
                 cplx w = L[k] * V[-k];
                 u += (k & 1) ? -w : w;
             }
+            for (int e = tv.l3off[b]; e < tv.l3off[b + 1]; ++e) u += part[poff3[e] + c0 + t - p0];
             ufar[c0 + t] = u;
         }
     }
 }
 
-// M2P over List 3, only for the leaves that have List-3 boxes; adds to the
-// far field L2P wrote.  Each thread's Hankel sequence sits in its LDS column.
-__global__ void k_h2d_m2p(const int* __restrict__ leaves, TreeView tv, PointsView pv, double kappa,
-                          const cplx* __restrict__ mpole, cplx* __restrict__ ufar)
+// M2P by List-3 entries: entry e = (leaf owner[e], box l3idx[e]) evaluates the
+// box's multipole at the leaf's points into part[poff[e] + i - pbeg], one
+// block per entry.  Each thread's Hankel sequence sits in its LDS column.
+__global__ void k_h2d_m2p_part(const int* __restrict__ owner, const int64_t* __restrict__ poff, TreeView tv,
+                               PointsView pv, double kappa, const cplx* __restrict__ mpole,
+                               cplx* __restrict__ part)
 {
     extern __shared__ cplx rows[];      // rows[k * blockDim.x + thread]
-    int b = leaves[blockIdx.x];
+    int e = blockIdx.x;
+    int b = owner[e], a = tv.l3idx[e];
     int nbx = tv.nbox, st = blockDim.x, t = threadIdx.x;
     int64_t n = pv.n;
-    int p0 = tv.pbeg[b], p1 = tv.pend[b];
-    for (int i = p0 + t; i < p1; i += st) {
-        cplx u = mk(0.0, 0.0);
-        cplx x1 = mk(pv.xre[i], pv.xim[i]), x2 = mk(pv.xre[n + i], pv.xim[n + i]);
-        for (int e = tv.l3off[b]; e < tv.l3off[b + 1]; ++e) {
-            int a = tv.l3idx[e];
-            int la = tv.level[a];
-            int Pa = tv.P[la];
-            double ra = tv.rs[la];
-            cplx Y1 = x1 - mk(tv.cre[a], tv.cim[a]), Y2 = x2 - mk(tv.cre[nbx + a], tv.cim[nbx + a]);
-            cplx bp, bm;
-            hcore2(Y1, Y2, kappa, ra, Pa, c_ghx, c_ghw, rows + t, st, &bp, &bm);
-            const cplx* M = mpole + tv.eoff[a] + Pa;
-            cplx pp = mk(1.0, 0.0), pm = mk(1.0, 0.0);
-            for (int k = 0; k <= Pa; ++k) {
-                cplx term = pp * M[k];
-                if (k > 0) {
-                    cplx v = pm * M[-k];
-                    term += (k & 1) ? -v : v;
-                }
-                u += rows[k * st + t] * term;
-                pp = pp * bp;
-                pm = pm * bm;
+    int la = tv.level[a];
+    int Pa = tv.P[la];
+    double ra = tv.rs[la];
+    cplx ca1 = mk(tv.cre[a], tv.cim[a]), ca2 = mk(tv.cre[nbx + a], tv.cim[nbx + a]);
+    const cplx* M = mpole + tv.eoff[a] + Pa;
+    cplx* o = part + poff[e] - tv.pbeg[b];
+    for (int i = tv.pbeg[b] + t; i < tv.pend[b]; i += st) {
+        cplx Y1 = mk(pv.xre[i], pv.xim[i]) - ca1, Y2 = mk(pv.xre[n + i], pv.xim[n + i]) - ca2;
+        cplx bp, bm;
+        hcore2(Y1, Y2, kappa, ra, Pa, c_ghx, c_ghw, rows + t, st, &bp, &bm);
+        cplx pp = mk(1.0, 0.0), pm = mk(1.0, 0.0), u = mk(0.0, 0.0);
+        for (int k = 0; k <= Pa; ++k) {
+            cplx term = pp * M[k];
+            if (k > 0) {
+                cplx v = pm * M[-k];
+                term += (k & 1) ? -v : v;
             }
+            u += rows[k * st + t] * term;
+            pp = pp * bp;
+            pm = pm * bm;
         }
-        ufar[i] += u;
+        o[i] = u;
     }
 }
 
@@ -829,19 +830,22 @@ hipError_t h2d_l2l(const int* boxes, int nb, int ncoef, const TreeView& tv, cons
     return hipGetLastError();
 }
 
-hipError_t h2d_leaf_far(const int* leaves, int nleaf, const int* m2p_leaves, int nm2p, int top, int pmax,
+hipError_t h2d_leaf_far(const int* leaves, int nleaf, const M2PParts& m2p, int m2p_pmax, int top, int pmax,
                         const TreeView& tv, const PointsView& pv, double kappa, const int64_t* poff,
                         const cplx* vals, const cplx* mpole, const cplx* local, cplx* ufar, hipStream_t st)
 {
+    if (m2p.n > 0) {
+        int threads = 64;
+        size_t lds = (size_t)threads * (m2p_pmax + 1) * sizeof(cplx);
+        k_h2d_m2p_part<<<m2p.n, threads, lds, st>>>(m2p.owner, m2p.poff, tv, pv, kappa, mpole, m2p.part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (nleaf > 0) {
         // LDS for at least one point at the largest P, up to 32 KB
         int cap = 2048 > 2 * pmax + 1 ? 2048 : 2 * pmax + 1;
-        k_h2d_l2p<<<nleaf, 64, sizeof(cplx) * (size_t)cap, st>>>(leaves, top, cap, tv, poff, vals, local, ufar);
-    }
-    if (nm2p > 0) {
-        int threads = 64;
-        size_t lds = (size_t)threads * (pmax + 1) * sizeof(cplx);
-        k_h2d_m2p<<<nm2p, threads, lds, st>>>(m2p_leaves, tv, pv, kappa, mpole, ufar);
+        k_h2d_l2p<<<nleaf, 64, sizeof(cplx) * (size_t)cap, st>>>(leaves, top, cap, tv, poff, vals, local, m2p.poff,
+                                                                 m2p.part, ufar);
     }
     return hipGetLastError();
 }

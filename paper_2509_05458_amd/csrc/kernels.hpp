@@ -97,7 +97,7 @@ hipError_t h2d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const Po
                    double kappa, cplx* local, hipStream_t st);
 hipError_t h2d_l2l(const int* boxes, int nb, int ncoef, const TreeView& tv, const H2DOps& ops, cplx* local,
                    hipStream_t st);
-hipError_t h2d_leaf_far(const int* leaves, int nleaf, const int* m2p_leaves, int nm2p, int top, int pmax,
+hipError_t h2d_leaf_far(const int* leaves, int nleaf, const M2PParts& m2p, int m2p_pmax, int top, int pmax,
                         const TreeView& tv, const PointsView& pv, double kappa, const int64_t* poff,
                         const cplx* vals, const cplx* mpole, const cplx* local, cplx* ufar, hipStream_t st);
 // Near-field work of the 2D Helmholtz plan: List-1 entries as work items
