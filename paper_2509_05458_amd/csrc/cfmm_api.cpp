@@ -93,8 +93,6 @@ struct cfmm_plan_s {
     int64_t *d_o_m2l = nullptr, *d_o_tr = nullptr;
     cplx *d_g_m2l = nullptr, *d_g_m2m = nullptr, *d_g_l2l = nullptr;
     double* d_pw = nullptr;
-    int64_t* d_poff = nullptr;   // per box: offset of its points' expansion values
-    cplx* d_pvals = nullptr;
     double *d_io_in = nullptr, *d_io_out = nullptr;       // staging for host pointers
     // 3D Helmholtz: per-level kappa w and scale; translation stages and chunks
     struct H3Chunk {
@@ -773,7 +771,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         p->near3.C = dC;
     }
     if ((rc = upload(p, &p->d_work, work))) return rc;
-    int64_t gsz = 0, tsz = 0, psz = 0;
+    int64_t gsz = 0, tsz = 0;
     if (h2d) {
     // -------- translation operators (generators of M2L, M2M, L2L)
     std::vector<int64_t> o_m2l(npairs), o_tr(nb, -1);
@@ -794,17 +792,8 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         (rc = upload(p, &p->d_pw, pw)) || (rc = p->alloc(&p->d_g_m2l, gsz)) ||
         (rc = p->alloc(&p->d_g_m2m, tsz)) || (rc = p->alloc(&p->d_g_l2l, tsz)))
         return rc;
-    std::vector<int64_t> poff(nb, -1);
-    for (int b = 0; b < nb; ++b)
-        if (t.nchild[b] == 0 && t.level[b] >= top) {
-            poff[b] = psz;
-            psz += (int64_t)(t.pend[b] - t.pbeg[b]) * (2 * p->P[t.level[b]] + 1);
-        }
-    if ((rc = upload(p, &p->d_poff, poff)) || (rc = p->alloc(&p->d_pvals, psz))) return rc;
     {
         TreeView tv = p->view();
-        HIPCHK(h2d_gen_pts(p->d_work + p->off_p2m, p->n_p2m, tv, p->pview(), p->kappa, p->d_poff,
-                           p->d_pvals, st));
         HIPCHK(h2d_gen_ops(p->d_work + off_pairb, npairs, p->d_work + off_tr, n_tr, tv, p->kappa,
                            p->d_o_m2l, p->d_g_m2l, p->d_o_tr, p->d_g_m2m, p->d_g_l2l, st));
     }
@@ -936,7 +925,16 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
     HIPCHK(launch_gather_density(sig, p->d_perm, n, p->d_sre, p->d_sim, st));
     HIPCHK(mark(1));
     if (p->dim == 2) {
-        HIPCHK(h2d_p2m(W + p->off_p2m, p->n_p2m, tv, pv, p->d_poff, p->d_pvals, p->d_mpole, st));
+        {
+            // the P2M list is in level order; one launch per level sizes its LDS by that level's P
+            int k0 = 0;
+            while (k0 < p->n_p2m) {
+                int l = t.level[p->p2m_h[k0]], k1 = k0;
+                while (k1 < p->n_p2m && t.level[p->p2m_h[k1]] == l) ++k1;
+                HIPCHK(h2d_p2m(W + p->off_p2m + k0, k1 - k0, p->P[l], tv, pv, p->kappa, p->d_mpole, st));
+                k0 = k1;
+            }
+        }
         HIPCHK(mark(2));
         for (int l = nlev - 2; l >= top; --l)
             HIPCHK(h2d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], 2 * p->P[l] + 1, tv, p->ops(), p->d_mpole, st));
@@ -967,8 +965,8 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         for (int l = top + 1; l < nlev; ++l)
             HIPCHK(h2d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], 2 * p->P[l] + 1, tv, p->ops(), p->d_local, st));
         HIPCHK(mark(5));
-        HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, p->m2p_parts(), p->m2p_pmax, top, std::max(1, p->pmax), tv,
-                            pv, p->kappa, p->d_poff, p->d_pvals, p->d_mpole, p->d_local, p->d_ufar, st));
+        HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, p->m2p_parts(), p->m2p_pmax, top, tv, pv, p->kappa,
+                            p->d_mpole, p->d_local, p->d_ufar, st));
         HIPCHK(mark(6));
         HIPCHK(h2d_p2p(p->near2, W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out, st));
     } else if (p->kernel == CFMM_HELMHOLTZ) {

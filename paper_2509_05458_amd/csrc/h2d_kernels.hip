@@ -23,6 +23,8 @@ namespace cfmm {
 
 __constant__ double c_ghx[kGHHalf];
 __constant__ double c_ghw[kGHHalf];
+constexpr int kRcp = 512;
+__constant__ double c_rcp[kRcp];     // 1/m, c_rcp[0] = 0
 
 static double h_ghx[kGHHalf], h_ghw[kGHHalf];
 static bool h_gh_ready = false;
@@ -39,8 +41,12 @@ hipError_t h2d_init_tables(int device)
 {
     (void)device;
     host_gh();
+    static double rcp[kRcp];
+    rcp[0] = 0.0;
+    for (int m = 1; m < kRcp; ++m) rcp[m] = 1.0 / m;
     hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_ghx), h_ghx, sizeof(h_ghx));
     if (e != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_rcp), rcp, sizeof(rcp))) != hipSuccess) return e;
     return hipMemcpyToSymbol(HIP_SYMBOL(c_ghw), h_ghw, sizeof(h_ghw));
 }
 
@@ -57,67 +63,174 @@ __device__ inline int iabs_(int a) { return a < 0 ? -a : a; }
 // ------------------------------------------------------------------ P2M
 constexpr int kChunk = 16;
 
-// Per-point expansion values, built once per plan for every point of a leaf
-// that carries expansions (Y = y - c, the leaf's complexified centre):
-//   v[n + P] = J_n(kappa rho_Y) e^{-in phi_Y} / r^|n|,  n = -P..P.
-// P2M is M_n = sum_j sigma_j v_n(j); L2P reuses them since
+// Regular values at a point Y = y - c of a box with expansion length P and
+// scale r (Sec. 4.2):
+//   v_n = J_n(kappa rho_Y) e^{-in phi_Y} / r^|n|,  n = -P..P,
+// with v_n = s_n bm^n / n! and v_{-n} = (-1)^n s_n bp^n / n! for n >= 0, where
+// s_n = n! J_n(z)/(z/2)^n (z = kappa rho_Y), an entire function of
+// rho_Y^2, comes from its power series at P and P+1 and the stable downward
+// recurrence s_{n-1} = s_n + qq s_{n+1} / (n(n+1)), qq = -z^2/4, and
+// bp, bm = kappa (y1 +- i y2) / (2r).  For |qq| > P + 1 the values come from
+// Miller's recurrence for J_n (jcore2).  Reciprocals of integers come from a
+// table.  P2M is M_n = sum_j sigma_j v_n(j), and L2P uses
 // J_n(kappa rho_X) e^{in phi_X} / r^|n| = (-1)^n v_{-n} at the same point.
-// Within a leaf the values are stored point-major, v_n(j) at j * (2P+1) + n + P.
-__global__ void k_h2d_gen_pts(const int* __restrict__ leaves, int nleaf, TreeView tv, PointsView pv,
-                              double kappa, const int64_t* __restrict__ poff, cplx* __restrict__ vals)
+__device__ inline cplx series_s(cplx qq, int n)
 {
-    int li = blockIdx.x;
-    if (li >= nleaf) return;
-    int b = leaves[li];
-    int l = tv.level[b];
-    int P = tv.P[l], nc = 2 * P + 1;
-    double r = tv.rs[l];
-    int nbx = tv.nbox;
-    int64_t n = pv.n;
-    cplx c1 = mk(tv.cre[b], tv.cim[b]), c2 = mk(tv.cre[nbx + b], tv.cim[nbx + b]);
-    for (int j = tv.pbeg[b] + threadIdx.x; j < tv.pend[b]; j += blockDim.x) {
-        cplx y1 = mk(pv.xre[j] - c1.re, pv.xim[j] - c1.im);
-        cplx y2 = mk(pv.xre[n + j] - c2.re, pv.xim[n + j] - c2.im);
-        cplx* v = vals + poff[b] + (int64_t)(j - tv.pbeg[b]) * nc + P;
-        cplx bp, bm;
-        bool fact;
-        // core sequence into v[0..P], then expand: v[n] uses e^{-i phi} (bm), v[-n] e^{+i phi}
-        jcore2(y1, y2, kappa, r, P, v, 1, &bp, &bm, &fact);
-        cplx pp = mk(1.0, 0.0), pm = mk(1.0, 0.0);
-        for (int k = 1; k <= P; ++k) {
-            double f = fact ? 1.0 / k : 1.0;
-            pp = pp * bp * f;
-            pm = pm * bm * f;
-            cplx s = v[k];
-            v[k] = s * pm;
-            cplx w = s * pp;
-            v[-k] = (k & 1) ? -w : w;
+    cplx term = mk(1.0, 0.0), sum = term;
+    for (int j = 1; j < 200; ++j) {
+        term = (term * qq) * (c_rcp[j] * c_rcp[n + j]);
+        sum += term;
+        if (cabs2(term) < 1e-36 * cabs2(sum)) break;
+    }
+    return sum;
+}
+
+// v[n * st], n = -P..P, for Y = (y1, y2); half = kappa / (2r)
+__device__ inline void regular_values(cplx y1, cplx y2, double kappa, double half, double r, int P, cplx* v,
+                                      int st)
+{
+    cplx zp = mk(y1.re - y2.im, y1.im + y2.re);   // y1 + i y2
+    cplx zm = mk(y1.re + y2.im, y1.im - y2.re);   // y1 - i y2
+    cplx qq = (-0.25 * kappa * kappa) * (y1 * y1 + y2 * y2);
+    cplx bp, bm;
+    bool fact;
+    if (cabs2(qq) <= (double)(P + 1) * (double)(P + 1)) {
+        cplx hi = series_s(qq, P + 1), cur = series_s(qq, P);
+        v[P * st] = cur;
+        for (int k = P; k >= 1; --k) {
+            cplx lo = cur + (qq * hi) * (c_rcp[k] * c_rcp[k + 1]);
+            v[(k - 1) * st] = lo;
+            hi = cur;
+            cur = lo;
         }
+        bp = half * zp;
+        bm = half * zm;
+        fact = true;
+    } else {
+        jcore2(y1, y2, kappa, r, P, v, st, &bp, &bm, &fact);
+    }
+    // v[0..P] holds s_n; expand in place: v[n] = s_n bm^n/n!, v[-n] = (-1)^n s_n bp^n/n!
+    cplx pp = mk(1.0, 0.0), pm = mk(1.0, 0.0);
+    for (int k = 1; k <= P; ++k) {
+        double f = fact ? c_rcp[k] : 1.0;
+        pp = (pp * bp) * f;
+        pm = (pm * bm) * f;
+        cplx sk = v[k * st];
+        v[k * st] = sk * pm;
+        cplx w = sk * pp;
+        v[-k * st] = (k & 1) ? -w : w;
     }
 }
 
-// one wavefront per leaf, lane = coefficient
-__global__ __launch_bounds__(256) void k_h2d_p2m(const int* __restrict__ leaves, int nleaf, TreeView tv,
-                                                 PointsView pv, const int64_t* __restrict__ poff,
-                                                 const cplx* __restrict__ vals, cplx* __restrict__ mpole)
+// u = sum_n L_n (-1)^n v_{-n} = sum_k s_k (L_k bp^k + (-1)^k L_{-k} bm^k) / k!
+// (k = 0 once), accumulated by Horner in bp and bm while the downward
+// recurrence produces s_k.  L points at L_0.
+__device__ inline cplx l2p_value(cplx y1, cplx y2, double kappa, double half, double r, int P,
+                                 const cplx* __restrict__ L)
 {
-    int lane = threadIdx.x & 63;
-    int li = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (li >= nleaf) return;
-    int b = leaves[li];
-    int P = tv.P[tv.level[b]], nc = 2 * P + 1;
-    int p0 = tv.pbeg[b], p1 = tv.pend[b];
-    const cplx* V = vals + poff[b];
-    for (int m0 = 0; m0 < nc; m0 += 64) {
-        int mi = m0 + lane;
-        if (mi >= nc) break;
-        cplx acc = mk(0.0, 0.0);
-        for (int j = p0; j < p1; ++j) {
-            cplx sg = mk(pv.sre[j], pv.sim[j]);
-            acc += V[(int64_t)(j - p0) * nc + mi] * sg;
+    cplx zp = mk(y1.re - y2.im, y1.im + y2.re);
+    cplx zm = mk(y1.re + y2.im, y1.im - y2.re);
+    cplx qq = (-0.25 * kappa * kappa) * (y1 * y1 + y2 * y2);
+    if (cabs2(qq) <= (double)(P + 1) * (double)(P + 1)) {
+        cplx bp = half * zp, bm = half * zm;
+        cplx hi = series_s(qq, P + 1), cur = series_s(qq, P);
+        // H+_k = a_k + bp/(k+1) H+_{k+1},  H-_k = c_k + bm/(k+1) H-_{k+1} (k >= 1)
+        cplx Hp = L[P] * cur;
+        cplx Hm = (P & 1) ? -(L[-P] * cur) : L[-P] * cur;
+        if (P == 0) Hm = mk(0.0, 0.0);
+        for (int k = P; k >= 1; --k) {
+            cplx lo = cur + (qq * hi) * (c_rcp[k] * c_rcp[k + 1]);   // s_{k-1}
+            double f = c_rcp[k];
+            Hp = (bp * Hp) * f + L[k - 1] * lo;
+            if (k >= 2) {
+                cplx c = L[-(k - 1)] * lo;
+                Hm = (bm * Hm) * f + (((k - 1) & 1) ? -c : c);
+            }
+            hi = cur;
+            cur = lo;
         }
-        mpole[tv.eoff[b] + mi] = acc;
+        return P >= 1 ? Hp + bm * Hm : Hp;
     }
+    // large argument (rare): J_k by Miller's backward recurrence, summed by
+    // Horner as it runs and normalised at the end as in jn_miller; bases
+    // e^{+-i phi} / r
+    cplx rho = csqrt_p(y1 * y1 + y2 * y2);
+    cplx z = kappa * rho;
+    cplx bp = cdiv(zp, rho) * (1.0 / r), bm = cdiv(zm, rho) * (1.0 / r);
+    cplx iz = cinv(z);
+    double az = sqrt(cabs2(z));
+    double mx = az > P ? az : (double)P;
+    int N = (int)mx + 30 + (int)(10.0 * cbrt(mx));
+    bool up = z.im > 0.0;
+    cplx fnp1 = mk(0.0, 0.0), fn = mk(1e-250, 0.0), norm = mk(0.0, 0.0);
+    cplx Hp = mk(0.0, 0.0), Hm = mk(0.0, 0.0);
+    for (int k = N; k >= 0; --k) {
+        if (k <= P) {
+            Hp = bp * Hp + L[k] * fn;
+            if (k >= 1) {
+                cplx c = L[-k] * fn;
+                Hm = bm * Hm + ((k & 1) ? -c : c);
+            }
+        }
+        if (k == 0) {
+            norm += fn;
+        } else {
+            int m = k & 3;
+            cplx ph;
+            if (m == 0) ph = mk(1.0, 0.0);
+            else if (m == 2) ph = mk(-1.0, 0.0);
+            else if ((m == 1) != up) ph = mk(0.0, 1.0);
+            else ph = mk(0.0, -1.0);
+            norm += 2.0 * (ph * fn);
+            cplx fnm1 = (2.0 * k) * (iz * fn) - fnp1;
+            fnp1 = fn;
+            fn = fnm1;
+            if (cabs2(fn) > 1e280) {
+                const double sc = 1e-140;
+                fn *= sc; fnp1 *= sc; norm *= sc; Hp *= sc; Hm *= sc;
+            }
+        }
+    }
+    cplx target = up ? cexp_(mk(z.im, -z.re)) : cexp_(mk(-z.im, z.re));
+    return cdiv(target, norm) * (Hp + bm * Hm);
+}
+
+// P2M: one workgroup of 64 per leaf; per chunk of up to 64 points each thread
+// writes its point's values to an LDS row (odd row length, so the rows of
+// neighbouring threads fall in different banks), then lane m sums sigma v_m
+// over the chunk for its coefficients.
+__global__ __launch_bounds__(64) void k_h2d_p2m(const int* __restrict__ leaves, int nleaf, TreeView tv,
+                                                PointsView pv, double kappa, cplx* __restrict__ mpole)
+{
+    extern __shared__ cplx vv[];          // [64][2P+1] (point-major), then sigma[64]
+    int b = leaves[blockIdx.x];
+    int l = tv.level[b];
+    int P = tv.P[l], nc = 2 * P + 1;
+    double r = tv.rs[l], half = 0.5 * kappa / r;
+    int nbx = tv.nbox, t = threadIdx.x;
+    int64_t n = pv.n;
+    cplx* sg = vv + (size_t)nc * 64;
+    cplx c1 = mk(tv.cre[b], tv.cim[b]), c2 = mk(tv.cre[nbx + b], tv.cim[nbx + b]);
+    cplx acc0 = mk(0.0, 0.0), acc1 = mk(0.0, 0.0);
+    int p0 = tv.pbeg[b], p1 = tv.pend[b];
+    for (int j0 = p0; j0 < p1; j0 += 64) {
+        int cnt = min(64, p1 - j0);
+        __syncthreads();
+        if (t < cnt) {
+            int j = j0 + t;
+            cplx y1 = mk(pv.xre[j] - c1.re, pv.xim[j] - c1.im);
+            cplx y2 = mk(pv.xre[n + j] - c2.re, pv.xim[n + j] - c2.im);
+            regular_values(y1, y2, kappa, half, r, P, vv + (size_t)t * nc + P, 1);
+            sg[t] = mk(pv.sre[j], pv.sim[j]);
+        }
+        __syncthreads();
+        if (t < nc)
+            for (int q = 0; q < cnt; ++q) cfma(acc0, vv[(size_t)q * nc + t], sg[q]);
+        if (t + 64 < nc)
+            for (int q = 0; q < cnt; ++q) cfma(acc1, vv[(size_t)q * nc + t + 64], sg[q]);
+    }
+    if (t < nc) mpole[tv.eoff[b] + t] = acc0;
+    if (t + 64 < nc) mpole[tv.eoff[b] + t + 64] = acc1;
 }
 
 // ------------------------------------------------------ operator generators
@@ -390,13 +503,14 @@ __global__ __launch_bounds__(256) void k_h2d_l2l(const int* __restrict__ boxes, 
 // leaves coarser than the top level).  The leaf's per-point values are
 // contiguous (point-major), so a chunk of points is staged into LDS with
 // coalesced loads and each thread then reads its own point's row there.
-__global__ __launch_bounds__(64) void k_h2d_l2p(const int* __restrict__ leaves, int top, int chunk_cap,
-                                                TreeView tv, const int64_t* __restrict__ poff,
-                                                const cplx* __restrict__ vals, const cplx* __restrict__ local,
+// ------------------------------------------------------------------ L2P
+// One thread per target of a leaf: the leaf's local expansion by l2p_value,
+// plus the leaf's List-3 parts in list order.
+__global__ __launch_bounds__(64) void k_h2d_l2p(const int* __restrict__ leaves, int top, TreeView tv,
+                                                PointsView pv, double kappa, const cplx* __restrict__ local,
                                                 const int64_t* __restrict__ poff3, const cplx* __restrict__ part,
                                                 cplx* __restrict__ ufar)
 {
-    extern __shared__ cplx rowv[];
     int b = leaves[blockIdx.x];
     int l = tv.level[b];
     int p0 = tv.pbeg[b], p1 = tv.pend[b];
@@ -405,26 +519,18 @@ __global__ __launch_bounds__(64) void k_h2d_l2p(const int* __restrict__ leaves, 
         for (int i = p0 + t; i < p1; i += blockDim.x) ufar[i] = mk(0.0, 0.0);
         return;
     }
-    int P = tv.P[l], nc = 2 * P + 1;
-    int chunk = min(chunk_cap / nc, (int)blockDim.x);
+    int P = tv.P[l];
+    double r = tv.rs[l], half = 0.5 * kappa / r;
+    int nbx = tv.nbox;
+    int64_t n = pv.n;
+    cplx c1 = mk(tv.cre[b], tv.cim[b]), c2 = mk(tv.cre[nbx + b], tv.cim[nbx + b]);
     const cplx* L = local + tv.eoff[b] + P;
-    for (int c0 = p0; c0 < p1; c0 += chunk) {
-        int cnt = min(chunk, p1 - c0);
-        const cplx* src = vals + poff[b] + (int64_t)(c0 - p0) * nc;
-        __syncthreads();
-        for (int e = t; e < cnt * nc; e += blockDim.x) rowv[e] = src[e];
-        __syncthreads();
-        if (t < cnt) {
-            // u = sum_n L_n (-1)^n v_{-n}
-            const cplx* V = rowv + t * nc + P;
-            cplx u = mk(0.0, 0.0);
-            for (int k = -P; k <= P; ++k) {
-                cplx w = L[k] * V[-k];
-                u += (k & 1) ? -w : w;
-            }
-            for (int e = tv.l3off[b]; e < tv.l3off[b + 1]; ++e) u += part[poff3[e] + c0 + t - p0];
-            ufar[c0 + t] = u;
-        }
+    for (int i = p0 + t; i < p1; i += blockDim.x) {
+        cplx y1 = mk(pv.xre[i] - c1.re, pv.xim[i] - c1.im);
+        cplx y2 = mk(pv.xre[n + i] - c2.re, pv.xim[n + i] - c2.im);
+        cplx u = l2p_value(y1, y2, kappa, half, r, P, L);
+        for (int e = tv.l3off[b]; e < tv.l3off[b + 1]; ++e) u += part[poff3[e] + i - p0];
+        ufar[i] = u;
     }
 }
 
@@ -739,19 +845,17 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_final(const int* __restrict__ le
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t h2d_gen_pts(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                       double kappa, const int64_t* poff, cplx* vals, hipStream_t st)
+hipError_t h2d_p2m(const int* leaves, int nleaf, int pmax, const TreeView& tv, const PointsView& pv,
+                   double kappa, cplx* mpole, hipStream_t st)
 {
     if (nleaf <= 0) return hipSuccess;
-    k_h2d_gen_pts<<<nleaf, 64, 0, st>>>(leaves, nleaf, tv, pv, kappa, poff, vals);
-    return hipGetLastError();
-}
-
-hipError_t h2d_p2m(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                   const int64_t* poff, const cplx* vals, cplx* mpole, hipStream_t st)
-{
-    if (nleaf <= 0) return hipSuccess;
-    k_h2d_p2m<<<(nleaf + 3) / 4, 256, 0, st>>>(leaves, nleaf, tv, pv, poff, vals, mpole);
+    size_t lds = sizeof(cplx) * (size_t)(2 * pmax + 2) * 64;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_h2d_p2m, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    k_h2d_p2m<<<nleaf, 64, lds, st>>>(leaves, nleaf, tv, pv, kappa, mpole);
     return hipGetLastError();
 }
 
@@ -830,9 +934,9 @@ hipError_t h2d_l2l(const int* boxes, int nb, int ncoef, const TreeView& tv, cons
     return hipGetLastError();
 }
 
-hipError_t h2d_leaf_far(const int* leaves, int nleaf, const M2PParts& m2p, int m2p_pmax, int top, int pmax,
-                        const TreeView& tv, const PointsView& pv, double kappa, const int64_t* poff,
-                        const cplx* vals, const cplx* mpole, const cplx* local, cplx* ufar, hipStream_t st)
+hipError_t h2d_leaf_far(const int* leaves, int nleaf, const M2PParts& m2p, int m2p_pmax, int top,
+                        const TreeView& tv, const PointsView& pv, double kappa, const cplx* mpole,
+                        const cplx* local, cplx* ufar, hipStream_t st)
 {
     if (m2p.n > 0) {
         int threads = 64;
@@ -841,12 +945,8 @@ hipError_t h2d_leaf_far(const int* leaves, int nleaf, const M2PParts& m2p, int m
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (nleaf > 0) {
-        // LDS for at least one point at the largest P, up to 32 KB
-        int cap = 2048 > 2 * pmax + 1 ? 2048 : 2 * pmax + 1;
-        k_h2d_l2p<<<nleaf, 64, sizeof(cplx) * (size_t)cap, st>>>(leaves, top, cap, tv, poff, vals, local, m2p.poff,
-                                                                 m2p.part, ufar);
-    }
+    if (nleaf > 0)
+        k_h2d_l2p<<<nleaf, 64, 0, st>>>(leaves, top, tv, pv, kappa, local, m2p.poff, m2p.part, ufar);
     return hipGetLastError();
 }
 

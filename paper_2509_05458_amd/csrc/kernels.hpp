@@ -85,10 +85,8 @@ hipError_t h2d_init_tables(int device);
 hipError_t h2d_gen_ops(const int* pair_b, int npairs, const int* tr_boxes, int ntr,
                        const TreeView& tv, double kappa, const int64_t* o_m2l, cplx* g_m2l,
                        const int64_t* o_tr, cplx* g_m2m, cplx* g_l2l, hipStream_t st);
-hipError_t h2d_gen_pts(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                       double kappa, const int64_t* poff, cplx* vals, hipStream_t st);
-hipError_t h2d_p2m(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                   const int64_t* poff, const cplx* vals, cplx* mpole, hipStream_t st);
+hipError_t h2d_p2m(const int* leaves, int nleaf, int pmax, const TreeView& tv, const PointsView& pv,
+                   double kappa, cplx* mpole, hipStream_t st);
 hipError_t h2d_m2m(const int* boxes, int nb, int ncoef, const TreeView& tv, const H2DOps& ops, cplx* mpole,
                    hipStream_t st);
 hipError_t h2d_m2l(const int* boxes, int nlv, const int* box_off, const int* nb, const int* ncoef,
@@ -97,9 +95,9 @@ hipError_t h2d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const Po
                    double kappa, cplx* local, hipStream_t st);
 hipError_t h2d_l2l(const int* boxes, int nb, int ncoef, const TreeView& tv, const H2DOps& ops, cplx* local,
                    hipStream_t st);
-hipError_t h2d_leaf_far(const int* leaves, int nleaf, const M2PParts& m2p, int m2p_pmax, int top, int pmax,
-                        const TreeView& tv, const PointsView& pv, double kappa, const int64_t* poff,
-                        const cplx* vals, const cplx* mpole, const cplx* local, cplx* ufar, hipStream_t st);
+hipError_t h2d_leaf_far(const int* leaves, int nleaf, const M2PParts& m2p, int m2p_pmax, int top,
+                        const TreeView& tv, const PointsView& pv, double kappa, const cplx* mpole,
+                        const cplx* local, cplx* ufar, hipStream_t st);
 // Near-field work of the 2D Helmholtz plan: List-1 entries as work items
 // (symmetric pair items, series row items, general row items) and the
 // partial-sum buffer C they write.
