@@ -56,8 +56,10 @@ METRIC = "N\u00b2-equiv interactions/s at 1e-6 rel err; served p50/p99 latency v
 
 
 TRAFFIC_PROFILES = {
-    # workload: counter summary of its P2P kernel (calibrated HBM bytes per launch)
+    # FP64 workload: counter summary of its P2P kernels (calibrated HBM bytes per launch)
     "c1": "profiles/helmholtz2d_n1m_p2p_traffic.md",
+    "c2": "profiles/laplace3d_n2m_p2p_traffic.md",
+    "c3": "profiles/helmholtz3d_n1m_p2p_traffic.md",
 }
 
 

@@ -86,9 +86,10 @@ class Server:
         self.keep = keep_results
         self.policy = policy
 
-    def run(self, prepared: list, rate_scale: float = 1.0) -> dict:
+    def run(self, prepared: list, rate_scale: float = 1.0, progress=None) -> dict:
         """Serve `prepared` requests with arrivals at req.arrival * rate_scale
-        seconds after the start; returns per-request records and stats."""
+        seconds after the start; returns per-request records and stats.
+        progress(msg), when given, is called every 64 admitted requests."""
         import torch
         dev = torch.device("cuda", self.device)
         work = queue.Queue()
@@ -149,6 +150,8 @@ class Server:
                 state["peak"] = max(state["peak"], state["used"])
             admit[k] = time.perf_counter()
             work.put((k, prep, est))
+            if progress is not None and (k + 1) % 64 == 0:
+                progress(f"admitted {k + 1}/{len(prepared)}")
         for _ in threads:
             work.put(None)
         for th in threads:
@@ -163,8 +166,9 @@ class Server:
                                         for k in range(len(prepared))])}
 
 
-def sequential_service_times(prepared: list, device: int = 0, keep_results: bool = False):
-    """Plain FP64, one request at a time on one stream; service time per request."""
+def sequential_service_times(prepared: list, device: int = 0, keep_results: bool = False, progress=None):
+    """Plain FP64, one request at a time on one stream; service time per request.
+    progress(msg), when given, is called every 64 requests."""
     import torch
     dev = torch.device("cuda", device)
     stream = torch.cuda.Stream(device=dev)
@@ -175,6 +179,8 @@ def sequential_service_times(prepared: list, device: int = 0, keep_results: bool
         _, last = _process(prep, "fp64", stream, dev, keep_results)
         times.append(time.perf_counter() - t0)
         results.append(last)
+        if progress is not None and len(times) % 64 == 0:
+            progress(f"sequential {len(times)}/{len(prepared)}")
     return np.array(times), results
 
 
@@ -193,7 +199,7 @@ def interactions(prepared) -> float:
 
 
 def serve_benchmark(nreq: int = 64, slots: int = 4, load: float = 0.8, nmax_log2: float = 18.0,
-                    hbm_budget: int = 64 << 30, check: int = 8, seed: int = 4000) -> dict:
+                    hbm_budget: int = 64 << 30, check: int = 8, seed: int = 4000, progress=None) -> dict:
     """Served stream against sequential plain FP64 on the same trace.
 
     The arrival rate is load / (mean sequential service time); sequential
@@ -206,14 +212,15 @@ def serve_benchmark(nreq: int = 64, slots: int = 4, load: float = 0.8, nmax_log2
     # warm the library and the allocator on a small plan of each kind
     warm = [Prepared(r) for r in synth.serving_trace(4, rate=1.0, nmax_log2=11.0, seed=seed + 1)]
     sequential_service_times(warm)
-    svc, seq_res = sequential_service_times(prepared, keep_results=True)
+    svc, seq_res = sequential_service_times(prepared, keep_results=True, progress=progress)
     mean_s = float(svc.mean())
     # unit-rate arrivals rescaled to the target load
     unit = np.array([p.req.arrival for p in prepared])
     rate_scale = mean_s / load
     arrivals = unit * rate_scale
     seq_lat, seq_span = fcfs_latencies(arrivals, svc)
-    srv = Server(slots=slots, hbm_budget=hbm_budget, keep_results=True).run(prepared, rate_scale=rate_scale)
+    srv = Server(slots=slots, hbm_budget=hbm_budget, keep_results=True).run(prepared, rate_scale=rate_scale,
+                                                                           progress=progress)
     lat = srv["latency"]
     diffs = []
     for k in range(min(check, nreq)):
@@ -225,7 +232,7 @@ def serve_benchmark(nreq: int = 64, slots: int = 4, load: float = 0.8, nmax_log2
     inter = interactions(prepared)
     nmat = sum(p.req.nmat for p in prepared)
     # saturation throughput: every request present at t = 0
-    burst = Server(slots=slots, hbm_budget=hbm_budget).run(prepared, rate_scale=0.0)
+    burst = Server(slots=slots, hbm_budget=hbm_budget).run(prepared, rate_scale=0.0, progress=progress)
     seq_total = float(svc.sum())
     return {
         "requests": nreq, "slots": slots, "load": load, "matvecs": nmat,
@@ -253,7 +260,11 @@ def main(argv=None):
     ap.add_argument("--nmax-log2", type=float, default=18.0)
     ap.add_argument("--hbm-budget-gib", type=float, default=64.0)
     a = ap.parse_args(argv)
-    res = serve_benchmark(a.requests, a.slots, a.load, a.nmax_log2, int(a.hbm_budget_gib * (1 << 30)))
+    def progress(msg):
+        print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
+    res = serve_benchmark(a.requests, a.slots, a.load, a.nmax_log2, int(a.hbm_budget_gib * (1 << 30)),
+                          progress=progress)
     print(json.dumps(res), flush=True)
 
 
