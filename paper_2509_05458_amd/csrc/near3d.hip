@@ -35,7 +35,23 @@ struct Tile {
 template <int KIND, int PREC>
 struct Kernel;
 
-// 1/r (principal r): (t - i Im s/(2t)) / |s|, t = sqrt((|s| + Re s)/2)
+// 1/sqrt(x) for positive normal x: the hardware estimate refined by two
+// Newton steps y <- y (1 + (1 - x y^2)/2), each of which squares the relative
+// error.
+__device__ inline double rsq_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    for (int it = 0; it < 2; ++it) {
+        double e = fma(-(x * y), y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+// 1/r (principal r): (t - i Im s/(2t)) / |s|, t = sqrt((|s| + Re s)/2).
+// The FP32 forms use the hardware reciprocal square root directly.
+// With u = 1/|s| and v = 1/t from rsq_nr: |s| = |s|^2 u, t = h v
+// (h = (|s| + Re s)/2), 1/r = (t u, -Im s u v / 2); no division.
 template <>
 struct Kernel<0, 0> {
     __device__ static void eval(const double* dr, const double* di, double, double& gr, double& gi)
@@ -46,11 +62,12 @@ struct Kernel<0, 0> {
             si += 2.0 * dr[d] * di[d];
         }
         if (sr == 0.0 && si == 0.0) { gr = gi = 0.0; return; }
-        double as = sqrt(sr * sr + si * si);
-        double tt = sqrt(0.5 * (as + sr));
-        double ias = 1.0 / as;
-        gr = tt * ias;
-        gi = -0.5 * si * ias / tt;
+        double q = sr * sr + si * si;
+        double u = rsq_nr(q);
+        double h = 0.5 * (q * u + sr);
+        double v = rsq_nr(h);
+        gr = (h * v) * u;
+        gi = -0.5 * si * (u * v);
     }
 };
 template <>
@@ -64,14 +81,16 @@ struct Kernel<0, 1> {
             si += 2.0f * a * b;
         }
         if (sr == 0.0f && si == 0.0f) { gr = gi = 0.0f; return; }
-        float as = sqrtf(sr * sr + si * si);
-        float tt = sqrtf(0.5f * (as + sr));
-        float ias = 1.0f / as;
-        gr = tt * ias;
-        gi = -0.5f * si * ias / tt;
+        float q = sr * sr + si * si;
+        float u = __builtin_amdgcn_rsqf(q);
+        float h = 0.5f * (q * u + sr);
+        float v = __builtin_amdgcn_rsqf(h);
+        gr = (h * v) * u;
+        gi = -0.5f * si * (u * v);
     }
 };
-// e^{i kappa r}/r = e^{-kappa Im r}(cos + i sin)(kappa Re r) conj(r)/|s|
+// e^{i kappa r}/r = e^{-kappa Im r}(cos + i sin)(kappa Re r) conj(r)/|s|, with
+// r = (t, Im s/(2t)) and 1/|s|, 1/t from rsq_nr as for 1/r.
 template <>
 struct Kernel<1, 0> {
     __device__ static void eval(const double* dr, const double* di, double kappa, double& gr, double& gi)
@@ -82,11 +101,14 @@ struct Kernel<1, 0> {
             si += 2.0 * dr[d] * di[d];
         }
         if (sr == 0.0 && si == 0.0) { gr = gi = 0.0; return; }
-        double as = sqrt(sr * sr + si * si);
-        double rr = sqrt(0.5 * (as + sr)), ri = 0.5 * si / rr;
+        double q = sr * sr + si * si;
+        double u = rsq_nr(q);
+        double h = 0.5 * (q * u + sr);
+        double v = rsq_nr(h);
+        double rr = h * v, ri = 0.5 * si * v;
         double sn, cs;
         sincos(kappa * rr, &sn, &cs);
-        double ex = exp(-kappa * ri) / as;
+        double ex = exp(-kappa * ri) * u;
         gr = (cs * rr + sn * ri) * ex;
         gi = (sn * rr - cs * ri) * ex;
     }
@@ -103,11 +125,14 @@ struct Kernel<1, 1> {
         }
         if (sr == 0.0f && si == 0.0f) { gr = gi = 0.0f; return; }
         float kf = (float)kappa;
-        float as = sqrtf(sr * sr + si * si);
-        float rr = sqrtf(0.5f * (as + sr)), ri = 0.5f * si / rr;
+        float q = sr * sr + si * si;
+        float u = __builtin_amdgcn_rsqf(q);
+        float h = 0.5f * (q * u + sr);
+        float v = __builtin_amdgcn_rsqf(h);
+        float rr = h * v, ri = 0.5f * si * v;
         float sn, cs;
         sincosf(kf * rr, &sn, &cs);
-        float ex = expf(-kf * ri) / as;
+        float ex = expf(-kf * ri) * u;
         gr = (cs * rr + sn * ri) * ex;
         gi = (sn * rr - cs * ri) * ex;
     }
@@ -123,14 +148,17 @@ struct Kernel<1, 2> {
             si += 2.0 * dr[d] * di[d];
         }
         if (sr == 0.0 && si == 0.0) { gr = gi = 0.0f; return; }
-        double as = sqrt(sr * sr + si * si);
-        double tt = sqrt(0.5 * (as + sr));
+        double q = sr * sr + si * si;
+        double u = rsq_nr(q);
+        double h = 0.5 * (q * u + sr);
+        double v = rsq_nr(h);
+        double tt = h * v;
         double ph = kappa * tt;
         ph -= (2.0 * kPi) * rint(ph * (1.0 / (2.0 * kPi)));
-        float rr = (float)tt, ri = (float)(0.5 * si / tt);
+        float rr = (float)tt, ri = (float)(0.5 * si * v);
         float sn, cs;
         sincosf((float)ph, &sn, &cs);
-        float ex = expf(-(float)kappa * ri) / (float)as;
+        float ex = expf(-(float)kappa * ri) * (float)u;
         gr = (cs * rr + sn * ri) * ex;
         gi = (sn * rr - cs * ri) * ex;
     }
