@@ -301,107 +301,129 @@ __global__ void k_h2d_gen_tr(const int* __restrict__ boxes, int nb, TreeView tv,
 // the output coefficients (G >= 2P+1 when possible), S groups of G lanes split
 // the input sum of a box (partial sums reduced through LDS), and 256/(G S)
 // boxes share a 256-thread block.  All boxes of a launch have the same P.
-struct TShape {
-    int G, S;
+// ------------------------------------------------------------------ translations
+// M2M, M2L and L2L are Toeplitz matvecs with per-entry level-power factors.
+// One workgroup of 64 per output box: for each source expansion the block
+// stages the generator window, the source coefficients and the level's
+// powers r^e in LDS; lane `lane` of slice s (G lanes x S slices, G >= 2P+1
+// rounded to 16, 32 or 64) owns output coefficient lane (and lane + 64 when
+// 2P+1 > 64) over the source terms n = -P + s, -P + s + S, ...; the S slice
+// sums are added through LDS in a fixed order.
+constexpr int kGenMax = 4 * kPMax2D + 1;
+
+struct TrShared {
+    cplx g[kGenMax];            // generator window
+    cplx m[kNCoef2DMax];        // source coefficients
+    double pw[kPwStride];       // r^e of the level that carries the factors
+    cplx part[64];
 };
 
-constexpr int kMaxLv = 32;
-struct LvTable {
-    int n;                          // levels in the launch
-    int first_block[kMaxLv + 1];    // block range of each level
-    int box_off[kMaxLv], nb[kMaxLv], G[kMaxLv], S[kMaxLv];
-};
+__device__ inline void tr_shape(int ncoef, int& G, int& S)
+{
+    G = ncoef <= 16 ? 16 : (ncoef <= 32 ? 32 : 64);
+    S = 64 / G;
+}
 
-__device__ inline cplx tsum(cplx acc, cplx* part, int G, int S, int s)
+__device__ inline cplx slice_sum(cplx acc, TrShared& sh, int G, int S, int s)
 {
     if (S == 1) return acc;
-    part[threadIdx.x] = acc;
+    __syncthreads();
+    sh.part[threadIdx.x] = acc;
     __syncthreads();
     cplx r = acc;
     if (s == 0)
-        for (int k = 1; k < S; ++k) r += part[threadIdx.x + k * G];
-    __syncthreads();
+        for (int k = 1; k < S; ++k) r += sh.part[threadIdx.x + k * G];
     return r;
 }
 
-// ------------------------------------------------------------------ M2M
 // Entry (m, n) of child c: gm2m[n - m] r_c^(|n-m| + |n| - |m|) (r_c/r_p)^|m|.
-__global__ __launch_bounds__(256) void k_h2d_m2m(const int* __restrict__ boxes, int nb, TShape sh, TreeView tv,
-                                                 H2DOps ops, cplx* __restrict__ mpole)
+__global__ __launch_bounds__(64) void k_h2d_m2m(const int* __restrict__ boxes, int nb, TreeView tv, H2DOps ops,
+                                                cplx* __restrict__ mpole)
 {
-    __shared__ cplx part[256];
-    int G = sh.G, S = sh.S, per = G * S;
-    int lane = threadIdx.x % G, s = (threadIdx.x / G) % S;
-    int bi = blockIdx.x * (256 / per) + threadIdx.x / per;
-    bool valid = bi < nb;
-    int p = boxes[valid ? bi : 0];
+    __shared__ TrShared sh;
+    int p = boxes[xcd_contiguous(blockIdx.x, nb)];
     int l = tv.level[p];
     int Pp = tv.P[l], Pc = tv.P[l + 1];
-    int K = Pp + Pc, ncoef = 2 * Pp + 1;
-    const double* pwc = ops.pw + (size_t)(l + 1) * kPwStride;
-    double rat = tv.rs[l + 1] / tv.rs[l];
+    int K = Pp + Pc, ncoef = 2 * Pp + 1, nsrc = 2 * Pc + 1;
+    int G, S;
+    tr_shape(ncoef, G, S);
+    int t = threadIdx.x, lane = t % G, s = t / G;
+    for (int e = t; e < kPwStride; e += 64) sh.pw[e] = ops.pw[(size_t)(l + 1) * kPwStride + e];
+    cplx acc0 = mk(0.0, 0.0), acc1 = mk(0.0, 0.0);
     int c0 = tv.child0[p], nc = tv.nchild[p];
-    for (int m0 = 0; m0 < ncoef; m0 += G) {
-        int mi = m0 + lane;
-        int mm = mi - Pp, am = mm < 0 ? -mm : mm;
-        cplx acc = mk(0.0, 0.0);
-        if (valid && mi < ncoef) {
-            for (int ci = 0; ci < nc; ++ci) {
-                int c = c0 + ci;
-                const cplx* M = mpole + tv.eoff[c] + Pc;
-                const cplx* Gv = ops.g_m2m + ops.o_tr[c] + K - mm;
-                for (int nn = -Pc + s; nn <= Pc; nn += S) {
-                    int k = nn - mm;
-                    int e = (k < 0 ? -k : k) + (nn < 0 ? -nn : nn) - am;
-                    acc += (pwc[e] * Gv[nn]) * M[nn];
-                }
+    for (int ci = 0; ci < nc; ++ci) {
+        int c = c0 + ci;
+        const cplx* Gv = ops.g_m2m + ops.o_tr[c];
+        const cplx* M = mpole + tv.eoff[c];
+        __syncthreads();
+        for (int i = t; i <= 2 * K; i += 64) sh.g[i] = Gv[i];
+        for (int i = t; i < nsrc; i += 64) sh.m[i] = M[i];
+        __syncthreads();
+        for (int r = 0; r < 2; ++r) {
+            int mi = lane + 64 * r;
+            if (mi >= ncoef) break;
+            int mm = mi - Pp, am = mm < 0 ? -mm : mm;
+            cplx acc = mk(0.0, 0.0);
+            for (int nn = -Pc + s; nn <= Pc; nn += S) {
+                int k = nn - mm;
+                int e = (k < 0 ? -k : k) + (nn < 0 ? -nn : nn) - am;
+                cfma(acc, sh.pw[e] * sh.g[k + K], sh.m[nn + Pc]);
             }
+            if (r == 0) acc0 += acc;
+            else acc1 += acc;
         }
-        acc = tsum(acc, part, G, S, s);
-        if (valid && mi < ncoef && s == 0) mpole[tv.eoff[p] + mi] = pow(rat, (double)am) * acc;
+    }
+    double rat = tv.rs[l + 1] / tv.rs[l];
+    for (int r = 0; r < 2; ++r) {
+        cplx acc = slice_sum(r == 0 ? acc0 : acc1, sh, G, S, s);
+        int mi = lane + 64 * r;
+        int mm = mi - Pp, am = mm < 0 ? -mm : mm;
+        if (mi < ncoef && s == 0) mpole[tv.eoff[p] + mi] = pow(rat, (double)am) * acc;
     }
 }
 
-// ------------------------------------------------------------------ M2L
 // Entry (m, n) of source a: gm2l[n - m] r^(|m| + |n| - |n - m|), i.e.
-// r^(2 min(|m|,|n|)) when m, n have the same sign and 1 otherwise.
-// All levels go in one launch (M2L has no dependence between levels); the
-// block table gives each level its own contiguous block range and shape.
-__global__ __launch_bounds__(256) void k_h2d_m2l(const int* __restrict__ boxes, LvTable lt, TreeView tv,
-                                                 H2DOps ops, const cplx* __restrict__ mpole,
-                                                 cplx* __restrict__ local)
+// r^(2 min(|m|,|n|)) when m, n have the same sign and 1 otherwise.  All
+// levels go in one launch (M2L has no dependence between levels).
+__global__ __launch_bounds__(64) void k_h2d_m2l(const int* __restrict__ boxes, int nboxes, TreeView tv,
+                                                H2DOps ops, const cplx* __restrict__ mpole,
+                                                cplx* __restrict__ local)
 {
-    __shared__ cplx part[256];
-    int k = 0;
-    while (k + 1 < lt.n && (int)blockIdx.x >= lt.first_block[k + 1]) ++k;
-    int G = lt.G[k], S = lt.S[k], per = G * S, nb = lt.nb[k];
-    int lane = threadIdx.x % G, s = (threadIdx.x / G) % S;
-    int bi = (blockIdx.x - lt.first_block[k]) * (256 / per) + threadIdx.x / per;
-    bool valid = bi < nb;
-    int b = boxes[lt.box_off[k] + (valid ? bi : 0)];
+    __shared__ TrShared sh;
+    int b = boxes[xcd_contiguous(blockIdx.x, nboxes)];
     int l = tv.level[b];
     int P = tv.P[l], ncoef = 2 * P + 1;
-    const double* pw = ops.pw + (size_t)l * kPwStride;
-    int e0 = tv.l2off[b], e1 = tv.l2off[b + 1];
-    for (int m0 = 0; m0 < ncoef; m0 += G) {
-        int mi = m0 + lane;
-        int mm = mi - P, am = mm < 0 ? -mm : mm;
-        cplx acc = mk(0.0, 0.0);
-        if (valid && mi < ncoef) {
-            double rm = pw[2 * am];
-            for (int e = e0; e < e1; ++e) {
-                const cplx* M = mpole + tv.eoff[tv.l2idx[e]] + P;
-                const cplx* Gv = ops.g_m2l + ops.o_m2l[e] + 2 * P - mm;
-                for (int nn = -P + s; nn <= P; nn += S) {
-                    int an = nn < 0 ? -nn : nn;
-                    bool same = (nn > 0 && mm > 0) || (nn < 0 && mm < 0);
-                    double f = same ? (an <= am ? pw[2 * an] : rm) : 1.0;
-                    acc += (f * Gv[nn]) * M[nn];
-                }
+    int G, S;
+    tr_shape(ncoef, G, S);
+    int t = threadIdx.x, lane = t % G, s = t / G;
+    for (int e = t; e <= 2 * P; e += 64) sh.pw[e] = ops.pw[(size_t)l * kPwStride + e];
+    cplx acc0 = mk(0.0, 0.0), acc1 = mk(0.0, 0.0);
+    for (int e = tv.l2off[b]; e < tv.l2off[b + 1]; ++e) {
+        const cplx* Gv = ops.g_m2l + ops.o_m2l[e];
+        const cplx* M = mpole + tv.eoff[tv.l2idx[e]];
+        __syncthreads();
+        for (int i = t; i <= 4 * P; i += 64) sh.g[i] = Gv[i];
+        for (int i = t; i < ncoef; i += 64) sh.m[i] = M[i];
+        __syncthreads();
+        for (int r = 0; r < 2; ++r) {
+            int mi = lane + 64 * r;
+            if (mi >= ncoef) break;
+            int mm = mi - P, am = mm < 0 ? -mm : mm;
+            cplx acc = mk(0.0, 0.0);
+            for (int nn = -P + s; nn <= P; nn += S) {
+                int an = nn < 0 ? -nn : nn;
+                bool same = (nn > 0 && mm > 0) || (nn < 0 && mm < 0);
+                int ex = same ? 2 * (an < am ? an : am) : 0;
+                cfma(acc, sh.pw[ex] * sh.g[nn - mm + 2 * P], sh.m[nn + P]);
             }
+            if (r == 0) acc0 += acc;
+            else acc1 += acc;
         }
-        acc = tsum(acc, part, G, S, s);
-        if (valid && mi < ncoef && s == 0) local[tv.eoff[b] + mi] = acc;
+    }
+    for (int r = 0; r < 2; ++r) {
+        cplx acc = slice_sum(r == 0 ? acc0 : acc1, sh, G, S, s);
+        int mi = lane + 64 * r;
+        if (mi < ncoef && s == 0) local[tv.eoff[b] + mi] = acc;
     }
 }
 
@@ -464,37 +486,40 @@ __global__ __launch_bounds__(128) void k_h2d_p2l(const int* __restrict__ boxes, 
 }
 
 // ------------------------------------------------------------------ L2L
-// Entry (m, n): gl2l[n - m] r_p^(|n-m| + |m| - |n|) (r_c/r_p)^|m|.
-__global__ __launch_bounds__(256) void k_h2d_l2l(const int* __restrict__ boxes, int nb, TShape sh, TreeView tv,
-                                                 H2DOps ops, cplx* __restrict__ local)
+// Entry (m, n): gl2l[n - m] r_p^(|n-m| + |m| - |n|) (r_c/r_p)^|m|; one
+// workgroup per child.
+__global__ __launch_bounds__(64) void k_h2d_l2l(const int* __restrict__ boxes, int nb, TreeView tv, H2DOps ops,
+                                                cplx* __restrict__ local)
 {
-    __shared__ cplx part[256];
-    int G = sh.G, S = sh.S, per = G * S;
-    int lane = threadIdx.x % G, s = (threadIdx.x / G) % S;
-    int bi = blockIdx.x * (256 / per) + threadIdx.x / per;
-    bool valid = bi < nb;
-    int c = boxes[valid ? bi : 0];
+    __shared__ TrShared sh;
+    int c = boxes[xcd_contiguous(blockIdx.x, nb)];
     int p = tv.parent[c];
     int lc = tv.level[c];
     int Pc = tv.P[lc], Pp = tv.P[lc - 1];
-    int K = Pp + Pc, ncoef = 2 * Pc + 1;
-    const double* pwp = ops.pw + (size_t)(lc - 1) * kPwStride;
+    int K = Pp + Pc, ncoef = 2 * Pc + 1, nsrc = 2 * Pp + 1;
+    int G, S;
+    tr_shape(ncoef, G, S);
+    int t = threadIdx.x, lane = t % G, s = t / G;
+    for (int e = t; e < kPwStride; e += 64) sh.pw[e] = ops.pw[(size_t)(lc - 1) * kPwStride + e];
+    const cplx* Gv = ops.g_l2l + ops.o_tr[c];
+    const cplx* Lp = local + tv.eoff[p];
+    for (int i = t; i <= 2 * K; i += 64) sh.g[i] = Gv[i];
+    for (int i = t; i < nsrc; i += 64) sh.m[i] = Lp[i];
+    __syncthreads();
     double rat = tv.rs[lc] / tv.rs[lc - 1];
-    const cplx* Lp = local + tv.eoff[p] + Pp;
-    for (int m0 = 0; m0 < ncoef; m0 += G) {
-        int mi = m0 + lane;
+    for (int r = 0; r < 2; ++r) {
+        int mi = lane + 64 * r;
         int mm = mi - Pc, am = mm < 0 ? -mm : mm;
         cplx acc = mk(0.0, 0.0);
-        if (valid && mi < ncoef) {
-            const cplx* Gv = ops.g_l2l + ops.o_tr[c] + K - mm;
+        if (mi < ncoef)
             for (int nn = -Pp + s; nn <= Pp; nn += S) {
                 int k = nn - mm;
                 int e = (k < 0 ? -k : k) + am - (nn < 0 ? -nn : nn);
-                acc += (pwp[e] * Gv[nn]) * Lp[nn];
+                cfma(acc, sh.pw[e] * sh.g[k + K], sh.m[nn + Pp]);
             }
-        }
-        acc = tsum(acc, part, G, S, s);
-        if (valid && mi < ncoef && s == 0) local[tv.eoff[c] + mi] += pow(rat, (double)am) * acc;
+        acc = slice_sum(acc, sh, G, S, s);
+        if (mi < ncoef && s == 0) local[tv.eoff[c] + mi] += pow(rat, (double)am) * acc;
+        if (ncoef <= 64) break;
     }
 }
 
@@ -870,46 +895,25 @@ hipError_t h2d_gen_ops(const int* pair_b, int npairs, const int* tr_boxes, int n
 
 // G lanes cover the output coefficients; levels with few boxes split the
 // input sum over S = 256 / G groups so that the level still fills the chip.
-static TShape tshape(int ncoef, int nb)
-{
-    TShape sh;
-    sh.G = ncoef <= 32 ? 32 : (ncoef <= 64 ? 64 : 128);
-    sh.S = ((int64_t)nb * sh.G < 256 * 256) ? 256 / sh.G : 1;
-    return sh;
-}
-
-static unsigned tblocks(int nb, TShape sh) { return (unsigned)((nb + 256 / (sh.G * sh.S) - 1) / (256 / (sh.G * sh.S))); }
-
 hipError_t h2d_m2m(const int* boxes, int nb, int ncoef, const TreeView& tv, const H2DOps& ops, cplx* mpole,
                    hipStream_t st)
 {
+    (void)ncoef;
     if (nb <= 0) return hipSuccess;
-    TShape sh = tshape(ncoef, nb);
-    k_h2d_m2m<<<tblocks(nb, sh), 256, 0, st>>>(boxes, nb, sh, tv, ops, mpole);
+    k_h2d_m2m<<<nb, 64, 0, st>>>(boxes, nb, tv, ops, mpole);
     return hipGetLastError();
 }
 
 hipError_t h2d_m2l(const int* boxes, int nlv, const int* box_off, const int* nb, const int* ncoef,
                    const TreeView& tv, const H2DOps& ops, const cplx* mpole, cplx* local, hipStream_t st)
 {
-    LvTable lt;
-    lt.n = 0;
-    int blk = 0;
-    for (int k = 0; k < nlv; ++k) {
-        if (nb[k] <= 0) continue;
-        if (lt.n == kMaxLv) return hipErrorInvalidValue;
-        TShape sh = tshape(ncoef[k], nb[k]);
-        lt.first_block[lt.n] = blk;
-        lt.box_off[lt.n] = box_off[k];
-        lt.nb[lt.n] = nb[k];
-        lt.G[lt.n] = sh.G;
-        lt.S[lt.n] = sh.S;
-        blk += (int)tblocks(nb[k], sh);
-        ++lt.n;
-    }
-    if (lt.n == 0) return hipSuccess;
-    lt.first_block[lt.n] = blk;
-    k_h2d_m2l<<<blk, 256, 0, st>>>(boxes, lt, tv, ops, mpole, local);
+    // the boxes of all levels are contiguous in the list
+    (void)box_off;
+    (void)ncoef;
+    int total = 0;
+    for (int k = 0; k < nlv; ++k) total += nb[k] > 0 ? nb[k] : 0;
+    if (total <= 0) return hipSuccess;
+    k_h2d_m2l<<<total, 64, 0, st>>>(boxes, total, tv, ops, mpole, local);
     return hipGetLastError();
 }
 
@@ -928,9 +932,9 @@ hipError_t h2d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const Po
 hipError_t h2d_l2l(const int* boxes, int nb, int ncoef, const TreeView& tv, const H2DOps& ops, cplx* local,
                    hipStream_t st)
 {
+    (void)ncoef;
     if (nb <= 0) return hipSuccess;
-    TShape sh = tshape(ncoef, nb);
-    k_h2d_l2l<<<tblocks(nb, sh), 256, 0, st>>>(boxes, nb, sh, tv, ops, local);
+    k_h2d_l2l<<<nb, 64, 0, st>>>(boxes, nb, tv, ops, local);
     return hipGetLastError();
 }
 

@@ -118,7 +118,7 @@ hipError_t l3d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const Po
                    cplx* local, hipStream_t st);
 hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mpole, hipStream_t st);
 hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const int* map, int ntab, int R,
-                   const cplx* mpole, cplx* local, hipStream_t st);
+                   int mixed, const cplx* mpole, cplx* local, hipStream_t st);
 hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st);
 hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& tv,
                         const PointsView& pv, const cplx* mpole, const cplx* local, const M2PParts& m2p,

@@ -443,6 +443,111 @@ __global__ __launch_bounds__(64) void k_l3d_m2l(const int* __restrict__ boxes, i
     }
 }
 
+// Mixed-precision M2L: the same lane layout with an FP32 table and FP32
+// source coefficients (8-byte entries).  The table is built in FP64 and
+// rounded; each row n of the contraction (2n+1 terms) is summed in FP32 and
+// the row sums are added in FP64.  Used for P <= kM2LF32MaxP, where every
+// table entry I_l^q (l <= 2P, |D/w| > 1.7) stays far inside the FP32 range.
+constexpr int kM2LF32MaxP = 16;
+
+template <int R>
+__global__ __launch_bounds__(64) void k_l3d_m2l_f32(const int* __restrict__ boxes, int nboxes, TreeView tv,
+                                                    const int* __restrict__ map, int ntab,
+                                                    const cplx* __restrict__ mpole,
+                                                    cplx* __restrict__ local)
+{
+    extern __shared__ float2 tabf[];
+    int b = boxes[xcd_contiguous(blockIdx.x, nboxes)];
+    int l = tv.level[b];
+    int P = tv.P[l];
+    int nc = (P + 1) * (P + 1);
+    float2* Ms = tabf + ntab;
+    int* base = reinterpret_cast<int*>(Ms + nc);
+    double s = tv.rs[l];
+    int t = threadIdx.x;
+    int jg[R], kg[R];
+    bool act[R];
+    cplx acc[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int code = map[2 * P + 1 + t + 64 * r];
+        jg[r] = code & 255;
+        kg[r] = -jg[r] + 4 * ((code >> 8) & 255);
+        act[r] = (code >> 16) & 1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = mk(0.0, 0.0);
+    }
+    for (int i = t; i < ntab; i += 64) tabf[i] = make_float2(0.0f, 0.0f);
+    for (int i = t; i <= 2 * P; i += 64) base[i] = map[i];
+    cplx cb[3];
+    box_centre(tv, b, cb);
+    for (int e = tv.l2off[b]; e < tv.l2off[b + 1]; ++e) {
+        int a = tv.l2idx[e];
+        cplx ca[3];
+        box_centre(tv, a, ca);
+        Vec3 d;
+        d.x = (cb[0] - ca[0]) * s; d.y = (cb[1] - ca[1]) * s; d.z = (cb[2] - ca[2]) * s;
+        const cplx* M = mpole + tv.eoff[a];
+        __syncthreads();
+        for (int i = t; i < nc; i += 64) Ms[i] = make_float2((float)M[i].re, (float)M[i].im);
+        for (int q = t - 2 * P; q <= 2 * P; q += 64)
+            col_I(d, q, 2 * P, false,
+                  [&](int n, cplx v) { tabf[base[n] + q] = make_float2((float)v.re, (float)v.im); });
+        __syncthreads();
+        for (int n = 0; n <= P; ++n) {
+            const float2* Mn = Ms + n * n + n;
+            const float2* row[R];
+            float2 w1[R], w2[R], w3[R], f[R][4];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                row[r] = tabf + base[jg[r] + n] - kg[r];
+                w1[r] = row[r][-n - 1];
+                w2[r] = row[r][-n - 2];
+                w3[r] = row[r][-n - 3];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) f[r][c] = make_float2(0.0f, 0.0f);
+            }
+#pragma unroll 4
+            for (int m = -n; m <= n; ++m) {
+                float2 am = Mn[m];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    float2 w0 = row[r][m];
+                    float2 wv[4] = {w0, w1[r], w2[r], w3[r]};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        f[r][c].x = fmaf(am.x, wv[c].x, f[r][c].x);
+                        f[r][c].x = fmaf(-am.y, wv[c].y, f[r][c].x);
+                        f[r][c].y = fmaf(am.x, wv[c].y, f[r][c].y);
+                        f[r][c].y = fmaf(am.y, wv[c].x, f[r][c].y);
+                    }
+                    w3[r] = w2[r];
+                    w2[r] = w1[r];
+                    w1[r] = w0;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] += mk((double)f[r][c].x, (double)f[r][c].y);
+        }
+    }
+    cplx* o = local + tv.eoff[b];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!act[r]) continue;
+        int j = jg[r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            int k = kg[r] + c;
+            if (k > j) break;
+            cplx v = acc[r][c];
+            if ((j + k) & 1) v = -v;
+            o[nm(j, k)] = v;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ L2L
 __global__ __launch_bounds__(256) void k_l3d_l2l(const int* __restrict__ boxes, TreeView tv,
                                                  cplx* __restrict__ local)
@@ -601,10 +706,31 @@ size_t l3d_m2l_lds(int P, int ntab)
     return (size_t)(ntab + (P + 1) * (P + 1)) * sizeof(cplx) + (size_t)(2 * P + 1) * sizeof(int);
 }
 
+template <int R>
+static hipError_t launch_m2l_f32(const int* boxes, int nb, size_t lds, const TreeView& tv, const int* map,
+                                 int ntab, const cplx* mpole, cplx* local, hipStream_t st)
+{
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_l3d_m2l_f32<R>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    k_l3d_m2l_f32<R><<<nb, 64, lds, st>>>(boxes, nb, tv, map, ntab, mpole, local);
+    return hipGetLastError();
+}
+
 hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const int* map, int ntab, int R,
-                   const cplx* mpole, cplx* local, hipStream_t st)
+                   int mixed, const cplx* mpole, cplx* local, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
+    if (mixed && P <= kM2LF32MaxP) {
+        size_t lds = (size_t)(ntab + (P + 1) * (P + 1)) * sizeof(float2) + (size_t)(2 * P + 1) * sizeof(int);
+        switch (R) {
+        case 1: return launch_m2l_f32<1>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
+        case 2: return launch_m2l_f32<2>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     size_t lds = l3d_m2l_lds(P, ntab);
     switch (R) {
     case 1: return launch_m2l<1>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
