@@ -423,25 +423,41 @@ __global__ void k_h3d_rot_prep(H3DTr tr, int back, const int* __restrict__ eoff,
     tr.A[(size_t)i * tr.sA + c] = t;
 }
 
-// K1: rotation samples.  Thread (pair, n-block, node j): x = Q y_j (forward) or
-// Q^T y_j (back); accumulates F_n(j) = sum_m a_n^m S_n^m(x) and, from the
-// derivative coefficients t of K1a, G_n(j) = sum_m t_{n-1}^m S_{n-1}^m(x) for
-// the n of its block, sweeping the columns m with the diagonal start kept
-// incrementally and folded into the column.  On the unit sphere r2 = 1.
+// K1: rotation samples.  Workgroup (pair, n-block), thread = node j: x = Q y_j
+// (forward) or Q^T y_j (back); accumulates F_n(j) = sum_m a_n^m S_n^m(x) and,
+// from the derivative coefficients t of K1a, G_n(j) = sum_m t_{n-1}^m
+// S_{n-1}^m(x) for the n of its block, sweeping the columns m with the
+// diagonal start kept incrementally and folded into the column.  The block's
+// coefficients a_n^m (n = nlo-1..nhi) and t_n^m are staged in LDS first, so
+// the sweep reads them at one LDS address across the workgroup.  On the unit
+// sphere r2 = 1.
 template <int NB>
-__global__ __launch_bounds__(256) void k_h3d_rot_sample(H3DTr tr, int back, const int* __restrict__ eoff, const cplx* __restrict__ coef)
+__global__ __launch_bounds__(128) void k_h3d_rot_sample(H3DTr tr, int back, const int* __restrict__ eoff,
+                                                        const cplx* __restrict__ coef)
 {
+    extern __shared__ cplx cs[];
     int P = back ? tr.Pt : tr.Ps;
     int J = 2 * P + 1;
     int nblk = (P + NB) / NB;
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)tr.np * nblk * J) return;
-    int j = (int)(gid % J);
-    int blk = (int)((gid / J) % nblk);
-    int i = (int)(gid / ((int64_t)J * nblk));
+    int blk = blockIdx.x % nblk;
+    int i = blockIdx.x / nblk;
+    int j = threadIdx.x;
     const cplx* g = tr.geo + (size_t)i * 10;
     const cplx* a = back ? tr.B + (size_t)i * tr.sB : coef + eoff[tr.src[i]];
     const cplx* at = tr.A + (size_t)i * tr.sA;
+    int nlo = blk * NB, nhi = min(P, nlo + NB - 1);
+    int n0 = nlo > 0 ? nlo - 1 : 0;
+    int rows = nhi - n0 + 1;
+    cplx* ca = cs;                       // a_n^m at (n - n0) J + m + P
+    cplx* ct = cs + (size_t)(NB + 1) * J;
+    for (int e = threadIdx.x; e < rows * J; e += blockDim.x) {
+        int nn = n0 + e / J, mm = e % J - P;
+        bool in = mm >= -nn && mm <= nn;
+        ca[e] = in ? a[hnm(nn, mm)] : mk(0.0, 0.0);
+        ct[e] = (in && nn < P) ? at[hnm(nn, mm)] : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (j >= J) return;
     double sp, cp;
     sincospi(2.0 * j / J, &sp, &cp);
     // x = M y with y = (cp, sp, 0); M = Q or Q^T
@@ -451,7 +467,6 @@ __global__ __launch_bounds__(256) void k_h3d_rot_sample(H3DTr tr, int back, cons
     } else {
         x.x = cp * g[0] + sp * g[3]; x.y = cp * g[1] + sp * g[4]; x.z = cp * g[2] + sp * g[5];
     }
-    int nlo = blk * NB, nhi = min(P, nlo + NB - 1);
     cplx F[NB], G[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) { F[k] = mk(0.0, 0.0); G[k] = mk(0.0, 0.0); }
@@ -463,6 +478,8 @@ __global__ __launch_bounds__(256) void k_h3d_rot_sample(H3DTr tr, int back, cons
             if (am > 0) D = (D * w) * c_ck[am];
             if (sgn && am == 0) continue;
             int m = sgn ? -am : am;
+            const cplx* cam = ca + (m + P);   // cam[(n - n0) J] = a_n^m
+            const cplx* ctm = ct + (m + P);
             cplx q0 = zero, q1 = D;
             int n = am;
             // advance to n = nlo - 1 when the column starts below the block
@@ -471,7 +488,7 @@ __global__ __launch_bounds__(256) void k_h3d_rot_sample(H3DTr tr, int back, cons
                 col_step_nd(n, am, x.z, one, q0, q1);
             }
             // G of degree nlo takes the column at nlo - 1
-            if (nlo >= 1 && n == nlo - 1) cfma(G[0], at[hnm(n, m)], q1);
+            if (nlo >= 1 && n == nlo - 1) cfma(G[0], ctm[(n - n0) * J], q1);
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 int nn = nlo + k;
@@ -480,8 +497,8 @@ __global__ __launch_bounds__(256) void k_h3d_rot_sample(H3DTr tr, int back, cons
                     col_step_nd(nn, am, x.z, one, q0, q1);
                     n = nn;
                 }
-                cfma(F[k], a[hnm(nn, m)], q1);
-                if (k + 1 < NB && nn + 1 <= nhi) cfma(G[k + 1], at[hnm(nn, m)], q1);
+                cfma(F[k], cam[(nn - n0) * J], q1);
+                if (k + 1 < NB && nn + 1 <= nhi) cfma(G[k + 1], ctm[(nn - n0) * J], q1);
             }
         }
     }
@@ -780,8 +797,12 @@ hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_sr
     k_h3d_geo<<<blocks(tr.np, bs), bs, 0, st>>>(tr, tv);
     int Ps = tr.Ps, Pt = tr.Pt;
     k_h3d_rot_prep<<<blocks((int64_t)tr.np * Ps * Ps, bs), bs, 0, st>>>(tr, 0, eoff_src, coef_src);
-    int64_t n1 = (int64_t)tr.np * ((Ps + NB) / NB) * (2 * Ps + 1);
-    k_h3d_rot_sample<NB><<<blocks(n1, bs), bs, 0, st>>>(tr, 0, eoff_src, coef_src);
+    {
+        int J = 2 * Ps + 1;
+        size_t lds = sizeof(cplx) * (size_t)2 * (NB + 1) * J;
+        k_h3d_rot_sample<NB><<<(unsigned)((int64_t)tr.np * ((Ps + NB) / NB)), J <= 64 ? 64 : 128, lds, st>>>(
+            tr, 0, eoff_src, coef_src);
+    }
     int64_t n2 = (int64_t)tr.np * (Ps + 1) * (Ps + 1);
     k_h3d_rot_dft<<<blocks(n2, bs), bs, sizeof(double) * 2 * (2 * Ps + 1), st>>>(tr, 0, eq_p0, eq_d0);
     int64_t n3 = (int64_t)tr.np * tr.nq;
@@ -792,8 +813,12 @@ hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_sr
     int64_t nwave = (int64_t)(2 * Pt + 1) * ((Pt + 16) / 16) * ((tr.np + 3) / 4);
     k_h3d_coax_proj<<<(unsigned)((nwave + 3) / 4), 256, 0, st>>>(tr);
     k_h3d_rot_prep<<<blocks((int64_t)tr.np * Pt * Pt, bs), bs, 0, st>>>(tr, 1, nullptr, nullptr);
-    int64_t n6 = (int64_t)tr.np * ((Pt + NB) / NB) * (2 * Pt + 1);
-    k_h3d_rot_sample<NB><<<blocks(n6, bs), bs, 0, st>>>(tr, 1, nullptr, nullptr);
+    {
+        int J = 2 * Pt + 1;
+        size_t lds = sizeof(cplx) * (size_t)2 * (NB + 1) * J;
+        k_h3d_rot_sample<NB><<<(unsigned)((int64_t)tr.np * ((Pt + NB) / NB)), J <= 64 ? 64 : 128, lds, st>>>(
+            tr, 1, nullptr, nullptr);
+    }
     k_h3d_rot_dft<<<blocks(n5, bs), bs, sizeof(double) * 2 * (2 * Pt + 1), st>>>(tr, 1, eq_p0, eq_d0);
     int64_t n7 = (int64_t)ng * (Pt + 1) * (Pt + 1);
     k_h3d_accum<<<blocks(n7, bs), bs, 0, st>>>(tr, gdst, goff, ng, eoff_dst, coef_dst);
