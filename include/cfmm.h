@@ -68,10 +68,14 @@ typedef struct {
     int64_t n;                 /* number of points, 1 <= n < 2^31 */
     const void* points;        /* complex128[n][dim], row-major */
     int points_on_device;      /* 1: device pointer, 0: host pointer */
-    int precision;             /* cfmm_precision: FP64, or FP32 near field (MIXED) */
+    int precision;             /* cfmm_precision: FP64, or MIXED: FP32 3D near field (FP64-formed
+                                  differences, FP64 tile sums) and, for tol >= 1e-6, an FP32 3D
+                                  Laplace M2L when P <= 16 (FP64 row sums); its rounding floor is
+                                  about 1e-7 relative, so it is meant for tol >= 1e-6.  The 2D
+                                  near field stays FP64 (small-argument Hankel). */
     void* stream;              /* hipStream_t for all work; NULL: the null stream */
-    int leaf_size;             /* N_s, max points per leaf (Sec. 6.1); 0: default */
-    int separation;            /* k in {1, 2} (Sec. 6.2, Sec. 6.5); 0: 1 */
+    int leaf_size;             /* N_s, max points per leaf (Sec. 6.1); 0: 64 in 2D, 256 in 3D */
+    int separation;            /* k in {1, 2} (Sec. 6.2, Sec. 6.5); 0: 1 in 2D, 2 in 3D */
 } cfmm_plan_desc;
 
 /* Build a plan: sort, tree, lists, centres, expansion lengths (Sec. 6.1-6.3).

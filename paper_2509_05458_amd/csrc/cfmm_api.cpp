@@ -1039,8 +1039,11 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         for (int l = nlev - 2; l >= top; --l)
             HIPCHK(l3d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], P, tv, p->d_mpole, st));
         HIPCHK(mark(3));
-        HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, p->precision,
-                       p->d_mpole, p->d_local, st));
+        // FP32 M2L in mixed precision only where its ~1e-7 rounding floor sits
+        // below the requested accuracy
+        int m2l32 = p->precision == CFMM_MIXED && p->tol >= 1e-6;
+        HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, m2l32, p->d_mpole,
+                       p->d_local, st));
         HIPCHK(l3d_p2l(W + p->off_p2l, p->n_p2l, P, tv, pv, p->d_local, st));
         HIPCHK(mark(4));
         for (int l = top + 1; l < nlev; ++l)

@@ -572,19 +572,26 @@ __global__ void k_h3d_coax_radial(H3DTr tr)
     else radial_j(r2, tr.ks, tr.sc, tr.Ps + 1, R, tr.nq);
 }
 
-// K3: coaxial samples.  Thread (pair, order m >= 0, node j): the column of
-// order m at x_j (y = 0, so S_n^-m = S_n^m there) with its derivative along
-// s_j = (sin t_j, 0, cos t_j); with F = R_n(rho) S_n^m(x),
+// K3: coaxial samples.  Workgroup (pair, order m >= 0), thread = node j: the
+// column of order m at x_j (y = 0, so S_n^-m = S_n^m there) with its
+// derivative along s_j = (sin t_j, 0, cos t_j); with F = R_n(rho) S_n^m(x),
 //   dF/drs = fac R_{n+1} (s.x) S_n^m + R_n s.grad S_n^m,
-// fac = -kw sc for the regular A_n and -kw / sc for the singular B_n.
-__global__ void k_h3d_coax_sample(H3DTr tr)
+// fac = -kw sc for the regular A_n and -kw / sc for the singular B_n.  The
+// column's coefficients of orders +m and -m are staged in LDS first.
+__global__ __launch_bounds__(128) void k_h3d_coax_sample(H3DTr tr)
 {
+    __shared__ cplx cpm[2][kPMaxH3 + 1];
     int Ps = tr.Ps, nq = tr.nq;
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)tr.np * (Ps + 1) * nq) return;
-    int j = (int)(gid % nq);
-    int am = (int)((gid / nq) % (Ps + 1));
-    int i = (int)(gid / ((int64_t)nq * (Ps + 1)));
+    int am = blockIdx.x % (Ps + 1);
+    int i = blockIdx.x / (Ps + 1);
+    int j = threadIdx.x;
+    const cplx* a = tr.A + (size_t)i * tr.sA;
+    for (int n = am + threadIdx.x; n <= Ps; n += blockDim.x) {
+        cpm[0][n] = a[hnm(n, am)];
+        cpm[1][n] = a[hnm(n, -am)];
+    }
+    __syncthreads();
+    if (j >= nq) return;
     cplx t = tr.geo[(size_t)i * 10 + 9];
     double s1 = tr.sth[j], s3 = tr.cth[j];
     cplx x1 = mk(tr.rs * s1, 0.0);
@@ -593,7 +600,6 @@ __global__ void k_h3d_coax_sample(H3DTr tr)
     cplx sx = s1 * x1 + s3 * x3;
     cplx dr2 = 2.0 * sx;
     const cplx* R = tr.R + (size_t)i * tr.sR + j;
-    const cplx* a = tr.A + (size_t)i * tr.sA;
     double fac = tr.src_h ? -tr.ks / tr.sc : -tr.ks * tr.sc;
     // diagonal start c_m x1^m and its derivative c_m m x1^{m-1} s1
     cplx D = mk(c_cs[am], 0.0), dD = mk(0.0, 0.0);
@@ -608,20 +614,22 @@ __global__ void k_h3d_coax_sample(H3DTr tr)
     cplx fp = mk(0.0, 0.0), fm = fp, gp = fp, gm = fp;
     cplx q0 = mk(0.0, 0.0), q1 = mk(1.0, 0.0), dq0 = q0, dq1 = q0;
     cplx z = x3, dz = mk(s3, 0.0);
+    cplx Rn = R[(size_t)am * nq];
     for (int n = am; n <= Ps; ++n) {
         if (n > am) col_step(n, am, z, dz, r2, dr2, q0, q1, dq0, dq1);
         cplx S = D * q1, dS = dD * q1 + D * dq1;
-        cplx Rn = R[(size_t)n * nq], Rn1 = R[(size_t)(n + 1) * nq];
+        cplx Rn1 = R[(size_t)(n + 1) * nq];
         cplx f = Rn * S;
         cplx gg = (fac * Rn1) * (sx * S) + Rn * dS;
-        cplx cp = a[hnm(n, am)];
+        cplx cp = cpm[0][n];
         fp += cp * f;
         gp += cp * gg;
         if (am) {
-            cplx cm = a[hnm(n, -am)];
+            cplx cm = cpm[1][n];
             fm += cm * f;
             gm += cm * gg;
         }
+        Rn = Rn1;
     }
     // samples stored pair-fastest for the projection GEMM:
     // fg[((m + Ps) nq + j) np + i] = (f.re, f.im, g.re, g.im)
@@ -792,6 +800,8 @@ hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_sr
                          const double* eq_p0, const double* eq_d0, hipStream_t st)
 {
     if (tr.np <= 0) return hipSuccess;
+    // one thread per node or per equator sample in the sampling kernels
+    if (tr.nq > 128 || 2 * tr.Ps + 1 > 128 || 2 * tr.Pt + 1 > 128) return hipErrorInvalidValue;
     const int bs = 256;
     constexpr int NB = 8;
     k_h3d_geo<<<blocks(tr.np, bs), bs, 0, st>>>(tr, tv);
@@ -807,8 +817,7 @@ hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_sr
     k_h3d_rot_dft<<<blocks(n2, bs), bs, sizeof(double) * 2 * (2 * Ps + 1), st>>>(tr, 0, eq_p0, eq_d0);
     int64_t n3 = (int64_t)tr.np * tr.nq;
     k_h3d_coax_radial<<<blocks(n3, bs), bs, 0, st>>>(tr);
-    int64_t n4 = (int64_t)tr.np * (Ps + 1) * tr.nq;
-    k_h3d_coax_sample<<<blocks(n4, bs), bs, 0, st>>>(tr);
+    k_h3d_coax_sample<<<(unsigned)((int64_t)tr.np * (Ps + 1)), tr.nq <= 64 ? 64 : 128, 0, st>>>(tr);
     int64_t n5 = (int64_t)tr.np * (Pt + 1) * (Pt + 1);
     int64_t nwave = (int64_t)(2 * Pt + 1) * ((Pt + 16) / 16) * ((tr.np + 3) / 4);
     k_h3d_coax_proj<<<(unsigned)((nwave + 3) / 4), 256, 0, st>>>(tr);

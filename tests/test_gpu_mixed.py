@@ -59,3 +59,25 @@ def test_full_size_mixed_sampled_parity(ci, kernel):
     em = oracle.rel_l2(um[tg], u0)
     print(f"[gpu] {cfg.name} full n={cfg.n} mixed rel_l2={em:.3e}", flush=True)
     assert em <= 1e-6
+
+
+# 3D Laplace M2L in mixed precision: FP32 contraction for P <= 16 when
+# tol >= 1e-6 (P = 9 and 14 here with separation 2), FP64 otherwise (P = 17
+# with separation 1); both against the oracle and the FP64 plan.
+@pytest.mark.parametrize("tol,sep", [(1e-4, 2), (1e-6, 2), (1e-4, 1)])
+def test_laplace_mixed_m2l(tol, sep):
+    cfg = synth.make_config(2, n=44 * 44)
+    u0 = oracle.direct_self(3, "laplace", 0.0, cfg.points, cfg.sigma, nthreads=NTHREADS)
+    print(f"[gpu] laplace mixed m2l tol={tol} sep={sep}", flush=True)
+    outs = {}
+    for prec in ("mixed", "fp64"):
+        plan = cf.Plan(torch.from_numpy(cfg.points).cuda(), "laplace", 0.0, tol, precision=prec, leaf_size=32,
+                       separation=sep)
+        u = plan(torch.from_numpy(cfg.sigma).cuda())
+        torch.cuda.synchronize()
+        outs[prec] = (u.cpu().numpy(), plan.info()["max_p"])
+    em, ed = oracle.rel_l2(outs["mixed"][0], u0), oracle.rel_l2(outs["fp64"][0], u0)
+    print(f"[gpu] P={outs['mixed'][1]}: mixed rel_l2={em:.3e}  fp64 rel_l2={ed:.3e}", flush=True)
+    assert em <= tol
+    # the mixed result stays within its rounding floor of the FP64 one
+    assert oracle.rel_l2(outs["mixed"][0], outs["fp64"][0]) <= 1e-6
