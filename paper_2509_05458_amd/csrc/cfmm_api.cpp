@@ -455,7 +455,28 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     if ((rc = upload(p, &p->d_cre, cre)) || (rc = p->alloc(&p->d_cim, (size_t)dim * nb)) ||
         (rc = p->alloc(&d_delta, nb)))
         return rc;
-    HIPCHK(launch_centres(p->d_pbeg, p->d_pend, nb, n, dim, p->d_xim, p->d_cim, d_delta, st));
+    int *d_cbox = nullptr, *d_cbeg = nullptr, *d_cend = nullptr, *d_coff = nullptr;
+    double *d_cpart = nullptr, *d_cpmax = nullptr;
+    {
+        std::vector<int> cbox, cbeg, cend, coff(nb + 1, 0);
+        for (int b = 0; b < nb; ++b) {
+            for (int i0 = t.pbeg[b]; i0 < t.pend[b]; i0 += kCentreChunk) {
+                cbox.push_back(b);
+                cbeg.push_back(i0);
+                cend.push_back(std::min(t.pend[b], i0 + kCentreChunk));
+            }
+            coff[b + 1] = (int)cbox.size();
+        }
+        CentreChunks ch;
+        if ((rc = upload(p, &d_cbox, cbox)) || (rc = upload(p, &d_cbeg, cbeg)) || (rc = upload(p, &d_cend, cend)) ||
+            (rc = upload(p, &d_coff, coff)) || (rc = p->alloc(&d_cpart, 3 * cbox.size() + 3)) ||
+            (rc = p->alloc(&d_cpmax, cbox.size() + 1)))
+            return rc;
+        ch.n = (int)cbox.size();
+        ch.box = d_cbox; ch.beg = d_cbeg; ch.end = d_cend; ch.off = d_coff;
+        ch.part = d_cpart; ch.pmax = d_cpmax;
+        HIPCHK(launch_centres(ch, p->d_pbeg, p->d_pend, nb, n, dim, p->d_xim, p->d_cim, d_delta, st));
+    }
     std::vector<double> delta(nb), cim((size_t)dim * nb);
     HIPCHK(hipMemcpyAsync(delta.data(), d_delta, nb * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(cim.data(), p->d_cim, (size_t)dim * nb * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -820,7 +841,8 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     // -------- release planning scratch; the plan keeps the rest resident
     HIPCHK(hipStreamSynchronize(st));
     for (void* q : {(void*)d_pts, (void*)d_part, (void*)d_bb, (void*)d_keys, (void*)d_keys2,
-                    (void*)d_idx2, (void*)d_scr, (void*)d_delta, (void*)d_flag}) {
+                    (void*)d_idx2, (void*)d_scr, (void*)d_delta, (void*)d_flag, (void*)d_cbox, (void*)d_cbeg,
+                    (void*)d_cend, (void*)d_coff, (void*)d_cpart, (void*)d_cpmax}) {
         auto it = std::find(p->allocs.begin(), p->allocs.end(), q);
         if (it != p->allocs.end()) {
             size_t k = it - p->allocs.begin();
@@ -999,6 +1021,9 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
                     tr.dst = p->d_h3_dst + C.pair_begin;
                     tr.Ps = S.Ps; tr.Pt = S.Pt; tr.nq = S.nq;
                     tr.src_h = S.src_h; tr.trg_h = S.trg_h;
+                    // mixed precision samples the M2L rotations in FP32 (angular
+                    // values only; M2M and L2L stay FP64)
+                    tr.f32 = kind == 1 && p->precision == CFMM_MIXED && p->tol >= 1e-6;
                     tr.ks = S.ks; tr.sc = S.sc; tr.rs = S.rs_s; tr.inv_w = S.inv_w;
                     tr.sth = p->d_h3_tabd + S.o_nodes;
                     tr.cth = tr.sth + S.nq;

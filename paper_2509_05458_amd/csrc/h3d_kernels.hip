@@ -44,6 +44,8 @@ namespace {
 constexpr int kT = kPMaxH3 + 3;       // recurrence tables cover n <= kPMaxH3 + 2
 __constant__ double c_ca[kT * kT];    // sqrt((n+m-1)(n-m-1))            [n * kT + m]
 __constant__ double c_cb[kT * kT];    // 1 / sqrt((n-m)(n+m)),  n > m
+__constant__ float c_caf[kT * kT];    // the same two tables rounded to FP32
+__constant__ float c_cbf[kT * kT];
 __constant__ double c_cs[kT];         // c_m = prod_{k<=m} sqrt((2k-1)/(2k))
 __constant__ double c_ck[kT];         // sqrt((2m-1)/(2m))
 
@@ -423,6 +425,31 @@ __global__ void k_h3d_rot_prep(H3DTr tr, int back, const int* __restrict__ eoff,
     tr.A[(size_t)i * tr.sA + c] = t;
 }
 
+// Complex arithmetic in the sampling type T (double, or float for the
+// mixed-precision M2L stages).
+template <class T>
+struct cz {
+    T re, im;
+};
+template <class T>
+__device__ inline cz<T> czmul(cz<T> a, cz<T> b)
+{
+    return cz<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T>
+__device__ inline void czfma(cz<T>& acc, cz<T> a, cz<T> b)
+{
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+}
+template <class T>
+__device__ inline cz<T> tocz(cplx a)
+{
+    return cz<T>{(T)a.re, (T)a.im};
+}
+
 // K1: rotation samples.  Workgroup (pair, n-block), thread = node j: x = Q y_j
 // (forward) or Q^T y_j (back); accumulates F_n(j) = sum_m a_n^m S_n^m(x) and,
 // from the derivative coefficients t of K1a, G_n(j) = sum_m t_{n-1}^m
@@ -430,12 +457,15 @@ __global__ void k_h3d_rot_prep(H3DTr tr, int back, const int* __restrict__ eoff,
 // diagonal start kept incrementally and folded into the column.  The block's
 // coefficients a_n^m (n = nlo-1..nhi) and t_n^m are staged in LDS first, so
 // the sweep reads them at one LDS address across the workgroup.  On the unit
-// sphere r2 = 1.
-template <int NB>
+// sphere r2 = 1, and the column step is
+//   q_n = ((2n-1) z q_{n-1} - sqrt((n+m-1)(n-m-1)) q_{n-2}) / sqrt((n-m)(n+m)).
+// T is the arithmetic type of the sweep (the samples are stored in FP64).
+template <int NB, class T>
 __global__ __launch_bounds__(128) void k_h3d_rot_sample(H3DTr tr, int back, const int* __restrict__ eoff,
                                                         const cplx* __restrict__ coef)
 {
-    extern __shared__ cplx cs[];
+    extern __shared__ double csraw[];
+    cz<T>* cs = reinterpret_cast<cz<T>*>(csraw);
     int P = back ? tr.Pt : tr.Ps;
     int J = 2 * P + 1;
     int nblk = (P + NB) / NB;
@@ -448,13 +478,14 @@ __global__ __launch_bounds__(128) void k_h3d_rot_sample(H3DTr tr, int back, cons
     int nlo = blk * NB, nhi = min(P, nlo + NB - 1);
     int n0 = nlo > 0 ? nlo - 1 : 0;
     int rows = nhi - n0 + 1;
-    cplx* ca = cs;                       // a_n^m at (n - n0) J + m + P
-    cplx* ct = cs + (size_t)(NB + 1) * J;
+    cz<T>* ca = cs;                       // a_n^m at (n - n0) J + m + P
+    cz<T>* ct = cs + (size_t)(NB + 1) * J;
+    cz<T> zero = {(T)0, (T)0};
     for (int e = threadIdx.x; e < rows * J; e += blockDim.x) {
         int nn = n0 + e / J, mm = e % J - P;
         bool in = mm >= -nn && mm <= nn;
-        ca[e] = in ? a[hnm(nn, mm)] : mk(0.0, 0.0);
-        ct[e] = (in && nn < P) ? at[hnm(nn, mm)] : mk(0.0, 0.0);
+        ca[e] = in ? tocz<T>(a[hnm(nn, mm)]) : zero;
+        ct[e] = (in && nn < P) ? tocz<T>(at[hnm(nn, mm)]) : zero;
     }
     __syncthreads();
     if (j >= J) return;
@@ -467,38 +498,57 @@ __global__ __launch_bounds__(128) void k_h3d_rot_sample(H3DTr tr, int back, cons
     } else {
         x.x = cp * g[0] + sp * g[3]; x.y = cp * g[1] + sp * g[4]; x.z = cp * g[2] + sp * g[5];
     }
-    cplx F[NB], G[NB];
+    cz<T> z = tocz<T>(x.z);
+    cz<T> F[NB], G[NB];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) { F[k] = mk(0.0, 0.0); G[k] = mk(0.0, 0.0); }
-    cplx one = mk(1.0, 0.0), zero = mk(0.0, 0.0);
+    for (int k = 0; k < NB; ++k) { F[k] = zero; G[k] = zero; }
     for (int sgn = 0; sgn < 2; ++sgn) {
-        cplx w = sgn ? mk(x.x.re + x.y.im, x.x.im - x.y.re) : mk(x.x.re - x.y.im, x.x.im + x.y.re);
-        cplx D = one;
+        cz<T> w = tocz<T>(sgn ? mk(x.x.re + x.y.im, x.x.im - x.y.re) : mk(x.x.re - x.y.im, x.x.im + x.y.re));
+        cz<T> D = {(T)1, (T)0};
         for (int am = 0; am <= nhi; ++am) {
-            if (am > 0) D = (D * w) * c_ck[am];
+            if (am > 0) {
+                D = czmul(D, w);
+                D.re *= (T)c_ck[am];
+                D.im *= (T)c_ck[am];
+            }
             if (sgn && am == 0) continue;
             int m = sgn ? -am : am;
-            const cplx* cam = ca + (m + P);   // cam[(n - n0) J] = a_n^m
-            const cplx* ctm = ct + (m + P);
-            cplx q0 = zero, q1 = D;
+            const cz<T>* cam = ca + (m + P);   // cam[(n - n0) J] = a_n^m
+            const cz<T>* ctm = ct + (m + P);
+            cz<T> q0 = zero, q1 = D;
             int n = am;
+            auto step = [&](int nn) {
+                T ca_, cb_;
+                if (sizeof(T) == 4) {
+                    ca_ = (T)c_caf[nn * kT + am];
+                    cb_ = (T)c_cbf[nn * kT + am];
+                } else {
+                    ca_ = (T)c_ca[nn * kT + am];
+                    cb_ = (T)c_cb[nn * kT + am];
+                }
+                T s2 = (T)(2 * nn - 1);
+                cz<T> zq = czmul(z, q1);
+                cz<T> q2 = {(s2 * zq.re - ca_ * q0.re) * cb_, (s2 * zq.im - ca_ * q0.im) * cb_};
+                q0 = q1;
+                q1 = q2;
+            };
             // advance to n = nlo - 1 when the column starts below the block
             while (n < nlo - 1) {
                 ++n;
-                col_step_nd(n, am, x.z, one, q0, q1);
+                step(n);
             }
             // G of degree nlo takes the column at nlo - 1
-            if (nlo >= 1 && n == nlo - 1) cfma(G[0], ctm[(n - n0) * J], q1);
+            if (nlo >= 1 && n == nlo - 1) czfma(G[0], ctm[(n - n0) * J], q1);
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 int nn = nlo + k;
                 if (nn > nhi || nn < am) continue;
                 if (nn > n) {
-                    col_step_nd(nn, am, x.z, one, q0, q1);
+                    step(nn);
                     n = nn;
                 }
-                cfma(F[k], cam[(nn - n0) * J], q1);
-                if (k + 1 < NB && nn + 1 <= nhi) cfma(G[k + 1], ctm[(nn - n0) * J], q1);
+                czfma(F[k], cam[(nn - n0) * J], q1);
+                if (k + 1 < NB && nn + 1 <= nhi) czfma(G[k + 1], ctm[(nn - n0) * J], q1);
             }
         }
     }
@@ -507,8 +557,8 @@ __global__ __launch_bounds__(128) void k_h3d_rot_sample(H3DTr tr, int back, cons
     for (int k = 0; k < NB; ++k) {
         int nn = nlo + k;
         if (nn > nhi) break;
-        FG[(size_t)nn * J + j] = F[k];
-        FG[(size_t)(P + 1) * J + (size_t)nn * J + j] = G[k];
+        FG[(size_t)nn * J + j] = mk((double)F[k].re, (double)F[k].im);
+        FG[(size_t)(P + 1) * J + (size_t)nn * J + j] = mk((double)G[k].re, (double)G[k].im);
     }
 }
 
@@ -740,6 +790,13 @@ hipError_t h3d_init_tables(int device)
     hipError_t e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_ca), ca, sizeof(ca))) != hipSuccess) return e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_cb), cb, sizeof(cb))) != hipSuccess) return e;
+    static float caf[kT * kT], cbf[kT * kT];
+    for (int k = 0; k < kT * kT; ++k) {
+        caf[k] = (float)ca[k];
+        cbf[k] = (float)cb[k];
+    }
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_caf), caf, sizeof(caf))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_cbf), cbf, sizeof(cbf))) != hipSuccess) return e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_cs), cs, sizeof(cs))) != hipSuccess) return e;
     return hipMemcpyToSymbol(HIP_SYMBOL(c_ck), ck, sizeof(ck));
 }
@@ -809,9 +866,13 @@ hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_sr
     k_h3d_rot_prep<<<blocks((int64_t)tr.np * Ps * Ps, bs), bs, 0, st>>>(tr, 0, eoff_src, coef_src);
     {
         int J = 2 * Ps + 1;
-        size_t lds = sizeof(cplx) * (size_t)2 * (NB + 1) * J;
-        k_h3d_rot_sample<NB><<<(unsigned)((int64_t)tr.np * ((Ps + NB) / NB)), J <= 64 ? 64 : 128, lds, st>>>(
-            tr, 0, eoff_src, coef_src);
+        unsigned grid = (unsigned)((int64_t)tr.np * ((Ps + NB) / NB));
+        if (tr.f32)
+            k_h3d_rot_sample<NB, float><<<grid, J <= 64 ? 64 : 128, 8 * (size_t)2 * (NB + 1) * J, st>>>(
+                tr, 0, eoff_src, coef_src);
+        else
+            k_h3d_rot_sample<NB, double><<<grid, J <= 64 ? 64 : 128, 16 * (size_t)2 * (NB + 1) * J, st>>>(
+                tr, 0, eoff_src, coef_src);
     }
     int64_t n2 = (int64_t)tr.np * (Ps + 1) * (Ps + 1);
     k_h3d_rot_dft<<<blocks(n2, bs), bs, sizeof(double) * 2 * (2 * Ps + 1), st>>>(tr, 0, eq_p0, eq_d0);
@@ -824,9 +885,13 @@ hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_sr
     k_h3d_rot_prep<<<blocks((int64_t)tr.np * Pt * Pt, bs), bs, 0, st>>>(tr, 1, nullptr, nullptr);
     {
         int J = 2 * Pt + 1;
-        size_t lds = sizeof(cplx) * (size_t)2 * (NB + 1) * J;
-        k_h3d_rot_sample<NB><<<(unsigned)((int64_t)tr.np * ((Pt + NB) / NB)), J <= 64 ? 64 : 128, lds, st>>>(
-            tr, 1, nullptr, nullptr);
+        unsigned grid = (unsigned)((int64_t)tr.np * ((Pt + NB) / NB));
+        if (tr.f32)
+            k_h3d_rot_sample<NB, float><<<grid, J <= 64 ? 64 : 128, 8 * (size_t)2 * (NB + 1) * J, st>>>(
+                tr, 1, nullptr, nullptr);
+        else
+            k_h3d_rot_sample<NB, double><<<grid, J <= 64 ? 64 : 128, 16 * (size_t)2 * (NB + 1) * J, st>>>(
+                tr, 1, nullptr, nullptr);
     }
     k_h3d_rot_dft<<<blocks(n5, bs), bs, sizeof(double) * 2 * (2 * Pt + 1), st>>>(tr, 1, eq_p0, eq_d0);
     int64_t n7 = (int64_t)ng * (Pt + 1) * (Pt + 1);

@@ -26,8 +26,19 @@ hipError_t launch_gather_points(const double* pts, const int* perm, int64_t n, i
                                 double* xre, double* xim, hipStream_t st);
 hipError_t launch_gather_density(const double* sig, const int* perm, int64_t n, double* sre,
                                  double* sim, hipStream_t st);
-hipError_t launch_centres(const int* pbeg, const int* pend, int nbox, int64_t n, int dim,
-                          const double* xim, double* cim, double* delta, hipStream_t st);
+// Boxes cut into chunks of at most kCentreChunk points for the centre pass.
+constexpr int kCentreChunk = 4096;
+struct CentreChunks {
+    int n;                 // chunks
+    const int* box;        // [n] owning box
+    const int* beg;        // [n] point range
+    const int* end;
+    const int* off;        // [nbox + 1] chunks of each box
+    double* part;          // [3 n] scratch: per-chunk sums
+    double* pmax;          // [n] scratch: per-chunk largest squared spread
+};
+hipError_t launch_centres(const CentreChunks& ch, const int* pbeg, const int* pend, int nbox, int64_t n,
+                          int dim, const double* xim, double* cim, double* delta, hipStream_t st);
 hipError_t launch_check_near(const int* leaves, int nleaf, const int* pbeg, const int* pend,
                              const int* l1off, const int* l1idx, int64_t n, int dim,
                              const double* xre, const double* xim, int* flag, hipStream_t st);
@@ -141,6 +152,7 @@ struct H3DTr {
     const int* dst;         // target box per pair
     int Ps, Pt, nq;         // source / target expansion lengths, coaxial nodes
     int src_h, trg_h;       // 1: singular (multipole) expansion, 0: regular (local)
+    int f32;                // 1: rotation sampling in FP32 (mixed-precision M2L)
     double ks, sc;          // kappa w_src and the source level's scale
     double rs;              // coaxial sampling radius / w_src
     double inv_w;           // 1 / w_src

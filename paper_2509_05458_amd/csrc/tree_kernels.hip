@@ -218,18 +218,18 @@ __global__ void k_gather_density(const double* __restrict__ sig, const int* __re
     sim[i] = sig[2 * p + 1];
 }
 
-// Complexified centres: real part from the tree, imaginary part the mean of
-// Im over the box's points (fixed-order block reduction); delta[b] the
-// largest distance of a point's imaginary part from the centre's.
-__global__ void k_centres(const int* __restrict__ pbeg, const int* __restrict__ pend, int nbox,
-                          int64_t n, int dim, const double* __restrict__ xim,
-                          double* __restrict__ cim, double* __restrict__ delta)
+// Complexified centres (a4): the mean imaginary part of each box's points and
+// their largest imaginary spread about it.  Boxes are cut into chunks of at
+// most kCentreChunk points (the root holds all N), so every level runs in
+// parallel: per chunk a block sum, per box the chunk sums in order, then per
+// chunk the largest squared spread and per box its maximum.
+__global__ void k_chunk_sum(const int* __restrict__ cbeg, const int* __restrict__ cend, int64_t n, int dim,
+                            const double* __restrict__ xim, double* __restrict__ part)
 {
     __shared__ double s[3][256];
-    int b = blockIdx.x, t = threadIdx.x;
-    int b0 = pbeg[b], b1 = pend[b];
+    int c = blockIdx.x, t = threadIdx.x;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int i = b0 + t; i < b1; i += blockDim.x)
+    for (int i = cbeg[c] + t; i < cend[c]; i += blockDim.x)
         for (int d = 0; d < dim; ++d) acc[d] += xim[d * n + i];
     for (int d = 0; d < 3; ++d) s[d][t] = acc[d];
     __syncthreads();
@@ -238,12 +238,34 @@ __global__ void k_centres(const int* __restrict__ pbeg, const int* __restrict__ 
             for (int d = 0; d < 3; ++d) s[d][t] += s[d][t + st];
         __syncthreads();
     }
-    double mean[3];
-    double inv = 1.0 / (double)(b1 - b0);
-    for (int d = 0; d < 3; ++d) mean[d] = s[d][0] * inv;
-    __syncthreads();
+    if (t == 0)
+        for (int d = 0; d < 3; ++d) part[3 * c + d] = s[d][0];
+}
+
+__global__ void k_box_mean(const int* __restrict__ coff, const int* __restrict__ pbeg,
+                           const int* __restrict__ pend, int nbox, int dim, const double* __restrict__ part,
+                           double* __restrict__ cim)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int c = coff[b]; c < coff[b + 1]; ++c)
+        for (int d = 0; d < 3; ++d) acc[d] += part[3 * c + d];
+    double inv = 1.0 / (double)(pend[b] - pbeg[b]);
+    for (int d = 0; d < dim; ++d) cim[d * nbox + b] = acc[d] * inv;
+}
+
+__global__ void k_chunk_spread(const int* __restrict__ cbox, const int* __restrict__ cbeg,
+                               const int* __restrict__ cend, int nbox, int64_t n, int dim,
+                               const double* __restrict__ xim, const double* __restrict__ cim,
+                               double* __restrict__ pmax)
+{
+    __shared__ double s[256];
+    int c = blockIdx.x, t = threadIdx.x, b = cbox[c];
+    double mean[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < dim; ++d) mean[d] = cim[d * nbox + b];
     double dm = 0.0;
-    for (int i = b0 + t; i < b1; i += blockDim.x) {
+    for (int i = cbeg[c] + t; i < cend[c]; i += blockDim.x) {
         double q = 0.0;
         for (int d = 0; d < dim; ++d) {
             double e = xim[d * n + i] - mean[d];
@@ -251,16 +273,23 @@ __global__ void k_centres(const int* __restrict__ pbeg, const int* __restrict__ 
         }
         dm = fmax(dm, q);
     }
-    s[0][t] = dm;
+    s[t] = dm;
     __syncthreads();
     for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-        if (t < st) s[0][t] = fmax(s[0][t], s[0][t + st]);
+        if (t < st) s[t] = fmax(s[t], s[t + st]);
         __syncthreads();
     }
-    if (t == 0) {
-        for (int d = 0; d < dim; ++d) cim[d * nbox + b] = mean[d];
-        delta[b] = sqrt(s[0][0]);
-    }
+    if (t == 0) pmax[c] = s[0];
+}
+
+__global__ void k_box_delta(const int* __restrict__ coff, int nbox, const double* __restrict__ pmax,
+                            double* __restrict__ delta)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    double m = 0.0;
+    for (int c = coff[b]; c < coff[b + 1]; ++c) m = fmax(m, pmax[c]);
+    delta[b] = sqrt(m);
 }
 
 // Flags a near pair (List 1) with Re r^2 <= 0 and r^2 != 0: the principal
@@ -369,10 +398,14 @@ hipError_t launch_gather_density(const double* sig, const int* perm, int64_t n, 
     return hipGetLastError();
 }
 
-hipError_t launch_centres(const int* pbeg, const int* pend, int nbox, int64_t n, int dim,
-                          const double* xim, double* cim, double* delta, hipStream_t st)
+hipError_t launch_centres(const CentreChunks& ch, const int* pbeg, const int* pend, int nbox, int64_t n,
+                          int dim, const double* xim, double* cim, double* delta, hipStream_t st)
 {
-    k_centres<<<nbox, 256, 0, st>>>(pbeg, pend, nbox, n, dim, xim, cim, delta);
+    if (nbox <= 0 || ch.n <= 0) return hipSuccess;
+    k_chunk_sum<<<ch.n, 256, 0, st>>>(ch.beg, ch.end, n, dim, xim, ch.part);
+    k_box_mean<<<(nbox + 255) / 256, 256, 0, st>>>(ch.off, pbeg, pend, nbox, dim, ch.part, cim);
+    k_chunk_spread<<<ch.n, 256, 0, st>>>(ch.box, ch.beg, ch.end, nbox, n, dim, xim, cim, ch.pmax);
+    k_box_delta<<<(nbox + 255) / 256, 256, 0, st>>>(ch.off, nbox, ch.pmax, delta);
     return hipGetLastError();
 }
 
