@@ -306,6 +306,9 @@ __global__ void k_check_near(const int* __restrict__ leaves, const int* __restri
     for (int i = pbeg[b] + threadIdx.x; i < pend[b]; i += blockDim.x) {
         for (int e = l1off[b]; e < l1off[b + 1]; ++e) {
             int a = l1idx[e];
+            // List 1 is symmetric and s is the same for (i, j) and (j, i): each
+            // unordered leaf pair is checked once, from its lower leaf
+            if (a < b) continue;
             for (int j = pbeg[a]; j < pend[a]; ++j) {
                 double sr = 0.0, si = 0.0;
                 for (int d = 0; d < dim; ++d) {
