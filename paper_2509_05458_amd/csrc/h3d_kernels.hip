@@ -450,45 +450,57 @@ __device__ inline cz<T> tocz(cplx a)
     return cz<T>{(T)a.re, (T)a.im};
 }
 
-// K1: rotation samples.  Workgroup (pair, n-block), thread = node j: x = Q y_j
-// (forward) or Q^T y_j (back); accumulates F_n(j) = sum_m a_n^m S_n^m(x) and,
-// from the derivative coefficients t of K1a, G_n(j) = sum_m t_{n-1}^m
-// S_{n-1}^m(x) for the n of its block, sweeping the columns m with the
-// diagonal start kept incrementally and folded into the column.  The block's
-// coefficients a_n^m (n = nlo-1..nhi) and t_n^m are staged in LDS first, so
-// the sweep reads them at one LDS address across the workgroup.  On the unit
-// sphere r2 = 1, and the column step is
+// K1: rotation samples.  Workgroup (n-block, group of U pairs), thread =
+// (pair u of the group, node j): x = Q y_j (forward) or Q^T y_j (back);
+// accumulates F_n(j) = sum_m a_n^m S_n^m(x) and, from the derivative
+// coefficients t of K1a, G_n(j) = sum_m t_{n-1}^m S_{n-1}^m(x) for the n of
+// its block, sweeping the columns m with the diagonal start kept
+// incrementally and folded into the column.  Each pair's coefficients of the
+// block (a_n^m for n = nlo-1..nhi, t_n^m for n < P, in the packed n^2 + n + m
+// order) are staged in LDS first, so the sweep reads them at one LDS address
+// per pair.  With J = 2P + 1 nodes a pair fills only part of a wavefront at
+// small P; U pairs per workgroup keep the lanes busy.  On the unit sphere
+// r2 = 1, and the column step is
 //   q_n = ((2n-1) z q_{n-1} - sqrt((n+m-1)(n-m-1)) q_{n-2}) / sqrt((n-m)(n+m)).
 // T is the arithmetic type of the sweep (the samples are stored in FP64).
+// smax: LDS entries per pair and array (the largest block's count).
 template <int NB, class T>
-__global__ __launch_bounds__(128) void k_h3d_rot_sample(H3DTr tr, int back, const int* __restrict__ eoff,
-                                                        const cplx* __restrict__ coef)
+__global__ __launch_bounds__(256) void k_h3d_rot_sample(H3DTr tr, int back, const int* __restrict__ eoff,
+                                                        const cplx* __restrict__ coef, int U, int smax)
 {
     extern __shared__ double csraw[];
     cz<T>* cs = reinterpret_cast<cz<T>*>(csraw);
     int P = back ? tr.Pt : tr.Ps;
     int J = 2 * P + 1;
-    int nblk = (P + NB) / NB;
-    int blk = blockIdx.x % nblk;
-    int i = blockIdx.x / nblk;
-    int j = threadIdx.x;
-    const cplx* g = tr.geo + (size_t)i * 10;
-    const cplx* a = back ? tr.B + (size_t)i * tr.sB : coef + eoff[tr.src[i]];
-    const cplx* at = tr.A + (size_t)i * tr.sA;
+    int wpb = (tr.np + U - 1) / U;            // workgroups per n-block
+    int blk = blockIdx.x / wpb;
+    int i0 = (blockIdx.x - blk * wpb) * U;
     int nlo = blk * NB, nhi = min(P, nlo + NB - 1);
     int n0 = nlo > 0 ? nlo - 1 : 0;
-    int rows = nhi - n0 + 1;
-    cz<T>* ca = cs;                       // a_n^m at (n - n0) J + m + P
-    cz<T>* ct = cs + (size_t)(NB + 1) * J;
-    cz<T> zero = {(T)0, (T)0};
-    for (int e = threadIdx.x; e < rows * J; e += blockDim.x) {
-        int nn = n0 + e / J, mm = e % J - P;
-        bool in = mm >= -nn && mm <= nn;
-        ca[e] = in ? tocz<T>(a[hnm(nn, mm)]) : zero;
-        ct[e] = (in && nn < P) ? tocz<T>(at[hnm(nn, mm)]) : zero;
+    int na = (nhi + 1) * (nhi + 1) - n0 * n0;            // a_n^m, n = n0..nhi
+    int nt1 = min(nhi, P - 1) + 1;
+    int nt = nt1 > n0 ? nt1 * nt1 - n0 * n0 : 0;         // t_n^m, n = n0..min(nhi, P-1)
+    for (int e = threadIdx.x; e < U * na; e += blockDim.x) {
+        int u = e / na, k = e - u * na;
+        int iu = min(i0 + u, tr.np - 1);
+        const cplx* a = back ? tr.B + (size_t)iu * tr.sB : coef + eoff[tr.src[iu]];
+        cz<T>* cu = cs + (size_t)u * 2 * smax;
+        cu[k] = tocz<T>(a[n0 * n0 + k]);
+        if (k < nt) cu[smax + k] = tocz<T>(tr.A[(size_t)iu * tr.sA + n0 * n0 + k]);
     }
     __syncthreads();
-    if (j >= J) return;
+    int u = threadIdx.x / J;
+    if (u >= U) return;
+    int j = threadIdx.x - u * J;
+    int i = i0 + u;
+    bool own = i < tr.np;                     // the group's tail repeats the last pair
+    if (!own) i = tr.np - 1;
+    const cplx* g = tr.geo + (size_t)i * 10;
+    // ca[hnm(n, m) - n0^2] = a_n^m and ct[hnm(n, m) - n0^2] = t_n^m for the block's rows
+    const cz<T>* ca = cs + (size_t)u * 2 * smax;
+    const cz<T>* ct = ca + smax;
+    int h0 = n0 * n0;
+    cz<T> zero = {(T)0, (T)0};
     double sp, cp;
     sincospi(2.0 * j / J, &sp, &cp);
     // x = M y with y = (cp, sp, 0); M = Q or Q^T
@@ -513,8 +525,6 @@ __global__ __launch_bounds__(128) void k_h3d_rot_sample(H3DTr tr, int back, cons
             }
             if (sgn && am == 0) continue;
             int m = sgn ? -am : am;
-            const cz<T>* cam = ca + (m + P);   // cam[(n - n0) J] = a_n^m
-            const cz<T>* ctm = ct + (m + P);
             cz<T> q0 = zero, q1 = D;
             int n = am;
             auto step = [&](int nn) {
@@ -538,7 +548,7 @@ __global__ __launch_bounds__(128) void k_h3d_rot_sample(H3DTr tr, int back, cons
                 step(n);
             }
             // G of degree nlo takes the column at nlo - 1
-            if (nlo >= 1 && n == nlo - 1) czfma(G[0], ctm[(n - n0) * J], q1);
+            if (nlo >= 1 && n == nlo - 1) czfma(G[0], ct[hnm(n, m) - h0], q1);
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 int nn = nlo + k;
@@ -547,11 +557,12 @@ __global__ __launch_bounds__(128) void k_h3d_rot_sample(H3DTr tr, int back, cons
                     step(nn);
                     n = nn;
                 }
-                czfma(F[k], cam[(nn - n0) * J], q1);
-                if (k + 1 < NB && nn + 1 <= nhi) czfma(G[k + 1], ctm[(nn - n0) * J], q1);
+                czfma(F[k], ca[hnm(nn, m) - h0], q1);
+                if (k + 1 < NB && nn + 1 <= nhi) czfma(G[k + 1], ct[hnm(nn, m) - h0], q1);
             }
         }
     }
+    if (!own) return;
     cplx* FG = tr.FG + (size_t)i * tr.sFG;
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
@@ -622,26 +633,36 @@ __global__ void k_h3d_coax_radial(H3DTr tr)
     else radial_j(r2, tr.ks, tr.sc, tr.Ps + 1, R, tr.nq);
 }
 
-// K3: coaxial samples.  Workgroup (pair, order m >= 0), thread = node j: the
-// column of order m at x_j (y = 0, so S_n^-m = S_n^m there) with its
-// derivative along s_j = (sin t_j, 0, cos t_j); with F = R_n(rho) S_n^m(x),
+// K3: coaxial samples.  Workgroup (group of U pairs, order m >= 0), thread =
+// (pair u of the group, node j): the column of order m at x_j (y = 0, so
+// S_n^-m = S_n^m there) with its derivative along s_j = (sin t_j, 0, cos t_j);
+// with F = R_n(rho) S_n^m(x),
 //   dF/drs = fac R_{n+1} (s.x) S_n^m + R_n s.grad S_n^m,
-// fac = -kw sc for the regular A_n and -kw / sc for the singular B_n.  The
-// column's coefficients of orders +m and -m are staged in LDS first.
-__global__ __launch_bounds__(128) void k_h3d_coax_sample(H3DTr tr)
+// fac = -kw sc for the regular A_n and -kw / sc for the singular B_n.  Each
+// pair's column coefficients of orders +m and -m are staged in LDS first; U
+// pairs share a workgroup so that small node counts still fill the lanes.
+__global__ __launch_bounds__(256) void k_h3d_coax_sample(H3DTr tr, int U)
 {
-    __shared__ cplx cpm[2][kPMaxH3 + 1];
+    extern __shared__ cplx cpm[];   // [U][2][Ps + 1]
     int Ps = tr.Ps, nq = tr.nq;
     int am = blockIdx.x % (Ps + 1);
-    int i = blockIdx.x / (Ps + 1);
-    int j = threadIdx.x;
-    const cplx* a = tr.A + (size_t)i * tr.sA;
-    for (int n = am + threadIdx.x; n <= Ps; n += blockDim.x) {
-        cpm[0][n] = a[hnm(n, am)];
-        cpm[1][n] = a[hnm(n, -am)];
+    int i0 = (blockIdx.x / (Ps + 1)) * U;
+    int cnt = Ps + 1 - am;
+    for (int e = threadIdx.x; e < U * cnt; e += blockDim.x) {
+        int u = e / cnt, n = am + (e - u * cnt);
+        const cplx* a = tr.A + (size_t)min(i0 + u, tr.np - 1) * tr.sA;
+        cpm[(2 * u) * (Ps + 1) + n] = a[hnm(n, am)];
+        cpm[(2 * u + 1) * (Ps + 1) + n] = a[hnm(n, -am)];
     }
     __syncthreads();
-    if (j >= nq) return;
+    int u = threadIdx.x / nq;
+    if (u >= U) return;
+    int j = threadIdx.x - u * nq;
+    int i = i0 + u;
+    bool own = i < tr.np;                     // the group's tail repeats the last pair
+    if (!own) i = tr.np - 1;
+    const cplx* cpp = cpm + (2 * u) * (Ps + 1);
+    const cplx* cpn = cpp + (Ps + 1);
     cplx t = tr.geo[(size_t)i * 10 + 9];
     double s1 = tr.sth[j], s3 = tr.cth[j];
     cplx x1 = mk(tr.rs * s1, 0.0);
@@ -671,16 +692,17 @@ __global__ __launch_bounds__(128) void k_h3d_coax_sample(H3DTr tr)
         cplx Rn1 = R[(size_t)(n + 1) * nq];
         cplx f = Rn * S;
         cplx gg = (fac * Rn1) * (sx * S) + Rn * dS;
-        cplx cp = cpm[0][n];
+        cplx cp = cpp[n];
         fp += cp * f;
         gp += cp * gg;
         if (am) {
-            cplx cm = cpm[1][n];
+            cplx cm = cpn[n];
             fm += cm * f;
             gm += cm * gg;
         }
         Rn = Rn1;
     }
+    if (!own) return;
     // samples stored pair-fastest for the projection GEMM:
     // fg[((m + Ps) nq + j) np + i] = (f.re, f.im, g.re, g.im)
     double* o = (double*)tr.fg;
@@ -850,6 +872,53 @@ hipError_t h3d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const T
 }
 
 
+// Workgroup shape for a kernel whose item takes w consecutive threads: the
+// size in {64, 128, 192, 256} that leaves the fewest lanes idle (the smaller
+// one unless a larger one fills 2% more), with per-workgroup LDS lds(U) for U
+// items at most 64 KiB.  threads = 0 when no size fits.
+struct PackShape {
+    int threads, per;
+};
+template <class F>
+static PackShape pack_items(int w, F lds)
+{
+    PackShape best{0, 0};
+    double bu = -1.0;
+    for (int bt = 64; bt <= 256; bt += 64) {
+        int U = bt / w;
+        if (U < 1 || lds(U) > 65536) continue;
+        double util = (double)(U * w) / bt;
+        if (util > bu + 0.02) {
+            bu = util;
+            best = {bt, U};
+        }
+    }
+    return best;
+}
+
+template <int NB>
+static hipError_t launch_rot_sample(const H3DTr& tr, int back, const int* eoff, const cplx* coef, hipStream_t st)
+{
+    int P = back ? tr.Pt : tr.Ps;
+    int J = 2 * P + 1, nblk = (P + NB) / NB;
+    int smax = 0;
+    for (int b = 0; b < nblk; ++b) {
+        int nlo = b * NB, nhi = std::min(P, nlo + NB - 1), n0 = nlo > 0 ? nlo - 1 : 0;
+        smax = std::max(smax, (nhi + 1) * (nhi + 1) - n0 * n0);
+    }
+    size_t esz = tr.f32 ? 2 * sizeof(float) : 2 * sizeof(double);
+    PackShape pk = pack_items(J, [&](int U) { return (size_t)U * 2 * smax * esz; });
+    if (pk.threads == 0) return hipErrorInvalidValue;
+    int64_t wpb = (tr.np + pk.per - 1) / pk.per;
+    unsigned grid = (unsigned)(wpb * nblk);
+    size_t lds = (size_t)pk.per * 2 * smax * esz;
+    if (tr.f32)
+        k_h3d_rot_sample<NB, float><<<grid, pk.threads, lds, st>>>(tr, back, eoff, coef, pk.per, smax);
+    else
+        k_h3d_rot_sample<NB, double><<<grid, pk.threads, lds, st>>>(tr, back, eoff, coef, pk.per, smax);
+    return hipGetLastError();
+}
+
 // One chunk of a translation stage: pairs [0, tr.np) of the chunk, target
 // groups [0, ng) with pair ranges goff (chunk-relative).
 hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_src, const cplx* coef_src,
@@ -861,38 +930,27 @@ hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_sr
     if (tr.nq > 128 || 2 * tr.Ps + 1 > 128 || 2 * tr.Pt + 1 > 128) return hipErrorInvalidValue;
     const int bs = 256;
     constexpr int NB = 8;
+    hipError_t e;
     k_h3d_geo<<<blocks(tr.np, bs), bs, 0, st>>>(tr, tv);
     int Ps = tr.Ps, Pt = tr.Pt;
     k_h3d_rot_prep<<<blocks((int64_t)tr.np * Ps * Ps, bs), bs, 0, st>>>(tr, 0, eoff_src, coef_src);
-    {
-        int J = 2 * Ps + 1;
-        unsigned grid = (unsigned)((int64_t)tr.np * ((Ps + NB) / NB));
-        if (tr.f32)
-            k_h3d_rot_sample<NB, float><<<grid, J <= 64 ? 64 : 128, 8 * (size_t)2 * (NB + 1) * J, st>>>(
-                tr, 0, eoff_src, coef_src);
-        else
-            k_h3d_rot_sample<NB, double><<<grid, J <= 64 ? 64 : 128, 16 * (size_t)2 * (NB + 1) * J, st>>>(
-                tr, 0, eoff_src, coef_src);
-    }
+    if ((e = launch_rot_sample<NB>(tr, 0, eoff_src, coef_src, st)) != hipSuccess) return e;
     int64_t n2 = (int64_t)tr.np * (Ps + 1) * (Ps + 1);
     k_h3d_rot_dft<<<blocks(n2, bs), bs, sizeof(double) * 2 * (2 * Ps + 1), st>>>(tr, 0, eq_p0, eq_d0);
     int64_t n3 = (int64_t)tr.np * tr.nq;
     k_h3d_coax_radial<<<blocks(n3, bs), bs, 0, st>>>(tr);
-    k_h3d_coax_sample<<<(unsigned)((int64_t)tr.np * (Ps + 1)), tr.nq <= 64 ? 64 : 128, 0, st>>>(tr);
+    {
+        PackShape pk = pack_items(tr.nq, [&](int U) { return (size_t)U * 2 * (Ps + 1) * sizeof(cplx); });
+        if (pk.threads == 0) return hipErrorInvalidValue;
+        int64_t groups = (tr.np + pk.per - 1) / pk.per;
+        k_h3d_coax_sample<<<(unsigned)(groups * (Ps + 1)), pk.threads,
+                            (size_t)pk.per * 2 * (Ps + 1) * sizeof(cplx), st>>>(tr, pk.per);
+    }
     int64_t n5 = (int64_t)tr.np * (Pt + 1) * (Pt + 1);
     int64_t nwave = (int64_t)(2 * Pt + 1) * ((Pt + 16) / 16) * ((tr.np + 3) / 4);
     k_h3d_coax_proj<<<(unsigned)((nwave + 3) / 4), 256, 0, st>>>(tr);
     k_h3d_rot_prep<<<blocks((int64_t)tr.np * Pt * Pt, bs), bs, 0, st>>>(tr, 1, nullptr, nullptr);
-    {
-        int J = 2 * Pt + 1;
-        unsigned grid = (unsigned)((int64_t)tr.np * ((Pt + NB) / NB));
-        if (tr.f32)
-            k_h3d_rot_sample<NB, float><<<grid, J <= 64 ? 64 : 128, 8 * (size_t)2 * (NB + 1) * J, st>>>(
-                tr, 1, nullptr, nullptr);
-        else
-            k_h3d_rot_sample<NB, double><<<grid, J <= 64 ? 64 : 128, 16 * (size_t)2 * (NB + 1) * J, st>>>(
-                tr, 1, nullptr, nullptr);
-    }
+    if ((e = launch_rot_sample<NB>(tr, 1, nullptr, nullptr, st)) != hipSuccess) return e;
     k_h3d_rot_dft<<<blocks(n5, bs), bs, sizeof(double) * 2 * (2 * Pt + 1), st>>>(tr, 1, eq_p0, eq_d0);
     int64_t n7 = (int64_t)ng * (Pt + 1) * (Pt + 1);
     k_h3d_accum<<<blocks(n7, bs), bs, 0, st>>>(tr, gdst, goff, ng, eoff_dst, coef_dst);
