@@ -339,27 +339,46 @@ __global__ __launch_bounds__(256) void k_l3d_m2m(const int* __restrict__ boxes, 
 }
 
 // ------------------------------------------------------------------ M2L
-// One wavefront per target box.  For each List-2 source box the table
-// I_l^q(D / w), l <= 2P, is built by columns (one lane per order q) in LDS,
-// entry (l, q) at base[l] + q with zero guards (layout in l3d_layout.hpp), and
-// the source multipole is copied beside it.  The outputs are split into groups
-// of four consecutive orders (j, k0..k0+3), k0 = -j + 4g; a lane owns up to R
-// groups, as the layout's lane slots assign them.  Over the source
-// coefficients (n, m), read at one LDS address by the whole wavefront, a group
-// needs I_{j+n}^{m-k0-c}, c = 0..3: at fixed n these four entries slide one
-// place along the row l = j + n per step in m, so each step loads one table
-// entry for four complex multiply-adds, and the sixteen lanes of a quarter
-// wave read sixteen distinct bank slots.  Orders past k = j in the last group
-// of a row read guard or neighbouring entries and are discarded.
+// One workgroup of W wavefronts per target box.  For each List-2
+// source box the table I_l^q(D / w), l <= 2P, is built by columns (one lane per
+// order q) in LDS, entry (l, q) at base[l] + q with zero guards (layout in
+// l3d_layout.hpp), and the source multipole is copied beside it.  The outputs
+// are split into groups of four consecutive orders (j, k0..k0+3),
+// k0 = -j + 4g; a lane owns up to R groups, as the layout's lane slots assign
+// them.  Over the source coefficients (n, m), read at one LDS address by the
+// whole wavefront, a group needs I_{j+n}^{m-k0-c}, c = 0..3: at fixed n these
+// four entries slide one place along the row l = j + n per step in m, so each
+// step loads one table entry for four complex multiply-adds, and the sixteen
+// lanes of a quarter wave read sixteen distinct bank slots.  Orders past k = j
+// in the last group of a row read guard or neighbouring entries and are
+// discarded.  The W wavefronts of the workgroup share the table: each takes a
+// contiguous 1/W of the (P+1)^2 steps (n, m) in n^2 + n + m order, starting a
+// row segment with three loads of the window, and the partial sums meet in
+// LDS at the end, added in wavefront order.  Sharing the table lets W times as
+// many wavefronts reside per unit of LDS; the table itself is built by one
+// wavefront while the others wait, which caps W (measured best: 4 with the
+// FP64 table, 2 with the FP32 table of half the size).
+constexpr int kM2LWaves = 4;
+constexpr int kM2LWavesF32 = 2;
+
+// first and last row n of the steps [s0, s1) in n^2 + n + m order
+__device__ inline int step_row(int s)
+{
+    int n = (int)sqrt((double)s);
+    while (n * n > s) --n;
+    while ((n + 1) * (n + 1) <= s) ++n;
+    return n;
+}
+
 struct alignas(16) cplx16 {
     double re, im;
 };
 
 template <int R>
-__global__ __launch_bounds__(64) void k_l3d_m2l(const int* __restrict__ boxes, int nboxes, TreeView tv,
-                                                const int* __restrict__ map, int ntab,
-                                                const cplx* __restrict__ mpole,
-                                                cplx* __restrict__ local)
+__global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restrict__ boxes, int nboxes, TreeView tv,
+                                                 const int* __restrict__ map, int ntab,
+                                                 const cplx* __restrict__ mpole,
+                                                 cplx* __restrict__ local)
 {
     extern __shared__ cplx16 tab16[];
     int b = boxes[xcd_contiguous(blockIdx.x, nboxes)];
@@ -370,48 +389,55 @@ __global__ __launch_bounds__(64) void k_l3d_m2l(const int* __restrict__ boxes, i
     cplx* Ms = tab + ntab;
     int* base = reinterpret_cast<int*>(Ms + nc);
     double s = tv.rs[l];
-    int t = threadIdx.x;
+    int t = threadIdx.x, lane = t & 63;
+    int W = blockDim.x >> 6;
+    int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    int s0 = nc * wv / W, s1 = nc * (wv + 1) / W;   // this wavefront's steps
+    int na = step_row(s0), nb = s1 > s0 ? step_row(s1 - 1) : na - 1;
     int jg[R], kg[R];
     bool act[R];
     cplx acc[R][4];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        int code = map[2 * P + 1 + t + 64 * r];
+        int code = map[2 * P + 1 + lane + 64 * r];
         jg[r] = code & 255;
         kg[r] = -jg[r] + 4 * ((code >> 8) & 255);
         act[r] = (code >> 16) & 1;
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = mk(0.0, 0.0);
     }
-    for (int i = t; i < ntab; i += 64) tab[i] = mk(0.0, 0.0);
-    for (int i = t; i <= 2 * P; i += 64) base[i] = map[i];
+    for (int i = t; i < ntab; i += blockDim.x) tab[i] = mk(0.0, 0.0);
+    for (int i = t; i <= 2 * P; i += blockDim.x) base[i] = map[i];
     cplx cb[3];
     box_centre(tv, b, cb);
     for (int e = tv.l2off[b]; e < tv.l2off[b + 1]; ++e) {
         int a = tv.l2idx[e];
-        cplx ca[3];
-        box_centre(tv, a, ca);
-        Vec3 d;
-        d.x = (cb[0] - ca[0]) * s; d.y = (cb[1] - ca[1]) * s; d.z = (cb[2] - ca[2]) * s;
         const cplx* M = mpole + tv.eoff[a];
         __syncthreads();
-        for (int i = t; i < nc; i += 64) Ms[i] = M[i];
-        for (int q = t - 2 * P; q <= 2 * P; q += 64)
+        for (int i = t; i < nc; i += blockDim.x) Ms[i] = M[i];
+        if (t <= 4 * P) {
+            cplx ca[3];
+            box_centre(tv, a, ca);
+            Vec3 d;
+            d.x = (cb[0] - ca[0]) * s; d.y = (cb[1] - ca[1]) * s; d.z = (cb[2] - ca[2]) * s;
+            int q = t - 2 * P;
             col_I(d, q, 2 * P, false, [&](int n, cplx v) { tab[base[n] + q] = v; });
+        }
         __syncthreads();
-        for (int n = 0; n <= P; ++n) {
+        for (int n = na; n <= nb; ++n) {
+            int mlo = max(-n, s0 - n * n - n), mhi = min(n, s1 - 1 - n * n - n);
             const cplx* Mn = Ms + n * n + n;
             const cplx16* row[R];
             cplx16 w1[R], w2[R], w3[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 row[r] = tab16 + base[jg[r] + n] - kg[r];
-                w1[r] = row[r][-n - 1];
-                w2[r] = row[r][-n - 2];
-                w3[r] = row[r][-n - 3];
+                w1[r] = row[r][mlo - 1];
+                w2[r] = row[r][mlo - 2];
+                w3[r] = row[r][mlo - 3];
             }
 #pragma unroll 4
-            for (int m = -n; m <= n; ++m) {
+            for (int m = mlo; m <= mhi; ++m) {
                 cplx am = Mn[m];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -427,6 +453,21 @@ __global__ __launch_bounds__(64) void k_l3d_m2l(const int* __restrict__ boxes, i
             }
         }
     }
+    // partial sums of wavefronts 1..W-1 through LDS (the table is free now)
+    __syncthreads();
+    if (wv > 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) tab[((size_t)((wv - 1) * R + r) * 4 + c) * 64 + lane] = acc[r][c];
+    }
+    __syncthreads();
+    if (wv > 0) return;
+    for (int w = 1; w < W; ++w)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] += tab[((size_t)((w - 1) * R + r) * 4 + c) * 64 + lane];
     cplx* o = local + tv.eoff[b];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -451,10 +492,10 @@ __global__ __launch_bounds__(64) void k_l3d_m2l(const int* __restrict__ boxes, i
 constexpr int kM2LF32MaxP = 16;
 
 template <int R>
-__global__ __launch_bounds__(64) void k_l3d_m2l_f32(const int* __restrict__ boxes, int nboxes, TreeView tv,
-                                                    const int* __restrict__ map, int ntab,
-                                                    const cplx* __restrict__ mpole,
-                                                    cplx* __restrict__ local)
+__global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __restrict__ boxes, int nboxes, TreeView tv,
+                                                     const int* __restrict__ map, int ntab,
+                                                     const cplx* __restrict__ mpole,
+                                                     cplx* __restrict__ local)
 {
     extern __shared__ float2 tabf[];
     int b = boxes[xcd_contiguous(blockIdx.x, nboxes)];
@@ -464,62 +505,69 @@ __global__ __launch_bounds__(64) void k_l3d_m2l_f32(const int* __restrict__ boxe
     float2* Ms = tabf + ntab;
     int* base = reinterpret_cast<int*>(Ms + nc);
     double s = tv.rs[l];
-    int t = threadIdx.x;
+    int t = threadIdx.x, lane = t & 63;
+    int W = blockDim.x >> 6;
+    int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    int s0 = nc * wv / W, s1 = nc * (wv + 1) / W;   // this wavefront's steps
+    int na = step_row(s0), nb = s1 > s0 ? step_row(s1 - 1) : na - 1;
     int jg[R], kg[R];
     bool act[R];
     cplx acc[R][4];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        int code = map[2 * P + 1 + t + 64 * r];
+        int code = map[2 * P + 1 + lane + 64 * r];
         jg[r] = code & 255;
         kg[r] = -jg[r] + 4 * ((code >> 8) & 255);
         act[r] = (code >> 16) & 1;
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = mk(0.0, 0.0);
     }
-    for (int i = t; i < ntab; i += 64) tabf[i] = make_float2(0.0f, 0.0f);
-    for (int i = t; i <= 2 * P; i += 64) base[i] = map[i];
+    for (int i = t; i < ntab; i += blockDim.x) tabf[i] = make_float2(0.0f, 0.0f);
+    for (int i = t; i <= 2 * P; i += blockDim.x) base[i] = map[i];
     cplx cb[3];
     box_centre(tv, b, cb);
     for (int e = tv.l2off[b]; e < tv.l2off[b + 1]; ++e) {
         int a = tv.l2idx[e];
-        cplx ca[3];
-        box_centre(tv, a, ca);
-        Vec3 d;
-        d.x = (cb[0] - ca[0]) * s; d.y = (cb[1] - ca[1]) * s; d.z = (cb[2] - ca[2]) * s;
         const cplx* M = mpole + tv.eoff[a];
         __syncthreads();
-        for (int i = t; i < nc; i += 64) Ms[i] = make_float2((float)M[i].re, (float)M[i].im);
-        for (int q = t - 2 * P; q <= 2 * P; q += 64)
+        for (int i = t; i < nc; i += blockDim.x) Ms[i] = make_float2((float)M[i].re, (float)M[i].im);
+        if (t <= 4 * P) {
+            cplx ca[3];
+            box_centre(tv, a, ca);
+            Vec3 d;
+            d.x = (cb[0] - ca[0]) * s; d.y = (cb[1] - ca[1]) * s; d.z = (cb[2] - ca[2]) * s;
+            int q = t - 2 * P;
             col_I(d, q, 2 * P, false,
                   [&](int n, cplx v) { tabf[base[n] + q] = make_float2((float)v.re, (float)v.im); });
+        }
         __syncthreads();
-        for (int n = 0; n <= P; ++n) {
+        for (int n = na; n <= nb; ++n) {
+            int mlo = max(-n, s0 - n * n - n), mhi = min(n, s1 - 1 - n * n - n);
             const float2* Mn = Ms + n * n + n;
             const float2* row[R];
             float2 w1[R], w2[R], w3[R], f[R][4];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 row[r] = tabf + base[jg[r] + n] - kg[r];
-                w1[r] = row[r][-n - 1];
-                w2[r] = row[r][-n - 2];
-                w3[r] = row[r][-n - 3];
+                w1[r] = row[r][mlo - 1];
+                w2[r] = row[r][mlo - 2];
+                w3[r] = row[r][mlo - 3];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) f[r][c] = make_float2(0.0f, 0.0f);
             }
 #pragma unroll 4
-            for (int m = -n; m <= n; ++m) {
+            for (int m = mlo; m <= mhi; ++m) {
                 float2 am = Mn[m];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     float2 w0 = row[r][m];
-                    float2 wv[4] = {w0, w1[r], w2[r], w3[r]};
+                    float2 wv4[4] = {w0, w1[r], w2[r], w3[r]};
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
-                        f[r][c].x = fmaf(am.x, wv[c].x, f[r][c].x);
-                        f[r][c].x = fmaf(-am.y, wv[c].y, f[r][c].x);
-                        f[r][c].y = fmaf(am.x, wv[c].y, f[r][c].y);
-                        f[r][c].y = fmaf(am.y, wv[c].x, f[r][c].y);
+                        f[r][c].x = fmaf(am.x, wv4[c].x, f[r][c].x);
+                        f[r][c].x = fmaf(-am.y, wv4[c].y, f[r][c].x);
+                        f[r][c].y = fmaf(am.x, wv4[c].y, f[r][c].y);
+                        f[r][c].y = fmaf(am.y, wv4[c].x, f[r][c].y);
                     }
                     w3[r] = w2[r];
                     w2[r] = w1[r];
@@ -532,6 +580,22 @@ __global__ __launch_bounds__(64) void k_l3d_m2l_f32(const int* __restrict__ boxe
                 for (int c = 0; c < 4; ++c) acc[r][c] += mk((double)f[r][c].x, (double)f[r][c].y);
         }
     }
+    // partial sums of wavefronts 1..W-1 through LDS (the table is free now)
+    cplx* red = reinterpret_cast<cplx*>(tabf);
+    __syncthreads();
+    if (wv > 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[((size_t)((wv - 1) * R + r) * 4 + c) * 64 + lane] = acc[r][c];
+    }
+    __syncthreads();
+    if (wv > 0) return;
+    for (int w = 1; w < W; ++w)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] += red[((size_t)((w - 1) * R + r) * 4 + c) * 64 + lane];
     cplx* o = local + tv.eoff[b];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -697,13 +761,28 @@ static hipError_t launch_m2l(const int* boxes, int nb, size_t lds, const TreeVie
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_l3d_m2l<R><<<nb, 64, lds, st>>>(boxes, nb, tv, map, ntab, mpole, local);
+    k_l3d_m2l<R><<<nb, 64 * kM2LWaves, lds, st>>>(boxes, nb, tv, map, ntab, mpole, local);
     return hipGetLastError();
+}
+
+// LDS of the M2L workgroup: the table, the source multipole and the row
+// bases, or the partial sums of wavefronts 1..W-1 if those need more.
+static size_t m2l_red_bytes(int R, int W)
+{
+    return (size_t)(W - 1) * R * 4 * 64 * sizeof(cplx);
+}
+
+static int m2l_groups_per_lane(int P)
+{
+    int G = 0;
+    for (int j = 0; j <= P; ++j) G += j / 2 + 1;
+    return (G + 63) / 64;
 }
 
 size_t l3d_m2l_lds(int P, int ntab)
 {
-    return (size_t)(ntab + (P + 1) * (P + 1)) * sizeof(cplx) + (size_t)(2 * P + 1) * sizeof(int);
+    size_t tab = (size_t)(ntab + (P + 1) * (P + 1)) * sizeof(cplx) + (size_t)(2 * P + 1) * sizeof(int);
+    return std::max(tab, m2l_red_bytes(m2l_groups_per_lane(P), kM2LWaves));
 }
 
 template <int R>
@@ -715,7 +794,7 @@ static hipError_t launch_m2l_f32(const int* boxes, int nb, size_t lds, const Tre
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_l3d_m2l_f32<R><<<nb, 64, lds, st>>>(boxes, nb, tv, map, ntab, mpole, local);
+    k_l3d_m2l_f32<R><<<nb, 64 * kM2LWavesF32, lds, st>>>(boxes, nb, tv, map, ntab, mpole, local);
     return hipGetLastError();
 }
 
@@ -724,7 +803,8 @@ hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const in
 {
     if (nb <= 0) return hipSuccess;
     if (mixed && P <= kM2LF32MaxP) {
-        size_t lds = (size_t)(ntab + (P + 1) * (P + 1)) * sizeof(float2) + (size_t)(2 * P + 1) * sizeof(int);
+        size_t lds = std::max((size_t)(ntab + (P + 1) * (P + 1)) * sizeof(float2) + (size_t)(2 * P + 1) * sizeof(int),
+                              m2l_red_bytes(R, kM2LWavesF32));
         switch (R) {
         case 1: return launch_m2l_f32<1>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
         case 2: return launch_m2l_f32<2>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
