@@ -992,7 +992,7 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         HIPCHK(mark(6));
         HIPCHK(h2d_p2p(p->near2, W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out, st));
     } else if (p->kernel == CFMM_HELMHOLTZ) {
-        H3DLevels hl{p->d_h3_kw, p->d_h3_sc};
+        H3DLevels hl{p->d_h3_kw, p->d_h3_sc, nullptr};
         HIPCHK(hipMemsetAsync(p->d_mpole, 0, p->ecount * sizeof(cplx), st));
         HIPCHK(hipMemsetAsync(p->d_local, 0, p->ecount * sizeof(cplx), st));
         // the P2M and P2L lists are in level order; one launch per level sizes

@@ -42,10 +42,32 @@ namespace cfmm {
 namespace {
 
 constexpr int kT = kPMaxH3 + 3;       // recurrence tables cover n <= kPMaxH3 + 2
-__constant__ double c_ca[kT * kT];    // sqrt((n+m-1)(n-m-1))            [n * kT + m]
-__constant__ double c_cb[kT * kT];    // 1 / sqrt((n-m)(n+m)),  n > m
-__constant__ float c_caf[kT * kT];    // the same two tables rounded to FP32
-__constant__ float c_cbf[kT * kT];
+// Column recurrence constants by column, entry [m * kT + n] for n > m:
+// s = (2n-1) b and a = sqrt((n+m-1)(n-m-1)) b with b = 1/sqrt((n-m)(n+m)),
+// so that Q_n = s z Q_{n-1} - a r2 Q_{n-2}.  A column's entries are
+// contiguous, so a few steps' constants come in one scalar load.
+struct alignas(16) RecAB {
+    double s, a;
+};
+struct alignas(8) RecABf {
+    float s, a;
+};
+__constant__ RecAB c_rab[kT * kT];
+__constant__ RecABf c_rabf[kT * kT];  // the same table rounded to FP32
+template <class T>
+struct RecOf {
+    typedef RecAB type;
+};
+template <>
+struct RecOf<float> {
+    typedef RecABf type;
+};
+// Device addresses of the two tables per device, taken once at set-up and
+// passed to the kernels as arguments (an argument pointer stays in scalar
+// registers; the symbol's address would be reloaded through the GOT).
+constexpr int kMaxDev = 64;
+const void* g_rab[kMaxDev];
+const void* g_rabf[kMaxDev];
 __constant__ double c_cs[kT];         // c_m = prod_{k<=m} sqrt((2k-1)/(2k))
 __constant__ double c_ck[kT];         // sqrt((2m-1)/(2m))
 
@@ -60,19 +82,19 @@ __device__ inline cplx dot(const V3& a, const V3& b) { return a.x * b.x + a.y * 
 
 // One column step: (q0, q1) = (Q_{n-2}, Q_{n-1}) -> Q_n, with its derivative
 // along a direction where z' = dz and (r2)' = dr2.
-__device__ inline void col_step(int n, int am, cplx z, cplx dz, cplx r2, cplx dr2, cplx& q0, cplx& q1,
+__device__ inline void col_step(const RecAB* col, int n, cplx z, cplx dz, cplx r2, cplx dr2, cplx& q0, cplx& q1,
                                 cplx& dq0, cplx& dq1)
 {
-    double a = c_ca[n * kT + am], b = c_cb[n * kT + am], s = 2.0 * n - 1.0;
-    cplx q2 = (s * (z * q1) - a * (r2 * q0)) * b;
-    cplx dq2 = (s * (dz * q1 + z * dq1) - a * (dr2 * q0 + r2 * dq0)) * b;
+    RecAB c = col[n];
+    cplx q2 = c.s * (z * q1) - c.a * (r2 * q0);
+    cplx dq2 = c.s * (dz * q1 + z * dq1) - c.a * (dr2 * q0 + r2 * dq0);
     q0 = q1; q1 = q2; dq0 = dq1; dq1 = dq2;
 }
 
-__device__ inline void col_step_nd(int n, int am, cplx z, cplx r2, cplx& q0, cplx& q1)
+__device__ inline void col_step_nd(const RecAB* col, int n, cplx z, cplx r2, cplx& q0, cplx& q1)
 {
-    double a = c_ca[n * kT + am], b = c_cb[n * kT + am], s = 2.0 * n - 1.0;
-    cplx q2 = (s * (z * q1) - a * (r2 * q0)) * b;
+    RecAB c = col[n];
+    cplx q2 = c.s * (z * q1) - c.a * (r2 * q0);
     q0 = q1; q1 = q2;
 }
 
@@ -208,6 +230,7 @@ __global__ __launch_bounds__(128) void k_h3d_p2x(const int* __restrict__ boxes, 
                                                  H3DLevels hl, int useL4, cplx* __restrict__ out)
 {
     extern __shared__ cplx lds[];
+    const RecAB* rec = static_cast<const RecAB*>(hl.rec);
     int b = boxes[blockIdx.x];
     int l = tv.level[b];
     int P = tv.P[l];
@@ -257,7 +280,7 @@ __global__ __launch_bounds__(128) void k_h3d_p2x(const int* __restrict__ boxes, 
                 cplx q0 = mk(0.0, 0.0), q1 = mk(1.0, 0.0);
                 acc[am * st + t] += D * rad[am * kPC + q];
                 for (int nn = am + 1; nn <= P; ++nn) {
-                    col_step_nd(nn, am, z, r2, q0, q1);
+                    col_step_nd(rec + am * kT, nn, z, r2, q0, q1);
                     acc[nn * st + t] += (D * q1) * rad[nn * kPC + q];
                 }
             }
@@ -280,6 +303,7 @@ __global__ __launch_bounds__(128) void k_h3d_p2x(const int* __restrict__ boxes, 
 __device__ inline cplx h3d_eval_point(int i, int a, bool loc, const TreeView& tv, const PointsView& pv,
                                       const H3DLevels& hl, const cplx* __restrict__ coef, cplx* my)
 {
+    const RecAB* rec = static_cast<const RecAB*>(hl.rec);
     int64_t n = pv.n;
     int nb = tv.nbox;
     int la = tv.level[a];
@@ -306,7 +330,7 @@ __device__ inline cplx h3d_eval_point(int i, int a, bool loc, const TreeView& tv
             cplx q0 = mk(0.0, 0.0), q1 = mk(1.0, 0.0);
             cplx s = C[hnm(am, m)] * my[am * 64];
             for (int nn = am + 1; nn <= P; ++nn) {
-                col_step_nd(nn, am, x[2], r2, q0, q1);
+                col_step_nd(rec + am * kT, nn, x[2], r2, q0, q1);
                 s += (C[hnm(nn, m)] * q1) * my[nn * 64];
             }
             u += D * s;
@@ -470,6 +494,8 @@ __global__ __launch_bounds__(256) void k_h3d_rot_sample(H3DTr tr, int back, cons
 {
     extern __shared__ double csraw[];
     cz<T>* cs = reinterpret_cast<cz<T>*>(csraw);
+    typedef typename RecOf<T>::type RecT;
+    const RecT* rec = static_cast<const RecT*>(sizeof(T) == 4 ? tr.recf : tr.rec);
     int P = back ? tr.Pt : tr.Ps;
     int J = 2 * P + 1;
     int wpb = (tr.np + U - 1) / U;            // workgroups per n-block
@@ -527,34 +553,50 @@ __global__ __launch_bounds__(256) void k_h3d_rot_sample(H3DTr tr, int back, cons
             int m = sgn ? -am : am;
             cz<T> q0 = zero, q1 = D;
             int n = am;
-            auto step = [&](int nn) {
-                T ca_, cb_;
-                if (sizeof(T) == 4) {
-                    ca_ = (T)c_caf[nn * kT + am];
-                    cb_ = (T)c_cbf[nn * kT + am];
-                } else {
-                    ca_ = (T)c_ca[nn * kT + am];
-                    cb_ = (T)c_cb[nn * kT + am];
-                }
-                T s2 = (T)(2 * nn - 1);
+            // (s, a) of column am at degree nn (r2 = 1 on the unit sphere)
+            auto coef = [&](int nn, T& cs_, T& ca_) {
+                RecT c = rec[am * kT + nn];
+                cs_ = (T)c.s;
+                ca_ = (T)c.a;
+            };
+            auto step = [&](T cs_, T ca_) {
                 cz<T> zq = czmul(z, q1);
-                cz<T> q2 = {(s2 * zq.re - ca_ * q0.re) * cb_, (s2 * zq.im - ca_ * q0.im) * cb_};
+                cz<T> q2 = {cs_ * zq.re - ca_ * q0.re, cs_ * zq.im - ca_ * q0.im};
                 q0 = q1;
                 q1 = q2;
             };
-            // advance to n = nlo - 1 when the column starts below the block
+            // advance to n = nlo - 1 when the column starts below the block,
+            // four steps per batch of constants
+            while (n + 4 <= nlo - 1) {
+                T s0, a0, s1, a1, s2, a2, s3, a3;
+                coef(n + 1, s0, a0);
+                coef(n + 2, s1, a1);
+                coef(n + 3, s2, a2);
+                coef(n + 4, s3, a3);
+                step(s0, a0);
+                step(s1, a1);
+                step(s2, a2);
+                step(s3, a3);
+                n += 4;
+            }
             while (n < nlo - 1) {
                 ++n;
-                step(n);
+                T s0, a0;
+                coef(n, s0, a0);
+                step(s0, a0);
             }
             // G of degree nlo takes the column at nlo - 1
             if (nlo >= 1 && n == nlo - 1) czfma(G[0], ct[hnm(n, m) - h0], q1);
+            // the block's constants, loaded before the sweep
+            T bs[NB], ba[NB];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) coef(min(nlo + k, kT - 1), bs[k], ba[k]);
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 int nn = nlo + k;
                 if (nn > nhi || nn < am) continue;
                 if (nn > n) {
-                    step(nn);
+                    step(bs[k], ba[k]);
                     n = nn;
                 }
                 czfma(F[k], ca[hnm(nn, m) - h0], q1);
@@ -645,8 +687,11 @@ __global__ __launch_bounds__(256) void k_h3d_coax_sample(H3DTr tr, int U)
 {
     extern __shared__ cplx cpm[];   // [U][2][Ps + 1]
     int Ps = tr.Ps, nq = tr.nq;
-    int am = blockIdx.x % (Ps + 1);
-    int i0 = (blockIdx.x / (Ps + 1)) * U;
+    // the Ps + 1 orders of one pair group run on one XCD, so that the group's
+    // radial values and coefficients are read from that XCD's L2
+    int wg = xcd_contiguous(blockIdx.x, gridDim.x);
+    int am = wg % (Ps + 1);
+    int i0 = (wg / (Ps + 1)) * U;
     int cnt = Ps + 1 - am;
     for (int e = threadIdx.x; e < U * cnt; e += blockDim.x) {
         int u = e / cnt, n = am + (e - u * cnt);
@@ -663,6 +708,7 @@ __global__ __launch_bounds__(256) void k_h3d_coax_sample(H3DTr tr, int U)
     if (!own) i = tr.np - 1;
     const cplx* cpp = cpm + (2 * u) * (Ps + 1);
     const cplx* cpn = cpp + (Ps + 1);
+    const RecAB* rec = static_cast<const RecAB*>(tr.rec) + am * kT;   // column am
     cplx t = tr.geo[(size_t)i * 10 + 9];
     double s1 = tr.sth[j], s3 = tr.cth[j];
     cplx x1 = mk(tr.rs * s1, 0.0);
@@ -683,15 +729,17 @@ __global__ __launch_bounds__(256) void k_h3d_coax_sample(H3DTr tr, int U)
         D = c_cs[am] * pw;
     }
     cplx fp = mk(0.0, 0.0), fm = fp, gp = fp, gm = fp;
-    cplx q0 = mk(0.0, 0.0), q1 = mk(1.0, 0.0), dq0 = q0, dq1 = q0;
+    // the diagonal start is folded into the column: Q = D q obeys the same
+    // recurrence as q, and its derivative dQ = dD q + D dq the differentiated
+    // one, so S_n^m = Q_n and its derivative is dQ_n
+    cplx q0 = mk(0.0, 0.0), q1 = D, dq0 = q0, dq1 = dD;
     cplx z = x3, dz = mk(s3, 0.0);
-    cplx Rn = R[(size_t)am * nq];
-    for (int n = am; n <= Ps; ++n) {
-        if (n > am) col_step(n, am, z, dz, r2, dr2, q0, q1, dq0, dq1);
-        cplx S = D * q1, dS = dD * q1 + D * dq1;
-        cplx Rn1 = R[(size_t)(n + 1) * nq];
-        cplx f = Rn * S;
-        cplx gg = (fac * Rn1) * (sx * S) + Rn * dS;
+    // radial values one degree ahead: the load for n + 2 is in flight while
+    // degree n is summed
+    cplx Rn = R[(size_t)am * nq], Rn1 = R[(size_t)(am + 1) * nq];
+    auto accum = [&](int n) {
+        cplx f = Rn * q1;
+        cplx gg = (fac * Rn1) * (sx * q1) + Rn * dq1;
         cplx cp = cpp[n];
         fp += cp * f;
         gp += cp * gg;
@@ -700,7 +748,20 @@ __global__ __launch_bounds__(256) void k_h3d_coax_sample(H3DTr tr, int U)
             fm += cm * f;
             gm += cm * gg;
         }
+    };
+    {
+        cplx Rn2 = am + 2 <= Ps + 1 ? R[(size_t)(am + 2) * nq] : mk(0.0, 0.0);
+        accum(am);
         Rn = Rn1;
+        Rn1 = Rn2;
+    }
+#pragma unroll 2
+    for (int n = am + 1; n <= Ps; ++n) {
+        cplx Rn2 = n + 2 <= Ps + 1 ? R[(size_t)(n + 2) * nq] : mk(0.0, 0.0);
+        col_step(rec, n, z, dz, r2, dr2, q0, q1, dq0, dq1);
+        accum(n);
+        Rn = Rn1;
+        Rn1 = Rn2;
     }
     if (!own) return;
     // samples stored pair-fastest for the projection GEMM:
@@ -794,14 +855,18 @@ inline unsigned blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs)
 
 hipError_t h3d_init_tables(int device)
 {
-    (void)device;
-    static double ca[kT * kT], cb[kT * kT], cs[kT], ck[kT];
-    for (int n = 0; n < kT; ++n)
-        for (int m = 0; m < kT; ++m) {
+    static RecAB rab[kT * kT];
+    static RecABf rabf[kT * kT];
+    static double cs[kT], ck[kT];
+    for (int m = 0; m < kT; ++m)
+        for (int n = 0; n < kT; ++n) {
             double a = (double)(n + m - 1) * (double)(n - m - 1);
-            ca[n * kT + m] = a > 0.0 ? sqrt(a) : 0.0;
             double b = (double)(n - m) * (double)(n + m);
-            cb[n * kT + m] = b > 0.0 ? 1.0 / sqrt(b) : 0.0;
+            double ib = n > m && b > 0.0 ? 1.0 / sqrt(b) : 0.0;
+            RecAB& r = rab[m * kT + n];
+            r.s = (2.0 * n - 1.0) * ib;
+            r.a = (a > 0.0 ? sqrt(a) : 0.0) * ib;
+            rabf[m * kT + n] = RecABf{(float)r.s, (float)r.a};
         }
     cs[0] = 1.0;
     ck[0] = 1.0;
@@ -810,17 +875,28 @@ hipError_t h3d_init_tables(int device)
         cs[m] = cs[m - 1] * ck[m];
     }
     hipError_t e;
-    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_ca), ca, sizeof(ca))) != hipSuccess) return e;
-    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_cb), cb, sizeof(cb))) != hipSuccess) return e;
-    static float caf[kT * kT], cbf[kT * kT];
-    for (int k = 0; k < kT * kT; ++k) {
-        caf[k] = (float)ca[k];
-        cbf[k] = (float)cb[k];
-    }
-    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_caf), caf, sizeof(caf))) != hipSuccess) return e;
-    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_cbf), cbf, sizeof(cbf))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_rab), rab, sizeof(rab))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_rabf), rabf, sizeof(rabf))) != hipSuccess) return e;
+    if (device < 0 || device >= kMaxDev) return hipErrorInvalidDevice;
+    void* a = nullptr;
+    if ((e = hipGetSymbolAddress(&a, HIP_SYMBOL(c_rab))) != hipSuccess) return e;
+    g_rab[device] = a;
+    if ((e = hipGetSymbolAddress(&a, HIP_SYMBOL(c_rabf))) != hipSuccess) return e;
+    g_rabf[device] = a;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_cs), cs, sizeof(cs))) != hipSuccess) return e;
     return hipMemcpyToSymbol(HIP_SYMBOL(c_ck), ck, sizeof(ck));
+}
+
+// the recurrence tables of the current device (h3d_init_tables ran for it)
+static hipError_t rec_tables(const void** rec, const void** recf)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDev || !g_rab[dev]) return hipErrorNotInitialized;
+    *rec = g_rab[dev];
+    if (recf) *recf = g_rabf[dev];
+    return hipSuccess;
 }
 
 static size_t p2x_lds(int P, int st)
@@ -840,7 +916,10 @@ static hipError_t launch_p2x(const int* boxes, int nb, int pmax, const TreeView&
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_h3d_p2x<IRREG><<<nb, threads, lds, st>>>(boxes, tv, pv, hl, useL4, out);
+    H3DLevels h = hl;
+    hipError_t e = rec_tables(&h.rec, nullptr);
+    if (e != hipSuccess) return e;
+    k_h3d_p2x<IRREG><<<nb, threads, lds, st>>>(boxes, tv, pv, h, useL4, out);
     return hipGetLastError();
 }
 
@@ -861,13 +940,16 @@ hipError_t h3d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const T
                         const cplx* local, const M2PParts& m2p, cplx* ufar, hipStream_t st)
 {
     if (nleaf <= 0) return hipSuccess;
+    H3DLevels h = hl;
+    hipError_t er = rec_tables(&h.rec, nullptr);
+    if (er != hipSuccess) return er;
     size_t lds = sizeof(cplx) * (size_t)(pmax + 3) * 64;
     if (m2p.n > 0) {
-        k_h3d_m2p_part<<<m2p.n, 64, lds, st>>>(m2p.owner, m2p.poff, tv, pv, hl, mpole, m2p.part);
+        k_h3d_m2p_part<<<m2p.n, 64, lds, st>>>(m2p.owner, m2p.poff, tv, pv, h, mpole, m2p.part);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    k_h3d_leaf_far<<<nleaf, 64, lds, st>>>(leaves, top, tv, pv, hl, local, m2p.poff, m2p.part, ufar);
+    k_h3d_leaf_far<<<nleaf, 64, lds, st>>>(leaves, top, tv, pv, h, local, m2p.poff, m2p.part, ufar);
     return hipGetLastError();
 }
 
@@ -921,11 +1003,16 @@ static hipError_t launch_rot_sample(const H3DTr& tr, int back, const int* eoff, 
 
 // One chunk of a translation stage: pairs [0, tr.np) of the chunk, target
 // groups [0, ng) with pair ranges goff (chunk-relative).
-hipError_t h3d_translate(const H3DTr& tr, const TreeView& tv, const int* eoff_src, const cplx* coef_src,
+hipError_t h3d_translate(const H3DTr& tr_in, const TreeView& tv, const int* eoff_src, const cplx* coef_src,
                          const int* gdst, const int* goff, int ng, const int* eoff_dst, cplx* coef_dst,
                          const double* eq_p0, const double* eq_d0, hipStream_t st)
 {
-    if (tr.np <= 0) return hipSuccess;
+    if (tr_in.np <= 0) return hipSuccess;
+    H3DTr tr = tr_in;
+    {
+        hipError_t e0 = rec_tables(&tr.rec, &tr.recf);
+        if (e0 != hipSuccess) return e0;
+    }
     // one thread per node or per equator sample in the sampling kernels
     if (tr.nq > 128 || 2 * tr.Ps + 1 > 128 || 2 * tr.Pt + 1 > 128) return hipErrorInvalidValue;
     const int bs = 256;

@@ -141,6 +141,7 @@ int l3d_pmax_supported();
 struct H3DLevels {
     const double* kw;      // kappa * w_l per level
     const double* sc;      // min(1, kappa * w_l)
+    const void* rec;       // column recurrence table (set by the launchers)
 };
 
 // One chunk of a translation stage (M2M, M2L or L2L at one level): its pairs,
@@ -153,6 +154,8 @@ struct H3DTr {
     int Ps, Pt, nq;         // source / target expansion lengths, coaxial nodes
     int src_h, trg_h;       // 1: singular (multipole) expansion, 0: regular (local)
     int f32;                // 1: rotation sampling in FP32 (mixed-precision M2L)
+    const void* rec;        // column recurrence tables, FP64 and FP32 (set by h3d_translate)
+    const void* recf;
     double ks, sc;          // kappa w_src and the source level's scale
     double rs;              // coaxial sampling radius / w_src
     double inv_w;           // 1 / w_src
