@@ -615,9 +615,14 @@ __global__ __launch_bounds__(256) void k_h3d_rot_sample(H3DTr tr, int back, cons
     }
 }
 
-// K2: DFT over the samples.  Thread (pair, coefficient (n, m)):
+// K2: DFT over the samples.  Thread (pair, degree n, order |m|):
 // b_n^m = (1/J) sum_j e^{-i m phi_j} F_n(j) / S_n^m(e_x)  (n+m even)
 //       = (1/J) sum_j e^{-i m phi_j} G_n(j) / d_n^m        (n+m odd).
+// Orders +m and -m read the same samples (n+m and n-m have one parity) and
+// conjugate twiddles, so one pass over j gives both from four sums:
+// with X = F or G and e^{i m phi_j} = c + i s,
+//   sum X e^{-i m phi} = (Sa + Sb, Sd - Se),  sum X e^{+i m phi} = (Sa - Sb, Sd + Se),
+//   Sa = sum Re X c, Sb = sum Im X s, Sd = sum Im X c, Se = sum Re X s.
 __global__ void k_h3d_rot_dft(H3DTr tr, int back, const double* __restrict__ eq_p0,
                               const double* __restrict__ eq_d0)
 {
@@ -631,31 +636,34 @@ __global__ void k_h3d_rot_dft(H3DTr tr, int back, const double* __restrict__ eq_
         tw[2 * k + 1] = s;
     }
     __syncthreads();
-    int nc = (P + 1) * (P + 1);
+    int nt = (P + 1) * (P + 2) / 2;
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)tr.np * nc) return;
-    int c = (int)(gid % nc);
-    int i = (int)(gid / nc);
-    int n = (int)sqrt((double)c);
-    while (n * n > c) --n;
-    while ((n + 1) * (n + 1) <= c) ++n;
-    int m = c - n * n - n;
-    int am = m < 0 ? -m : m;
-    bool even = ((n + m) & 1) == 0;
+    if (gid >= (int64_t)tr.np * nt) return;
+    int c = (int)(gid % nt);
+    int i = (int)(gid / nt);
+    int n = (int)((sqrt(8.0 * c + 1.0) - 1.0) * 0.5);
+    while (n * (n + 1) / 2 > c) --n;
+    while ((n + 1) * (n + 2) / 2 <= c) ++n;
+    int am = c - n * (n + 1) / 2;
+    bool even = ((n + am) & 1) == 0;
     const cplx* FG = tr.FG + (size_t)i * tr.sFG + (even ? 0 : (size_t)(P + 1) * J) + (size_t)n * J;
-    double sr = 0.0, si = 0.0;
-    int mj = ((m % J) + J) % J, k = 0;
+    double sa = 0.0, sb = 0.0, sd = 0.0, se = 0.0;
+    int k = 0;
+#pragma unroll 4
     for (int j = 0; j < J; ++j) {
-        double cr = tw[2 * k], ci = -tw[2 * k + 1];   // e^{-i m phi_j}
+        double cr = tw[2 * k], ci = tw[2 * k + 1];   // e^{i am phi_j}
         cplx f = FG[j];
-        sr += f.re * cr - f.im * ci;
-        si += f.re * ci + f.im * cr;
-        k += mj;
+        sa = fma(f.re, cr, sa);
+        sb = fma(f.im, ci, sb);
+        sd = fma(f.im, cr, sd);
+        se = fma(f.re, ci, se);
+        k += am;
         if (k >= J) k -= J;
     }
-    double den = (even ? eq_p0[tri(n, am)] : eq_d0[tri(n, am)]) * J;
+    double inv = 1.0 / ((even ? eq_p0[tri(n, am)] : eq_d0[tri(n, am)]) * J);
     cplx* o = tr.A + (size_t)i * tr.sA;
-    o[c] = mk(sr / den, si / den);
+    o[hnm(n, am)] = mk((sa + sb) * inv, (sd - se) * inv);
+    if (am > 0) o[hnm(n, -am)] = mk((sa - sb) * inv, (sd + se) * inv);
 }
 
 // K3a: radial functions of the source expansion at the coaxial nodes
@@ -845,6 +853,9 @@ __global__ void k_h3d_accum(H3DTr tr, const int* __restrict__ gdst, const int* _
     int c = (int)(gid % nc);
     int k = (int)(gid / nc);
     cplx s = mk(0.0, 0.0);
+    // unrolled so that several pairs' loads are in flight; the sum stays in
+    // pair order
+#pragma unroll 8
     for (int i = goff[k]; i < goff[k + 1]; ++i) s += tr.A[(size_t)i * tr.sA + c];
     out[eoff[gdst[k]] + c] += s;
 }
@@ -1022,7 +1033,7 @@ hipError_t h3d_translate(const H3DTr& tr_in, const TreeView& tv, const int* eoff
     int Ps = tr.Ps, Pt = tr.Pt;
     k_h3d_rot_prep<<<blocks((int64_t)tr.np * Ps * Ps, bs), bs, 0, st>>>(tr, 0, eoff_src, coef_src);
     if ((e = launch_rot_sample<NB>(tr, 0, eoff_src, coef_src, st)) != hipSuccess) return e;
-    int64_t n2 = (int64_t)tr.np * (Ps + 1) * (Ps + 1);
+    int64_t n2 = (int64_t)tr.np * (Ps + 1) * (Ps + 2) / 2;
     k_h3d_rot_dft<<<blocks(n2, bs), bs, sizeof(double) * 2 * (2 * Ps + 1), st>>>(tr, 0, eq_p0, eq_d0);
     int64_t n3 = (int64_t)tr.np * tr.nq;
     k_h3d_coax_radial<<<blocks(n3, bs), bs, 0, st>>>(tr);
@@ -1033,7 +1044,7 @@ hipError_t h3d_translate(const H3DTr& tr_in, const TreeView& tv, const int* eoff
         k_h3d_coax_sample<<<(unsigned)(groups * (Ps + 1)), pk.threads,
                             (size_t)pk.per * 2 * (Ps + 1) * sizeof(cplx), st>>>(tr, pk.per);
     }
-    int64_t n5 = (int64_t)tr.np * (Pt + 1) * (Pt + 1);
+    int64_t n5 = (int64_t)tr.np * (Pt + 1) * (Pt + 2) / 2;
     int64_t nwave = (int64_t)(2 * Pt + 1) * ((Pt + 16) / 16) * ((tr.np + 3) / 4);
     k_h3d_coax_proj<<<(unsigned)((nwave + 3) / 4), 256, 0, st>>>(tr);
     k_h3d_rot_prep<<<blocks((int64_t)tr.np * Pt * Pt, bs), bs, 0, st>>>(tr, 1, nullptr, nullptr);
