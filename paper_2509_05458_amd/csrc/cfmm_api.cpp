@@ -102,7 +102,7 @@ struct cfmm_plan_s {
         int kind, level, Ps, Pt, nq, src_h, trg_h;
         double ks, sc, rs_s, inv_w;
         int64_t o_nodes, o_W, o_T;
-        int64_t sFG, sA, sR, sfg, sB, per_pair;
+        int64_t sFG, sA, sR, sB, per_pair;
         std::vector<H3Chunk> chunks;
     };
     std::vector<H3Stage> h3;
@@ -299,9 +299,8 @@ int plan_h3d(cfmm_plan_s* p, int nlev, int top)
         S.sFG = 2 * (int64_t)(Pm + 1) * J;
         S.sA = (int64_t)(Pm + 1) * (Pm + 1);
         S.sR = (int64_t)(S.Ps + 2) * S.nq;
-        S.sfg = 2 * (int64_t)(2 * S.Ps + 1) * S.nq;
         S.sB = (int64_t)(S.Pt + 1) * (S.Pt + 1);
-        S.per_pair = 10 + S.sFG + S.sA + S.sR + S.sfg + S.sB;
+        S.per_pair = 10 + S.sFG + S.sA + S.sR + S.sB;
         int64_t maxg = 1;
         for (auto& v : srcs) maxg = std::max<int64_t>(maxg, (int64_t)v.size());
         int64_t cap = std::max<int64_t>(maxg, cap_bytes / (S.per_pair * (int64_t)sizeof(cplx)));
@@ -1035,8 +1034,7 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
                     tr.FG = tr.geo + 10 * np; tr.sFG = S.sFG;
                     tr.A = tr.FG + S.sFG * np; tr.sA = S.sA;
                     tr.R = tr.A + S.sA * np; tr.sR = S.sR;
-                    tr.fg = tr.R + S.sR * np; tr.sfg = S.sfg;
-                    tr.B = tr.fg + S.sfg * np; tr.sB = S.sB;
+                    tr.B = tr.R + S.sR * np; tr.sB = S.sB;
                     HIPCHK(h3d_translate(tr, tv, p->d_eoff, src, p->d_h3_gdst + C.grp_begin,
                                          p->d_h3_goff + C.goff_off, C.ng, p->d_eoff, dst, p->d_h3_eq,
                                          p->d_h3_eq + p->h3_eq_half, st));

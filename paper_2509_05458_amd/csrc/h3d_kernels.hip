@@ -683,18 +683,53 @@ __global__ void k_h3d_coax_radial(H3DTr tr)
     else radial_j(r2, tr.ks, tr.sc, tr.Ps + 1, R, tr.nq);
 }
 
-// K3: coaxial samples.  Workgroup (group of U pairs, order m >= 0), thread =
-// (pair u of the group, node j): the column of order m at x_j (y = 0, so
-// S_n^-m = S_n^m there) with its derivative along s_j = (sin t_j, 0, cos t_j);
-// with F = R_n(rho) S_n^m(x),
+// K3: coaxial samples and their projection.  Workgroup (group of U pairs,
+// order m >= 0), thread = (pair u of the group, node j): the column of order m
+// at x_j (y = 0, so S_n^-m = S_n^m there) with its derivative along
+// s_j = (sin t_j, 0, cos t_j); with F = R_n(rho) S_n^m(x),
 //   dF/drs = fac R_{n+1} (s.x) S_n^m + R_n s.grad S_n^m,
 // fac = -kw sc for the regular A_n and -kw / sc for the singular B_n.  Each
 // pair's column coefficients of orders +m and -m are staged in LDS first; U
 // pairs share a workgroup so that small node counts still fill the lanes.
-__global__ __launch_bounds__(256) void k_h3d_coax_sample(H3DTr tr, int U)
+//
+// The samples then stay in LDS for the Legendre projection, a real GEMM per
+// order whose matrix W^m (rows n = |m|..Pt, columns the nodes j) is the same
+// for every pair of the stage:
+//     Out[n][(u, c)] = sum_j W^m[n][j] S[j][(u, c)],   c in {f.re, f.im, g.re, g.im},
+// and b_n^m = Tc_n (f) + Tdc_n (g).  The workgroup's wavefronts take its
+// 16 x 16 tiles (16 degrees x 4 pairs) on the FP64 matrix cores with
+// v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16] and
+// holds D[4v + l/16][l%16], v = 0..3.  The workgroup of order Ps also writes
+// the zero coefficients of orders Ps < |m| <= Pt, which have no samples.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// LDS of the coaxial workgroup: staged coefficients [U][2][Ps + 1] (complex),
+// samples [2 signs][nq][ncp] (double) and one 16 x 17 transposition tile per
+// wavefront.
+struct CoaxLds {
+    int ncp;                 // sample columns per node: 4 U rounded up to 16
+    size_t cpm, smp, tile;   // offsets in doubles
+    size_t bytes;
+};
+__host__ __device__ inline CoaxLds coax_lds(int U, int Ps, int nq, int waves)
 {
-    extern __shared__ cplx cpm[];   // [U][2][Ps + 1]
-    int Ps = tr.Ps, nq = tr.nq;
+    CoaxLds L;
+    L.ncp = (4 * U + 15) / 16 * 16;
+    L.cpm = 0;
+    L.smp = L.cpm + (size_t)U * 2 * (Ps + 1) * 2;
+    L.tile = L.smp + (size_t)2 * nq * L.ncp;
+    L.bytes = (L.tile + (size_t)waves * 16 * 17) * sizeof(double);
+    return L;
+}
+
+__global__ __launch_bounds__(256) void k_h3d_coax(H3DTr tr, int U)
+{
+    extern __shared__ double cl[];
+    int Ps = tr.Ps, Pt = tr.Pt, nq = tr.nq;
+    int nw = blockDim.x >> 6;
+    CoaxLds L = coax_lds(U, Ps, nq, nw);
+    cplx* cpm = reinterpret_cast<cplx*>(cl + L.cpm);
+    double* smp = cl + L.smp;
     // the Ps + 1 orders of one pair group run on one XCD, so that the group's
     // radial values and coefficients are read from that XCD's L2
     int wg = xcd_contiguous(blockIdx.x, gridDim.x);
@@ -709,137 +744,117 @@ __global__ __launch_bounds__(256) void k_h3d_coax_sample(H3DTr tr, int U)
     }
     __syncthreads();
     int u = threadIdx.x / nq;
-    if (u >= U) return;
-    int j = threadIdx.x - u * nq;
-    int i = i0 + u;
-    bool own = i < tr.np;                     // the group's tail repeats the last pair
-    if (!own) i = tr.np - 1;
-    const cplx* cpp = cpm + (2 * u) * (Ps + 1);
-    const cplx* cpn = cpp + (Ps + 1);
-    const RecAB* rec = static_cast<const RecAB*>(tr.rec) + am * kT;   // column am
-    cplx t = tr.geo[(size_t)i * 10 + 9];
-    double s1 = tr.sth[j], s3 = tr.cth[j];
-    cplx x1 = mk(tr.rs * s1, 0.0);
-    cplx x3 = t + mk(tr.rs * s3, 0.0);
-    cplx r2 = x1 * x1 + x3 * x3;
-    cplx sx = s1 * x1 + s3 * x3;
-    cplx dr2 = 2.0 * sx;
-    const cplx* R = tr.R + (size_t)i * tr.sR + j;
-    double fac = tr.src_h ? -tr.ks / tr.sc : -tr.ks * tr.sc;
-    // diagonal start c_m x1^m and its derivative c_m m x1^{m-1} s1
-    cplx D = mk(c_cs[am], 0.0), dD = mk(0.0, 0.0);
-    {
-        cplx pw = mk(1.0, 0.0);
-        for (int k = 0; k < am; ++k) {
-            if (k == am - 1) dD = (double)am * c_cs[am] * s1 * pw;
-            pw = pw * x1;
+    if (u < U) {
+        int j = threadIdx.x - u * nq;
+        int i = min(i0 + u, tr.np - 1);       // the group's tail repeats the last pair
+        const cplx* cpp = cpm + (2 * u) * (Ps + 1);
+        const cplx* cpn = cpp + (Ps + 1);
+        const RecAB* rec = static_cast<const RecAB*>(tr.rec) + am * kT;   // column am
+        cplx t = tr.geo[(size_t)i * 10 + 9];
+        double s1 = tr.sth[j], s3 = tr.cth[j];
+        cplx x1 = mk(tr.rs * s1, 0.0);
+        cplx x3 = t + mk(tr.rs * s3, 0.0);
+        cplx r2 = x1 * x1 + x3 * x3;
+        cplx sx = s1 * x1 + s3 * x3;
+        cplx dr2 = 2.0 * sx;
+        const cplx* R = tr.R + (size_t)i * tr.sR + j;
+        double fac = tr.src_h ? -tr.ks / tr.sc : -tr.ks * tr.sc;
+        // diagonal start c_m x1^m and its derivative c_m m x1^{m-1} s1
+        cplx D = mk(c_cs[am], 0.0), dD = mk(0.0, 0.0);
+        {
+            cplx pw = mk(1.0, 0.0);
+            for (int k = 0; k < am; ++k) {
+                if (k == am - 1) dD = (double)am * c_cs[am] * s1 * pw;
+                pw = pw * x1;
+            }
+            D = c_cs[am] * pw;
         }
-        D = c_cs[am] * pw;
-    }
-    cplx fp = mk(0.0, 0.0), fm = fp, gp = fp, gm = fp;
-    // the diagonal start is folded into the column: Q = D q obeys the same
-    // recurrence as q, and its derivative dQ = dD q + D dq the differentiated
-    // one, so S_n^m = Q_n and its derivative is dQ_n
-    cplx q0 = mk(0.0, 0.0), q1 = D, dq0 = q0, dq1 = dD;
-    cplx z = x3, dz = mk(s3, 0.0);
-    // radial values one degree ahead: the load for n + 2 is in flight while
-    // degree n is summed
-    cplx Rn = R[(size_t)am * nq], Rn1 = R[(size_t)(am + 1) * nq];
-    auto accum = [&](int n) {
-        cplx f = Rn * q1;
-        cplx gg = (fac * Rn1) * (sx * q1) + Rn * dq1;
-        cplx cp = cpp[n];
-        fp += cp * f;
-        gp += cp * gg;
-        if (am) {
-            cplx cm = cpn[n];
-            fm += cm * f;
-            gm += cm * gg;
+        cplx fp = mk(0.0, 0.0), fm = fp, gp = fp, gm = fp;
+        // the diagonal start is folded into the column: Q = D q obeys the same
+        // recurrence as q, and its derivative dQ = dD q + D dq the
+        // differentiated one, so S_n^m = Q_n and its derivative is dQ_n
+        cplx q0 = mk(0.0, 0.0), q1 = D, dq0 = q0, dq1 = dD;
+        cplx z = x3, dz = mk(s3, 0.0);
+        // radial values one degree ahead: the load for n + 2 is in flight
+        // while degree n is summed
+        cplx Rn = R[(size_t)am * nq], Rn1 = R[(size_t)(am + 1) * nq];
+        auto accum = [&](int n) {
+            cplx f = Rn * q1;
+            cplx gg = (fac * Rn1) * (sx * q1) + Rn * dq1;
+            cplx cp = cpp[n];
+            fp += cp * f;
+            gp += cp * gg;
+            if (am) {
+                cplx cm = cpn[n];
+                fm += cm * f;
+                gm += cm * gg;
+            }
+        };
+        {
+            cplx Rn2 = am + 2 <= Ps + 1 ? R[(size_t)(am + 2) * nq] : mk(0.0, 0.0);
+            accum(am);
+            Rn = Rn1;
+            Rn1 = Rn2;
         }
-    };
-    {
-        cplx Rn2 = am + 2 <= Ps + 1 ? R[(size_t)(am + 2) * nq] : mk(0.0, 0.0);
-        accum(am);
-        Rn = Rn1;
-        Rn1 = Rn2;
-    }
 #pragma unroll 2
-    for (int n = am + 1; n <= Ps; ++n) {
-        cplx Rn2 = n + 2 <= Ps + 1 ? R[(size_t)(n + 2) * nq] : mk(0.0, 0.0);
-        col_step(rec, n, z, dz, r2, dr2, q0, q1, dq0, dq1);
-        accum(n);
-        Rn = Rn1;
-        Rn1 = Rn2;
-    }
-    if (!own) return;
-    // samples stored pair-fastest for the projection GEMM:
-    // fg[((m + Ps) nq + j) np + i] = (f.re, f.im, g.re, g.im)
-    double* o = (double*)tr.fg;
-    size_t row = ((size_t)(am + Ps) * nq + j) * tr.np + i;
-    o[4 * row + 0] = fp.re; o[4 * row + 1] = fp.im; o[4 * row + 2] = gp.re; o[4 * row + 3] = gp.im;
-    if (am) {
-        row = ((size_t)(Ps - am) * nq + j) * tr.np + i;
-        o[4 * row + 0] = fm.re; o[4 * row + 1] = fm.im; o[4 * row + 2] = gm.re; o[4 * row + 3] = gm.im;
-    }
-}
-
-// K4: Legendre projection as a dense real GEMM on the FP64 matrix cores.  For
-// each order m the projection matrix W^m (rows n = |m|..Pt, columns the nodes
-// j) is the same for every pair of the stage, so
-//     Out^m[n][(i, c)] = sum_j W^m[n][j] S^m[j][(i, c)],   c in {f.re, f.im, g.re, g.im},
-// over all pairs i of the chunk, and then b_n^m = Tc_n (f) + Tdc_n (g).  One
-// wavefront computes a 16 x 16 tile (16 degrees x 4 pairs) with
-// v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16] and
-// holds D[4v + l/16][l%16], v = 0..3.  Orders |m| > Ps have no samples and
-// give zero coefficients.
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-__global__ __launch_bounds__(256) void k_h3d_coax_proj(H3DTr tr)
-{
-    __shared__ double tile[4][16][17];
-    int Pt = tr.Pt, Ps = tr.Ps, nq = tr.nq, np = tr.np;
-    int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    int pgroups = (np + 3) / 4;
-    int rt_max = (Pt + 16) / 16;                 // row tiles for m = 0
-    int64_t wid = (int64_t)blockIdx.x * 4 + wave;
-    int64_t nw = (int64_t)(2 * Pt + 1) * rt_max * pgroups;
-    // every wavefront reaches the barrier below; inactive ones only skip work
-    bool live = wid < nw;
-    int pg = live ? (int)(wid % pgroups) : 0;
-    int rt = live ? (int)((wid / pgroups) % rt_max) : 0;
-    int m = live ? (int)(wid / ((int64_t)pgroups * rt_max)) - Pt : 0;
-    int am = m < 0 ? -m : m;
-    int n0 = am + 16 * rt;
-    live = live && n0 <= Pt;
-    bool sampled = am <= Ps;
-    int i0 = pg * 4;
-    int r = l & 15, kq = l >> 4;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    if (live && sampled) {
-        const double* S = (const double*)tr.fg + (size_t)(m + Ps) * nq * np * 4;
-        int na = n0 + r;                          // A row this lane supplies
-        bool arow = na <= Pt;
-        size_t wrow = (size_t)tri(arow ? na : n0, am) * nq;
-        int col = i0 * 4 + r;                     // B column this lane supplies
-        bool bcol = i0 + (r >> 2) < np;
-        for (int k0 = 0; k0 < nq; k0 += 4) {
-            int j = k0 + kq;
-            double a = (arow && j < nq) ? tr.W[wrow + j] : 0.0;
-            double b = (bcol && j < nq) ? S[(size_t)j * np * 4 + col] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        for (int n = am + 1; n <= Ps; ++n) {
+            cplx Rn2 = n + 2 <= Ps + 1 ? R[(size_t)(n + 2) * nq] : mk(0.0, 0.0);
+            col_step(rec, n, z, dz, r2, dr2, q0, q1, dq0, dq1);
+            accum(n);
+            Rn = Rn1;
+            Rn1 = Rn2;
         }
+        double* sp = smp + (size_t)j * L.ncp + 4 * u;               // order +m
+        double* sm = smp + (size_t)(nq + j) * L.ncp + 4 * u;        // order -m
+        sp[0] = fp.re; sp[1] = fp.im; sp[2] = gp.re; sp[3] = gp.im;
+        sm[0] = fm.re; sm[1] = fm.im; sm[2] = gm.re; sm[3] = gm.im;
     }
-    // gather the four components of each pair through LDS
-    for (int v = 0; v < 4; ++v) tile[wave][4 * v + kq][r] = acc[v];
     __syncthreads();
-    // lane l: degree row dr = l >> 2 (0..15), pair p = l & 3
-    int dr = l >> 2, p = l & 3;
-    int n = n0 + dr, i = i0 + p;
-    if (live && n <= Pt && i < np) {
-        const double* t = tile[wave][dr];
-        cplx pf = mk(t[4 * p + 0], t[4 * p + 1]), pgv = mk(t[4 * p + 2], t[4 * p + 3]);
-        // orders beyond the source expansion have no samples: zero coefficients
-        tr.B[(size_t)i * tr.sB + hnm(n, m)] = sampled ? tr.Tc[n] * pf + tr.Tdc[n] * pgv : mk(0.0, 0.0);
+    // projection tiles: (sign, 16-degree row tile, 4-pair column tile)
+    int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+    int r = l & 15, kq = l >> 4;
+    double* tile = cl + L.tile + (size_t)wave * 16 * 17;
+    int nsg = am ? 2 : 1, nrt = (Pt - am + 16) / 16, nct = (U + 3) / 4;
+    for (int tix = wave; tix < nsg * nrt * nct; tix += nw) {
+        int sg = tix / (nrt * nct), rt = (tix / nct) % nrt, ct = tix % nct;
+        int n0 = am + 16 * rt;
+        const double* S = smp + (size_t)sg * nq * L.ncp + 16 * ct;
+        int na = n0 + r;                      // A row this lane supplies
+        bool arow = na <= Pt;
+        const double* wrow = tr.W + (size_t)tri(arow ? na : n0, am) * nq;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < nq; k0 += 4) {
+            int jj = k0 + kq;
+            double av = (arow && jj < nq) ? wrow[jj] : 0.0;
+            double bv = jj < nq ? S[(size_t)jj * L.ncp + r] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        // gather the four components of each pair through the wave's tile
+        for (int v = 0; v < 4; ++v) tile[(4 * v + kq) * 17 + r] = acc[v];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        int dr = l >> 2, pq = l & 3;
+        int n = n0 + dr, uo = 4 * ct + pq, io = i0 + uo;
+        if (n <= Pt && uo < U && io < tr.np) {
+            const double* tv = tile + dr * 17 + 4 * pq;
+            cplx pf = mk(tv[0], tv[1]), pg = mk(tv[2], tv[3]);
+            int m = sg ? -am : am;
+            tr.B[(size_t)io * tr.sB + hnm(n, m)] = tr.Tc[n] * pf + tr.Tdc[n] * pg;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    // orders beyond the source expansion have no samples: zero coefficients
+    if (am == Ps && Pt > Ps) {
+        int per = (Pt + 1) * (Pt + 1);
+        for (int e = threadIdx.x; e < U * per; e += blockDim.x) {
+            int uo = e / per, c = e - uo * per, io = i0 + uo;
+            int n = (int)sqrt((double)c);
+            while (n * n > c) --n;
+            while ((n + 1) * (n + 1) <= c) ++n;
+            int m = c - n * n - n;
+            if (io < tr.np && (m > Ps || m < -Ps)) tr.B[(size_t)io * tr.sB + c] = mk(0.0, 0.0);
+        }
     }
 }
 
@@ -967,8 +982,8 @@ hipError_t h3d_leaf_far(const int* leaves, int nleaf, int top, int pmax, const T
 
 // Workgroup shape for a kernel whose item takes w consecutive threads: the
 // size in {64, 128, 192, 256} that leaves the fewest lanes idle (the smaller
-// one unless a larger one fills 2% more), with per-workgroup LDS lds(U) for U
-// items at most 64 KiB.  threads = 0 when no size fits.
+// one unless a larger one fills 2% more), with per-workgroup LDS lds(U, size)
+// for U items at most 64 KiB.  threads = 0 when no size fits.
 struct PackShape {
     int threads, per;
 };
@@ -979,7 +994,7 @@ static PackShape pack_items(int w, F lds)
     double bu = -1.0;
     for (int bt = 64; bt <= 256; bt += 64) {
         int U = bt / w;
-        if (U < 1 || lds(U) > 65536) continue;
+        if (U < 1 || lds(U, bt) > 65536) continue;
         double util = (double)(U * w) / bt;
         if (util > bu + 0.02) {
             bu = util;
@@ -1000,7 +1015,7 @@ static hipError_t launch_rot_sample(const H3DTr& tr, int back, const int* eoff, 
         smax = std::max(smax, (nhi + 1) * (nhi + 1) - n0 * n0);
     }
     size_t esz = tr.f32 ? 2 * sizeof(float) : 2 * sizeof(double);
-    PackShape pk = pack_items(J, [&](int U) { return (size_t)U * 2 * smax * esz; });
+    PackShape pk = pack_items(J, [&](int U, int) { return (size_t)U * 2 * smax * esz; });
     if (pk.threads == 0) return hipErrorInvalidValue;
     int64_t wpb = (tr.np + pk.per - 1) / pk.per;
     unsigned grid = (unsigned)(wpb * nblk);
@@ -1038,17 +1053,16 @@ hipError_t h3d_translate(const H3DTr& tr_in, const TreeView& tv, const int* eoff
     int64_t n3 = (int64_t)tr.np * tr.nq;
     k_h3d_coax_radial<<<blocks(n3, bs), bs, 0, st>>>(tr);
     {
-        PackShape pk = pack_items(tr.nq, [&](int U) { return (size_t)U * 2 * (Ps + 1) * sizeof(cplx); });
+        // the workgroup size leaves room for its waves' tiles in the LDS bound
+        PackShape pk = pack_items(tr.nq, [&](int U, int bt) { return coax_lds(U, Ps, tr.nq, bt / 64).bytes; });
         if (pk.threads == 0) return hipErrorInvalidValue;
         int64_t groups = (tr.np + pk.per - 1) / pk.per;
-        k_h3d_coax_sample<<<(unsigned)(groups * (Ps + 1)), pk.threads,
-                            (size_t)pk.per * 2 * (Ps + 1) * sizeof(cplx), st>>>(tr, pk.per);
+        k_h3d_coax<<<(unsigned)(groups * (Ps + 1)), pk.threads,
+                     coax_lds(pk.per, Ps, tr.nq, pk.threads / 64).bytes, st>>>(tr, pk.per);
     }
-    int64_t n5 = (int64_t)tr.np * (Pt + 1) * (Pt + 2) / 2;
-    int64_t nwave = (int64_t)(2 * Pt + 1) * ((Pt + 16) / 16) * ((tr.np + 3) / 4);
-    k_h3d_coax_proj<<<(unsigned)((nwave + 3) / 4), 256, 0, st>>>(tr);
     k_h3d_rot_prep<<<blocks((int64_t)tr.np * Pt * Pt, bs), bs, 0, st>>>(tr, 1, nullptr, nullptr);
     if ((e = launch_rot_sample<NB>(tr, 1, nullptr, nullptr, st)) != hipSuccess) return e;
+    int64_t n5 = (int64_t)tr.np * (Pt + 1) * (Pt + 2) / 2;
     k_h3d_rot_dft<<<blocks(n5, bs), bs, sizeof(double) * 2 * (2 * Pt + 1), st>>>(tr, 1, eq_p0, eq_d0);
     int64_t n7 = (int64_t)ng * (Pt + 1) * (Pt + 1);
     k_h3d_accum<<<blocks(n7, bs), bs, 0, st>>>(tr, gdst, goff, ng, eoff_dst, coef_dst);

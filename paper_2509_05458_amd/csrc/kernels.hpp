@@ -168,7 +168,6 @@ struct H3DTr {
     cplx* FG;  int64_t sFG;
     cplx* A;   int64_t sA;
     cplx* R;   int64_t sR;
-    cplx* fg;  int64_t sfg;
     cplx* B;   int64_t sB;
 };
 
