@@ -386,8 +386,7 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
     int P = tv.P[l];
     int nc = (P + 1) * (P + 1);
     cplx* tab = reinterpret_cast<cplx*>(tab16);
-    cplx* Ms = tab + ntab;
-    int* base = reinterpret_cast<int*>(Ms + nc);
+    int* base = reinterpret_cast<int*>(tab16 + ntab);
     double s = tv.rs[l];
     int t = threadIdx.x, lane = t & 63;
     int W = blockDim.x >> 6;
@@ -414,7 +413,6 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
         int a = tv.l2idx[e];
         const cplx* M = mpole + tv.eoff[a];
         __syncthreads();
-        for (int i = t; i < nc; i += blockDim.x) Ms[i] = M[i];
         if (t <= 4 * P) {
             cplx ca[3];
             box_centre(tv, a, ca);
@@ -426,7 +424,9 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
         __syncthreads();
         for (int n = na; n <= nb; ++n) {
             int mlo = max(-n, s0 - n * n - n), mhi = min(n, s1 - 1 - n * n - n);
-            const cplx* Mn = Ms + n * n + n;
+            // the source coefficients are read at one address by the whole
+            // wavefront: scalar loads, which leave the LDS to the table
+            const cplx16* Mn = reinterpret_cast<const cplx16*>(M) + n * n + n;
             const cplx16* row[R];
             cplx16 w1[R], w2[R], w3[R];
 #pragma unroll
@@ -436,9 +436,10 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
                 w2[r] = row[r][mlo - 2];
                 w3[r] = row[r][mlo - 3];
             }
-#pragma unroll 4
+#pragma unroll 6
             for (int m = mlo; m <= mhi; ++m) {
-                cplx am = Mn[m];
+                cplx16 mv = Mn[m];
+                cplx am = mk(mv.re, mv.im);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     cplx16 w0 = row[r][m];
@@ -781,7 +782,7 @@ static int m2l_groups_per_lane(int P)
 
 size_t l3d_m2l_lds(int P, int ntab)
 {
-    size_t tab = (size_t)(ntab + (P + 1) * (P + 1)) * sizeof(cplx) + (size_t)(2 * P + 1) * sizeof(int);
+    size_t tab = (size_t)ntab * sizeof(cplx) + (size_t)(2 * P + 1) * sizeof(int);
     return std::max(tab, m2l_red_bytes(m2l_groups_per_lane(P), kM2LWaves));
 }
 
