@@ -597,6 +597,49 @@ __global__ void k_h2d_m2p_part(const int* __restrict__ owner, const int64_t* __r
 }
 
 
+// 1/b for positive normal b: the hardware estimate y0 refined by one
+// third-order step of the series 1/(1 - e) = 1 + e + e^2 + O(e^3),
+// e = 1 - b y0 (truncation below 2^-70 for |e| < 2^-23).
+__device__ inline double rcp_nr(double b)
+{
+    double y = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, y, 1.0);
+    return fma(y, fma(e, e, e), y);
+}
+
+// Argument of (x, y) != (0, 0) in (-pi, pi], as atan2(y, x).  With
+// num = min(|x|, |y|) and den = max(|x|, |y|), atan(num/den) lies in
+// [0, pi/4]; the addition formula atan(t) = atan(c) + atan((t - c)/(1 + t c)),
+// with c = 0 for t below tan(pi/16), c = tan(pi/8) up to tan(3 pi/16) and
+// c = 1 above, leaves |t'| <= tan(pi/16) < 0.2.  There atan(t') = t' P(t'^2)
+// with P of degree 7, the odd Chebyshev interpolant of atan on [-0.2, 0.2]
+// (nodes of degree 15, computed in extended precision and rounded): relative
+// error below 3e-17.  atan(c) is taken for the rounded c the code uses, so
+// the identity is exact, and c = 0 keeps small angles to relative accuracy.
+__device__ inline double arg2(double x, double y)
+{
+    double ax = fabs(x), ay = fabs(y);
+    bool sw = ay > ax;
+    double num = sw ? ax : ay, den = sw ? ay : ax;
+    bool mid = num > 0.198912367379658 * den;             // t > tan(pi/16)
+    bool hi = num > 0.6681786379192989 * den;             // t > tan(3 pi/16)
+    double c = hi ? 1.0 : (mid ? 0.41421356237309503 : 0.0);
+    double ac = hi ? 0.7853981633974483 : (mid ? 0.39269908169872414 : 0.0);
+    double tp = fma(-c, den, num) * rcp_nr(fma(c, num, den));
+    double u = tp * tp;
+    double p = -0.05797887584396482;
+    p = fma(p, u, 0.07637157054800217);
+    p = fma(p, u, -0.09089056697674516);
+    p = fma(p, u, 0.11111076353854933);
+    p = fma(p, u, -0.14285713928935914);
+    p = fma(p, u, 0.19999999998180903);
+    p = fma(p, u, -0.3333333333332968);
+    double th = fma(tp * u, p, tp) + ac;                  // atan(num/den)
+    if (sw) th = 1.5707963267948966 - th;
+    if (x < 0.0) th = 3.141592653589793 - th;
+    return signbit(y) ? -th : th;
+}
+
 // Natural logarithm of a positive, finite, normal x: with x = 2^e m,
 // m in [sqrt(1/2), sqrt(2)), log x = e ln 2 + 2 atanh(t), t = (m - 1)/(m + 1),
 // |t| < 0.1716, and atanh t = t sum_k t^(2k) / (2k + 1), truncated after
@@ -609,7 +652,7 @@ __device__ inline double log_pos(double x)
         m *= 2.0;
         e -= 1;
     }
-    double t = (m - 1.0) / (m + 1.0);
+    double t = (m - 1.0) * rcp_nr(m + 1.0);
     double t2 = t * t;
     double p = 1.0 / 21.0;
     p = fma(p, t2, 1.0 / 19.0);
@@ -654,7 +697,7 @@ __device__ inline cplx h0_series_s(double sr, double si, double k2, double lk2, 
 {
     constexpr SeriesTab T = make_series_tab();
     double lm = 0.5 * log_pos(sr * sr + si * si) + lk2;   // log|q|
-    double ag = atan2(si, sr);                            // arg q
+    double ag = arg2(sr, si);                             // arg q
     double qr = -k2 * sr, qi = -k2 * si;                  // -q
     double tr = 1.0, ti = 0.0, jr = 1.0, ji = 0.0, sr0 = 0.0, si0 = 0.0;
     for (int k = 1; k <= K; ++k) {
