@@ -666,6 +666,60 @@ __global__ void k_h3d_rot_dft(H3DTr tr, int back, const double* __restrict__ eq_
     if (am > 0) o[hnm(n, -am)] = mk((sa - sb) * inv, (sd + se) * inv);
 }
 
+// The same DFT with the samples of U pairs staged in LDS first (coalesced
+// loads), for stages where (P+1)(P+2)/2 <= 256 and the samples fit: thread
+// (pair u of the workgroup, degree n, order |m|).
+__global__ __launch_bounds__(256) void k_h3d_rot_dft_lds(H3DTr tr, int back, const double* __restrict__ eq_p0,
+                                                         const double* __restrict__ eq_d0, int U)
+{
+    extern __shared__ double sh[];
+    int P = back ? tr.Pt : tr.Ps;
+    int J = 2 * P + 1;
+    double* tw = sh;                                      // cos, sin of 2 pi k / J
+    cplx* fg = reinterpret_cast<cplx*>(sh + 2 * J + (J & 1 ? 2 : 0));
+    int rowlen = 2 * (P + 1) * J;                         // F rows, then G rows
+    int i0 = blockIdx.x * U;
+    for (int k = threadIdx.x; k < J; k += blockDim.x) {
+        double s, c;
+        sincospi(2.0 * k / J, &s, &c);
+        tw[2 * k] = c;
+        tw[2 * k + 1] = s;
+    }
+    for (int e = threadIdx.x; e < U * rowlen; e += blockDim.x) {
+        int u = e / rowlen, k = e - u * rowlen;
+        fg[e] = tr.FG[(size_t)min(i0 + u, tr.np - 1) * tr.sFG + k];
+    }
+    __syncthreads();
+    int nt = (P + 1) * (P + 2) / 2;
+    int u = threadIdx.x / nt;
+    int i = i0 + u;
+    if (u >= U || i >= tr.np) return;
+    int c = threadIdx.x - u * nt;
+    int n = (int)((sqrt(8.0 * c + 1.0) - 1.0) * 0.5);
+    while (n * (n + 1) / 2 > c) --n;
+    while ((n + 1) * (n + 2) / 2 <= c) ++n;
+    int am = c - n * (n + 1) / 2;
+    bool even = ((n + am) & 1) == 0;
+    const cplx* X = fg + (size_t)u * rowlen + (even ? 0 : (size_t)(P + 1) * J) + (size_t)n * J;
+    double sa = 0.0, sb = 0.0, sd = 0.0, se = 0.0;
+    int k = 0;
+#pragma unroll 4
+    for (int j = 0; j < J; ++j) {
+        double cr = tw[2 * k], ci = tw[2 * k + 1];   // e^{i am phi_j}
+        cplx f = X[j];
+        sa = fma(f.re, cr, sa);
+        sb = fma(f.im, ci, sb);
+        sd = fma(f.im, cr, sd);
+        se = fma(f.re, ci, se);
+        k += am;
+        if (k >= J) k -= J;
+    }
+    double inv = 1.0 / ((even ? eq_p0[tri(n, am)] : eq_d0[tri(n, am)]) * J);
+    cplx* o = tr.A + (size_t)i * tr.sA;
+    o[hnm(n, am)] = mk((sa + sb) * inv, (sd - se) * inv);
+    if (am > 0) o[hnm(n, -am)] = mk((sa - sb) * inv, (sd + se) * inv);
+}
+
 // K3a: radial functions of the source expansion at the coaxial nodes
 // x_j = (rs sin t_j, 0, rho_D + rs cos t_j) (source-scaled coordinates).
 __global__ void k_h3d_coax_radial(H3DTr tr)
@@ -1027,6 +1081,28 @@ static hipError_t launch_rot_sample(const H3DTr& tr, int back, const int* eoff, 
     return hipGetLastError();
 }
 
+// The rotation DFT of one side (P = Ps forward, Pt back): staged in LDS when a
+// pair's (P+1)(P+2)/2 outputs fit one workgroup and U pairs' samples fit
+// 48 KiB, else one thread per output reading the samples from memory.
+static hipError_t launch_rot_dft(const H3DTr& tr, int back, const double* eq_p0, const double* eq_d0,
+                                 hipStream_t st)
+{
+    int P = back ? tr.Pt : tr.Ps;
+    int J = 2 * P + 1, nt = (P + 1) * (P + 2) / 2;
+    size_t row = (size_t)2 * (P + 1) * J * sizeof(cplx), head = (size_t)(2 * J + 2) * sizeof(double);
+    int U = nt <= 256 ? 256 / nt : 0;
+    while (U > 0 && head + U * row > 49152) --U;
+    if (U > 0) {
+        int threads = (U * nt + 63) / 64 * 64;
+        unsigned grid = (unsigned)((tr.np + U - 1) / U);
+        k_h3d_rot_dft_lds<<<grid, threads, head + U * row, st>>>(tr, back, eq_p0, eq_d0, U);
+    } else {
+        int64_t n = (int64_t)tr.np * nt;
+        k_h3d_rot_dft<<<blocks(n, 256), 256, sizeof(double) * 2 * J, st>>>(tr, back, eq_p0, eq_d0);
+    }
+    return hipGetLastError();
+}
+
 // One chunk of a translation stage: pairs [0, tr.np) of the chunk, target
 // groups [0, ng) with pair ranges goff (chunk-relative).
 hipError_t h3d_translate(const H3DTr& tr_in, const TreeView& tv, const int* eoff_src, const cplx* coef_src,
@@ -1048,8 +1124,7 @@ hipError_t h3d_translate(const H3DTr& tr_in, const TreeView& tv, const int* eoff
     int Ps = tr.Ps, Pt = tr.Pt;
     k_h3d_rot_prep<<<blocks((int64_t)tr.np * Ps * Ps, bs), bs, 0, st>>>(tr, 0, eoff_src, coef_src);
     if ((e = launch_rot_sample<NB>(tr, 0, eoff_src, coef_src, st)) != hipSuccess) return e;
-    int64_t n2 = (int64_t)tr.np * (Ps + 1) * (Ps + 2) / 2;
-    k_h3d_rot_dft<<<blocks(n2, bs), bs, sizeof(double) * 2 * (2 * Ps + 1), st>>>(tr, 0, eq_p0, eq_d0);
+    if ((e = launch_rot_dft(tr, 0, eq_p0, eq_d0, st)) != hipSuccess) return e;
     int64_t n3 = (int64_t)tr.np * tr.nq;
     k_h3d_coax_radial<<<blocks(n3, bs), bs, 0, st>>>(tr);
     {
@@ -1062,8 +1137,7 @@ hipError_t h3d_translate(const H3DTr& tr_in, const TreeView& tv, const int* eoff
     }
     k_h3d_rot_prep<<<blocks((int64_t)tr.np * Pt * Pt, bs), bs, 0, st>>>(tr, 1, nullptr, nullptr);
     if ((e = launch_rot_sample<NB>(tr, 1, nullptr, nullptr, st)) != hipSuccess) return e;
-    int64_t n5 = (int64_t)tr.np * (Pt + 1) * (Pt + 2) / 2;
-    k_h3d_rot_dft<<<blocks(n5, bs), bs, sizeof(double) * 2 * (2 * Pt + 1), st>>>(tr, 1, eq_p0, eq_d0);
+    if ((e = launch_rot_dft(tr, 1, eq_p0, eq_d0, st)) != hipSuccess) return e;
     int64_t n7 = (int64_t)ng * (Pt + 1) * (Pt + 1);
     k_h3d_accum<<<blocks(n7, bs), bs, 0, st>>>(tr, gdst, goff, ng, eoff_dst, coef_dst);
     return hipGetLastError();
