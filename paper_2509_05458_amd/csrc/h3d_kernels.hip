@@ -220,9 +220,12 @@ __device__ void radial_h(cplx rho2, double kw, double sc, int N, cplx* out, int 
 }
 
 // ------------------------------------------------------------------ P2M / P2L
-// One workgroup per box; thread t owns the order m = t - P of the output and
-// sweeps the box's points (or its List-4 boxes' points) in chunks of kPC,
-// whose radial values the first kPC threads compute into LDS.
+// One workgroup per box; the 2P+1 output orders are repeated over S slices of
+// the threads (S = blockDim / (2P+1), so that small P still fills the lanes):
+// thread (slice s, order m) sweeps the points q = s, s + S, ... of each chunk
+// of kPC points of the box (or of its List-4 boxes), whose radial values the
+// first kPC threads compute into LDS, into its slice's accumulators; the
+// slices are added in order at the end.
 constexpr int kPC = 32;
 
 template <bool IRREG>
@@ -235,13 +238,14 @@ __global__ __launch_bounds__(128) void k_h3d_p2x(const int* __restrict__ boxes, 
     int l = tv.level[b];
     int P = tv.P[l];
     double iw = tv.rs[l], kw = hl.kw[l], sc = hl.sc[l];
-    int st = blockDim.x;
+    int W2 = 2 * P + 1, S = blockDim.x / W2;
+    int st = S * W2;                               // accumulator row: [slice][order]
     cplx* acc = lds;                               // [(P+1)][st]
     cplx* rad = acc + (size_t)(P + 1) * st;        // [(P+2)][kPC]
     cplx* py = rad + (size_t)(P + 2) * kPC;        // [kPC][3]
     cplx* ps = py + 3 * kPC;                       // [kPC]
-    int t = threadIdx.x, mm = t - P;
-    bool act = t < 2 * P + 1;
+    int t = threadIdx.x, sl = t / W2, mm = t - sl * W2 - P;
+    bool act = sl < S;
     int am = mm < 0 ? -mm : mm;
     if (act)
         for (int n = am; n <= P; ++n) acc[n * st + t] = mk(0.0, 0.0);
@@ -270,7 +274,7 @@ __global__ __launch_bounds__(128) void k_h3d_p2x(const int* __restrict__ boxes, 
             if (!act) continue;
             // order o = -mm of the source side
             int o = -mm;
-            for (int q = 0; q < cnt; ++q) {
+            for (int q = sl; q < cnt; q += S) {
                 cplx x = py[3 * q], yv = py[3 * q + 1], z = py[3 * q + 2];
                 cplx w = o >= 0 ? mk(x.re - yv.im, x.im + yv.re) : mk(x.re + yv.im, x.im - yv.re);
                 cplx r2 = x * x + yv * yv + z * z;
@@ -286,10 +290,13 @@ __global__ __launch_bounds__(128) void k_h3d_p2x(const int* __restrict__ boxes, 
             }
         }
     }
-    if (act) {
+    __syncthreads();
+    if (act && sl == 0) {
         cplx* o = out + tv.eoff[b];
         for (int nn = am; nn <= P; ++nn) {
-            cplx v = (2.0 * nn + 1.0) * acc[nn * st + t];
+            cplx a = acc[nn * st + t];
+            for (int k = 1; k < S; ++k) a += acc[nn * st + k * W2 + t];
+            cplx v = (2.0 * nn + 1.0) * a;
             if (useL4) o[hnm(nn, mm)] += v;
             else o[hnm(nn, mm)] = v;
         }
@@ -979,8 +986,9 @@ static hipError_t rec_tables(const void** rec, const void** recf)
     return hipSuccess;
 }
 
-static size_t p2x_lds(int P, int st)
+static size_t p2x_lds(int P, int threads)
 {
+    size_t st = (size_t)(threads / (2 * P + 1)) * (2 * P + 1);
     return sizeof(cplx) * ((size_t)(P + 1) * st + (size_t)(P + 2) * kPC + 4 * kPC);
 }
 
@@ -989,7 +997,8 @@ static hipError_t launch_p2x(const int* boxes, int nb, int pmax, const TreeView&
                              const H3DLevels& hl, int useL4, cplx* out, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    int threads = 2 * pmax + 1 <= 64 ? 64 : 128;
+    // up to 128 threads: as many slices of the 2P+1 orders as fit
+    int threads = 128;
     size_t lds = p2x_lds(pmax, threads);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_h3d_p2x<IRREG>,
