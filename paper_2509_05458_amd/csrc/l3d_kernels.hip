@@ -178,31 +178,32 @@ __device__ inline cplx irr_sum(const Vec3& y, int P, const cplx* __restrict__ C)
 }
 
 // ------------------------------------------------------------ P2M / P2L
-// One wavefront per box.  Lane (h, c), c < 2P+1, owns the output order
-// m = c - P for the points h, h + H, ... of each staged chunk (H = 64 / (2P+1)
-// point streams).  The coefficient of order m is (-1)^m X_n^{-m}, i.e. the
+// One workgroup of kL3P2XThreads per box.  Thread (h, c), c < 2P+1, owns the
+// output order m = c - P for the points h, h + H, ... of each staged chunk
+// (H = kL3P2XThreads / (2P+1) point streams).  The coefficient of order m is (-1)^m X_n^{-m}, i.e. the
 // column of |m| started from w- (m >= 0) or from w+ with the sign (-1)^|m|
 // (m < 0); sigma is folded into the start, so a step of the column recurrence
 // adds its value to the lane's LDS accumulator.  The diagonal start takes |m|
 // steps and the column P - |m|, so every lane takes P steps per point.
 constexpr int kP2XChunk = 64;
+constexpr int kL3P2XThreads = 128;
 
 template <bool IRREGULAR>
-__global__ __launch_bounds__(64) void k_l3d_p2x(const int* __restrict__ boxes, TreeView tv, PointsView pv, int useL4,
+__global__ __launch_bounds__(kL3P2XThreads) void k_l3d_p2x(const int* __restrict__ boxes, TreeView tv, PointsView pv, int useL4,
                                                 cplx* __restrict__ out)
 {
     extern __shared__ cplx sh[];
     int b = boxes[blockIdx.x];
     int l = tv.level[b];
     int P = tv.P[l];
-    int ncol = 2 * P + 1, H = 64 / ncol;
+    int ncol = 2 * P + 1, H = blockDim.x / ncol;
     double* pts = reinterpret_cast<double*>(sh);          // [8][kP2XChunk]: x,y,z re, x,y,z im, sigma re, im
     cplx* acc = sh + 4 * kP2XChunk;                      // [H][P+1][ncol]
     double s = tv.rs[l];
     int t = threadIdx.x, h = t / ncol, col = t % ncol;
     int m = col - P, am = m < 0 ? -m : m;
     bool act = h < H;
-    for (int i = t; i < H * (P + 1) * ncol; i += 64) acc[i] = mk(0.0, 0.0);
+    for (int i = t; i < H * (P + 1) * ncol; i += blockDim.x) acc[i] = mk(0.0, 0.0);
     cplx c[3];
     box_centre(tv, b, c);
     double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
@@ -708,14 +709,14 @@ static size_t lds_bytes(int nelem) { return (size_t)nelem * sizeof(cplx); }
 static size_t p2x_lds(int P)
 {
     int ncol = 2 * P + 1;
-    return lds_bytes(4 * kP2XChunk + (64 / ncol) * (P + 1) * ncol);
+    return lds_bytes(4 * kP2XChunk + (kL3P2XThreads / ncol) * (P + 1) * ncol);
 }
 
 hipError_t l3d_p2m(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
                    cplx* mpole, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    k_l3d_p2x<false><<<nb, 64, p2x_lds(P), st>>>(boxes, tv, pv, 0, mpole);
+    k_l3d_p2x<false><<<nb, kL3P2XThreads, p2x_lds(P), st>>>(boxes, tv, pv, 0, mpole);
     return hipGetLastError();
 }
 
@@ -723,7 +724,7 @@ hipError_t l3d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const Po
                    cplx* local, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    k_l3d_p2x<true><<<nb, 64, p2x_lds(P), st>>>(boxes, tv, pv, 1, local);
+    k_l3d_p2x<true><<<nb, kL3P2XThreads, p2x_lds(P), st>>>(boxes, tv, pv, 1, local);
     return hipGetLastError();
 }
 
