@@ -153,8 +153,8 @@ __device__ void radial_j(cplx rho2, double kw, double sc, int N, cplx* out, int 
     {
         // sin z, cos z for complex z
         double s, c;
-        sincos(z.re, &s, &c);
-        double eh = exp(z.im), ehm = exp(-z.im);
+        sincos_cw(z.re, &s, &c);
+        double eh = exp_cw(z.im), ehm = exp_cw(-z.im);
         double ch = 0.5 * (eh + ehm), sh = 0.5 * (eh - ehm);
         sz = mk(s * ch, c * sh);
         cz = mk(c * ch, -s * sh);
@@ -180,7 +180,7 @@ __device__ void radial_h_fwd(cplx rho, double kw, double sc, int N, cplx* out, i
 {
     cplx z = kw * rho;
     cplx iz = cinv(z);
-    cplx e = cexp_(times_i(z));
+    cplx e = cexp_cw(times_i(z));
     cplx h0 = times_i(e * iz) * -1.0;                   // -i e^{iz} / z
     cplx h1 = -(e * (z + mk(0.0, 1.0)) * iz * iz);      // -e^{iz}(z+i)/z^2
     cplx ir2 = cinv(rho * rho);
@@ -399,12 +399,14 @@ __global__ void k_h3d_geo(H3DTr tr, TreeView tv)
     cplx rho = csqrt_p(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
     cplx ir = cinv(rho);
     cplx u[3] = {D[0] * ir, D[1] * ir, D[2] * ir};
-    int k = 0;
-    for (int q = 1; q < 3; ++q)
-        if (cabs2(u[q]) < cabs2(u[k])) k = q;
+    // the axis k with the smallest |u_k|, selected without a run-time index
+    // into the arrays (which would put them on the stack)
+    double m0 = cabs2(u[0]), m1 = cabs2(u[1]), m2 = cabs2(u[2]);
+    int k = m1 < m0 ? 1 : 0;
+    if (m2 < (k ? m1 : m0)) k = 2;
+    cplx uk = k == 0 ? u[0] : (k == 1 ? u[1] : u[2]);
     cplx q1[3];
-    for (int q = 0; q < 3; ++q) q1[q] = -(u[k] * u[q]);
-    q1[k] += mk(1.0, 0.0);
+    for (int q = 0; q < 3; ++q) q1[q] = -(uk * u[q]) + mk(q == k ? 1.0 : 0.0, 0.0);
     cplx nrm = cinv(csqrt_p(q1[0] * q1[0] + q1[1] * q1[1] + q1[2] * q1[2]));
     for (int q = 0; q < 3; ++q) q1[q] = q1[q] * nrm;
     cplx q2[3] = {u[1] * q1[2] - u[2] * q1[1], u[2] * q1[0] - u[0] * q1[2], u[0] * q1[1] - u[1] * q1[0]};

@@ -35,72 +35,6 @@ struct Tile {
 template <int KIND, int PREC>
 struct Kernel;
 
-// sin and cos of x for |x| < 2^20 (the phases kappa Re r of a near field):
-// Cody-Waite reduction x = k pi/2 + t with pi/2 split into a 33-bit head
-// (k * head is exact) and its tail, |t| <= pi/4, then the Taylor series of
-// sin t to t^17 and of cos t to t^18 (truncation below 1e-19 relative), and
-// the quadrant k mod 4.  The constants are pi/2 and its head and tail,
-// computed from pi to 60 digits; the series coefficients are 1/n!.
-__device__ inline void sincos_near(double x, double* sn, double* cs)
-{
-    const double two_over_pi = 0.6366197723675814;
-    const double pio2_hi = 1.5707963267341256;
-    const double pio2_lo = 6.077100506506192e-11;
-    double k = rint(x * two_over_pi);
-    double t = fma(-k, pio2_lo, fma(-k, pio2_hi, x));
-    double t2 = t * t;
-    double ps = 1.0 / 355687428096000.0;                    // 1/17!
-    ps = fma(ps, t2, -1.0 / 1307674368000.0);               // -1/15!
-    ps = fma(ps, t2, 1.0 / 6227020800.0);
-    ps = fma(ps, t2, -1.0 / 39916800.0);
-    ps = fma(ps, t2, 1.0 / 362880.0);
-    ps = fma(ps, t2, -1.0 / 5040.0);
-    ps = fma(ps, t2, 1.0 / 120.0);
-    ps = fma(ps, t2, -1.0 / 6.0);
-    double st = fma(ps * t2, t, t);
-    double pc = 1.0 / 6402373705728000.0;                   // 1/18!
-    pc = fma(pc, t2, -1.0 / 20922789888000.0);              // -1/16!
-    pc = fma(pc, t2, 1.0 / 87178291200.0);
-    pc = fma(pc, t2, -1.0 / 479001600.0);
-    pc = fma(pc, t2, 1.0 / 3628800.0);
-    pc = fma(pc, t2, -1.0 / 40320.0);
-    pc = fma(pc, t2, 1.0 / 720.0);
-    pc = fma(pc, t2, -1.0 / 24.0);
-    pc = fma(pc, t2, 0.5);
-    double ct = fma(-pc, t2, 1.0);
-    int q = (int)k & 3;
-    double s0 = (q & 1) ? ct : st, c0 = (q & 1) ? st : ct;
-    *sn = (q & 2) ? -s0 : s0;
-    *cs = ((q + 1) & 2) ? -c0 : c0;
-}
-
-// exp(y): y = k ln2 + t with ln 2 split as pi/2 above, |t| <= ln2/2, the
-// Taylor series of e^t to t^13 (truncation below 5e-18 relative), times 2^k
-// (which gives 0 and inf beyond the double range, as exp does).
-__device__ inline double exp_near(double y)
-{
-    const double inv_ln2 = 1.4426950408889634;
-    const double ln2_hi = 0.6931471804855391;
-    const double ln2_lo = 7.440617110012397e-11;
-    double k = rint(y * inv_ln2);
-    double t = fma(-k, ln2_lo, fma(-k, ln2_hi, y));
-    double p = 1.0 / 6227020800.0;                          // 1/13!
-    p = fma(p, t, 1.0 / 479001600.0);
-    p = fma(p, t, 1.0 / 39916800.0);
-    p = fma(p, t, 1.0 / 3628800.0);
-    p = fma(p, t, 1.0 / 362880.0);
-    p = fma(p, t, 1.0 / 40320.0);
-    p = fma(p, t, 1.0 / 5040.0);
-    p = fma(p, t, 1.0 / 720.0);
-    p = fma(p, t, 1.0 / 120.0);
-    p = fma(p, t, 1.0 / 24.0);
-    p = fma(p, t, 1.0 / 6.0);
-    p = fma(p, t, 0.5);
-    p = fma(p, t, 1.0);
-    p = fma(p, t, 1.0);
-    return ldexp(p, (int)k);
-}
-
 // 1/sqrt(x) for positive normal x: the hardware estimate y0 (relative error
 // below 2^-24 on gfx950) refined by one third-order step of the binomial
 // series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + O(e^3), e = 1 - x y0^2:
@@ -175,8 +109,8 @@ struct Kernel<1, 0> {
         // near-field phases stay far below 2^20: the expansion-length limit
         // bounds a leaf's width in wavelengths
         double sn, cs;
-        sincos_near(kappa * rr, &sn, &cs);
-        double ex = exp_near(-kappa * ri) * u;
+        sincos_cw(kappa * rr, &sn, &cs);
+        double ex = exp_cw(-kappa * ri) * u;
         gr = (cs * rr + sn * ri) * ex;
         gi = (sn * rr - cs * ri) * ex;
     }
