@@ -607,6 +607,15 @@ __device__ inline double rcp_nr(double b)
     return fma(y, fma(e, e, e), y);
 }
 
+// Polynomial coefficients, read through scalar loads so that each Horner step
+// is one FMA with a scalar addend: atan(t) = t + t^3 sum_k c_atanp[6-k] t^(2k)
+// (below) and atanh(t)/t = sum_k c_logp[10-k] t^(2k) (1/(2k+1)).
+__constant__ double c_atanp[7] = {-0.05797887584396482, 0.07637157054800217, -0.09089056697674516,
+                                  0.11111076353854933, -0.14285713928935914, 0.19999999998180903,
+                                  -0.3333333333332968};
+__constant__ double c_logp[11] = {1.0 / 21.0, 1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0, 1.0 / 11.0,
+                                  1.0 / 9.0,  1.0 / 7.0,  1.0 / 5.0,  1.0 / 3.0,  1.0};
+
 // Argument of (x, y) != (0, 0) in (-pi, pi], as atan2(y, x).  With
 // num = min(|x|, |y|) and den = max(|x|, |y|), atan(num/den) lies in
 // [0, pi/4]; the addition formula atan(t) = atan(c) + atan((t - c)/(1 + t c)),
@@ -627,13 +636,9 @@ __device__ inline double arg2(double x, double y)
     double ac = hi ? 0.7853981633974483 : (mid ? 0.39269908169872414 : 0.0);
     double tp = fma(-c, den, num) * rcp_nr(fma(c, num, den));
     double u = tp * tp;
-    double p = -0.05797887584396482;
-    p = fma(p, u, 0.07637157054800217);
-    p = fma(p, u, -0.09089056697674516);
-    p = fma(p, u, 0.11111076353854933);
-    p = fma(p, u, -0.14285713928935914);
-    p = fma(p, u, 0.19999999998180903);
-    p = fma(p, u, -0.3333333333332968);
+    double p = c_atanp[0];
+#pragma unroll
+    for (int k = 1; k < 7; ++k) p = fma(p, u, c_atanp[k]);
     double th = fma(tp * u, p, tp) + ac;                  // atan(num/den)
     if (sw) th = 1.5707963267948966 - th;
     if (x < 0.0) th = 3.141592653589793 - th;
@@ -654,17 +659,9 @@ __device__ inline double log_pos(double x)
     }
     double t = (m - 1.0) * rcp_nr(m + 1.0);
     double t2 = t * t;
-    double p = 1.0 / 21.0;
-    p = fma(p, t2, 1.0 / 19.0);
-    p = fma(p, t2, 1.0 / 17.0);
-    p = fma(p, t2, 1.0 / 15.0);
-    p = fma(p, t2, 1.0 / 13.0);
-    p = fma(p, t2, 1.0 / 11.0);
-    p = fma(p, t2, 1.0 / 9.0);
-    p = fma(p, t2, 1.0 / 7.0);
-    p = fma(p, t2, 1.0 / 5.0);
-    p = fma(p, t2, 1.0 / 3.0);
-    p = fma(p, t2, 1.0);
+    double p = c_logp[0];
+#pragma unroll
+    for (int k = 1; k < 11; ++k) p = fma(p, t2, c_logp[k]);
     // ln 2 split so that e * ln2_hi is exact for |e| < 2^11
     const double ln2_hi = 0.693147180559890330187045037746;
     const double ln2_lo = 5.4979230187083711552420206e-14;
