@@ -199,22 +199,26 @@ __device__ inline cplx l2p_value(cplx y1, cplx y2, double kappa, double half, do
 // writes its point's values to an LDS row (odd row length, so the rows of
 // neighbouring threads fall in different banks), then lane m sums sigma v_m
 // over the chunk for its coefficients.
+// points per staged chunk: the LDS of a chunk's values (2P+1 per point) bounds
+// how many workgroups a compute unit holds
+constexpr int kP2MChunk = 32;
+
 __global__ __launch_bounds__(64) void k_h2d_p2m(const int* __restrict__ leaves, int nleaf, TreeView tv,
                                                 PointsView pv, double kappa, cplx* __restrict__ mpole)
 {
-    extern __shared__ cplx vv[];          // [64][2P+1] (point-major), then sigma[64]
+    extern __shared__ cplx vv[];          // [kP2MChunk][2P+1] (point-major), then sigma[kP2MChunk]
     int b = leaves[blockIdx.x];
     int l = tv.level[b];
     int P = tv.P[l], nc = 2 * P + 1;
     double r = tv.rs[l], half = 0.5 * kappa / r;
     int nbx = tv.nbox, t = threadIdx.x;
     int64_t n = pv.n;
-    cplx* sg = vv + (size_t)nc * 64;
+    cplx* sg = vv + (size_t)nc * kP2MChunk;
     cplx c1 = mk(tv.cre[b], tv.cim[b]), c2 = mk(tv.cre[nbx + b], tv.cim[nbx + b]);
     cplx acc0 = mk(0.0, 0.0), acc1 = mk(0.0, 0.0);
     int p0 = tv.pbeg[b], p1 = tv.pend[b];
-    for (int j0 = p0; j0 < p1; j0 += 64) {
-        int cnt = min(64, p1 - j0);
+    for (int j0 = p0; j0 < p1; j0 += kP2MChunk) {
+        int cnt = min(kP2MChunk, p1 - j0);
         __syncthreads();
         if (t < cnt) {
             int j = j0 + t;
@@ -914,7 +918,7 @@ hipError_t h2d_p2m(const int* leaves, int nleaf, int pmax, const TreeView& tv, c
                    double kappa, cplx* mpole, hipStream_t st)
 {
     if (nleaf <= 0) return hipSuccess;
-    size_t lds = sizeof(cplx) * (size_t)(2 * pmax + 2) * 64;
+    size_t lds = sizeof(cplx) * (size_t)(2 * pmax + 2) * kP2MChunk;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_h2d_p2m, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);
