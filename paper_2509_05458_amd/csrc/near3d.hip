@@ -52,15 +52,40 @@ __device__ inline double rsq_nr(double x)
 // The FP32 forms use the hardware reciprocal square root directly.
 // With u = 1/|s| and v = 1/t from rsq_nr: |s| = |s|^2 u, t = h v
 // (h = (|s| + Re s)/2), 1/r = (t u, -Im s u v / 2); no division.
+// s = (x - y).(x - y) from the FP64 differences dr + i di, started from the
+// first product (an accumulation started from zero costs a register copy per
+// evaluation: fma(a, b, +0) is not a * b when the product is -0).
+__device__ inline void sdist(const double* dr, const double* di, double& sr, double& si)
+{
+    double a = fma(dr[0], dr[0], -(di[0] * di[0]));
+    a = fma(dr[1], dr[1], a);
+    a = fma(-di[1], di[1], a);
+    a = fma(dr[2], dr[2], a);
+    sr = fma(-di[2], di[2], a);
+    double b = dr[0] * di[0];
+    b = fma(dr[1], di[1], b);
+    si = 2.0 * fma(dr[2], di[2], b);
+}
+__device__ inline void sdistf(const double* dr, const double* di, float& sr, float& si)
+{
+    float x0 = (float)dr[0], x1 = (float)dr[1], x2 = (float)dr[2];
+    float y0 = (float)di[0], y1 = (float)di[1], y2 = (float)di[2];
+    float a = fmaf(x0, x0, -(y0 * y0));
+    a = fmaf(x1, x1, a);
+    a = fmaf(-y1, y1, a);
+    a = fmaf(x2, x2, a);
+    sr = fmaf(-y2, y2, a);
+    float b = x0 * y0;
+    b = fmaf(x1, y1, b);
+    si = 2.0f * fmaf(x2, y2, b);
+}
+
 template <>
 struct Kernel<0, 0> {
     __device__ static void eval(const double* dr, const double* di, double, double& gr, double& gi)
     {
-        double sr = 0.0, si = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            sr += dr[d] * dr[d] - di[d] * di[d];
-            si += 2.0 * dr[d] * di[d];
-        }
+        double sr, si;
+        sdist(dr, di, sr, si);
         if (sr == 0.0 && si == 0.0) { gr = gi = 0.0; return; }
         double q = sr * sr + si * si;
         double u = rsq_nr(q);
@@ -74,12 +99,8 @@ template <>
 struct Kernel<0, 1> {
     __device__ static void eval(const double* dr, const double* di, double, float& gr, float& gi)
     {
-        float sr = 0.0f, si = 0.0f;
-        for (int d = 0; d < 3; ++d) {
-            float a = (float)dr[d], b = (float)di[d];
-            sr += a * a - b * b;
-            si += 2.0f * a * b;
-        }
+        float sr, si;
+        sdistf(dr, di, sr, si);
         if (sr == 0.0f && si == 0.0f) { gr = gi = 0.0f; return; }
         float q = sr * sr + si * si;
         float u = __builtin_amdgcn_rsqf(q);
@@ -95,11 +116,8 @@ template <>
 struct Kernel<1, 0> {
     __device__ static void eval(const double* dr, const double* di, double kappa, double& gr, double& gi)
     {
-        double sr = 0.0, si = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            sr += dr[d] * dr[d] - di[d] * di[d];
-            si += 2.0 * dr[d] * di[d];
-        }
+        double sr, si;
+        sdist(dr, di, sr, si);
         if (sr == 0.0 && si == 0.0) { gr = gi = 0.0; return; }
         double q = sr * sr + si * si;
         double u = rsq_nr(q);
@@ -119,12 +137,8 @@ template <>
 struct Kernel<1, 1> {
     __device__ static void eval(const double* dr, const double* di, double kappa, float& gr, float& gi)
     {
-        float sr = 0.0f, si = 0.0f;
-        for (int d = 0; d < 3; ++d) {
-            float a = (float)dr[d], b = (float)di[d];
-            sr += a * a - b * b;
-            si += 2.0f * a * b;
-        }
+        float sr, si;
+        sdistf(dr, di, sr, si);
         if (sr == 0.0f && si == 0.0f) { gr = gi = 0.0f; return; }
         float kf = (float)kappa;
         float q = sr * sr + si * si;
@@ -144,11 +158,8 @@ template <>
 struct Kernel<1, 2> {
     __device__ static void eval(const double* dr, const double* di, double kappa, float& gr, float& gi)
     {
-        double sr = 0.0, si = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            sr += dr[d] * dr[d] - di[d] * di[d];
-            si += 2.0 * dr[d] * di[d];
-        }
+        double sr, si;
+        sdist(dr, di, sr, si);
         if (sr == 0.0 && si == 0.0) { gr = gi = 0.0f; return; }
         double q = sr * sr + si * si;
         double u = rsq_nr(q);
