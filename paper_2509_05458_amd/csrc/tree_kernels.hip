@@ -295,29 +295,54 @@ __global__ void k_box_delta(const int* __restrict__ coff, int nbox, const double
 // Flags a near pair (List 1) with Re r^2 <= 0 and r^2 != 0: the principal
 // branch of the complexified distance is then not the continuation the
 // expansions assume (the Lipschitz condition of Sec. 4.1 / 5.1 fails).
-__global__ void k_check_near(const int* __restrict__ leaves, const int* __restrict__ pbeg,
-                             const int* __restrict__ pend, const int* __restrict__ l1off,
-                             const int* __restrict__ l1idx, int64_t n, int dim,
-                             const double* __restrict__ xre, const double* __restrict__ xim,
-                             int* __restrict__ flag)
+__global__ __launch_bounds__(64) void k_check_near(const int* __restrict__ leaves, const int* __restrict__ pbeg,
+                                                   const int* __restrict__ pend, const int* __restrict__ l1off,
+                                                   const int* __restrict__ l1idx, int64_t n, int dim,
+                                                   const double* __restrict__ xre, const double* __restrict__ xim,
+                                                   int* __restrict__ flag)
 {
+    // source tiles of 64 points staged in LDS (coalesced loads), read at one
+    // address by the whole wavefront
+    __shared__ double tre[3][64], tim[3][64];
     int b = leaves[blockIdx.x];
+    int t = threadIdx.x;
     int bad = 0;
-    for (int i = pbeg[b] + threadIdx.x; i < pend[b]; i += blockDim.x) {
+    for (int i0 = pbeg[b]; i0 < pend[b]; i0 += 64) {
+        int i = i0 + t;
+        bool ok = i < pend[b];
+        double xr[3] = {0.0, 0.0, 0.0}, xi[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < dim; ++d)
+            if (ok) {
+                xr[d] = xre[d * n + i];
+                xi[d] = xim[d * n + i];
+            }
         for (int e = l1off[b]; e < l1off[b + 1]; ++e) {
             int a = l1idx[e];
             // List 1 is symmetric and s is the same for (i, j) and (j, i): each
             // unordered leaf pair is checked once, from its lower leaf
             if (a < b) continue;
-            for (int j = pbeg[a]; j < pend[a]; ++j) {
-                double sr = 0.0, si = 0.0;
-                for (int d = 0; d < dim; ++d) {
-                    double dr = xre[d * n + i] - xre[d * n + j];
-                    double di = xim[d * n + i] - xim[d * n + j];
-                    sr += dr * dr - di * di;
-                    si += 2.0 * dr * di;
+            for (int j0 = pbeg[a]; j0 < pend[a]; j0 += 64) {
+                int cnt = min(64, pend[a] - j0);
+                __syncthreads();
+                if (t < cnt)
+                    for (int d = 0; d < dim; ++d) {
+                        tre[d][t] = xre[d * n + j0 + t];
+                        tim[d][t] = xim[d * n + j0 + t];
+                    }
+                __syncthreads();
+                if (!ok) continue;
+                for (int q = 0; q < cnt; ++q) {
+                    double dr = xr[0] - tre[0][q], di = xi[0] - tim[0][q];
+                    double sr = dr * dr - di * di, si = dr * di;
+                    for (int d = 1; d < dim; ++d) {
+                        dr = xr[d] - tre[d][q];
+                        di = xi[d] - tim[d][q];
+                        sr = fma(dr, dr, sr);
+                        sr = fma(-di, di, sr);
+                        si = fma(dr, di, si);
+                    }
+                    if (sr <= 0.0 && !(sr == 0.0 && si == 0.0)) bad = 1;
                 }
-                if (sr <= 0.0 && !(sr == 0.0 && si == 0.0)) bad = 1;
             }
         }
     }
