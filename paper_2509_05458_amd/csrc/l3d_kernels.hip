@@ -88,15 +88,20 @@ __device__ inline void col_I(const Vec3& v, int m, int P, bool flip, F f)
     cplx r2 = dot3(v);
     cplx ir2 = cinv(r2);
     cplx d = cinv(csqrt_p(r2));
-    for (int k = 1; k <= am; ++k) d = d * w * ir2 * (double)(2 * k - 1);
+    // w / r2 and z / r2 are folded once, so that a step's dependent chain is a
+    // complex multiply and one fused multiply-add (the ir2 a term is off it)
+    cplx wi = w * ir2, zi = v.z * ir2;
+    for (int k = 1; k <= am; ++k) d = (d * wi) * (double)(2 * k - 1);
     bool neg = (m < 0 && (am & 1)) != flip;
     if (neg) d = -d;
     f(am, d);
     if (am + 1 > P) return;
-    cplx a = d, b = (2.0 * am + 1.0) * (v.z * d * ir2);
+    cplx a = d, b = (2.0 * am + 1.0) * (zi * d);
     f(am + 1, b);
     for (int n = am + 2; n <= P; ++n) {
-        cplx c = ((2.0 * n - 1.0) * (v.z * b) - ((double)(n + am - 1) * (double)(n - am - 1)) * a) * ir2;
+        cplx x = zi * b, y = ir2 * a;
+        double c1 = 2.0 * n - 1.0, c2 = (double)(n + am - 1) * (double)(n - am - 1);
+        cplx c = mk(fma(c1, x.re, -c2 * y.re), fma(c1, x.im, -c2 * y.im));
         f(n, c);
         a = b;
         b = c;
