@@ -315,20 +315,26 @@ __global__ void k_h2d_gen_tr(const int* __restrict__ boxes, int nb, TreeView tv,
 // sums are added through LDS in a fixed order.
 constexpr int kGenMax = 4 * kPMax2D + 1;
 
+// NT = threads of the block (one slice partial each); M2L runs 64-thread
+// blocks and keeps its LDS small so that more of them fit on a CU
+template <int NT>
 struct TrShared {
     cplx g[kGenMax];            // generator window
     cplx m[kNCoef2DMax];        // source coefficients
     double pw[kPwStride];       // r^e of the level that carries the factors
-    cplx part[64];
+    cplx part[NT];
 };
 
+// G lanes per output group (outputs beyond 64 take a second round) and S =
+// blockDim / G slices of the source terms
 __device__ inline void tr_shape(int ncoef, int& G, int& S)
 {
     G = ncoef <= 16 ? 16 : (ncoef <= 32 ? 32 : 64);
-    S = 64 / G;
+    S = (int)blockDim.x / G;
 }
 
-__device__ inline cplx slice_sum(cplx acc, TrShared& sh, int G, int S, int s)
+template <int NT>
+__device__ inline cplx slice_sum(cplx acc, TrShared<NT>& sh, int G, int S, int s)
 {
     if (S == 1) return acc;
     __syncthreads();
@@ -341,10 +347,10 @@ __device__ inline cplx slice_sum(cplx acc, TrShared& sh, int G, int S, int s)
 }
 
 // Entry (m, n) of child c: gm2m[n - m] r_c^(|n-m| + |n| - |m|) (r_c/r_p)^|m|.
-__global__ __launch_bounds__(64) void k_h2d_m2m(const int* __restrict__ boxes, int nb, TreeView tv, H2DOps ops,
+__global__ __launch_bounds__(256) void k_h2d_m2m(const int* __restrict__ boxes, int nb, TreeView tv, H2DOps ops,
                                                 cplx* __restrict__ mpole)
 {
-    __shared__ TrShared sh;
+    __shared__ TrShared<256> sh;
     int p = boxes[xcd_contiguous(blockIdx.x, nb)];
     int l = tv.level[p];
     int Pp = tv.P[l], Pc = tv.P[l + 1];
@@ -352,7 +358,7 @@ __global__ __launch_bounds__(64) void k_h2d_m2m(const int* __restrict__ boxes, i
     int G, S;
     tr_shape(ncoef, G, S);
     int t = threadIdx.x, lane = t % G, s = t / G;
-    for (int e = t; e < kPwStride; e += 64) sh.pw[e] = ops.pw[(size_t)(l + 1) * kPwStride + e];
+    for (int e = t; e < kPwStride; e += blockDim.x) sh.pw[e] = ops.pw[(size_t)(l + 1) * kPwStride + e];
     cplx acc0 = mk(0.0, 0.0), acc1 = mk(0.0, 0.0);
     int c0 = tv.child0[p], nc = tv.nchild[p];
     for (int ci = 0; ci < nc; ++ci) {
@@ -360,8 +366,8 @@ __global__ __launch_bounds__(64) void k_h2d_m2m(const int* __restrict__ boxes, i
         const cplx* Gv = ops.g_m2m + ops.o_tr[c];
         const cplx* M = mpole + tv.eoff[c];
         __syncthreads();
-        for (int i = t; i <= 2 * K; i += 64) sh.g[i] = Gv[i];
-        for (int i = t; i < nsrc; i += 64) sh.m[i] = M[i];
+        for (int i = t; i <= 2 * K; i += blockDim.x) sh.g[i] = Gv[i];
+        for (int i = t; i < nsrc; i += blockDim.x) sh.m[i] = M[i];
         __syncthreads();
         for (int r = 0; r < 2; ++r) {
             int mi = lane + 64 * r;
@@ -393,7 +399,7 @@ __global__ __launch_bounds__(64) void k_h2d_m2l(const int* __restrict__ boxes, i
                                                 H2DOps ops, const cplx* __restrict__ mpole,
                                                 cplx* __restrict__ local)
 {
-    __shared__ TrShared sh;
+    __shared__ TrShared<64> sh;
     int b = boxes[xcd_contiguous(blockIdx.x, nboxes)];
     int l = tv.level[b];
     int P = tv.P[l], ncoef = 2 * P + 1;
@@ -492,10 +498,10 @@ __global__ __launch_bounds__(128) void k_h2d_p2l(const int* __restrict__ boxes, 
 // ------------------------------------------------------------------ L2L
 // Entry (m, n): gl2l[n - m] r_p^(|n-m| + |m| - |n|) (r_c/r_p)^|m|; one
 // workgroup per child.
-__global__ __launch_bounds__(64) void k_h2d_l2l(const int* __restrict__ boxes, int nb, TreeView tv, H2DOps ops,
+__global__ __launch_bounds__(256) void k_h2d_l2l(const int* __restrict__ boxes, int nb, TreeView tv, H2DOps ops,
                                                 cplx* __restrict__ local)
 {
-    __shared__ TrShared sh;
+    __shared__ TrShared<256> sh;
     int c = boxes[xcd_contiguous(blockIdx.x, nb)];
     int p = tv.parent[c];
     int lc = tv.level[c];
@@ -504,11 +510,11 @@ __global__ __launch_bounds__(64) void k_h2d_l2l(const int* __restrict__ boxes, i
     int G, S;
     tr_shape(ncoef, G, S);
     int t = threadIdx.x, lane = t % G, s = t / G;
-    for (int e = t; e < kPwStride; e += 64) sh.pw[e] = ops.pw[(size_t)(lc - 1) * kPwStride + e];
+    for (int e = t; e < kPwStride; e += blockDim.x) sh.pw[e] = ops.pw[(size_t)(lc - 1) * kPwStride + e];
     const cplx* Gv = ops.g_l2l + ops.o_tr[c];
     const cplx* Lp = local + tv.eoff[p];
-    for (int i = t; i <= 2 * K; i += 64) sh.g[i] = Gv[i];
-    for (int i = t; i < nsrc; i += 64) sh.m[i] = Lp[i];
+    for (int i = t; i <= 2 * K; i += blockDim.x) sh.g[i] = Gv[i];
+    for (int i = t; i < nsrc; i += blockDim.x) sh.m[i] = Lp[i];
     __syncthreads();
     double rat = tv.rs[lc] / tv.rs[lc - 1];
     for (int r = 0; r < 2; ++r) {
@@ -942,9 +948,10 @@ hipError_t h2d_gen_ops(const int* pair_b, int npairs, const int* tr_boxes, int n
 hipError_t h2d_m2m(const int* boxes, int nb, int ncoef, const TreeView& tv, const H2DOps& ops, cplx* mpole,
                    hipStream_t st)
 {
-    (void)ncoef;
     if (nb <= 0) return hipSuccess;
-    k_h2d_m2m<<<nb, 64, 0, st>>>(boxes, nb, tv, ops, mpole);
+    // long expansions (the coarse levels, few boxes each) split their source
+    // terms over four times the lanes
+    k_h2d_m2m<<<nb, ncoef > 32 ? 256 : 64, 0, st>>>(boxes, nb, tv, ops, mpole);
     return hipGetLastError();
 }
 
@@ -976,9 +983,8 @@ hipError_t h2d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const Po
 hipError_t h2d_l2l(const int* boxes, int nb, int ncoef, const TreeView& tv, const H2DOps& ops, cplx* local,
                    hipStream_t st)
 {
-    (void)ncoef;
     if (nb <= 0) return hipSuccess;
-    k_h2d_l2l<<<nb, 64, 0, st>>>(boxes, nb, tv, ops, local);
+    k_h2d_l2l<<<nb, ncoef > 32 ? 256 : 64, 0, st>>>(boxes, nb, tv, ops, local);
     return hipGetLastError();
 }
 
