@@ -619,12 +619,13 @@ __device__ inline double rcp_nr(double b)
 
 // Polynomial coefficients, read through scalar loads so that each Horner step
 // is one FMA with a scalar addend: atan(t) = t + t^3 sum_k c_atanp[6-k] t^(2k)
-// (below) and atanh(t)/t = sum_k c_logp[10-k] t^(2k) (1/(2k+1)).
+// and atanh(t)/t = sum_k c_logp[7-k] t^(2k) (both below).
 __constant__ double c_atanp[7] = {-0.05797887584396482, 0.07637157054800217, -0.09089056697674516,
                                   0.11111076353854933, -0.14285713928935914, 0.19999999998180903,
                                   -0.3333333333332968};
-__constant__ double c_logp[11] = {1.0 / 21.0, 1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0, 1.0 / 11.0,
-                                  1.0 / 9.0,  1.0 / 7.0,  1.0 / 5.0,  1.0 / 3.0,  1.0};
+__constant__ double c_logp[8] = {0.07404856752435146, 0.07656263923854066, 0.09091815845727959,
+                                 0.11111098528259822, 0.14285714380321807, 0.19999999999651163,
+                                 0.33333333333333826, 1.0};
 
 // Argument of (x, y) != (0, 0) in (-pi, pi], as atan2(y, x).  With
 // num = min(|x|, |y|) and den = max(|x|, |y|), atan(num/den) lies in
@@ -657,8 +658,11 @@ __device__ inline double arg2(double x, double y)
 
 // Natural logarithm of a positive, finite, normal x: with x = 2^e m,
 // m in [sqrt(1/2), sqrt(2)), log x = e ln 2 + 2 atanh(t), t = (m - 1)/(m + 1),
-// |t| < 0.1716, and atanh t = t sum_k t^(2k) / (2k + 1), truncated after
-// k = 10 (the next term is below 2^-56 relative).  About 1-2 ulp.
+// |t| < B = (sqrt2 - 1)/(sqrt2 + 1) = 0.1716.  atanh t = t P(t^2) with P of
+// degree 7, the odd Chebyshev interpolant of atanh on [-B, B] (nodes of
+// degree 15, computed in extended precision, coefficients rounded): relative
+// error below 1e-17, against 2^-56 for the Taylor series cut after eleven
+// terms.  About 1-2 ulp.
 __device__ inline double log_pos(double x)
 {
     int e;
@@ -671,7 +675,7 @@ __device__ inline double log_pos(double x)
     double t2 = t * t;
     double p = c_logp[0];
 #pragma unroll
-    for (int k = 1; k < 11; ++k) p = fma(p, t2, c_logp[k]);
+    for (int k = 1; k < 8; ++k) p = fma(p, t2, c_logp[k]);
     // ln 2 split so that e * ln2_hi is exact for |e| < 2^11
     const double ln2_hi = 0.693147180559890330187045037746;
     const double ln2_lo = 5.4979230187083711552420206e-14;
@@ -692,6 +696,15 @@ __device__ inline double log_pos(double x)
 // stays in the lane, while the source's column sum travels with the source:
 // after each step it moves one lane down, so after 64 steps lane l holds the
 // column sum of source l, which goes to the partner entry e' = (a, b).
+// (ar, ai) += h (wr + i wi) as four chained FMAs
+__device__ inline void cfma2(double& ar, double& ai, cplx h, double wr, double wi)
+{
+    ar = fma(h.re, wr, ar);
+    ar = fma(-h.im, wi, ar);
+    ai = fma(h.re, wi, ai);
+    ai = fma(h.im, wr, ai);
+}
+
 struct P2PMap {
     const int* row_of;      // target leaf of each List-1 entry
     const int* partner;     // entry (a, b) for entry (b, a)
@@ -699,28 +712,75 @@ struct P2PMap {
     cplx* C;
 };
 
+// Coefficients of the two power series in x = -q behind H0:
+// J0 = sum_k x^k / (k!)^2 and (2/pi) S with S = sum_k H_k x^k / (k!)^2 (H_k
+// harmonic), the factor 2/pi of Y0 taken into the table.
+struct SerCoef {
+    double j, y;
+};
+constexpr int kSerTerms = 40;
+struct SerTab {
+    SerCoef c[kSerTerms];
+};
+constexpr SerTab make_ser_tab()
+{
+    SerTab t{};
+    double a = 1.0, h = 0.0;
+    t.c[0] = {1.0, 0.0};
+    for (int k = 1; k < kSerTerms; ++k) {
+        a /= (double)k * (double)k;
+        h += 1.0 / (double)k;
+        t.c[k] = {a, (2.0 / kPi) * h * a};
+    }
+    return t;
+}
+__constant__ SerTab c_ser = make_ser_tab();
+
+// a - s b with the coefficient a in scalar registers.  Written as one
+// instruction so that the scheduler cannot hoist it into a two-address FMA
+// whose accumulator is a copy of a.
+__device__ inline double fnms_s(double s, double b, double a)
+{
+    double r;
+    asm("v_fma_f64 %0, -%1, %2, %3" : "=v"(r) : "v"(s), "v"(b), "s"(a));
+    return r;
+}
+
 // H0(kappa r) from s = r^2 by the power series with K terms (|kappa r| < 3).
+// Both series have real coefficients, so they are evaluated at the complex x
+// by Knuth's scheme (division by the real quadratic w^2 - 2 Re(x) w + |x|^2,
+// whose roots are x and its conjugate): b_k = a_k + 2 Re(x) b_(k+1)
+// - |x|^2 b_(k+2), then p(x) = x b_1 + a_0 - |x|^2 b_2.  Two FMAs per
+// coefficient instead of a complex product; on |x| <= 2.25 its rounding
+// error matches that of summing the terms.
 __device__ inline cplx h0_series_s(double sr, double si, double k2, double lk2, int K)
 {
-    constexpr SeriesTab T = make_series_tab();
-    double lm = 0.5 * log_pos(sr * sr + si * si) + lk2;   // log|q|
+    double n2 = sr * sr + si * si;                        // |s|^2
+    double ln2 = log_pos(n2);                             // 2 log|s|
     double ag = arg2(sr, si);                             // arg q
-    double qr = -k2 * sr, qi = -k2 * si;                  // -q
-    double tr = 1.0, ti = 0.0, jr = 1.0, ji = 0.0, sr0 = 0.0, si0 = 0.0;
-    for (int k = 1; k <= K; ++k) {
-        double c = T.inv_k2[k];
-        double nr = (tr * qr - ti * qi) * c, ni = (tr * qi + ti * qr) * c;
-        tr = nr;
-        ti = ni;
-        jr += tr;
-        ji += ti;
-        double h = T.harm[k];
-        sr0 += h * tr;
-        si0 += h * ti;
+    double xr = -k2 * sr, xi = -k2 * si;                  // x = -q
+    double rr = 2.0 * xr, ss = (k2 * k2) * n2;            // 2 Re x, |x|^2
+    // two steps per pass with the roles of the two registers alternating
+    // (b_(k+1) in *1, b_(k+2) in *2 at the top); an odd K takes b_K first
+    double bj1 = 0.0, by1 = 0.0, bj2 = 0.0, by2 = 0.0;
+    int k = K;
+    if (K & 1) {
+        bj1 = c_ser.c[K].j;
+        by1 = c_ser.c[K].y;
+        --k;
     }
-    double lgr = 0.5 * lm + kEuler, lgi = 0.5 * ag;
-    double yr = (2.0 / kPi) * (lgr * jr - lgi * ji - sr0);
-    double yi = (2.0 / kPi) * (lgr * ji + lgi * jr - si0);
+    for (; k >= 2; k -= 2) {
+        SerCoef a = c_ser.c[k], a1 = c_ser.c[k - 1];
+        bj2 = fma(rr, bj1, fnms_s(ss, bj2, a.j));         // b_k
+        by2 = fma(rr, by1, fnms_s(ss, by2, a.y));
+        bj1 = fma(rr, bj2, fnms_s(ss, bj1, a1.j));        // b_(k-1)
+        by1 = fma(rr, by2, fnms_s(ss, by1, a1.y));
+    }
+    double jr = fma(xr, bj1, fma(-ss, bj2, 1.0)), ji = xi * bj1;
+    double sr0 = fma(xr, by1, -ss * by2), si0 = xi * by1;  // S has a_0 = 0
+    // Y0 = (2/pi)(log(z/2) + gamma) J0 - (2/pi) S, log(z/2) = log(q)/2
+    double lr = fma(0.5 / kPi, ln2, (lk2 + 2.0 * kEuler) * (1.0 / kPi)), li = ag * (1.0 / kPi);
+    double yr = fma(lr, jr, fma(-li, ji, -sr0)), yi = fma(lr, ji, fma(li, jr, -si0));
     return mk(jr - yi, ji + yr);                          // J0 + i Y0
 }
 
@@ -769,10 +829,8 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_sym(const int* __restrict__ item
                     double si = 2.0 * (d1r * d1i + d2r * d2i);
                     if (sr != 0.0 || si != 0.0) {
                         cplx h = h0_series_s(sr, si, k2, lk2, K);
-                        ar += h.re * ssr[q] - h.im * ssi[q];
-                        ai += h.re * ssi[q] + h.im * ssr[q];
-                        cr += h.re * wr - h.im * wi;
-                        ci += h.re * wi + h.im * wr;
+                        cfma2(ar, ai, h, ssr[q], ssi[q]);
+                        cfma2(cr, ci, h, wr, wi);
                     }
                 }
                 // hand the column sum to the lane that meets this source next
@@ -828,10 +886,8 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_diag(const int* __restrict__ ite
             double si = 2.0 * (d1r * d1i + d2r * d2i);
             if (sr != 0.0 || si != 0.0) {
                 cplx h = h0_series_s(sr, si, k2, lk2, K);
-                ar += h.re * ssr[q] - h.im * ssi[q];
-                ai += h.re * ssi[q] + h.im * ssr[q];
-                cr += h.re * wr - h.im * wi;
-                ci += h.re * wi + h.im * wr;
+                cfma2(ar, ai, h, ssr[q], ssi[q]);
+                cfma2(cr, ci, h, wr, wi);
             }
         }
         cr = __shfl(cr, nxt, 64);
@@ -893,8 +949,7 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_row(const int* __restrict__ item
                 if (sr == 0.0 && si == 0.0) continue;
                 cplx h = SERIES ? h0_series_s(sr, si, k2, lk2, K)
                                 : hankel0_s(mk(sr, si), kappa, c_ghx, c_ghw);
-                ar += h.re * ssr[q] - h.im * ssi[q];
-                ai += h.re * ssi[q] + h.im * ssr[q];
+                cfma2(ar, ai, h, ssr[q], ssi[q]);
             }
         }
         if (active) Crow[i - pb0] = mk(ar, ai);
