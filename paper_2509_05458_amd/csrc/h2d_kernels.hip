@@ -690,12 +690,70 @@ __device__ inline double log_pos(double x)
 // partials of its List-1 entries in list order (deterministic).
 //
 // Symmetric items (a < b, every pair in the small-argument regime): since
-// G(x, y) = G(y, x), one evaluation serves both directions.  A wavefront holds
-// 64 targets of b in its lanes and a tile of 64 sources of a in LDS; at step s
-// lane l pairs its target with source (l + s) mod 64.  The target's row sum
-// stays in the lane, while the source's column sum travels with the source:
-// after each step it moves one lane down, so after 64 steps lane l holds the
-// column sum of source l, which goes to the partner entry e' = (a, b).
+// G(x, y) = G(y, x), one evaluation serves both directions: the row sum of
+// target i and the column sum of source j, which goes to the partner entry
+// e' = (a, b).  Diagonal items (a == b) evaluate each unordered pair once.
+//
+// Pair walk.  The R x C pairs of a tile (R, C <= 64) are spread over all 64
+// lanes, so that every lane but those past the end of the last step is busy
+// (one target per lane would idle 64 - R of them).  With F = min(R, C) and
+// O = max(R, C), pair p has fast index f = p mod F, block g = p div F and
+// other index o = (g + f) mod O.  Within a block the f are distinct and so
+// are the o (F <= O).  A step (64 consecutive p) spans a few blocks; lane p
+// adds its terms into slot g - g0 (g0 = the step's first block) of per-slot
+// row and column sums, so no two lanes of a step touch the same slot entry,
+// and the slots are added in slot order at the end: the result does not
+// depend on timing.  Steps that span more than kPairSlots blocks make several
+// passes over the slots: with F between 32 and 63 a step spans two or three
+// blocks, and two slots (a second pass now and then) beat three, whose LDS
+// costs a wavefront per SIMD.
+constexpr int kPairSlots = 2;
+
+struct PairWalk {
+    int F, O, dF, rF;       // 64 = dF F + rF
+    int f, g;               // this lane's pair
+    __device__ void init(int F_, int O_, int t)
+    {
+        F = F_;
+        O = O_;
+        dF = 64 / F;
+        rF = 64 - dF * F;
+        f = t % F;
+        g = t / F;
+    }
+    __device__ int other() const
+    {
+        int o = g + f;
+        return o >= O ? o - O : o;
+    }
+    __device__ void next()
+    {
+        f += rF;
+        g += dF;
+        if (f >= F) {
+            f -= F;
+            ++g;
+        }
+    }
+};
+
+// Adds (xr, xi) to row slot sums rs[slot][ri] and (yr, yi) to column slot sums
+// cs[slot][ci] for this lane's block, in as many passes as the step needs.
+__device__ inline void slot_add(double (*rs)[64], double (*rsi)[64], double (*cs)[64], double (*csi)[64],
+                                bool act, int b, int nsl, int ri, int ci, double xr, double xi,
+                                double yr, double yi)
+{
+    for (int ph = 0; ph < nsl; ph += kPairSlots) {
+        int sl = b - ph;
+        if (act && sl >= 0 && sl < kPairSlots) {
+            rs[sl][ri] += xr;
+            rsi[sl][ri] += xi;
+            cs[sl][ci] += yr;
+            csi[sl][ci] += yi;
+        }
+    }
+}
+
 // (ar, ai) += h (wr + i wi) as four chained FMAs
 __device__ inline void cfma2(double& ar, double& ai, cplx h, double wr, double wi)
 {
@@ -787,7 +845,9 @@ __device__ inline cplx h0_series_s(double sr, double si, double k2, double lk2, 
 __global__ __launch_bounds__(64) void k_h2d_p2p_sym(const int* __restrict__ items, const int* __restrict__ nterm,
                                                     P2PMap mp, TreeView tv, PointsView pv, double kappa)
 {
-    __shared__ double s1r[64], s1i[64], s2r[64], s2i[64], ssr[64], ssi[64];
+    __shared__ double s1r[64], s1i[64], s2r[64], s2i[64], ssr[64], ssi[64];   // source tile
+    __shared__ double t1r[64], t1i[64], t2r[64], t2i[64], twr[64], twi[64];   // target tile
+    __shared__ double rs[kPairSlots][64], rsi[kPairSlots][64], cs[kPairSlots][64], csi[kPairSlots][64];
     int e = items[blockIdx.x], K = nterm[blockIdx.x];
     int b = mp.row_of[e], a = tv.l1idx[e], ep = mp.partner[e];
     int64_t n = pv.n;
@@ -797,112 +857,140 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_sym(const int* __restrict__ item
     cplx* Crow = mp.C + mp.coff[e];
     cplx* Ccol = mp.C + mp.coff[ep];
     for (int i0 = pb0; i0 < pb1; i0 += 64) {
-        int i = i0 + t;
-        bool ti_ok = i < pb1;
-        double x1r = 0, x1i = 0, x2r = 0, x2i = 0, wr = 0, wi = 0;
-        if (ti_ok) {
-            x1r = pv.xre[i]; x1i = pv.xim[i];
-            x2r = pv.xre[n + i]; x2i = pv.xim[n + i];
-            wr = pv.sre[i]; wi = pv.sim[i];
+        int R = min(64, pb1 - i0);
+        __syncthreads();
+        if (t < R) {
+            int i = i0 + t;
+            t1r[t] = pv.xre[i]; t1i[t] = pv.xim[i];
+            t2r[t] = pv.xre[n + i]; t2i[t] = pv.xim[n + i];
+            twr[t] = pv.sre[i]; twi[t] = pv.sim[i];
         }
-        double ar = 0.0, ai = 0.0;
+        for (int k = 0; k < kPairSlots; ++k) rs[k][t] = rsi[k][t] = 0.0;
         for (int j0 = pa0; j0 < pa1; j0 += 64) {
-            int cnt = min(64, pa1 - j0);
+            int C = min(64, pa1 - j0);
             __syncthreads();
-            if (t < cnt) {
+            if (t < C) {
                 int j = j0 + t;
                 s1r[t] = pv.xre[j]; s1i[t] = pv.xim[j];
                 s2r[t] = pv.xre[n + j]; s2i[t] = pv.xim[n + j];
                 ssr[t] = pv.sre[j]; ssi[t] = pv.sim[j];
             }
+            for (int k = 0; k < kPairSlots; ++k) cs[k][t] = csi[k][t] = 0.0;
             __syncthreads();
-            // rotation with period L = max(rows, sources): see k_near3 in near3d.hip
-            int R = min(64, pb1 - i0), L = max(R, cnt);
-            int nxt = t < L ? (t + 1 == L ? 0 : t + 1) : t;
-            double cr = 0.0, ci = 0.0;   // column sum of source (t + step) mod L
-            int q = t < L ? t : 0;
-            for (int step = 0; step < L; ++step) {
-                if (ti_ok && q < cnt) {
-                    double d1r = x1r - s1r[q], d1i = x1i - s1i[q];
-                    double d2r = x2r - s2r[q], d2i = x2i - s2i[q];
+            bool rfast = R <= C;                      // targets on the fast index
+            int P = R * C;
+            PairWalk w;
+            w.init(rfast ? R : C, rfast ? C : R, t);
+            for (int p0 = 0; p0 < P; p0 += 64) {
+                bool act = p0 + t < P;
+                int o = w.other();
+                int i = rfast ? w.f : o, j = rfast ? o : w.f;
+                int g0 = __builtin_amdgcn_readfirstlane(w.g);
+                int last = min(63, P - 1 - p0);
+                int nsl = __shfl(w.g, last, 64) - g0 + 1;
+                double xr = 0.0, xi = 0.0, yr = 0.0, yi = 0.0;
+                if (act) {
+                    double d1r = t1r[i] - s1r[j], d1i = t1i[i] - s1i[j];
+                    double d2r = t2r[i] - s2r[j], d2i = t2i[i] - s2i[j];
                     double sr = d1r * d1r - d1i * d1i + d2r * d2r - d2i * d2i;
                     double si = 2.0 * (d1r * d1i + d2r * d2i);
                     if (sr != 0.0 || si != 0.0) {
                         cplx h = h0_series_s(sr, si, k2, lk2, K);
-                        cfma2(ar, ai, h, ssr[q], ssi[q]);
-                        cfma2(cr, ci, h, wr, wi);
+                        cfma2(xr, xi, h, ssr[j], ssi[j]);
+                        cfma2(yr, yi, h, twr[i], twi[i]);
                     }
                 }
-                // hand the column sum to the lane that meets this source next
-                cr = __shfl(cr, nxt, 64);
-                ci = __shfl(ci, nxt, 64);
-                if (++q >= L) q -= L;
+                slot_add(rs, rsi, cs, csi, act, w.g - g0, nsl, i, j, xr, xi, yr, yi);
+                w.next();
             }
-            if (t < cnt) {
+            __syncthreads();
+            if (t < C) {
+                double cr = cs[0][t], ci = csi[0][t];
+                for (int k = 1; k < kPairSlots; ++k) {
+                    cr += cs[k][t];
+                    ci += csi[k][t];
+                }
                 cplx* cc = Ccol + (j0 - pa0) + t;
                 if (i0 == pb0) *cc = mk(cr, ci);
                 else *cc = *cc + mk(cr, ci);
             }
         }
-        if (ti_ok) Crow[i - pb0] = mk(ar, ai);
+        __syncthreads();
+        if (t < R) {
+            double ar = rs[0][t], ai = rsi[0][t];
+            for (int k = 1; k < kPairSlots; ++k) {
+                ar += rs[k][t];
+                ai += rsi[k][t];
+            }
+            Crow[i0 + t - pb0] = mk(ar, ai);
+        }
     }
 }
 
-// Diagonal items (a == b, at most 64 points, series regime): the same
-// rotation within one tile of L points.  Steps s = 1..L/2 pair lane l with
-// point (l + s) mod L, which covers every unordered pair once (at s = L/2,
-// L even, only lanes l < L/2 work, since (l, l + L/2) and (l + L/2, l) are the
-// same pair); a final shuffle returns each travelling column sum to its own
-// lane.
+// Diagonal items (a == b, at most 64 points, series regime): the L(L - 1)/2
+// unordered pairs in the pair walk with F = O = L, where block g pairs point
+// f with point (f + g + 1) mod L: blocks g < (L - 1)/2 hold L pairs each and,
+// for even L, the last block the L/2 pairs (f, f + L/2), f < L/2.  Point f
+// gains the term of its partner as a row sum and the partner that of f as a
+// column sum.
 __global__ __launch_bounds__(64) void k_h2d_p2p_diag(const int* __restrict__ items, const int* __restrict__ nterm,
                                                      P2PMap mp, TreeView tv, PointsView pv, double kappa)
 {
     __shared__ double s1r[64], s1i[64], s2r[64], s2i[64], ssr[64], ssi[64];
+    __shared__ double rs[kPairSlots][64], rsi[kPairSlots][64], cs[kPairSlots][64], csi[kPairSlots][64];
     int e = items[blockIdx.x], K = nterm[blockIdx.x];
     int b = mp.row_of[e];
     int64_t n = pv.n;
     int t = threadIdx.x;
     double k2 = 0.25 * kappa * kappa, lk2 = log(k2);
-    int p0 = tv.pbeg[b], cnt = tv.pend[b] - p0;
-    bool ok = t < cnt;
-    if (ok) {
-        int j = p0 + t;
+    int p0b = tv.pbeg[b], L = tv.pend[b] - p0b;
+    if (t < L) {
+        int j = p0b + t;
         s1r[t] = pv.xre[j]; s1i[t] = pv.xim[j];
         s2r[t] = pv.xre[n + j]; s2i[t] = pv.xim[n + j];
         ssr[t] = pv.sre[j]; ssi[t] = pv.sim[j];
     }
+    for (int k = 0; k < kPairSlots; ++k) rs[k][t] = rsi[k][t] = cs[k][t] = csi[k][t] = 0.0;
     __syncthreads();
-    double x1r = s1r[t & 63], x1i = s1i[t & 63], x2r = s2r[t & 63], x2i = s2i[t & 63];
-    double wr = ssr[t & 63], wi = ssi[t & 63];
-    double ar = 0.0, ai = 0.0, cr = 0.0, ci = 0.0;
-    int L = cnt, nxt = t < L ? (t + 1 == L ? 0 : t + 1) : t;
-    int q = t + 1 < L ? t + 1 : 0;
-    for (int step = 1; 2 * step <= L; ++step) {
-        // the column sum held here belongs to point (t + step) mod L
-        if (ok && (2 * step < L || 2 * t < L)) {
-            double d1r = x1r - s1r[q], d1i = x1i - s1i[q];
-            double d2r = x2r - s2r[q], d2i = x2i - s2i[q];
+    int P = L * (L - 1) / 2;
+    PairWalk w;
+    w.init(L > 0 ? L : 1, L > 0 ? L : 1, t);
+    for (int p0 = 0; p0 < P; p0 += 64) {
+        bool act = p0 + t < P;
+        int i = w.f;
+        int j = i + w.g + 1;
+        if (j >= L) j -= L;
+        int g0 = __builtin_amdgcn_readfirstlane(w.g);
+        int last = min(63, P - 1 - p0);
+        int nsl = __shfl(w.g, last, 64) - g0 + 1;
+        double xr = 0.0, xi = 0.0, yr = 0.0, yi = 0.0;
+        if (act) {
+            double d1r = s1r[i] - s1r[j], d1i = s1i[i] - s1i[j];
+            double d2r = s2r[i] - s2r[j], d2i = s2i[i] - s2i[j];
             double sr = d1r * d1r - d1i * d1i + d2r * d2r - d2i * d2i;
             double si = 2.0 * (d1r * d1i + d2r * d2i);
             if (sr != 0.0 || si != 0.0) {
                 cplx h = h0_series_s(sr, si, k2, lk2, K);
-                cfma2(ar, ai, h, ssr[q], ssi[q]);
-                cfma2(cr, ci, h, wr, wi);
+                cfma2(xr, xi, h, ssr[j], ssi[j]);
+                cfma2(yr, yi, h, ssr[i], ssi[i]);
             }
         }
-        cr = __shfl(cr, nxt, 64);
-        ci = __shfl(ci, nxt, 64);
-        if (++q >= L) q -= L;
+        slot_add(rs, rsi, cs, csi, act, w.g - g0, nsl, i, j, xr, xi, yr, yi);
+        w.next();
     }
-    // after L/2 hand-offs lane u holds the sum of point (u + L/2 + 1) mod L
-    int src = t;
+    __syncthreads();
     if (t < L) {
-        src = t - L / 2 - 1;
-        while (src < 0) src += L;
+        double ar = rs[0][t], ai = rsi[0][t];
+        for (int k = 1; k < kPairSlots; ++k) {
+            ar += rs[k][t];
+            ai += rsi[k][t];
+        }
+        for (int k = 0; k < kPairSlots; ++k) {
+            ar += cs[k][t];
+            ai += csi[k][t];
+        }
+        mp.C[mp.coff[e] + t] = mk(ar, ai);
     }
-    cr = __shfl(cr, src, 64);
-    ci = __shfl(ci, src, 64);
-    if (ok) mp.C[mp.coff[e] + t] = mk(ar + cr, ai + ci);
 }
 
 // Row items: one direction of an entry, the small-argument series (SERIES,
