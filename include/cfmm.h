@@ -142,12 +142,18 @@ int cfmm_plan_export_centers(cfmm_plan_t plan, void* centers);
 int cfmm_plan_export_expansions(cfmm_plan_t plan, void* mpole, void* local, int64_t* offsets,
                                 int64_t* count);
 
-/* Per-stage timing: when enabled, cfmm_eval records HIP events around each
- * stage on the plan's stream; cfmm_stage_ms reads the last evaluation's
- * times (after cfmm_sync).  Stages: 0 gather, 1 P2M, 2 M2M, 3 M2L+P2L,
- * 4 L2L, 5 L2P+M2P, 6 P2P (+ scatter), 7 whole eval. */
-int cfmm_set_profiling(cfmm_plan_t plan, int enable);
+/* Per-stage timing.  mode 0: off.  mode 1: cfmm_eval records HIP events
+ * around each stage on the plan's stream; cfmm_stage_ms reads the last
+ * evaluation's times (after cfmm_sync).  Stages: 0 gather, 1 P2M, 2 M2M,
+ * 3 M2L+P2L, 4 L2L, 5 L2P+M2P, 6 P2P (+ scatter), 7 whole eval.
+ * mode 2: only stage 6 is bracketed, each evaluation into its own slot of a
+ * ring of 64 event pairs, so back-to-back evaluations need no host sync;
+ * setting mode 2 empties the ring.  cfmm_near_ms (after cfmm_sync) writes
+ * the summed stage-6 time of the last min(count, 64) evaluations recorded
+ * since, and their number to *count.  Any other mode: CFMM_EINVAL. */
+int cfmm_set_profiling(cfmm_plan_t plan, int mode);
 int cfmm_stage_ms(cfmm_plan_t plan, int stage, double* ms);
+int cfmm_near_ms(cfmm_plan_t plan, double* total_ms, int* count);
 
 /* ---- host-side planning logic, callable without a GPU (for checking) ----
  * The integer tree and Lists 1-4 that cfmm_plan builds from the

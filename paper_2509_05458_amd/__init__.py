@@ -78,6 +78,7 @@ def lib():
         L.cfmm_plan_export_centers.argtypes = [vp, vp]
         L.cfmm_plan_export_expansions.argtypes = [vp, vp, vp, i64p, i64p]
         L.cfmm_set_profiling.argtypes = [vp, ctypes.c_int]
+        L.cfmm_near_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         L.cfmm_stage_ms.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.cfmm_htree_build.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64, u64p, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int]
@@ -230,8 +231,15 @@ class Plan:
                                                  None, None))
         return mp[:cnt.value], lc[:cnt.value], off
 
-    def set_profiling(self, on: bool = True):
-        _check(lib().cfmm_set_profiling(self._handle, 1 if on else 0))
+    def set_profiling(self, mode=True):
+        """0/False off, 1/True every stage (stage_ms), 2 near-field ring (near_ms)."""
+        _check(lib().cfmm_set_profiling(self._handle, int(mode)))
+
+    def near_ms(self):
+        """(summed near-field stage ms, evaluations) recorded in profiling mode 2."""
+        tot, cnt = ctypes.c_double(), ctypes.c_int()
+        _check(lib().cfmm_near_ms(self._handle, ctypes.byref(tot), ctypes.byref(cnt)))
+        return tot.value, cnt.value
 
     def stage_ms(self) -> dict:
         out = {}

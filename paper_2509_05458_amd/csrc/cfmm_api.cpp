@@ -122,9 +122,13 @@ struct cfmm_plan_s {
     int64_t ecount = 0;
     int64_t info[16];
 
-    bool prof = false;
+    int prof = 0;                       // 0 off, 1 every stage, 2 near-field ring
     hipEvent_t ev[8];
     bool ev_made = false;
+    static constexpr int kRing = 64;    // evaluations whose near-field time is kept
+    hipEvent_t rev[2 * kRing];
+    bool rev_made = false;
+    int64_t ring_n = 0;                 // evaluations recorded since mode 2 was set
 
     template <class T>
     int alloc(T** p, size_t count)
@@ -149,6 +153,8 @@ struct cfmm_plan_s {
         for (void* q : allocs) hipFree(q);
         if (ev_made)
             for (int i = 0; i < 8; ++i) hipEventDestroy(ev[i]);
+        if (rev_made)
+            for (int i = 0; i < 2 * kRing; ++i) hipEventDestroy(rev[i]);
     }
 
     TreeView view() const
@@ -932,11 +938,22 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         sig = p->d_io_in;
         out = p->d_io_out;
     }
-    if (p->prof && !p->ev_made) {
+    if (p->prof == 1 && !p->ev_made) {
         for (int i = 0; i < 8; ++i) HIPCHK(hipEventCreate(&p->ev[i]));
         p->ev_made = true;
     }
-    auto mark = [&](int i) -> hipError_t { return p->prof ? hipEventRecord(p->ev[i], st) : hipSuccess; };
+    if (p->prof == 2 && !p->rev_made) {
+        for (int i = 0; i < 2 * cfmm_plan_s::kRing; ++i) HIPCHK(hipEventCreate(&p->rev[i]));
+        p->rev_made = true;
+    }
+    // mode 1 brackets every stage; mode 2 only the near field (stage 6), into
+    // the next ring slot, so that back-to-back evaluations need no host sync
+    int slot = (int)(p->ring_n % cfmm_plan_s::kRing);
+    auto mark = [&](int i) -> hipError_t {
+        if (p->prof == 1) return hipEventRecord(p->ev[i], st);
+        if (p->prof == 2 && i >= 6) return hipEventRecord(p->rev[2 * slot + (i - 6)], st);
+        return hipSuccess;
+    };
     TreeView tv = p->view();
     PointsView pv = p->pview();
     const HostTree& t = p->tree;
@@ -1079,6 +1096,7 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
                          p->d_perm, out, st));
     }
     HIPCHK(mark(7));
+    if (p->prof == 2) ++p->ring_n;
     if (!on_device) {
         HIPCHK(hipMemcpyAsync(potential, p->d_io_out, 2 * n * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1261,10 +1279,27 @@ int cfmm_plan_export_expansions(cfmm_plan_t p, void* mpole, void* local, int64_t
     return CFMM_OK;
 }
 
-int cfmm_set_profiling(cfmm_plan_t p, int enable)
+int cfmm_set_profiling(cfmm_plan_t p, int mode)
 {
     if (!p) return fail(CFMM_EINVAL, "plan is NULL");
-    p->prof = enable != 0;
+    if (mode < 0 || mode > 2) return fail(CFMM_EINVAL, "profiling mode must be 0, 1 or 2");
+    p->prof = mode;
+    if (mode == 2) p->ring_n = 0;
+    return CFMM_OK;
+}
+
+int cfmm_near_ms(cfmm_plan_t p, double* total_ms, int* count)
+{
+    if (!p || !total_ms || !count) return fail(CFMM_EINVAL, "bad argument");
+    int n = (int)(p->ring_n < cfmm_plan_s::kRing ? p->ring_n : cfmm_plan_s::kRing);
+    double tot = 0.0;
+    for (int s = 0; s < n; ++s) {
+        float f = 0.0f;
+        HIPCHK(hipEventElapsedTime(&f, p->rev[2 * s], p->rev[2 * s + 1]));
+        tot += f;
+    }
+    *total_ms = tot;
+    *count = n;
     return CFMM_OK;
 }
 

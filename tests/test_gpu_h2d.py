@@ -147,3 +147,35 @@ def test_invalid_geometry_is_rejected():
     with pytest.raises(cf.CfmmError) as ei:
         cf.Plan(bad, "helmholtz", 1.0, 1e-6)
     assert ei.value.code == cf.CFMM_EGEOMETRY
+
+
+def test_profiling_modes():
+    """Mode 1 brackets every stage of the last evaluation; mode 2 keeps the
+    near-field time of back-to-back evaluations (ring of 64) without a host
+    sync between them; other modes are rejected."""
+    cfg = synth.make_config(0)
+    pts = torch.from_numpy(cfg.points).cuda()
+    sig = torch.from_numpy(cfg.sigma).cuda()
+    plan = cf.Plan(pts, "helmholtz", cfg.kappa, 1e-6)
+    out = torch.empty_like(sig)
+    plan.set_profiling(1)
+    plan.eval_into(sig, out)
+    torch.cuda.synchronize()
+    st = plan.stage_ms()
+    assert all(v >= 0.0 for v in st.values()) and st["eval"] > 0.0
+    plan.set_profiling(2)
+    for _ in range(3):
+        plan.eval_into(sig, out)
+    torch.cuda.synchronize()
+    tot, cnt = plan.near_ms()
+    assert cnt == 3 and tot > 0.0
+    for _ in range(70):
+        plan.eval_into(sig, out)
+    torch.cuda.synchronize()
+    tot2, cnt2 = plan.near_ms()
+    assert cnt2 == 64 and tot2 > 0.0
+    plan.set_profiling(0)
+    with pytest.raises(cf.CfmmError):
+        plan.set_profiling(3)
+    u0 = plan(sig).cpu().numpy()
+    assert oracle.rel_l2(u0, out.cpu().numpy()) == 0.0
