@@ -122,6 +122,46 @@ __device__ inline void regular_values(cplx y1, cplx y2, double kappa, double hal
     }
 }
 
+// The same values computed by two lanes, t and t ^ 32, of one wavefront:
+// side = +1 writes v_n, n = 0..P, side = -1 writes v_{-n}, n = 0..P (v_0 by
+// both, the same value).  Each lane sums one of the two starting series (at P
+// and P+1) and takes the other from its partner; both run the downward
+// recurrence, and each expands its own half.  Both lanes must be active and
+// have the same point.
+__device__ inline void regular_values_pair(cplx y1, cplx y2, double kappa, double half, double r, int P,
+                                           cplx* v, int side)
+{
+    cplx zp = mk(y1.re - y2.im, y1.im + y2.re);   // y1 + i y2
+    cplx zm = mk(y1.re + y2.im, y1.im - y2.re);   // y1 - i y2
+    cplx qq = (-0.25 * kappa * kappa) * (y1 * y1 + y2 * y2);
+    cplx bp, bm;
+    bool fact;
+    if (cabs2(qq) <= (double)(P + 1) * (double)(P + 1)) {
+        cplx mine = series_s(qq, side > 0 ? P + 1 : P);
+        cplx other = mk(__shfl_xor(mine.re, 32, 64), __shfl_xor(mine.im, 32, 64));
+        cplx hi = side > 0 ? mine : other, cur = side > 0 ? other : mine;
+        v[P * side] = cur;
+        for (int k = P; k >= 1; --k) {
+            cplx lo = cur + (qq * hi) * (c_rcp[k] * c_rcp[k + 1]);
+            v[(k - 1) * side] = lo;
+            hi = cur;
+            cur = lo;
+        }
+        bp = half * zp;
+        bm = half * zm;
+        fact = true;
+    } else {
+        jcore2(y1, y2, kappa, r, P, v, side, &bp, &bm, &fact);
+    }
+    cplx pw = mk(1.0, 0.0), base = side > 0 ? bm : bp;
+    for (int k = 1; k <= P; ++k) {
+        double f = fact ? c_rcp[k] : 1.0;
+        pw = (pw * base) * f;
+        cplx w = v[k * side] * pw;
+        v[k * side] = (side < 0 && (k & 1)) ? -w : w;
+    }
+}
+
 // u = sum_n L_n (-1)^n v_{-n} = sum_k s_k (L_k bp^k + (-1)^k L_{-k} bm^k) / k!
 // (k = 0 once), accumulated by Horner in bp and bm while the downward
 // recurrence produces s_k.  L points at L_0.
@@ -195,13 +235,15 @@ __device__ inline cplx l2p_value(cplx y1, cplx y2, double kappa, double half, do
     return cdiv(target, norm) * (Hp + bm * Hm);
 }
 
-// P2M: one workgroup of 64 per leaf; per chunk of up to 64 points each thread
-// writes its point's values to an LDS row (odd row length, so the rows of
-// neighbouring threads fall in different banks), then lane m sums sigma v_m
-// over the chunk for its coefficients.
+// P2M: one workgroup of 64 per leaf; per chunk of up to 32 points, lanes q
+// and q + 32 write point q's values to an LDS row (odd row length, so the
+// rows of neighbouring points fall in different banks), the n >= 0 half and
+// the n <= 0 half, then lane m sums sigma v_m over the chunk for its
+// coefficients.
 // points per staged chunk: the LDS of a chunk's values (2P+1 per point) bounds
 // how many workgroups a compute unit holds
 constexpr int kP2MChunk = 32;
+static_assert(kP2MChunk == 32, "P2M pairs lanes q and q + 32 on point q of a chunk");
 
 __global__ __launch_bounds__(64) void k_h2d_p2m(const int* __restrict__ leaves, int nleaf, TreeView tv,
                                                 PointsView pv, double kappa, cplx* __restrict__ mpole)
@@ -220,12 +262,13 @@ __global__ __launch_bounds__(64) void k_h2d_p2m(const int* __restrict__ leaves, 
     for (int j0 = p0; j0 < p1; j0 += kP2MChunk) {
         int cnt = min(kP2MChunk, p1 - j0);
         __syncthreads();
-        if (t < cnt) {
-            int j = j0 + t;
+        int q = t & 31;
+        if (q < cnt) {
+            int j = j0 + q;
             cplx y1 = mk(pv.xre[j] - c1.re, pv.xim[j] - c1.im);
             cplx y2 = mk(pv.xre[n + j] - c2.re, pv.xim[n + j] - c2.im);
-            regular_values(y1, y2, kappa, half, r, P, vv + (size_t)t * nc + P, 1);
-            sg[t] = mk(pv.sre[j], pv.sim[j]);
+            regular_values_pair(y1, y2, kappa, half, r, P, vv + (size_t)q * nc + P, t < 32 ? 1 : -1);
+            if (t < 32) sg[q] = mk(pv.sre[j], pv.sim[j]);
         }
         __syncthreads();
         if (t < nc)
