@@ -482,11 +482,23 @@ __global__ __launch_bounds__(64) void k_h2d_m2l(const int* __restrict__ boxes, i
 
 // ------------------------------------------------------------------ P2L
 // Sources of the coarser leaves in List 4 go directly into the local
-// expansion (added after M2L wrote it).  Launched per level.  Every thread of
-// the block computes the Hankel sequence of one source of the current chunk
-// into LDS; then thread t accumulates output coefficient t % G over the
-// sources q = t / G (mod S) of the chunk, and the S partial sums are reduced
-// through LDS at the end.
+// expansion (added after M2L wrote it).  Launched per level.  Threads q and
+// q + 64 of the block compute the two Hankel sequences of source q of the
+// current chunk (at most 64) into LDS, H_k e^{+ik phi} r^k and
+// H_k e^{-ik phi} r^k; then thread t accumulates output coefficient t % G
+// over the sources q = t / G (mod S) of the chunk, and the S partial sums
+// are reduced through LDS at the end.
+__device__ inline void hseq2_side(cplx y1, cplx y2, double kappa, double r, int K, cplx* seq, bool pos)
+{
+    cplx bp, bm;
+    hcore2(y1, y2, kappa, r, K, c_ghx, c_ghw, seq, 1, &bp, &bm);
+    cplx b = pos ? bp : bm, pw = mk(1.0, 0.0);
+    for (int k = 1; k <= K; ++k) {
+        pw = pw * b;
+        seq[k] = pw * seq[k];
+    }
+}
+
 __global__ __launch_bounds__(128) void k_h2d_p2l(const int* __restrict__ boxes, TreeView tv,
                                                  PointsView pv, double kappa, int chunk, int pstride,
                                                  cplx* __restrict__ local)
@@ -511,12 +523,13 @@ __global__ __launch_bounds__(128) void k_h2d_p2l(const int* __restrict__ boxes, 
         int q0 = tv.pbeg[c], q1 = tv.pend[c];
         for (int j0 = q0; j0 < q1; j0 += chunk) {
             int cnt = min(chunk, q1 - j0);
-            if (t < cnt) {
-                int j = j0 + t;
+            int qs = t & 63;
+            if (qs < cnt) {
+                int j = j0 + qs;
                 cplx y1 = mk(pv.xre[j] - cb1.re, pv.xim[j] - cb1.im);
                 cplx y2 = mk(pv.xre[n + j] - cb2.re, pv.xim[n + j] - cb2.im);
-                hseq2(y1, y2, kappa, r, P, c_ghx, c_ghw, gp + (size_t)t * pstride, gn + (size_t)t * pstride, 1);
-                ss[t] = mk(pv.sre[j], pv.sim[j]);
+                hseq2_side(y1, y2, kappa, r, P, (t < 64 ? gp : gn) + (size_t)qs * pstride, t < 64);
+                if (t < 64) ss[qs] = mk(pv.sre[j], pv.sim[j]);
             }
             __syncthreads();
             if (mi < ncoef) {
@@ -1160,7 +1173,7 @@ hipError_t h2d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const Po
     if (nb <= 0) return hipSuccess;
     int pstride = P + 1;
     int chunk = (int)(48000 / (sizeof(cplx) * (2 * (size_t)pstride + 1)));
-    chunk = chunk > 128 ? 128 : (chunk < 1 ? 1 : chunk);
+    chunk = chunk > 64 ? 64 : (chunk < 1 ? 1 : chunk);   // threads q and q + 64 share source q
     size_t lds = sizeof(cplx) * ((size_t)chunk * (2 * (size_t)pstride + 1) + 128);
     k_h2d_p2l<<<nb, 128, lds, st>>>(boxes, tv, pv, kappa, chunk, pstride, local);
     return hipGetLastError();
