@@ -1,5 +1,6 @@
 """GPU parity of the 2D Helmholtz path (through the C-ABI) against the oracle:
 the direct FP64 sum for the potentials, the oracle tree for the integer work."""
+import dataclasses
 import os
 
 import numpy as np
@@ -179,3 +180,19 @@ def test_profiling_modes():
         plan.set_profiling(3)
     u0 = plan(sig).cpu().numpy()
     assert oracle.rel_l2(u0, out.cpu().numpy()) == 0.0
+
+
+@pytest.mark.parametrize("leaf,kappa", [(8, 100.0), (24, 100.0), (128, 15.0)])
+def test_series_pair_walk_leaf_sizes(leaf, kappa):
+    """The small-argument near field of the C1 curve (scale 0.1) at leaf
+    sizes whose tiles need several slot passes per step (8, 24) or several
+    tiles per leaf (128; kappa lowered so that those boxes stay in the series
+    regime); every potential against the direct sum."""
+    cfg = dataclasses.replace(synth.make_config(1, n=6000), kappa=kappa)
+    plan, u = _run(cfg, 1e-9, leaf=leaf)
+    nw = plan.near_work()
+    assert nw["evaluations"] < nw["interactions"]     # symmetric items ran
+    u0 = _oracle(cfg, None)
+    e = oracle.rel_l2(u, u0)
+    _say(f"[gpu] c1 n=6000 leaf={leaf} rel_l2={e:.3e} near={nw}")
+    assert e <= 1e-9
