@@ -357,6 +357,36 @@ __global__ void k_h2d_gen_tr(const int* __restrict__ boxes, int nb, TreeView tv,
 // 2P+1 > 64) over the source terms n = -P + s, -P + s + S, ...; the S slice
 // sums are added through LDS in a fixed order.
 constexpr int kGenMax = 4 * kPMax2D + 1;
+static_assert(kGenMax <= 4 * 64 && kNCoef2DMax <= 2 * 64, "M2M/M2L operand prefetch holds 4 + 2 values per lane");
+
+// Operands of one translation held in registers between their load and their
+// store to LDS: generator values i = t + nt k (k < 4, i < ng) and source
+// coefficients i = t + nt k (k < 2, i < nm).
+// (plain double2 registers: a struct of cplx members was kept in scratch)
+using TrRegs = double2[6];
+__device__ inline double2 ld2(const cplx* p)
+{
+    return *reinterpret_cast<const double2*>(p);
+}
+__device__ inline void tr_load(double2 (&r)[6], const cplx* __restrict__ G, int ng,
+                               const cplx* __restrict__ M, int nm, int t, int nt)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        r[k] = (t + k * nt < ng) ? ld2(G + t + k * nt) : double2{0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        r[4 + k] = (t + k * nt < nm) ? ld2(M + t + k * nt) : double2{0.0, 0.0};
+}
+__device__ inline void tr_store(const double2 (&r)[6], cplx* g, int ng, cplx* m, int nm, int t, int nt)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (t + k * nt < ng) g[t + k * nt] = mk(r[k].x, r[k].y);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        if (t + k * nt < nm) m[t + k * nt] = mk(r[4 + k].x, r[4 + k].y);
+}
 
 // NT = threads of the block (one slice partial each); M2L runs 64-thread
 // blocks and keeps its LDS small so that more of them fit on a CU
@@ -404,14 +434,17 @@ __global__ __launch_bounds__(256) void k_h2d_m2m(const int* __restrict__ boxes, 
     for (int e = t; e < kPwStride; e += blockDim.x) sh.pw[e] = ops.pw[(size_t)(l + 1) * kPwStride + e];
     cplx acc0 = mk(0.0, 0.0), acc1 = mk(0.0, 0.0);
     int c0 = tv.child0[p], nc = tv.nchild[p];
+    // the next child's generator and coefficients are loaded into registers
+    // while the current one is summed (2K+1 <= 4 x 64, 2P_c+1 <= 2 x 64)
+    int ng = 2 * K + 1, nt = (int)blockDim.x;
+    TrRegs rr;
+    if (nc > 0) tr_load(rr, ops.g_m2m + ops.o_tr[c0], ng, mpole + tv.eoff[c0], nsrc, t, nt);
     for (int ci = 0; ci < nc; ++ci) {
-        int c = c0 + ci;
-        const cplx* Gv = ops.g_m2m + ops.o_tr[c];
-        const cplx* M = mpole + tv.eoff[c];
         __syncthreads();
-        for (int i = t; i <= 2 * K; i += blockDim.x) sh.g[i] = Gv[i];
-        for (int i = t; i < nsrc; i += blockDim.x) sh.m[i] = M[i];
+        tr_store(rr, sh.g, ng, sh.m, nsrc, t, nt);
         __syncthreads();
+        if (ci + 1 < nc)
+            tr_load(rr, ops.g_m2m + ops.o_tr[c0 + ci + 1], ng, mpole + tv.eoff[c0 + ci + 1], nsrc, t, nt);
         for (int r = 0; r < 2; ++r) {
             int mi = lane + 64 * r;
             if (mi >= ncoef) break;
@@ -451,13 +484,17 @@ __global__ __launch_bounds__(64) void k_h2d_m2l(const int* __restrict__ boxes, i
     int t = threadIdx.x, lane = t % G, s = t / G;
     for (int e = t; e <= 2 * P; e += 64) sh.pw[e] = ops.pw[(size_t)l * kPwStride + e];
     cplx acc0 = mk(0.0, 0.0), acc1 = mk(0.0, 0.0);
-    for (int e = tv.l2off[b]; e < tv.l2off[b + 1]; ++e) {
-        const cplx* Gv = ops.g_m2l + ops.o_m2l[e];
-        const cplx* M = mpole + tv.eoff[tv.l2idx[e]];
+    // the next entry's generator and coefficients are loaded into registers
+    // while the current one is summed (4P+1 <= 4 x 64, 2P+1 <= 2 x 64)
+    int ng = 4 * P + 1, e0 = tv.l2off[b], e1 = tv.l2off[b + 1];
+    TrRegs rr;
+    if (e0 < e1) tr_load(rr, ops.g_m2l + ops.o_m2l[e0], ng, mpole + tv.eoff[tv.l2idx[e0]], ncoef, t, 64);
+    for (int e = e0; e < e1; ++e) {
         __syncthreads();
-        for (int i = t; i <= 4 * P; i += 64) sh.g[i] = Gv[i];
-        for (int i = t; i < ncoef; i += 64) sh.m[i] = M[i];
+        tr_store(rr, sh.g, ng, sh.m, ncoef, t, 64);
         __syncthreads();
+        if (e + 1 < e1)
+            tr_load(rr, ops.g_m2l + ops.o_m2l[e + 1], ng, mpole + tv.eoff[tv.l2idx[e + 1]], ncoef, t, 64);
         for (int r = 0; r < 2; ++r) {
             int mi = lane + 64 * r;
             if (mi >= ncoef) break;
