@@ -12,12 +12,15 @@ definitions (Sec. 4.1, Sec. 5.1, Sec. 6.3):
   practice), R = (0.5 + k) w, r = sqrt(d)/2 w, required at n and n + 1 so a
   zero of g_n cannot end the search early.  Laplace uses (r/R)^n (the
   scale-free form of r^n / R^(n+1)); Helmholtz |H_n(kR) J_n(kr)| in 2D and
-  |h_n(kR) j_n(kr)| in 3D, evaluated with scipy's library routines.
+  |h_n(kR) j_n(kr)| in 3D, evaluated with scipy's library routines.  Where
+  those over- or underflow (small kappa w at high order: |h_n| ~ (2n-1)!!/z^(n+1)
+  leaves the FP64 range) the same product is evaluated in mpmath at 30 digits.
 """
 from __future__ import annotations
 
 import math
 
+import mpmath
 import scipy.special as sp
 
 
@@ -34,13 +37,34 @@ def separation_ratio(dim: int, sep: int) -> float:
     return (0.5 + sep) / (math.sqrt(dim) / 2.0)
 
 
+def _normal(*xs) -> bool:
+    """Every factor finite and of normal magnitude (no overflow, no underflow)."""
+    return all(math.isfinite(abs(x)) and abs(x) >= 1e-300 for x in xs)
+
+
+def _crit_mp(dim, kappa, R, r, n):
+    with mpmath.workdps(30):
+        X, x = mpmath.mpf(kappa) * R, mpmath.mpf(kappa) * r
+        if dim == 2:
+            v = mpmath.hankel1(n, X) * mpmath.besselj(n, x)
+        else:
+            h = mpmath.sqrt(mpmath.pi / (2 * X)) * mpmath.hankel1(n + 0.5, X)
+            j = mpmath.sqrt(mpmath.pi / (2 * x)) * mpmath.besselj(n + 0.5, x)
+            v = h * j
+        return float(abs(v))
+
+
 def _crit(dim, kernel, kappa, R, r, n):
     if kernel == "laplace":
         return (r / R) ** n
     if dim == 2:
-        return abs(sp.hankel1(n, kappa * R) * sp.jv(n, kappa * r))
-    h = sp.spherical_jn(n, kappa * R) + 1j * sp.spherical_yn(n, kappa * R)
-    return abs(h * sp.spherical_jn(n, kappa * r))
+        h, j = sp.hankel1(n, kappa * R), sp.jv(n, kappa * r)
+    else:
+        h = sp.spherical_jn(n, kappa * R) + 1j * sp.spherical_yn(n, kappa * R)
+        j = sp.spherical_jn(n, kappa * r)
+    if _normal(h, j):
+        return abs(h * j)
+    return _crit_mp(dim, kappa, R, r, n)
 
 
 def nterms(dim: int, kernel: str, kappa: float, w: float, sep: int, eps: float,

@@ -14,61 +14,70 @@ namespace {
 // / (k! prod_{i<=k} (2n+2i+1)) at the two top orders, then downward
 // recurrence (stable for the regular solution); valid while x^2 is small
 // next to 2(2 nmax + 5), so the series has no cancellation.
-void jn_series_down(int nmax, double x, double* j)
+template <class T>
+void jn_series_down(int nmax, T x, T* j)
 {
     auto series = [&](int n) {
-        double pref = 1.0;
-        for (int i = 1; i <= n; ++i) pref *= x / (2.0 * i + 1.0);
-        double term = 1.0, sum = 1.0, q = -0.5 * x * x;
+        T pref = 1.0;
+        for (int i = 1; i <= n; ++i) pref *= x / (T)(2.0 * i + 1.0);
+        T term = 1.0, sum = 1.0, q = -(T)0.5 * x * x;
         for (int k = 1; k < 200; ++k) {
-            term *= q / ((double)k * (2.0 * n + 2.0 * k + 1.0));
+            term *= q / (T)((double)k * (2.0 * n + 2.0 * k + 1.0));
             sum += term;
-            if (fabs(term) < 1e-18 * fabs(sum)) break;
+            if (fabsl(term) < 1e-18L * fabsl(sum)) break;
         }
         return pref * sum;
     };
     j[nmax] = series(nmax);
     if (nmax == 0) return;
     j[nmax - 1] = series(nmax - 1);
-    for (int n = nmax - 1; n >= 1; --n) j[n - 1] = (2.0 * n + 1.0) / x * j[n] - j[n + 1];
+    for (int n = nmax - 1; n >= 1; --n) j[n - 1] = (T)(2.0 * n + 1.0) / x * j[n] - j[n + 1];
 }
 
 // j_n by Miller's backward recurrence normalised on j_0 and j_1 (least squares
 // on both, so a zero of either costs nothing).
-void jn_miller(int nmax, double x, double* j)
+template <class T>
+void jn_miller(int nmax, T x, T* j)
 {
     int start = nmax + 20 + (int)(x);
-    std::vector<double> t(start + 2, 0.0);
+    std::vector<T> t(start + 2, 0.0);
     t[start + 1] = 0.0;
     t[start] = 1e-30;
     for (int n = start; n >= 1; --n) {
-        t[n - 1] = (2.0 * n + 1.0) / x * t[n] - t[n + 1];
-        if (fabs(t[n - 1]) > 1e250) {
-            for (int k = n - 1; k <= start; ++k) t[k] *= 1e-250;
+        t[n - 1] = (T)(2.0 * n + 1.0) / x * t[n] - t[n + 1];
+        if (fabsl(t[n - 1]) > 1e250L) {
+            for (int k = n - 1; k <= start; ++k) t[k] *= (T)1e-250L;
         }
     }
-    double j0 = sin(x) / x, j1 = sin(x) / (x * x) - cos(x) / x;
-    double nrm = std::max(fabs(t[0]), fabs(t[1]));
-    double a0 = t[0] / nrm, a1 = t[1] / nrm;
-    double s = (j0 * a0 + j1 * a1) / (a0 * a0 + a1 * a1) / nrm;
+    T j0 = sinl(x) / x, j1 = sinl(x) / (x * x) - cosl(x) / x;
+    T nrm = std::max(fabsl(t[0]), fabsl(t[1]));
+    T a0 = t[0] / nrm, a1 = t[1] / nrm;
+    T s = (j0 * a0 + j1 * a1) / (a0 * a0 + a1 * a1) / nrm;
     for (int n = 0; n <= nmax; ++n) j[n] = s * t[n];
+}
+
+// j_n and y_n for n <= nmax + 1 in the arithmetic T
+template <class T>
+void sph_jy(int nmax, T x, T* jj, T* yy)
+{
+    if (x * x < (T)(2.0 * (2.0 * (nmax + 1) + 5.0))) jn_series_down<T>(nmax + 1, x, jj);
+    else jn_miller<T>(nmax + 1, x, jj);
+    yy[0] = -cosl(x) / x;
+    if (nmax + 1 >= 1) yy[1] = -cosl(x) / (x * x) - sinl(x) / x;
+    for (int n = 1; n <= nmax; ++n) yy[n + 1] = (T)(2.0 * n + 1.0) / x * yy[n] - yy[n - 1];
 }
 
 }  // namespace
 
 void sph_bessel_real(int nmax, double x, double* j, double* y, double* jd, double* yd)
 {
-    std::vector<double> jj(nmax + 2), yy(nmax + 2);
-    if (x * x < 2.0 * (2.0 * (nmax + 1) + 5.0)) jn_series_down(nmax + 1, x, jj.data());
-    else jn_miller(nmax + 1, x, jj.data());
-    yy[0] = -cos(x) / x;
-    if (nmax + 1 >= 1) yy[1] = -cos(x) / (x * x) - sin(x) / x;
-    for (int n = 1; n <= nmax; ++n) yy[n + 1] = (2.0 * n + 1.0) / x * yy[n] - yy[n - 1];
+    std::vector<long double> jj(nmax + 2), yy(nmax + 2);
+    sph_jy<long double>(nmax, x, jj.data(), yy.data());
     for (int n = 0; n <= nmax; ++n) {
-        if (j) j[n] = jj[n];
-        if (y) y[n] = yy[n];
-        if (jd) jd[n] = n / x * jj[n] - jj[n + 1];
-        if (yd) yd[n] = n / x * yy[n] - yy[n + 1];
+        if (j) j[n] = (double)jj[n];
+        if (y) y[n] = (double)yy[n];
+        if (jd) jd[n] = (double)(n / (long double)x * jj[n] - jj[n + 1]);
+        if (yd) yd[n] = (double)(n / (long double)x * yy[n] - yy[n + 1]);
     }
 }
 
@@ -104,11 +113,13 @@ void gauss_legendre(int n, double* x, double* w)
 
 int h3d_nterms(double kappa, double w, int sep, double eps, int pmax)
 {
+    // in x87 extended precision: at small kappa w, |h_n(kR)| ~ (2n-1)!!/(kR)^(n+1)
+    // and j_n(kr) ~ (kr)^n/(2n+1)!! leave the FP64 range long before n = pmax
     double R = (0.5 + sep) * w, r = sqrt(3.0) * 0.5 * w;
-    std::vector<double> jR(pmax + 3), yR(pmax + 3), jr(pmax + 3);
-    sph_bessel_real(pmax + 2, kappa * R, jR.data(), yR.data(), nullptr, nullptr);
-    sph_bessel_real(pmax + 2, kappa * r, jr.data(), nullptr, nullptr, nullptr);
-    auto crit = [&](int n) { return hypot(jR[n], yR[n]) * fabs(jr[n]); };
+    std::vector<long double> jR(pmax + 4), yR(pmax + 4), jr(pmax + 4), yr(pmax + 4);   // orders 0 .. pmax + 3
+    sph_jy<long double>(pmax + 2, (long double)kappa * R, jR.data(), yR.data());
+    sph_jy<long double>(pmax + 2, (long double)kappa * r, jr.data(), yr.data());
+    auto crit = [&](int n) { return sqrtl(jR[n] * jR[n] + yR[n] * yR[n]) * fabsl(jr[n]); };
     for (int n = 1; n <= pmax; ++n)
         if (crit(n) <= eps && crit(n + 1) <= eps) return n;
     return pmax + 1;

@@ -104,6 +104,16 @@ def test_nterms_3d_helmholtz_equals_oracle_rule(eps, w, sep):
     assert got == ref
 
 
+@pytest.mark.parametrize("kappa", [1e-6, 1e-3, 0.3])
+@pytest.mark.parametrize("sep", [1, 2])
+def test_nterms_3d_helmholtz_low_frequency_equals_oracle_rule(kappa, sep):
+    # small kappa w: |h_n| and j_n leave the FP64 range well before n = 50
+    for eps in (1e-6, 1e-10):
+        got = cf.nterms(3, "helmholtz", kappa, 1.0, sep, eps, 50)
+        ref = params.nterms(3, "helmholtz", kappa, 1.0, sep, eps, 50)
+        assert got == ref, (eps, got, ref)
+
+
 def test_2d_laplace_not_supported():
     import ctypes
     pts = np.zeros((4, 2), np.complex128)

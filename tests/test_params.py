@@ -42,3 +42,27 @@ def test_helmholtz_nterms_low_frequency_limit():
     # high frequency: P grows with kappa w (beyond kappa r)
     p_hi = params.nterms(2, "helmholtz", 40.0, 1.0, 1, 1e-10, 400)
     assert p_hi > 40.0 * r
+
+
+@pytest.mark.parametrize("sep,eps", [(1, 1e-6), (2, 1e-6), (2, 1e-10)])
+def test_helmholtz3d_nterms_low_frequency_limit(sep, eps):
+    # small-argument forms (DLMF 10.52.1, 10.52.2): j_n(z) ~ z^n / (2n+1)!! and
+    # |h_n(z)| ~ (2n-1)!! / z^(n+1), so |h_n(kR) j_n(kr)| -> (r/R)^n / ((2n+1) kR)
+    kappa = 1e-6
+    R, r = 0.5 + sep, math.sqrt(3) / 2
+
+    def crit(n):
+        return (r / R) ** n / ((2 * n + 1) * kappa * R)
+
+    expect = next(n for n in range(1, 400) if crit(n) <= eps and crit(n + 1) <= eps)
+    # the closed form is not borderline at this n (so the O((kR)^2) corrections cannot flip it)
+    assert crit(expect - 1) > 1.01 * eps or crit(expect) > 1.01 * eps or expect == 1
+    assert params.nterms(3, "helmholtz", kappa, 1.0, sep, eps, 400) == expect
+
+
+def test_helmholtz3d_nterms_grows_with_frequency():
+    # in the oscillatory range |h_n(kR)| stays O(1/kR) until n passes kR, so the
+    # length must exceed kappa r (the target radius in wavelengths)
+    r = math.sqrt(3) / 2
+    p = params.nterms(3, "helmholtz", 30.0, 1.0, 2, 1e-10, 400)
+    assert p > 30.0 * r

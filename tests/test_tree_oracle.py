@@ -54,6 +54,20 @@ def built(request):
     return pts, T.build_tree(pts, ns, k), ns, k
 
 
+# The library starts the far field at a level >= 2 (boxes coarser than that
+# carry no expansions and count as near everything), so the lists are also
+# pinned at the top levels it uses.
+TOPS = [2, 3, 4]
+
+
+@pytest.fixture(scope="module", params=[(c, top) for c in CASES for top in TOPS],
+                ids=[f"{c[0]}-top{top}" for c in CASES for top in TOPS])
+def built_top(request):
+    (name, make, ns, k), top = request.param
+    pts = make()
+    return pts, T.build_tree(pts, ns, k, top_level=top), ns, k, top
+
+
 def test_points_lie_in_their_leaf_and_occupancy(built):
     pts, t, ns, k = built
     assert sorted(t.perm.tolist()) == list(range(pts.shape[0]))
@@ -96,8 +110,7 @@ def _ancestors(t, b):
     return out
 
 
-def test_every_pair_covered_exactly_once(built):
-    pts, t, ns, k = built
+def _coverage(t):
     rows = {name: [set(idx[off[b]:off[b + 1]].tolist()) for b in range(t.nbox)]
             for name, (off, idx) in t.lists.items()}
     leaves = np.flatnonzero(t.nchild == 0)
@@ -111,21 +124,112 @@ def test_every_pair_covered_exactly_once(built):
             assert n == 1, (b, a, n)
 
 
-def test_list_structure(built):
+def test_every_pair_covered_exactly_once(built):
     pts, t, ns, k = built
+    _coverage(t)
+
+
+def test_every_pair_covered_exactly_once_above_top(built_top):
+    pts, t, ns, k, top = built_top
+    _coverage(t)
+
+
+def _structure(t, k, top):
+    """Row order and symmetry, plus each list's geometric definition, where a
+    box coarser than `top` is near every box (it carries no expansion)."""
+    def near(a, b):
+        if t.level[a] < top or t.level[b] < top:
+            return True
+        return _near_real(t, a, b, k)
+
     rows = {name: [idx[off[b]:off[b + 1]].tolist() for b in range(t.nbox)]
             for name, (off, idx) in t.lists.items()}
     for b in range(t.nbox):
         for name in rows:
             assert rows[name][b] == sorted(set(rows[name][b]))
         for a in rows["L1"][b]:
-            assert b in rows["L1"][a] and _near_real(t, a, b, k)
+            assert b in rows["L1"][a] and near(a, b)
         for a in rows["L2"][b]:
             assert b in rows["L2"][a] and t.level[a] == t.level[b]
-            assert not _near_real(t, a, b, k)
-            assert _near_real(t, t.parent[a], t.parent[b], k)
+            assert t.level[a] >= top
+            assert not near(a, b)
+            assert near(t.parent[a], t.parent[b])
         for a in rows["L3"][b]:
             assert b in rows["L4"][a] and t.level[a] > t.level[b]
-            assert not _near_real(t, a, b, k) and _near_real(t, t.parent[a], b, k)
+            assert t.level[a] >= top
+            assert not near(a, b) and near(t.parent[a], b)
         if t.nchild[b]:
             assert not rows["L1"][b] and not rows["L3"][b]
+        if t.level[b] < top:
+            # no expansion at b: every interaction of b is direct
+            assert not rows["L2"][b] and not rows["L3"][b] and not rows["L4"][b]
+    # List 2 is complete: every same-level pair at or below top that is not
+    # near but whose parents are near is in it
+    for l in range(max(top, 1), int(t.level.max()) + 1):
+        bl = np.flatnonzero(t.level == l)
+        for b in bl:
+            want = sorted(int(a) for a in bl if not near(a, b) and near(t.parent[a], t.parent[b]))
+            assert rows["L2"][b] == want, (b, l)
+
+
+def test_list_structure(built):
+    pts, t, ns, k = built
+    _structure(t, k, 0)
+
+
+def test_list_structure_above_top(built_top):
+    pts, t, ns, k, top = built_top
+    _structure(t, k, top)
+
+
+def _cube_members(t, re, b):
+    """Indices of the points whose real part lies in box b's half-open cube
+    [lo + c w, lo + (c + 1) w) per coordinate, from the box geometry alone."""
+    w = t.D * 2.0 ** (-int(t.level[b]))
+    c = np.array(t.coords(b), dtype=np.float64)
+    lo = t.lo + c * w
+    hi = lo + w
+    inside = np.all((re >= lo) & (re < hi), axis=1)
+    return np.flatnonzero(inside)
+
+
+@pytest.mark.parametrize("case", CASES[:1] + CASES[2:3] + CASES[4:5], ids=lambda c: c[0])
+def test_complex_centers_definition(case):
+    """The complexified centre of every box (Sec. 6.1): its real part is the
+    cube's geometric centre and its imaginary part the mean imaginary part of
+    the points whose real parts lie in the cube, descendants included; the
+    membership here comes from the cube bounds, not from the sorted ranges."""
+    name, make, ns, k = case
+    pts = make()
+    t = T.build_tree(pts, ns, k)
+    cen = T.complex_centers(t, pts)
+    re = pts.real
+    for b in range(t.nbox):
+        members = _cube_members(t, re, b)
+        assert members.size == t.pend[b] - t.pbeg[b] and members.size > 0
+        w = t.D * 2.0 ** (-int(t.level[b]))
+        mid = t.lo + (np.array(t.coords(b), dtype=np.float64) + 0.5) * w
+        assert np.array_equal(cen[b].real, mid)
+        want = pts[members].imag.mean(axis=0)
+        assert np.allclose(cen[b].imag, want, rtol=1e-13, atol=1e-15 * np.abs(pts.imag).max())
+
+
+def test_complex_centers_planted_box():
+    """Hand-made case: four points in two quadrants of the unit square; the
+    level-1 boxes' centres are known in closed form."""
+    pts = np.array([[0.1 + 0.2j, 0.1 + 0.0j], [0.2 + 0.4j, 0.3 - 0.2j],
+                    [0.9 + 1.0j, 0.8 + 0.5j], [0.0 + 0.0j, 1.0 + 0.0j]])
+    t = T.build_tree(pts, 2, 1)
+    cen = T.complex_centers(t, pts)
+    lo, D = t.lo, t.D
+    assert np.allclose(cen[0], (lo + 0.5 * D) + 1j * pts.imag.mean(axis=0), rtol=0, atol=1e-15)
+    for b in range(t.nbox):
+        if t.level[b] != 1:
+            continue
+        members = _cube_members(t, pts.real, b)
+        expect_im = pts[members].imag.mean(axis=0)
+        assert np.allclose(cen[b].imag, expect_im, rtol=0, atol=1e-15)
+    # the lower-left quadrant holds points 0 and 1: Im mean (0.3, -0.1)
+    ll = [b for b in range(t.nbox) if t.level[b] == 1 and t.coords(b) == (0, 0)]
+    assert len(ll) == 1
+    assert np.allclose(cen[ll[0]].imag, [0.3, -0.1], rtol=0, atol=1e-15)
