@@ -7,14 +7,19 @@ Morton sort, tree, centres, lists, expansion lengths) is built once before
 timing, as in the iterative solves the method serves, and its time is
 reported separately.
 
-Workload (default, --workload c1): 2D Helmholtz single layer, N = 2^20
-points on the complexified curve x(t) = (t + i psi(t), 0.2 exp(-t^2)) scaled
-by 0.1, kappa = 100, tolerance 1e-6, FP64.  --workload c2: 3D Laplace on the
-1448^2 complexified plane; c3: 3D Helmholtz on the 1000^2 plane with bumps,
-kappa = 20 * 2 pi / 12.
+Workload (default, --workload c2, the largest single-GPU configuration): 3D
+Laplace single layer, N = 1448^2 = 2,096,704 points on the complexified plane
+(s + i psi(s), t + i psi(t), 0.3 exp(-(s^2 + t^2))), tolerance 1e-6, FP64.
+--workload c1: 2D Helmholtz, N = 2^20 points on the complexified curve
+(t + i psi(t), 0.2 exp(-t^2)) scaled by 0.1, kappa = 100; c3: 3D Helmholtz on
+the 1000^2 plane with bumps, kappa = 20 * 2 pi / 12.
 
 Prints one JSON line.  metric: N^2-equivalent interactions per second,
-N (N - 1) / t_eval.
+N (N - 1) / t_eval, with a roofline block for the dominant kernel (HIP events
+on the plan's stream over the timed steps), the oracle's direct sum on the
+host's cores as cpu_baseline, and a serving block: a seeded stream of
+GMRES-like requests served with overlap and memory admission against the same
+trace replayed sequentially in plain FP64.
 """
 from __future__ import annotations
 
@@ -49,7 +54,6 @@ WORKLOADS = {
     "c2": (2, 3, "laplace", 1e-6, "P2P stage: k_near3_pair + k_near3_diag + k_near3_final", 35.0),
     "c3": (3, 3, "helmholtz", 1e-6, "P2P stage: k_near3_pair + k_near3_diag + k_near3_final", 47.0),
 }
-P2P_FLOPS_PER_INTERACTION = WORKLOADS["c1"][5]
 PEAK_FP64_VALU = 78.6e12          # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
 PEAK_FP32_VALU = 157.3e12
 METRIC = "N\u00b2-equiv interactions/s at 1e-6 rel err; served p50/p99 latency vs plain"
@@ -57,6 +61,7 @@ METRIC = "N\u00b2-equiv interactions/s at 1e-6 rel err; served p50/p99 latency v
 
 TRAFFIC_PROFILES = {
     # FP64 workload: counter summary of its P2P kernels (calibrated HBM bytes per launch)
+    "c2_m2l": "profiles/laplace3d_n2m_m2l_traffic.md",
     "c1": "profiles/helmholtz2d_n1m_p2p_traffic.md",
     "c2": "profiles/laplace3d_n2m_p2p_traffic.md",
     "c3": "profiles/helmholtz3d_n1m_p2p_traffic.md",
@@ -92,7 +97,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--leaf", type=int, default=0)
@@ -102,6 +107,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration for HBM traffic)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving block")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-nmax-log2", type=float, default=16.0)
     return ap.parse_args()
 
 
@@ -137,16 +145,29 @@ def main():
         plan.eval_into(sigs[w % nsig], out)
     torch.cuda.synchronize()
     # timed region: back-to-back evaluations; HIP events on the plan's stream
-    # bracket the near-field stage of each one (profiling mode 2)
-    plan.set_profiling(2)
+    # bracket the roofline kernel of each one (profiling mode 3: the M2L
+    # translations; mode 2: the near-field stage)
+    roof_m2l = a.workload == "c2"
+    plan.set_profiling(3 if roof_m2l else 2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(a.steps):
         plan.eval_into(sigs[s % nsig], out)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    near_tot, near_cnt = plan.near_ms()
+    ring_tot, ring_cnt = plan.ring_ms()
+    # the other stage's ring over a few more evaluations (after the timed region)
+    nside = max(1, min(a.steps, 5))
+    plan.set_profiling(2 if roof_m2l else 3)
+    for s in range(nside):
+        plan.eval_into(sigs[s % nsig], out)
+    torch.cuda.synchronize()
+    side_tot, side_cnt = plan.ring_ms()
     plan.set_profiling(0)
+    if roof_m2l:
+        m2l_ms, near_ms = ring_tot / max(1, ring_cnt), side_tot / max(1, side_cnt)
+    else:
+        near_ms, m2l_ms = ring_tot / max(1, ring_cnt), side_tot / max(1, side_cnt)
     ms_per_step = dt * 1e3 / a.steps
     pairs = n * (n - 1)
     value = pairs / (ms_per_step * 1e-3)
@@ -183,11 +204,33 @@ def main():
                             nthreads=min(16, os.cpu_count() or 1))
     rel = oracle.rel_l2(u_gpu[tg], u0)
 
-    p2p_ms = near_tot / max(1, near_cnt)     # near-field stage, mean over the timed steps
     nw = plan.near_work()
     p2p_flops = (p2p_flops_unit - MAC_FLOPS) * nw["evaluations"] + MAC_FLOPS * nw["interactions"]
-    achieved = p2p_flops / (p2p_ms * 1e-3)
     peak = PEAK_FP64_VALU if a.precision == "fp64" else PEAK_FP32_VALU
+    p2p_block = {
+        "kernel": p2p_kernel, "bound": "alu", "achieved": p2p_flops / (near_ms * 1e-3) / 1e12,
+        "peak": peak / 1e12, "unit": "TFLOP/s", "frac": p2p_flops / (near_ms * 1e-3) / peak,
+        "traffic": measured_traffic(a.workload) if a.precision == "fp64" else None,
+        "flops_per_interaction": p2p_flops_unit, "ms_per_launch_set": near_ms,
+        "near_interactions": nw["interactions"], "near_evaluations": nw["evaluations"],
+    }
+    if roof_m2l:
+        # k_l3d_m2l: the O(P^4) addition-theorem contraction, (P+1)^4 complex
+        # multiply-adds (8 flops) per List-2 pair; P is the same on every level
+        P = info["max_p"]
+        m2l_flops = 8.0 * (P + 1) ** 4 * info["m2l_pairs"]
+        m2l_peak = PEAK_FP64_VALU if not (a.precision == "mixed" and P <= 16) else PEAK_FP32_VALU
+        roof = {
+            "kernel": "k_l3d_m2l" + ("_f32" if m2l_peak == PEAK_FP32_VALU else ""),
+            "bound": "alu", "achieved": m2l_flops / (m2l_ms * 1e-3) / 1e12, "peak": m2l_peak / 1e12,
+            "unit": "TFLOP/s", "frac": m2l_flops / (m2l_ms * 1e-3) / m2l_peak,
+            "traffic": measured_traffic("c2_m2l") if a.precision == "fp64" else None,
+            "flops_per_pair": 8.0 * (P + 1) ** 4, "pairs": info["m2l_pairs"], "ms_per_launch": m2l_ms,
+            "p2p": p2p_block,
+        }
+    else:
+        roof = dict(p2p_block)
+        roof["m2l_ms"] = m2l_ms
     names = {"c1": f"2D Helmholtz single layer, N={n} complexified curve (C0 curve scaled 0.1), "
                    f"kappa={cfg.kappa}, tol={tol}, targets=sources",
              "c2": f"3D Laplace single layer, N={n} complexified plane ({cfg.meta.get('grid')}^2 grid), "
@@ -219,17 +262,7 @@ def main():
             "rel_l2_err_sampled": rel, "err_targets": int(len(tg)),
             "step": "one cfmm_eval on a warm plan",
         },
-        "roofline": {
-            "kernel": p2p_kernel,
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": peak / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / peak,
-            "traffic": measured_traffic(a.workload) if a.precision == "fp64" else None,
-            "flops_per_interaction": p2p_flops_unit,
-            "near_interactions": nw["interactions"], "near_evaluations": nw["evaluations"],
-        },
+        "roofline": roof,
     }
     if not a.no_cpu:
         import oracle as orc
@@ -244,6 +277,27 @@ def main():
             "cores": cores,
             "kind": "oracle",
             "sample": f"{len(ct)} seeded targets x all {n} sources, FP64 direct sum ({cdt:.1f} s)",
+        }
+    if not a.no_serve:
+        del plan, sigs, out, pts
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        from paper_2509_05458_amd import serve
+        sv = serve.serve_benchmark(nreq=a.serve_requests, slots=4, load=0.8,
+                                   nmax_log2=a.serve_nmax_log2, check=4,
+                                   progress=lambda m: print(f"[bench serve] {m}", file=sys.stderr, flush=True))
+        res["serving"] = {
+            "trace": (f"{sv['requests']} seeded requests (trace seed 4000), Poisson arrivals at load 0.8 of the "
+                      f"sequential service rate, N log-uniform in [2^10, 2^{a.serve_nmax_log2:g}], 2D/3D "
+                      f"Helmholtz, kappa in [1, 200], tol in {{1e-4, 1e-6, 1e-10}}, {sv['matvecs'] // sv['requests']}"
+                      f" dependent (Arnoldi) matvecs each"),
+            "slots": sv["slots"], "arrival_rate_per_s": sv["arrival_rate_per_s"],
+            "served": {k: sv["served"][k] for k in ("p50_ms", "p99_ms", "matvecs_per_s", "makespan_s")},
+            "sequential_fp64": {k: sv["sequential_fp64"][k] for k in ("p50_ms", "p99_ms", "matvecs_per_s",
+                                                                     "makespan_s")},
+            "saturation_matvecs_per_s": {"served": sv["burst"]["served_matvecs_per_s"],
+                                         "sequential_fp64": sv["burst"]["sequential_matvecs_per_s"]},
+            "within_tol": sv["within_tol"],
         }
     print(json.dumps(res), flush=True)
 

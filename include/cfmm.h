@@ -4,21 +4,23 @@
  * Evaluates the discrete single-layer sum of the complex-coordinate FMM
  * paper (Sec. 2.3, the M-body sum)
  *
- *     u(x_i) = sum_{j != i} G(x_i, x_j) sigma_j ,   i = 0 .. n-1
+ *     u(x_i) = sum_j G(x_i, y_j) sigma_j ,   i = 0 .. n_trg-1,  j = 0 .. n_src-1
  *
- * at complex points x in C^d (targets = sources, self term excluded), with
- * the complexified distance r = sqrt(sum_d (x_{i,d} - x_{j,d})^2) on the
- * principal branch (Sec. 2.1; complex polar / spherical coordinates of
- * Sec. 3.1).  Kernels:
+ * at complex targets x and sources y in C^d, with the complexified distance
+ * r = sqrt(sum_d (x_{i,d} - y_{j,d})^2) on the principal branch (Sec. 2.1;
+ * complex polar / spherical coordinates of Sec. 3.1).  When no targets are
+ * given, the targets are the sources and the self term j = i is left out.
+ * A pair at squared distance exactly 0 contributes nothing.  Kernels:
  *
  *     dim 2, CFMM_HELMHOLTZ :  G = (i/4) H0^(1)(kappa r)        (Sec. 4.3)
  *     dim 3, CFMM_LAPLACE   :  G = 1 / (4 pi r)                 (Sec. 5.2)
  *     dim 3, CFMM_HELMHOLTZ :  G = exp(i kappa r) / (4 pi r)    (Sec. 5.3)
  *
  * The method (Sec. 6): an adaptive level-restricted tree on the real parts of
- * the points (a Morton sort), complexified box centres, Lists 1-4, and the
- * eight FMM steps (P2M, M2M, P2P, M2L, M2P, P2L, L2L, L2P) with analytically
- * continued expansions.  Everything on the hot path runs as HIP kernels.
+ * the points (sources and targets together, a Morton sort), complexified box
+ * centres, Lists 1-4, and the eight FMM steps (P2M, M2M, P2P, M2L, M2P, P2L,
+ * L2L, L2P) with analytically continued expansions.  Everything on the hot
+ * path runs as HIP kernels.
  *
  * Geometry: the imaginary parts must be a Lipschitz function of the real
  * parts with constant L < 1 (Sec. 4.1, Sec. 5.1); the configurations this
@@ -48,12 +50,22 @@ extern "C" {
 #endif
 
 #define CFMM_OK 0
-#define CFMM_EINVAL (-1)     /* bad dim / kernel / kappa / tol / n / pointer */
-#define CFMM_ENOTSUP (-2)    /* combination not supported (2D Laplace) */
+#define CFMM_EINVAL (-1)     /* bad dim / kernel / kappa / tol / precision / n / pointer */
+#define CFMM_ENOTSUP (-2)    /* not supported: 2D Laplace, or boxes so many wavelengths
+                                wide that the expansion length exceeds the maximum */
 #define CFMM_EGEOMETRY (-3)  /* non-finite coordinates, or Re r^2 <= 0 in a near pair */
 #define CFMM_ENOMEM (-4)     /* device allocation failed */
 #define CFMM_EHIP (-5)       /* a HIP runtime call failed (message has the HIP error) */
-#define CFMM_ERANGE (-6)     /* an expansion length beyond the supported maximum */
+#define CFMM_ERANGE (-6)     /* an evaluation wrote a non-finite potential (inf or NaN) */
+
+/* Smallest tol each kernel accepts: below it the FP64 rounding of the
+ * translations, not the truncation, sets the error, and the requested
+ * accuracy could not be met.  CFMM_MIXED needs tol >= CFMM_MIXED_TOL_MIN: its
+ * FP32 stages round at about 1e-7 relative. */
+#define CFMM_TOL_MIN_HELMHOLTZ_2D 1e-12
+#define CFMM_TOL_MIN_LAPLACE_3D 1e-12
+#define CFMM_TOL_MIN_HELMHOLTZ_3D 1e-10
+#define CFMM_MIXED_TOL_MIN 1e-6
 
 typedef struct cfmm_plan_s* cfmm_plan_t;
 
@@ -64,35 +76,50 @@ typedef struct {
     int dim;                   /* 2 or 3 */
     int kernel;                /* cfmm_kernel */
     double wavenumber;         /* kappa > 0 for Helmholtz; ignored for Laplace */
-    double tol;                /* requested relative accuracy, 1e-15 < tol < 1 */
-    int64_t n;                 /* number of points, 1 <= n < 2^31 */
-    const void* points;        /* complex128[n][dim], row-major */
-    int points_on_device;      /* 1: device pointer, 0: host pointer */
-    int precision;             /* cfmm_precision: FP64, or MIXED: FP32 3D near field (FP64-formed
-                                  differences, FP64 tile sums) and, for tol >= 1e-6, an FP32 3D
-                                  Laplace M2L when P <= 16 (FP64 row sums); its rounding floor is
-                                  about 1e-7 relative, so it is meant for tol >= 1e-6.  The 2D
-                                  near field stays FP64 (small-argument Hankel). */
+    double tol;                /* requested relative accuracy: CFMM_TOL_MIN_* <= tol < 1 */
+    int64_t n_src;             /* number of sources, >= 1 */
+    const void* src;           /* complex128[n_src][dim], row-major */
+    int64_t n_trg;             /* number of targets (ignored when trg is NULL) */
+    const void* trg;           /* complex128[n_trg][dim], row-major; NULL: the targets are
+                                  the sources and the self term is left out.
+                                  n_src + n_trg < 2^31 */
+    int points_on_device;      /* src and trg are 1: device pointers, 0: host pointers */
+    int precision;             /* cfmm_precision: FP64, or MIXED (tol >= CFMM_MIXED_TOL_MIN):
+                                  FP32 3D near field (FP64-formed differences, compensated
+                                  FP32 tile sums added in FP64) and an FP32 3D Laplace M2L
+                                  when P <= 16 (FP64 row sums).  The 2D near field stays FP64
+                                  (small-argument Hankel). */
     void* stream;              /* hipStream_t for all work; NULL: the null stream */
     int leaf_size;             /* N_s, max points per leaf (Sec. 6.1); 0: 64 in 2D, 256 in 3D */
     int separation;            /* k in {1, 2} (Sec. 6.2, Sec. 6.5); 0: 1 in 2D, 2 in 3D */
 } cfmm_plan_desc;
 
 /* Build a plan: sort, tree, lists, centres, expansion lengths (Sec. 6.1-6.3).
- * On success *out owns device memory until cfmm_destroy.  Synchronises the
- * stream once (box and list counts are read back to size allocations). */
+ * The tree is built on the sources and targets together (Sec. 6.1: a box's
+ * complexified centre is the mean over all its points).  On success *out owns
+ * device memory until cfmm_destroy.  Synchronises the stream (box and list
+ * counts are read back to size allocations). */
 int cfmm_plan(cfmm_plan_t* out, const cfmm_plan_desc* desc);
 
 /* One evaluation (Sec. 6.4 steps 1-8) with densities sigma:
- *   density   : complex128[n]; potential : complex128[n], overwritten.
+ *   density   : complex128[n_src];
+ *   potential : complex128[n_trg] (n_src when the plan has no targets), overwritten.
  *   on_device : 1 if both pointers are device pointers (asynchronous on the
- *               plan's stream), 0 if both are host pointers (synchronous). */
+ *               plan's stream; a non-finite potential is reported by the next
+ *               cfmm_sync), 0 if both are host pointers (synchronous; returns
+ *               CFMM_ERANGE when a potential is not finite). */
 int cfmm_eval(cfmm_plan_t plan, const void* density, void* potential, int on_device);
 
-/* Wait for all work enqueued on the plan's stream. */
+/* Wait for all work enqueued on the plan's stream.  Returns CFMM_ERANGE if an
+ * evaluation since the previous cfmm_sync (or since the plan was built) wrote
+ * a non-finite potential (the potentials are written nevertheless). */
 int cfmm_sync(cfmm_plan_t plan);
 
-/* Free a plan (NULL is accepted).  Synchronises its stream first. */
+/* Free a plan (NULL is accepted).  Synchronises its stream first.  Plans
+ * allocate and free stream-ordered (hipMallocAsync / hipFreeAsync on the plan's
+ * stream, from the device's default memory pool, which the library sets to keep
+ * freed memory for reuse), so building or destroying a plan does not wait for
+ * work on other streams. */
 int cfmm_destroy(cfmm_plan_t plan);
 
 /* Device bytes held by the plan (the resident footprint used for admission). */
@@ -102,23 +129,28 @@ int64_t cfmm_plan_bytes(cfmm_plan_t plan);
 const char* cfmm_last_error(void);
 
 /* Plan description for tests and reporting.
- * info[0..15] = { nbox, nleaf, nlevels, top_level, n_list1, n_list2, n_list3,
+ * info[0..19] = { nbox, nleaf, nlevels, top_level, n_list1, n_list2, n_list3,
  *                 n_list4, p2p_pairs (interactions per eval), m2l_pairs,
- *                 max_p, dim, kernel, separation, leaf_size, precision } */
-int cfmm_plan_info(cfmm_plan_t plan, int64_t* info16);
+ *                 max_p, dim, kernel, separation, leaf_size, precision,
+ *                 n_src, n_trg (potentials written), n_points (tree points:
+ *                 n_src, or n_src + n_trg with distinct targets), 0 }
+ * The tree, lists and interaction counts are over the tree points. */
+int cfmm_plan_info(cfmm_plan_t plan, int64_t* info20);
 
-/* Near-field work of one evaluation: work2[0] = ordered interactions
- * G(x_i, x_j) sigma_j summed directly (j != i), work2[1] = kernel evaluations
- * that produce them.  G(x, y) = G(y, x), so a pair of near leaves in the
- * small-argument regime of the 2D Helmholtz kernel is evaluated once for both
- * directions and work2[1] < work2[0]; otherwise the two are equal. */
+/* Near-field work of one evaluation over the tree points: work2[0] = ordered
+ * interactions G(x_i, x_j) sigma_j summed directly (j != i), work2[1] = kernel
+ * evaluations that produce them.  G(x, y) = G(y, x), so a pair of near leaves
+ * in the small-argument regime of the 2D Helmholtz kernel, and every pair of
+ * near leaves in 3D, is evaluated once for both directions and
+ * work2[1] < work2[0]. */
 int cfmm_plan_near_work(cfmm_plan_t plan, int64_t* work2);
 
 /* Expansion length of level l (0 if the level has no expansions). */
 int cfmm_plan_nterms(cfmm_plan_t plan, int level);
 
 /* Copy the integer tree to caller-owned host arrays (any may be NULL):
- *   perm[n]  (int64: sorted position -> input index), keys[n] (uint64),
+ *   perm[n]  (int64: sorted position -> input index: sources 0 .. n_src-1,
+ *   then targets n_src ..), keys[n] (uint64), n = info[18] tree points,
  *   box_level, box_parent, box_child0, box_nchild, box_pbeg, box_pend [nbox]
  *   (int32), box_prefix[nbox] (uint64). */
 int cfmm_plan_export_tree(cfmm_plan_t plan, int64_t* perm, uint64_t* keys,
@@ -142,18 +174,21 @@ int cfmm_plan_export_centers(cfmm_plan_t plan, void* centers);
 int cfmm_plan_export_expansions(cfmm_plan_t plan, void* mpole, void* local, int64_t* offsets,
                                 int64_t* count);
 
-/* Per-stage timing.  mode 0: off.  mode 1: cfmm_eval records HIP events
- * around each stage on the plan's stream; cfmm_stage_ms reads the last
- * evaluation's times (after cfmm_sync).  Stages: 0 gather, 1 P2M, 2 M2M,
- * 3 M2L+P2L, 4 L2L, 5 L2P+M2P, 6 P2P (+ scatter), 7 whole eval.
- * mode 2: only stage 6 is bracketed, each evaluation into its own slot of a
- * ring of 64 event pairs, so back-to-back evaluations need no host sync;
- * setting mode 2 empties the ring.  cfmm_near_ms (after cfmm_sync) writes
- * the summed stage-6 time of the last min(count, 64) evaluations recorded
- * since, and their number to *count.  Any other mode: CFMM_EINVAL. */
+/* Per-stage timing with HIP events on the plan's stream.
+ * mode 0: off.
+ * mode 1: cfmm_eval records events around each stage; cfmm_stage_ms reads
+ *   the last evaluation's times (after cfmm_sync).  Stages: 0 gather, 1 P2M,
+ *   2 M2M, 3 M2L+P2L, 4 L2L, 5 L2P+M2P, 6 P2P (+ scatter), 7 whole eval.
+ * mode 2: only the near field (stage 6) is bracketed, and mode 3 only the
+ *   M2L translations (stage 3 without P2L), each evaluation into its own slot
+ *   of a ring of 64 event pairs, so back-to-back evaluations need no host
+ *   sync; setting mode 2 or 3 empties the ring.  cfmm_ring_ms (after
+ *   cfmm_sync) writes the summed time of the last min(count, 64) evaluations
+ *   recorded since, and their number to *count.
+ * Any other mode: CFMM_EINVAL. */
 int cfmm_set_profiling(cfmm_plan_t plan, int mode);
 int cfmm_stage_ms(cfmm_plan_t plan, int stage, double* ms);
-int cfmm_near_ms(cfmm_plan_t plan, double* total_ms, int* count);
+int cfmm_ring_ms(cfmm_plan_t plan, double* total_ms, int* count);
 
 /* ---- host-side planning logic, callable without a GPU (for checking) ----
  * The integer tree and Lists 1-4 that cfmm_plan builds from the

@@ -40,9 +40,15 @@ class CfmmError(RuntimeError):
         self.code = code
 
 
+# smallest tolerances the library accepts (include/cfmm.h)
+TOL_MIN = {(2, "helmholtz"): 1e-12, (3, "laplace"): 1e-12, (3, "helmholtz"): 1e-10}
+MIXED_TOL_MIN = 1e-6
+
+
 class PlanDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("kernel", ctypes.c_int), ("wavenumber", ctypes.c_double),
-                ("tol", ctypes.c_double), ("n", ctypes.c_int64), ("points", ctypes.c_void_p),
+                ("tol", ctypes.c_double), ("n_src", ctypes.c_int64), ("src", ctypes.c_void_p),
+                ("n_trg", ctypes.c_int64), ("trg", ctypes.c_void_p),
                 ("points_on_device", ctypes.c_int), ("precision", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("leaf_size", ctypes.c_int),
                 ("separation", ctypes.c_int)]
@@ -78,7 +84,7 @@ def lib():
         L.cfmm_plan_export_centers.argtypes = [vp, vp]
         L.cfmm_plan_export_expansions.argtypes = [vp, vp, vp, i64p, i64p]
         L.cfmm_set_profiling.argtypes = [vp, ctypes.c_int]
-        L.cfmm_near_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+        L.cfmm_ring_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         L.cfmm_stage_ms.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.cfmm_htree_build.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64, u64p, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int]
@@ -105,47 +111,71 @@ def _is_torch(x) -> bool:
     return type(x).__module__.startswith("torch")
 
 
-class Plan:
-    """A complex-coordinate FMM plan for u_i = sum_{j != i} G(x_i, x_j) sigma_j.
+def _as_points(x, name):
+    """(keep-alive object, pointer, n, dim, on_device) of complex128 points [n, dim]."""
+    if _is_torch(x) and x.is_cuda:
+        import torch
+        if x.dtype != torch.complex128 or x.dim() != 2:
+            raise ValueError(f"{name}: expected a complex128 CUDA tensor [n, dim]")
+        x = x.contiguous()
+        return x, x.data_ptr(), x.shape[0], x.shape[1], True
+    a = np.ascontiguousarray(x, dtype=np.complex128)
+    if a.ndim != 2:
+        raise ValueError(f"{name}: expected a complex array [n, dim]")
+    return a, a.ctypes.data, a.shape[0], a.shape[1], False
 
-    points: complex128 array [n, dim] (numpy on the host, or a torch CUDA
-    tensor).  Evaluate with ``plan(sigma)`` for any number of densities.
+
+class Plan:
+    """A complex-coordinate FMM plan for u_i = sum_j G(x_i, y_j) sigma_j.
+
+    points: complex128 sources [n_src, dim] (numpy on the host, or a torch
+    CUDA tensor).  targets: optional complex128 [n_trg, dim] on the same side;
+    without it the targets are the sources and the self term is left out.
+    Evaluate with ``plan(sigma)`` for any number of densities.
     """
 
     def __init__(self, points, kernel: str = "helmholtz", kappa: float = 0.0,
                  tol: float = 1e-6, precision: str = "fp64", leaf_size: int = 0,
-                 separation: int = 0, stream=None):
+                 separation: int = 0, stream=None, targets=None):
         L = lib()
         self._handle = ctypes.c_void_p()
-        on_dev = _is_torch(points) and points.is_cuda
-        if on_dev:
-            import torch
-            pts = points.contiguous()
-            assert pts.dtype == torch.complex128
-            n, dim = pts.shape
-            ptr = pts.data_ptr()
-        else:
-            pts = np.ascontiguousarray(points, dtype=np.complex128)
-            n, dim = pts.shape
-            ptr = pts.ctypes.data
-        self._keep = pts
+        src, sptr, n, dim, on_dev = _as_points(points, "points")
+        trg, tptr, nt = None, None, 0
+        if targets is not None:
+            trg, tptr, nt, tdim, t_dev = _as_points(targets, "targets")
+            if tdim != dim or t_dev != on_dev:
+                raise ValueError("targets must have the sources' dimension and live on the same side")
         if stream is None and on_dev:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
         d = PlanDesc(dim=dim, kernel={"laplace": LAPLACE, "helmholtz": HELMHOLTZ}[kernel],
-                     wavenumber=float(kappa), tol=float(tol), n=n, points=ptr,
-                     points_on_device=1 if on_dev else 0,
+                     wavenumber=float(kappa), tol=float(tol), n_src=n, src=sptr,
+                     n_trg=nt, trg=tptr, points_on_device=1 if on_dev else 0,
                      precision={"fp64": FP64, "mixed": MIXED}[precision],
                      stream=stream or 0, leaf_size=int(leaf_size), separation=int(separation))
         _check(L.cfmm_plan(ctypes.byref(self._handle), ctypes.byref(d)))
-        self._keep = None
-        self.n, self.dim, self.kernel, self.kappa, self.tol = n, dim, kernel, kappa, tol
+        del src, trg
+        self.n = n
+        self.n_out = nt if targets is not None else n
+        self.dim, self.kernel, self.kappa, self.tol = dim, kernel, kappa, tol
         self.precision = precision
         self.stream = stream
 
     # ----------------------------------------------------------- evaluation
+    def _check_tensor(self, x, n, name):
+        import torch
+        if not (_is_torch(x) and x.is_cuda and x.dtype == torch.complex128 and x.is_contiguous()
+                and x.numel() == n):
+            raise ValueError(f"{name}: expected a contiguous complex128 CUDA tensor of {n} elements")
+
     def eval_into(self, sigma, out) -> None:
-        """Asynchronous device evaluation: sigma, out are complex128 CUDA tensors [n]."""
+        """Asynchronous device evaluation on the plan's stream: sigma [n_src]
+        and out [n_out] are contiguous complex128 CUDA tensors.  The caller
+        orders the plan's stream against the streams that produce sigma and
+        consume out (the plan's stream is the current stream at plan time
+        unless one was given)."""
+        self._check_tensor(sigma, self.n, "sigma")
+        self._check_tensor(out, self.n_out, "out")
         _check(lib().cfmm_eval(self._handle, sigma.data_ptr(), out.data_ptr(), 1))
 
     def __call__(self, sigma):
@@ -153,13 +183,23 @@ class Plan:
         if _is_torch(sigma):
             import torch
             s = sigma.contiguous()
-            assert s.dtype == torch.complex128 and s.is_cuda and s.numel() == self.n
-            out = torch.empty_like(s)
+            self._check_tensor(s, self.n, "sigma")
+            out = torch.empty(self.n_out, dtype=torch.complex128, device=s.device)
+            cur = torch.cuda.current_stream(s.device)
+            ps = torch.cuda.ExternalStream(self.stream or 0, device=s.device) \
+                if (self.stream or 0) != cur.cuda_stream else cur
+            if ps is not cur:
+                ps.wait_stream(cur)           # sigma and out were made on the current stream
             _check(L.cfmm_eval(self._handle, s.data_ptr(), out.data_ptr(), 1))
+            if ps is not cur:
+                cur.wait_stream(ps)           # the caller reads out on the current stream
+                s.record_stream(ps)
+                out.record_stream(ps)
             return out
         s = np.ascontiguousarray(sigma, dtype=np.complex128).reshape(-1)
-        assert s.shape[0] == self.n
-        out = np.empty_like(s)
+        if s.shape[0] != self.n:
+            raise ValueError(f"sigma: expected {self.n} values, got {s.shape[0]}")
+        out = np.empty(self.n_out, dtype=np.complex128)
         _check(L.cfmm_eval(self._handle, s.ctypes.data, out.ctypes.data, 0))
         return out
 
@@ -172,11 +212,11 @@ class Plan:
         return int(lib().cfmm_plan_bytes(self._handle))
 
     def info(self) -> dict:
-        a = np.zeros(16, dtype=np.int64)
+        a = np.zeros(20, dtype=np.int64)
         _check(lib().cfmm_plan_info(self._handle, _ptr(a, ctypes.c_int64)))
         keys = ("nbox", "nleaf", "nlevels", "top_level", "n_list1", "n_list2", "n_list3",
                 "n_list4", "p2p_pairs", "m2l_pairs", "max_p", "dim", "kernel", "separation",
-                "leaf_size", "precision")
+                "leaf_size", "precision", "n_src", "n_trg", "n_points")
         return {k: int(v) for k, v in zip(keys, a)}
 
     def near_work(self) -> dict:
@@ -189,8 +229,9 @@ class Plan:
         return [int(lib().cfmm_plan_nterms(self._handle, l)) for l in range(self.info()["nlevels"])]
 
     def export_tree(self) -> dict:
-        nb = self.info()["nbox"]
-        out = {"perm": np.zeros(self.n, np.int64), "keys": np.zeros(self.n, np.uint64)}
+        info = self.info()
+        nb, npt = info["nbox"], info["n_points"]
+        out = {"perm": np.zeros(npt, np.int64), "keys": np.zeros(npt, np.uint64)}
         for k in ("level", "parent", "child0", "nchild", "pbeg", "pend"):
             out[k] = np.zeros(nb, np.int32)
         out["prefix"] = np.zeros(nb, np.uint64)
@@ -232,13 +273,14 @@ class Plan:
         return mp[:cnt.value], lc[:cnt.value], off
 
     def set_profiling(self, mode=True):
-        """0/False off, 1/True every stage (stage_ms), 2 near-field ring (near_ms)."""
+        """0/False off, 1/True every stage (stage_ms), 2 near-field ring and
+        3 M2L-translation ring (ring_ms)."""
         _check(lib().cfmm_set_profiling(self._handle, int(mode)))
 
-    def near_ms(self):
-        """(summed near-field stage ms, evaluations) recorded in profiling mode 2."""
+    def ring_ms(self):
+        """(summed ms, evaluations) of the stage bracketed in profiling mode 2 or 3."""
         tot, cnt = ctypes.c_double(), ctypes.c_int()
-        _check(lib().cfmm_near_ms(self._handle, ctypes.byref(tot), ctypes.byref(cnt)))
+        _check(lib().cfmm_ring_ms(self._handle, ctypes.byref(tot), ctypes.byref(cnt)))
         return tot.value, cnt.value
 
     def stage_ms(self) -> dict:

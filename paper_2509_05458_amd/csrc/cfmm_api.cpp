@@ -46,6 +46,12 @@ int ensure_device_tables()
     HIPCHK(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_init_mu);
     if (g_inited.count(dev)) return CFMM_OK;
+    // plans allocate from the device's default memory pool; keep freed memory
+    // in the pool for the next plan instead of returning it at every sync
+    hipMemPool_t pool;
+    HIPCHK(hipDeviceGetDefaultMemPool(&pool, dev));
+    uint64_t keep = UINT64_MAX;
+    HIPCHK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
     HIPCHK(h2d_init_tables(dev));
     HIPCHK(h3d_init_tables(dev));
     HIPCHK(l3d_init_tables(dev));
@@ -58,7 +64,11 @@ int ensure_device_tables()
 struct cfmm_plan_s {
     int dim = 0, kernel = 0, precision = 0, sep = 1, leaf_size = 64;
     double kappa = 0.0, tol = 0.0;
-    int64_t n = 0;
+    int64_t n = 0;                // tree points: the sources, then the targets if distinct
+    int64_t n_src = 0;            // densities per evaluation
+    int64_t n_out = 0;            // potentials per evaluation
+    int64_t obase = 0;            // tree point index of the first target (0: targets = sources)
+    int* d_flag_nf = nullptr;     // set when an evaluation writes a non-finite potential
     hipStream_t stream = nullptr;
     HostTree tree;
     std::vector<uint64_t> keys_h;
@@ -120,7 +130,7 @@ struct cfmm_plan_s {
     int n_m2p3 = 0, m2p_pmax = 0;
     M2PParts m2p_parts() const { return M2PParts{n_m2p3, d_m2p_owner, d_m2p_poff, d_m2p_part}; }
     int64_t ecount = 0;
-    int64_t info[16];
+    int64_t info[20];
 
     int prof = 0;                       // 0 off, 1 every stage, 2 near-field ring
     hipEvent_t ev[8];
@@ -136,9 +146,12 @@ struct cfmm_plan_s {
         *p = nullptr;
         if (count == 0) count = 1;
         void* q = nullptr;
-        hipError_t e = hipMalloc(&q, count * sizeof(T));
+        // stream-ordered, from the device's memory pool: neither this nor the
+        // matching hipFreeAsync waits for work on other streams, so plans
+        // made and destroyed on one stream do not stall evaluations on others
+        hipError_t e = hipMallocAsync(&q, count * sizeof(T), stream);
         if (e != hipSuccess)
-            return fail(CFMM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+            return fail(CFMM_ENOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
         allocs.push_back(q);
         alloc_sz.push_back(count * sizeof(T));
         bytes += (int64_t)(count * sizeof(T));
@@ -148,9 +161,9 @@ struct cfmm_plan_s {
 
     ~cfmm_plan_s()
     {
-        if (stream) hipStreamSynchronize(stream);
-        else hipDeviceSynchronize();
-        for (void* q : allocs) hipFree(q);
+        hipStreamSynchronize(stream);
+        for (void* q : allocs) hipFreeAsync(q, stream);
+        hipStreamSynchronize(stream);
         if (ev_made)
             for (int i = 0; i < 8; ++i) hipEventDestroy(ev[i]);
         if (rev_made)
@@ -177,6 +190,7 @@ struct cfmm_plan_s {
         o.o_tr = d_o_tr; o.pw = d_pw;
         return o;
     }
+    IoMap io() const { return IoMap{d_perm, n_src, obase, d_flag_nf}; }
     PointsView pview() const
     {
         PointsView pv;
@@ -392,13 +406,17 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
 {
     int rc;
     int dim = d->dim;
-    int64_t n = d->n;
+    int64_t n = p->n;
     hipStream_t st = p->stream;
-    // -------- points onto the device
+    // -------- points onto the device: the sources, then the distinct targets;
+    // the tree holds both (a box's centre averages all its points, Sec. 6.1)
     double* d_pts = nullptr;
     if ((rc = p->alloc(&d_pts, (size_t)n * dim * 2))) return rc;
-    HIPCHK(hipMemcpyAsync(d_pts, d->points, (size_t)n * dim * 2 * sizeof(double),
-                          d->points_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    hipMemcpyKind kind = d->points_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemcpyAsync(d_pts, d->src, (size_t)d->n_src * dim * 2 * sizeof(double), kind, st));
+    if (p->obase > 0)
+        HIPCHK(hipMemcpyAsync(d_pts + (size_t)d->n_src * dim * 2, d->trg,
+                              (size_t)d->n_trg * dim * 2 * sizeof(double), kind, st));
     // -------- real bounding box (a1)
     int nbb = (int)std::min<int64_t>(1024, (n + 255) / 256);
     double *d_part = nullptr, *d_bb = nullptr;
@@ -520,7 +538,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
                 continue;
             }
             if (m > kPMax2D)
-                return fail(CFMM_ERANGE, "expansion length above the supported maximum (" +
+                return fail(CFMM_ENOTSUP, "expansion length above the supported maximum (" +
                                              std::to_string(kPMax2D) + ") at level " + std::to_string(l) +
                                              "; the boxes are too many wavelengths wide");
             p->P[l] = m;
@@ -542,7 +560,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
                 continue;
             }
             if (m > kPMaxH3)
-                return fail(CFMM_ERANGE, "expansion length above the supported maximum (" +
+                return fail(CFMM_ENOTSUP, "expansion length above the supported maximum (" +
                                              std::to_string(kPMaxH3) + ") at level " + std::to_string(l) +
                                              "; the boxes are too many wavelengths wide");
             p->P[l] = m;
@@ -554,7 +572,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         int m = nterms_laplace(dim, p->sep, p->tol);
         int lim = l3d_pmax_supported();
         if (m > lim)
-            return fail(CFMM_ERANGE, "expansion length " + std::to_string(m) +
+            return fail(CFMM_ENOTSUP, "expansion length " + std::to_string(m) +
                                          " above the supported maximum " + std::to_string(lim));
         for (int l = top; l < nlev; ++l) {
             p->rs[l] = 1.0 / (p->D * ldexp(1.0, -l));
@@ -582,7 +600,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
             eoff[b] = (int)ecount;
             ecount += ncoef(t.level[b]);
         }
-    if (ecount > (int64_t)0x7fffffff) return fail(CFMM_ERANGE, "expansion storage above 2^31 entries");
+    if (ecount > (int64_t)0x7fffffff) return fail(CFMM_ENOTSUP, "expansion storage above 2^31 entries");
     p->ecount = ecount;
     if ((rc = upload(p, &p->d_eoff, eoff)) || (rc = upload(p, &p->d_P, p->P)) || (rc = upload(p, &p->d_rs, p->rs)))
         return rc;
@@ -841,8 +859,9 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     // -------- evaluation buffers
     if ((rc = p->alloc(&p->d_sre, n)) || (rc = p->alloc(&p->d_sim, n)) ||
         (rc = p->alloc(&p->d_mpole, ecount)) || (rc = p->alloc(&p->d_local, ecount)) ||
-        (rc = p->alloc(&p->d_ufar, n)))
+        (rc = p->alloc(&p->d_ufar, n)) || (rc = p->alloc(&p->d_flag_nf, 1)))
         return rc;
+    HIPCHK(hipMemsetAsync(p->d_flag_nf, 0, sizeof(int), st));
     // -------- release planning scratch; the plan keeps the rest resident
     HIPCHK(hipStreamSynchronize(st));
     for (void* q : {(void*)d_pts, (void*)d_part, (void*)d_bb, (void*)d_keys, (void*)d_keys2,
@@ -854,7 +873,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
             p->bytes -= (int64_t)p->alloc_sz[k];
             p->allocs.erase(it);
             p->alloc_sz.erase(p->alloc_sz.begin() + k);
-            hipFree(q);
+            HIPCHK(hipFreeAsync(q, st));
         }
     }
     // -------- description
@@ -873,8 +892,12 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     for (int q = 0; q < 4; ++q) I[4 + q] = (int64_t)t.idx[q].size();
     I[8] = p2p; I[9] = m2l; I[10] = pmax; I[11] = dim; I[12] = p->kernel; I[13] = p->sep;
     I[14] = p->leaf_size; I[15] = p->precision;
+    I[16] = p->n_src; I[17] = p->n_out; I[18] = p->n; I[19] = 0;
     return CFMM_OK;
 }
+
+int check_finite(cfmm_plan_s* p);
+int eval_on_device(cfmm_plan_s* p, const double* sig, double* out);
 
 }  // namespace
 
@@ -889,14 +912,24 @@ int cfmm_plan(cfmm_plan_t* out, const cfmm_plan_desc* d)
     if (d->kernel != CFMM_LAPLACE && d->kernel != CFMM_HELMHOLTZ) return fail(CFMM_EINVAL, "unknown kernel");
     if (d->kernel == CFMM_HELMHOLTZ && !(d->wavenumber > 0.0 && isfinite(d->wavenumber)))
         return fail(CFMM_EINVAL, "Helmholtz needs a finite wavenumber > 0");
-    if (!(d->tol > 1e-15 && d->tol < 1.0)) return fail(CFMM_EINVAL, "tol must lie in (1e-15, 1)");
-    if (d->n < 1 || d->n > 0x7fffffffLL) return fail(CFMM_EINVAL, "n must lie in [1, 2^31)");
-    if (!d->points) return fail(CFMM_EINVAL, "points is NULL");
-    if (d->precision != CFMM_FP64 && d->precision != CFMM_MIXED) return fail(CFMM_EINVAL, "unknown precision");
-    if (d->leaf_size < 0 || d->leaf_size > 4096) return fail(CFMM_EINVAL, "leaf_size must lie in [0, 4096]");
-    if (d->separation < 0 || d->separation > 2) return fail(CFMM_EINVAL, "separation must be 0, 1 or 2");
     if (d->dim == 2 && d->kernel == CFMM_LAPLACE)
         return fail(CFMM_ENOTSUP, "supported: dim 2 Helmholtz, dim 3 Laplace and Helmholtz");
+    double tmin = d->dim == 2 ? CFMM_TOL_MIN_HELMHOLTZ_2D
+                              : (d->kernel == CFMM_LAPLACE ? CFMM_TOL_MIN_LAPLACE_3D : CFMM_TOL_MIN_HELMHOLTZ_3D);
+    if (!(d->tol >= tmin && d->tol < 1.0))
+        return fail(CFMM_EINVAL, "tol must lie in [" + std::to_string(tmin) + ", 1) for this kernel: below it "
+                                 "the FP64 rounding of the translations sets the error");
+    if (d->precision != CFMM_FP64 && d->precision != CFMM_MIXED) return fail(CFMM_EINVAL, "unknown precision");
+    if (d->precision == CFMM_MIXED && !(d->tol >= CFMM_MIXED_TOL_MIN))
+        return fail(CFMM_EINVAL, "CFMM_MIXED needs tol >= 1e-6 (its FP32 stages round at about 1e-7); "
+                                 "use CFMM_FP64 below that");
+    if (d->n_src < 1) return fail(CFMM_EINVAL, "n_src must be >= 1");
+    if (!d->src) return fail(CFMM_EINVAL, "src is NULL");
+    if (d->trg && d->n_trg < 1) return fail(CFMM_EINVAL, "n_trg must be >= 1 when trg is given");
+    int64_t ntot = d->n_src + (d->trg ? d->n_trg : 0);
+    if (ntot > 0x7fffffffLL) return fail(CFMM_EINVAL, "n_src + n_trg must be below 2^31");
+    if (d->leaf_size < 0 || d->leaf_size > 4096) return fail(CFMM_EINVAL, "leaf_size must lie in [0, 4096]");
+    if (d->separation < 0 || d->separation > 2) return fail(CFMM_EINVAL, "separation must be 0, 1 or 2");
     int rc = ensure_device_tables();
     if (rc) return rc;
     cfmm_plan_s* p = new cfmm_plan_s();
@@ -904,7 +937,10 @@ int cfmm_plan(cfmm_plan_t* out, const cfmm_plan_desc* d)
     p->kernel = d->kernel;
     p->kappa = d->kernel == CFMM_HELMHOLTZ ? d->wavenumber : 0.0;
     p->tol = d->tol;
-    p->n = d->n;
+    p->n_src = d->n_src;
+    p->obase = d->trg ? d->n_src : 0;
+    p->n_out = d->trg ? d->n_trg : d->n_src;
+    p->n = d->n_src + (d->trg ? d->n_trg : 0);
     p->precision = d->precision;
     // default separation: k = 1 in 2D; k = 2 in 3D, where the convergence of the
     // continued expansions degrades fastest with the Lipschitz constant (Sec. 5.1, 6.5)
@@ -926,32 +962,67 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
     if (!p) return fail(CFMM_EINVAL, "plan is NULL");
     if (!density || !potential) return fail(CFMM_EINVAL, "density or potential is NULL");
     hipStream_t st = p->stream;
-    int64_t n = p->n;
     const double* sig = (const double*)density;
     double* out = (double*)potential;
     if (!on_device) {
         if (!p->d_io_in) {
             int rc;
-            if ((rc = p->alloc(&p->d_io_in, 2 * n)) || (rc = p->alloc(&p->d_io_out, 2 * n))) return rc;
+            if ((rc = p->alloc(&p->d_io_in, 2 * p->n_src)) || (rc = p->alloc(&p->d_io_out, 2 * p->n_out)))
+                return rc;
         }
-        HIPCHK(hipMemcpyAsync(p->d_io_in, density, 2 * n * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(p->d_io_in, density, 2 * p->n_src * sizeof(double), hipMemcpyHostToDevice, st));
         sig = p->d_io_in;
         out = p->d_io_out;
     }
-    if (p->prof == 1 && !p->ev_made) {
-        for (int i = 0; i < 8; ++i) HIPCHK(hipEventCreate(&p->ev[i]));
-        p->ev_made = true;
+    int rc = eval_on_device(p, sig, out);
+    if (rc) return rc;
+    if (!on_device) {
+        HIPCHK(hipMemcpyAsync(potential, p->d_io_out, 2 * p->n_out * sizeof(double), hipMemcpyDeviceToHost, st));
+        return check_finite(p);
     }
-    if (p->prof == 2 && !p->rev_made) {
-        for (int i = 0; i < 2 * cfmm_plan_s::kRing; ++i) HIPCHK(hipEventCreate(&p->rev[i]));
-        p->rev_made = true;
-    }
-    // mode 1 brackets every stage; mode 2 only the near field (stage 6), into
-    // the next ring slot, so that back-to-back evaluations need no host sync
+    return CFMM_OK;
+}
+
+int cfmm_sync(cfmm_plan_t p)
+{
+    if (!p) return fail(CFMM_EINVAL, "plan is NULL");
+    return check_finite(p);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Waits for the plan's stream, then reads and clears the non-finite flag.
+int check_finite(cfmm_plan_s* p)
+{
+    hipStream_t st = p->stream;
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, p->d_flag_nf, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (!flag) return CFMM_OK;
+    int zero = 0;
+    HIPCHK(hipMemcpyAsync(p->d_flag_nf, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return fail(CFMM_ERANGE, "an evaluation wrote a non-finite potential (inf or NaN); "
+                             "are the densities finite?");
+}
+
+// Steps 1-8 of Sec. 6.4 on the plan's stream, densities sig[n_src] and
+// potentials out[n_out] in device memory.
+int eval_on_device(cfmm_plan_s* p, const double* sig, double* out)
+{
+    hipStream_t st = p->stream;
+    int64_t n = p->n;
+    // mode 1 brackets every stage (marks 0..7); mode 2 only the near field
+    // (marks 6, 7) and mode 3 only the M2L translations (marks 8, 9), into the
+    // next ring slot, so that back-to-back evaluations need no host sync
     int slot = (int)(p->ring_n % cfmm_plan_s::kRing);
+    int ring_lo = p->prof == 2 ? 6 : 8;
     auto mark = [&](int i) -> hipError_t {
-        if (p->prof == 1) return hipEventRecord(p->ev[i], st);
-        if (p->prof == 2 && i >= 6) return hipEventRecord(p->rev[2 * slot + (i - 6)], st);
+        if (p->prof == 1 && i < 8) return hipEventRecord(p->ev[i], st);
+        if (p->prof >= 2 && (i == ring_lo || i == ring_lo + 1))
+            return hipEventRecord(p->rev[2 * slot + (i - ring_lo)], st);
         return hipSuccess;
     };
     TreeView tv = p->view();
@@ -960,7 +1031,7 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
     int top = t.top, nlev = t.nlevels();
     const int* W = p->d_work;
     HIPCHK(mark(0));
-    HIPCHK(launch_gather_density(sig, p->d_perm, n, p->d_sre, p->d_sim, st));
+    HIPCHK(launch_gather_density(sig, p->io(), n, p->d_sre, p->d_sim, st));
     HIPCHK(mark(1));
     if (p->dim == 2) {
         {
@@ -986,8 +1057,10 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
                 cnt[k] = t.lvl_beg[l + 1] - t.lvl_beg[l];
                 nco[k] = 2 * p->P[l] + 1;
             }
+            HIPCHK(mark(8));
             HIPCHK(h2d_m2l(W + p->off_m2l, std::min(nlv, 64), boff, cnt, nco, tv, p->ops(), p->d_mpole,
                            p->d_local, st));
+            HIPCHK(mark(9));
         }
         {
             // the P2L list is in level order; one launch per level sizes its LDS by that level's P
@@ -1006,7 +1079,7 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, p->m2p_parts(), p->m2p_pmax, top, tv, pv, p->kappa,
                             p->d_mpole, p->d_local, p->d_ufar, st));
         HIPCHK(mark(6));
-        HIPCHK(h2d_p2p(p->near2, W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->d_perm, out, st));
+        HIPCHK(h2d_p2p(p->near2, W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->io(), out, st));
     } else if (p->kernel == CFMM_HELMHOLTZ) {
         H3DLevels hl{p->d_h3_kw, p->d_h3_sc, nullptr};
         HIPCHK(hipMemsetAsync(p->d_mpole, 0, p->ecount * sizeof(cplx), st));
@@ -1062,7 +1135,9 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         int rc;
         if ((rc = run(0, p->d_mpole, p->d_mpole))) return rc;
         HIPCHK(mark(3));
+        HIPCHK(mark(8));
         if ((rc = run(1, p->d_mpole, p->d_local))) return rc;
+        HIPCHK(mark(9));
         if ((rc0 = per_level(p->p2l_h, p->off_p2l, p->n_p2l, true))) return rc0;
         HIPCHK(mark(4));
         if ((rc = run(2, p->d_local, p->d_local))) return rc;
@@ -1071,7 +1146,7 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
                             p->d_mpole, p->d_local, p->m2p_parts(), p->d_ufar, st));
         HIPCHK(mark(6));
         HIPCHK(near3_p2p(p->near3, 1, p->precision, W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar,
-                         p->d_perm, out, st));
+                         p->io(), out, st));
     } else {
         int P = p->pmax;
         HIPCHK(l3d_p2m(W + p->off_p2m, p->n_p2m, P, tv, pv, p->d_mpole, st));
@@ -1082,8 +1157,10 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         // FP32 M2L in mixed precision only where its ~1e-7 rounding floor sits
         // below the requested accuracy
         int m2l32 = p->precision == CFMM_MIXED && p->tol >= 1e-6;
+        HIPCHK(mark(8));
         HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, m2l32, p->d_mpole,
                        p->d_local, st));
+        HIPCHK(mark(9));
         HIPCHK(l3d_p2l(W + p->off_p2l, p->n_p2l, P, tv, pv, p->d_local, st));
         HIPCHK(mark(4));
         for (int l = top + 1; l < nlev; ++l)
@@ -1093,23 +1170,16 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
                             p->m2p_parts(), p->d_ufar, st));
         HIPCHK(mark(6));
         HIPCHK(near3_p2p(p->near3, 0, p->precision, W + p->off_leaves, p->nleaf, tv, pv, 0.0, p->d_ufar,
-                         p->d_perm, out, st));
+                         p->io(), out, st));
     }
     HIPCHK(mark(7));
-    if (p->prof == 2) ++p->ring_n;
-    if (!on_device) {
-        HIPCHK(hipMemcpyAsync(potential, p->d_io_out, 2 * n * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-    }
+    if (p->prof >= 2) ++p->ring_n;
     return CFMM_OK;
 }
 
-int cfmm_sync(cfmm_plan_t p)
-{
-    if (!p) return fail(CFMM_EINVAL, "plan is NULL");
-    HIPCHK(hipStreamSynchronize(p->stream));
-    return CFMM_OK;
-}
+}  // namespace
+
+extern "C" {
 
 int cfmm_destroy(cfmm_plan_t p)
 {
@@ -1121,10 +1191,10 @@ int64_t cfmm_plan_bytes(cfmm_plan_t p) { return p ? p->bytes : 0; }
 
 const char* cfmm_last_error(void) { return g_err.c_str(); }
 
-int cfmm_plan_info(cfmm_plan_t p, int64_t* info16)
+int cfmm_plan_info(cfmm_plan_t p, int64_t* info20)
 {
-    if (!p || !info16) return fail(CFMM_EINVAL, "NULL argument");
-    memcpy(info16, p->info, sizeof(p->info));
+    if (!p || !info20) return fail(CFMM_EINVAL, "NULL argument");
+    memcpy(info20, p->info, sizeof(p->info));
     return CFMM_OK;
 }
 
@@ -1282,13 +1352,22 @@ int cfmm_plan_export_expansions(cfmm_plan_t p, void* mpole, void* local, int64_t
 int cfmm_set_profiling(cfmm_plan_t p, int mode)
 {
     if (!p) return fail(CFMM_EINVAL, "plan is NULL");
-    if (mode < 0 || mode > 2) return fail(CFMM_EINVAL, "profiling mode must be 0, 1 or 2");
+    if (mode < 0 || mode > 3) return fail(CFMM_EINVAL, "profiling mode must be 0, 1, 2 or 3");
+    // the events are made here, so that an evaluation creates nothing
+    if (mode == 1 && !p->ev_made) {
+        for (int i = 0; i < 8; ++i) HIPCHK(hipEventCreate(&p->ev[i]));
+        p->ev_made = true;
+    }
+    if (mode >= 2 && !p->rev_made) {
+        for (int i = 0; i < 2 * cfmm_plan_s::kRing; ++i) HIPCHK(hipEventCreate(&p->rev[i]));
+        p->rev_made = true;
+    }
     p->prof = mode;
-    if (mode == 2) p->ring_n = 0;
+    if (mode >= 2) p->ring_n = 0;
     return CFMM_OK;
 }
 
-int cfmm_near_ms(cfmm_plan_t p, double* total_ms, int* count)
+int cfmm_ring_ms(cfmm_plan_t p, double* total_ms, int* count)
 {
     if (!p || !total_ms || !count) return fail(CFMM_EINVAL, "bad argument");
     int n = (int)(p->ring_n < cfmm_plan_s::kRing ? p->ring_n : cfmm_plan_s::kRing);

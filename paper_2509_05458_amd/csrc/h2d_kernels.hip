@@ -1137,21 +1137,24 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_row(const int* __restrict__ item
     }
 }
 
-// Final pass: u[perm[i]] = (i/4)(near + far), the near field summed over the
-// target's List-1 entries in list order.
+// Final pass: u[perm[i] - obase] = (i/4)(near + far) at the targets, the
+// near field summed over the target's List-1 entries in list order.
 __global__ __launch_bounds__(64) void k_h2d_p2p_final(const int* __restrict__ leaves, P2PMap mp, TreeView tv,
-                                                      const cplx* __restrict__ ufar,
-                                                      const int* __restrict__ perm, double* __restrict__ out)
+                                                      const cplx* __restrict__ ufar, IoMap io,
+                                                      double* __restrict__ out)
 {
     int b = leaves[blockIdx.x];
     int p0 = tv.pbeg[b], p1 = tv.pend[b];
     int e0 = tv.l1off[b], e1 = tv.l1off[b + 1];
     for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+        int64_t p = (int64_t)io.perm[i] - io.obase;
+        if (p < 0) continue;            // a source that is not a target
         cplx u = ufar[i];
         for (int e = e0; e < e1; ++e) u += mp.C[mp.coff[e] + (i - p0)];
-        int64_t p = perm[i];
-        out[2 * p] = -0.25 * u.im;      // (i/4) u
-        out[2 * p + 1] = 0.25 * u.re;
+        double vr = -0.25 * u.im, vi = 0.25 * u.re;      // (i/4) u
+        out[2 * p] = vr;
+        out[2 * p + 1] = vi;
+        if (!isfinite(vr) || !isfinite(vi)) atomicOr(io.nonfinite, 1);
     }
 }
 
@@ -1241,14 +1244,14 @@ hipError_t h2d_leaf_far(const int* leaves, int nleaf, const M2PParts& m2p, int m
 }
 
 hipError_t h2d_p2p(const H2DNear& nr, const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                   double kappa, const cplx* ufar, const int* perm, double* out, hipStream_t st)
+                   double kappa, const cplx* ufar, const IoMap& io, double* out, hipStream_t st)
 {
     P2PMap mp{nr.row_of, nr.partner, nr.coff, nr.C};
     if (nr.nsym > 0) k_h2d_p2p_sym<<<nr.nsym, 64, 0, st>>>(nr.sym, nr.sym_k, mp, tv, pv, kappa);
     if (nr.ndiag > 0) k_h2d_p2p_diag<<<nr.ndiag, 64, 0, st>>>(nr.diag, nr.diag_k, mp, tv, pv, kappa);
     if (nr.nser > 0) k_h2d_p2p_row<true><<<nr.nser, 64, 0, st>>>(nr.ser, nr.ser_k, mp, tv, pv, kappa);
     if (nr.ngen > 0) k_h2d_p2p_row<false><<<nr.ngen, 64, 0, st>>>(nr.gen, nullptr, mp, tv, pv, kappa);
-    if (nleaf > 0) k_h2d_p2p_final<<<nleaf, 64, 0, st>>>(leaves, mp, tv, ufar, perm, out);
+    if (nleaf > 0) k_h2d_p2p_final<<<nleaf, 64, 0, st>>>(leaves, mp, tv, ufar, io, out);
     return hipGetLastError();
 }
 

@@ -24,7 +24,17 @@ hipError_t launch_radix_sort(uint64_t* keys, int* vals, uint64_t* keys_alt, int*
                              int64_t n, int key_bits, void* scratch, hipStream_t st);
 hipError_t launch_gather_points(const double* pts, const int* perm, int64_t n, int dim,
                                 double* xre, double* xim, hipStream_t st);
-hipError_t launch_gather_density(const double* sig, const int* perm, int64_t n, double* sre,
+// Caller order <-> sorted tree order.  Tree points are the sources
+// (0 .. nsrc-1), then the distinct targets; obase is the tree index of the
+// first target (0 when the targets are the sources).  A final pass that writes
+// a non-finite potential sets *nonfinite.
+struct IoMap {
+    const int* perm;       // sorted position -> tree point index
+    int64_t nsrc;
+    int64_t obase;
+    int* nonfinite;
+};
+hipError_t launch_gather_density(const double* sig, const IoMap& io, int64_t n, double* sre,
                                  double* sim, hipStream_t st);
 // Boxes cut into chunks of at most kCentreChunk points for the centre pass.
 constexpr int kCentreChunk = 4096;
@@ -120,7 +130,7 @@ struct H2DNear {
     const int* row_of; const int* partner; const int64_t* coff; cplx* C;
 };
 hipError_t h2d_p2p(const H2DNear& nr, const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                   double kappa, const cplx* ufar, const int* perm, double* out, hipStream_t st);
+                   double kappa, const cplx* ufar, const IoMap& io, double* out, hipStream_t st);
 
 // 3D Laplace evaluation (l3d_kernels.hip); P is the common expansion length
 hipError_t l3d_p2m(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
@@ -197,7 +207,7 @@ struct Near3Work {
     const int* row_of; const int* partner; const int64_t* coff; cplx* C;
 };
 hipError_t near3_p2p(const Near3Work& w, int kernel, int mixed, const int* leaves, int nleaf, const TreeView& tv,
-                     const PointsView& pv, double kappa, const cplx* ufar, const int* perm, double* out,
+                     const PointsView& pv, double kappa, const cplx* ufar, const IoMap& io, double* out,
                      hipStream_t st);
 
 // host-side special functions for the expansion-length rule

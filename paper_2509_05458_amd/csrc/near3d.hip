@@ -18,7 +18,8 @@
 // L is even), which covers each unordered pair once.
 //
 // Precision: FP64, or MIXED (differences formed in FP64 and cast to FP32, the
-// kernel in FP32, each tile's sums in FP32 and added in FP64).  In MIXED mode a
+// kernel in FP32, each tile's sums accumulated in FP32 with Kahan compensation
+// and the compensated sum formed and added in FP64).  In MIXED mode a
 // Helmholtz item whose near field can reach kappa r > 8 (flag from the plan)
 // forms r and the phase in FP64, reduced mod 2 pi before the FP32 sincos.
 #include "common.hpp"
@@ -190,6 +191,35 @@ struct Acc<2> {
     typedef float T;
 };
 
+// A tile's running sum.  FP64: plain.  FP32: compensated (Kahan): c carries
+// the rounding error of the last addition, which the next term corrects, so
+// the error of a sum of up to 64 terms stays near one FP32 rounding of the
+// total instead of growing with the term count; val() forms s - c in FP64.
+template <class T>
+struct Sum {
+    T s = 0;
+    __device__ inline void add(T x) { s += x; }
+    __device__ inline double val() const { return (double)s; }
+    __device__ inline void shfl(int src) { s = __shfl(s, src, 64); }
+};
+template <>
+struct Sum<float> {
+    float s = 0.0f, c = 0.0f;
+    __device__ inline void add(float x)
+    {
+        float y = x - c;
+        float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ inline double val() const { return (double)s - (double)c; }
+    __device__ inline void shfl(int src)
+    {
+        s = __shfl(s, src, 64);
+        c = __shfl(c, src, 64);
+    }
+};
+
 __device__ inline void load_tile(Tile& sh, const PointsView& pv, int j0, int cnt, int t)
 {
     int64_t n = pv.n;
@@ -222,7 +252,7 @@ __device__ inline void tile_pair(const Tile& sh, int R, int C, bool self, const 
     int L = max(R, C);
     int nxt = t < L ? (t + 1 == L ? 0 : t + 1) : t;
     int s0 = self ? 1 : 0, s1 = self ? L / 2 : L - 1;
-    T rr = 0, ri = 0, cr = 0, ci = 0;
+    Sum<T> rr, ri, cr, ci;
     T fwr = (T)wr, fwi = (T)wi;
     int q = t + s0;
     if (q >= L) q -= L;
@@ -237,13 +267,13 @@ __device__ inline void tile_pair(const Tile& sh, int R, int C, bool self, const 
             T gr, gi;
             Kernel<KIND, PREC>::eval(dr, di, kappa, gr, gi);
             T sr = (T)sh.sr[q], si = (T)sh.si[q];
-            rr += gr * sr - gi * si;
-            ri += gr * si + gi * sr;
-            cr += gr * fwr - gi * fwi;
-            ci += gr * fwi + gi * fwr;
+            rr.add(gr * sr - gi * si);
+            ri.add(gr * si + gi * sr);
+            cr.add(gr * fwr - gi * fwi);
+            ci.add(gr * fwi + gi * fwr);
         }
-        cr = __shfl(cr, nxt, 64);
-        ci = __shfl(ci, nxt, 64);
+        cr.shfl(nxt);
+        ci.shfl(nxt);
         if (++q >= L) q -= L;
     }
     if (self) {
@@ -253,13 +283,13 @@ __device__ inline void tile_pair(const Tile& sh, int R, int C, bool self, const 
             src = t - L / 2 - 1;
             while (src < 0) src += L;
         }
-        cr = __shfl(cr, src, 64);
-        ci = __shfl(ci, src, 64);
+        cr.shfl(src);
+        ci.shfl(src);
     }
-    ar += (double)rr;
-    ai += (double)ri;
-    cr_out = (double)cr;
-    ci_out = (double)ci;
+    ar += rr.val();
+    ai += ri.val();
+    cr_out = cr.val();
+    ci_out = ci.val();
 }
 
 // The same rotation for a tile of C sources against two rows of targets per
@@ -277,7 +307,7 @@ __device__ inline void tile_pair2(const Tile& sh, int R0, int R1, int C, const d
     int t = threadIdx.x;
     int L = max(R0, C);
     int nxt = t < L ? (t + 1 == L ? 0 : t + 1) : t;
-    T rr[2] = {0, 0}, ri[2] = {0, 0}, cr = 0, ci = 0;
+    Sum<T> rr[2], ri[2], cr, ci;
     T fwr[2] = {(T)wr[0], (T)wr[1]}, fwi[2] = {(T)wi[0], (T)wi[1]};
     int q = t;
     for (int step = 0; step < L; ++step) {
@@ -298,24 +328,24 @@ __device__ inline void tile_pair2(const Tile& sh, int R0, int R1, int C, const d
                     }
                     T gr, gi;
                     Kernel<KIND, PREC>::eval(dr, di, kappa, gr, gi);
-                    rr[r] += gr * sr - gi * si;
-                    ri[r] += gr * si + gi * sr;
-                    cr += gr * fwr[r] - gi * fwi[r];
-                    ci += gr * fwi[r] + gi * fwr[r];
+                    rr[r].add(gr * sr - gi * si);
+                    ri[r].add(gr * si + gi * sr);
+                    cr.add(gr * fwr[r] - gi * fwi[r]);
+                    ci.add(gr * fwi[r] + gi * fwr[r]);
                 }
             }
         }
-        cr = __shfl(cr, nxt, 64);
-        ci = __shfl(ci, nxt, 64);
+        cr.shfl(nxt);
+        ci.shfl(nxt);
         if (++q >= L) q -= L;
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        ar[r] += (double)rr[r];
-        ai[r] += (double)ri[r];
+        ar[r] += rr[r].val();
+        ai[r] += ri[r].val();
     }
-    cr_out = (double)cr;
-    ci_out = (double)ci;
+    cr_out = cr.val();
+    ci_out = ci.val();
 }
 
 // Neighbour items (a < b): rows into C[e], columns into C[partner e].  Targets
@@ -412,25 +442,29 @@ __global__ __launch_bounds__(64) void k_near3_diag(const int* __restrict__ items
     }
 }
 
-// u[perm[i]] = (1/4pi)(near + far), far = ufar (Laplace) or i kappa ufar
-// (Helmholtz, whose expansions carry the factor i kappa / 4pi).
+// u[perm[i] - obase] = (1/4pi)(near + far) at the targets, far = ufar
+// (Laplace) or i kappa ufar (Helmholtz, whose expansions carry the factor
+// i kappa / 4pi).
 template <int KIND>
 __global__ __launch_bounds__(64) void k_near3_final(const int* __restrict__ leaves, Near3Map mp, TreeView tv,
-                                                    double kappa, const cplx* __restrict__ ufar,
-                                                    const int* __restrict__ perm, double* __restrict__ out)
+                                                    double kappa, const cplx* __restrict__ ufar, IoMap io,
+                                                    double* __restrict__ out)
 {
     int b = leaves[blockIdx.x];
     int p0 = tv.pbeg[b], p1 = tv.pend[b];
     int e0 = tv.l1off[b], e1 = tv.l1off[b + 1];
     double k = 1.0 / (4.0 * kPi);
     for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+        int64_t p = (int64_t)io.perm[i] - io.obase;
+        if (p < 0) continue;            // a source that is not a target
         cplx u = mk(0.0, 0.0);
         for (int e = e0; e < e1; ++e) u += mp.C[mp.coff[e] + (i - p0)];
         cplx f = ufar[i];
         if (KIND == 1) f = mk(-kappa * f.im, kappa * f.re);
-        int64_t p = perm[i];
-        out[2 * p] = k * (u.re + f.re);
-        out[2 * p + 1] = k * (u.im + f.im);
+        double vr = k * (u.re + f.re), vi = k * (u.im + f.im);
+        out[2 * p] = vr;
+        out[2 * p + 1] = vi;
+        if (!isfinite(vr) || !isfinite(vi)) atomicOr(io.nonfinite, 1);
     }
 }
 
@@ -450,14 +484,14 @@ void launch_items(const Near3Work& w, int which, const Near3Map& mp, const TreeV
 // items[0]: neighbour items, items[1]: diagonal items; in MIXED Helmholtz,
 // items[2], items[3]: the same for wide-phase pairs.
 hipError_t near3_p2p(const Near3Work& w, int kernel, int mixed, const int* leaves, int nleaf, const TreeView& tv,
-                     const PointsView& pv, double kappa, const cplx* ufar, const int* perm, double* out,
+                     const PointsView& pv, double kappa, const cplx* ufar, const IoMap& io, double* out,
                      hipStream_t st)
 {
     Near3Map mp{w.row_of, w.partner, w.coff, w.C};
     if (kernel == 0) {
         if (mixed) { launch_items<0, 1>(w, 0, mp, tv, pv, kappa, st); launch_items<0, 1>(w, 1, mp, tv, pv, kappa, st); }
         else { launch_items<0, 0>(w, 0, mp, tv, pv, kappa, st); launch_items<0, 0>(w, 1, mp, tv, pv, kappa, st); }
-        if (nleaf > 0) k_near3_final<0><<<nleaf, 64, 0, st>>>(leaves, mp, tv, kappa, ufar, perm, out);
+        if (nleaf > 0) k_near3_final<0><<<nleaf, 64, 0, st>>>(leaves, mp, tv, kappa, ufar, io, out);
     } else {
         if (mixed) {
             launch_items<1, 1>(w, 0, mp, tv, pv, kappa, st);
@@ -468,7 +502,7 @@ hipError_t near3_p2p(const Near3Work& w, int kernel, int mixed, const int* leave
             launch_items<1, 0>(w, 0, mp, tv, pv, kappa, st);
             launch_items<1, 0>(w, 1, mp, tv, pv, kappa, st);
         }
-        if (nleaf > 0) k_near3_final<1><<<nleaf, 64, 0, st>>>(leaves, mp, tv, kappa, ufar, perm, out);
+        if (nleaf > 0) k_near3_final<1><<<nleaf, 64, 0, st>>>(leaves, mp, tv, kappa, ufar, io, out);
     }
     return hipGetLastError();
 }

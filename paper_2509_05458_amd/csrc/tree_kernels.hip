@@ -208,14 +208,16 @@ __global__ void k_gather_points(const double* __restrict__ pts, const int* __res
     }
 }
 
-__global__ void k_gather_density(const double* __restrict__ sig, const int* __restrict__ perm,
+// sigma into sorted order; target-only tree points carry zero density
+__global__ void k_gather_density(const double* __restrict__ sig, IoMap io,
                                  int64_t n, double* __restrict__ sre, double* __restrict__ sim)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int64_t p = perm[i];
-    sre[i] = sig[2 * p];
-    sim[i] = sig[2 * p + 1];
+    int64_t p = io.perm[i];
+    bool src = p < io.nsrc;
+    sre[i] = src ? sig[2 * p] : 0.0;
+    sim[i] = src ? sig[2 * p + 1] : 0.0;
 }
 
 // Complexified centres (a4): the mean imaginary part of each box's points and
@@ -419,10 +421,10 @@ hipError_t launch_gather_points(const double* pts, const int* perm, int64_t n, i
     return hipGetLastError();
 }
 
-hipError_t launch_gather_density(const double* sig, const int* perm, int64_t n, double* sre,
+hipError_t launch_gather_density(const double* sig, const IoMap& io, int64_t n, double* sre,
                                  double* sim, hipStream_t st)
 {
-    k_gather_density<<<(int)((n + 255) / 256), 256, 0, st>>>(sig, perm, n, sre, sim);
+    k_gather_density<<<(int)((n + 255) / 256), 256, 0, st>>>(sig, io, n, sre, sim);
     return hipGetLastError();
 }
 

@@ -10,9 +10,15 @@ stays resident for all of its matvecs and is freed when the request ends.
 Precision policy: the mixed near field where the tolerance is 1e-6 or looser,
 FP64 otherwise.
 
-The reference point is sequential plain-FP64 evaluation: one request at a
-time on one stream, every request in FP64.  Its latencies under the same
-arrivals follow from its measured service times (first come, first served).
+Each request is an iterative solve: its matvecs run one after another, the
+density of matvec m + 1 formed from the result of matvec m by an Arnoldi step
+(orthogonalised against the request's earlier densities and normalised, as
+GMRES does), with a host wait on each step's norm.  So a request's matvecs
+never overlap each other; requests overlap one another.
+
+The reference point is sequential plain-FP64 evaluation: the same arrival
+trace replayed through one slot on one stream, every request in FP64
+(measured, not modelled).
 
     python -m paper_2509_05458_amd.serve --requests 64 --slots 4
 """
@@ -54,24 +60,36 @@ class Prepared:
 
 
 def _process(prep, precision, stream, dev, keep_last=False, on_plan=None):
-    """Plan + nmat matvecs of one request on `stream`; returns (plan bytes, last result).
-    on_plan(nbytes) is called once the plan exists (for memory accounting)."""
+    """Plan + nmat dependent matvecs of one request on `stream`.
+
+    Matvec 0 takes the request's seeded density a (normalised); matvec m + 1
+    takes the Arnoldi vector of matvec m's result w = A v_m: w minus its
+    projections on v_0 .. v_m, divided by its norm, which the host reads
+    (the wait a GMRES iteration makes).  Returns (plan bytes, (last density,
+    last result) or None).  on_plan(nbytes) is called once the plan exists
+    (for memory accounting)."""
     import torch
     r = prep.req
     with torch.cuda.stream(stream):
         pts = torch.from_numpy(prep.points).to(dev)
         a = torch.from_numpy(prep.a).to(dev)
-        b = torch.from_numpy(prep.b).to(dev)
         plan = Plan(pts, "helmholtz", r.kappa, r.tol, precision=precision, stream=stream.cuda_stream)
         nbytes = plan.nbytes
         if on_plan is not None:
             on_plan(nbytes)
+        V = torch.empty((r.nmat, r.n), dtype=torch.complex128, device=dev)
         out = torch.empty(r.n, dtype=torch.complex128, device=dev)
-        two_pi_i = 2j * math.pi
+        V[0] = a / torch.linalg.vector_norm(a)
         for m in range(r.nmat):
-            sig = a * torch.exp((two_pi_i * m) * b)
-            plan.eval_into(sig, out)
-        last = out.clone() if keep_last else None
+            plan.eval_into(V[m], out)
+            if m + 1 == r.nmat:
+                break
+            h = torch.mv(V[: m + 1].conj(), out)            # projections on v_0 .. v_m
+            w = out - torch.mv(V[: m + 1].transpose(0, 1), h)
+            nrm = float(torch.linalg.vector_norm(w))        # host wait
+            V[m + 1] = w / nrm
+        last = (V[r.nmat - 1].clone(), out.clone()) if keep_last else None
+    plan.sync()
     stream.synchronize()
     del plan
     return nbytes, last
@@ -166,88 +184,71 @@ class Server:
                                         for k in range(len(prepared))])}
 
 
-def sequential_service_times(prepared: list, device: int = 0, keep_results: bool = False, progress=None):
-    """Plain FP64, one request at a time on one stream; service time per request.
-    progress(msg), when given, is called every 64 requests."""
-    import torch
-    dev = torch.device("cuda", device)
-    stream = torch.cuda.Stream(device=dev)
-    times, results = [], []
-    torch.cuda.synchronize(dev)
-    for prep in prepared:
-        t0 = time.perf_counter()
-        _, last = _process(prep, "fp64", stream, dev, keep_results)
-        times.append(time.perf_counter() - t0)
-        results.append(last)
-        if progress is not None and len(times) % 64 == 0:
-            progress(f"sequential {len(times)}/{len(prepared)}")
-    return np.array(times), results
-
-
-def fcfs_latencies(arrivals: np.ndarray, service: np.ndarray):
-    """Latency of each request through a single FIFO server."""
-    finish = np.empty_like(service)
-    t = 0.0
-    for i in range(len(service)):
-        t = max(t, arrivals[i]) + service[i]
-        finish[i] = t
-    return finish - arrivals, finish[-1] - arrivals[0]
+def sequential_fp64(slots_run_kwargs=None):
+    """The sequential plain-FP64 reference: one slot (one stream), FP64 for
+    every request."""
+    return Server(slots=1, policy=lambda tol: "fp64", **(slots_run_kwargs or {}))
 
 
 def interactions(prepared) -> float:
     return float(sum(p.req.n * (p.req.n - 1) * p.req.nmat for p in prepared))
 
 
-def serve_benchmark(nreq: int = 64, slots: int = 4, load: float = 0.8, nmax_log2: float = 18.0,
-                    hbm_budget: int = 64 << 30, check: int = 8, seed: int = 4000, progress=None) -> dict:
-    """Served stream against sequential plain FP64 on the same trace.
+def _stats(run, nmat, inter):
+    lat = run["latency"]
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "makespan_s": run["makespan"], "matvecs_per_s": nmat / run["makespan"],
+            "interactions_per_s": inter / run["makespan"], "peak_admitted_bytes": int(run["peak_bytes"])}
 
-    The arrival rate is load / (mean sequential service time); sequential
-    latencies come from its measured service times under those arrivals.
+
+def serve_benchmark(nreq: int = 64, slots: int = 4, load: float = 0.8, nmax_log2: float = 18.0,
+                    hbm_budget: int = 64 << 30, check: int = 8, seed: int = 4000, progress=None,
+                    nmat: int = 20) -> dict:
+    """Served stream against sequential plain FP64 on the same arrival trace.
+
+    1. Sequential FP64 with every request present at t = 0 gives the mean
+       sequential service time S and the sequential saturation throughput.
+    2. Arrivals are Poisson at load / S.  The trace is replayed through the
+       server (slots, mixed where tol >= 1e-6) and through one FP64 slot;
+       both latencies are measured (arrival to the last matvec's result).
+    3. The served run with every request present at t = 0 gives the served
+       saturation throughput.
     `check` requests are compared served vs sequential on their last matvec.
     """
     import synth
-    trace = synth.serving_trace(nreq, rate=1.0, nmax_log2=nmax_log2, seed=seed)
+    trace = synth.serving_trace(nreq, rate=1.0, nmax_log2=nmax_log2, seed=seed, nmat=nmat)
     prepared = [Prepared(r) for r in trace]
     # warm the library and the allocator on a small plan of each kind
-    warm = [Prepared(r) for r in synth.serving_trace(4, rate=1.0, nmax_log2=11.0, seed=seed + 1)]
-    sequential_service_times(warm)
-    svc, seq_res = sequential_service_times(prepared, keep_results=True, progress=progress)
+    warm = [Prepared(r) for r in synth.serving_trace(4, rate=1.0, nmax_log2=11.0, seed=seed + 1, nmat=2)]
+    sequential_fp64().run(warm, rate_scale=0.0)
+    seq_burst = sequential_fp64({"keep_results": True}).run(prepared, rate_scale=0.0, progress=progress)
+    svc = np.array([r["end"] - r["start"] for r in seq_burst["records"]])
     mean_s = float(svc.mean())
-    # unit-rate arrivals rescaled to the target load
-    unit = np.array([p.req.arrival for p in prepared])
-    rate_scale = mean_s / load
-    arrivals = unit * rate_scale
-    seq_lat, seq_span = fcfs_latencies(arrivals, svc)
+    rate_scale = mean_s / load                  # unit-rate arrivals rescaled to the target load
     srv = Server(slots=slots, hbm_budget=hbm_budget, keep_results=True).run(prepared, rate_scale=rate_scale,
                                                                            progress=progress)
-    lat = srv["latency"]
+    seq = sequential_fp64().run(prepared, rate_scale=rate_scale, progress=progress)
     diffs = []
     for k in range(min(check, nreq)):
-        a = srv["records"][k]["result"].cpu().numpy()
-        b = seq_res[k].cpu().numpy()
+        a = srv["records"][k]["result"][1].cpu().numpy()
+        b = seq_burst["records"][k]["result"][1].cpu().numpy()
         diffs.append(float(np.linalg.norm(a - b) / np.linalg.norm(b)))
     # both results are within tol of the exact sum, so they differ by at most 2 tol
-    ok = all(d <= 2.0 * prepared[k].req.tol for k, d in enumerate(diffs))
+    # (the Arnoldi chains of the two runs differ by as much, through their densities)
+    ok = all(d <= 2.0 * nmat * prepared[k].req.tol for k, d in enumerate(diffs))
     inter = interactions(prepared)
-    nmat = sum(p.req.nmat for p in prepared)
-    # saturation throughput: every request present at t = 0
+    nmv = sum(p.req.nmat for p in prepared)
     burst = Server(slots=slots, hbm_budget=hbm_budget).run(prepared, rate_scale=0.0, progress=progress)
-    seq_total = float(svc.sum())
     return {
-        "requests": nreq, "slots": slots, "load": load, "matvecs": nmat,
+        "requests": nreq, "slots": slots, "load": load, "matvecs": nmv, "nmax_log2": nmax_log2,
         "arrival_rate_per_s": 1.0 / rate_scale, "mean_sequential_service_s": mean_s,
-        "served": {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                   "makespan_s": srv["makespan"], "matvecs_per_s": nmat / srv["makespan"],
-                   "interactions_per_s": inter / srv["makespan"], "peak_admitted_bytes": int(srv["peak_bytes"])},
-        "sequential_fp64": {"p50_ms": float(np.percentile(seq_lat, 50) * 1e3),
-                            "p99_ms": float(np.percentile(seq_lat, 99) * 1e3),
-                            "makespan_s": float(seq_span), "matvecs_per_s": nmat / float(seq_span),
-                            "interactions_per_s": inter / float(seq_span)},
-        "burst": {"served_makespan_s": burst["makespan"], "sequential_fp64_makespan_s": seq_total,
-                  "served_matvecs_per_s": nmat / burst["makespan"], "sequential_matvecs_per_s": nmat / seq_total,
+        "served": _stats(srv, nmv, inter),
+        "sequential_fp64": _stats(seq, nmv, inter),
+        "burst": {"served_makespan_s": burst["makespan"], "sequential_fp64_makespan_s": seq_burst["makespan"],
+                  "served_matvecs_per_s": nmv / burst["makespan"],
+                  "sequential_matvecs_per_s": nmv / seq_burst["makespan"],
                   "served_interactions_per_s": inter / burst["makespan"],
-                  "sequential_interactions_per_s": inter / seq_total},
+                  "sequential_interactions_per_s": inter / seq_burst["makespan"]},
         "served_vs_sequential_rel_diff": diffs, "within_tol": ok,
     }
 
@@ -259,12 +260,13 @@ def main(argv=None):
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--nmax-log2", type=float, default=18.0)
     ap.add_argument("--hbm-budget-gib", type=float, default=64.0)
+    ap.add_argument("--matvecs", type=int, default=20)
     a = ap.parse_args(argv)
     def progress(msg):
         print(f"[serve] {msg}", file=sys.stderr, flush=True)
 
     res = serve_benchmark(a.requests, a.slots, a.load, a.nmax_log2, int(a.hbm_budget_gib * (1 << 30)),
-                          progress=progress)
+                          progress=progress, nmat=a.matvecs)
     print(json.dumps(res), flush=True)
 
 

@@ -28,14 +28,23 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
-@pytest.mark.parametrize("bad", [dict(dim=4), dict(kernel=7), dict(tol=0.0), dict(tol=2.0),
-                                 dict(n=0), dict(wavenumber=-1.0), dict(precision=5),
-                                 dict(separation=3), dict(leaf_size=-2)])
+_PTS = np.zeros((4, 3), np.complex128)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dim=4), dict(kernel=7), dict(tol=0.0), dict(tol=2.0), dict(n_src=0), dict(wavenumber=-1.0),
+    dict(precision=5), dict(separation=3), dict(leaf_size=-2),
+    # below each kernel's accuracy floor
+    dict(tol=1e-13), dict(dim=3, kernel=cf.LAPLACE, tol=1e-13), dict(dim=3, tol=1e-11),
+    # mixed precision below its FP32 rounding floor
+    dict(precision=cf.MIXED, tol=1e-8), dict(dim=3, kernel=cf.LAPLACE, precision=cf.MIXED, tol=1e-7),
+    # targets: a count without points is fine (ignored), points without a count is not
+    dict(n_trg=0, trg=_PTS.ctypes.data), dict(n_trg=-3, trg=_PTS.ctypes.data),
+    dict(n_src=2 ** 30, n_trg=2 ** 30, trg=_PTS.ctypes.data), dict(src=None)])
 def test_invalid_arguments_rejected(bad):
     import ctypes
-    pts = np.zeros((4, 2), np.complex128)
-    kw = dict(dim=2, kernel=cf.HELMHOLTZ, wavenumber=1.0, tol=1e-6, n=4, points=pts.ctypes.data,
-              points_on_device=0, precision=0, stream=None, leaf_size=0, separation=0)
+    kw = dict(dim=2, kernel=cf.HELMHOLTZ, wavenumber=1.0, tol=1e-6, n_src=4, src=_PTS.ctypes.data,
+              n_trg=0, trg=None, points_on_device=0, precision=0, stream=None, leaf_size=0, separation=0)
     kw.update(bad)
     d = cf.PlanDesc(**kw)
     h = ctypes.c_void_p()
@@ -43,6 +52,23 @@ def test_invalid_arguments_rejected(bad):
     assert rc == cf.CFMM_EINVAL
     assert cf.lib().cfmm_last_error().decode() != ""
     assert not h.value
+
+
+def test_accuracy_floors_match_the_binding():
+    src = open(os.path.join(ROOT, "include", "cfmm.h")).read()
+    vals = dict(re.findall(r"#define (CFMM_(?:TOL_MIN_\w+|MIXED_TOL_MIN)) ([0-9.e-]+)", src))
+    assert float(vals["CFMM_TOL_MIN_HELMHOLTZ_2D"]) == cf.TOL_MIN[(2, "helmholtz")]
+    assert float(vals["CFMM_TOL_MIN_LAPLACE_3D"]) == cf.TOL_MIN[(3, "laplace")]
+    assert float(vals["CFMM_TOL_MIN_HELMHOLTZ_3D"]) == cf.TOL_MIN[(3, "helmholtz")]
+    assert float(vals["CFMM_MIXED_TOL_MIN"]) == cf.MIXED_TOL_MIN
+
+
+def test_binding_rejects_bad_points_before_the_library():
+    with pytest.raises(ValueError):
+        cf.Plan(np.zeros(5, np.complex128), "helmholtz", 1.0, 1e-6)
+    with pytest.raises(ValueError):
+        cf.Plan(np.zeros((5, 2), np.complex128), "helmholtz", 1.0, 1e-6,
+                targets=np.zeros((5, 3), np.complex128))
 
 
 def test_null_arguments_rejected():
@@ -117,8 +143,9 @@ def test_nterms_3d_helmholtz_low_frequency_equals_oracle_rule(kappa, sep):
 def test_2d_laplace_not_supported():
     import ctypes
     pts = np.zeros((4, 2), np.complex128)
-    d = cf.PlanDesc(dim=2, kernel=cf.LAPLACE, wavenumber=0.0, tol=1e-6, n=4, points=pts.ctypes.data,
-                    points_on_device=0, precision=0, stream=None, leaf_size=0, separation=0)
+    d = cf.PlanDesc(dim=2, kernel=cf.LAPLACE, wavenumber=0.0, tol=1e-6, n_src=4, src=pts.ctypes.data,
+                    n_trg=0, trg=None, points_on_device=0, precision=0, stream=None, leaf_size=0,
+                    separation=0)
     h = ctypes.c_void_p()
     assert cf.lib().cfmm_plan(ctypes.byref(h), ctypes.byref(d)) == cf.CFMM_ENOTSUP
     assert not h.value

@@ -168,16 +168,22 @@ def test_profiling_modes():
     for _ in range(3):
         plan.eval_into(sig, out)
     torch.cuda.synchronize()
-    tot, cnt = plan.near_ms()
+    tot, cnt = plan.ring_ms()
     assert cnt == 3 and tot > 0.0
     for _ in range(70):
         plan.eval_into(sig, out)
     torch.cuda.synchronize()
-    tot2, cnt2 = plan.near_ms()
+    tot2, cnt2 = plan.ring_ms()
     assert cnt2 == 64 and tot2 > 0.0
+    plan.set_profiling(3)
+    for _ in range(2):
+        plan.eval_into(sig, out)
+    torch.cuda.synchronize()
+    tot3, cnt3 = plan.ring_ms()
+    assert cnt3 == 2 and 0.0 < tot3 < 2 * st["eval"] + 1.0
     plan.set_profiling(0)
     with pytest.raises(cf.CfmmError):
-        plan.set_profiling(3)
+        plan.set_profiling(4)
     u0 = plan(sig).cpu().numpy()
     assert oracle.rel_l2(u0, out.cpu().numpy()) == 0.0
 

@@ -1,5 +1,5 @@
-"""CPU checks of the serving layer: trace recipe, precision policy, FIFO
-latency model, admission estimate."""
+"""CPU checks of the serving layer: trace recipe, precision policy,
+admission estimate."""
 import math
 
 import numpy as np
@@ -41,14 +41,6 @@ def test_precision_policy():
     assert serve.precision_for(1e-4) == "mixed"
     assert serve.precision_for(1e-6) == "mixed"
     assert serve.precision_for(1e-10) == "fp64"
-
-
-def test_fcfs_latencies():
-    arr = np.array([0.0, 1.0, 1.5, 10.0])
-    svc = np.array([2.0, 1.0, 1.0, 0.5])
-    lat, span = serve.fcfs_latencies(arr, svc)
-    # finishes: 2, 3, 4, 10.5
-    assert np.allclose(lat, [2.0, 2.0, 2.5, 0.5]) and math.isclose(span, 10.5)
 
 
 def test_estimate_grows_with_n():
