@@ -134,7 +134,7 @@ def test_collinear_complex_points_closed_form():
 
 
 @pytest.mark.parametrize("dim,kernel,kappa", [(2, "helmholtz", 10.0), (3, "laplace", 0.0),
-                                              (3, "helmholtz", 5.0)])
+                                              (3, "helmholtz", 5.0), (2, "laplace", 0.0)])
 def test_symmetric_matrix_bitwise(dim, kernel, kappa):
     pts = synth.curve2d(300, 21) if dim == 2 else synth.plane3d_grid(17)
     n = pts.shape[0]
@@ -169,7 +169,8 @@ def test_complex_translation_and_rotation_invariance():
 
 def test_holomorphy_in_each_coordinate():
     rng = np.random.default_rng(41)
-    for dim, kernel, kappa in ((2, "helmholtz", 6.0), (3, "laplace", 0.0), (3, "helmholtz", 6.0)):
+    for dim, kernel, kappa in ((2, "helmholtz", 6.0), (3, "laplace", 0.0), (3, "helmholtz", 6.0),
+                               (2, "laplace", 0.0)):
         for _ in range(20):
             x = rng.uniform(-1, 1, dim) + 0.2j * rng.uniform(-1, 1, dim)
             y = rng.uniform(-1, 1, dim) + 0.2j * rng.uniform(-1, 1, dim)
@@ -200,3 +201,26 @@ def test_self_term_and_coincident_points_contribute_nothing():
     u = oracle.direct_self(2, "helmholtz", 3.0, pts2, sig, targets=[0])
     u_ref = oracle.direct_self(2, "helmholtz", 3.0, pts, sig[:50], targets=[0])
     assert u[0] == pytest.approx(u_ref[0], rel=1e-14)
+
+
+def test_laplace2d_collinear_closed_form_and_split_logs():
+    """2D Laplace, G = -(1/2 pi) log r.  On the line x2 = y2 = 0, r = +-(x1 - y1)
+    with Re r > 0, so G = -(1/2 pi) Log(+-(x1 - y1)).  Off the line, with
+    z = x1 + i x2 and w = x1 - i x2 (independent complex numbers), r^2 =
+    (z_x - z_y)(w_x - w_y), and for points close to the real plane the
+    principal logs split: log r = (Log dz + Log dw)/2."""
+    rng = np.random.default_rng(71)
+    a = rng.uniform(-5, 5, 300) + 0.4j * rng.uniform(-1, 1, 300)
+    b = rng.uniform(-5, 5, 300) + 0.4j * rng.uniform(-1, 1, 300)
+    d = a - b
+    d = np.where(d.real >= 0, d, -d)
+    g = oracle.green(2, "laplace", 0.0, d * d)
+    assert np.allclose(g, -np.log(d) / (2 * np.pi), rtol=1e-14, atol=1e-15)
+    x = rng.uniform(-1, 1, (300, 2)) + 0.1j * rng.uniform(-1, 1, (300, 2))
+    y = rng.uniform(2, 3, (300, 2)) + 0.1j * rng.uniform(-1, 1, (300, 2))
+    dz = (x[:, 0] + 1j * x[:, 1]) - (y[:, 0] + 1j * y[:, 1])
+    dw = (x[:, 0] - 1j * x[:, 1]) - (y[:, 0] - 1j * y[:, 1])
+    s = np.sum((x - y) ** 2, axis=1)
+    assert np.allclose(dz * dw, s, rtol=1e-14)
+    g = oracle.green(2, "laplace", 0.0, s)
+    assert np.allclose(g, -(np.log(dz) + np.log(dw)) / (4 * np.pi), rtol=1e-13, atol=1e-15)
