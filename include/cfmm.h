@@ -115,6 +115,22 @@ int cfmm_eval(cfmm_plan_t plan, const void* density, void* potential, int on_dev
  * a non-finite potential (the potentials are written nevertheless). */
 int cfmm_sync(cfmm_plan_t plan);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation): the
+ * evaluation of cfmm_eval with host pointers (on_device = 0), staged through
+ * a static device buffer instead of staging the library allocates.
+ *   density   : host complex128[n_src]; potential : host complex128[n_trg]
+ *               (n_src without targets), overwritten.  Synchronous.
+ * Requires n_src + n_trg <= CFMM_STATIC_MAX; larger plans get CFMM_EINVAL.
+ * Calls no allocator.  The buffer (CFMM_STATIC_MAX complex values, 64 MiB)
+ * is held by every GPU the library runs on until the process ends, and is
+ * shared by all calls on that GPU: calls that overlap on one GPU (from
+ * several threads or streams) race and must be serialised by the caller.
+ * Errors as cfmm_eval with host pointers (CFMM_ERANGE for a non-finite
+ * potential). */
+#define CFMM_STATIC_MAX 4194304
+int cfmm_eval_static(cfmm_plan_t plan, const void* density, void* potential);
+
 /* Free a plan (NULL is accepted).  Synchronises its stream first.  Plans
  * allocate and free stream-ordered (hipMallocAsync / hipFreeAsync on the plan's
  * stream, from the device's default memory pool, which the library sets to keep

@@ -43,6 +43,7 @@ class CfmmError(RuntimeError):
 # smallest tolerances the library accepts (include/cfmm.h)
 TOL_MIN = {(2, "helmholtz"): 1e-12, (3, "laplace"): 1e-12, (3, "helmholtz"): 1e-10}
 MIXED_TOL_MIN = 1e-6
+STATIC_MAX = 1 << 22            # complex values of cfmm_eval_static's staging
 
 
 class PlanDesc(ctypes.Structure):
@@ -71,6 +72,7 @@ def lib():
                                      ctypes.POINTER(ctypes.c_uint64))
         L.cfmm_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PlanDesc)]
         L.cfmm_eval.argtypes = [vp, vp, vp, ctypes.c_int]
+        L.cfmm_eval_static.argtypes = [vp, vp, vp]
         L.cfmm_sync.argtypes = [vp]
         L.cfmm_destroy.argtypes = [vp]
         L.cfmm_plan_bytes.argtypes = [vp]
@@ -201,6 +203,16 @@ class Plan:
             raise ValueError(f"sigma: expected {self.n} values, got {s.shape[0]}")
         out = np.empty(self.n_out, dtype=np.complex128)
         _check(L.cfmm_eval(self._handle, s.ctypes.data, out.ctypes.data, 0))
+        return out
+
+    def eval_static(self, sigma):
+        """Host evaluation staged through the library's static device buffer
+        (cfmm_eval_static: no allocation; n_src + n_out <= STATIC_MAX)."""
+        s = np.ascontiguousarray(sigma, dtype=np.complex128).reshape(-1)
+        if s.shape[0] != self.n:
+            raise ValueError(f"sigma: expected {self.n} values, got {s.shape[0]}")
+        out = np.empty(self.n_out, dtype=np.complex128)
+        _check(lib().cfmm_eval_static(self._handle, s.ctypes.data, out.ctypes.data))
         return out
 
     def sync(self):

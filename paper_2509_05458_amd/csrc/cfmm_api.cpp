@@ -52,6 +52,7 @@ int ensure_device_tables()
     HIPCHK(hipDeviceGetDefaultMemPool(&pool, dev));
     uint64_t keep = UINT64_MAX;
     HIPCHK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+    HIPCHK(static_scratch_init(dev));
     HIPCHK(h2d_init_tables(dev));
     HIPCHK(h3d_init_tables(dev));
     HIPCHK(l3d_init_tables(dev));
@@ -68,6 +69,7 @@ struct cfmm_plan_s {
     int64_t n_src = 0;            // densities per evaluation
     int64_t n_out = 0;            // potentials per evaluation
     int64_t obase = 0;            // tree point index of the first target (0: targets = sources)
+    int device = 0;               // the GPU the plan lives on
     int* d_flag_nf = nullptr;     // set when an evaluation writes a non-finite potential
     hipStream_t stream = nullptr;
     HostTree tree;
@@ -933,6 +935,10 @@ int cfmm_plan(cfmm_plan_t* out, const cfmm_plan_desc* d)
     int rc = ensure_device_tables();
     if (rc) return rc;
     cfmm_plan_s* p = new cfmm_plan_s();
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return fail(CFMM_EHIP, "hipGetDevice failed");
+    }
     p->dim = d->dim;
     p->kernel = d->kernel;
     p->kappa = d->kernel == CFMM_HELMHOLTZ ? d->wavenumber : 0.0;
@@ -986,6 +992,26 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
 int cfmm_sync(cfmm_plan_t p)
 {
     if (!p) return fail(CFMM_EINVAL, "plan is NULL");
+    return check_finite(p);
+}
+
+int cfmm_eval_static(cfmm_plan_t p, const void* density, void* potential)
+{
+    if (!p) return fail(CFMM_EINVAL, "plan is NULL");
+    if (!density || !potential) return fail(CFMM_EINVAL, "density or potential is NULL");
+    if (p->n_src + p->n_out > kStaticScratch)
+        return fail(CFMM_EINVAL, "n_src + n_trg = " + std::to_string(p->n_src + p->n_out) +
+                                     " exceeds the static staging of CFMM_STATIC_MAX = " +
+                                     std::to_string(kStaticScratch) + " complex values; use cfmm_eval");
+    cplx* scr = static_scratch(p->device);
+    if (!scr) return fail(CFMM_EINVAL, "the library was not initialised on the plan's device");
+    hipStream_t st = p->stream;
+    double* sig = reinterpret_cast<double*>(scr);
+    double* out = reinterpret_cast<double*>(scr + p->n_src);
+    HIPCHK(hipMemcpyAsync(sig, density, 2 * p->n_src * sizeof(double), hipMemcpyHostToDevice, st));
+    int rc = eval_on_device(p, sig, out);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(potential, out, 2 * p->n_out * sizeof(double), hipMemcpyDeviceToHost, st));
     return check_finite(p);
 }
 

@@ -210,6 +210,12 @@ hipError_t near3_p2p(const Near3Work& w, int kernel, int mixed, const int* leave
                      const PointsView& pv, double kappa, const cplx* ufar, const IoMap& io, double* out,
                      hipStream_t st);
 
+// Static staging of cfmm_eval_static (scratch.hip): kStaticScratch complex
+// values per device, resolved once per device with that device current.
+constexpr int64_t kStaticScratch = (int64_t)1 << 22;
+hipError_t static_scratch_init(int device);
+cplx* static_scratch(int device);
+
 // host-side special functions for the expansion-length rule
 double h2d_nterms_crit(double kappa, double R, double r, int n);
 
