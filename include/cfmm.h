@@ -12,6 +12,7 @@
  * given, the targets are the sources and the self term j = i is left out.
  * A pair at squared distance exactly 0 contributes nothing.  Kernels:
  *
+ *     dim 2, CFMM_LAPLACE   :  G = -(1/(2 pi)) log r           (Sec. 4.2)
  *     dim 2, CFMM_HELMHOLTZ :  G = (i/4) H0^(1)(kappa r)        (Sec. 4.3)
  *     dim 3, CFMM_LAPLACE   :  G = 1 / (4 pi r)                 (Sec. 5.2)
  *     dim 3, CFMM_HELMHOLTZ :  G = exp(i kappa r) / (4 pi r)    (Sec. 5.3)
@@ -51,8 +52,8 @@ extern "C" {
 
 #define CFMM_OK 0
 #define CFMM_EINVAL (-1)     /* bad dim / kernel / kappa / tol / precision / n / pointer */
-#define CFMM_ENOTSUP (-2)    /* not supported: 2D Laplace, or boxes so many wavelengths
-                                wide that the expansion length exceeds the maximum */
+#define CFMM_ENOTSUP (-2)    /* not supported: boxes so many wavelengths wide that the
+                                expansion length exceeds the maximum */
 #define CFMM_EGEOMETRY (-3)  /* non-finite coordinates, or Re r^2 <= 0 in a near pair */
 #define CFMM_ENOMEM (-4)     /* device allocation failed */
 #define CFMM_EHIP (-5)       /* a HIP runtime call failed (message has the HIP error) */
@@ -62,6 +63,7 @@ extern "C" {
  * translations, not the truncation, sets the error, and the requested
  * accuracy could not be met.  CFMM_MIXED needs tol >= CFMM_MIXED_TOL_MIN: its
  * FP32 stages round at about 1e-7 relative. */
+#define CFMM_TOL_MIN_LAPLACE_2D 1e-12
 #define CFMM_TOL_MIN_HELMHOLTZ_2D 1e-12
 #define CFMM_TOL_MIN_LAPLACE_3D 1e-12
 #define CFMM_TOL_MIN_HELMHOLTZ_3D 1e-10

@@ -41,7 +41,7 @@ class CfmmError(RuntimeError):
 
 
 # smallest tolerances the library accepts (include/cfmm.h)
-TOL_MIN = {(2, "helmholtz"): 1e-12, (3, "laplace"): 1e-12, (3, "helmholtz"): 1e-10}
+TOL_MIN = {(2, "laplace"): 1e-12, (2, "helmholtz"): 1e-12, (3, "laplace"): 1e-12, (3, "helmholtz"): 1e-10}
 MIXED_TOL_MIN = 1e-6
 STATIC_MAX = 1 << 22            # complex values of cfmm_eval_static's staging
 

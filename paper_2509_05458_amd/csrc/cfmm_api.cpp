@@ -54,6 +54,7 @@ int ensure_device_tables()
     HIPCHK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
     HIPCHK(static_scratch_init(dev));
     HIPCHK(h2d_init_tables(dev));
+    HIPCHK(l2d_init_tables(dev));
     HIPCHK(h3d_init_tables(dev));
     HIPCHK(l3d_init_tables(dev));
     g_inited.insert(dev);
@@ -526,10 +527,24 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     if (top > nlev) top = nlev;
     // -------- expansion lengths (a6)
     bool h2d = dim == 2;
+    bool lap2 = h2d && p->kernel == CFMM_LAPLACE;
     p->P.assign(nlev, 0);
     p->rs.assign(nlev, 1.0);
     int pmax = 0;
-    if (h2d) {
+    if (lap2) {
+        // 2D Laplace: (r/R)^n <= tol with R = (0.5 + k) w, r = sqrt(2)/2 w (Sec.
+        // 6.3 with the prefactors dropped), the same on every level;
+        // coordinates of level l are scaled by 1/w_l
+        int m = nterms_laplace(dim, p->sep, p->tol);
+        if (m > kPMax2D)
+            return fail(CFMM_ENOTSUP, "expansion length " + std::to_string(m) + " above the supported maximum " +
+                                          std::to_string(kPMax2D));
+        for (int l = top; l < nlev; ++l) {
+            p->rs[l] = 1.0 / (p->D * ldexp(1.0, -l));
+            p->P[l] = m;
+        }
+        pmax = m;
+    } else if (h2d) {
         double eps = 0.1 * p->tol;
         for (int l = top; l < nlev; ++l) {
             double w = p->D * ldexp(1.0, -l);
@@ -713,8 +728,8 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         for (int e = 0; e < ne; ++e) {
             int b = row_of[e], a = t.idx[0][e];
             if (a > b) continue;                      // the pair is visited from a's row
-            double qb = bound(b, a);
-            bool series = qb < 2.25;
+            double qb = lap2 ? 0.0 : bound(b, a);
+            bool series = lap2 || qb < 2.25;          // 2D Laplace: Log s for every pair
             if (a == b) {
                 if (series && t.pend[b] - t.pbeg[b] <= 64) { diag.push_back(e); diag_k.push_back(nterms_series(qb)); }
                 else if (series) { ser.push_back(e); ser_k.push_back(nterms_series(qb)); }
@@ -818,7 +833,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     }
     if ((rc = upload(p, &p->d_work, work))) return rc;
     int64_t gsz = 0, tsz = 0;
-    if (h2d) {
+    if (h2d && !lap2) {
     // -------- translation operators (generators of M2L, M2M, L2L)
     std::vector<int64_t> o_m2l(npairs), o_tr(nb, -1);
     for (int b = 0; b < nb; ++b)
@@ -914,9 +929,7 @@ int cfmm_plan(cfmm_plan_t* out, const cfmm_plan_desc* d)
     if (d->kernel != CFMM_LAPLACE && d->kernel != CFMM_HELMHOLTZ) return fail(CFMM_EINVAL, "unknown kernel");
     if (d->kernel == CFMM_HELMHOLTZ && !(d->wavenumber > 0.0 && isfinite(d->wavenumber)))
         return fail(CFMM_EINVAL, "Helmholtz needs a finite wavenumber > 0");
-    if (d->dim == 2 && d->kernel == CFMM_LAPLACE)
-        return fail(CFMM_ENOTSUP, "supported: dim 2 Helmholtz, dim 3 Laplace and Helmholtz");
-    double tmin = d->dim == 2 ? CFMM_TOL_MIN_HELMHOLTZ_2D
+    double tmin = d->dim == 2 ? (d->kernel == CFMM_LAPLACE ? CFMM_TOL_MIN_LAPLACE_2D : CFMM_TOL_MIN_HELMHOLTZ_2D)
                               : (d->kernel == CFMM_LAPLACE ? CFMM_TOL_MIN_LAPLACE_3D : CFMM_TOL_MIN_HELMHOLTZ_3D);
     if (!(d->tol >= tmin && d->tol < 1.0))
         return fail(CFMM_EINVAL, "tol must lie in [" + std::to_string(tmin) + ", 1) for this kernel: below it "
@@ -1059,7 +1072,23 @@ int eval_on_device(cfmm_plan_s* p, const double* sig, double* out)
     HIPCHK(mark(0));
     HIPCHK(launch_gather_density(sig, p->io(), n, p->d_sre, p->d_sim, st));
     HIPCHK(mark(1));
-    if (p->dim == 2) {
+    if (p->dim == 2 && p->kernel == CFMM_LAPLACE) {
+        HIPCHK(l2d_p2m(W + p->off_p2m, p->n_p2m, tv, pv, p->d_mpole, st));
+        HIPCHK(mark(2));
+        for (int l = nlev - 2; l >= top; --l) HIPCHK(l2d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], tv, p->d_mpole, st));
+        HIPCHK(mark(3));
+        HIPCHK(mark(8));
+        HIPCHK(l2d_m2l(W + p->off_m2l, p->n_m2l, tv, p->d_mpole, p->d_local, st));
+        HIPCHK(mark(9));
+        HIPCHK(l2d_p2l(W + p->off_p2l, p->n_p2l, tv, pv, p->d_local, st));
+        HIPCHK(mark(4));
+        for (int l = top + 1; l < nlev; ++l) HIPCHK(l2d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], tv, p->d_local, st));
+        HIPCHK(mark(5));
+        HIPCHK(l2d_leaf_far(W + p->off_leaves, p->nleaf, p->m2p_parts(), top, tv, pv, p->d_mpole, p->d_local,
+                            p->d_ufar, st));
+        HIPCHK(mark(6));
+        HIPCHK(h2d_p2p(p->near2, W + p->off_leaves, p->nleaf, tv, pv, 0.0, p->d_ufar, p->io(), out, 1, st));
+    } else if (p->dim == 2) {
         {
             // the P2M list is in level order; one launch per level sizes its LDS by that level's P
             int k0 = 0;
@@ -1105,7 +1134,7 @@ int eval_on_device(cfmm_plan_s* p, const double* sig, double* out)
         HIPCHK(h2d_leaf_far(W + p->off_leaves, p->nleaf, p->m2p_parts(), p->m2p_pmax, top, tv, pv, p->kappa,
                             p->d_mpole, p->d_local, p->d_ufar, st));
         HIPCHK(mark(6));
-        HIPCHK(h2d_p2p(p->near2, W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->io(), out, st));
+        HIPCHK(h2d_p2p(p->near2, W + p->off_leaves, p->nleaf, tv, pv, p->kappa, p->d_ufar, p->io(), out, 0, st));
     } else if (p->kernel == CFMM_HELMHOLTZ) {
         H3DLevels hl{p->d_h3_kw, p->d_h3_sc, nullptr};
         HIPCHK(hipMemsetAsync(p->d_mpole, 0, p->ecount * sizeof(cplx), st));

@@ -935,6 +935,18 @@ __device__ inline cplx h0_series_s(double sr, double si, double k2, double lk2, 
     return mk(jr - yi, ji + yr);                          // J0 + i Y0
 }
 
+// The near-field kernel value of a pair from s = r^2: MODE 1, the power
+// series of H0 (2D Helmholtz, |kappa r| < 3, K terms); MODE 2, Log s = 2 log r
+// (2D Laplace: log |s| from |s|^2 and arg s).  The final pass applies the
+// constant ((i/4) or -(1/4 pi)).
+template <int MODE>
+__device__ inline cplx near_value(double sr, double si, double k2, double lk2, int K)
+{
+    if (MODE == 2) return mk(0.5 * log_pos(sr * sr + si * si), arg2(sr, si));
+    return h0_series_s(sr, si, k2, lk2, K);
+}
+
+template <int MODE>
 __global__ __launch_bounds__(64) void k_h2d_p2p_sym(const int* __restrict__ items, const int* __restrict__ nterm,
                                                     P2PMap mp, TreeView tv, PointsView pv, double kappa)
 {
@@ -988,7 +1000,7 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_sym(const int* __restrict__ item
                     double sr = d1r * d1r - d1i * d1i + d2r * d2r - d2i * d2i;
                     double si = 2.0 * (d1r * d1i + d2r * d2i);
                     if (sr != 0.0 || si != 0.0) {
-                        cplx h = h0_series_s(sr, si, k2, lk2, K);
+                        cplx h = near_value<MODE>(sr, si, k2, lk2, K);
                         cfma2(xr, xi, h, ssr[j], ssi[j]);
                         cfma2(yr, yi, h, twr[i], twi[i]);
                     }
@@ -1026,6 +1038,7 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_sym(const int* __restrict__ item
 // for even L, the last block the L/2 pairs (f, f + L/2), f < L/2.  Point f
 // gains the term of its partner as a row sum and the partner that of f as a
 // column sum.
+template <int MODE>
 __global__ __launch_bounds__(64) void k_h2d_p2p_diag(const int* __restrict__ items, const int* __restrict__ nterm,
                                                      P2PMap mp, TreeView tv, PointsView pv, double kappa)
 {
@@ -1063,7 +1076,7 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_diag(const int* __restrict__ ite
             double sr = d1r * d1r - d1i * d1i + d2r * d2r - d2i * d2i;
             double si = 2.0 * (d1r * d1i + d2r * d2i);
             if (sr != 0.0 || si != 0.0) {
-                cplx h = h0_series_s(sr, si, k2, lk2, K);
+                cplx h = near_value<MODE>(sr, si, k2, lk2, K);
                 cfma2(xr, xi, h, ssr[j], ssi[j]);
                 cfma2(yr, yi, h, ssr[i], ssi[i]);
             }
@@ -1086,15 +1099,16 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_diag(const int* __restrict__ ite
     }
 }
 
-// Row items: one direction of an entry, the small-argument series (SERIES,
-// K terms) or the general Hankel evaluation; a == b skips the self pair.
-template <bool SERIES>
+// Row items: one direction of an entry, by the general Hankel evaluation
+// (MODE 0) or near_value<MODE> (the small-argument series with K terms, or
+// Log s); a == b skips the self pair.
+template <int MODE>
 __global__ __launch_bounds__(64) void k_h2d_p2p_row(const int* __restrict__ items, const int* __restrict__ nterm,
                                                     P2PMap mp, TreeView tv, PointsView pv, double kappa)
 {
     __shared__ double s1r[64], s1i[64], s2r[64], s2i[64], ssr[64], ssi[64];
     int e = items[blockIdx.x];
-    int K = SERIES ? nterm[blockIdx.x] : 0;
+    int K = MODE == 1 ? nterm[blockIdx.x] : 0;
     int b = mp.row_of[e], a = tv.l1idx[e];
     int64_t n = pv.n;
     int t = threadIdx.x;
@@ -1128,8 +1142,8 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_row(const int* __restrict__ item
                 double sr = d1r * d1r - d1i * d1i + d2r * d2r - d2i * d2i;
                 double si = 2.0 * (d1r * d1i + d2r * d2i);
                 if (sr == 0.0 && si == 0.0) continue;
-                cplx h = SERIES ? h0_series_s(sr, si, k2, lk2, K)
-                                : hankel0_s(mk(sr, si), kappa, c_ghx, c_ghw);
+                cplx h = MODE != 0 ? near_value<MODE>(sr, si, k2, lk2, K)
+                                   : hankel0_s(mk(sr, si), kappa, c_ghx, c_ghw);
                 cfma2(ar, ai, h, ssr[q], ssi[q]);
             }
         }
@@ -1137,8 +1151,11 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_row(const int* __restrict__ item
     }
 }
 
-// Final pass: u[perm[i] - obase] = (i/4)(near + far) at the targets, the
-// near field summed over the target's List-1 entries in list order.
+// Final pass: u[perm[i] - obase] = (i/4)(near + far) (Helmholtz) or
+// -(1/4 pi)(near + far) (Laplace, whose sums are of Log s = 2 log r) at the
+// targets, the near field summed over the target's List-1 entries in list
+// order.
+template <int LAP>
 __global__ __launch_bounds__(64) void k_h2d_p2p_final(const int* __restrict__ leaves, P2PMap mp, TreeView tv,
                                                       const cplx* __restrict__ ufar, IoMap io,
                                                       double* __restrict__ out)
@@ -1151,7 +1168,8 @@ __global__ __launch_bounds__(64) void k_h2d_p2p_final(const int* __restrict__ le
         if (p < 0) continue;            // a source that is not a target
         cplx u = ufar[i];
         for (int e = e0; e < e1; ++e) u += mp.C[mp.coff[e] + (i - p0)];
-        double vr = -0.25 * u.im, vi = 0.25 * u.re;      // (i/4) u
+        double vr = LAP ? u.re * (-0.25 / kPi) : -0.25 * u.im;
+        double vi = LAP ? u.im * (-0.25 / kPi) : 0.25 * u.re;
         out[2 * p] = vr;
         out[2 * p + 1] = vi;
         if (!isfinite(vr) || !isfinite(vi)) atomicOr(io.nonfinite, 1);
@@ -1244,14 +1262,21 @@ hipError_t h2d_leaf_far(const int* leaves, int nleaf, const M2PParts& m2p, int m
 }
 
 hipError_t h2d_p2p(const H2DNear& nr, const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                   double kappa, const cplx* ufar, const IoMap& io, double* out, hipStream_t st)
+                   double kappa, const cplx* ufar, const IoMap& io, double* out, int laplace, hipStream_t st)
 {
     P2PMap mp{nr.row_of, nr.partner, nr.coff, nr.C};
-    if (nr.nsym > 0) k_h2d_p2p_sym<<<nr.nsym, 64, 0, st>>>(nr.sym, nr.sym_k, mp, tv, pv, kappa);
-    if (nr.ndiag > 0) k_h2d_p2p_diag<<<nr.ndiag, 64, 0, st>>>(nr.diag, nr.diag_k, mp, tv, pv, kappa);
-    if (nr.nser > 0) k_h2d_p2p_row<true><<<nr.nser, 64, 0, st>>>(nr.ser, nr.ser_k, mp, tv, pv, kappa);
-    if (nr.ngen > 0) k_h2d_p2p_row<false><<<nr.ngen, 64, 0, st>>>(nr.gen, nullptr, mp, tv, pv, kappa);
-    if (nleaf > 0) k_h2d_p2p_final<<<nleaf, 64, 0, st>>>(leaves, mp, tv, ufar, io, out);
+    if (laplace) {
+        if (nr.nsym > 0) k_h2d_p2p_sym<2><<<nr.nsym, 64, 0, st>>>(nr.sym, nr.sym_k, mp, tv, pv, 0.0);
+        if (nr.ndiag > 0) k_h2d_p2p_diag<2><<<nr.ndiag, 64, 0, st>>>(nr.diag, nr.diag_k, mp, tv, pv, 0.0);
+        if (nr.nser > 0) k_h2d_p2p_row<2><<<nr.nser, 64, 0, st>>>(nr.ser, nr.ser_k, mp, tv, pv, 0.0);
+        if (nleaf > 0) k_h2d_p2p_final<1><<<nleaf, 64, 0, st>>>(leaves, mp, tv, ufar, io, out);
+        return hipGetLastError();
+    }
+    if (nr.nsym > 0) k_h2d_p2p_sym<1><<<nr.nsym, 64, 0, st>>>(nr.sym, nr.sym_k, mp, tv, pv, kappa);
+    if (nr.ndiag > 0) k_h2d_p2p_diag<1><<<nr.ndiag, 64, 0, st>>>(nr.diag, nr.diag_k, mp, tv, pv, kappa);
+    if (nr.nser > 0) k_h2d_p2p_row<1><<<nr.nser, 64, 0, st>>>(nr.ser, nr.ser_k, mp, tv, pv, kappa);
+    if (nr.ngen > 0) k_h2d_p2p_row<0><<<nr.ngen, 64, 0, st>>>(nr.gen, nullptr, mp, tv, pv, kappa);
+    if (nleaf > 0) k_h2d_p2p_final<0><<<nleaf, 64, 0, st>>>(leaves, mp, tv, ufar, io, out);
     return hipGetLastError();
 }
 

@@ -129,8 +129,24 @@ struct H2DNear {
     const int* gen; int ngen;
     const int* row_of; const int* partner; const int64_t* coff; cplx* C;
 };
+// laplace = 1: the 2D Laplace near field (Log s by every item kind; no
+// general items), final constant -(1/4 pi) instead of (i/4)
 hipError_t h2d_p2p(const H2DNear& nr, const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv,
-                   double kappa, const cplx* ufar, const IoMap& io, double* out, hipStream_t st);
+                   double kappa, const cplx* ufar, const IoMap& io, double* out, int laplace, hipStream_t st);
+
+// 2D Laplace evaluation (l2d_kernels.hip): expansions of 2P+1 values per box
+// (two power series, in z = x1 + i x2 and w = x1 - i x2), P the same on
+// every level, tv.rs[l] = 1 / w_l
+hipError_t l2d_init_tables(int device);
+hipError_t l2d_p2m(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv, cplx* mpole,
+                   hipStream_t st);
+hipError_t l2d_m2m(const int* boxes, int nb, const TreeView& tv, cplx* mpole, hipStream_t st);
+hipError_t l2d_m2l(const int* boxes, int nb, const TreeView& tv, const cplx* mpole, cplx* local, hipStream_t st);
+hipError_t l2d_p2l(const int* boxes, int nb, const TreeView& tv, const PointsView& pv, cplx* local,
+                   hipStream_t st);
+hipError_t l2d_l2l(const int* boxes, int nb, const TreeView& tv, cplx* local, hipStream_t st);
+hipError_t l2d_leaf_far(const int* leaves, int nleaf, const M2PParts& m2p, int top, const TreeView& tv,
+                        const PointsView& pv, const cplx* mpole, const cplx* local, cplx* ufar, hipStream_t st);
 
 // 3D Laplace evaluation (l3d_kernels.hip); P is the common expansion length
 hipError_t l3d_p2m(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,

@@ -58,6 +58,7 @@ def test_accuracy_floors_match_the_binding():
     src = open(os.path.join(ROOT, "include", "cfmm.h")).read()
     vals = dict(re.findall(r"#define (CFMM_(?:TOL_MIN_\w+|MIXED_TOL_MIN)) ([0-9.e-]+)", src))
     assert float(vals["CFMM_TOL_MIN_HELMHOLTZ_2D"]) == cf.TOL_MIN[(2, "helmholtz")]
+    assert float(vals["CFMM_TOL_MIN_LAPLACE_2D"]) == cf.TOL_MIN[(2, "laplace")]
     assert float(vals["CFMM_TOL_MIN_LAPLACE_3D"]) == cf.TOL_MIN[(3, "laplace")]
     assert float(vals["CFMM_TOL_MIN_HELMHOLTZ_3D"]) == cf.TOL_MIN[(3, "helmholtz")]
     assert float(vals["CFMM_MIXED_TOL_MIN"]) == cf.MIXED_TOL_MIN
@@ -140,12 +141,12 @@ def test_nterms_3d_helmholtz_low_frequency_equals_oracle_rule(kappa, sep):
         assert got == ref, (eps, got, ref)
 
 
-def test_2d_laplace_not_supported():
+def test_2d_laplace_floor_rejected():
     import ctypes
     pts = np.zeros((4, 2), np.complex128)
-    d = cf.PlanDesc(dim=2, kernel=cf.LAPLACE, wavenumber=0.0, tol=1e-6, n_src=4, src=pts.ctypes.data,
+    d = cf.PlanDesc(dim=2, kernel=cf.LAPLACE, wavenumber=0.0, tol=1e-13, n_src=4, src=pts.ctypes.data,
                     n_trg=0, trg=None, points_on_device=0, precision=0, stream=None, leaf_size=0,
                     separation=0)
     h = ctypes.c_void_p()
-    assert cf.lib().cfmm_plan(ctypes.byref(h), ctypes.byref(d)) == cf.CFMM_ENOTSUP
+    assert cf.lib().cfmm_plan(ctypes.byref(h), ctypes.byref(d)) == cf.CFMM_EINVAL
     assert not h.value
