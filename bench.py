@@ -207,17 +207,19 @@ def main():
         "near_interactions": nw["interactions"], "near_evaluations": nw["evaluations"],
     }
     if roof_m2l:
-        # k_l3d_m2l: the O(P^4) addition-theorem contraction, (P+1)^4 complex
-        # multiply-adds (8 flops) per List-2 pair; P is the same on every level
+        # k_l3d_m2l: the addition-theorem contraction, (P+1)^2 (Ps+1)^2 complex
+        # multiply-adds (8 flops) per List-2 pair, Ps the pair's source
+        # expansion length (m2l_source_coefs sums (Ps+1)^2 over the pairs)
         P = info["max_p"]
-        m2l_flops = 8.0 * (P + 1) ** 4 * info["m2l_pairs"]
+        m2l_flops = 8.0 * (P + 1) ** 2 * info["m2l_source_coefs"]
         m2l_peak = PEAK_FP64_VALU if not (a.precision == "mixed" and P <= 16) else PEAK_FP32_VALU
         roof = {
             "kernel": "k_l3d_m2l" + ("_f32" if m2l_peak == PEAK_FP32_VALU else ""),
             "bound": "alu", "achieved": m2l_flops / (m2l_ms * 1e-3) / 1e12, "peak": m2l_peak / 1e12,
             "unit": "TFLOP/s", "frac": m2l_flops / (m2l_ms * 1e-3) / m2l_peak,
             "traffic": measured_traffic("c2_m2l") if a.precision == "fp64" else None,
-            "flops_per_pair": 8.0 * (P + 1) ** 4, "pairs": info["m2l_pairs"], "ms_per_launch": m2l_ms,
+            "flops_per_pair_mean": m2l_flops / max(1, info["m2l_pairs"]), "pairs": info["m2l_pairs"],
+            "ms_per_launch": m2l_ms,
             "p2p": p2p_block,
         }
     else:

@@ -151,7 +151,9 @@ const char* cfmm_last_error(void);
  *                 n_list4, p2p_pairs (interactions per eval), m2l_pairs,
  *                 max_p, dim, kernel, separation, leaf_size, precision,
  *                 n_src, n_trg (potentials written), n_points (tree points:
- *                 n_src, or n_src + n_trg with distinct targets), 0 }
+ *                 n_src, or n_src + n_trg with distinct targets),
+ *                 m2l_source_coefs (source coefficients contracted by M2L per
+ *                 evaluation, summed over the List-2 pairs) }
  * The tree, lists and interaction counts are over the tree points. */
 int cfmm_plan_info(cfmm_plan_t plan, int64_t* info20);
 

@@ -228,7 +228,7 @@ class Plan:
         _check(lib().cfmm_plan_info(self._handle, _ptr(a, ctypes.c_int64)))
         keys = ("nbox", "nleaf", "nlevels", "top_level", "n_list1", "n_list2", "n_list3",
                 "n_list4", "p2p_pairs", "m2l_pairs", "max_p", "dim", "kernel", "separation",
-                "leaf_size", "precision", "n_src", "n_trg", "n_points")
+                "leaf_size", "precision", "n_src", "n_trg", "n_points", "m2l_source_coefs")
         return {k: int(v) for k, v in zip(keys, a)}
 
     def near_work(self) -> dict:

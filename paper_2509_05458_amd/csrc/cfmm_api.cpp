@@ -126,6 +126,7 @@ struct cfmm_plan_s {
     // 3D Laplace M2L: table row bases and lane slots (l3d_layout.hpp)
     int* d_l3map = nullptr;
     int l3_ntab = 0, l3_R = 0;
+    L3PairP l3_pp{};              // source expansion length per M2L pair distance
     // 3D M2P by List-3 entries: owner leaf, partial-sum offsets and storage
     int* d_m2p_owner = nullptr;
     int64_t* d_m2p_poff = nullptr;
@@ -596,6 +597,17 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
             p->P[l] = m;
         }
         pmax = m;
+        // per M2L pair: the same rule with the pair's nearest target distance
+        // (d - 1/2) w, d the max-norm centre distance in box widths
+        for (int d = 0; d < 8; ++d) {
+            double ratio = sqrt(3.0) * 0.5 / (d - 0.5);
+            int md = m;
+            if (d > p->sep) {
+                md = 1;
+                while (pow(ratio, md) > p->tol && md < m) ++md;
+            }
+            p->l3_pp.p[d] = md;
+        }
         L3dM2LLayout lay = l3d_m2l_layout(m);
         std::vector<int> map(lay.base);
         map.insert(map.end(), lay.slot.begin(), lay.slot.end());
@@ -909,7 +921,24 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     for (int q = 0; q < 4; ++q) I[4 + q] = (int64_t)t.idx[q].size();
     I[8] = p2p; I[9] = m2l; I[10] = pmax; I[11] = dim; I[12] = p->kernel; I[13] = p->sep;
     I[14] = p->leaf_size; I[15] = p->precision;
-    I[16] = p->n_src; I[17] = p->n_out; I[18] = p->n; I[19] = 0;
+    // M2L work: the source coefficients contracted over all List-2 pairs (3D
+    // Laplace: (Ps+1)^2 with the pair's own Ps; otherwise the level's count)
+    int64_t m2l_src = 0;
+    for (int b = 0; b < nb; ++b)
+        for (int e = t.off[1][b]; e < t.off[1][b + 1]; ++e) {
+            int a = t.idx[1][e];
+            int l = t.level[b];
+            int Ps = p->P[l];
+            if (dim == 3 && p->kernel == CFMM_LAPLACE) {
+                int64_t cb[3], ca[3], dm = 0;
+                box_coords(t, b, cb);
+                box_coords(t, a, ca);
+                for (int k = 0; k < 3; ++k) dm = std::max<int64_t>(dm, std::llabs(cb[k] - ca[k]));
+                Ps = p->l3_pp.p[dm < 7 ? dm : 7];
+            }
+            m2l_src += h2d ? 2 * Ps + 1 : (int64_t)(Ps + 1) * (Ps + 1);
+        }
+    I[16] = p->n_src; I[17] = p->n_out; I[18] = p->n; I[19] = m2l_src;
     return CFMM_OK;
 }
 
@@ -1213,8 +1242,8 @@ int eval_on_device(cfmm_plan_s* p, const double* sig, double* out)
         // below the requested accuracy
         int m2l32 = p->precision == CFMM_MIXED && p->tol >= 1e-6;
         HIPCHK(mark(8));
-        HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, m2l32, p->d_mpole,
-                       p->d_local, st));
+        HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, p->l3_pp, m2l32,
+                       p->d_mpole, p->d_local, st));
         HIPCHK(mark(9));
         HIPCHK(l3d_p2l(W + p->off_p2l, p->n_p2l, P, tv, pv, p->d_local, st));
         HIPCHK(mark(4));

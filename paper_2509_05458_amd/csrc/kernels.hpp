@@ -154,8 +154,14 @@ hipError_t l3d_p2m(const int* boxes, int nb, int P, const TreeView& tv, const Po
 hipError_t l3d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
                    cplx* local, hipStream_t st);
 hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mpole, hipStream_t st);
+// Source expansion length of an M2L pair by the max-norm distance d of the
+// box centres in box widths: p[min(d, 7)] (Sec. 6.3's rule with the pair's
+// own nearest target distance (d - 1/2) w in place of (k + 1/2) w).
+struct L3PairP {
+    int p[8];
+};
 hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const int* map, int ntab, int R,
-                   int mixed, const cplx* mpole, cplx* local, hipStream_t st);
+                   const L3PairP& pp, int mixed, const cplx* mpole, cplx* local, hipStream_t st);
 hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st);
 hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& tv,
                         const PointsView& pv, const cplx* mpole, const cplx* local, const M2PParts& m2p,

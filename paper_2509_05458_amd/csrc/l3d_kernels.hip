@@ -380,9 +380,19 @@ struct alignas(16) cplx16 {
     double re, im;
 };
 
+// Source expansion length of a List-2 pair from the max-norm distance of the
+// box centres in box widths (the real parts; 3..5 with separation 2).
+__device__ inline int pair_terms(const L3PairP& pp, const cplx* cb, const cplx* ca, double s)
+{
+    double dm = 0.0;
+    for (int k = 0; k < 3; ++k) dm = fmax(dm, fabs(cb[k].re - ca[k].re));
+    int d = (int)(dm * s + 0.5);
+    return pp.p[d < 7 ? d : 7];
+}
+
 template <int R>
 __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restrict__ boxes, int nboxes, TreeView tv,
-                                                 const int* __restrict__ map, int ntab,
+                                                 const int* __restrict__ map, int ntab, L3PairP pp,
                                                  const cplx* __restrict__ mpole,
                                                  cplx* __restrict__ local)
 {
@@ -397,8 +407,6 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
     int t = threadIdx.x, lane = t & 63;
     int W = blockDim.x >> 6;
     int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-    int s0 = nc * wv / W, s1 = nc * (wv + 1) / W;   // this wavefront's steps
-    int na = step_row(s0), nb = s1 > s0 ? step_row(s1 - 1) : na - 1;
     int jg[R], kg[R];
     bool act[R];
     cplx acc[R][4];
@@ -418,14 +426,20 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
     for (int e = tv.l2off[b]; e < tv.l2off[b + 1]; ++e) {
         int a = tv.l2idx[e];
         const cplx* M = mpole + tv.eoff[a];
+        cplx ca[3];
+        box_centre(tv, a, ca);
+        // source orders n <= Ps of this pair: rows l = j + n <= P + Ps of the
+        // table, and (Ps+1)^2 steps split over the W wavefronts
+        int Ps = __builtin_amdgcn_readfirstlane(pair_terms(pp, cb, ca, s));
+        int Lt = P + Ps, ncp = (Ps + 1) * (Ps + 1);
+        int s0 = ncp * wv / W, s1 = ncp * (wv + 1) / W;   // this wavefront's steps
+        int na = step_row(s0), nb = s1 > s0 ? step_row(s1 - 1) : na - 1;
         __syncthreads();
-        if (t <= 4 * P) {
-            cplx ca[3];
-            box_centre(tv, a, ca);
+        if (t <= 4 * P && abs(t - 2 * P) <= Lt) {
             Vec3 d;
             d.x = (cb[0] - ca[0]) * s; d.y = (cb[1] - ca[1]) * s; d.z = (cb[2] - ca[2]) * s;
             int q = t - 2 * P;
-            col_I(d, q, 2 * P, false, [&](int n, cplx v) { tab[base[n] + q] = v; });
+            col_I(d, q, Lt, false, [&](int n, cplx v) { tab[base[n] + q] = v; });
         }
         __syncthreads();
         for (int n = na; n <= nb; ++n) {
@@ -500,7 +514,7 @@ constexpr int kM2LF32MaxP = 16;
 
 template <int R>
 __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __restrict__ boxes, int nboxes, TreeView tv,
-                                                     const int* __restrict__ map, int ntab,
+                                                     const int* __restrict__ map, int ntab, L3PairP pp,
                                                      const cplx* __restrict__ mpole,
                                                      cplx* __restrict__ local)
 {
@@ -515,8 +529,6 @@ __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __
     int t = threadIdx.x, lane = t & 63;
     int W = blockDim.x >> 6;
     int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-    int s0 = nc * wv / W, s1 = nc * (wv + 1) / W;   // this wavefront's steps
-    int na = step_row(s0), nb = s1 > s0 ? step_row(s1 - 1) : na - 1;
     int jg[R], kg[R];
     bool act[R];
     cplx acc[R][4];
@@ -536,15 +548,19 @@ __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __
     for (int e = tv.l2off[b]; e < tv.l2off[b + 1]; ++e) {
         int a = tv.l2idx[e];
         const cplx* M = mpole + tv.eoff[a];
+        cplx ca[3];
+        box_centre(tv, a, ca);
+        int Ps = __builtin_amdgcn_readfirstlane(pair_terms(pp, cb, ca, s));
+        int Lt = P + Ps, ncp = (Ps + 1) * (Ps + 1);
+        int s0 = ncp * wv / W, s1 = ncp * (wv + 1) / W;   // this wavefront's steps
+        int na = step_row(s0), nb = s1 > s0 ? step_row(s1 - 1) : na - 1;
         __syncthreads();
-        for (int i = t; i < nc; i += blockDim.x) Ms[i] = make_float2((float)M[i].re, (float)M[i].im);
-        if (t <= 4 * P) {
-            cplx ca[3];
-            box_centre(tv, a, ca);
+        for (int i = t; i < ncp; i += blockDim.x) Ms[i] = make_float2((float)M[i].re, (float)M[i].im);
+        if (t <= 4 * P && abs(t - 2 * P) <= Lt) {
             Vec3 d;
             d.x = (cb[0] - ca[0]) * s; d.y = (cb[1] - ca[1]) * s; d.z = (cb[2] - ca[2]) * s;
             int q = t - 2 * P;
-            col_I(d, q, 2 * P, false,
+            col_I(d, q, Lt, false,
                   [&](int n, cplx v) { tabf[base[n] + q] = make_float2((float)v.re, (float)v.im); });
         }
         __syncthreads();
@@ -761,14 +777,14 @@ hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mp
 
 template <int R>
 static hipError_t launch_m2l(const int* boxes, int nb, size_t lds, const TreeView& tv, const int* map, int ntab,
-                             const cplx* mpole, cplx* local, hipStream_t st)
+                             const L3PairP& pp, const cplx* mpole, cplx* local, hipStream_t st)
 {
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_l3d_m2l<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_l3d_m2l<R><<<nb, 64 * kM2LWaves, lds, st>>>(boxes, nb, tv, map, ntab, mpole, local);
+    k_l3d_m2l<R><<<nb, 64 * kM2LWaves, lds, st>>>(boxes, nb, tv, map, ntab, pp, mpole, local);
     return hipGetLastError();
 }
 
@@ -794,37 +810,37 @@ size_t l3d_m2l_lds(int P, int ntab)
 
 template <int R>
 static hipError_t launch_m2l_f32(const int* boxes, int nb, size_t lds, const TreeView& tv, const int* map,
-                                 int ntab, const cplx* mpole, cplx* local, hipStream_t st)
+                                 int ntab, const L3PairP& pp, const cplx* mpole, cplx* local, hipStream_t st)
 {
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_l3d_m2l_f32<R>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_l3d_m2l_f32<R><<<nb, 64 * kM2LWavesF32, lds, st>>>(boxes, nb, tv, map, ntab, mpole, local);
+    k_l3d_m2l_f32<R><<<nb, 64 * kM2LWavesF32, lds, st>>>(boxes, nb, tv, map, ntab, pp, mpole, local);
     return hipGetLastError();
 }
 
 hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const int* map, int ntab, int R,
-                   int mixed, const cplx* mpole, cplx* local, hipStream_t st)
+                   const L3PairP& pp, int mixed, const cplx* mpole, cplx* local, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
     if (mixed && P <= kM2LF32MaxP) {
         size_t lds = std::max((size_t)(ntab + (P + 1) * (P + 1)) * sizeof(float2) + (size_t)(2 * P + 1) * sizeof(int),
                               m2l_red_bytes(R, kM2LWavesF32));
         switch (R) {
-        case 1: return launch_m2l_f32<1>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
-        case 2: return launch_m2l_f32<2>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
+        case 1: return launch_m2l_f32<1>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
+        case 2: return launch_m2l_f32<2>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
         default: return hipErrorInvalidValue;
         }
     }
     size_t lds = l3d_m2l_lds(P, ntab);
     switch (R) {
-    case 1: return launch_m2l<1>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
-    case 2: return launch_m2l<2>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
-    case 3: return launch_m2l<3>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
-    case 4: return launch_m2l<4>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
-    case 5: return launch_m2l<5>(boxes, nb, lds, tv, map, ntab, mpole, local, st);
+    case 1: return launch_m2l<1>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
+    case 2: return launch_m2l<2>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
+    case 3: return launch_m2l<3>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
+    case 4: return launch_m2l<4>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
+    case 5: return launch_m2l<5>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -91,7 +91,7 @@ def test_deterministic():
 
 
 def test_zz_c3_full_size_sampled_parity():
-    cfg = synth.make_config(3, n_oracle=128)
+    cfg = synth.make_config(3, n_oracle=1024)
     plan, u = _plan_eval(cfg.points, cfg.sigma, K3, 1e-10)
     tg = cfg.oracle_targets
     u0 = oracle.direct_self(3, "helmholtz", K3, cfg.points, cfg.sigma, targets=tg, nthreads=NTHREADS)

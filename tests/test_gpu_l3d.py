@@ -82,7 +82,8 @@ def test_clustered_adaptive_tree_parity():
 
 
 def test_c2_full_size_sampled_parity():
-    cfg = synth.make_config(2, n_oracle=128)
+    # the configuration's 4096 seeded oracle targets
+    cfg = synth.make_config(2, n_oracle=4096)
     plan, u = _plan_eval(cfg.points, cfg.sigma, 1e-6)
     tg = cfg.oracle_targets
     u0 = oracle.direct_self(3, "laplace", 0.0, cfg.points, cfg.sigma, targets=tg, nthreads=NTHREADS)

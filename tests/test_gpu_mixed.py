@@ -52,7 +52,7 @@ def test_2d_mixed_parity():
 
 @pytest.mark.parametrize("ci,kernel", [(3, "helmholtz"), (2, "laplace")])
 def test_full_size_mixed_sampled_parity(ci, kernel):
-    cfg = synth.make_config(ci, n_oracle=128)
+    cfg = synth.make_config(ci, n_oracle=1024)
     um = _run(cfg.points, cfg.sigma, kernel, cfg.kappa, 1e-6, "mixed")
     tg = cfg.oracle_targets
     u0 = oracle.direct_self(3, kernel, cfg.kappa, cfg.points, cfg.sigma, targets=tg, nthreads=NTHREADS)
