@@ -5,6 +5,8 @@ coordinate FMM computes, used to check the HIP library:
 
 * ``direct``   : FP64 direct sum u_i = sum_j G(x_i, y_j) sigma_j with the
                  principal complexified distance (oracle.c);
+* ``layer3``   : the 3D layer potentials with charges and dipoles (single
+                 and double layer) and their gradients at the targets;
 * ``tree``     : the adaptive tree on the real parts and Lists 1-4 (tree.py),
                  the integer result the library's tree must reproduce bit for bit.
 
@@ -57,6 +59,9 @@ def _load():
         lib.oracle_green.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_int64, dp, dp]
         lib.oracle_green.restype = None
+        lib.oracle_layer3.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, dp, ctypes.c_int64, dp,
+                                      dp, dp, lp, dp, dp, ctypes.c_int]
+        lib.oracle_layer3.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -89,6 +94,40 @@ def direct(dim: int, kernel: str, kappa: float, trg: np.ndarray, src: np.ndarray
     if rc != 0:
         raise ValueError("oracle_direct: invalid arguments")
     return out
+
+
+def layer3(kernel: str, kappa: float, trg: np.ndarray, src: np.ndarray, charge=None, dipole=None,
+           self_idx=None, nthreads: int = 0):
+    """3D layer potentials (oracle.c, oracle_layer3): with dipole vectors
+    v_j = tau_j nu_j,  u_i = sum_j G sigma_j + v_j . grad_y G,  g_i = grad_x u_i.
+    Returns (u [n_trg], g [n_trg, 3])."""
+    lib = _load()
+    trg = np.ascontiguousarray(trg, dtype=np.complex128).reshape(-1, 3)
+    src = np.ascontiguousarray(src, dtype=np.complex128).reshape(-1, 3)
+    ns = src.shape[0]
+    q = None if charge is None else np.ascontiguousarray(charge, dtype=np.complex128).reshape(ns)
+    v = None if dipole is None else np.ascontiguousarray(dipole, dtype=np.complex128).reshape(ns, 3)
+    u = np.empty(trg.shape[0], dtype=np.complex128)
+    g = np.empty((trg.shape[0], 3), dtype=np.complex128)
+    sp = None
+    if self_idx is not None:
+        si = np.ascontiguousarray(self_idx, dtype=np.int64).reshape(-1)
+        sp = si.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    rc = lib.oracle_layer3(kernel_code(kernel), float(kappa), trg.shape[0], _dptr(trg), ns, _dptr(src),
+                           None if q is None else _dptr(q), None if v is None else _dptr(v), sp,
+                           _dptr(u), _dptr(g), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_layer3: invalid arguments")
+    return u, g
+
+
+def layer3_self(kernel, kappa, pts, charge=None, dipole=None, targets=None, nthreads=0):
+    """layer3 with targets = sources (self term left out), optionally at `targets`."""
+    pts = np.ascontiguousarray(pts, dtype=np.complex128)
+    if targets is None:
+        targets = np.arange(pts.shape[0], dtype=np.int64)
+    targets = np.asarray(targets, dtype=np.int64)
+    return layer3(kernel, kappa, pts[targets], pts, charge, dipole, targets, nthreads)
 
 
 def direct_self(dim, kernel, kappa, pts, sigma, targets=None, nthreads=0):

@@ -245,3 +245,93 @@ void oracle_green(int dim, int kernel, double kappa, int64_t n, const double* s,
     cplx* O = (cplx*)out;
     for (int64_t i = 0; i < n; ++i) O[i] = green(dim, kernel, kappa, S[i]);
 }
+
+/*
+ * Layer potentials with charges and dipoles, potential and gradient (Sec. 2.1:
+ * the single and double layer potentials S[sigma], D[tau] and their normal
+ * derivatives at the targets; a dipole vector v_j = tau_j nu_j carries the
+ * double-layer density and the source normal):
+ *
+ *   u_i = sum_j G(x_i, y_j) sigma_j + v_j . grad_y G(x_i, y_j)
+ *   g_i = grad_x u_i
+ *
+ * 3D kernels.  With d = x - y, r the principal root of d.d and G = g(r), the
+ * chain rule (r^2 = d.d, bilinear, so grad_x r = d / r) gives
+ *   grad_x G = g'(r) d / r,   grad_y G = -g'(r) d / r,
+ *   grad_x (v . grad_y G) = -[ g'(r) v / r + (g''(r) - g'(r)/r) (v.d) d / r^2 ]
+ * with g = 1/(4 pi r), g' = -g/r, g'' = 2 g / r^2 (Laplace) and
+ * g = e^{i kappa r}/(4 pi r), g' = g (i kappa - 1/r),
+ * g'' = g ((i kappa - 1/r)^2 + 1/r^2) (Helmholtz).
+ *   charge : complex128[n_src] or NULL;  dipole : complex128[n_src][3] or NULL
+ *   pot    : complex128[n_trg] or NULL;  grad   : complex128[n_trg][3] or NULL
+ * Self pairs (self_idx) and pairs at s = 0 are skipped.  Neumaier sums.
+ */
+int oracle_layer3(int kernel, double kappa, int64_t n_trg, const double* trg, int64_t n_src,
+                  const double* src, const double* charge, const double* dipole,
+                  const int64_t* self_idx, double* pot, double* grad, int nthreads)
+{
+    if (kernel != OR_LAPLACE && kernel != OR_HELMHOLTZ) return -1;
+    if (kernel == OR_HELMHOLTZ && !(kappa > 0.0)) return -1;
+    if (n_trg < 0 || n_src < 0) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    const cplx* T = (const cplx*)trg;
+    const cplx* S = (const cplx*)src;
+    const cplx* Q = (const cplx*)charge;
+    const cplx* V = (const cplx*)dipole;
+    cplx* U = (cplx*)pot;
+    cplx* G = (cplx*)grad;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n_trg; ++i) {
+        neum_t acc[8];
+        for (int k = 0; k < 8; ++k) acc[k].s = acc[k].c = 0.0;
+        int64_t skip = self_idx ? self_idx[i] : -1;
+        for (int64_t j = 0; j < n_src; ++j) {
+            if (j == skip) continue;
+            cplx d[3], s = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                d[k] = T[i * 3 + k] - S[j * 3 + k];
+                s += d[k] * d[k];
+            }
+            if (creal(s) == 0.0 && cimag(s) == 0.0) continue;
+            cplx r = csqrt(s);
+            cplx g, g1, g2;
+            if (kernel == OR_HELMHOLTZ) {
+                g = cexp(I * kappa * r) / (4.0 * OR_PI * r);
+                cplx a = I * kappa - 1.0 / r;
+                g1 = g * a;
+                g2 = g * (a * a + 1.0 / (r * r));
+            } else {
+                g = 1.0 / (4.0 * OR_PI * r);
+                g1 = -g / r;
+                g2 = 2.0 * g / (r * r);
+            }
+            cplx u = 0.0, gr[3] = {0.0, 0.0, 0.0};
+            if (Q) {
+                u += g * Q[j];
+                for (int k = 0; k < 3; ++k) gr[k] += g1 * d[k] / r * Q[j];
+            }
+            if (V) {
+                const cplx* v = V + j * 3;
+                cplx vd = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
+                u += -g1 * vd / r;
+                for (int k = 0; k < 3; ++k)
+                    gr[k] += -(g1 * v[k] / r + (g2 - g1 / r) * vd * d[k] / (r * r));
+            }
+            neum_add(&acc[0], creal(u));
+            neum_add(&acc[1], cimag(u));
+            for (int k = 0; k < 3; ++k) {
+                neum_add(&acc[2 + 2 * k], creal(gr[k]));
+                neum_add(&acc[3 + 2 * k], cimag(gr[k]));
+            }
+        }
+        if (U) U[i] = (acc[0].s + acc[0].c) + I * (acc[1].s + acc[1].c);
+        if (G)
+            for (int k = 0; k < 3; ++k)
+                G[i * 3 + k] = (acc[2 + 2 * k].s + acc[2 + 2 * k].c) + I * (acc[3 + 2 * k].s + acc[3 + 2 * k].c);
+    }
+    return 0;
+}
