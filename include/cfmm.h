@@ -112,6 +112,25 @@ int cfmm_plan(cfmm_plan_t* out, const cfmm_plan_desc* desc);
  *               CFMM_ERANGE when a potential is not finite). */
 int cfmm_eval(cfmm_plan_t plan, const void* density, void* potential, int on_device);
 
+/* Layer potentials (Sec. 2.1: the single layer S[sigma], the double layer
+ * D[tau] with the source normals nu, and their normal derivatives S', D' at
+ * the targets, Sec. 2.2), for dim 3 Laplace (CFMM_ENOTSUP otherwise):
+ *   u_i = sum_j G(x_i, y_j) sigma_j + v_j . grad_y G(x_i, y_j),   g_i = grad_x u_i
+ * with dipole vectors v_j = tau_j nu_j (complex: bilinear dot products, no
+ * conjugation).  S'[sigma], D'[tau] at a target with normal nu_i are
+ * nu_i . g_i.  The self term j = i is left out when targets = sources.
+ *   charge    : complex128[n_src] or NULL (no charges)
+ *   dipole    : complex128[n_src][3] or NULL (no dipoles); not both NULL
+ *   potential : complex128[n_trg] or NULL, overwritten
+ *   gradient  : complex128[n_trg][3] or NULL, overwritten; not both NULL
+ *   on_device : as cfmm_eval.  The first call allocates the dipole and
+ *   gradient buffers (and the host staging for host pointers).
+ * The expansions have the plan's length, so the gradients, one derivative
+ * rougher, carry a somewhat larger relative error than tol.  FP64 near field
+ * (owner computes per target leaf, no symmetric pairs). */
+int cfmm_eval_layer(cfmm_plan_t plan, const void* charge, const void* dipole, void* potential, void* gradient,
+                    int on_device);
+
 /* Wait for all work enqueued on the plan's stream.  Returns CFMM_ERANGE if an
  * evaluation since the previous cfmm_sync (or since the plan was built) wrote
  * a non-finite potential (the potentials are written nevertheless). */

@@ -73,6 +73,7 @@ def lib():
         L.cfmm_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PlanDesc)]
         L.cfmm_eval.argtypes = [vp, vp, vp, ctypes.c_int]
         L.cfmm_eval_static.argtypes = [vp, vp, vp]
+        L.cfmm_eval_layer.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int]
         L.cfmm_sync.argtypes = [vp]
         L.cfmm_destroy.argtypes = [vp]
         L.cfmm_plan_bytes.argtypes = [vp]
@@ -204,6 +205,36 @@ class Plan:
         out = np.empty(self.n_out, dtype=np.complex128)
         _check(L.cfmm_eval(self._handle, s.ctypes.data, out.ctypes.data, 0))
         return out
+
+    def eval_layer(self, charge=None, dipole=None, potential: bool = True, gradient: bool = False):
+        """Layer potentials (cfmm_eval_layer, dim 3 Laplace): charges sigma
+        [n_src] and/or dipole vectors v [n_src, 3] (v = tau nu); returns
+        (u [n_out] or None, grad u [n_out, 3] or None).  numpy arrays run on
+        the host path, CUDA tensors on the device (asynchronous; call sync())."""
+        dev = (charge is not None and _is_torch(charge)) or (dipole is not None and _is_torch(dipole))
+        if dev:
+            import torch
+            d = (charge if charge is not None else dipole).device
+            q = None if charge is None else charge.contiguous()
+            v = None if dipole is None else dipole.contiguous()
+            if q is not None:
+                self._check_tensor(q, self.n, "charge")
+            if v is not None:
+                self._check_tensor(v, 3 * self.n, "dipole")
+            u = torch.empty(self.n_out, dtype=torch.complex128, device=d) if potential else None
+            g = torch.empty((self.n_out, 3), dtype=torch.complex128, device=d) if gradient else None
+            _check(lib().cfmm_eval_layer(self._handle, None if q is None else q.data_ptr(),
+                                         None if v is None else v.data_ptr(), None if u is None else u.data_ptr(),
+                                         None if g is None else g.data_ptr(), 1))
+            return u, g
+        q = None if charge is None else np.ascontiguousarray(charge, dtype=np.complex128).reshape(self.n)
+        v = None if dipole is None else np.ascontiguousarray(dipole, dtype=np.complex128).reshape(self.n, 3)
+        u = np.empty(self.n_out, dtype=np.complex128) if potential else None
+        g = np.empty((self.n_out, 3), dtype=np.complex128) if gradient else None
+        _check(lib().cfmm_eval_layer(self._handle, None if q is None else q.ctypes.data,
+                                     None if v is None else v.ctypes.data, None if u is None else u.ctypes.data,
+                                     None if g is None else g.ctypes.data, 0))
+        return u, g
 
     def eval_static(self, sigma):
         """Host evaluation staged through the library's static device buffer

@@ -132,6 +132,13 @@ struct cfmm_plan_s {
     int64_t* d_m2p_poff = nullptr;
     cplx* d_m2p_part = nullptr;
     int n_m2p3 = 0, m2p_pmax = 0;
+    std::vector<int64_t> m2p_poff_h;   // host copy of the List-3 part offsets
+    // layer potentials (3D Laplace, allocated on first use): dipoles in
+    // sorted SoA, far-field gradients, gradient M2P parts, host staging
+    double *d_dre = nullptr, *d_dim = nullptr;
+    cplx *d_gfar = nullptr, *d_m2p_part4 = nullptr;
+    int64_t* d_m2p_poff4 = nullptr;
+    double *d_lio_q = nullptr, *d_lio_v = nullptr, *d_lio_u = nullptr, *d_lio_g = nullptr;
     M2PParts m2p_parts() const { return M2PParts{n_m2p3, d_m2p_owner, d_m2p_poff, d_m2p_part}; }
     int64_t ecount = 0;
     int64_t info[20];
@@ -674,6 +681,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
                 p->m2p_pmax = std::max(p->m2p_pmax, p->P[t.level[t.idx[2][e]]]);
             }
         for (int e = 0; e < n3; ++e) poff[e + 1] += poff[e];
+        p->m2p_poff_h = poff;
         if ((rc = upload(p, &p->d_m2p_owner, owner)) || (rc = upload(p, &p->d_m2p_poff, poff)) ||
             (rc = p->alloc(&p->d_m2p_part, (size_t)std::max<int64_t>(1, poff[n3]))))
             return rc;
@@ -1035,6 +1043,84 @@ int cfmm_sync(cfmm_plan_t p)
 {
     if (!p) return fail(CFMM_EINVAL, "plan is NULL");
     return check_finite(p);
+}
+
+int cfmm_eval_layer(cfmm_plan_t p, const void* charge, const void* dipole, void* potential, void* gradient,
+                    int on_device)
+{
+    if (!p) return fail(CFMM_EINVAL, "plan is NULL");
+    if (!charge && !dipole) return fail(CFMM_EINVAL, "charge and dipole are both NULL");
+    if (!potential && !gradient) return fail(CFMM_EINVAL, "potential and gradient are both NULL");
+    if (!(p->dim == 3 && p->kernel == CFMM_LAPLACE))
+        return fail(CFMM_ENOTSUP, "layer potentials (dipoles, gradients) are implemented for dim 3 Laplace");
+    hipStream_t st = p->stream;
+    int64_t n = p->n;
+    int rc;
+    if (!p->d_dre) {
+        if ((rc = p->alloc(&p->d_dre, 3 * n)) || (rc = p->alloc(&p->d_dim, 3 * n)) ||
+            (rc = p->alloc(&p->d_gfar, 3 * n)))
+            return rc;
+        if (p->n_m2p3 > 0) {
+            std::vector<int64_t> p4(p->m2p_poff_h.size());
+            for (size_t k = 0; k < p4.size(); ++k) p4[k] = 4 * p->m2p_poff_h[k];
+            if ((rc = upload(p, &p->d_m2p_poff4, p4)) || (rc = p->alloc(&p->d_m2p_part4, std::max<int64_t>(1, p4.back()))))
+                return rc;
+        }
+    }
+    const double* q = (const double*)charge;
+    const double* v = (const double*)dipole;
+    double* u = (double*)potential;
+    double* g = (double*)gradient;
+    if (!on_device) {
+        if (!p->d_lio_q) {
+            if ((rc = p->alloc(&p->d_lio_q, 2 * p->n_src)) || (rc = p->alloc(&p->d_lio_v, 6 * p->n_src)) ||
+                (rc = p->alloc(&p->d_lio_u, 2 * p->n_out)) || (rc = p->alloc(&p->d_lio_g, 6 * p->n_out)))
+                return rc;
+        }
+        if (q) HIPCHK(hipMemcpyAsync(p->d_lio_q, q, 2 * p->n_src * sizeof(double), hipMemcpyHostToDevice, st));
+        if (v) HIPCHK(hipMemcpyAsync(p->d_lio_v, v, 6 * p->n_src * sizeof(double), hipMemcpyHostToDevice, st));
+        q = q ? p->d_lio_q : nullptr;
+        v = v ? p->d_lio_v : nullptr;
+        u = u ? p->d_lio_u : nullptr;
+        g = g ? p->d_lio_g : nullptr;
+    }
+    TreeView tv = p->view();
+    PointsView pv = p->pview();
+    const HostTree& t = p->tree;
+    int top = t.top, nlev = t.nlevels(), P = p->pmax;
+    const int* W = p->d_work;
+    if (q) HIPCHK(launch_gather_density(q, p->io(), n, p->d_sre, p->d_sim, st));
+    else {
+        HIPCHK(hipMemsetAsync(p->d_sre, 0, n * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(p->d_sim, 0, n * sizeof(double), st));
+    }
+    if (v) HIPCHK(launch_gather_dipole(v, p->io(), n, p->d_dre, p->d_dim, st));
+    if (v) HIPCHK(l3d_p2x_dip(W + p->off_p2m, p->n_p2m, P, 0, tv, pv, p->d_dre, p->d_dim, p->d_mpole, st));
+    else HIPCHK(l3d_p2m(W + p->off_p2m, p->n_p2m, P, tv, pv, p->d_mpole, st));
+    for (int l = nlev - 2; l >= top; --l) HIPCHK(l3d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], P, tv, p->d_mpole, st));
+    HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, p->l3_pp, 0, p->d_mpole,
+                   p->d_local, st));
+    if (v) HIPCHK(l3d_p2x_dip(W + p->off_p2l, p->n_p2l, P, 1, tv, pv, p->d_dre, p->d_dim, p->d_local, st));
+    else HIPCHK(l3d_p2l(W + p->off_p2l, p->n_p2l, P, tv, pv, p->d_local, st));
+    for (int l = top + 1; l < nlev; ++l) HIPCHK(l3d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], P, tv, p->d_local, st));
+    if (g) {
+        M2PParts m4{p->n_m2p3, p->d_m2p_owner, p->d_m2p_poff4, p->d_m2p_part4};
+        HIPCHK(l3d_leaf_far_grad(W + p->off_leaves, p->nleaf, top, tv, pv, p->d_mpole, p->d_local, m4, p->d_ufar,
+                                 p->d_gfar, st));
+    } else {
+        HIPCHK(l3d_leaf_far(W + p->off_leaves, p->nleaf, top, tv, pv, p->d_mpole, p->d_local, p->m2p_parts(),
+                            p->d_ufar, st));
+    }
+    HIPCHK(l3d_near_layer(W + p->off_leaves, p->nleaf, tv, pv, p->d_dre, p->d_dim, v != nullptr, p->d_ufar,
+                          p->d_gfar, p->io(), u, g, st));
+    if (!on_device) {
+        if (potential)
+            HIPCHK(hipMemcpyAsync(potential, p->d_lio_u, 2 * p->n_out * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (gradient)
+            HIPCHK(hipMemcpyAsync(gradient, p->d_lio_g, 6 * p->n_out * sizeof(double), hipMemcpyDeviceToHost, st));
+        return check_finite(p);
+    }
+    return CFMM_OK;
 }
 
 int cfmm_eval_static(cfmm_plan_t p, const void* density, void* potential)

@@ -167,6 +167,21 @@ hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& t
                         const PointsView& pv, const cplx* mpole, const cplx* local, const M2PParts& m2p,
                         cplx* ufar, hipStream_t st);
 size_t l3d_m2l_lds(int P, int ntab);
+// Layer potentials (3D Laplace): dipoles v in sorted SoA dre/dim [3][n];
+// P2M (irregular = 0) or P2L over List 4 (irregular = 1) with charges and
+// dipoles; L2P + M2P with gradients (m2p4: 4 complex per point per List-3
+// entry); the near field by target leaf, writing pot[n_out] and
+// grad[n_out][3] (either may be NULL) with the far field and 1/(4 pi).
+hipError_t l3d_p2x_dip(const int* boxes, int nb, int P, int irregular, const TreeView& tv, const PointsView& pv,
+                       const double* dre, const double* dim, cplx* out, hipStream_t st);
+hipError_t l3d_leaf_far_grad(const int* leaves, int nleaf, int top, const TreeView& tv, const PointsView& pv,
+                             const cplx* mpole, const cplx* local, const M2PParts& m2p4, cplx* ufar, cplx* gfar,
+                             hipStream_t st);
+hipError_t l3d_near_layer(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv, const double* dre,
+                          const double* dim, int has_dip, const cplx* ufar, const cplx* gfar, const IoMap& io,
+                          double* pot, double* grad, hipStream_t st);
+hipError_t launch_gather_dipole(const double* dip, const IoMap& io, int64_t n, double* dre, double* dim,
+                                hipStream_t st);
 int l3d_pmax_supported();
 
 // 3D Helmholtz evaluation (h3d_kernels.hip)

@@ -724,6 +724,391 @@ __global__ __launch_bounds__(64) void k_l3d_leaf_far(const int* __restrict__ lea
     }
 }
 
+// ------------------------------------------------- layer potentials (Sec. 2.1)
+// Dipole sources v_j = tau_j nu_j (the double layer) and gradients at the
+// targets (the normal derivatives S', D' follow by the target normal).  The
+// derivatives of the solid harmonics (checked against central differences):
+//   d_z R_n^m = R_{n-1}^m,   (d_x + i d_y) R_n^m = -R_{n-1}^{m+1},  (d_x - i d_y) R_n^m = R_{n-1}^{m-1}
+//   d_z I_n^m = -I_{n+1}^m,  (d_x + i d_y) I_n^m = -I_{n+1}^{m+1},  (d_x - i d_y) I_n^m = I_{n+1}^{m-1}
+// and v . grad = (v- (d_x + i d_y) + v+ (d_x - i d_y))/2 + v_z d_z with
+// v+- = v_x +- i v_y (bilinear: no conjugate).  Coordinates of a level are
+// scaled by 1/w, so each derivative in a physical coordinate carries 1/w.
+//
+// P2M / P2L with dipoles: thread (h, col) owns the column of order m of
+// (-1)^m X_n^{-m} (X = R for P2M, I for P2L) at the points h, h + H, ...;
+// each value c_n feeds four accumulators, all in the owner's column:
+//   acc[n]     += sigma c_n                 (charge, output (n, m))
+//   accZ[n']   += a_z  v_z c_n              (output (n', m))
+//   accP[n']   += a_pm v- c_n / 2           (output (n', m + 1))
+//   accM[n']   -= a_pm v+ c_n / 2           (output (n', m - 1))
+// with n' = n + 1, a_z = 1, a_pm = 1 for R (P2M) and n' = n - 1, a_z = -1,
+// a_pm = 1 for I (P2L), all over w; the output (n, m) adds acc and accZ of
+// its own column, accP of column m - 1 and accM of column m + 1.
+template <bool IRREGULAR>
+__global__ void k_l3d_p2x_dip(const int* __restrict__ boxes, TreeView tv, PointsView pv,
+                              const double* __restrict__ dre, const double* __restrict__ dim, int useL4,
+                              cplx* __restrict__ out)
+{
+    extern __shared__ cplx sh[];
+    int b = boxes[blockIdx.x];
+    int l = tv.level[b];
+    int P = tv.P[l];
+    int ncol = 2 * P + 1, H = blockDim.x / ncol;
+    int NR = P + 2;                                       // rows 0 .. P+1
+    double* pts = reinterpret_cast<double*>(sh);          // [14][kP2XChunk]
+    cplx* acc = sh + 7 * kP2XChunk;                       // [4][H][NR][ncol]
+    size_t AS = (size_t)H * NR * ncol;
+    double s = tv.rs[l];
+    int t = threadIdx.x, h = t / ncol, col = t % ncol;
+    int m = col - P, am = m < 0 ? -m : m;
+    bool act = h < H;
+    for (size_t i = t; i < 4 * AS; i += blockDim.x) acc[i] = mk(0.0, 0.0);
+    cplx c[3];
+    box_centre(tv, b, c);
+    double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
+    int e0 = useL4 ? tv.l4off[b] : 0, e1 = useL4 ? tv.l4off[b + 1] : 1;
+    int64_t n = pv.n;
+    int top = IRREGULAR ? P + 1 : P;                      // highest degree of the column
+    for (int e = e0; e < e1; ++e) {
+        int src = useL4 ? tv.l4idx[e] : b;
+        for (int j0 = tv.pbeg[src]; j0 < tv.pend[src]; j0 += kP2XChunk) {
+            int cnt = min(kP2XChunk, tv.pend[src] - j0);
+            __syncthreads();
+            if (t < cnt) {
+                int j = j0 + t;
+                for (int d = 0; d < 3; ++d) {
+                    pts[d * kP2XChunk + t] = (pv.xre[d * n + j] - c[d].re) * s;
+                    pts[(3 + d) * kP2XChunk + t] = (pv.xim[d * n + j] - c[d].im) * s;
+                    pts[(8 + d) * kP2XChunk + t] = dre[d * n + j] * s;       // v / w
+                    pts[(11 + d) * kP2XChunk + t] = dim[d * n + j] * s;
+                }
+                pts[6 * kP2XChunk + t] = pv.sre[j];
+                pts[7 * kP2XChunk + t] = pv.sim[j];
+            }
+            __syncthreads();
+            if (!act) continue;
+            cplx* a0 = acc + (size_t)h * NR * ncol + col;
+            cplx* aZ = a0 + AS;
+            cplx* aP = a0 + 2 * AS;
+            cplx* aM = a0 + 3 * AS;
+            for (int q = h; q < cnt; q += H) {
+                Vec3 y;
+                y.x = mk(pts[q], pts[3 * kP2XChunk + q]);
+                y.y = mk(pts[kP2XChunk + q], pts[4 * kP2XChunk + q]);
+                y.z = mk(pts[2 * kP2XChunk + q], pts[5 * kP2XChunk + q]);
+                cplx sig = mk(pts[6 * kP2XChunk + q], pts[7 * kP2XChunk + q]);
+                cplx vx = mk(pts[8 * kP2XChunk + q], pts[11 * kP2XChunk + q]);
+                cplx vy = mk(pts[9 * kP2XChunk + q], pts[12 * kP2XChunk + q]);
+                cplx vz = mk(pts[10 * kP2XChunk + q], pts[13 * kP2XChunk + q]);
+                cplx vm = mk(vx.re + vy.im, vx.im - vy.re) * 0.5;     // (v_x - i v_y) / 2
+                cplx vp = mk(vx.re - vy.im, vx.im + vy.re) * -0.5;    // -(v_x + i v_y) / 2
+                if (IRREGULAR) vz = -vz;
+                cplx w = m >= 0 ? wminus(y) : wplus(y);
+                cplx r2 = dot3(y);
+                auto feed = [&](int nn, cplx v) {
+                    if (nn <= P) a0[nn * ncol] += sig * v;
+                    int nd = IRREGULAR ? nn - 1 : nn + 1;
+                    if (nd >= 0 && nd <= P) {
+                        aZ[nd * ncol] += vz * v;
+                        aP[nd * ncol] += vm * v;
+                        aM[nd * ncol] += vp * v;
+                    }
+                };
+                if (!IRREGULAR) {
+                    cplx a = mk(sg, 0.0);
+                    for (int k = 1; k <= am; ++k) a = (a * w) * c_ldg[k];
+                    feed(am, a);
+                    if (am + 1 > top) continue;
+                    cplx bb = y.z * a;
+                    feed(am + 1, bb);
+                    for (int nn = am + 2; nn <= top; ++nn) {
+                        cplx cc = (c_lodd[nn] * (y.z * bb) - r2 * a) * c_lrr[nn * kLT + am];
+                        feed(nn, cc);
+                        a = bb;
+                        bb = cc;
+                    }
+                } else {
+                    cplx ir2 = cinv(r2), u = w * ir2, zi = y.z * ir2;
+                    cplx a = cinv(csqrt_p(r2)) * sg;
+                    for (int k = 1; k <= am; ++k) a = (a * u) * c_lodd[k];
+                    feed(am, a);
+                    if (am + 1 > top) continue;
+                    cplx bb = c_lodd[am + 1] * (zi * a);
+                    feed(am + 1, bb);
+                    for (int nn = am + 2; nn <= top; ++nn) {
+                        cplx cc = c_lodd[nn] * (zi * bb) - c_lka[nn * kLT + am] * (ir2 * a);
+                        feed(nn, cc);
+                        a = bb;
+                        bb = cc;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (h == 0) {
+        cplx* o = out + tv.eoff[b];
+        for (int nn = am; nn <= P; ++nn) {
+            cplx v = mk(0.0, 0.0);
+            for (int hh = 0; hh < H; ++hh) {
+                const cplx* base = acc + (size_t)hh * NR * ncol + nn * ncol;
+                v += base[col] + base[AS + col];
+                if (col > 0) v += base[2 * AS + col - 1];          // accP of order m - 1
+                if (col + 1 < ncol) v += base[3 * AS + col + 1];   // accM of order m + 1
+            }
+            if (useL4) o[nm(nn, m)] += v;
+            else o[nm(nn, m)] = v;
+        }
+    }
+}
+
+// sum_n C[nm(n, m)] R_n^m(x) and its gradient in x (scaled units): each
+// value R_n^m feeds u (C_n^m), d_z u (C_{n+1}^m), (d_x + i d_y) u
+// (-C_{n+1}^{m-1}) and (d_x - i d_y) u (C_{n+1}^{m+1}).
+__device__ inline void reg_sum_grad(const Vec3& x, int P, const cplx* __restrict__ C, cplx& u, cplx* g)
+{
+    cplx wp = wplus(x), wm = wminus(x), r2 = dot3(x), z = x.z;
+    cplx dp = mk(1.0, 0.0), dm = mk(1.0, 0.0);
+    cplx uz = mk(0.0, 0.0), up = mk(0.0, 0.0), um = mk(0.0, 0.0);
+    u = mk(0.0, 0.0);
+    auto feed = [&](int n, int m, cplx v) {
+        cfma(u, C[nm(n, m)], v);
+        if (n + 1 <= P) {
+            cfma(uz, C[nm(n + 1, m)], v);
+            cfma(up, -C[nm(n + 1, m - 1)], v);
+            cfma(um, C[nm(n + 1, m + 1)], v);
+        }
+    };
+    for (int m = 0; m <= P; ++m) {
+        if (m > 0) {
+            double f = c_ldg[m];
+            dp = (dp * wp) * f;
+            dm = (dm * wm) * f;
+        }
+        cplx ap = dp, am = (m & 1) ? -dm : dm;
+        feed(m, m, ap);
+        if (m > 0) feed(m, -m, am);
+        if (m + 1 > P) continue;
+        cplx bp = z * ap, bm = z * am;
+        feed(m + 1, m, bp);
+        if (m > 0) feed(m + 1, -m, bm);
+        for (int n = m + 2; n <= P; ++n) {
+            double o = c_lodd[n], f = c_lrr[n * kLT + m];
+            cplx cp = (o * (z * bp) - r2 * ap) * f;
+            cplx cm = (o * (z * bm) - r2 * am) * f;
+            feed(n, m, cp);
+            if (m > 0) feed(n, -m, cm);
+            ap = bp; bp = cp;
+            am = bm; bm = cm;
+        }
+    }
+    g[0] = (up + um) * 0.5;
+    g[1] = mk(0.5 * (up.im - um.im), -0.5 * (up.re - um.re));   // -(i/2)(up - um)
+    g[2] = uz;
+}
+
+// sum_n C[nm(n, m)] I_n^m(y) and its gradient (scaled units): each value
+// I_n^m, n <= P + 1, feeds u (C_n^m), d_z u (-C_{n-1}^m), (d_x + i d_y) u
+// (-C_{n-1}^{m-1}) and (d_x - i d_y) u (C_{n-1}^{m+1}).
+__device__ inline void irr_sum_grad(const Vec3& y, int P, const cplx* __restrict__ C, cplx& u, cplx* g)
+{
+    cplx r2 = dot3(y), ir2 = cinv(r2);
+    cplx upw = wplus(y) * ir2, umw = wminus(y) * ir2, zi = y.z * ir2;
+    cplx dp = cinv(csqrt_p(r2)), dm = dp;
+    cplx uz = mk(0.0, 0.0), up = mk(0.0, 0.0), um = mk(0.0, 0.0);
+    u = mk(0.0, 0.0);
+    int Q = P + 1;
+    auto coef = [&](int n, int m) -> cplx {
+        return (n >= 0 && n <= P && m >= -n && m <= n) ? C[nm(n, m)] : mk(0.0, 0.0);
+    };
+    auto feed = [&](int n, int m, cplx v) {
+        if (n <= P) cfma(u, C[nm(n, m)], v);
+        cfma(uz, -coef(n - 1, m), v);
+        cfma(up, -coef(n - 1, m - 1), v);
+        cfma(um, coef(n - 1, m + 1), v);
+    };
+    for (int m = 0; m <= Q; ++m) {
+        if (m > 0) {
+            double f = c_lodd[m];
+            dp = (dp * upw) * f;
+            dm = (dm * umw) * f;
+        }
+        cplx ap = dp, am = (m & 1) ? -dm : dm;
+        feed(m, m, ap);
+        if (m > 0) feed(m, -m, am);
+        if (m + 1 > Q) continue;
+        double o1 = c_lodd[m + 1];
+        cplx bp = o1 * (zi * ap), bm = o1 * (zi * am);
+        feed(m + 1, m, bp);
+        if (m > 0) feed(m + 1, -m, bm);
+        for (int n = m + 2; n <= Q; ++n) {
+            double o = c_lodd[n], k = c_lka[n * kLT + m];
+            cplx cp = o * (zi * bp) - k * (ir2 * ap);
+            cplx cm = o * (zi * bm) - k * (ir2 * am);
+            feed(n, m, cp);
+            if (m > 0) feed(n, -m, cm);
+            ap = bp; bp = cp;
+            am = bm; bm = cm;
+        }
+    }
+    g[0] = (up + um) * 0.5;
+    g[1] = mk(0.5 * (up.im - um.im), -0.5 * (up.re - um.re));
+    g[2] = uz;
+}
+
+// M2P with gradient by List-3 entries: 4 complex per point (u, grad).
+__global__ __launch_bounds__(64) void k_l3d_m2p_part_grad(const int* __restrict__ owner,
+                                                          const int64_t* __restrict__ poff4, TreeView tv,
+                                                          PointsView pv, const cplx* __restrict__ mpole,
+                                                          cplx* __restrict__ part)
+{
+    int e = blockIdx.x;
+    int b = owner[e], a = tv.l3idx[e];
+    int la = tv.level[a];
+    double sa = tv.rs[la];
+    cplx c[3];
+    box_centre(tv, a, c);
+    cplx* o = part + poff4[e];
+    int p0 = tv.pbeg[b];
+    for (int i = p0 + threadIdx.x; i < tv.pend[b]; i += blockDim.x) {
+        cplx u, g[3];
+        irr_sum_grad(point_rel(pv, i, c, sa), tv.P[la], mpole + tv.eoff[a], u, g);
+        cplx* oi = o + 4 * (i - p0);
+        oi[0] = sa * u;
+        for (int k = 0; k < 3; ++k) oi[1 + k] = (sa * sa) * g[k];
+    }
+}
+
+// L2P with gradient plus the List-3 parts: ufar[i] and gfar[3 i + k].
+__global__ __launch_bounds__(64) void k_l3d_leaf_far_grad(const int* __restrict__ leaves, int top, TreeView tv,
+                                                          PointsView pv, const cplx* __restrict__ local,
+                                                          const int64_t* __restrict__ poff4,
+                                                          const cplx* __restrict__ part, cplx* __restrict__ ufar,
+                                                          cplx* __restrict__ gfar)
+{
+    int b = leaves[blockIdx.x];
+    int l = tv.level[b];
+    int p0 = tv.pbeg[b];
+    for (int i = p0 + threadIdx.x; i < tv.pend[b]; i += blockDim.x) {
+        cplx u = mk(0.0, 0.0), g[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+        if (l >= top) {
+            int P = tv.P[l];
+            double s = tv.rs[l];
+            cplx c[3];
+            box_centre(tv, b, c);
+            reg_sum_grad(point_rel(pv, i, c, s), P, local + tv.eoff[b], u, g);
+            u = s * u;
+            for (int k = 0; k < 3; ++k) g[k] = (s * s) * g[k];
+            for (int e = tv.l3off[b]; e < tv.l3off[b + 1]; ++e) {
+                const cplx* pe = part + poff4[e] + 4 * (i - p0);
+                u += pe[0];
+                for (int k = 0; k < 3; ++k) g[k] += pe[1 + k];
+            }
+        }
+        ufar[i] = u;
+        for (int k = 0; k < 3; ++k) gfar[3 * (int64_t)i + k] = g[k];
+    }
+}
+
+// Near field of the layer potentials, by target leaf (owner computes; no
+// symmetric pairs: the dipole and gradient kernels are not symmetric).  Per
+// pair, d = x - y, r the principal root, 1/r from the reciprocal square root:
+//   u += sigma / r + (v.d) / r^3
+//   grad u += -sigma d / r^3 + v / r^3 - 3 (v.d) d / r^5
+// (times 1/(4 pi) in the final write, with the far field).
+__global__ __launch_bounds__(64) void k_l3d_near_layer(const int* __restrict__ leaves, TreeView tv, PointsView pv,
+                                                       const double* __restrict__ dre,
+                                                       const double* __restrict__ dim, int has_dip,
+                                                       const cplx* __restrict__ ufar,
+                                                       const cplx* __restrict__ gfar, IoMap io,
+                                                       double* __restrict__ pot, double* __restrict__ grad)
+{
+    __shared__ double sx[3][64], sxi[3][64], ssr[64], ssi[64], sv[3][64], svi[3][64];
+    int b = leaves[blockIdx.x];
+    int64_t n = pv.n;
+    int t = threadIdx.x;
+    int p0 = tv.pbeg[b], p1 = tv.pend[b];
+    const double k4 = 1.0 / (4.0 * kPi);
+    for (int i0 = p0; i0 < p1; i0 += 64) {
+        int i = i0 + t;
+        bool tok = i < p1;
+        double xr[3] = {0, 0, 0}, xi[3] = {0, 0, 0};
+        if (tok)
+            for (int d = 0; d < 3; ++d) { xr[d] = pv.xre[d * n + i]; xi[d] = pv.xim[d * n + i]; }
+        cplx u = mk(0.0, 0.0), g[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+        for (int e = tv.l1off[b]; e < tv.l1off[b + 1]; ++e) {
+            int a = tv.l1idx[e];
+            for (int j0 = tv.pbeg[a]; j0 < tv.pend[a]; j0 += 64) {
+                int cnt = min(64, tv.pend[a] - j0);
+                __syncthreads();
+                if (t < cnt) {
+                    int j = j0 + t;
+                    for (int d = 0; d < 3; ++d) {
+                        sx[d][t] = pv.xre[d * n + j];
+                        sxi[d][t] = pv.xim[d * n + j];
+                        sv[d][t] = has_dip ? dre[d * n + j] : 0.0;
+                        svi[d][t] = has_dip ? dim[d * n + j] : 0.0;
+                    }
+                    ssr[t] = pv.sre[j];
+                    ssi[t] = pv.sim[j];
+                }
+                __syncthreads();
+                if (!tok) continue;
+                for (int q = 0; q < cnt; ++q) {
+                    if (j0 + q == i) continue;
+                    cplx dd[3];
+                    cplx s2 = mk(0.0, 0.0);
+                    for (int d = 0; d < 3; ++d) {
+                        dd[d] = mk(xr[d] - sx[d][q], xi[d] - sxi[d][q]);
+                        s2 += dd[d] * dd[d];
+                    }
+                    if (s2.re == 0.0 && s2.im == 0.0) continue;
+                    cplx ir = cinv(csqrt_p(s2));
+                    cplx ir2 = ir * ir, ir3 = ir2 * ir;
+                    cplx sig = mk(ssr[q], ssi[q]);
+                    cplx v[3] = {mk(sv[0][q], svi[0][q]), mk(sv[1][q], svi[1][q]), mk(sv[2][q], svi[2][q])};
+                    cplx vd = v[0] * dd[0] + v[1] * dd[1] + v[2] * dd[2];
+                    u += sig * ir + vd * ir3;
+                    cplx a = sig * ir3 + 3.0 * (vd * ir3 * ir2);
+                    for (int d = 0; d < 3; ++d) g[d] += v[d] * ir3 - a * dd[d];
+                }
+            }
+        }
+        if (!tok) continue;
+        int64_t pidx = (int64_t)io.perm[i] - io.obase;
+        if (pidx < 0) continue;
+        u = (u + ufar[i]) * k4;
+        bool bad = false;
+        if (pot) {
+            pot[2 * pidx] = u.re;
+            pot[2 * pidx + 1] = u.im;
+            bad = !isfinite(u.re) || !isfinite(u.im);
+        }
+        if (grad)
+            for (int d = 0; d < 3; ++d) {
+                cplx gd = (g[d] + gfar[3 * (int64_t)i + d]) * k4;
+                bad = bad || !isfinite(gd.re) || !isfinite(gd.im);
+                grad[2 * (3 * pidx + d)] = gd.re;
+                grad[2 * (3 * pidx + d) + 1] = gd.im;
+            }
+        if (bad) atomicOr(io.nonfinite, 1);
+    }
+}
+
+// dipole vectors into sorted order, SoA [3][n] (zero at target-only points)
+__global__ void k_gather_dipole(const double* __restrict__ dip, IoMap io, int64_t n, double* __restrict__ dre,
+                                double* __restrict__ dim)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t p = io.perm[i];
+    bool src = dip && p < io.nsrc;
+    for (int d = 0; d < 3; ++d) {
+        dre[d * n + i] = src ? dip[2 * (3 * p + d)] : 0.0;
+        dim[d * n + i] = src ? dip[2 * (3 * p + d) + 1] : 0.0;
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 static size_t lds_bytes(int nelem) { return (size_t)nelem * sizeof(cplx); }
 
@@ -882,6 +1267,64 @@ int l3d_pmax_supported()
     int P = 31;
     while (P > 1 && (l3d_m2l_layout(P).R > 5 || l3d_m2l_lds(P, l3d_m2l_layout(P).entries) > (size_t)lds)) --P;
     return P;
+}
+
+static size_t p2x_dip_lds(int P, int threads)
+{
+    int ncol = 2 * P + 1, H = threads / ncol;
+    return lds_bytes(7 * kP2XChunk + 4 * (size_t)H * (P + 2) * ncol);
+}
+
+static int p2x_dip_threads(int P)
+{
+    int ncol = 2 * P + 1;
+    return ((ncol + 63) / 64) * 64;      // one point stream per 64-lane multiple
+}
+
+hipError_t l3d_p2x_dip(const int* boxes, int nb, int P, int irregular, const TreeView& tv, const PointsView& pv,
+                       const double* dre, const double* dim, cplx* out, hipStream_t st)
+{
+    if (nb <= 0) return hipSuccess;
+    int th = p2x_dip_threads(P);
+    size_t lds = p2x_dip_lds(P, th);
+    const void* f = irregular ? (const void*)k_l3d_p2x_dip<true> : (const void*)k_l3d_p2x_dip<false>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    if (irregular) k_l3d_p2x_dip<true><<<nb, th, lds, st>>>(boxes, tv, pv, dre, dim, 1, out);
+    else k_l3d_p2x_dip<false><<<nb, th, lds, st>>>(boxes, tv, pv, dre, dim, 0, out);
+    return hipGetLastError();
+}
+
+hipError_t l3d_leaf_far_grad(const int* leaves, int nleaf, int top, const TreeView& tv, const PointsView& pv,
+                             const cplx* mpole, const cplx* local, const M2PParts& m2p4, cplx* ufar, cplx* gfar,
+                             hipStream_t st)
+{
+    if (nleaf <= 0) return hipSuccess;
+    if (m2p4.n > 0) {
+        k_l3d_m2p_part_grad<<<m2p4.n, 64, 0, st>>>(m2p4.owner, m2p4.poff, tv, pv, mpole, m2p4.part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_l3d_leaf_far_grad<<<nleaf, 64, 0, st>>>(leaves, top, tv, pv, local, m2p4.poff, m2p4.part, ufar, gfar);
+    return hipGetLastError();
+}
+
+hipError_t l3d_near_layer(const int* leaves, int nleaf, const TreeView& tv, const PointsView& pv, const double* dre,
+                          const double* dim, int has_dip, const cplx* ufar, const cplx* gfar, const IoMap& io,
+                          double* pot, double* grad, hipStream_t st)
+{
+    if (nleaf <= 0) return hipSuccess;
+    k_l3d_near_layer<<<nleaf, 64, 0, st>>>(leaves, tv, pv, dre, dim, has_dip, ufar, gfar, io, pot, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_dipole(const double* dip, const IoMap& io, int64_t n, double* dre, double* dim,
+                                hipStream_t st)
+{
+    k_gather_dipole<<<(int)((n + 255) / 256), 256, 0, st>>>(dip, io, n, dre, dim);
+    return hipGetLastError();
 }
 
 }  // namespace cfmm
