@@ -107,6 +107,8 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration for HBM traffic)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving block")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision block")
+    ap.add_argument("--no-cpu-fmm", action="store_true", help="skip the CPU FMM reference")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-nmax-log2", type=float, default=16.0)
     return ap.parse_args()
@@ -196,6 +198,26 @@ def main():
 
     u_gpu = out.cpu().numpy()
     sig_last = sigs[(a.steps - 1) % nsig].cpu().numpy()
+
+    # the same workload through the mixed-precision path (tol >= 1e-6 only),
+    # timed the same way, for the north-star's second precision form
+    mixed = None
+    if a.precision == "fp64" and not a.no_mixed and tol >= 1e-6 and dim == 3:
+        mplan = cf.Plan(pts, kern, cfg.kappa, tol, precision="mixed", leaf_size=a.leaf,
+                        stream=stream.cuda_stream)
+        for w in range(a.warmup):
+            mplan.eval_into(sigs[w % nsig], out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_ in range(a.steps):
+            mplan.eval_into(sigs[s_ % nsig], out)
+        torch.cuda.synchronize()
+        mdt = (time.perf_counter() - t0) * 1e3 / a.steps
+        mplan.eval_into(sigs[(a.steps - 1) % nsig], out)
+        torch.cuda.synchronize()
+        mixed = {"ms_per_step": mdt, "value": pairs / (mdt * 1e-3), "dtype": "f32+f64",
+                 "u": out.cpu().numpy()}
+        del mplan
     nw = plan.near_work()
     p2p_flops = (p2p_flops_unit - MAC_FLOPS) * nw["evaluations"] + MAC_FLOPS * nw["interactions"]
     peak = PEAK_FP64_VALU if a.precision == "fp64" else PEAK_FP32_VALU
@@ -284,6 +306,22 @@ def main():
         res["config"]["rel_err_paper_sampled"] = float(np.linalg.norm(u_gpu[ct] - u0) /
                                                        (np.linalg.norm(u0) + np.linalg.norm(sig_last[ct])))
         res["config"]["err_targets"] = int(len(ct))
+        if mixed is not None:
+            mixed["rel_l2_err_sampled"] = oracle.rel_l2(mixed["u"][ct], u0)
+        if a.workload == "c2" and not a.no_cpu_fmm:
+            # the CPU FMM reference: the same method and tolerance on the host's
+            # cores, on the whole workload (one evaluation, after its plan)
+            import cpu_ref
+            uc, (cplan, ceval) = cpu_ref.fmm3d_laplace(cfg.points, sig_last, tol, leaf_size=info["leaf_size"],
+                                                       sep=info["separation"], nthreads=cores)
+            res["cpu_fmm"] = {
+                "value": pairs / ceval, "unit": "interactions/s", "cores": cores, "kind": "cpu FMM reference",
+                "eval_s": ceval, "plan_s": cplan, "rel_l2_err_sampled": oracle.rel_l2(uc[ct], u0),
+                "sample": f"the whole workload, N={n}, tol={tol}, one evaluation",
+            }
+    if mixed is not None:
+        mixed.pop("u")
+        res["mixed_precision"] = mixed
     if not a.no_serve:
         del plan, sigs, out, pts
         torch.cuda.synchronize()
