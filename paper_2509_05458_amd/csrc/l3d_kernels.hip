@@ -366,6 +366,10 @@ __global__ __launch_bounds__(256) void k_l3d_m2m(const int* __restrict__ boxes, 
 // FP64 table, 2 with the FP32 table of half the size).
 constexpr int kM2LWaves = 4;
 constexpr int kM2LWavesF32 = 2;
+// steps per unrolled chunk of a contraction row, and the zeroed table entries
+// after the table that the last chunk of the last row may read
+constexpr int kM2LChunk = 6;
+constexpr int kM2LPad = 8;
 
 // first and last row n of the steps [s0, s1) in n^2 + n + m order
 __device__ inline int step_row(int s)
@@ -402,7 +406,7 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
     int P = tv.P[l];
     int nc = (P + 1) * (P + 1);
     cplx* tab = reinterpret_cast<cplx*>(tab16);
-    int* base = reinterpret_cast<int*>(tab16 + ntab);
+    int* base = reinterpret_cast<int*>(tab16 + ntab + kM2LPad);
     double s = tv.rs[l];
     int t = threadIdx.x, lane = t & 63;
     int W = blockDim.x >> 6;
@@ -419,7 +423,7 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = mk(0.0, 0.0);
     }
-    for (int i = t; i < ntab; i += blockDim.x) tab[i] = mk(0.0, 0.0);
+    for (int i = t; i < ntab + kM2LPad; i += blockDim.x) tab[i] = mk(0.0, 0.0);
     for (int i = t; i <= 2 * P; i += blockDim.x) base[i] = map[i];
     cplx cb[3];
     box_centre(tv, b, cb);
@@ -456,20 +460,28 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
                 w2[r] = row[r][mlo - 2];
                 w3[r] = row[r][mlo - 3];
             }
-#pragma unroll 6
-            for (int m = mlo; m <= mhi; ++m) {
-                cplx16 mv = Mn[m];
-                cplx am = mk(mv.re, mv.im);
+            // whole chunks of kM2LChunk steps: the steps past the row's end
+            // take a zero coefficient (and read finite table entries, or the
+            // zeroed pad after the table), so no remainder loop waits on
+            // single LDS reads
+            for (int m0 = mlo; m0 <= mhi; m0 += kM2LChunk) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    cplx16 w0 = row[r][m];
-                    cfma(acc[r][0], am, mk(w0.re, w0.im));
-                    cfma(acc[r][1], am, mk(w1[r].re, w1[r].im));
-                    cfma(acc[r][2], am, mk(w2[r].re, w2[r].im));
-                    cfma(acc[r][3], am, mk(w3[r].re, w3[r].im));
-                    w3[r] = w2[r];
-                    w2[r] = w1[r];
-                    w1[r] = w0;
+                for (int u = 0; u < kM2LChunk; ++u) {
+                    int m = m0 + u;
+                    bool on = m <= mhi;
+                    cplx16 mv = Mn[on ? m : mhi];
+                    cplx am = on ? mk(mv.re, mv.im) : mk(0.0, 0.0);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        cplx16 w0 = row[r][m];
+                        cfma(acc[r][0], am, mk(w0.re, w0.im));
+                        cfma(acc[r][1], am, mk(w1[r].re, w1[r].im));
+                        cfma(acc[r][2], am, mk(w2[r].re, w2[r].im));
+                        cfma(acc[r][3], am, mk(w3[r].re, w3[r].im));
+                        w3[r] = w2[r];
+                        w2[r] = w1[r];
+                        w1[r] = w0;
+                    }
                 }
             }
         }
@@ -523,7 +535,7 @@ __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __
     int l = tv.level[b];
     int P = tv.P[l];
     int nc = (P + 1) * (P + 1);
-    float2* Ms = tabf + ntab;
+    float2* Ms = tabf + ntab + kM2LPad;
     int* base = reinterpret_cast<int*>(Ms + nc);
     double s = tv.rs[l];
     int t = threadIdx.x, lane = t & 63;
@@ -541,7 +553,7 @@ __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = mk(0.0, 0.0);
     }
-    for (int i = t; i < ntab; i += blockDim.x) tabf[i] = make_float2(0.0f, 0.0f);
+    for (int i = t; i < ntab + kM2LPad; i += blockDim.x) tabf[i] = make_float2(0.0f, 0.0f);
     for (int i = t; i <= 2 * P; i += blockDim.x) base[i] = map[i];
     cplx cb[3];
     box_centre(tv, b, cb);
@@ -1189,7 +1201,7 @@ static int m2l_groups_per_lane(int P)
 
 size_t l3d_m2l_lds(int P, int ntab)
 {
-    size_t tab = (size_t)ntab * sizeof(cplx) + (size_t)(2 * P + 1) * sizeof(int);
+    size_t tab = (size_t)(ntab + kM2LPad) * sizeof(cplx) + (size_t)(2 * P + 1) * sizeof(int);
     return std::max(tab, m2l_red_bytes(m2l_groups_per_lane(P), kM2LWaves));
 }
 
@@ -1211,7 +1223,8 @@ hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const in
 {
     if (nb <= 0) return hipSuccess;
     if (mixed && P <= kM2LF32MaxP) {
-        size_t lds = std::max((size_t)(ntab + (P + 1) * (P + 1)) * sizeof(float2) + (size_t)(2 * P + 1) * sizeof(int),
+        size_t lds = std::max((size_t)(ntab + kM2LPad + (P + 1) * (P + 1)) * sizeof(float2) +
+                                  (size_t)(2 * P + 1) * sizeof(int),
                               m2l_red_bytes(R, kM2LWavesF32));
         switch (R) {
         case 1: return launch_m2l_f32<1>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
