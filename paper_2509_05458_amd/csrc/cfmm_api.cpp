@@ -125,6 +125,9 @@ struct cfmm_plan_s {
     int64_t h3_eq_half = 0;
     // 3D Laplace M2L: table row bases and lane slots (l3d_layout.hpp)
     int* d_l3map = nullptr;
+    cplx* d_l3pc = nullptr;       // 3D Laplace M2L: table constants per List-2 entry (5 complex)
+    int* d_l3ps = nullptr;        // and source expansion length per entry
+    L3Pairs l3_pairs() const { return L3Pairs{d_l3pc, d_l3ps}; }
     int l3_ntab = 0, l3_R = 0;
     L3PairP l3_pp{};              // source expansion length per M2L pair distance
     // 3D M2P by List-3 entries: owner leaf, partial-sum offsets and storage
@@ -881,6 +884,13 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     }  // h2d operator tables
     if (dim == 3 && p->kernel == CFMM_HELMHOLTZ)
         if ((rc = plan_h3d(p, nlev, top))) return rc;
+    if (dim == 3 && p->kernel == CFMM_LAPLACE) {
+        // M2L pair constants: fixed by the geometry, formed once per plan
+        size_t nl2 = std::max<size_t>(t.idx[1].size(), 1);
+        if ((rc = p->alloc(&p->d_l3pc, 5 * nl2)) || (rc = p->alloc(&p->d_l3ps, nl2))) return rc;
+        TreeView tv = p->view();
+        HIPCHK(l3d_m2l_pairs(p->d_work + p->off_m2l, p->n_m2l, tv, p->l3_pp, p->d_l3pc, p->d_l3ps, st));
+    }
     // -------- geometry check on the near pairs
     int* d_flag = nullptr;
     if ((rc = p->alloc(&d_flag, 1))) return rc;
@@ -1098,8 +1108,8 @@ int cfmm_eval_layer(cfmm_plan_t p, const void* charge, const void* dipole, void*
     if (v) HIPCHK(l3d_p2x_dip(W + p->off_p2m, p->n_p2m, P, 0, tv, pv, p->d_dre, p->d_dim, p->d_mpole, st));
     else HIPCHK(l3d_p2m(W + p->off_p2m, p->n_p2m, P, tv, pv, p->d_mpole, st));
     for (int l = nlev - 2; l >= top; --l) HIPCHK(l3d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], P, tv, p->d_mpole, st));
-    HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, p->l3_pp, 0, p->d_mpole,
-                   p->d_local, st));
+    HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, p->l3_pairs(), 0,
+                   p->d_mpole, p->d_local, st));
     if (v) HIPCHK(l3d_p2x_dip(W + p->off_p2l, p->n_p2l, P, 1, tv, pv, p->d_dre, p->d_dim, p->d_local, st));
     else HIPCHK(l3d_p2l(W + p->off_p2l, p->n_p2l, P, tv, pv, p->d_local, st));
     for (int l = top + 1; l < nlev; ++l) HIPCHK(l3d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], P, tv, p->d_local, st));
@@ -1328,7 +1338,7 @@ int eval_on_device(cfmm_plan_s* p, const double* sig, double* out)
         // below the requested accuracy
         int m2l32 = p->precision == CFMM_MIXED && p->tol >= 1e-6;
         HIPCHK(mark(8));
-        HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, p->l3_pp, m2l32,
+        HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, p->l3_pairs(), m2l32,
                        p->d_mpole, p->d_local, st));
         HIPCHK(mark(9));
         HIPCHK(l3d_p2l(W + p->off_p2l, p->n_p2l, P, tv, pv, p->d_local, st));

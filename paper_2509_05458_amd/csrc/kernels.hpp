@@ -160,8 +160,16 @@ hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mp
 struct L3PairP {
     int p[8];
 };
+// The table constants of every List-2 pair of the boxes (5 complex per entry)
+// and its source expansion length, formed once per plan.
+struct L3Pairs {
+    const cplx* c;         // [5 * n_list2]
+    const int* ps;         // [n_list2]
+};
+hipError_t l3d_m2l_pairs(const int* boxes, int nb, const TreeView& tv, const L3PairP& pp, cplx* c, int* ps,
+                         hipStream_t st);
 hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const int* map, int ntab, int R,
-                   const L3PairP& pp, int mixed, const cplx* mpole, cplx* local, hipStream_t st);
+                   const L3Pairs& pr, int mixed, const cplx* mpole, cplx* local, hipStream_t st);
 hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st);
 hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& tv,
                         const PointsView& pv, const cplx* mpole, const cplx* local, const M2PParts& m2p,

@@ -108,6 +108,45 @@ __device__ inline void col_I(const Vec3& v, int m, int P, bool flip, F f)
     }
 }
 
+// The M2L table of one pair: I_l^q(v) for l = 0..Lt in this lane's order q
+// (|q| <= Lt), passed to st(i, value) with i = base(l) + q in the table layout
+// (rows packed in order of l, q = 0 of row l at a multiple of 16 entries and
+// three guard entries below q = -l; the row bases are formed here in scalar
+// registers, so no load sits on the chain).  The pair enters through its
+// constants 1/r2, 1/rho, z/r2 and w/r2 (w = w+ for q >= 0, w- below; formed
+// once per plan by k_l3d_m2l_pairs).  Every lane runs the same loop over l:
+// steps l <= |q| climb the diagonal I_l^l, the steps past it the three-term
+// recurrence in l, both of the form
+//   next = (2l - 1) (u cur) - beta_l (prev / r2),  u = w / r2 or z / r2,
+// where beta_l = max((l-1)^2 - q^2, 0) is (l+|q|-1)(l-|q|-1) past the
+// diagonal and zero up to l = |q| + 1; so the wavefront never diverges, and a
+// lane stores row l once l >= |q|.
+template <class F>
+__device__ inline void table_I(cplx ir2, cplx cur, cplx zi, cplx wi, int q, int Lt, F st)
+{
+    int aq = q < 0 ? -q : q;
+    if (q < 0 && (aq & 1)) cur = -cur;
+    cplx prev = mk(0.0, 0.0);
+    int end = 3;                                 // one past the last entry of the previous row
+    int rb = (end + 3 + 15) & ~15;               // base of row 0
+    end = rb + 1;
+    if (aq == 0) st(rb, cur);
+    double c1 = 1.0, c2 = -(double)aq * (double)aq;
+    for (int l = 1; l <= Lt; ++l) {
+        cplx u = l <= aq ? wi : zi;
+        double b2 = fmax(c2, 0.0);
+        cplx x = u * cur, y = ir2 * prev;
+        cplx c = mk(fma(c1, x.re, -b2 * y.re), fma(c1, x.im, -b2 * y.im));
+        prev = cur;
+        cur = c;
+        rb = (end + l + 3 + 15) & ~15;
+        end = rb + l + 1;
+        if (l >= aq) st(rb + q, cur);
+        c2 += c1;
+        c1 += 2.0;
+    }
+}
+
 // Recurrence constants, n, m <= 31: 1/((n+m)(n-m)) for m < n, 1/(2m), 2n-1 and
 // (n+m-1)(n-m-1).
 constexpr int kLT = 32;
@@ -394,9 +433,38 @@ __device__ inline int pair_terms(const L3PairP& pp, const cplx* cb, const cplx* 
     return pp.p[d < 7 ? d : 7];
 }
 
+// Per List-2 pair (entry e of the target box's list), once per plan: the
+// constants of its table, c[5e..5e+4] = 1/r2, 1/rho, z/r2, w+/r2, w-/r2 at the
+// scaled offset D / w = (c_target - c_source) / w, and its source expansion
+// length ps[e].
+__global__ __launch_bounds__(64) void k_l3d_m2l_pairs(const int* __restrict__ boxes, TreeView tv, L3PairP pp,
+                                                      cplx* __restrict__ c, int* __restrict__ ps)
+{
+    int b = boxes[blockIdx.x];
+    double s = tv.rs[tv.level[b]];
+    cplx cb[3];
+    box_centre(tv, b, cb);
+    for (int e = tv.l2off[b] + (int)threadIdx.x; e < tv.l2off[b + 1]; e += blockDim.x) {
+        int a = tv.l2idx[e];
+        cplx ca[3];
+        box_centre(tv, a, ca);
+        Vec3 d;
+        d.x = (cb[0] - ca[0]) * s; d.y = (cb[1] - ca[1]) * s; d.z = (cb[2] - ca[2]) * s;
+        cplx r2 = dot3(d);
+        cplx ir2 = cinv(r2);
+        c[5 * (size_t)e + 0] = ir2;
+        c[5 * (size_t)e + 1] = cinv(csqrt_p(r2));
+        c[5 * (size_t)e + 2] = d.z * ir2;
+        c[5 * (size_t)e + 3] = wplus(d) * ir2;
+        c[5 * (size_t)e + 4] = wminus(d) * ir2;
+        ps[e] = pair_terms(pp, cb, ca, s);
+    }
+}
+
 template <int R>
 __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restrict__ boxes, int nboxes, TreeView tv,
-                                                 const int* __restrict__ map, int ntab, L3PairP pp,
+                                                 const int* __restrict__ map, int ntab,
+                                                 const cplx* __restrict__ pc, const int* __restrict__ pps,
                                                  const cplx* __restrict__ mpole,
                                                  cplx* __restrict__ local)
 {
@@ -430,20 +498,17 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
     for (int e = tv.l2off[b]; e < tv.l2off[b + 1]; ++e) {
         int a = tv.l2idx[e];
         const cplx* M = mpole + tv.eoff[a];
-        cplx ca[3];
-        box_centre(tv, a, ca);
         // source orders n <= Ps of this pair: rows l = j + n <= P + Ps of the
         // table, and (Ps+1)^2 steps split over the W wavefronts
-        int Ps = __builtin_amdgcn_readfirstlane(pair_terms(pp, cb, ca, s));
+        int Ps = pps[e];
         int Lt = P + Ps, ncp = (Ps + 1) * (Ps + 1);
         int s0 = ncp * wv / W, s1 = ncp * (wv + 1) / W;   // this wavefront's steps
         int na = step_row(s0), nb = s1 > s0 ? step_row(s1 - 1) : na - 1;
         __syncthreads();
         if (t <= 4 * P && abs(t - 2 * P) <= Lt) {
-            Vec3 d;
-            d.x = (cb[0] - ca[0]) * s; d.y = (cb[1] - ca[1]) * s; d.z = (cb[2] - ca[2]) * s;
             int q = t - 2 * P;
-            col_I(d, q, Lt, false, [&](int n, cplx v) { tab[base[n] + q] = v; });
+            const cplx* k = pc + 5 * (size_t)e;
+            table_I(k[0], k[1], k[2], q < 0 ? k[4] : k[3], q, Lt, [&](int i, cplx v) { tab[i] = v; });
         }
         __syncthreads();
         for (int n = na; n <= nb; ++n) {
@@ -526,7 +591,8 @@ constexpr int kM2LF32MaxP = 16;
 
 template <int R>
 __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __restrict__ boxes, int nboxes, TreeView tv,
-                                                     const int* __restrict__ map, int ntab, L3PairP pp,
+                                                     const int* __restrict__ map, int ntab,
+                                                     const cplx* __restrict__ pc, const int* __restrict__ pps,
                                                      const cplx* __restrict__ mpole,
                                                      cplx* __restrict__ local)
 {
@@ -560,20 +626,17 @@ __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __
     for (int e = tv.l2off[b]; e < tv.l2off[b + 1]; ++e) {
         int a = tv.l2idx[e];
         const cplx* M = mpole + tv.eoff[a];
-        cplx ca[3];
-        box_centre(tv, a, ca);
-        int Ps = __builtin_amdgcn_readfirstlane(pair_terms(pp, cb, ca, s));
+        int Ps = pps[e];
         int Lt = P + Ps, ncp = (Ps + 1) * (Ps + 1);
         int s0 = ncp * wv / W, s1 = ncp * (wv + 1) / W;   // this wavefront's steps
         int na = step_row(s0), nb = s1 > s0 ? step_row(s1 - 1) : na - 1;
         __syncthreads();
         for (int i = t; i < ncp; i += blockDim.x) Ms[i] = make_float2((float)M[i].re, (float)M[i].im);
         if (t <= 4 * P && abs(t - 2 * P) <= Lt) {
-            Vec3 d;
-            d.x = (cb[0] - ca[0]) * s; d.y = (cb[1] - ca[1]) * s; d.z = (cb[2] - ca[2]) * s;
             int q = t - 2 * P;
-            col_I(d, q, Lt, false,
-                  [&](int n, cplx v) { tabf[base[n] + q] = make_float2((float)v.re, (float)v.im); });
+            const cplx* k = pc + 5 * (size_t)e;
+            table_I(k[0], k[1], k[2], q < 0 ? k[4] : k[3], q, Lt,
+                    [&](int i, cplx v) { tabf[i] = make_float2((float)v.re, (float)v.im); });
         }
         __syncthreads();
         for (int n = na; n <= nb; ++n) {
@@ -1174,14 +1237,14 @@ hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mp
 
 template <int R>
 static hipError_t launch_m2l(const int* boxes, int nb, size_t lds, const TreeView& tv, const int* map, int ntab,
-                             const L3PairP& pp, const cplx* mpole, cplx* local, hipStream_t st)
+                             const L3Pairs& pr, const cplx* mpole, cplx* local, hipStream_t st)
 {
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_l3d_m2l<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_l3d_m2l<R><<<nb, 64 * kM2LWaves, lds, st>>>(boxes, nb, tv, map, ntab, pp, mpole, local);
+    k_l3d_m2l<R><<<nb, 64 * kM2LWaves, lds, st>>>(boxes, nb, tv, map, ntab, pr.c, pr.ps, mpole, local);
     return hipGetLastError();
 }
 
@@ -1207,19 +1270,27 @@ size_t l3d_m2l_lds(int P, int ntab)
 
 template <int R>
 static hipError_t launch_m2l_f32(const int* boxes, int nb, size_t lds, const TreeView& tv, const int* map,
-                                 int ntab, const L3PairP& pp, const cplx* mpole, cplx* local, hipStream_t st)
+                                 int ntab, const L3Pairs& pr, const cplx* mpole, cplx* local, hipStream_t st)
 {
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_l3d_m2l_f32<R>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_l3d_m2l_f32<R><<<nb, 64 * kM2LWavesF32, lds, st>>>(boxes, nb, tv, map, ntab, pp, mpole, local);
+    k_l3d_m2l_f32<R><<<nb, 64 * kM2LWavesF32, lds, st>>>(boxes, nb, tv, map, ntab, pr.c, pr.ps, mpole, local);
+    return hipGetLastError();
+}
+
+hipError_t l3d_m2l_pairs(const int* boxes, int nb, const TreeView& tv, const L3PairP& pp, cplx* c, int* ps,
+                         hipStream_t st)
+{
+    if (nb <= 0) return hipSuccess;
+    k_l3d_m2l_pairs<<<nb, 64, 0, st>>>(boxes, tv, pp, c, ps);
     return hipGetLastError();
 }
 
 hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const int* map, int ntab, int R,
-                   const L3PairP& pp, int mixed, const cplx* mpole, cplx* local, hipStream_t st)
+                   const L3Pairs& pr, int mixed, const cplx* mpole, cplx* local, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
     if (mixed && P <= kM2LF32MaxP) {
@@ -1227,18 +1298,18 @@ hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const in
                                   (size_t)(2 * P + 1) * sizeof(int),
                               m2l_red_bytes(R, kM2LWavesF32));
         switch (R) {
-        case 1: return launch_m2l_f32<1>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
-        case 2: return launch_m2l_f32<2>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
+        case 1: return launch_m2l_f32<1>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
+        case 2: return launch_m2l_f32<2>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
         default: return hipErrorInvalidValue;
         }
     }
     size_t lds = l3d_m2l_lds(P, ntab);
     switch (R) {
-    case 1: return launch_m2l<1>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
-    case 2: return launch_m2l<2>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
-    case 3: return launch_m2l<3>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
-    case 4: return launch_m2l<4>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
-    case 5: return launch_m2l<5>(boxes, nb, lds, tv, map, ntab, pp, mpole, local, st);
+    case 1: return launch_m2l<1>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
+    case 2: return launch_m2l<2>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
+    case 3: return launch_m2l<3>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
+    case 4: return launch_m2l<4>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
+    case 5: return launch_m2l<5>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
     default: return hipErrorInvalidValue;
     }
 }
