@@ -1168,8 +1168,9 @@ int check_finite(cfmm_plan_s* p)
     int zero = 0;
     HIPCHK(hipMemcpyAsync(p->d_flag_nf, &zero, sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
-    return fail(CFMM_ERANGE, "an evaluation wrote a non-finite potential (inf or NaN); "
-                             "are the densities finite?");
+    return fail(CFMM_ERANGE, "an evaluation wrote a non-finite potential (inf or NaN): the densities are "
+                             "not finite, or the growth e^{kappa |Im r|} of the complexified kernel "
+                             "exceeds the FP64 range");
 }
 
 // Steps 1-8 of Sec. 6.4 on the plan's stream, densities sig[n_src] and

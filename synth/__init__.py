@@ -37,14 +37,29 @@ def psi(t):
     return 0.5 * np.logaddexp(0.0, np.abs(t) - 4.0)
 
 
-def curve2d(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
-    """n points on the complexified 2D curve, complex128[n, 2]."""
+def curve2d(n: int, seed: int, scale: float = 1.0, amp: float = 1.0) -> np.ndarray:
+    """n points on the complexified 2D curve, complex128[n, 2]; amp scales the
+    imaginary part (Lipschitz constant 0.5 amp)."""
     rng = np.random.default_rng(seed)
     t = rng.uniform(-8.0, 8.0, size=n)
     x = np.empty((n, 2), dtype=np.complex128)
-    x[:, 0] = t + 1j * psi(t)
+    x[:, 0] = t + 1j * amp * psi(t)
     x[:, 1] = 0.2 * np.exp(-t * t)
     return x * scale
+
+
+def curve2d_literal(n: int, seed: int, kappa: float, ppw: float = 10.0) -> np.ndarray:
+    """The curve family with t ~ U[-L, L] sized for ppw points per wavelength
+    (2L = n lambda / ppw): the literal large-N recipe, whose imaginary parts
+    reach 0.5 (L - 4), far beyond what e^{kappa Im r} allows in FP64."""
+    lam = 2.0 * math.pi / kappa
+    L = n * lam / (2.0 * ppw)
+    rng = np.random.default_rng(seed)
+    t = rng.uniform(-L, L, size=n)
+    x = np.empty((n, 2), dtype=np.complex128)
+    x[:, 0] = t + 1j * psi(t)
+    x[:, 1] = 0.2 * np.exp(-t * t)
+    return x
 
 
 def plane3d_grid(m: int, lo: float = -6.0, hi: float = 6.0) -> np.ndarray:
@@ -61,8 +76,9 @@ def plane3d_grid(m: int, lo: float = -6.0, hi: float = 6.0) -> np.ndarray:
 
 
 def plane3d_bumps(m: int, seed: int, lo: float = -6.0, hi: float = 6.0,
-                  nbumps: int = 8, scale: float = 1.0) -> np.ndarray:
-    """m*m grid on the complexified plane, height = sum of nbumps seeded Gaussians."""
+                  nbumps: int = 8, scale: float = 1.0, amp: float = 1.0) -> np.ndarray:
+    """m*m grid on the complexified plane, height = sum of nbumps seeded Gaussians;
+    amp scales the imaginary parts."""
     rng = np.random.default_rng(seed)
     c = rng.uniform(-4.0, 4.0, size=(nbumps, 2))
     w = rng.uniform(0.5, 2.0, size=nbumps)
@@ -74,8 +90,8 @@ def plane3d_bumps(m: int, seed: int, lo: float = -6.0, hi: float = 6.0,
     for b in range(nbumps):
         h += 0.3 * np.exp(-((s - c[b, 0]) ** 2 + (t - c[b, 1]) ** 2) / (w[b] ** 2))
     x = np.empty((s.size, 3), dtype=np.complex128)
-    x[:, 0] = s + 1j * psi(s)
-    x[:, 1] = t + 1j * psi(t)
+    x[:, 0] = s + 1j * amp * psi(s)
+    x[:, 1] = t + 1j * amp * psi(t)
     x[:, 2] = h
     return x * scale
 
