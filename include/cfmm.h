@@ -176,6 +176,15 @@ const char* cfmm_last_error(void);
  * The tree, lists and interaction counts are over the tree points. */
 int cfmm_plan_info(cfmm_plan_t plan, int64_t* info20);
 
+/* Wall-clock milliseconds of the plan's phases (Sec. 6.1, 6.2, 6.3), each
+ * ended by a stream synchronisation: ms7[0] points to the device, bounding
+ * box, Morton keys and sort; [1] tree topology (occupancy split and level
+ * restriction, on the device); [2] complexified centres, top level and
+ * expansion lengths; [3] Lists 1-4 (on the device); [4] operator tables,
+ * work lists and near-field classes; [5] the geometry check of every near
+ * point pair (on the device) and the plan's description; [6] the total. */
+int cfmm_plan_timing(cfmm_plan_t plan, double* ms7);
+
 /* Near-field work of one evaluation over the tree points: work2[0] = ordered
  * interactions G(x_i, x_j) sigma_j summed directly (j != i), work2[1] = kernel
  * evaluations that produce them.  G(x, y) = G(y, x), so a pair of near leaves

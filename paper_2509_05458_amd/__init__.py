@@ -80,6 +80,7 @@ def lib():
         L.cfmm_plan_bytes.restype = i64
         L.cfmm_last_error.restype = ctypes.c_char_p
         L.cfmm_plan_info.argtypes = [vp, i64p]
+        L.cfmm_plan_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.cfmm_plan_nterms.argtypes = [vp, ctypes.c_int]
         L.cfmm_plan_near_work.argtypes = [vp, i64p]
         L.cfmm_plan_export_tree.argtypes = [vp, i64p, u64p, i32p, i32p, i32p, i32p, i32p, i32p, u64p]
@@ -261,6 +262,13 @@ class Plan:
                 "n_list4", "p2p_pairs", "m2l_pairs", "max_p", "dim", "kernel", "separation",
                 "leaf_size", "precision", "n_src", "n_trg", "n_points", "m2l_source_coefs")
         return {k: int(v) for k, v in zip(keys, a)}
+
+    def timing(self) -> dict:
+        """Wall-clock ms of the plan's phases (cfmm_plan_timing)."""
+        a = np.zeros(7, dtype=np.float64)
+        _check(lib().cfmm_plan_timing(self._handle, _ptr(a, ctypes.c_double)))
+        keys = ("keys_sort", "topology", "centres_p", "lists", "tables", "check", "total")
+        return {k: float(v) for k, v in zip(keys, a)}
 
     def near_work(self) -> dict:
         """Ordered near-field interactions and the kernel evaluations producing them."""

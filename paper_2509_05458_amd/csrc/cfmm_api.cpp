@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <set>
 #include <string>
@@ -15,6 +16,7 @@
 #include "kernels.hpp"
 #include "l3d_layout.hpp"
 #include "tree_host.hpp"
+#include "tree_device.hpp"
 
 #pragma clang fp contract(off)
 
@@ -145,6 +147,24 @@ struct cfmm_plan_s {
     M2PParts m2p_parts() const { return M2PParts{n_m2p3, d_m2p_owner, d_m2p_poff, d_m2p_part}; }
     int64_t ecount = 0;
     int64_t info[20];
+    // plan phases, wall-clock ms: keys and sort, topology, centres and
+    // expansion lengths, lists, operator tables and work lists, geometry
+    // check and description; [6] the total
+    std::chrono::steady_clock::time_point clk0;
+    double tphase[7] = {0, 0, 0, 0, 0, 0, 0};
+    double tlast = 0;
+    void clock_start()
+    {
+        clk0 = std::chrono::steady_clock::now();
+        tlast = 0;
+    }
+    void clock_mark(int k)
+    {
+        double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - clk0).count();
+        tphase[k] = ms - tlast;
+        tlast = ms;
+        tphase[6] = ms;
+    }
 
     int prof = 0;                       // 0 off, 1 every stage, 2 near-field ring
     hipEvent_t ev[8];
@@ -419,6 +439,7 @@ int plan_h3d(cfmm_plan_s* p, int nlev, int top)
 int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
 {
     int rc;
+    p->clock_start();
     int dim = d->dim;
     int64_t n = p->n;
     hipStream_t st = p->stream;
@@ -468,14 +489,30 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     p->keys_h.resize(n);
     HIPCHK(hipMemcpyAsync(p->keys_h.data(), d_keys, n * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    // -------- tree (a3)
-    build_topology(p->keys_h.data(), n, dim, p->leaf_size, p->sep, p->tree);
+    p->clock_mark(0);
+    // -------- tree (a3) on the device; the host keeps a copy for planning
+    DeviceTree dtree;
+    HIPCHK(dtree.build(d_keys, n, dim, B, p->leaf_size, p->sep, st));
     HostTree& t = p->tree;
-    int nb = t.nbox(), nlev = t.nlevels();
-    if ((rc = upload(p, &p->d_pbeg, t.pbeg)) || (rc = upload(p, &p->d_pend, t.pend)) ||
-        (rc = upload(p, &p->d_level, t.level)) || (rc = upload(p, &p->d_parent, t.parent)) ||
-        (rc = upload(p, &p->d_child0, t.child0)) || (rc = upload(p, &p->d_nchild, t.nchild)))
+    int nb = dtree.nbox();
+    if ((rc = p->alloc(&p->d_pbeg, nb)) || (rc = p->alloc(&p->d_pend, nb)) || (rc = p->alloc(&p->d_level, nb)) ||
+        (rc = p->alloc(&p->d_parent, nb)) || (rc = p->alloc(&p->d_child0, nb)) || (rc = p->alloc(&p->d_nchild, nb)))
         return rc;
+    HIPCHK(dtree.export_topology(p->d_level, p->d_parent, p->d_child0, p->d_nchild, p->d_pbeg, p->d_pend, t.level,
+                                 t.parent, t.child0, t.nchild, t.pbeg, t.pend, t.prefix));
+    t.dim = dim;
+    t.nbits = B;
+    t.sep = p->sep;
+    t.n = n;
+    {
+        int maxl = 0;
+        for (int b = 0; b < nb; ++b) maxl = std::max(maxl, t.level[b]);
+        t.lvl_beg.assign(maxl + 2, 0);
+        for (int b = 0; b < nb; ++b) t.lvl_beg[t.level[b] + 1]++;
+        for (int l = 0; l <= maxl; ++l) t.lvl_beg[l + 1] += t.lvl_beg[l];
+    }
+    int nlev = t.nlevels();
+    p->clock_mark(1);
     // -------- sorted SoA points
     if ((rc = p->alloc(&p->d_xre, (size_t)dim * n)) || (rc = p->alloc(&p->d_xim, (size_t)dim * n)))
         return rc;
@@ -626,11 +663,19 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         p->l3_R = lay.R;
     }
     p->pmax = pmax;
-    // -------- lists (a5), from the final top level
-    build_lists(t, top);
-    for (int q = 0; q < 4; ++q)
-        if ((rc = upload(p, &p->d_loff[q], t.off[q])) || (rc = upload(p, &p->d_lidx[q], t.idx[q])))
-            return rc;
+    p->clock_mark(2);
+    // -------- lists (a5) on the device, from the final top level
+    {
+        int64_t cnt[4];
+        HIPCHK(dtree.count_lists(top, t.lvl_beg, cnt));
+        for (int q = 0; q < 4; ++q)
+            if ((rc = p->alloc(&p->d_loff[q], (size_t)nb + 1)) || (rc = p->alloc(&p->d_lidx[q], (size_t)cnt[q])))
+                return rc;
+        HIPCHK(dtree.fill_lists(p->d_loff, p->d_lidx, t.off, t.idx));
+        t.top = top;
+        dtree.release();
+    }
+    p->clock_mark(3);
     auto ncoef = [&](int l) -> int64_t { return h2d ? 2 * p->P[l] + 1 : (int64_t)(p->P[l] + 1) * (p->P[l] + 1); };
     std::vector<int> eoff(nb, -1);
     int64_t ecount = 0;
@@ -891,6 +936,8 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         TreeView tv = p->view();
         HIPCHK(l3d_m2l_pairs(p->d_work + p->off_m2l, p->n_m2l, tv, p->l3_pp, p->d_l3pc, p->d_l3ps, st));
     }
+    HIPCHK(hipStreamSynchronize(st));
+    p->clock_mark(4);
     // -------- geometry check on the near pairs
     int* d_flag = nullptr;
     if ((rc = p->alloc(&d_flag, 1))) return rc;
@@ -942,21 +989,23 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     // M2L work: the source coefficients contracted over all List-2 pairs (3D
     // Laplace: (Ps+1)^2 with the pair's own Ps; otherwise the level's count)
     int64_t m2l_src = 0;
-    for (int b = 0; b < nb; ++b)
-        for (int e = t.off[1][b]; e < t.off[1][b + 1]; ++e) {
-            int a = t.idx[1][e];
-            int l = t.level[b];
-            int Ps = p->P[l];
-            if (dim == 3 && p->kernel == CFMM_LAPLACE) {
-                int64_t cb[3], ca[3], dm = 0;
-                box_coords(t, b, cb);
-                box_coords(t, a, ca);
-                for (int k = 0; k < 3; ++k) dm = std::max<int64_t>(dm, std::llabs(cb[k] - ca[k]));
-                Ps = p->l3_pp.p[dm < 7 ? dm : 7];
-            }
-            m2l_src += h2d ? 2 * Ps + 1 : (int64_t)(Ps + 1) * (Ps + 1);
+    if (dim == 3 && p->kernel == CFMM_LAPLACE) {
+        // the pairs' own lengths, formed on the device with the pair constants
+        std::vector<int> ps(t.idx[1].size());
+        if (!ps.empty()) {
+            HIPCHK(hipMemcpyAsync(ps.data(), p->d_l3ps, ps.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
         }
+        for (int v : ps) m2l_src += (int64_t)(v + 1) * (v + 1);
+    } else {
+        for (int b = 0; b < nb; ++b) {
+            int Ps = p->P[t.level[b]];
+            m2l_src += (int64_t)(t.off[1][b + 1] - t.off[1][b]) * (h2d ? 2 * Ps + 1 : (int64_t)(Ps + 1) * (Ps + 1));
+        }
+    }
     I[16] = p->n_src; I[17] = p->n_out; I[18] = p->n; I[19] = m2l_src;
+    HIPCHK(hipStreamSynchronize(st));
+    p->clock_mark(5);
     return CFMM_OK;
 }
 
@@ -1046,6 +1095,13 @@ int cfmm_eval(cfmm_plan_t p, const void* density, void* potential, int on_device
         HIPCHK(hipMemcpyAsync(potential, p->d_io_out, 2 * p->n_out * sizeof(double), hipMemcpyDeviceToHost, st));
         return check_finite(p);
     }
+    return CFMM_OK;
+}
+
+int cfmm_plan_timing(cfmm_plan_t p, double* ms)
+{
+    if (!p || !ms) return fail(CFMM_EINVAL, "plan or ms is NULL");
+    for (int k = 0; k < 7; ++k) ms[k] = p->tphase[k];
     return CFMM_OK;
 }
 

@@ -20,6 +20,9 @@ hipError_t launch_bbox(const double* pts, int64_t n, int dim, double* partial, i
 hipError_t launch_morton(const double* pts, int64_t n, int dim, const KeyParams& kp,
                          uint64_t* keys, int* idx, hipStream_t st);
 size_t radix_sort_scratch_bytes(int64_t n);
+// in-place exclusive scan of m unsigned values; tmp holds scan_scratch_elems(m)
+size_t scan_scratch_elems(int64_t m);
+void launch_scan_exclusive(unsigned* a, int64_t m, unsigned* tmp, hipStream_t st);
 hipError_t launch_radix_sort(uint64_t* keys, int* vals, uint64_t* keys_alt, int* vals_alt,
                              int64_t n, int key_bits, void* scratch, hipStream_t st);
 hipError_t launch_gather_points(const double* pts, const int* perm, int64_t n, int dim,

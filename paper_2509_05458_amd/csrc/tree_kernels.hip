@@ -380,6 +380,18 @@ static void scan_exclusive(unsigned* a, int64_t m, unsigned* tmp, hipStream_t st
     k_scan_add<<<nb, 256, 0, st>>>(a, m, tmp);
 }
 
+size_t scan_scratch_elems(int64_t m)
+{
+    int64_t tmp = 0, mm = m;
+    while (mm > 2048) { mm = (mm + 2047) / 2048; tmp += mm; }
+    return (size_t)tmp + 16;
+}
+
+void launch_scan_exclusive(unsigned* a, int64_t m, unsigned* tmp, hipStream_t st)
+{
+    scan_exclusive(a, m, tmp, st);
+}
+
 size_t radix_sort_scratch_bytes(int64_t n)
 {
     int64_t nblk = (n + kRsTile - 1) / kRsTile;
