@@ -137,6 +137,10 @@ def main():
                    stream=stream.cuda_stream)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t0) * 1e3
+    # the plan's own phase clock: keys and sort, topology and lists (both on
+    # the device), centres and expansion lengths, tables and work lists (host),
+    # the geometry check (device)
+    plan_phases = {k: round(v, 3) for k, v in plan.timing().items()}
     info = plan.info()
     # fresh seeded densities per step, resident in HBM before timing
     nsig = max(1, min(4, a.steps))
@@ -274,7 +278,7 @@ def main():
             "top_level": info["top_level"], "levels": info["nlevels"], "max_p": info["max_p"],
             "p2p_pairs": info["p2p_pairs"], "m2l_pairs": info["m2l_pairs"],
             "boxes": info["nbox"], "leaves": info["nleaf"], "list3": info["n_list3"], "list4": info["n_list4"],
-            "plan_ms": plan_ms, "stage_ms": stage_avg,
+            "plan_ms": plan_ms, "plan_phases_ms": plan_phases, "stage_ms": stage_avg,
             "step": "one cfmm_eval on a warm plan",
         },
         "roofline": roof,

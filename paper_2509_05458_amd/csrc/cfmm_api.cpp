@@ -129,7 +129,8 @@ struct cfmm_plan_s {
     int* d_l3map = nullptr;
     cplx* d_l3pc = nullptr;       // 3D Laplace M2L: table constants per List-2 entry (5 complex)
     int* d_l3ps = nullptr;        // and source expansion length per entry
-    L3Pairs l3_pairs() const { return L3Pairs{d_l3pc, d_l3ps}; }
+    unsigned *d_l3rows64 = nullptr, *d_l3rows32 = nullptr;   // rows per wavefront (l3d_m2l_rows)
+    L3Pairs l3_pairs() const { return L3Pairs{d_l3pc, d_l3ps, d_l3rows64, d_l3rows32}; }
     int l3_ntab = 0, l3_R = 0;
     L3PairP l3_pp{};              // source expansion length per M2L pair distance
     // 3D M2P by List-3 entries: owner leaf, partial-sum offsets and storage
@@ -658,7 +659,9 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         L3dM2LLayout lay = l3d_m2l_layout(m);
         std::vector<int> map(lay.base);
         map.insert(map.end(), lay.slot.begin(), lay.slot.end());
-        if ((rc = upload(p, &p->d_l3map, map))) return rc;
+        if ((rc = upload(p, &p->d_l3map, map)) || (rc = upload(p, &p->d_l3rows64, l3d_m2l_rows(l3d_m2l_waves(0)))) ||
+            (rc = upload(p, &p->d_l3rows32, l3d_m2l_rows(l3d_m2l_waves(1)))))
+            return rc;
         p->l3_ntab = lay.entries;
         p->l3_R = lay.R;
     }

@@ -164,11 +164,17 @@ struct L3PairP {
     int p[8];
 };
 // The table constants of every List-2 pair of the boxes (5 complex per entry)
-// and its source expansion length, formed once per plan.
+// and its source expansion length, formed once per plan; rows64 / rows32: per
+// source length Ps the rows n <= Ps each wavefront of the FP64 (4 waves) or
+// FP32 (2 waves) M2L contracts, as bit masks [Ps * W + w].
 struct L3Pairs {
     const cplx* c;         // [5 * n_list2]
     const int* ps;         // [n_list2]
+    const unsigned* rows64;
+    const unsigned* rows32;
 };
+// wavefronts per workgroup of the FP64 (fp32 = 0) or FP32 M2L
+int l3d_m2l_waves(int fp32);
 hipError_t l3d_m2l_pairs(const int* boxes, int nb, const TreeView& tv, const L3PairP& pp, cplx* c, int* ps,
                          hipStream_t st);
 hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const int* map, int ntab, int R,

@@ -396,10 +396,11 @@ __global__ __launch_bounds__(256) void k_l3d_m2m(const int* __restrict__ boxes, 
 // step loads one table entry for four complex multiply-adds, and the sixteen
 // lanes of a quarter wave read sixteen distinct bank slots.  Orders past k = j
 // in the last group of a row read guard or neighbouring entries and are
-// discarded.  The W wavefronts of the workgroup share the table: each takes a
-// contiguous 1/W of the (P+1)^2 steps (n, m) in n^2 + n + m order, starting a
-// row segment with three loads of the window, and the partial sums meet in
-// LDS at the end, added in wavefront order.  Sharing the table lets W times as
+// discarded.  The W wavefronts of the workgroup share the table: the rows n
+// of the pair's (Ps+1)^2 steps are dealt to them whole (a row starts with
+// three loads of the window and runs in chunks of six steps), balanced by
+// their padded length, and the partial sums meet in LDS at the end, added in
+// wavefront order.  Sharing the table lets W times as
 // many wavefronts reside per unit of LDS; the table itself is built by one
 // wavefront while the others wait, which caps W (measured best: 4 with the
 // FP64 table, 2 with the FP32 table of half the size).
@@ -409,15 +410,6 @@ constexpr int kM2LWavesF32 = 2;
 // after the table that the last chunk of the last row may read
 constexpr int kM2LChunk = 6;
 constexpr int kM2LPad = 8;
-
-// first and last row n of the steps [s0, s1) in n^2 + n + m order
-__device__ inline int step_row(int s)
-{
-    int n = (int)sqrt((double)s);
-    while (n * n > s) --n;
-    while ((n + 1) * (n + 1) <= s) ++n;
-    return n;
-}
 
 struct alignas(16) cplx16 {
     double re, im;
@@ -461,10 +453,45 @@ __global__ __launch_bounds__(64) void k_l3d_m2l_pairs(const int* __restrict__ bo
     }
 }
 
+// C consecutive steps m0 .. m0 + C - 1 of contraction row n (see below);
+// with PAD the steps past m = n take a zero coefficient and read finite table
+// entries, or the zeroed pad after the table (at most C - 1 entries past the
+// row's last step).
+template <int R, int C, bool PAD>
+__device__ inline void m2l_steps(cplx (&acc)[R][4], const cplx16* const (&row)[R], cplx16 (&w1)[R],
+                                 cplx16 (&w2)[R], cplx16 (&w3)[R], const cplx16* Mn, int m0, int n)
+{
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+        int m = m0 + u;
+        cplx am;
+        if (PAD) {
+            bool on = m <= n;
+            cplx16 mv = Mn[on ? m : n];
+            am = on ? mk(mv.re, mv.im) : mk(0.0, 0.0);
+        } else {
+            cplx16 mv = Mn[m];
+            am = mk(mv.re, mv.im);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cplx16 w0 = row[r][m];
+            cfma(acc[r][0], am, mk(w0.re, w0.im));
+            cfma(acc[r][1], am, mk(w1[r].re, w1[r].im));
+            cfma(acc[r][2], am, mk(w2[r].re, w2[r].im));
+            cfma(acc[r][3], am, mk(w3[r].re, w3[r].im));
+            w3[r] = w2[r];
+            w2[r] = w1[r];
+            w1[r] = w0;
+        }
+    }
+}
+
 template <int R>
 __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restrict__ boxes, int nboxes, TreeView tv,
                                                  const int* __restrict__ map, int ntab,
                                                  const cplx* __restrict__ pc, const int* __restrict__ pps,
+                                                 const unsigned* __restrict__ rows64,
                                                  const cplx* __restrict__ mpole,
                                                  cplx* __restrict__ local)
 {
@@ -499,11 +526,10 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
         int a = tv.l2idx[e];
         const cplx* M = mpole + tv.eoff[a];
         // source orders n <= Ps of this pair: rows l = j + n <= P + Ps of the
-        // table, and (Ps+1)^2 steps split over the W wavefronts
+        // table; this wavefront contracts the rows n of its mask
         int Ps = pps[e];
-        int Lt = P + Ps, ncp = (Ps + 1) * (Ps + 1);
-        int s0 = ncp * wv / W, s1 = ncp * (wv + 1) / W;   // this wavefront's steps
-        int na = step_row(s0), nb = s1 > s0 ? step_row(s1 - 1) : na - 1;
+        int Lt = P + Ps;
+        unsigned rows = rows64[Ps * kM2LWaves + wv];
         __syncthreads();
         if (t <= 4 * P && abs(t - 2 * P) <= Lt) {
             int q = t - 2 * P;
@@ -511,8 +537,9 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
             table_I(k[0], k[1], k[2], q < 0 ? k[4] : k[3], q, Lt, [&](int i, cplx v) { tab[i] = v; });
         }
         __syncthreads();
-        for (int n = na; n <= nb; ++n) {
-            int mlo = max(-n, s0 - n * n - n), mhi = min(n, s1 - 1 - n * n - n);
+        while (rows) {
+            int n = __builtin_ctz(rows);
+            rows &= rows - 1;
             // the source coefficients are read at one address by the whole
             // wavefront: scalar loads, which leave the LDS to the table
             const cplx16* Mn = reinterpret_cast<const cplx16*>(M) + n * n + n;
@@ -521,34 +548,13 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 row[r] = tab16 + base[jg[r] + n] - kg[r];
-                w1[r] = row[r][mlo - 1];
-                w2[r] = row[r][mlo - 2];
-                w3[r] = row[r][mlo - 3];
+                w1[r] = row[r][-n - 1];
+                w2[r] = row[r][-n - 2];
+                w3[r] = row[r][-n - 3];
             }
-            // whole chunks of kM2LChunk steps: the steps past the row's end
-            // take a zero coefficient (and read finite table entries, or the
-            // zeroed pad after the table), so no remainder loop waits on
-            // single LDS reads
-            for (int m0 = mlo; m0 <= mhi; m0 += kM2LChunk) {
-#pragma unroll
-                for (int u = 0; u < kM2LChunk; ++u) {
-                    int m = m0 + u;
-                    bool on = m <= mhi;
-                    cplx16 mv = Mn[on ? m : mhi];
-                    cplx am = on ? mk(mv.re, mv.im) : mk(0.0, 0.0);
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        cplx16 w0 = row[r][m];
-                        cfma(acc[r][0], am, mk(w0.re, w0.im));
-                        cfma(acc[r][1], am, mk(w1[r].re, w1[r].im));
-                        cfma(acc[r][2], am, mk(w2[r].re, w2[r].im));
-                        cfma(acc[r][3], am, mk(w3[r].re, w3[r].im));
-                        w3[r] = w2[r];
-                        w2[r] = w1[r];
-                        w1[r] = w0;
-                    }
-                }
-            }
+            // the 2n + 1 steps in whole chunks of kM2LChunk, the last one
+            // zero-padded, so no remainder loop waits on single LDS reads
+            for (int m = -n; m <= n; m += kM2LChunk) m2l_steps<R, kM2LChunk, true>(acc, row, w1, w2, w3, Mn, m, n);
         }
     }
     // partial sums of wavefronts 1..W-1 through LDS (the table is free now)
@@ -593,6 +599,7 @@ template <int R>
 __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __restrict__ boxes, int nboxes, TreeView tv,
                                                      const int* __restrict__ map, int ntab,
                                                      const cplx* __restrict__ pc, const int* __restrict__ pps,
+                                                     const unsigned* __restrict__ rows32,
                                                      const cplx* __restrict__ mpole,
                                                      cplx* __restrict__ local)
 {
@@ -628,8 +635,7 @@ __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __
         const cplx* M = mpole + tv.eoff[a];
         int Ps = pps[e];
         int Lt = P + Ps, ncp = (Ps + 1) * (Ps + 1);
-        int s0 = ncp * wv / W, s1 = ncp * (wv + 1) / W;   // this wavefront's steps
-        int na = step_row(s0), nb = s1 > s0 ? step_row(s1 - 1) : na - 1;
+        unsigned rows = rows32[Ps * kM2LWavesF32 + wv];   // this wavefront's rows n
         __syncthreads();
         for (int i = t; i < ncp; i += blockDim.x) Ms[i] = make_float2((float)M[i].re, (float)M[i].im);
         if (t <= 4 * P && abs(t - 2 * P) <= Lt) {
@@ -639,8 +645,10 @@ __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __
                     [&](int i, cplx v) { tabf[i] = make_float2((float)v.re, (float)v.im); });
         }
         __syncthreads();
-        for (int n = na; n <= nb; ++n) {
-            int mlo = max(-n, s0 - n * n - n), mhi = min(n, s1 - 1 - n * n - n);
+        while (rows) {
+            int n = __builtin_ctz(rows);
+            rows &= rows - 1;
+            int mlo = -n, mhi = n;
             const float2* Mn = Ms + n * n + n;
             const float2* row[R];
             float2 w1[R], w2[R], w3[R], f[R][4];
@@ -1244,7 +1252,7 @@ static hipError_t launch_m2l(const int* boxes, int nb, size_t lds, const TreeVie
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_l3d_m2l<R><<<nb, 64 * kM2LWaves, lds, st>>>(boxes, nb, tv, map, ntab, pr.c, pr.ps, mpole, local);
+    k_l3d_m2l<R><<<nb, 64 * kM2LWaves, lds, st>>>(boxes, nb, tv, map, ntab, pr.c, pr.ps, pr.rows64, mpole, local);
     return hipGetLastError();
 }
 
@@ -1277,7 +1285,8 @@ static hipError_t launch_m2l_f32(const int* boxes, int nb, size_t lds, const Tre
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_l3d_m2l_f32<R><<<nb, 64 * kM2LWavesF32, lds, st>>>(boxes, nb, tv, map, ntab, pr.c, pr.ps, mpole, local);
+    k_l3d_m2l_f32<R><<<nb, 64 * kM2LWavesF32, lds, st>>>(boxes, nb, tv, map, ntab, pr.c, pr.ps, pr.rows32, mpole,
+                                                         local);
     return hipGetLastError();
 }
 
@@ -1339,6 +1348,8 @@ hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& t
 // Largest P the kernels take: at most 5 output groups per M2L lane (P <= 31),
 // 4 outputs per thread of the 256-thread M2M/L2L workgroups ((P+1)^2 <= 1024),
 // and the M2L table within one workgroup's share of the CU's LDS.
+int l3d_m2l_waves(int fp32) { return fp32 ? kM2LWavesF32 : kM2LWaves; }
+
 int l3d_pmax_supported()
 {
     int dev = 0, lds = 65536;

@@ -27,6 +27,28 @@ struct L3dM2LLayout {
     std::vector<int> slot;     // 64 R lane slots: j | g << 8 | active << 16
 };
 
+// Rows n <= Ps of an M2L pair's contraction dealt to W wavefronts: each row
+// (2n + 1 steps) runs as chunks of six steps, the last one zero-padded, plus a
+// window start of about three steps; rows go to the least loaded wavefront,
+// longest first.  mask[Ps * W + w] has bit n set when wavefront w takes row n.
+inline std::vector<unsigned> l3d_m2l_rows(int W)
+{
+    std::vector<unsigned> mask(32 * (size_t)W, 0u);
+    for (int Ps = 0; Ps < 32; ++Ps) {
+        std::vector<int> rows(Ps + 1), load(W, 0);
+        auto cost = [](int n) { return 6 * ((2 * n + 1 + 5) / 6) + 3; };
+        for (int n = 0; n <= Ps; ++n) rows[n] = Ps - n;          // longest first
+        for (int n : rows) {
+            int best = 0;
+            for (int w = 1; w < W; ++w)
+                if (load[w] < load[best]) best = w;
+            load[best] += cost(n);
+            mask[(size_t)Ps * W + best] |= 1u << n;
+        }
+    }
+    return mask;
+}
+
 inline L3dM2LLayout l3d_m2l_layout(int P)
 {
     L3dM2LLayout L;

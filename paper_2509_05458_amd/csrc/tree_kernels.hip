@@ -46,18 +46,36 @@ __global__ void k_bbox_partial(const double* __restrict__ pts, int64_t n, int di
     }
 }
 
+// one block of 256 threads over the per-block partials (min and max are
+// exact, so the order of the reduction does not matter)
 __global__ void k_bbox_final(const double* __restrict__ partial, int nb, int dim, double* __restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double smin[3][256], smax[3][256], sbad[256];
+    int t = threadIdx.x;
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     double bad = 0.0;
-    for (int b = 0; b < nb; ++b) {
+    for (int b = t; b < nb; b += blockDim.x) {
         const double* p = partial + (size_t)b * (2 * dim + 1);
         for (int d = 0; d < dim; ++d) { mn[d] = fmin(mn[d], p[d]); mx[d] = fmax(mx[d], p[dim + d]); }
         bad = fmax(bad, p[2 * dim]);
     }
-    for (int d = 0; d < dim; ++d) { out[d] = mn[d]; out[dim + d] = mx[d]; }
-    out[2 * dim] = bad;
+    for (int d = 0; d < 3; ++d) { smin[d][t] = mn[d]; smax[d][t] = mx[d]; }
+    sbad[t] = bad;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            for (int d = 0; d < 3; ++d) {
+                smin[d][t] = fmin(smin[d][t], smin[d][t + s]);
+                smax[d][t] = fmax(smax[d][t], smax[d][t + s]);
+            }
+            sbad[t] = fmax(sbad[t], sbad[t + s]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        for (int d = 0; d < dim; ++d) { out[d] = smin[d][0]; out[dim + d] = smax[d][0]; }
+        out[2 * dim] = sbad[0];
+    }
 }
 
 // ------------------------------------------------------------- Morton keys
@@ -356,7 +374,7 @@ hipError_t launch_bbox(const double* pts, int64_t n, int dim, double* partial, i
                        double* out, hipStream_t st)
 {
     k_bbox_partial<<<nb, 256, 0, st>>>(pts, n, dim, partial);
-    k_bbox_final<<<1, 64, 0, st>>>(partial, nb, dim, out);
+    k_bbox_final<<<1, 256, 0, st>>>(partial, nb, dim, out);
     return hipGetLastError();
 }
 
