@@ -199,6 +199,8 @@ template <class T>
 struct Sum {
     T s = 0;
     __device__ inline void add(T x) { s += x; }
+    // s + a b + c d as two fused multiply-adds
+    __device__ inline void add2(T a, T b, T c, T d) { s = fma(a, b, fma(c, d, s)); }
     __device__ inline double val() const { return (double)s; }
     __device__ inline void shfl(int src) { s = __shfl(s, src, 64); }
 };
@@ -212,6 +214,7 @@ struct Sum<float> {
         c = (t - s) - y;
         s = t;
     }
+    __device__ inline void add2(float a, float b, float c2, float d) { add(fmaf(a, b, c2 * d)); }
     __device__ inline double val() const { return (double)s - (double)c; }
     __device__ inline void shfl(int src)
     {
@@ -267,10 +270,10 @@ __device__ inline void tile_pair(const Tile& sh, int R, int C, bool self, const 
             T gr, gi;
             Kernel<KIND, PREC>::eval(dr, di, kappa, gr, gi);
             T sr = (T)sh.sr[q], si = (T)sh.si[q];
-            rr.add(gr * sr - gi * si);
-            ri.add(gr * si + gi * sr);
-            cr.add(gr * fwr - gi * fwi);
-            ci.add(gr * fwi + gi * fwr);
+            rr.add2(gr, sr, -gi, si);
+            ri.add2(gr, si, gi, sr);
+            cr.add2(gr, fwr, -gi, fwi);
+            ci.add2(gr, fwi, gi, fwr);
         }
         cr.shfl(nxt);
         ci.shfl(nxt);
@@ -328,10 +331,10 @@ __device__ inline void tile_pair2(const Tile& sh, int R0, int R1, int C, const d
                     }
                     T gr, gi;
                     Kernel<KIND, PREC>::eval(dr, di, kappa, gr, gi);
-                    rr[r].add(gr * sr - gi * si);
-                    ri[r].add(gr * si + gi * sr);
-                    cr.add(gr * fwr[r] - gi * fwi[r]);
-                    ci.add(gr * fwi[r] + gi * fwr[r]);
+                    rr[r].add2(gr, sr, -gi, si);
+                    ri[r].add2(gr, si, gi, sr);
+                    cr.add2(gr, fwr[r], -gi, fwi[r]);
+                    ci.add2(gr, fwi[r], gi, fwr[r]);
                 }
             }
         }
@@ -348,8 +351,10 @@ __device__ inline void tile_pair2(const Tile& sh, int R0, int R1, int C, const d
     ci_out = ci.val();
 }
 
-// Neighbour items (a < b): rows into C[e], columns into C[partner e].  Targets
-// go in blocks of 128, two per lane.
+// Neighbour items (a < b): rows into C[e], columns into C[partner e].  b's
+// targets are cut into the fewest row sets of at most 64, all of one size R,
+// taken two per lane; a's sources into the fewest tiles of at most 64, of one
+// size, so a ragged leaf does not leave most lanes idle for a whole period.
 template <int KIND, int PREC>
 __global__ __launch_bounds__(64) void k_near3_pair(const int* __restrict__ items, Near3Map mp, TreeView tv,
                                                    PointsView pv, double kappa)
@@ -362,12 +367,17 @@ __global__ __launch_bounds__(64) void k_near3_pair(const int* __restrict__ items
     int pb0 = tv.pbeg[b], pb1 = tv.pend[b], pa0 = tv.pbeg[a], pa1 = tv.pend[a];
     cplx* Crow = mp.C + mp.coff[e];
     cplx* Ccol = mp.C + mp.coff[ep];
-    for (int i0 = pb0; i0 < pb1; i0 += 128) {
+    int nt = pb1 - pb0, na = pa1 - pa0;
+    int kt = (nt + 63) / 64, R = (nt + kt - 1) / kt;      // row sets of R <= 64 targets
+    int kc = (na + 63) / 64, Cs = (na + kc - 1) / kc;     // source tiles of Cs <= 64
+    for (int rs = 0; rs < kt; rs += 2) {
         double x[2][3], y[2][3], wr[2], wi[2], ar[2] = {0.0, 0.0}, ai[2] = {0.0, 0.0};
+        int Rn[2];
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-            int i = i0 + 64 * r + t;
-            bool tok = i < pb1;
+            Rn[r] = rs + r < kt ? min(R, nt - (rs + r) * R) : 0;
+            int i = pb0 + (rs + r) * R + t;
+            bool tok = t < Rn[r];
             for (int d = 0; d < 3; ++d) {
                 x[r][d] = tok ? pv.xre[d * n + i] : 0.0;
                 y[r][d] = tok ? pv.xim[d * n + i] : 0.0;
@@ -375,25 +385,22 @@ __global__ __launch_bounds__(64) void k_near3_pair(const int* __restrict__ items
             wr[r] = tok ? pv.sre[i] : 0.0;
             wi[r] = tok ? pv.sim[i] : 0.0;
         }
-        int R0 = min(64, pb1 - i0), R1 = max(0, min(64, pb1 - i0 - 64));
-        for (int j0 = pa0; j0 < pa1; j0 += 64) {
-            int cnt = min(64, pa1 - j0);
+        for (int j0 = pa0; j0 < pa1; j0 += Cs) {
+            int cnt = min(Cs, pa1 - j0);
             __syncthreads();
             load_tile(sh, pv, j0, cnt, t);
             __syncthreads();
             double cr, ci;
-            tile_pair2<KIND, PREC>(sh, R0, R1, cnt, x, y, wr, wi, kappa, ar, ai, cr, ci);
+            tile_pair2<KIND, PREC>(sh, Rn[0], Rn[1], cnt, x, y, wr, wi, kappa, ar, ai, cr, ci);
             if (t < cnt) {
                 cplx* cc = Ccol + (j0 - pa0) + t;
-                if (i0 == pb0) *cc = mk(cr, ci);
+                if (rs == 0) *cc = mk(cr, ci);
                 else *cc = *cc + mk(cr, ci);
             }
         }
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            int i = i0 + 64 * r + t;
-            if (i < pb1) Crow[i - pb0] = mk(ar[r], ai[r]);
-        }
+        for (int r = 0; r < 2; ++r)
+            if (t < Rn[r]) Crow[(rs + r) * R + t] = mk(ar[r], ai[r]);
     }
 }
 
