@@ -129,8 +129,9 @@ struct cfmm_plan_s {
     int* d_l3map = nullptr;
     cplx* d_l3pc = nullptr;       // 3D Laplace M2L: table constants per List-2 entry (5 complex)
     int* d_l3ps = nullptr;        // and source expansion length per entry
+    int* d_l3src = nullptr;       // and the source box's expansion offset
     unsigned *d_l3rows64 = nullptr, *d_l3rows32 = nullptr;   // rows per wavefront (l3d_m2l_rows)
-    L3Pairs l3_pairs() const { return L3Pairs{d_l3pc, d_l3ps, d_l3rows64, d_l3rows32}; }
+    L3Pairs l3_pairs() const { return L3Pairs{d_l3pc, d_l3ps, d_l3src, d_l3rows64, d_l3rows32}; }
     int l3_ntab = 0, l3_R = 0;
     L3PairP l3_pp{};              // source expansion length per M2L pair distance
     // 3D M2P by List-3 entries: owner leaf, partial-sum offsets and storage
@@ -935,9 +936,11 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     if (dim == 3 && p->kernel == CFMM_LAPLACE) {
         // M2L pair constants: fixed by the geometry, formed once per plan
         size_t nl2 = std::max<size_t>(t.idx[1].size(), 1);
-        if ((rc = p->alloc(&p->d_l3pc, 5 * nl2)) || (rc = p->alloc(&p->d_l3ps, nl2))) return rc;
+        if ((rc = p->alloc(&p->d_l3pc, 5 * nl2)) || (rc = p->alloc(&p->d_l3ps, nl2)) ||
+            (rc = p->alloc(&p->d_l3src, nl2)))
+            return rc;
         TreeView tv = p->view();
-        HIPCHK(l3d_m2l_pairs(p->d_work + p->off_m2l, p->n_m2l, tv, p->l3_pp, p->d_l3pc, p->d_l3ps, st));
+        HIPCHK(l3d_m2l_pairs(p->d_work + p->off_m2l, p->n_m2l, tv, p->l3_pp, p->d_l3pc, p->d_l3ps, p->d_l3src, st));
     }
     HIPCHK(hipStreamSynchronize(st));
     p->clock_mark(4);

@@ -170,13 +170,14 @@ struct L3PairP {
 struct L3Pairs {
     const cplx* c;         // [5 * n_list2]
     const int* ps;         // [n_list2]
+    const int* src;        // [n_list2] expansion offset of the source box
     const unsigned* rows64;
     const unsigned* rows32;
 };
 // wavefronts per workgroup of the FP64 (fp32 = 0) or FP32 M2L
 int l3d_m2l_waves(int fp32);
 hipError_t l3d_m2l_pairs(const int* boxes, int nb, const TreeView& tv, const L3PairP& pp, cplx* c, int* ps,
-                         hipStream_t st);
+                         int* src, hipStream_t st);
 hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const int* map, int ntab, int R,
                    const L3Pairs& pr, int mixed, const cplx* mpole, cplx* local, hipStream_t st);
 hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st);

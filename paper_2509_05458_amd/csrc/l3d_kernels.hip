@@ -427,10 +427,11 @@ __device__ inline int pair_terms(const L3PairP& pp, const cplx* cb, const cplx* 
 
 // Per List-2 pair (entry e of the target box's list), once per plan: the
 // constants of its table, c[5e..5e+4] = 1/r2, 1/rho, z/r2, w+/r2, w-/r2 at the
-// scaled offset D / w = (c_target - c_source) / w, and its source expansion
-// length ps[e].
+// scaled offset D / w = (c_target - c_source) / w, its source expansion
+// length ps[e] and the offset src[e] of the source box's multipole.
 __global__ __launch_bounds__(64) void k_l3d_m2l_pairs(const int* __restrict__ boxes, TreeView tv, L3PairP pp,
-                                                      cplx* __restrict__ c, int* __restrict__ ps)
+                                                      cplx* __restrict__ c, int* __restrict__ ps,
+                                                      int* __restrict__ src)
 {
     int b = boxes[blockIdx.x];
     double s = tv.rs[tv.level[b]];
@@ -450,6 +451,7 @@ __global__ __launch_bounds__(64) void k_l3d_m2l_pairs(const int* __restrict__ bo
         c[5 * (size_t)e + 3] = wplus(d) * ir2;
         c[5 * (size_t)e + 4] = wminus(d) * ir2;
         ps[e] = pair_terms(pp, cb, ca, s);
+        src[e] = tv.eoff[a];
     }
 }
 
@@ -491,7 +493,7 @@ template <int R>
 __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restrict__ boxes, int nboxes, TreeView tv,
                                                  const int* __restrict__ map, int ntab,
                                                  const cplx* __restrict__ pc, const int* __restrict__ pps,
-                                                 const unsigned* __restrict__ rows64,
+                                                 const int* __restrict__ psrc, const unsigned* __restrict__ rows64,
                                                  const cplx* __restrict__ mpole,
                                                  cplx* __restrict__ local)
 {
@@ -520,11 +522,11 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
     }
     for (int i = t; i < ntab + kM2LPad; i += blockDim.x) tab[i] = mk(0.0, 0.0);
     for (int i = t; i <= 2 * P; i += blockDim.x) base[i] = map[i];
-    cplx cb[3];
-    box_centre(tv, b, cb);
-    for (int e = tv.l2off[b]; e < tv.l2off[b + 1]; ++e) {
-        int a = tv.l2idx[e];
-        const cplx* M = mpole + tv.eoff[a];
+    // the pair loop's bounds and per-pair data in scalar registers
+    int e0 = __builtin_amdgcn_readfirstlane(tv.l2off[b]);
+    int e1 = __builtin_amdgcn_readfirstlane(tv.l2off[b + 1]);
+    for (int e = e0; e < e1; ++e) {
+        const cplx* M = mpole + psrc[e];
         // source orders n <= Ps of this pair: rows l = j + n <= P + Ps of the
         // table; this wavefront contracts the rows n of its mask
         int Ps = pps[e];
@@ -599,6 +601,7 @@ template <int R>
 __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __restrict__ boxes, int nboxes, TreeView tv,
                                                      const int* __restrict__ map, int ntab,
                                                      const cplx* __restrict__ pc, const int* __restrict__ pps,
+                                                     const int* __restrict__ psrc,
                                                      const unsigned* __restrict__ rows32,
                                                      const cplx* __restrict__ mpole,
                                                      cplx* __restrict__ local)
@@ -628,11 +631,10 @@ __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __
     }
     for (int i = t; i < ntab + kM2LPad; i += blockDim.x) tabf[i] = make_float2(0.0f, 0.0f);
     for (int i = t; i <= 2 * P; i += blockDim.x) base[i] = map[i];
-    cplx cb[3];
-    box_centre(tv, b, cb);
-    for (int e = tv.l2off[b]; e < tv.l2off[b + 1]; ++e) {
-        int a = tv.l2idx[e];
-        const cplx* M = mpole + tv.eoff[a];
+    int e0 = __builtin_amdgcn_readfirstlane(tv.l2off[b]);
+    int e1 = __builtin_amdgcn_readfirstlane(tv.l2off[b + 1]);
+    for (int e = e0; e < e1; ++e) {
+        const cplx* M = mpole + psrc[e];
         int Ps = pps[e];
         int Lt = P + Ps, ncp = (Ps + 1) * (Ps + 1);
         unsigned rows = rows32[Ps * kM2LWavesF32 + wv];   // this wavefront's rows n
@@ -1252,7 +1254,8 @@ static hipError_t launch_m2l(const int* boxes, int nb, size_t lds, const TreeVie
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_l3d_m2l<R><<<nb, 64 * kM2LWaves, lds, st>>>(boxes, nb, tv, map, ntab, pr.c, pr.ps, pr.rows64, mpole, local);
+    k_l3d_m2l<R><<<nb, 64 * kM2LWaves, lds, st>>>(boxes, nb, tv, map, ntab, pr.c, pr.ps, pr.src, pr.rows64, mpole,
+                                                  local);
     return hipGetLastError();
 }
 
@@ -1285,16 +1288,16 @@ static hipError_t launch_m2l_f32(const int* boxes, int nb, size_t lds, const Tre
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_l3d_m2l_f32<R><<<nb, 64 * kM2LWavesF32, lds, st>>>(boxes, nb, tv, map, ntab, pr.c, pr.ps, pr.rows32, mpole,
-                                                         local);
+    k_l3d_m2l_f32<R><<<nb, 64 * kM2LWavesF32, lds, st>>>(boxes, nb, tv, map, ntab, pr.c, pr.ps, pr.src,
+                                                         pr.rows32, mpole, local);
     return hipGetLastError();
 }
 
 hipError_t l3d_m2l_pairs(const int* boxes, int nb, const TreeView& tv, const L3PairP& pp, cplx* c, int* ps,
-                         hipStream_t st)
+                         int* src, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    k_l3d_m2l_pairs<<<nb, 64, 0, st>>>(boxes, tv, pp, c, ps);
+    k_l3d_m2l_pairs<<<nb, 64, 0, st>>>(boxes, tv, pp, c, ps, src);
     return hipGetLastError();
 }
 
