@@ -107,6 +107,12 @@ struct cfmm_plan_s {
     // plan-time translation operators (2D Helmholtz)
     int64_t *d_o_m2l = nullptr, *d_o_tr = nullptr;
     cplx *d_g_m2l = nullptr, *d_g_m2m = nullptr, *d_g_l2l = nullptr;
+    int* d_m2l_src = nullptr;
+    // 2D Helmholtz window M2L: groups (first, count) of consecutive M2L-list
+    // boxes of one level, the boxes they cover and their LDS
+    int2* d_m2lw_grp = nullptr;
+    int m2lw_ngrp = 0, m2lw_nbox = 0;
+    size_t m2lw_lds = 0;
     double* d_pw = nullptr;
     double *d_io_in = nullptr, *d_io_out = nullptr;       // staging for host pointers
     // 3D Helmholtz: per-level kappa w and scale; translation stages and chunks
@@ -223,6 +229,7 @@ struct cfmm_plan_s {
     {
         H2DOps o;
         o.g_m2l = d_g_m2l; o.o_m2l = d_o_m2l; o.g_m2m = d_g_m2m; o.g_l2l = d_g_l2l;
+        o.m2l_src = d_m2l_src;
         o.o_tr = d_o_tr; o.pw = d_pw;
         return o;
     }
@@ -921,6 +928,37 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     std::vector<double> pw((size_t)nlev * kPwStride, 0.0);
     for (int l = 0; l < nlev; ++l)
         for (int e = 0; e < kPwStride; ++e) pw[(size_t)l * kPwStride + e] = pow(p->rs[l], (double)e);
+    std::vector<int> msrc(t.idx[1].size());
+    for (size_t e = 0; e < msrc.size(); ++e) msrc[e] = eoff[t.idx[1][e]];
+    if ((rc = upload(p, &p->d_m2l_src, msrc))) return rc;
+    {
+        // window M2L for the levels whose operator fits FP64 unscaled
+        // (r^(2P) > 1e-250; a prefix of the levels from top, r growing with
+        // the box): consecutive boxes of a level grouped while their List-2
+        // entries fit one round, a box with more entries alone
+        std::vector<int2> grp;
+        int k = 0;
+        for (int l = top; l < nlev; ++l) {
+            int P = p->P[l];
+            if (!(p->rs[l] > 0.0 && 2.0 * P * log10(p->rs[l]) > -250.0)) break;
+            int E = h2d_m2l_w_slots(P);
+            int b = t.lvl_beg[l], bend = t.lvl_beg[l + 1];
+            if (b < bend) p->m2lw_lds = std::max(p->m2lw_lds, h2d_m2l_w_lds(P));
+            while (b < bend) {
+                int first = b, ne = t.off[1][b + 1] - t.off[1][b];
+                ++b;
+                while (b < bend && ne + (t.off[1][b + 1] - t.off[1][b]) <= E) {
+                    ne += t.off[1][b + 1] - t.off[1][b];
+                    ++b;
+                }
+                grp.push_back(make_int2(k + (first - t.lvl_beg[l]), b - first));
+            }
+            k += t.lvl_beg[l + 1] - t.lvl_beg[l];
+        }
+        p->m2lw_nbox = k;
+        p->m2lw_ngrp = (int)grp.size();
+        if ((rc = upload(p, &p->d_m2lw_grp, grp))) return rc;
+    }
     if ((rc = upload(p, &p->d_o_m2l, o_m2l)) || (rc = upload(p, &p->d_o_tr, o_tr)) ||
         (rc = upload(p, &p->d_pw, pw)) || (rc = p->alloc(&p->d_g_m2l, gsz)) ||
         (rc = p->alloc(&p->d_g_m2m, tsz)) || (rc = p->alloc(&p->d_g_l2l, tsz)))
@@ -1291,20 +1329,10 @@ int eval_on_device(cfmm_plan_s* p, const double* sig, double* out)
         for (int l = nlev - 2; l >= top; --l)
             HIPCHK(h2d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], 2 * p->P[l] + 1, tv, p->ops(), p->d_mpole, st));
         HIPCHK(mark(3));
-        {
-            // the M2L list holds the boxes of levels >= top in level order
-            int nlv = nlev - top, boff[64], cnt[64], nco[64];
-            for (int k = 0; k < nlv && k < 64; ++k) {
-                int l = top + k;
-                boff[k] = t.lvl_beg[l] - t.lvl_beg[top];
-                cnt[k] = t.lvl_beg[l + 1] - t.lvl_beg[l];
-                nco[k] = 2 * p->P[l] + 1;
-            }
-            HIPCHK(mark(8));
-            HIPCHK(h2d_m2l(W + p->off_m2l, std::min(nlv, 64), boff, cnt, nco, tv, p->ops(), p->d_mpole,
-                           p->d_local, st));
-            HIPCHK(mark(9));
-        }
+        HIPCHK(mark(8));
+        HIPCHK(h2d_m2l(W + p->off_m2l, p->d_m2lw_grp, p->m2lw_ngrp, p->m2lw_lds, p->m2lw_nbox, p->n_m2l, tv,
+                       p->ops(), p->d_mpole, p->d_local, st));
+        HIPCHK(mark(9));
         {
             // the P2L list is in level order; one launch per level sizes its LDS by that level's P
             int k0 = 0;

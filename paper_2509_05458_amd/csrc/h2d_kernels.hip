@@ -517,6 +517,111 @@ __global__ __launch_bounds__(64) void k_h2d_m2l(const int* __restrict__ boxes, i
     }
 }
 
+// M2L by sliding windows, for levels whose operator stays in FP64 range
+// unscaled (r^(2P) above 1e-250).  Unscaled, the operator is Toeplitz:
+//   L_m = sum_n G[n - m] M_n,  G[k] = gm2l[k] / r^|k|,  M_n = r^|n| Mhat_n,
+// and Lhat_m = r^|m| L_m.  A lane owns kWin consecutive outputs m0 .. m0 + 3
+// of one List-2 entry and streams n: output m0 + c needs G[n - m0 - c], so
+// each step loads one new G for kWin complex multiply-adds, the others
+// sliding through registers.  ceil((2P+1)/4) lanes serve an entry, so one
+// wavefront takes E = 64 / that many entries of the target box per round (7
+// at P = 17) instead of idling the lanes beyond 2P+1; the E partial sums meet
+// in LDS at the end, added in entry-slot order.  G is stored with one gap
+// entry after every eight (index i at i + i/8) to spread the lanes' reads
+// over the banks.
+constexpr int kWin = 4;
+
+__device__ inline int gskew(int i) { return i + (i >> 3); }
+
+__global__ __launch_bounds__(64) void k_h2d_m2l_w(const int* __restrict__ boxes, const int2* __restrict__ grp,
+                                                  int ngrp, TreeView tv, H2DOps ops,
+                                                  const cplx* __restrict__ mpole, cplx* __restrict__ local)
+{
+    extern __shared__ cplx wlds[];
+    int2 gr = grp[xcd_contiguous(blockIdx.x, ngrp)];
+    const int* gbox = boxes + gr.x;               // gr.y consecutive boxes of one level
+    int nbx = gr.y;
+    int b = gbox[0];
+    int l = tv.level[b];
+    int P = tv.P[l], nc = 2 * P + 1;
+    int NG = (nc + kWin - 1) / kWin, E = 64 / NG;
+    int glen = 4 * P + 1 + (kWin - 1);            // G[k], k = -2P-7 .. 2P (zero guards below -2P)
+    int GS = gskew(glen - 1) + 1;
+    cplx* gb = wlds;                              // [E][GS]
+    cplx* ab = wlds + (size_t)E * GS;             // [E][nc]
+    const double* pw = ops.pw + (size_t)l * kPwStride;
+    int t = threadIdx.x, slot = t / NG, j = t - slot * NG;
+    bool act = slot < E;
+    int m0 = -P + kWin * j;
+    cplx acc[kWin];
+#pragma unroll
+    for (int c = 0; c < kWin; ++c) acc[c] = mk(0.0, 0.0);
+    int e0 = __builtin_amdgcn_readfirstlane(tv.l2off[b]);
+    int e1 = __builtin_amdgcn_readfirstlane(tv.l2off[gbox[nbx - 1] + 1]);
+    for (int eb = e0; eb < e1; eb += E) {
+        int ne = min(E, e1 - eb);
+        __syncthreads();
+        for (int i = t; i < ne * glen; i += 64) {
+            int sl = i / glen, q = i - sl * glen;
+            int k = q - 2 * P - (kWin - 1);
+            cplx v = mk(0.0, 0.0);
+            if (k >= -2 * P) v = ops.g_m2l[ops.o_m2l[eb + sl] + k + 2 * P] * (1.0 / pw[k < 0 ? -k : k]);
+            gb[(size_t)sl * GS + gskew(q)] = v;
+        }
+        for (int i = t; i < ne * nc; i += 64) {
+            int sl = i / nc, q = i - sl * nc, an = q - P < 0 ? P - q : q - P;
+            ab[(size_t)sl * nc + q] = pw[an] * mpole[ops.m2l_src[eb + sl] + q];
+        }
+        __syncthreads();
+        if (act && slot < ne) {
+            const cplx* G = gb + (size_t)slot * GS;
+            const cplx* A = ab + (size_t)slot * nc;
+            int q0 = P - m0 + (kWin - 1);          // G[n - m0] at n = -P
+            cplx w[kWin];
+#pragma unroll
+            for (int c = 1; c < kWin; ++c) w[c] = G[gskew(q0 - c)];
+#pragma unroll 2
+            for (int n = 0; n < nc; ++n) {
+                w[0] = G[gskew(q0 + n)];
+                cplx av = A[n];
+#pragma unroll
+                for (int c = 0; c < kWin; ++c) cfma(acc[c], w[c], av);
+#pragma unroll
+                for (int c = kWin - 1; c > 0; --c) w[c] = w[c - 1];
+            }
+        }
+    }
+    __syncthreads();
+    cplx* red = wlds;                             // [E][NG][kWin]
+    if (act)
+#pragma unroll
+        for (int c = 0; c < kWin; ++c) red[((size_t)slot * NG + j) * kWin + c] = acc[c];
+    __syncthreads();
+    // thread u = (box, j, c) adds output m0(j) + c of a box over its slots:
+    // all slots for a box alone in its group (it may take several rounds),
+    // else the slots of its own entries (one round)
+    for (int u = t; u < nbx * NG * kWin; u += 64) {
+        int bi = u / (NG * kWin), r = u - bi * NG * kWin;
+        int jj = r / kWin, c = r - jj * kWin, m = -P + kWin * jj + c;
+        if (m > P) continue;
+        int bb = gbox[bi];
+        int s0 = nbx == 1 ? 0 : tv.l2off[bb] - e0, s1 = nbx == 1 ? E : tv.l2off[bb + 1] - e0;
+        cplx v = mk(0.0, 0.0);
+        for (int sl = s0; sl < s1; ++sl) v += red[((size_t)sl * NG + jj) * kWin + c];
+        local[tv.eoff[bb] + m + P] = pw[m < 0 ? -m : m] * v;
+    }
+}
+
+// LDS of k_h2d_m2l_w at expansion length P
+static size_t m2l_w_lds(int P)
+{
+    int nc = 2 * P + 1, NG = (nc + kWin - 1) / kWin, E = 64 / NG;
+    int glen = 4 * P + 1 + (kWin - 1);
+    size_t stage = (size_t)E * ((size_t)(glen - 1 + ((glen - 1) >> 3) + 1) + nc);
+    size_t red = (size_t)E * NG * kWin;
+    return sizeof(cplx) * (stage > red ? stage : red);
+}
+
 // ------------------------------------------------------------------ P2L
 // Sources of the coarser leaves in List 4 go directly into the local
 // expansion (added after M2L wrote it).  Launched per level.  Threads q and
@@ -1212,16 +1317,25 @@ hipError_t h2d_m2m(const int* boxes, int nb, int ncoef, const TreeView& tv, cons
     return hipGetLastError();
 }
 
-hipError_t h2d_m2l(const int* boxes, int nlv, const int* box_off, const int* nb, const int* ncoef,
+// Entries per round of the window kernel and its LDS at expansion length P,
+// for the plan's grouping of target boxes.
+int h2d_m2l_w_slots(int P) { return 64 / ((2 * P + 1 + kWin - 1) / kWin); }
+size_t h2d_m2l_w_lds(int P) { return m2l_w_lds(P); }
+
+// boxes[0 .. nwin) (the levels whose operator fits FP64 unscaled, grouped by
+// grp) take the window kernel; boxes[nwin .. total) the scaled one.
+hipError_t h2d_m2l(const int* boxes, const int2* grp, int ngrp, size_t lds, int nwin, int total,
                    const TreeView& tv, const H2DOps& ops, const cplx* mpole, cplx* local, hipStream_t st)
 {
-    // the boxes of all levels are contiguous in the list
-    (void)box_off;
-    (void)ncoef;
-    int total = 0;
-    for (int k = 0; k < nlv; ++k) total += nb[k] > 0 ? nb[k] : 0;
-    if (total <= 0) return hipSuccess;
-    k_h2d_m2l<<<total, 64, 0, st>>>(boxes, total, tv, ops, mpole, local);
+    if (ngrp > 0) {
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_h2d_m2l_w, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        k_h2d_m2l_w<<<ngrp, 64, lds, st>>>(boxes, grp, ngrp, tv, ops, mpole, local);
+    }
+    if (total > nwin) k_h2d_m2l<<<total - nwin, 64, 0, st>>>(boxes + nwin, total - nwin, tv, ops, mpole, local);
     return hipGetLastError();
 }
 

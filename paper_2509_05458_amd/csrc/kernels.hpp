@@ -102,6 +102,7 @@ struct H2DOps {
     const cplx* g_l2l;
     const int64_t* o_tr;    // per box offset into g_m2m / g_l2l (-1 if none)
     const double* pw;       // pw[l * kPwStride + e] = r_l^e
+    const int* m2l_src;     // per List-2 entry: expansion offset of the source box
 };
 
 // 2D Helmholtz evaluation (h2d_kernels.hip)
@@ -113,7 +114,11 @@ hipError_t h2d_p2m(const int* leaves, int nleaf, int pmax, const TreeView& tv, c
                    double kappa, cplx* mpole, hipStream_t st);
 hipError_t h2d_m2m(const int* boxes, int nb, int ncoef, const TreeView& tv, const H2DOps& ops, cplx* mpole,
                    hipStream_t st);
-hipError_t h2d_m2l(const int* boxes, int nlv, const int* box_off, const int* nb, const int* ncoef,
+// M2L: boxes[0 .. nwin) grouped by grp (first box, count) for the window
+// kernel, boxes[nwin .. total) by the scaled kernel
+int h2d_m2l_w_slots(int P);
+size_t h2d_m2l_w_lds(int P);
+hipError_t h2d_m2l(const int* boxes, const int2* grp, int ngrp, size_t lds, int nwin, int total,
                    const TreeView& tv, const H2DOps& ops, const cplx* mpole, cplx* local, hipStream_t st);
 hipError_t h2d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
                    double kappa, cplx* local, hipStream_t st);
