@@ -111,8 +111,9 @@ struct cfmm_plan_s {
     // 2D Helmholtz window M2L: groups (first, count) of consecutive M2L-list
     // boxes of one level, the boxes they cover and their LDS
     int2* d_m2lw_grp = nullptr;
-    int m2lw_ngrp = 0, m2lw_nbox = 0;
-    size_t m2lw_lds = 0;
+    int m2lw_ngrp1 = 0, m2lw_ngrp = 0, m2lw_nbox = 0;   // one-wavefront groups first, then many-entry boxes
+    int m2lw_lend = 0;            // levels [top, m2lw_lend) take the window kernel, their generators unscaled
+    size_t m2lw_lds1 = 0, m2lw_ldsw = 0;
     double* d_pw = nullptr;
     double *d_io_in = nullptr, *d_io_out = nullptr;       // staging for host pointers
     // 3D Helmholtz: per-level kappa w and scale; translation stages and chunks
@@ -932,30 +933,42 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     for (size_t e = 0; e < msrc.size(); ++e) msrc[e] = eoff[t.idx[1][e]];
     if ((rc = upload(p, &p->d_m2l_src, msrc))) return rc;
     {
-        // window M2L for the levels whose operator fits FP64 unscaled
-        // (r^(2P) > 1e-250; a prefix of the levels from top, r growing with
-        // the box): consecutive boxes of a level grouped while their List-2
-        // entries fit one round, a box with more entries alone
-        std::vector<int2> grp;
-        int k = 0;
+        // window M2L for the levels whose operator fits FP64 unscaled: the
+        // generator H_k e^{ik phi}, k <= 2P, is at most about (2P)! / r^(2P)
+        // (r = min(1, kappa w), the centres at least 2w apart), kept below
+        // 1e250; a prefix of the levels from top, r growing with the box.
+        // Consecutive boxes of a level are grouped while their List-2 entries
+        // fit one round, a box with more entries alone.
+        std::vector<int2> grp, big;
+        int k = 0, Wb = h2d_m2l_w_waves();
+        p->m2lw_lend = top;
         for (int l = top; l < nlev; ++l) {
             int P = p->P[l];
-            if (!(p->rs[l] > 0.0 && 2.0 * P * log10(p->rs[l]) > -250.0)) break;
+            if (!(p->rs[l] > 0.0 && lgamma(2.0 * P + 1.0) / log(10.0) - 2.0 * P * log10(p->rs[l]) < 250.0)) break;
+            p->m2lw_lend = l + 1;
             int E = h2d_m2l_w_slots(P);
             int b = t.lvl_beg[l], bend = t.lvl_beg[l + 1];
-            if (b < bend) p->m2lw_lds = std::max(p->m2lw_lds, h2d_m2l_w_lds(P));
             while (b < bend) {
                 int first = b, ne = t.off[1][b + 1] - t.off[1][b];
                 ++b;
-                while (b < bend && ne + (t.off[1][b + 1] - t.off[1][b]) <= E) {
+                if (ne > E) {
+                    big.push_back(make_int2(k + (first - t.lvl_beg[l]), 1));
+                    p->m2lw_ldsw = std::max(p->m2lw_ldsw, h2d_m2l_w_lds(P, Wb));
+                    continue;
+                }
+                while (b < bend && t.off[1][b + 1] - t.off[1][b] <= E &&
+                       ne + (t.off[1][b + 1] - t.off[1][b]) <= E) {
                     ne += t.off[1][b + 1] - t.off[1][b];
                     ++b;
                 }
                 grp.push_back(make_int2(k + (first - t.lvl_beg[l]), b - first));
+                p->m2lw_lds1 = std::max(p->m2lw_lds1, h2d_m2l_w_lds(P, 1));
             }
             k += t.lvl_beg[l + 1] - t.lvl_beg[l];
         }
         p->m2lw_nbox = k;
+        p->m2lw_ngrp1 = (int)grp.size();
+        grp.insert(grp.end(), big.begin(), big.end());
         p->m2lw_ngrp = (int)grp.size();
         if ((rc = upload(p, &p->d_m2lw_grp, grp))) return rc;
     }
@@ -965,7 +978,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
         return rc;
     {
         TreeView tv = p->view();
-        HIPCHK(h2d_gen_ops(p->d_work + off_pairb, npairs, p->d_work + off_tr, n_tr, tv, p->kappa,
+        HIPCHK(h2d_gen_ops(p->d_work + off_pairb, npairs, p->d_work + off_tr, n_tr, tv, p->kappa, p->m2lw_lend,
                            p->d_o_m2l, p->d_g_m2l, p->d_o_tr, p->d_g_m2m, p->d_g_l2l, st));
     }
     }  // h2d operator tables
@@ -1330,8 +1343,8 @@ int eval_on_device(cfmm_plan_s* p, const double* sig, double* out)
             HIPCHK(h2d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], 2 * p->P[l] + 1, tv, p->ops(), p->d_mpole, st));
         HIPCHK(mark(3));
         HIPCHK(mark(8));
-        HIPCHK(h2d_m2l(W + p->off_m2l, p->d_m2lw_grp, p->m2lw_ngrp, p->m2lw_lds, p->m2lw_nbox, p->n_m2l, tv,
-                       p->ops(), p->d_mpole, p->d_local, st));
+        HIPCHK(h2d_m2l(W + p->off_m2l, p->d_m2lw_grp, p->m2lw_ngrp1, p->m2lw_ngrp, p->m2lw_lds1, p->m2lw_ldsw,
+                       p->m2lw_nbox, p->n_m2l, tv, p->ops(), p->d_mpole, p->d_local, st));
         HIPCHK(mark(9));
         {
             // the P2L list is in level order; one launch per level sizes its LDS by that level's P

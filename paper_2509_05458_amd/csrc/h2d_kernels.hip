@@ -284,6 +284,7 @@ __global__ __launch_bounds__(64) void k_h2d_p2m(const int* __restrict__ leaves, 
 // Translation generators depend only on the geometry and are built once per
 // plan.  For a List-2 pair (target b, source a), D = c_b - c_a:
 //   gm2l[k + 2P] = H_k(kappa rho_D) e^{ik phi_D} r^|k|,            k = -2P..2P
+// with r = 1 (unscaled) on the levels below lwin, which the window M2L takes
 // and for each box c with parent p (K = P_p + P_c):
 //   gm2m[k + K] = J_k(kappa rho_D) e^{ik phi_D} / r_c^|k|,  D = c_p - c_c
 //   gl2l[k + K] = J_k(kappa rho_D) e^{ik phi_D} / r_p^|k|,  D = c_c - c_p
@@ -303,7 +304,7 @@ __device__ inline void fill_signed(cplx* g, int K, cplx bp, cplx bm, bool fact)
     }
 }
 
-__global__ void k_h2d_gen_m2l(int npairs, const int* __restrict__ pair_b, TreeView tv, double kappa,
+__global__ void k_h2d_gen_m2l(int npairs, const int* __restrict__ pair_b, TreeView tv, double kappa, int lwin,
                               const int64_t* __restrict__ goff, cplx* __restrict__ gen)
 {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,7 +312,7 @@ __global__ void k_h2d_gen_m2l(int npairs, const int* __restrict__ pair_b, TreeVi
     int b = pair_b[e], a = tv.l2idx[e];
     int l = tv.level[b];
     int K = 2 * tv.P[l];
-    double r = tv.rs[l];
+    double r = l < lwin ? 1.0 : tv.rs[l];
     int nbx = tv.nbox;
     cplx d1 = mk(tv.cre[b] - tv.cre[a], tv.cim[b] - tv.cim[a]);
     cplx d2 = mk(tv.cre[nbx + b] - tv.cre[nbx + a], tv.cim[nbx + b] - tv.cim[nbx + a]);
@@ -518,26 +519,34 @@ __global__ __launch_bounds__(64) void k_h2d_m2l(const int* __restrict__ boxes, i
 }
 
 // M2L by sliding windows, for levels whose operator stays in FP64 range
-// unscaled (r^(2P) above 1e-250).  Unscaled, the operator is Toeplitz:
-//   L_m = sum_n G[n - m] M_n,  G[k] = gm2l[k] / r^|k|,  M_n = r^|n| Mhat_n,
-// and Lhat_m = r^|m| L_m.  A lane owns kWin consecutive outputs m0 .. m0 + 3
+// unscaled.  Unscaled, the operator is Toeplitz:
+//   L_m = sum_n G[n - m] M_n,  G[k] = H_k e^{ik phi} (the plan stores it so),
+//   M_n = r^|n| Mhat_n,  and Lhat_m = r^|m| L_m.  A lane owns kWin consecutive outputs m0 .. m0 + 3
 // of one List-2 entry and streams n: output m0 + c needs G[n - m0 - c], so
 // each step loads one new G for kWin complex multiply-adds, the others
 // sliding through registers.  ceil((2P+1)/4) lanes serve an entry, so one
 // wavefront takes E = 64 / that many entries of the target box per round (7
 // at P = 17) instead of idling the lanes beyond 2P+1; the E partial sums meet
-// in LDS at the end, added in entry-slot order.  G is stored with one gap
-// entry after every eight (index i at i + i/8) to spread the lanes' reads
-// over the banks.
+// in LDS at the end, added in entry-slot order.  A box with more entries
+// than one round holds runs in a workgroup of W wavefronts that take the
+// rounds in turn, each with its own LDS (the slots of all W meet at the end,
+// in wavefront-major order).  G is stored with one gap entry after every
+// eight (index i at i + i/8) to spread the lanes' reads over the banks.
 constexpr int kWin = 4;
+// generator and coefficient values staged per lane and round: E (4P + 4) and
+// E (2P + 1) are at most 64 kStageG and 64 kStageA for every P <= 63
+constexpr int kStageG = 8, kStageA = 4;
 
 __device__ inline int gskew(int i) { return i + (i >> 3); }
 
-__global__ __launch_bounds__(64) void k_h2d_m2l_w(const int* __restrict__ boxes, const int2* __restrict__ grp,
-                                                  int ngrp, TreeView tv, H2DOps ops,
-                                                  const cplx* __restrict__ mpole, cplx* __restrict__ local)
+constexpr int kM2LWWaves = 8;    // wavefronts of a workgroup for one box with many entries
+
+__global__ __launch_bounds__(64 * kM2LWWaves) void k_h2d_m2l_w(const int* __restrict__ boxes,
+                                                              const int2* __restrict__ grp, int ngrp, TreeView tv,
+                                                              H2DOps ops, const cplx* __restrict__ mpole,
+                                                              cplx* __restrict__ local)
 {
-    extern __shared__ cplx wlds[];
+    extern __shared__ cplx wlds_all[];
     int2 gr = grp[xcd_contiguous(blockIdx.x, ngrp)];
     const int* gbox = boxes + gr.x;               // gr.y consecutive boxes of one level
     int nbx = gr.y;
@@ -547,10 +556,12 @@ __global__ __launch_bounds__(64) void k_h2d_m2l_w(const int* __restrict__ boxes,
     int NG = (nc + kWin - 1) / kWin, E = 64 / NG;
     int glen = 4 * P + 1 + (kWin - 1);            // G[k], k = -2P-7 .. 2P (zero guards below -2P)
     int GS = gskew(glen - 1) + 1;
+    int W = blockDim.x >> 6, wv = threadIdx.x >> 6;
+    cplx* wlds = wlds_all + (size_t)wv * E * (GS + nc);
     cplx* gb = wlds;                              // [E][GS]
     cplx* ab = wlds + (size_t)E * GS;             // [E][nc]
     const double* pw = ops.pw + (size_t)l * kPwStride;
-    int t = threadIdx.x, slot = t / NG, j = t - slot * NG;
+    int t = threadIdx.x & 63, slot = t / NG, j = t - slot * NG;
     bool act = slot < E;
     int m0 = -P + kWin * j;
     cplx acc[kWin];
@@ -558,21 +569,59 @@ __global__ __launch_bounds__(64) void k_h2d_m2l_w(const int* __restrict__ boxes,
     for (int c = 0; c < kWin; ++c) acc[c] = mk(0.0, 0.0);
     int e0 = __builtin_amdgcn_readfirstlane(tv.l2off[b]);
     int e1 = __builtin_amdgcn_readfirstlane(tv.l2off[gbox[nbx - 1] + 1]);
-    for (int eb = e0; eb < e1; eb += E) {
+    // wavefront wv takes rounds wv, wv + W, ...; within a wavefront the
+    // LDS writes and reads are ordered by wave barriers
+    for (int eb = e0 + wv * E; eb < e1; eb += W * E) {
         int ne = min(E, e1 - eb);
-        __syncthreads();
-        for (int i = t; i < ne * glen; i += 64) {
-            int sl = i / glen, q = i - sl * glen;
-            int k = q - 2 * P - (kWin - 1);
-            cplx v = mk(0.0, 0.0);
-            if (k >= -2 * P) v = ops.g_m2l[ops.o_m2l[eb + sl] + k + 2 * P] * (1.0 / pw[k < 0 ? -k : k]);
-            gb[(size_t)sl * GS + gskew(q)] = v;
+        __builtin_amdgcn_wave_barrier();
+        // all of the round's loads are issued before any is stored: lane sl
+        // < ne fetches entry sl's offsets, shared by shuffles; element u of a
+        // lane is (slot, q) = t + 64 u in slot-major order (the generator
+        // stored unscaled on these levels)
+        int64_t og = t < ne ? ops.o_m2l[eb + t] : 0;
+        int om = t < ne ? ops.m2l_src[eb + t] : 0;
+        cplx pg[kStageG], pa[kStageA];
+        {
+            int sl = 0, q = t;
+            while (q >= glen) { q -= glen; ++sl; }
+#pragma unroll
+            for (int u = 0; u < kStageG; ++u) {
+                int64_t o = __shfl(og, sl < 63 ? sl : 63, 64);
+                int k = q - 2 * P - (kWin - 1);
+                pg[u] = (sl < ne && k >= -2 * P) ? ops.g_m2l[o + k + 2 * P] : mk(0.0, 0.0);
+                q += 64;
+                while (q >= glen) { q -= glen; ++sl; }
+            }
+            sl = 0; q = t;
+            while (q >= nc) { q -= nc; ++sl; }
+#pragma unroll
+            for (int u = 0; u < kStageA; ++u) {
+                int o = __shfl(om, sl < 63 ? sl : 63, 64);
+                pa[u] = sl < ne ? mpole[o + q] : mk(0.0, 0.0);
+                q += 64;
+                while (q >= nc) { q -= nc; ++sl; }
+            }
         }
-        for (int i = t; i < ne * nc; i += 64) {
-            int sl = i / nc, q = i - sl * nc, an = q - P < 0 ? P - q : q - P;
-            ab[(size_t)sl * nc + q] = pw[an] * mpole[ops.m2l_src[eb + sl] + q];
+        {
+            int sl = 0, q = t;
+            while (q >= glen) { q -= glen; ++sl; }
+#pragma unroll
+            for (int u = 0; u < kStageG; ++u) {
+                if (sl < ne) gb[(size_t)sl * GS + gskew(q)] = pg[u];
+                q += 64;
+                while (q >= glen) { q -= glen; ++sl; }
+            }
+            sl = 0; q = t;
+            while (q >= nc) { q -= nc; ++sl; }
+#pragma unroll
+            for (int u = 0; u < kStageA; ++u) {
+                int an = q - P < 0 ? P - q : q - P;
+                if (sl < ne) ab[(size_t)sl * nc + q] = pw[an] * pa[u];
+                q += 64;
+                while (q >= nc) { q -= nc; ++sl; }
+            }
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
         if (act && slot < ne) {
             const cplx* G = gb + (size_t)slot * GS;
             const cplx* A = ab + (size_t)slot * nc;
@@ -580,7 +629,7 @@ __global__ __launch_bounds__(64) void k_h2d_m2l_w(const int* __restrict__ boxes,
             cplx w[kWin];
 #pragma unroll
             for (int c = 1; c < kWin; ++c) w[c] = G[gskew(q0 - c)];
-#pragma unroll 2
+#pragma unroll 4
             for (int n = 0; n < nc; ++n) {
                 w[0] = G[gskew(q0 + n)];
                 cplx av = A[n];
@@ -592,20 +641,21 @@ __global__ __launch_bounds__(64) void k_h2d_m2l_w(const int* __restrict__ boxes,
         }
     }
     __syncthreads();
-    cplx* red = wlds;                             // [E][NG][kWin]
+    cplx* red = wlds_all;                         // [W E][NG][kWin]
+    int gs = wv * E + slot;                       // slot over the workgroup
     if (act)
 #pragma unroll
-        for (int c = 0; c < kWin; ++c) red[((size_t)slot * NG + j) * kWin + c] = acc[c];
+        for (int c = 0; c < kWin; ++c) red[((size_t)gs * NG + j) * kWin + c] = acc[c];
     __syncthreads();
     // thread u = (box, j, c) adds output m0(j) + c of a box over its slots:
     // all slots for a box alone in its group (it may take several rounds),
     // else the slots of its own entries (one round)
-    for (int u = t; u < nbx * NG * kWin; u += 64) {
+    for (int u = threadIdx.x; u < nbx * NG * kWin; u += blockDim.x) {
         int bi = u / (NG * kWin), r = u - bi * NG * kWin;
         int jj = r / kWin, c = r - jj * kWin, m = -P + kWin * jj + c;
         if (m > P) continue;
         int bb = gbox[bi];
-        int s0 = nbx == 1 ? 0 : tv.l2off[bb] - e0, s1 = nbx == 1 ? E : tv.l2off[bb + 1] - e0;
+        int s0 = nbx == 1 ? 0 : tv.l2off[bb] - e0, s1 = nbx == 1 ? W * E : tv.l2off[bb + 1] - e0;
         cplx v = mk(0.0, 0.0);
         for (int sl = s0; sl < s1; ++sl) v += red[((size_t)sl * NG + jj) * kWin + c];
         local[tv.eoff[bb] + m + P] = pw[m < 0 ? -m : m] * v;
@@ -613,12 +663,12 @@ __global__ __launch_bounds__(64) void k_h2d_m2l_w(const int* __restrict__ boxes,
 }
 
 // LDS of k_h2d_m2l_w at expansion length P
-static size_t m2l_w_lds(int P)
+static size_t m2l_w_lds(int P, int W)
 {
     int nc = 2 * P + 1, NG = (nc + kWin - 1) / kWin, E = 64 / NG;
     int glen = 4 * P + 1 + (kWin - 1);
-    size_t stage = (size_t)E * ((size_t)(glen - 1 + ((glen - 1) >> 3) + 1) + nc);
-    size_t red = (size_t)E * NG * kWin;
+    size_t stage = (size_t)W * E * ((size_t)(glen - 1 + ((glen - 1) >> 3) + 1) + nc);
+    size_t red = (size_t)W * E * NG * kWin;
     return sizeof(cplx) * (stage > red ? stage : red);
 }
 
@@ -1297,10 +1347,10 @@ hipError_t h2d_p2m(const int* leaves, int nleaf, int pmax, const TreeView& tv, c
 }
 
 hipError_t h2d_gen_ops(const int* pair_b, int npairs, const int* tr_boxes, int ntr,
-                       const TreeView& tv, double kappa, const int64_t* o_m2l, cplx* g_m2l,
+                       const TreeView& tv, double kappa, int lwin, const int64_t* o_m2l, cplx* g_m2l,
                        const int64_t* o_tr, cplx* g_m2m, cplx* g_l2l, hipStream_t st)
 {
-    if (npairs > 0) k_h2d_gen_m2l<<<(npairs + 63) / 64, 64, 0, st>>>(npairs, pair_b, tv, kappa, o_m2l, g_m2l);
+    if (npairs > 0) k_h2d_gen_m2l<<<(npairs + 63) / 64, 64, 0, st>>>(npairs, pair_b, tv, kappa, lwin, o_m2l, g_m2l);
     if (ntr > 0) k_h2d_gen_tr<<<(ntr + 63) / 64, 64, 0, st>>>(tr_boxes, ntr, tv, kappa, o_tr, g_m2m, g_l2l);
     return hipGetLastError();
 }
@@ -1320,21 +1370,27 @@ hipError_t h2d_m2m(const int* boxes, int nb, int ncoef, const TreeView& tv, cons
 // Entries per round of the window kernel and its LDS at expansion length P,
 // for the plan's grouping of target boxes.
 int h2d_m2l_w_slots(int P) { return 64 / ((2 * P + 1 + kWin - 1) / kWin); }
-size_t h2d_m2l_w_lds(int P) { return m2l_w_lds(P); }
+int h2d_m2l_w_waves() { return kM2LWWaves; }
+size_t h2d_m2l_w_lds(int P, int W) { return m2l_w_lds(P, W); }
 
-// boxes[0 .. nwin) (the levels whose operator fits FP64 unscaled, grouped by
-// grp) take the window kernel; boxes[nwin .. total) the scaled one.
-hipError_t h2d_m2l(const int* boxes, const int2* grp, int ngrp, size_t lds, int nwin, int total,
-                   const TreeView& tv, const H2DOps& ops, const cplx* mpole, cplx* local, hipStream_t st)
+// boxes[0 .. nwin) (the levels whose operator fits FP64 unscaled) take the
+// window kernel: grp[0 .. ngrp1) one wavefront each, grp[ngrp1 .. ngrp)
+// (single boxes with many entries) kM2LWWaves wavefronts each;
+// boxes[nwin .. total) the scaled kernel.
+hipError_t h2d_m2l(const int* boxes, const int2* grp, int ngrp1, int ngrp, size_t lds1, size_t ldsw, int nwin,
+                   int total, const TreeView& tv, const H2DOps& ops, const cplx* mpole, cplx* local,
+                   hipStream_t st)
 {
-    if (ngrp > 0) {
-        if (lds > 65536) {
-            hipError_t e = hipFuncSetAttribute((const void*)k_h2d_m2l_w, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)lds);
-            if (e != hipSuccess) return e;
-        }
-        k_h2d_m2l_w<<<ngrp, 64, lds, st>>>(boxes, grp, ngrp, tv, ops, mpole, local);
+    size_t lmax = std::max(lds1, ldsw);
+    if (ngrp > 0 && lmax > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_h2d_m2l_w, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lmax);
+        if (e != hipSuccess) return e;
     }
+    if (ngrp1 > 0) k_h2d_m2l_w<<<ngrp1, 64, lds1, st>>>(boxes, grp, ngrp1, tv, ops, mpole, local);
+    if (ngrp > ngrp1)
+        k_h2d_m2l_w<<<ngrp - ngrp1, 64 * kM2LWWaves, ldsw, st>>>(boxes, grp + ngrp1, ngrp - ngrp1, tv, ops, mpole,
+                                                                 local);
     if (total > nwin) k_h2d_m2l<<<total - nwin, 64, 0, st>>>(boxes + nwin, total - nwin, tv, ops, mpole, local);
     return hipGetLastError();
 }

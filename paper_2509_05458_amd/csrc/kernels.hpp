@@ -108,7 +108,7 @@ struct H2DOps {
 // 2D Helmholtz evaluation (h2d_kernels.hip)
 hipError_t h2d_init_tables(int device);
 hipError_t h2d_gen_ops(const int* pair_b, int npairs, const int* tr_boxes, int ntr,
-                       const TreeView& tv, double kappa, const int64_t* o_m2l, cplx* g_m2l,
+                       const TreeView& tv, double kappa, int lwin, const int64_t* o_m2l, cplx* g_m2l,
                        const int64_t* o_tr, cplx* g_m2m, cplx* g_l2l, hipStream_t st);
 hipError_t h2d_p2m(const int* leaves, int nleaf, int pmax, const TreeView& tv, const PointsView& pv,
                    double kappa, cplx* mpole, hipStream_t st);
@@ -117,9 +117,11 @@ hipError_t h2d_m2m(const int* boxes, int nb, int ncoef, const TreeView& tv, cons
 // M2L: boxes[0 .. nwin) grouped by grp (first box, count) for the window
 // kernel, boxes[nwin .. total) by the scaled kernel
 int h2d_m2l_w_slots(int P);
-size_t h2d_m2l_w_lds(int P);
-hipError_t h2d_m2l(const int* boxes, const int2* grp, int ngrp, size_t lds, int nwin, int total,
-                   const TreeView& tv, const H2DOps& ops, const cplx* mpole, cplx* local, hipStream_t st);
+int h2d_m2l_w_waves();
+size_t h2d_m2l_w_lds(int P, int W);
+hipError_t h2d_m2l(const int* boxes, const int2* grp, int ngrp1, int ngrp, size_t lds1, size_t ldsw, int nwin,
+                   int total, const TreeView& tv, const H2DOps& ops, const cplx* mpole, cplx* local,
+                   hipStream_t st);
 hipError_t h2d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
                    double kappa, cplx* local, hipStream_t st);
 hipError_t h2d_l2l(const int* boxes, int nb, int ncoef, const TreeView& tv, const H2DOps& ops, cplx* local,
