@@ -233,18 +233,24 @@ def main():
         "near_interactions": nw["interactions"], "near_evaluations": nw["evaluations"],
     }
     if roof_m2l:
-        # k_l3d_m2l: the addition-theorem contraction, (P+1)^2 (Ps+1)^2 complex
-        # multiply-adds (8 flops) per List-2 pair, Ps the pair's source
-        # expansion length (m2l_source_coefs sums (Ps+1)^2 over the pairs)
+        # the M2L translations: point-and-shoot pairs (k_l3d_m2l_pns: four
+        # real rotations per degree, the coaxial shift and the diagonal
+        # phases) and direct-form pairs (k_l3d_m2l: (P+1)^2 (Ps+1)^2 complex
+        # multiply-adds); algorithmic flops of each from cfmm_plan_m2l_work
         P = info["max_p"]
-        m2l_flops = 8.0 * (P + 1) ** 2 * info["m2l_source_coefs"]
-        m2l_peak = PEAK_FP64_VALU if not (a.precision == "mixed" and P <= 16) else PEAK_FP32_VALU
+        mw = plan.m2l_work()
+        m2l_flops = float(mw["direct_flops"] + mw["pns_flops"])
+        mixed_direct = a.precision == "mixed" and P <= 16 and mw["direct_pairs"] > 0
+        m2l_peak = PEAK_FP64_VALU
+        kern = ("k_l3d_m2l_pns + " if mw["pns_pairs"] else "") + ("k_l3d_m2l_f32" if mixed_direct else "k_l3d_m2l")
         roof = {
-            "kernel": "k_l3d_m2l" + ("_f32" if m2l_peak == PEAK_FP32_VALU else ""),
+            "kernel": kern,
             "bound": "alu", "achieved": m2l_flops / (m2l_ms * 1e-3) / 1e12, "peak": m2l_peak / 1e12,
             "unit": "TFLOP/s", "frac": m2l_flops / (m2l_ms * 1e-3) / m2l_peak,
             "traffic": measured_traffic("c2_m2l") if a.precision == "fp64" else None,
             "flops_per_pair_mean": m2l_flops / max(1, info["m2l_pairs"]), "pairs": info["m2l_pairs"],
+            "pns_pairs": mw["pns_pairs"], "direct_pairs": mw["direct_pairs"],
+            "pns_flops": mw["pns_flops"], "direct_flops": mw["direct_flops"],
             "ms_per_launch": m2l_ms,
             "p2p": p2p_block,
         }

@@ -94,6 +94,11 @@ typedef struct {
     void* stream;              /* hipStream_t for all work; NULL: the null stream */
     int leaf_size;             /* N_s, max points per leaf (Sec. 6.1); 0: 64 in 2D, 256 in 3D */
     int separation;            /* k in {1, 2} (Sec. 6.2, Sec. 6.5); 0: 1 in 2D, 2 in 3D */
+    int m2l_form;              /* 3D Laplace M2L (Sec. 5.2): 0 automatic, the point-and-shoot
+                                  form (rotate, coaxial shift, rotate back) for every pair
+                                  whose rotation phases are well conditioned when P <= 15 and
+                                  tol >= 1e-10, the direct addition theorem for the rest;
+                                  1: the direct form for every pair */
 } cfmm_plan_desc;
 
 /* Build a plan: sort, tree, lists, centres, expansion lengths (Sec. 6.1-6.3).
@@ -175,6 +180,15 @@ const char* cfmm_last_error(void);
  *                 evaluation, summed over the List-2 pairs) }
  * The tree, lists and interaction counts are over the tree points. */
 int cfmm_plan_info(cfmm_plan_t plan, int64_t* info20);
+
+/* 3D Laplace M2L work of one evaluation by form (Sec. 5.2): work4 = {pairs
+ * in the direct addition-theorem form, their algorithmic flops, pairs in
+ * the point-and-shoot form, their algorithmic flops}.  Flops: direct
+ * 8 (P+1)^2 (Ps+1)^2 per pair (Ps the pair's source length); point and
+ * shoot 8 per entry of its four per-degree rotations (a real matrix times a
+ * complex vector, two at length Ps and two at P), 4 per entry of the coaxial
+ * shift and 6 per diagonal complex product.  Zeros for the other kernels. */
+int cfmm_plan_m2l_work(cfmm_plan_t plan, int64_t* work4);
 
 /* Wall-clock milliseconds of the plan's phases (Sec. 6.1, 6.2, 6.3), each
  * ended by a stream synchronisation: ms7[0] points to the device, bounding

@@ -52,7 +52,7 @@ class PlanDesc(ctypes.Structure):
                 ("n_trg", ctypes.c_int64), ("trg", ctypes.c_void_p),
                 ("points_on_device", ctypes.c_int), ("precision", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("leaf_size", ctypes.c_int),
-                ("separation", ctypes.c_int)]
+                ("separation", ctypes.c_int), ("m2l_form", ctypes.c_int)]
 
 
 _lib = None
@@ -80,6 +80,7 @@ def lib():
         L.cfmm_plan_bytes.restype = i64
         L.cfmm_last_error.restype = ctypes.c_char_p
         L.cfmm_plan_info.argtypes = [vp, i64p]
+        L.cfmm_plan_m2l_work.argtypes = [vp, i64p]
         L.cfmm_plan_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.cfmm_plan_nterms.argtypes = [vp, ctypes.c_int]
         L.cfmm_plan_near_work.argtypes = [vp, i64p]
@@ -135,12 +136,14 @@ class Plan:
     points: complex128 sources [n_src, dim] (numpy on the host, or a torch
     CUDA tensor).  targets: optional complex128 [n_trg, dim] on the same side;
     without it the targets are the sources and the self term is left out.
+    m2l_form: 3D Laplace M2L form, "auto" (point and shoot where it applies)
+    or "direct" (the addition theorem for every pair).
     Evaluate with ``plan(sigma)`` for any number of densities.
     """
 
     def __init__(self, points, kernel: str = "helmholtz", kappa: float = 0.0,
                  tol: float = 1e-6, precision: str = "fp64", leaf_size: int = 0,
-                 separation: int = 0, stream=None, targets=None):
+                 separation: int = 0, stream=None, targets=None, m2l_form: str = "auto"):
         L = lib()
         self._handle = ctypes.c_void_p()
         src, sptr, n, dim, on_dev = _as_points(points, "points")
@@ -156,7 +159,8 @@ class Plan:
                      wavenumber=float(kappa), tol=float(tol), n_src=n, src=sptr,
                      n_trg=nt, trg=tptr, points_on_device=1 if on_dev else 0,
                      precision={"fp64": FP64, "mixed": MIXED}[precision],
-                     stream=stream or 0, leaf_size=int(leaf_size), separation=int(separation))
+                     stream=stream or 0, leaf_size=int(leaf_size), separation=int(separation),
+                     m2l_form={"auto": 0, "direct": 1}[m2l_form])
         _check(L.cfmm_plan(ctypes.byref(self._handle), ctypes.byref(d)))
         del src, trg
         self.n = n
@@ -262,6 +266,13 @@ class Plan:
                 "n_list4", "p2p_pairs", "m2l_pairs", "max_p", "dim", "kernel", "separation",
                 "leaf_size", "precision", "n_src", "n_trg", "n_points", "m2l_source_coefs")
         return {k: int(v) for k, v in zip(keys, a)}
+
+    def m2l_work(self) -> dict:
+        """3D Laplace M2L pairs and algorithmic flops by form (cfmm_plan_m2l_work)."""
+        a = np.zeros(4, dtype=np.int64)
+        _check(lib().cfmm_plan_m2l_work(self._handle, _ptr(a, ctypes.c_int64)))
+        return {"direct_pairs": int(a[0]), "direct_flops": int(a[1]),
+                "pns_pairs": int(a[2]), "pns_flops": int(a[3])}
 
     def timing(self) -> dict:
         """Wall-clock ms of the plan's phases (cfmm_plan_timing)."""

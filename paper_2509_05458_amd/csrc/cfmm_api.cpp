@@ -156,6 +156,12 @@ struct cfmm_plan_s {
     M2PParts m2p_parts() const { return M2PParts{n_m2p3, d_m2p_owner, d_m2p_poff, d_m2p_part}; }
     int64_t ecount = 0;
     int64_t info[20];
+    // 3D Laplace M2L forms: m2l_form 0 automatic, 1 direct only; the pairs
+    // and algorithmic flops of each form; the boxes with direct-form pairs
+    int m2l_form = 0;
+    int64_t m2l_work[4] = {0, 0, 0, 0};
+    int* d_m2l_dir = nullptr;
+    int n_m2l_dir = 0;
     // plan phases, wall-clock ms: keys and sort, topology, centres and
     // expansion lengths, lists, operator tables and work lists, geometry
     // check and description; [6] the total
@@ -665,6 +671,12 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
             }
             p->l3_pp.p[d] = md;
         }
+        // point-and-shoot M2L where it applies: P within its lane layout,
+        // tol >= 1e-10, and per pair the phases' powers bounded so that
+        // K^(2P) stays below 1e10 tol (K the largest of |e^{+-ia}|,
+        // |e^{+-ib}|; the FP64 error of the rotations grows like K^(2P))
+        p->l3_pp.pns_P = (p->m2l_form == 0 && m <= l3d_pns_max_p() && p->tol >= 1e-10) ? m : 0;
+        p->l3_pp.pns_logb = log(1e10 * p->tol);
         L3dM2LLayout lay = l3d_m2l_layout(m);
         std::vector<int> map(lay.base);
         map.insert(map.end(), lay.slot.begin(), lay.slot.end());
@@ -1053,7 +1065,44 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
             HIPCHK(hipMemcpyAsync(ps.data(), p->d_l3ps, ps.size() * sizeof(int), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
         }
-        for (int v : ps) m2l_src += (int64_t)(v + 1) * (v + 1);
+        // a negative entry marks a point-and-shoot pair (~Ps); algorithmic
+        // flops: direct 8 (P+1)^2 (Ps+1)^2; point and shoot 8 per entry of
+        // the four rotations (real matrix, complex vector: 4 flops per entry,
+        // two rotations at each length), 4 per coaxial entry and 6 per
+        // diagonal complex product (three at each length)
+        auto rot = [](int64_t q) { return (q + 1) * (2 * q + 1) * (2 * q + 3) / 3; };
+        int64_t P1 = pmax + 1;
+        for (int v : ps) {
+            int64_t q = v < 0 ? ~v : v;
+            m2l_src += (q + 1) * (q + 1);
+            if (v >= 0) {
+                p->m2l_work[0] += 1;
+                p->m2l_work[1] += 8 * P1 * P1 * (q + 1) * (q + 1);
+            } else {
+                int64_t cx = 0;
+                for (int64_t k = -q; k <= q; ++k) {
+                    int64_t ak = k < 0 ? -k : k;
+                    cx += (P1 - ak) * (q + 1 - ak);
+                }
+                p->m2l_work[2] += 1;
+                p->m2l_work[3] += 8 * (rot(q) + rot(pmax)) + 4 * cx + 18 * ((q + 1) * (q + 1) + P1 * P1);
+            }
+        }
+        if (p->m2l_work[2] > 0) {
+            // the boxes with direct-form pairs, in the M2L work order
+            std::vector<int> dir;
+            const int* mb = work.data() + p->off_m2l;
+            for (int i = 0; i < p->n_m2l; ++i) {
+                int b = mb[i];
+                for (int e = t.off[1][b]; e < t.off[1][b + 1]; ++e)
+                    if (ps[e] >= 0) {
+                        dir.push_back(b);
+                        break;
+                    }
+            }
+            p->n_m2l_dir = (int)dir.size();
+            if (!dir.empty() && (rc = upload(p, &p->d_m2l_dir, dir))) return rc;
+        }
     } else {
         for (int b = 0; b < nb; ++b) {
             int Ps = p->P[t.level[b]];
@@ -1064,6 +1113,22 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
     HIPCHK(hipStreamSynchronize(st));
     p->clock_mark(5);
     return CFMM_OK;
+}
+
+// 3D Laplace M2L: the point-and-shoot kernel writes every box's local from
+// its pairs of that form, then the direct kernel adds the other pairs on the
+// boxes that have any; with no point-and-shoot pair the direct kernel writes.
+static hipError_t run_l3d_m2l(cfmm_plan_s* p, const TreeView& tv, int P, int mixed, hipStream_t st)
+{
+    const int* W = p->d_work;
+    if (p->m2l_work[2] > 0) {
+        hipError_t e = l3d_m2l_pns(W + p->off_m2l, p->n_m2l, P, tv, p->l3_pairs(), p->d_mpole, p->d_local, st);
+        if (e != hipSuccess) return e;
+        return l3d_m2l(p->d_m2l_dir, p->n_m2l_dir, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, p->l3_pairs(), mixed, 1,
+                       p->d_mpole, p->d_local, st);
+    }
+    return l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, p->l3_pairs(), mixed, 0,
+                   p->d_mpole, p->d_local, st);
 }
 
 int check_finite(cfmm_plan_s* p);
@@ -1098,6 +1163,7 @@ int cfmm_plan(cfmm_plan_t* out, const cfmm_plan_desc* d)
     if (ntot > 0x7fffffffLL) return fail(CFMM_EINVAL, "n_src + n_trg must be below 2^31");
     if (d->leaf_size < 0 || d->leaf_size > 4096) return fail(CFMM_EINVAL, "leaf_size must lie in [0, 4096]");
     if (d->separation < 0 || d->separation > 2) return fail(CFMM_EINVAL, "separation must be 0, 1 or 2");
+    if (d->m2l_form < 0 || d->m2l_form > 1) return fail(CFMM_EINVAL, "m2l_form must be 0 or 1");
     int rc = ensure_device_tables();
     if (rc) return rc;
     cfmm_plan_s* p = new cfmm_plan_s();
@@ -1118,6 +1184,7 @@ int cfmm_plan(cfmm_plan_t* out, const cfmm_plan_desc* d)
     // continued expansions degrades fastest with the Lipschitz constant (Sec. 5.1, 6.5)
     p->sep = d->separation ? d->separation : (d->dim == 3 ? 2 : 1);
     p->leaf_size = d->leaf_size ? d->leaf_size : (d->dim == 2 ? 64 : 256);
+    p->m2l_form = d->m2l_form;
     p->stream = (hipStream_t)d->stream;
     rc = plan_impl(p, d);
     if (rc) {
@@ -1221,8 +1288,7 @@ int cfmm_eval_layer(cfmm_plan_t p, const void* charge, const void* dipole, void*
     if (v) HIPCHK(l3d_p2x_dip(W + p->off_p2m, p->n_p2m, P, 0, tv, pv, p->d_dre, p->d_dim, p->d_mpole, st));
     else HIPCHK(l3d_p2m(W + p->off_p2m, p->n_p2m, P, tv, pv, p->d_mpole, st));
     for (int l = nlev - 2; l >= top; --l) HIPCHK(l3d_m2m(W + p->m2m_off[l], p->m2m_cnt[l], P, tv, p->d_mpole, st));
-    HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, p->l3_pairs(), 0,
-                   p->d_mpole, p->d_local, st));
+    HIPCHK(run_l3d_m2l(p, tv, P, 0, st));
     if (v) HIPCHK(l3d_p2x_dip(W + p->off_p2l, p->n_p2l, P, 1, tv, pv, p->d_dre, p->d_dim, p->d_local, st));
     else HIPCHK(l3d_p2l(W + p->off_p2l, p->n_p2l, P, tv, pv, p->d_local, st));
     for (int l = top + 1; l < nlev; ++l) HIPCHK(l3d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], P, tv, p->d_local, st));
@@ -1442,8 +1508,7 @@ int eval_on_device(cfmm_plan_s* p, const double* sig, double* out)
         // below the requested accuracy
         int m2l32 = p->precision == CFMM_MIXED && p->tol >= 1e-6;
         HIPCHK(mark(8));
-        HIPCHK(l3d_m2l(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, p->l3_pairs(), m2l32,
-                       p->d_mpole, p->d_local, st));
+        HIPCHK(run_l3d_m2l(p, tv, P, m2l32, st));
         HIPCHK(mark(9));
         HIPCHK(l3d_p2l(W + p->off_p2l, p->n_p2l, P, tv, pv, p->d_local, st));
         HIPCHK(mark(4));
@@ -1474,6 +1539,13 @@ int cfmm_destroy(cfmm_plan_t p)
 int64_t cfmm_plan_bytes(cfmm_plan_t p) { return p ? p->bytes : 0; }
 
 const char* cfmm_last_error(void) { return g_err.c_str(); }
+
+int cfmm_plan_m2l_work(cfmm_plan_t p, int64_t* work4)
+{
+    if (!p || !work4) return fail(CFMM_EINVAL, "null argument");
+    for (int i = 0; i < 4; ++i) work4[i] = p->m2l_work[i];
+    return CFMM_OK;
+}
 
 int cfmm_plan_info(cfmm_plan_t p, int64_t* info20)
 {

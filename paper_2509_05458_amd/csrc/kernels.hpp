@@ -169,6 +169,11 @@ hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mp
 // own nearest target distance (d - 1/2) w in place of (k + 1/2) w).
 struct L3PairP {
     int p[8];
+    // point-and-shoot M2L: the expansion length P (0: off) and the bound
+    // P ln(K^2) <= pns_logb on the pair's phases, K the largest of
+    // |e^{+-ia}|, |e^{+-ib}|
+    int pns_P;
+    double pns_logb;
 };
 // The table constants of every List-2 pair of the boxes (5 complex per entry)
 // and its source expansion length, formed once per plan; rows64 / rows32: per
@@ -185,8 +190,15 @@ struct L3Pairs {
 int l3d_m2l_waves(int fp32);
 hipError_t l3d_m2l_pairs(const int* boxes, int nb, const TreeView& tv, const L3PairP& pp, cplx* c, int* ps,
                          int* src, hipStream_t st);
+// The direct-form M2L over the pairs with ps >= 0 (the others are left to
+// l3d_m2l_pns): writes the boxes' locals, or adds to them with accum.
 hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const int* map, int ntab, int R,
-                   const L3Pairs& pr, int mixed, const cplx* mpole, cplx* local, hipStream_t st);
+                   const L3Pairs& pr, int mixed, int accum, const cplx* mpole, cplx* local, hipStream_t st);
+// The point-and-shoot M2L over the pairs with ps < 0 (P <= l3d_pns_max_p()):
+// writes the boxes' locals (zero for a box with no such pair).
+int l3d_pns_max_p();
+hipError_t l3d_m2l_pns(const int* boxes, int nb, int P, const TreeView& tv, const L3Pairs& pr, const cplx* mpole,
+                       cplx* local, hipStream_t st);
 hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st);
 hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& tv,
                         const PointsView& pv, const cplx* mpole, const cplx* local, const M2PParts& m2p,

@@ -425,10 +425,12 @@ __device__ inline int pair_terms(const L3PairP& pp, const cplx* cb, const cplx* 
     return pp.p[d < 7 ? d : 7];
 }
 
-// Per List-2 pair (entry e of the target box's list), once per plan: the
-// constants of its table, c[5e..5e+4] = 1/r2, 1/rho, z/r2, w+/r2, w-/r2 at the
-// scaled offset D / w = (c_target - c_source) / w, its source expansion
-// length ps[e] and the offset src[e] of the source box's multipole.
+// Per List-2 pair (entry e of the target box's list), once per plan, at the
+// scaled offset D / w = (c_target - c_source) / w: the offset src[e] of the
+// source box's multipole and the pair's source expansion length Ps.  A pair
+// the point-and-shoot kernel takes gets ps[e] = ~Ps (negative) and
+// c[5e..5e+4] = e^{ia}, e^{-ia}, e^{ib}, e^{-ib}, 1/rho; any other pair
+// ps[e] = Ps and the constants of its table, 1/r2, 1/rho, z/r2, w+/r2, w-/r2.
 __global__ __launch_bounds__(64) void k_l3d_m2l_pairs(const int* __restrict__ boxes, TreeView tv, L3PairP pp,
                                                       cplx* __restrict__ c, int* __restrict__ ps,
                                                       int* __restrict__ src)
@@ -445,13 +447,35 @@ __global__ __launch_bounds__(64) void k_l3d_m2l_pairs(const int* __restrict__ bo
         d.x = (cb[0] - ca[0]) * s; d.y = (cb[1] - ca[1]) * s; d.z = (cb[2] - ca[2]) * s;
         cplx r2 = dot3(d);
         cplx ir2 = cinv(r2);
+        int Ps = pair_terms(pp, cb, ca, s);
+        src[e] = tv.eoff[a];
+        if (pp.pns_P > 0) {
+            // point and shoot: D = rho (sin b cos a, sin b sin a, cos b) at
+            // complex angles, e^{ia} = w+ / s, e^{ib} = (z + i s) / rho with
+            // s^2 = x^2 + y^2; taken where the phases' powers stay bounded
+            cplx rho = csqrt_p(r2), sq = csqrt_p(d.x * d.x + d.y * d.y);
+            if (cabs2(sq) > 1e-24 * cabs2(r2)) {
+                cplx is = cinv(sq), irho = cinv(rho);
+                cplx ea = wplus(d) * is, iea = wminus(d) * is;
+                cplx eb = (d.z + times_i(sq)) * irho, ieb = (d.z - times_i(sq)) * irho;
+                double k2 = fmax(fmax(cabs2(ea), cabs2(iea)), fmax(cabs2(eb), cabs2(ieb)));
+                if ((double)pp.pns_P * log(k2) <= pp.pns_logb) {
+                    c[5 * (size_t)e + 0] = ea;
+                    c[5 * (size_t)e + 1] = iea;
+                    c[5 * (size_t)e + 2] = eb;
+                    c[5 * (size_t)e + 3] = ieb;
+                    c[5 * (size_t)e + 4] = irho;
+                    ps[e] = ~Ps;
+                    continue;
+                }
+            }
+        }
         c[5 * (size_t)e + 0] = ir2;
         c[5 * (size_t)e + 1] = cinv(csqrt_p(r2));
         c[5 * (size_t)e + 2] = d.z * ir2;
         c[5 * (size_t)e + 3] = wplus(d) * ir2;
         c[5 * (size_t)e + 4] = wminus(d) * ir2;
-        ps[e] = pair_terms(pp, cb, ca, s);
-        src[e] = tv.eoff[a];
+        ps[e] = Ps;
     }
 }
 
@@ -495,7 +519,7 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
                                                  const cplx* __restrict__ pc, const int* __restrict__ pps,
                                                  const int* __restrict__ psrc, const unsigned* __restrict__ rows64,
                                                  const cplx* __restrict__ mpole,
-                                                 cplx* __restrict__ local)
+                                                 cplx* __restrict__ local, int accum)
 {
     extern __shared__ cplx16 tab16[];
     int b = boxes[xcd_contiguous(blockIdx.x, nboxes)];
@@ -526,10 +550,12 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
     int e0 = __builtin_amdgcn_readfirstlane(tv.l2off[b]);
     int e1 = __builtin_amdgcn_readfirstlane(tv.l2off[b + 1]);
     for (int e = e0; e < e1; ++e) {
-        const cplx* M = mpole + psrc[e];
         // source orders n <= Ps of this pair: rows l = j + n <= P + Ps of the
-        // table; this wavefront contracts the rows n of its mask
+        // table; this wavefront contracts the rows n of its mask.  Pairs of
+        // the point-and-shoot kernel (Ps < 0) are left to it.
         int Ps = pps[e];
+        if (Ps < 0) continue;
+        const cplx* M = mpole + psrc[e];
         int Lt = P + Ps;
         unsigned rows = rows64[Ps * kM2LWaves + wv];
         __syncthreads();
@@ -585,6 +611,7 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_l3d_m2l(const int* __restric
             if (k > j) break;
             cplx v = acc[r][c];
             if ((j + k) & 1) v = -v;
+            if (accum) v += o[nm(j, k)];
             o[nm(j, k)] = v;
         }
     }
@@ -604,7 +631,7 @@ __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __
                                                      const int* __restrict__ psrc,
                                                      const unsigned* __restrict__ rows32,
                                                      const cplx* __restrict__ mpole,
-                                                     cplx* __restrict__ local)
+                                                     cplx* __restrict__ local, int accum)
 {
     extern __shared__ float2 tabf[];
     int b = boxes[xcd_contiguous(blockIdx.x, nboxes)];
@@ -634,8 +661,9 @@ __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __
     int e0 = __builtin_amdgcn_readfirstlane(tv.l2off[b]);
     int e1 = __builtin_amdgcn_readfirstlane(tv.l2off[b + 1]);
     for (int e = e0; e < e1; ++e) {
-        const cplx* M = mpole + psrc[e];
         int Ps = pps[e];
+        if (Ps < 0) continue;                 // a point-and-shoot pair
+        const cplx* M = mpole + psrc[e];
         int Lt = P + Ps, ncp = (Ps + 1) * (Ps + 1);
         unsigned rows = rows32[Ps * kM2LWavesF32 + wv];   // this wavefront's rows n
         __syncthreads();
@@ -715,9 +743,162 @@ __global__ __launch_bounds__(64 * kM2LWavesF32) void k_l3d_m2l_f32(const int* __
             if (k > j) break;
             cplx v = acc[r][c];
             if ((j + k) & 1) v = -v;
+            if (accum) v += o[nm(j, k)];
             o[nm(j, k)] = v;
         }
     }
+}
+
+// ------------------------------------------------- M2L by point and shoot
+// Sec. 5.2: rotate the multipole so that the offset D lies on the z axis,
+// translate along it, rotate the local back.  In the orthonormal scaling
+// Mh_n^m = c_n^m M_n^m, Lh_j^k = L_j^k / c_j^k with c_n^m = sqrt((n-m)!(n+m)!),
+// a rotation about z multiplies order m by a phase, and a rotation about y by
+// angle b is Y diag(e^{-imb}) Y^T with Y^n = d^n(pi/2), a fixed real orthogonal
+// matrix per degree (Wigner's; Y^n_{m m'} = (-1)^{m-m'} Y^n_{m' m}).  With
+// D = rho (sin b cos a, sin b sin a, cos b) at complex angles, one pair is
+//   x0 = (-i)^m e^{ima} Mh,  x1 = Y^T x0,  x2 = e^{imb} x1,  x3 = Y x2,
+//   y0_j^k = sum_n Zh^k_{jn} rho^-(j+n+1) x3_n^k,
+//   Zh^k_{jn} = (-1)^{j+k} (j+n)! / sqrt((j-k)!(j+k)!(n-k)!(n+k)!)   (coaxial),
+//   y1 = Y^T y0,  y2 = e^{-imb} y1,  y3 = Y y2,  Lh += i^k e^{-ika} y3,
+// every dense step a real matrix per degree, the same for all pairs; only the
+// phases and the powers of 1/rho belong to the pair.  One workgroup of 256
+// threads per target box, thread t = n^2 + n + m owning coefficient (n, m)
+// (P <= 15); its column of Y^n and its row of Zh stay in registers, the
+// stages pass the coefficient vector through LDS.
+constexpr int kPnsMaxP = 15;
+constexpr int kPnsY = (kPnsMaxP + 1) * (2 * kPnsMaxP + 1) * (2 * kPnsMaxP + 3) / 3;
+__device__ double g_pns_y[kPnsY];                                      // columns of Y^n, packed
+__device__ double g_pns_z[(kPnsMaxP + 1) * (2 * kPnsMaxP + 1) * (kPnsMaxP + 1)];   // [j][k + 15][n - |k|]
+__device__ double g_pns_c[(kPnsMaxP + 1) * (kPnsMaxP + 1)];            // c_n^m at n^2 + n + m
+
+// base of degree n's columns in g_pns_y: sum_{n' < n} (2n' + 1)^2
+__host__ __device__ constexpr int pns_ybase(int n) { return n * (2 * n - 1) * (2 * n + 1) / 3; }
+
+// z^q for 0 <= q < 32 by binary powers
+__device__ inline cplx cpow_small(cplx z, int q)
+{
+    cplx r = mk(1.0, 0.0);
+    while (q) {
+        if (q & 1) r = r * z;
+        q >>= 1;
+        if (q) z = z * z;
+    }
+    return r;
+}
+
+// sum_{m'} Y^n_{m' m} x_{m'} (T) or sum_{m'} Y^n_{m m'} x_{m'}, from the column
+// yc[s] = Y^n_{s-n, m} (zero past s = 2n) and x at xs[s] = x_{s-n}.  Steps
+// run in blocks of eight up to the wavefront's largest 2n (nw, uniform) with
+// no per-lane branch: a lane's steps past 2n read finite entries of the next
+// degrees and multiply them by zero, so the block's loads issue together.
+template <int PM, bool T>
+__device__ inline cplx pns_rot(const double (&yc)[2 * PM + 1], const cplx* xs, int n, int m, int nw)
+{
+    // four independent accumulation chains, by s mod 4
+    cplx a[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+#pragma unroll
+    for (int s0 = 0; s0 <= 2 * PM; s0 += 8) {
+        if (s0 <= 2 * nw) {
+#pragma unroll
+            for (int s = s0; s < s0 + 8 && s <= 2 * PM; ++s) {
+                cplx x = xs[s];
+                a[s & 3].re = fma(yc[s], x.re, a[s & 3].re);
+                a[s & 3].im = fma(yc[s], x.im, a[s & 3].im);
+            }
+        }
+    }
+    if (T) return (a[0] + a[2]) + (a[1] + a[3]);
+    // Y_{m m'} = (-1)^{m - m'} Y_{m' m}, (-1)^{m'} = (-1)^{s - n}
+    cplx v = (a[0] + a[2]) - (a[1] + a[3]);
+    return ((m + n) & 1) ? -v : v;
+}
+
+template <int PM>
+__global__ __launch_bounds__(256) void k_l3d_m2l_pns(const int* __restrict__ boxes, int nboxes, TreeView tv,
+                                                     const cplx* __restrict__ pc, const int* __restrict__ pps,
+                                                     const int* __restrict__ psrc,
+                                                     const cplx* __restrict__ mpole, cplx* __restrict__ local)
+{
+    __shared__ cplx bufA[256], bufB[256];
+    __shared__ cplx tEa[2 * PM + 1], tEb[2 * PM + 1], tR[PM + 2];
+    int b = boxes[xcd_contiguous(blockIdx.x, nboxes)];
+    int P = tv.P[tv.level[b]];
+    int t = threadIdx.x;
+    int n = (int)sqrtf((float)t);
+    while (n * n > t) --n;
+    while ((n + 1) * (n + 1) <= t) ++n;
+    int m = t - n * n - n, am = m < 0 ? -m : m;
+    bool on = n <= P;
+    // the largest degree among this wavefront's coefficients (uniform)
+    int tw = min((t | 63), (P + 1) * (P + 1) - 1);
+    int nw = (int)sqrtf((float)tw);
+    while (nw * nw > tw) --nw;
+    while ((nw + 1) * (nw + 1) <= tw) ++nw;
+    nw = __builtin_amdgcn_readfirstlane(nw);
+    double yc[2 * PM + 1], zr[PM + 1];
+#pragma unroll
+    for (int s = 0; s <= 2 * PM; ++s) yc[s] = (on && s <= 2 * n) ? g_pns_y[pns_ybase(n) + (m + n) * (2 * n + 1) + s] : 0.0;
+#pragma unroll
+    for (int i = 0; i <= PM; ++i)
+        zr[i] = (on && am + i <= P) ? g_pns_z[(n * (2 * kPnsMaxP + 1) + m + kPnsMaxP) * (kPnsMaxP + 1) + i] : 0.0;
+    double cn = on ? g_pns_c[t] : 0.0;
+    cplx acc = mk(0.0, 0.0);
+    // every entry a stage may read stays finite: zero at the start, and the
+    // degrees past a pair's source length are zeroed before the coaxial step
+    bufA[t] = mk(0.0, 0.0);
+    bufB[t] = mk(0.0, 0.0);
+    int e0 = __builtin_amdgcn_readfirstlane(tv.l2off[b]);
+    int e1 = __builtin_amdgcn_readfirstlane(tv.l2off[b + 1]);
+    for (int e = e0; e < e1; ++e) {
+        int Ps = pps[e];
+        if (Ps >= 0) continue;                // a direct-form pair
+        Ps = ~Ps;
+        bool src_on = on && n <= Ps;
+        cplx mv = src_on ? mpole[psrc[e] + t] : mk(0.0, 0.0);
+        const cplx* k = pc + 5 * (size_t)e;
+        __syncthreads();                      // the previous pair's last stage has read bufA and the tables
+        if (t < 2 * P + 1) {
+            int q = t - P, aq = q < 0 ? -q : q;
+            cplx ea = cpow_small(q < 0 ? k[1] : k[0], aq);
+            // (-i)^q
+            int r4 = q & 3;
+            cplx ph = r4 == 0 ? mk(1.0, 0.0) : r4 == 1 ? mk(0.0, -1.0) : r4 == 2 ? mk(-1.0, 0.0) : mk(0.0, 1.0);
+            tEa[t] = ph * ea;
+            tEb[t] = cpow_small(q < 0 ? k[3] : k[2], aq);
+        } else if (t >= 64 && t < 64 + P + 2) {
+            tR[t - 64] = cpow_small(k[4], t - 64);
+        }
+        __syncthreads();
+        if (src_on) bufA[t] = tEa[m + P] * (cn * mv);
+        __syncthreads();
+        if (src_on) bufB[t] = pns_rot<PM, true>(yc, bufA + n * n, n, m, min(nw, Ps)) * tEb[m + P];
+        __syncthreads();
+        if (on) bufA[t] = src_on ? pns_rot<PM, false>(yc, bufB + n * n, n, m, min(nw, Ps)) * tR[n] : mk(0.0, 0.0);
+        __syncthreads();
+        if (on) {
+            // coaxial: sum over source degrees nn = |m| .. Ps of order m
+            cplx v = mk(0.0, 0.0);
+            int ix = am * am + am + m;
+            // degrees past Ps hold zeros, past P zero factors; the index is
+            // clamped to the buffer
+#pragma unroll
+            for (int i = 0; i <= PM; ++i) {
+                if (i <= Ps) {
+                    cplx x = bufA[min(ix, 255)];
+                    v.re = fma(zr[i], x.re, v.re);
+                    v.im = fma(zr[i], x.im, v.im);
+                }
+                ix += 2 * (am + i) + 2;
+            }
+            bufB[t] = v * tR[n + 1];
+        }
+        __syncthreads();
+        if (on) bufA[t] = pns_rot<PM, true>(yc, bufB + n * n, n, m, nw) * tEb[P - m];
+        __syncthreads();
+        if (on) acc += pns_rot<PM, false>(yc, bufA + n * n, n, m, nw) * tEa[P - m];
+    }
+    if (on) local[tv.eoff[b] + t] = cn * acc;
 }
 
 // ------------------------------------------------------------------ L2L
@@ -1235,7 +1416,47 @@ hipError_t l3d_init_tables(int device)
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_lrr), rr, sizeof(rr))) != hipSuccess) return e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_ldg), dg, sizeof(dg))) != hipSuccess) return e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_lodd), odd, sizeof(odd))) != hipSuccess) return e;
-    return hipMemcpyToSymbol(HIP_SYMBOL(c_lka), ka, sizeof(ka));
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_lka), ka, sizeof(ka))) != hipSuccess) return e;
+    // point-and-shoot tables, in extended precision: Wigner's
+    //   d^n_{m m'}(pi/2) = 2^-n sqrt((n+m)!(n-m)!(n+m')!(n-m')!)
+    //                      sum_k (-1)^(k-m'+m) / ((n+m'-k)! k! (n-k-m)! (k-m'+m)!)
+    // (its cancellation costs about three digits at n = 15, which the 64-bit
+    // mantissa absorbs), the coaxial factors and the scaling c_n^m
+    static double ty[kPnsY], tz[(kPnsMaxP + 1) * (2 * kPnsMaxP + 1) * (kPnsMaxP + 1)],
+        tc[(kPnsMaxP + 1) * (kPnsMaxP + 1)];
+    long double fac[2 * kPnsMaxP + 2];
+    fac[0] = 1.0L;
+    for (int i = 1; i < 2 * kPnsMaxP + 2; ++i) fac[i] = fac[i - 1] * i;
+    for (int n = 0; n <= kPnsMaxP; ++n)
+        for (int m = -n; m <= n; ++m) {
+            tc[n * n + n + m] = (double)sqrtl(fac[n - m] * fac[n + m]);
+            for (int r = -n; r <= n; ++r) {
+                // column m, row r: d^n_{r m}
+                long double sum = 0.0L;
+                for (int k = 0; k <= 2 * n; ++k) {
+                    int a = n + m - k, c = n - k - r, d = k - m + r;
+                    if (a < 0 || c < 0 || d < 0) continue;
+                    long double term = 1.0L / (fac[a] * fac[k] * fac[c] * fac[d]);
+                    sum += ((k - m + r) & 1) ? -term : term;
+                }
+                long double v = sum * sqrtl(fac[n + r] * fac[n - r] * fac[n + m] * fac[n - m]) / powl(2.0L, n);
+                ty[pns_ybase(n) + (m + n) * (2 * n + 1) + (r + n)] = (double)v;
+            }
+        }
+    for (int j = 0; j <= kPnsMaxP; ++j)
+        for (int k = -kPnsMaxP; k <= kPnsMaxP; ++k)
+            for (int i = 0; i <= kPnsMaxP; ++i) {
+                int nn = (k < 0 ? -k : k) + i;
+                double v = 0.0;
+                if ((k < 0 ? -k : k) <= j && nn <= kPnsMaxP) {
+                    long double z = fac[j + nn] / sqrtl(fac[j - k] * fac[j + k] * fac[nn - k] * fac[nn + k]);
+                    v = (double)(((j + k) & 1) ? -z : z);
+                }
+                tz[(j * (2 * kPnsMaxP + 1) + k + kPnsMaxP) * (kPnsMaxP + 1) + i] = v;
+            }
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_pns_y), ty, sizeof(ty))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_pns_z), tz, sizeof(tz))) != hipSuccess) return e;
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_pns_c), tc, sizeof(tc));
 }
 
 hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mpole, hipStream_t st)
@@ -1247,7 +1468,7 @@ hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mp
 
 template <int R>
 static hipError_t launch_m2l(const int* boxes, int nb, size_t lds, const TreeView& tv, const int* map, int ntab,
-                             const L3Pairs& pr, const cplx* mpole, cplx* local, hipStream_t st)
+                             const L3Pairs& pr, const cplx* mpole, cplx* local, int accum, hipStream_t st)
 {
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_l3d_m2l<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1255,7 +1476,7 @@ static hipError_t launch_m2l(const int* boxes, int nb, size_t lds, const TreeVie
         if (e != hipSuccess) return e;
     }
     k_l3d_m2l<R><<<nb, 64 * kM2LWaves, lds, st>>>(boxes, nb, tv, map, ntab, pr.c, pr.ps, pr.src, pr.rows64, mpole,
-                                                  local);
+                                                  local, accum);
     return hipGetLastError();
 }
 
@@ -1281,7 +1502,8 @@ size_t l3d_m2l_lds(int P, int ntab)
 
 template <int R>
 static hipError_t launch_m2l_f32(const int* boxes, int nb, size_t lds, const TreeView& tv, const int* map,
-                                 int ntab, const L3Pairs& pr, const cplx* mpole, cplx* local, hipStream_t st)
+                                 int ntab, const L3Pairs& pr, const cplx* mpole, cplx* local, int accum,
+                                 hipStream_t st)
 {
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_l3d_m2l_f32<R>,
@@ -1289,7 +1511,7 @@ static hipError_t launch_m2l_f32(const int* boxes, int nb, size_t lds, const Tre
         if (e != hipSuccess) return e;
     }
     k_l3d_m2l_f32<R><<<nb, 64 * kM2LWavesF32, lds, st>>>(boxes, nb, tv, map, ntab, pr.c, pr.ps, pr.src,
-                                                         pr.rows32, mpole, local);
+                                                         pr.rows32, mpole, local, accum);
     return hipGetLastError();
 }
 
@@ -1302,7 +1524,7 @@ hipError_t l3d_m2l_pairs(const int* boxes, int nb, const TreeView& tv, const L3P
 }
 
 hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const int* map, int ntab, int R,
-                   const L3Pairs& pr, int mixed, const cplx* mpole, cplx* local, hipStream_t st)
+                   const L3Pairs& pr, int mixed, int accum, const cplx* mpole, cplx* local, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
     if (mixed && P <= kM2LF32MaxP) {
@@ -1310,20 +1532,34 @@ hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const in
                                   (size_t)(2 * P + 1) * sizeof(int),
                               m2l_red_bytes(R, kM2LWavesF32));
         switch (R) {
-        case 1: return launch_m2l_f32<1>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
-        case 2: return launch_m2l_f32<2>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
+        case 1: return launch_m2l_f32<1>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, accum, st);
+        case 2: return launch_m2l_f32<2>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, accum, st);
         default: return hipErrorInvalidValue;
         }
     }
     size_t lds = l3d_m2l_lds(P, ntab);
     switch (R) {
-    case 1: return launch_m2l<1>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
-    case 2: return launch_m2l<2>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
-    case 3: return launch_m2l<3>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
-    case 4: return launch_m2l<4>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
-    case 5: return launch_m2l<5>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, st);
+    case 1: return launch_m2l<1>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, accum, st);
+    case 2: return launch_m2l<2>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, accum, st);
+    case 3: return launch_m2l<3>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, accum, st);
+    case 4: return launch_m2l<4>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, accum, st);
+    case 5: return launch_m2l<5>(boxes, nb, lds, tv, map, ntab, pr, mpole, local, accum, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+int l3d_pns_max_p() { return kPnsMaxP; }
+
+hipError_t l3d_m2l_pns(const int* boxes, int nb, int P, const TreeView& tv, const L3Pairs& pr, const cplx* mpole,
+                       cplx* local, hipStream_t st)
+{
+    if (nb <= 0) return hipSuccess;
+    if (P > kPnsMaxP) return hipErrorInvalidValue;
+    if (P <= 10) k_l3d_m2l_pns<10><<<nb, 256, 0, st>>>(boxes, nb, tv, pr.c, pr.ps, pr.src, mpole, local);
+    else if (P <= 12) k_l3d_m2l_pns<12><<<nb, 256, 0, st>>>(boxes, nb, tv, pr.c, pr.ps, pr.src, mpole, local);
+    else if (P <= 14) k_l3d_m2l_pns<14><<<nb, 256, 0, st>>>(boxes, nb, tv, pr.c, pr.ps, pr.src, mpole, local);
+    else k_l3d_m2l_pns<15><<<nb, 256, 0, st>>>(boxes, nb, tv, pr.c, pr.ps, pr.src, mpole, local);
+    return hipGetLastError();
 }
 
 hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st)
