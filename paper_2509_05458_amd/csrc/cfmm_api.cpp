@@ -162,6 +162,8 @@ struct cfmm_plan_s {
     int64_t m2l_work[4] = {0, 0, 0, 0};
     int* d_m2l_dir = nullptr;
     int n_m2l_dir = 0;
+    int* d_pns_off = nullptr;     // per box: its point-and-shoot pairs ent[off[b] .. off[b+1]-1]
+    int4* d_pns_ent = nullptr;    // (List-2 entry, source expansion offset, Ps, 0)
     // plan phases, wall-clock ms: keys and sort, topology, centres and
     // expansion lengths, lists, operator tables and work lists, geometry
     // check and description; [6] the total
@@ -1089,8 +1091,17 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
             }
         }
         if (p->m2l_work[2] > 0) {
-            // the boxes with direct-form pairs, in the M2L work order
-            std::vector<int> dir;
+            // the boxes with direct-form pairs, in the M2L work order, and
+            // every box's point-and-shoot pairs in list order
+            std::vector<int> dir, poff(nb + 1, 0);
+            std::vector<int4> pent;
+            pent.reserve((size_t)p->m2l_work[2]);
+            for (int b = 0; b < nb; ++b) {
+                poff[b] = (int)pent.size();
+                for (int e = t.off[1][b]; e < t.off[1][b + 1]; ++e)
+                    if (ps[e] < 0) pent.push_back(make_int4(e, eoff[t.idx[1][e]], ~ps[e], 0));
+            }
+            poff[nb] = (int)pent.size();
             const int* mb = work.data() + p->off_m2l;
             for (int i = 0; i < p->n_m2l; ++i) {
                 int b = mb[i];
@@ -1102,6 +1113,7 @@ int plan_impl(cfmm_plan_s* p, const cfmm_plan_desc* d)
             }
             p->n_m2l_dir = (int)dir.size();
             if (!dir.empty() && (rc = upload(p, &p->d_m2l_dir, dir))) return rc;
+            if ((rc = upload(p, &p->d_pns_off, poff)) || (rc = upload(p, &p->d_pns_ent, pent))) return rc;
         }
     } else {
         for (int b = 0; b < nb; ++b) {
@@ -1122,7 +1134,8 @@ static hipError_t run_l3d_m2l(cfmm_plan_s* p, const TreeView& tv, int P, int mix
 {
     const int* W = p->d_work;
     if (p->m2l_work[2] > 0) {
-        hipError_t e = l3d_m2l_pns(W + p->off_m2l, p->n_m2l, P, tv, p->l3_pairs(), p->d_mpole, p->d_local, st);
+        hipError_t e = l3d_m2l_pns(W + p->off_m2l, p->n_m2l, P, tv, p->d_l3pc, p->d_pns_off, p->d_pns_ent,
+                                   p->d_mpole, p->d_local, st);
         if (e != hipSuccess) return e;
         return l3d_m2l(p->d_m2l_dir, p->n_m2l_dir, P, tv, p->d_l3map, p->l3_ntab, p->l3_R, p->l3_pairs(), mixed, 1,
                        p->d_mpole, p->d_local, st);

@@ -194,11 +194,13 @@ hipError_t l3d_m2l_pairs(const int* boxes, int nb, const TreeView& tv, const L3P
 // l3d_m2l_pns): writes the boxes' locals, or adds to them with accum.
 hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const int* map, int ntab, int R,
                    const L3Pairs& pr, int mixed, int accum, const cplx* mpole, cplx* local, hipStream_t st);
-// The point-and-shoot M2L over the pairs with ps < 0 (P <= l3d_pns_max_p()):
-// writes the boxes' locals (zero for a box with no such pair).
+// The point-and-shoot M2L over the pairs with ps < 0 (P <= l3d_pns_max_p()),
+// listed per box b as ent[off[b] .. off[b+1]-1] = (List-2 entry, source
+// expansion offset, Ps, 0): writes the boxes' locals (zero for a box with no
+// such pair).
 int l3d_pns_max_p();
-hipError_t l3d_m2l_pns(const int* boxes, int nb, int P, const TreeView& tv, const L3Pairs& pr, const cplx* mpole,
-                       cplx* local, hipStream_t st);
+hipError_t l3d_m2l_pns(const int* boxes, int nb, int P, const TreeView& tv, const cplx* pc, const int* off,
+                       const int4* ent, const cplx* mpole, cplx* local, hipStream_t st);
 hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st);
 hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& tv,
                         const PointsView& pv, const cplx* mpole, const cplx* local, const M2PParts& m2p,

@@ -771,6 +771,7 @@ constexpr int kPnsY = (kPnsMaxP + 1) * (2 * kPnsMaxP + 1) * (2 * kPnsMaxP + 3) /
 __device__ double g_pns_y[kPnsY];                                      // columns of Y^n, packed
 __device__ double g_pns_z[(kPnsMaxP + 1) * (2 * kPnsMaxP + 1) * (kPnsMaxP + 1)];   // [j][k + 15][n - |k|]
 __device__ double g_pns_c[(kPnsMaxP + 1) * (kPnsMaxP + 1)];            // c_n^m at n^2 + n + m
+__device__ double g_pns_fact[2 * kPnsMaxP + 1];                         // i!
 
 // base of degree n's columns in g_pns_y: sum_{n' < n} (2n' + 1)^2
 __host__ __device__ constexpr int pns_ybase(int n) { return n * (2 * n - 1) * (2 * n + 1) / 3; }
@@ -787,13 +788,17 @@ __device__ inline cplx cpow_small(cplx z, int q)
     return r;
 }
 
-// sum_{m'} Y^n_{m' m} x_{m'} (T) or sum_{m'} Y^n_{m m'} x_{m'}, from the column
-// yc[s] = Y^n_{s-n, m} (zero past s = 2n) and x at xs[s] = x_{s-n}.  Steps
-// run in blocks of eight up to the wavefront's largest 2n (nw, uniform) with
-// no per-lane branch: a lane's steps past 2n read finite entries of the next
-// degrees and multiply them by zero, so the block's loads issue together.
-template <int PM, bool T>
-__device__ inline cplx pns_rot(const double (&yc)[2 * PM + 1], const cplx* xs, int n, int m, int nw)
+// The even and odd halves (in s) of sum_s yc[s] x_{s-n}, yc[s] = Y^n_{s-n, m}
+// (zero past s = 2n), x at xs[s].  Steps run in blocks of eight up to the
+// wavefront's largest 2n (nw, uniform) with no per-lane branch: a lane's
+// steps past 2n read finite entries of the next degrees and multiply them by
+// zero, so the block's loads issue together.  With the symmetries of
+// d^n(pi/2), Y_{m' -m} = (-1)^{n+m'} Y_{m' m} and Y_{m m'} = (-1)^{m-m'} Y_{m' m},
+// both orders +m and -m of both products follow from the two halves E, O:
+//   (Y^T x)_{+m} = E + O,  (Y^T x)_{-m} = E - O,
+//   (Y x)_{+m} = (-1)^{m+n} (E - O),  (Y x)_{-m} = (-1)^{m+n} (E + O).
+template <int PM>
+__device__ inline void pns_halves(const double (&yc)[2 * PM + 1], const cplx* xs, int nw, cplx& E, cplx& O)
 {
     // four independent accumulation chains, by s mod 4
     cplx a[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
@@ -808,97 +813,202 @@ __device__ inline cplx pns_rot(const double (&yc)[2 * PM + 1], const cplx* xs, i
             }
         }
     }
-    if (T) return (a[0] + a[2]) + (a[1] + a[3]);
-    // Y_{m m'} = (-1)^{m - m'} Y_{m' m}, (-1)^{m'} = (-1)^{s - n}
-    cplx v = (a[0] + a[2]) - (a[1] + a[3]);
-    return ((m + n) & 1) ? -v : v;
+    E = a[0] + a[2];
+    O = a[1] + a[3];
 }
 
-template <int PM>
-__global__ __launch_bounds__(256) void k_l3d_m2l_pns(const int* __restrict__ boxes, int nboxes, TreeView tv,
-                                                     const cplx* __restrict__ pc, const int* __restrict__ pps,
-                                                     const int* __restrict__ psrc,
-                                                     const cplx* __restrict__ mpole, cplx* __restrict__ local)
+// Phase tables of one pair: tEa[q + P] = (-i)^q e^{iqa}, tEb[q + P] = e^{iqb}
+// (|q| <= P), tR[i] = rho^-i (i <= P + 1), from this lane's prefetched
+// constant (lanes 0..2P: e^{+-ia} and e^{+-ib} by the sign of q; lanes
+// 64..64+P+1: 1/rho).
+__device__ inline void pns_tables(int t, int P, cplx ka, cplx kb, cplx* tEa, cplx* tEb, cplx* tR)
 {
-    __shared__ cplx bufA[256], bufB[256];
-    __shared__ cplx tEa[2 * PM + 1], tEb[2 * PM + 1], tR[PM + 2];
+    if (t < 2 * P + 1) {
+        int q = t - P, aq = q < 0 ? -q : q;
+        int r4 = q & 3;
+        cplx ph = r4 == 0 ? mk(1.0, 0.0) : r4 == 1 ? mk(0.0, -1.0) : r4 == 2 ? mk(-1.0, 0.0) : mk(0.0, 1.0);
+        tEa[t] = ph * cpow_small(ka, aq);
+        tEb[t] = cpow_small(kb, aq);
+    } else if (t >= 64 && t < 64 + P + 2) {
+        tR[t - 64] = cpow_small(ka, t - 64);
+    }
+}
+
+// The constants a lane of pns_tables needs for pair entry e.
+__device__ inline void pns_consts(int t, int P, const cplx* __restrict__ pc, int e, cplx& ka, cplx& kb)
+{
+    const cplx* k = pc + 5 * (size_t)e;
+    bool lo = t < 2 * P + 1, hi = t >= 64 && t < 64 + P + 2;
+    int ia = hi ? 4 : (t < P ? 1 : 0), ib = t < P ? 3 : 2;
+    if (lo || hi) ka = k[ia];
+    if (lo) kb = k[ib];
+}
+
+// The pairs of a box run as a pipeline of five barrier-separated phases:
+//   A: stage 6 of the previous pair | stage 1 of this one,  B: stage 2,
+//   C: stage 3,  D: coaxial shift,  E: stage 5 | the next pair's phase tables.
+// Pair p writes its stages into buf[p & 1], buf[p & 1 ^ 1], ... alternately and
+// reads its tables from slot p & 1, so phase A's two halves touch disjoint
+// buffers; the next pair's multipole and constants are loaded into registers
+// one pair ahead.  Thread u = n (n + 1) / 2 + m owns the coefficients (n, +m)
+// and (n, -m), m >= 0.  ent[k] = (List-2 entry, source offset, Ps) of the
+// box's point-and-shoot pairs k = off[b] .. off[b+1]-1.
+template <int PM>
+constexpr int pns_threads() { return 64 * (((PM + 1) * (PM + 2) / 2 + 63) / 64); }
+
+template <int PM>
+__global__ __launch_bounds__(pns_threads<PM>()) void k_l3d_m2l_pns(const int* __restrict__ boxes, int nboxes,
+                                                                 TreeView tv, const cplx* __restrict__ pc,
+                                                                 const int* __restrict__ off,
+                                                                 const int4* __restrict__ ent,
+                                                                 const cplx* __restrict__ mpole,
+                                                                 cplx* __restrict__ local)
+{
+    __shared__ cplx buf[2][256];
+    __shared__ cplx tEa[2][2 * PM + 1], tEb[2][2 * PM + 1], tR[2][PM + 2];
     int b = boxes[xcd_contiguous(blockIdx.x, nboxes)];
     int P = tv.P[tv.level[b]];
     int t = threadIdx.x;
-    int n = (int)sqrtf((float)t);
-    while (n * n > t) --n;
-    while ((n + 1) * (n + 1) <= t) ++n;
-    int m = t - n * n - n, am = m < 0 ? -m : m;
+    int n = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+    while (n * (n + 1) / 2 > t) --n;
+    while ((n + 1) * (n + 2) / 2 <= t) ++n;
+    int m = t - n * (n + 1) / 2;
     bool on = n <= P;
-    // the largest degree among this wavefront's coefficients (uniform)
-    int tw = min((t | 63), (P + 1) * (P + 1) - 1);
-    int nw = (int)sqrtf((float)tw);
-    while (nw * nw > tw) --nw;
-    while ((nw + 1) * (nw + 1) <= tw) ++nw;
+    int ip = n * n + n + m, im = n * n + n - m;   // coefficients (n, +m), (n, -m)
+    bool two = on && m > 0;
+    double sg = ((m + n) & 1) ? -1.0 : 1.0;
+    // the largest degree among this wavefront's lanes (uniform)
+    int tw = min((t | 63), (P + 1) * (P + 2) / 2 - 1);
+    int nw = (int)((sqrtf(8.0f * tw + 1.0f) - 1.0f) * 0.5f);
+    while (nw * (nw + 1) / 2 > tw) --nw;
+    while ((nw + 1) * (nw + 2) / 2 <= tw) ++nw;
     nw = __builtin_amdgcn_readfirstlane(nw);
-    double yc[2 * PM + 1], zr[PM + 1];
+    double yc[2 * PM + 1];
 #pragma unroll
     for (int s = 0; s <= 2 * PM; ++s) yc[s] = (on && s <= 2 * n) ? g_pns_y[pns_ybase(n) + (m + n) * (2 * n + 1) + s] : 0.0;
-#pragma unroll
-    for (int i = 0; i <= PM; ++i)
-        zr[i] = (on && am + i <= P) ? g_pns_z[(n * (2 * kPnsMaxP + 1) + m + kPnsMaxP) * (kPnsMaxP + 1) + i] : 0.0;
-    double cn = on ? g_pns_c[t] : 0.0;
-    cplx acc = mk(0.0, 0.0);
+    double cn = on ? g_pns_c[ip] : 0.0;
+    // coaxial factors Zh^m_{n n'} = (-1)^{n+m} (n+n')! / (c_n^m c_n'^m): stage
+    // 3 divides by the source coefficient's own c, the coaxial step takes
+    // (n + m + i)! by a running product from (n + m)!
+    double icn = on ? 1.0 / cn : 0.0;
+    double zsg = sg * icn;
+    double f0 = on ? g_pns_fact[n + m] : 0.0;
+    cplx accp = mk(0.0, 0.0), accm = mk(0.0, 0.0);
     // every entry a stage may read stays finite: zero at the start, and the
     // degrees past a pair's source length are zeroed before the coaxial step
-    bufA[t] = mk(0.0, 0.0);
-    bufB[t] = mk(0.0, 0.0);
-    int e0 = __builtin_amdgcn_readfirstlane(tv.l2off[b]);
-    int e1 = __builtin_amdgcn_readfirstlane(tv.l2off[b + 1]);
-    for (int e = e0; e < e1; ++e) {
-        int Ps = pps[e];
-        if (Ps >= 0) continue;                // a direct-form pair
-        Ps = ~Ps;
+    for (int i = t; i < 256; i += blockDim.x) {
+        buf[0][i] = mk(0.0, 0.0);
+        buf[1][i] = mk(0.0, 0.0);
+    }
+    int k0 = __builtin_amdgcn_readfirstlane(off[b]);
+    int k1 = __builtin_amdgcn_readfirstlane(off[b + 1]);
+    int4 cur = k0 < k1 ? ent[k0] : make_int4(0, 0, -1, 0);
+    cplx ka = mk(0.0, 0.0), kb = mk(0.0, 0.0), mvp = mk(0.0, 0.0), mvm = mk(0.0, 0.0);
+    if (k0 < k1) {
+        pns_consts(t, P, pc, cur.x, ka, kb);
+        pns_tables(t, P, ka, kb, tEa[0], tEb[0], tR[0]);
+        if (on && n <= cur.z) {
+            mvp = mpole[cur.y + ip];
+            mvm = mpole[cur.y + im];
+        }
+    }
+    __syncthreads();
+    int qp = 0;                                   // slot of the previous pair
+    cplx E, O;
+    for (int k = k0; k < k1; ++k) {
+        int q = (k - k0) & 1;
+        int Ps = cur.z;
         bool src_on = on && n <= Ps;
-        cplx mv = src_on ? mpole[psrc[e] + t] : mk(0.0, 0.0);
-        const cplx* k = pc + 5 * (size_t)e;
-        __syncthreads();                      // the previous pair's last stage has read bufA and the tables
-        if (t < 2 * P + 1) {
-            int q = t - P, aq = q < 0 ? -q : q;
-            cplx ea = cpow_small(q < 0 ? k[1] : k[0], aq);
-            // (-i)^q
-            int r4 = q & 3;
-            cplx ph = r4 == 0 ? mk(1.0, 0.0) : r4 == 1 ? mk(0.0, -1.0) : r4 == 2 ? mk(-1.0, 0.0) : mk(0.0, 1.0);
-            tEa[t] = ph * ea;
-            tEb[t] = cpow_small(q < 0 ? k[3] : k[2], aq);
-        } else if (t >= 64 && t < 64 + P + 2) {
-            tR[t - 64] = cpow_small(k[4], t - 64);
+        cplx* X = buf[q];
+        cplx* Y = buf[q ^ 1];
+        // next pair's entry, multipole and constants, one pair ahead
+        int4 nxt = k + 1 < k1 ? ent[k + 1] : make_int4(0, 0, -1, 0);
+        // A: the previous pair's last stage (reads buf[qp], slot qp), then
+        // this pair's first stage (writes X)
+        if (k > k0 && on) {
+            pns_halves<PM>(yc, buf[qp] + n * n, nw, E, O);
+            accp += (sg * (E - O)) * tEa[qp][P - m];
+            accm += (sg * (E + O)) * tEa[qp][P + m];
+        }
+        if (src_on) {
+            X[ip] = tEa[q][m + P] * (cn * mvp);
+            X[im] = tEa[q][P - m] * (cn * mvm);
+        }
+        cplx np = mk(0.0, 0.0), nm_ = mk(0.0, 0.0);
+        if (k + 1 < k1) {
+            if (on && n <= nxt.z) {
+                np = mpole[nxt.y + ip];
+                nm_ = mpole[nxt.y + im];
+            }
+            pns_consts(t, P, pc, nxt.x, ka, kb);
         }
         __syncthreads();
-        if (src_on) bufA[t] = tEa[m + P] * (cn * mv);
+        // B: x1 = Y^T x0, x2 = e^{imb} x1
+        if (src_on) {
+            pns_halves<PM>(yc, X + n * n, min(nw, Ps), E, O);
+            Y[ip] = (E + O) * tEb[q][P + m];
+            Y[im] = (E - O) * tEb[q][P - m];
+        }
         __syncthreads();
-        if (src_on) bufB[t] = pns_rot<PM, true>(yc, bufA + n * n, n, m, min(nw, Ps)) * tEb[m + P];
-        __syncthreads();
-        if (on) bufA[t] = src_on ? pns_rot<PM, false>(yc, bufB + n * n, n, m, min(nw, Ps)) * tR[n] : mk(0.0, 0.0);
-        __syncthreads();
+        // C: x3 = Y x2, times rho^-n / c_n^m; degrees past Ps zeroed
         if (on) {
-            // coaxial: sum over source degrees nn = |m| .. Ps of order m
-            cplx v = mk(0.0, 0.0);
-            int ix = am * am + am + m;
-            // degrees past Ps hold zeros, past P zero factors; the index is
-            // clamped to the buffer
+            cplx vp = mk(0.0, 0.0), vm = mk(0.0, 0.0);
+            if (src_on) {
+                pns_halves<PM>(yc, Y + n * n, min(nw, Ps), E, O);
+                double r = sg * icn;
+                vp = (r * (E - O)) * tR[q][n];
+                vm = (r * (E + O)) * tR[q][n];
+            }
+            X[ip] = vp;
+            X[im] = vm;
+        }
+        __syncthreads();
+        // D: coaxial for orders +m and -m, sums over source degrees m .. Ps
+        // (the entries past Ps and past P are zeros; the index is clamped)
+        if (on) {
+            cplx vp = mk(0.0, 0.0), vm = mk(0.0, 0.0);
+            int ix = m * m + m;
+            double f = f0, d = (double)(n + m + 1);
 #pragma unroll
             for (int i = 0; i <= PM; ++i) {
                 if (i <= Ps) {
-                    cplx x = bufA[min(ix, 255)];
-                    v.re = fma(zr[i], x.re, v.re);
-                    v.im = fma(zr[i], x.im, v.im);
+                    cplx xp = X[min(ix + m, 255)], xm = X[min(ix - m, 255)];
+                    vp.re = fma(f, xp.re, vp.re);
+                    vp.im = fma(f, xp.im, vp.im);
+                    vm.re = fma(f, xm.re, vm.re);
+                    vm.im = fma(f, xm.im, vm.im);
+                    f *= d;
+                    d += 1.0;
                 }
-                ix += 2 * (am + i) + 2;
+                ix += 2 * (m + i) + 2;
             }
-            bufB[t] = v * tR[n + 1];
+            cplx z = tR[q][n + 1] * zsg;
+            Y[ip] = vp * z;
+            Y[im] = vm * z;
         }
         __syncthreads();
-        if (on) bufA[t] = pns_rot<PM, true>(yc, bufB + n * n, n, m, nw) * tEb[P - m];
+        // E: y1 = Y^T y0, y2 = e^{-imb} y1; the next pair's tables
+        if (on) {
+            pns_halves<PM>(yc, Y + n * n, nw, E, O);
+            X[ip] = (E + O) * tEb[q][P - m];
+            X[im] = (E - O) * tEb[q][P + m];
+        }
+        if (k + 1 < k1) pns_tables(t, P, ka, kb, tEa[q ^ 1], tEb[q ^ 1], tR[q ^ 1]);
         __syncthreads();
-        if (on) acc += pns_rot<PM, false>(yc, bufA + n * n, n, m, nw) * tEa[P - m];
+        qp = q;
+        cur = nxt;
+        mvp = np;
+        mvm = nm_;
     }
-    if (on) local[tv.eoff[b] + t] = cn * acc;
+    if (k1 > k0 && on) {
+        pns_halves<PM>(yc, buf[qp] + n * n, nw, E, O);
+        accp += (sg * (E - O)) * tEa[qp][P - m];
+        accm += (sg * (E + O)) * tEa[qp][P + m];
+    }
+    if (on) {
+        local[tv.eoff[b] + ip] = cn * accp;
+        if (m > 0) local[tv.eoff[b] + im] = cn * accm;
+    }
 }
 
 // ------------------------------------------------------------------ L2L
@@ -1456,6 +1566,9 @@ hipError_t l3d_init_tables(int device)
             }
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_pns_y), ty, sizeof(ty))) != hipSuccess) return e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_pns_z), tz, sizeof(tz))) != hipSuccess) return e;
+    double tf[2 * kPnsMaxP + 1];
+    for (int i = 0; i <= 2 * kPnsMaxP; ++i) tf[i] = (double)fac[i];
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_pns_fact), tf, sizeof(tf))) != hipSuccess) return e;
     return hipMemcpyToSymbol(HIP_SYMBOL(g_pns_c), tc, sizeof(tc));
 }
 
@@ -1550,15 +1663,15 @@ hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const in
 
 int l3d_pns_max_p() { return kPnsMaxP; }
 
-hipError_t l3d_m2l_pns(const int* boxes, int nb, int P, const TreeView& tv, const L3Pairs& pr, const cplx* mpole,
-                       cplx* local, hipStream_t st)
+hipError_t l3d_m2l_pns(const int* boxes, int nb, int P, const TreeView& tv, const cplx* pc, const int* off,
+                       const int4* ent, const cplx* mpole, cplx* local, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
     if (P > kPnsMaxP) return hipErrorInvalidValue;
-    if (P <= 10) k_l3d_m2l_pns<10><<<nb, 256, 0, st>>>(boxes, nb, tv, pr.c, pr.ps, pr.src, mpole, local);
-    else if (P <= 12) k_l3d_m2l_pns<12><<<nb, 256, 0, st>>>(boxes, nb, tv, pr.c, pr.ps, pr.src, mpole, local);
-    else if (P <= 14) k_l3d_m2l_pns<14><<<nb, 256, 0, st>>>(boxes, nb, tv, pr.c, pr.ps, pr.src, mpole, local);
-    else k_l3d_m2l_pns<15><<<nb, 256, 0, st>>>(boxes, nb, tv, pr.c, pr.ps, pr.src, mpole, local);
+    if (P <= 10) k_l3d_m2l_pns<10><<<nb, pns_threads<10>(), 0, st>>>(boxes, nb, tv, pc, off, ent, mpole, local);
+    else if (P <= 12) k_l3d_m2l_pns<12><<<nb, pns_threads<12>(), 0, st>>>(boxes, nb, tv, pc, off, ent, mpole, local);
+    else if (P <= 14) k_l3d_m2l_pns<14><<<nb, pns_threads<14>(), 0, st>>>(boxes, nb, tv, pc, off, ent, mpole, local);
+    else k_l3d_m2l_pns<15><<<nb, pns_threads<15>(), 0, st>>>(boxes, nb, tv, pc, off, ent, mpole, local);
     return hipGetLastError();
 }
 
