@@ -800,21 +800,21 @@ __device__ inline cplx cpow_small(cplx z, int q)
 template <int PM>
 __device__ inline void pns_halves(const double (&yc)[2 * PM + 1], const cplx* xs, int nw, cplx& E, cplx& O)
 {
-    // four independent accumulation chains, by s mod 4
-    cplx a[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+    // two accumulation chains, by the parity of s
+    cplx a[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
 #pragma unroll
     for (int s0 = 0; s0 <= 2 * PM; s0 += 8) {
         if (s0 <= 2 * nw) {
 #pragma unroll
             for (int s = s0; s < s0 + 8 && s <= 2 * PM; ++s) {
                 cplx x = xs[s];
-                a[s & 3].re = fma(yc[s], x.re, a[s & 3].re);
-                a[s & 3].im = fma(yc[s], x.im, a[s & 3].im);
+                a[s & 1].re = fma(yc[s], x.re, a[s & 1].re);
+                a[s & 1].im = fma(yc[s], x.im, a[s & 1].im);
             }
         }
     }
-    E = a[0] + a[2];
-    O = a[1] + a[3];
+    E = a[0];
+    O = a[1];
 }
 
 // Phase tables of one pair: tEa[q + P] = (-i)^q e^{iqa}, tEb[q + P] = e^{iqb}
@@ -857,7 +857,7 @@ template <int PM>
 constexpr int pns_threads() { return 64 * (((PM + 1) * (PM + 2) / 2 + 63) / 64); }
 
 template <int PM>
-__global__ __launch_bounds__(pns_threads<PM>()) void k_l3d_m2l_pns(const int* __restrict__ boxes, int nboxes,
+__global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int* __restrict__ boxes, int nboxes,
                                                                  TreeView tv, const cplx* __restrict__ pc,
                                                                  const int* __restrict__ off,
                                                                  const int4* __restrict__ ent,
@@ -967,7 +967,10 @@ __global__ __launch_bounds__(pns_threads<PM>()) void k_l3d_m2l_pns(const int* __
         // (the entries past Ps and past P are zeros; the index is clamped)
         if (on) {
             cplx vp = mk(0.0, 0.0), vm = mk(0.0, 0.0);
-            int ix = m * m + m;
+            // the start index made opaque per pair, so the compiler forms the
+            // step addresses here instead of holding 2 (P + 1) of them live
+            int ix = m * m + m, inc = 2 * m + 2;
+            asm volatile("" : "+v"(ix), "+v"(inc));
             double f = f0, d = (double)(n + m + 1);
 #pragma unroll
             for (int i = 0; i <= PM; ++i) {
@@ -980,7 +983,8 @@ __global__ __launch_bounds__(pns_threads<PM>()) void k_l3d_m2l_pns(const int* __
                     f *= d;
                     d += 1.0;
                 }
-                ix += 2 * (m + i) + 2;
+                ix += inc;
+                inc += 2;
             }
             cplx z = tR[q][n + 1] * zsg;
             Y[ip] = vp * z;
