@@ -844,6 +844,13 @@ __device__ inline void pns_consts(int t, int P, const cplx* __restrict__ pc, int
     if (lo) kb = k[ib];
 }
 
+// Stage buffers hold degree n's coefficients at pns_base(n) + n + m, with
+// pns_base(n) = n (mod 16): at a rotation step every lane of degree n reads
+// pns_base(n) + s, so the sixteen-byte reads of the degrees in a wavefront
+// fall in distinct groups of four banks.
+__host__ __device__ constexpr int pns_base(int n) { return 17 * n + 16 * (n > 9 ? n - 9 : 0); }
+constexpr int kPnsBuf = 384;                  // pns_base(15) + 31 < 384
+
 // The pairs of a box run as a pipeline of five barrier-separated phases:
 //   A: stage 6 of the previous pair | stage 1 of this one,  B: stage 2,
 //   C: stage 3,  D: coaxial shift,  E: stage 5 | the next pair's phase tables.
@@ -864,7 +871,7 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
                                                                  const cplx* __restrict__ mpole,
                                                                  cplx* __restrict__ local)
 {
-    __shared__ cplx buf[2][256];
+    __shared__ cplx buf[2][kPnsBuf];
     __shared__ cplx tEa[2][2 * PM + 1], tEb[2][2 * PM + 1], tR[2][PM + 2];
     int b = boxes[xcd_contiguous(blockIdx.x, nboxes)];
     int P = tv.P[tv.level[b]];
@@ -874,7 +881,8 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
     while ((n + 1) * (n + 2) / 2 <= t) ++n;
     int m = t - n * (n + 1) / 2;
     bool on = n <= P;
-    int ip = n * n + n + m, im = n * n + n - m;   // coefficients (n, +m), (n, -m)
+    int gp = n * n + n + m, gm = n * n + n - m;   // coefficients (n, +m), (n, -m) in the expansions
+    int bn = pns_base(n), ip = bn + n + m, im = bn + n - m;   // and in the stage buffers
     bool two = on && m > 0;
     double sg = ((m + n) & 1) ? -1.0 : 1.0;
     // the largest degree among this wavefront's lanes (uniform)
@@ -886,7 +894,7 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
     double yc[2 * PM + 1];
 #pragma unroll
     for (int s = 0; s <= 2 * PM; ++s) yc[s] = (on && s <= 2 * n) ? g_pns_y[pns_ybase(n) + (m + n) * (2 * n + 1) + s] : 0.0;
-    double cn = on ? g_pns_c[ip] : 0.0;
+    double cn = on ? g_pns_c[gp] : 0.0;
     // coaxial factors Zh^m_{n n'} = (-1)^{n+m} (n+n')! / (c_n^m c_n'^m): stage
     // 3 divides by the source coefficient's own c, the coaxial step takes
     // (n + m + i)! by a running product from (n + m)!
@@ -896,7 +904,7 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
     cplx accp = mk(0.0, 0.0), accm = mk(0.0, 0.0);
     // every entry a stage may read stays finite: zero at the start, and the
     // degrees past a pair's source length are zeroed before the coaxial step
-    for (int i = t; i < 256; i += blockDim.x) {
+    for (int i = t; i < kPnsBuf; i += blockDim.x) {
         buf[0][i] = mk(0.0, 0.0);
         buf[1][i] = mk(0.0, 0.0);
     }
@@ -908,8 +916,8 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
         pns_consts(t, P, pc, cur.x, ka, kb);
         pns_tables(t, P, ka, kb, tEa[0], tEb[0], tR[0]);
         if (on && n <= cur.z) {
-            mvp = mpole[cur.y + ip];
-            mvm = mpole[cur.y + im];
+            mvp = mpole[cur.y + gp];
+            mvm = mpole[cur.y + gm];
         }
     }
     __syncthreads();
@@ -926,7 +934,7 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
         // A: the previous pair's last stage (reads buf[qp], slot qp), then
         // this pair's first stage (writes X)
         if (k > k0 && on) {
-            pns_halves<PM>(yc, buf[qp] + n * n, nw, E, O);
+            pns_halves<PM>(yc, buf[qp] + bn, nw, E, O);
             accp += (sg * (E - O)) * tEa[qp][P - m];
             accm += (sg * (E + O)) * tEa[qp][P + m];
         }
@@ -937,15 +945,15 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
         cplx np = mk(0.0, 0.0), nm_ = mk(0.0, 0.0);
         if (k + 1 < k1) {
             if (on && n <= nxt.z) {
-                np = mpole[nxt.y + ip];
-                nm_ = mpole[nxt.y + im];
+                np = mpole[nxt.y + gp];
+                nm_ = mpole[nxt.y + gm];
             }
             pns_consts(t, P, pc, nxt.x, ka, kb);
         }
         __syncthreads();
         // B: x1 = Y^T x0, x2 = e^{imb} x1
         if (src_on) {
-            pns_halves<PM>(yc, X + n * n, min(nw, Ps), E, O);
+            pns_halves<PM>(yc, X + bn, min(nw, Ps), E, O);
             Y[ip] = (E + O) * tEb[q][P + m];
             Y[im] = (E - O) * tEb[q][P - m];
         }
@@ -954,7 +962,7 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
         if (on) {
             cplx vp = mk(0.0, 0.0), vm = mk(0.0, 0.0);
             if (src_on) {
-                pns_halves<PM>(yc, Y + n * n, min(nw, Ps), E, O);
+                pns_halves<PM>(yc, Y + bn, min(nw, Ps), E, O);
                 double r = sg * icn;
                 vp = (r * (E - O)) * tR[q][n];
                 vm = (r * (E + O)) * tR[q][n];
@@ -964,27 +972,28 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
         }
         __syncthreads();
         // D: coaxial for orders +m and -m, sums over source degrees m .. Ps
-        // (the entries past Ps and past P are zeros; the index is clamped)
         if (on) {
             cplx vp = mk(0.0, 0.0), vm = mk(0.0, 0.0);
             // the start index made opaque per pair, so the compiler forms the
             // step addresses here instead of holding 2 (P + 1) of them live
-            int ix = m * m + m, inc = 2 * m + 2;
-            asm volatile("" : "+v"(ix), "+v"(inc));
-            double f = f0, d = (double)(n + m + 1);
+            // source degree nn = m + i; the factor is zero from nn > Ps on,
+            // so a clamped index (finite entries) never contributes
+            int nn = m;
+            asm volatile("" : "+v"(nn));
+            double f = m <= Ps ? f0 : 0.0, d = (double)(n + m + 1);
 #pragma unroll
             for (int i = 0; i <= PM; ++i) {
                 if (i <= Ps) {
-                    cplx xp = X[min(ix + m, 255)], xm = X[min(ix - m, 255)];
+                    int ix = min(pns_base(nn) + nn, kPnsBuf - 1 - m);
+                    cplx xp = X[ix + m], xm = X[ix - m];
                     vp.re = fma(f, xp.re, vp.re);
                     vp.im = fma(f, xp.im, vp.im);
                     vm.re = fma(f, xm.re, vm.re);
                     vm.im = fma(f, xm.im, vm.im);
-                    f *= d;
+                    f = nn < Ps ? f * d : 0.0;
                     d += 1.0;
                 }
-                ix += inc;
-                inc += 2;
+                ++nn;
             }
             cplx z = tR[q][n + 1] * zsg;
             Y[ip] = vp * z;
@@ -993,7 +1002,7 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
         __syncthreads();
         // E: y1 = Y^T y0, y2 = e^{-imb} y1; the next pair's tables
         if (on) {
-            pns_halves<PM>(yc, Y + n * n, nw, E, O);
+            pns_halves<PM>(yc, Y + bn, nw, E, O);
             X[ip] = (E + O) * tEb[q][P - m];
             X[im] = (E - O) * tEb[q][P + m];
         }
@@ -1005,13 +1014,13 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
         mvm = nm_;
     }
     if (k1 > k0 && on) {
-        pns_halves<PM>(yc, buf[qp] + n * n, nw, E, O);
+        pns_halves<PM>(yc, buf[qp] + bn, nw, E, O);
         accp += (sg * (E - O)) * tEa[qp][P - m];
         accm += (sg * (E + O)) * tEa[qp][P + m];
     }
     if (on) {
-        local[tv.eoff[b] + ip] = cn * accp;
-        if (m > 0) local[tv.eoff[b] + im] = cn * accm;
+        local[tv.eoff[b] + gp] = cn * accp;
+        if (m > 0) local[tv.eoff[b] + gm] = cn * accm;
     }
 }
 

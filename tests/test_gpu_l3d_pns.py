@@ -50,13 +50,18 @@ def _vertical_mix(n, seed):
     return re + 1j * im
 
 
-@pytest.mark.parametrize("m,tol,leaf", [(48, 1e-6, 32), (64, 1e-6, 64), (48, 1e-4, 16), (40, 1e-5, 24)])
+# P = 14 (tol 1e-6), 9 (1e-4), 11 (1e-5) and 15 (2e-7: the largest length of
+# the point-and-shoot lane layout, three wavefronts)
+@pytest.mark.parametrize("m,tol,leaf", [(48, 1e-6, 32), (64, 1e-6, 64), (48, 1e-4, 16), (40, 1e-5, 24),
+                                        (48, 2e-7, 32)])
 def test_plane_pns_matches_direct_and_oracle(m, tol, leaf):
     cfg = synth.make_config(2, n=m * m)
     r = _both(cfg.points, cfg.sigma, tol, leaf)
     (pa, ua), (pd, ud) = r["auto"], r["direct"]
     wa, wd = pa.m2l_work(), pd.m2l_work()
     _say(f"[gpu] pns work auto={wa} direct={wd} P={pa.info()['max_p']}")
+    if tol == 2e-7:
+        assert pa.info()["max_p"] == 15
     assert wa["pns_pairs"] > 0 and wd["pns_pairs"] == 0
     assert wa["pns_pairs"] + wa["direct_pairs"] == wd["direct_pairs"] == pa.info()["n_list2"]
     d = oracle.rel_l2(ua, ud)
