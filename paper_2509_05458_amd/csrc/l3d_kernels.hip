@@ -321,6 +321,111 @@ __global__ __launch_bounds__(kL3P2XThreads) void k_l3d_p2x(const int* __restrict
     }
 }
 
+// The same for P <= PM with each thread's outputs (|m| + k, m), k = 0..P-|m|,
+// accumulated in registers (static index k) instead of LDS: the LDS then
+// holds only the staged points, and the slices meet there once at the end.
+template <bool IRREGULAR, int PM>
+__global__ __launch_bounds__(kL3P2XThreads) void k_l3d_p2x_r(const int* __restrict__ boxes, TreeView tv,
+                                                             PointsView pv, int useL4, cplx* __restrict__ out)
+{
+    extern __shared__ cplx sh[];
+    int b = boxes[blockIdx.x];
+    int l = tv.level[b];
+    int P = tv.P[l];
+    int ncol = 2 * P + 1, H = blockDim.x / ncol;
+    double* pts = reinterpret_cast<double*>(sh);          // [8][kP2XChunk]: x,y,z re, x,y,z im, sigma re, im
+    cplx* acc = sh + 4 * kP2XChunk;                      // [H][P+1][ncol], for the final reduction
+    double s = tv.rs[l];
+    int t = threadIdx.x, h = t / ncol, col = t % ncol;
+    int m = col - P, am = m < 0 ? -m : m;
+    bool act = h < H;
+    cplx r[PM + 1];
+#pragma unroll
+    for (int k = 0; k <= PM; ++k) r[k] = mk(0.0, 0.0);
+    cplx c[3];
+    box_centre(tv, b, c);
+    double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
+    int e0 = useL4 ? tv.l4off[b] : 0, e1 = useL4 ? tv.l4off[b + 1] : 1;
+    int64_t n = pv.n;
+    for (int e = e0; e < e1; ++e) {
+        int src = useL4 ? tv.l4idx[e] : b;
+        for (int j0 = tv.pbeg[src]; j0 < tv.pend[src]; j0 += kP2XChunk) {
+            int cnt = min(kP2XChunk, tv.pend[src] - j0);
+            __syncthreads();
+            if (t < cnt) {
+                int j = j0 + t;
+                for (int d = 0; d < 3; ++d) {
+                    pts[d * kP2XChunk + t] = (pv.xre[d * n + j] - c[d].re) * s;
+                    pts[(3 + d) * kP2XChunk + t] = (pv.xim[d * n + j] - c[d].im) * s;
+                }
+                pts[6 * kP2XChunk + t] = pv.sre[j];
+                pts[7 * kP2XChunk + t] = pv.sim[j];
+            }
+            __syncthreads();
+            if (!act) continue;
+            for (int q = h; q < cnt; q += H) {
+                Vec3 y;
+                y.x = mk(pts[q], pts[3 * kP2XChunk + q]);
+                y.y = mk(pts[kP2XChunk + q], pts[4 * kP2XChunk + q]);
+                y.z = mk(pts[2 * kP2XChunk + q], pts[5 * kP2XChunk + q]);
+                cplx sig = mk(pts[6 * kP2XChunk + q] * sg, pts[7 * kP2XChunk + q] * sg);
+                cplx w = m >= 0 ? wminus(y) : wplus(y);
+                cplx r2 = dot3(y);
+                if (!IRREGULAR) {
+                    cplx a = sig;
+                    for (int k = 1; k <= am; ++k) a = (a * w) * c_ldg[k];
+                    r[0] += a;
+                    cplx bb = y.z * a;
+                    if (am + 1 <= P) r[1] += bb;
+#pragma unroll
+                    for (int k = 2; k <= PM; ++k) {
+                        if (am + k <= P) {
+                            int nn = am + k;
+                            cplx cc = (c_lodd[nn] * (y.z * bb) - r2 * a) * c_lrr[nn * kLT + am];
+                            r[k] += cc;
+                            a = bb;
+                            bb = cc;
+                        }
+                    }
+                } else {
+                    cplx ir2 = cinv(r2), u = w * ir2, zi = y.z * ir2;
+                    cplx a = sig * cinv(csqrt_p(r2));
+                    for (int k = 1; k <= am; ++k) a = (a * u) * c_lodd[k];
+                    r[0] += a;
+                    cplx bb = c_lodd[am + 1] * (zi * a);
+                    if (am + 1 <= P) r[1] += bb;
+#pragma unroll
+                    for (int k = 2; k <= PM; ++k) {
+                        if (am + k <= P) {
+                            int nn = am + k;
+                            cplx cc = c_lodd[nn] * (zi * bb) - c_lka[nn * kLT + am] * (ir2 * a);
+                            r[k] += cc;
+                            a = bb;
+                            bb = cc;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int k = 0; k <= PM; ++k)
+            if (am + k <= P) acc[(h * (P + 1) + k) * ncol + col] = r[k];
+    }
+    __syncthreads();
+    if (h == 0) {
+        cplx* o = out + tv.eoff[b];
+        for (int k = 0; am + k <= P; ++k) {
+            cplx v = acc[k * ncol + col];
+            for (int hh = 1; hh < H; ++hh) v += acc[(hh * (P + 1) + k) * ncol + col];
+            if (useL4) o[nm(am + k, m)] += v;
+            else o[nm(am + k, m)] = v;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ M2M
 // One workgroup per parent; for each child, the table R_l^q(d / w_p) (l <= P)
 // and the child's multipole go to LDS; thread owns outputs (n, m).
@@ -1511,7 +1616,8 @@ hipError_t l3d_p2m(const int* boxes, int nb, int P, const TreeView& tv, const Po
                    cplx* mpole, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    k_l3d_p2x<false><<<nb, kL3P2XThreads, p2x_lds(P), st>>>(boxes, tv, pv, 0, mpole);
+    if (P <= 15) k_l3d_p2x_r<false, 15><<<nb, kL3P2XThreads, p2x_lds(P), st>>>(boxes, tv, pv, 0, mpole);
+    else k_l3d_p2x<false><<<nb, kL3P2XThreads, p2x_lds(P), st>>>(boxes, tv, pv, 0, mpole);
     return hipGetLastError();
 }
 
@@ -1519,7 +1625,8 @@ hipError_t l3d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const Po
                    cplx* local, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    k_l3d_p2x<true><<<nb, kL3P2XThreads, p2x_lds(P), st>>>(boxes, tv, pv, 1, local);
+    if (P <= 15) k_l3d_p2x_r<true, 15><<<nb, kL3P2XThreads, p2x_lds(P), st>>>(boxes, tv, pv, 1, local);
+    else k_l3d_p2x<true><<<nb, kL3P2XThreads, p2x_lds(P), st>>>(boxes, tv, pv, 1, local);
     return hipGetLastError();
 }
 
