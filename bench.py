@@ -242,9 +242,9 @@ def main():
         m2l_flops = float(mw["direct_flops"] + mw["pns_flops"])
         mixed_direct = a.precision == "mixed" and P <= 16 and mw["direct_pairs"] > 0
         m2l_peak = PEAK_FP64_VALU
-        kern = ("k_l3d_m2l_pns + " if mw["pns_pairs"] else "") + ("k_l3d_m2l_f32" if mixed_direct else "k_l3d_m2l")
+        m2l_kern = ("k_l3d_m2l_pns + " if mw["pns_pairs"] else "") + ("k_l3d_m2l_f32" if mixed_direct else "k_l3d_m2l")
         roof = {
-            "kernel": kern,
+            "kernel": m2l_kern,
             "bound": "alu", "achieved": m2l_flops / (m2l_ms * 1e-3) / 1e12, "peak": m2l_peak / 1e12,
             "unit": "TFLOP/s", "frac": m2l_flops / (m2l_ms * 1e-3) / m2l_peak,
             "traffic": measured_traffic("c2_m2l") if a.precision == "fp64" else None,
