@@ -33,7 +33,7 @@ _PTS = np.zeros((4, 3), np.complex128)
 
 @pytest.mark.parametrize("bad", [
     dict(dim=4), dict(kernel=7), dict(tol=0.0), dict(tol=2.0), dict(n_src=0), dict(wavenumber=-1.0),
-    dict(precision=5), dict(separation=3), dict(leaf_size=-2),
+    dict(precision=5), dict(separation=3), dict(leaf_size=-2), dict(m2l_form=2), dict(m2l_form=-1),
     # below each kernel's accuracy floor
     dict(tol=1e-13), dict(dim=3, kernel=cf.LAPLACE, tol=1e-13), dict(dim=3, tol=1e-11),
     # mixed precision below its FP32 rounding floor
@@ -79,6 +79,7 @@ def test_null_arguments_rejected():
     h = ctypes.c_void_p()
     assert L.cfmm_plan(ctypes.byref(h), None) == cf.CFMM_EINVAL
     assert L.cfmm_eval(None, None, None, 0) == cf.CFMM_EINVAL
+    assert L.cfmm_plan_m2l_work(None, None) == cf.CFMM_EINVAL
     assert L.cfmm_destroy(None) == cf.CFMM_OK
 
 
