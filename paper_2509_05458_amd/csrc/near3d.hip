@@ -81,13 +81,18 @@ __device__ inline void sdistf(const double* dr, const double* di, float& sr, flo
     si = 2.0f * fmaf(x2, y2, b);
 }
 
+// FP64 kernels: G = false leaves out the test for s = 0 (coincident points,
+// which contribute zero); pairs of distinct leaves never have s = 0 (points
+// with equal real parts share a leaf, and the plan's geometry check rejects
+// s = 0 between leaves).
 template <>
 struct Kernel<0, 0> {
+    template <bool G = true>
     __device__ static void eval(const double* dr, const double* di, double, double& gr, double& gi)
     {
         double sr, si;
         sdist(dr, di, sr, si);
-        if (sr == 0.0 && si == 0.0) { gr = gi = 0.0; return; }
+        if (G && sr == 0.0 && si == 0.0) { gr = gi = 0.0; return; }
         double q = sr * sr + si * si;
         double u = rsq_nr(q);
         double h = 0.5 * (q * u + sr);
@@ -115,11 +120,12 @@ struct Kernel<0, 1> {
 // r = (t, Im s/(2t)) and 1/|s|, 1/t from rsq_nr as for 1/r.
 template <>
 struct Kernel<1, 0> {
+    template <bool G = true>
     __device__ static void eval(const double* dr, const double* di, double kappa, double& gr, double& gi)
     {
         double sr, si;
         sdist(dr, di, sr, si);
-        if (sr == 0.0 && si == 0.0) { gr = gi = 0.0; return; }
+        if (G && sr == 0.0 && si == 0.0) { gr = gi = 0.0; return; }
         double q = sr * sr + si * si;
         double u = rsq_nr(q);
         double h = 0.5 * (q * u + sr);
@@ -330,7 +336,9 @@ __device__ inline void tile_pair2(const Tile& sh, int R0, int R1, int C, const d
                         di[d] = y[r][d] - sxi[d];
                     }
                     T gr, gi;
-                    Kernel<KIND, PREC>::eval(dr, di, kappa, gr, gi);
+                    // distinct leaves: s != 0, so FP64 skips the zero test
+                    if constexpr (PREC == 0) Kernel<KIND, PREC>::template eval<false>(dr, di, kappa, gr, gi);
+                    else Kernel<KIND, PREC>::eval(dr, di, kappa, gr, gi);
                     rr[r].add2(gr, sr, -gi, si);
                     ri[r].add2(gr, si, gi, sr);
                     cr.add2(gr, fwr[r], -gi, fwi[r]);

@@ -361,7 +361,9 @@ __global__ __launch_bounds__(64) void k_check_near(const int* __restrict__ leave
                         sr = fma(-di, di, sr);
                         si = fma(dr, di, si);
                     }
-                    if (sr <= 0.0 && !(sr == 0.0 && si == 0.0)) bad = 1;
+                    // s = 0 is allowed only for coincident points, which
+                    // share a leaf (equal real parts, equal keys)
+                    if (sr <= 0.0 && (a != b || !(sr == 0.0 && si == 0.0))) bad = 1;
                 }
             }
         }
