@@ -15,8 +15,9 @@ Laplace single layer, N = 1448^2 = 2,096,704 points on the complexified plane
 the 1000^2 plane with bumps, kappa = 20 * 2 pi / 12.
 
 Prints one JSON line.  metric: N^2-equivalent interactions per second,
-N (N - 1) / t_eval, with a roofline block for the dominant kernel (HIP events
-on the plan's stream over the timed steps), the oracle's direct sum on the
+N (N - 1) / t_eval, with a roofline block for the dominant kernel, the near
+field (HIP events on the plan's stream over the timed steps; for 3D Laplace
+the M2L translations are reported beside it), the oracle's direct sum on the
 host's cores as cpu_baseline, and a serving block: a seeded stream of
 GMRES-like requests served with overlap and memory admission against the same
 trace replayed sequentially in plain FP64.
@@ -150,10 +151,10 @@ def main():
         plan.eval_into(sigs[w % nsig], out)
     torch.cuda.synchronize()
     # timed region: back-to-back evaluations; HIP events on the plan's stream
-    # bracket the roofline kernel of each one (profiling mode 3: the M2L
-    # translations; mode 2: the near-field stage)
-    roof_m2l = a.workload == "c2"
-    plan.set_profiling(3 if roof_m2l else 2)
+    # bracket the dominant stage of each one, the near field on every
+    # workload (profiling mode 2); the M2L translations (mode 3) are
+    # bracketed over a few evaluations after it
+    plan.set_profiling(2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(a.steps):
@@ -163,16 +164,13 @@ def main():
     ring_tot, ring_cnt = plan.ring_ms()
     # the other stage's ring over a few more evaluations (after the timed region)
     nside = max(1, min(a.steps, 5))
-    plan.set_profiling(2 if roof_m2l else 3)
+    plan.set_profiling(3)
     for s in range(nside):
         plan.eval_into(sigs[s % nsig], out)
     torch.cuda.synchronize()
     side_tot, side_cnt = plan.ring_ms()
     plan.set_profiling(0)
-    if roof_m2l:
-        m2l_ms, near_ms = ring_tot / max(1, ring_cnt), side_tot / max(1, side_cnt)
-    else:
-        near_ms, m2l_ms = ring_tot / max(1, ring_cnt), side_tot / max(1, side_cnt)
+    near_ms, m2l_ms = ring_tot / max(1, ring_cnt), side_tot / max(1, side_cnt)
     ms_per_step = dt * 1e3 / a.steps
     pairs = n * (n - 1)
     value = pairs / (ms_per_step * 1e-3)
@@ -232,7 +230,8 @@ def main():
         "flops_per_interaction": p2p_flops_unit, "ms_per_launch_set": near_ms,
         "near_interactions": nw["interactions"], "near_evaluations": nw["evaluations"],
     }
-    if roof_m2l:
+    roof = dict(p2p_block)
+    if dim == 3 and kern == "laplace":
         # the M2L translations: point-and-shoot pairs (k_l3d_m2l_pns: four
         # real rotations per degree, the coaxial shift and the diagonal
         # phases) and direct-form pairs (k_l3d_m2l: (P+1)^2 (Ps+1)^2 complex
@@ -243,19 +242,17 @@ def main():
         mixed_direct = a.precision == "mixed" and P <= 16 and mw["direct_pairs"] > 0
         m2l_peak = PEAK_FP64_VALU
         m2l_kern = ("k_l3d_m2l_pns + " if mw["pns_pairs"] else "") + ("k_l3d_m2l_f32" if mixed_direct else "k_l3d_m2l")
-        roof = {
+        roof["m2l"] = {
             "kernel": m2l_kern,
             "bound": "alu", "achieved": m2l_flops / (m2l_ms * 1e-3) / 1e12, "peak": m2l_peak / 1e12,
             "unit": "TFLOP/s", "frac": m2l_flops / (m2l_ms * 1e-3) / m2l_peak,
-            "traffic": measured_traffic("c2_m2l") if a.precision == "fp64" else None,
+            "traffic": measured_traffic("c2_m2l") if (a.precision == "fp64" and a.workload == "c2") else None,
             "flops_per_pair_mean": m2l_flops / max(1, info["m2l_pairs"]), "pairs": info["m2l_pairs"],
             "pns_pairs": mw["pns_pairs"], "direct_pairs": mw["direct_pairs"],
             "pns_flops": mw["pns_flops"], "direct_flops": mw["direct_flops"],
             "ms_per_launch": m2l_ms,
-            "p2p": p2p_block,
         }
     else:
-        roof = dict(p2p_block)
         roof["m2l_ms"] = m2l_ms
     names = {"c1": f"2D Helmholtz single layer, N={n} complexified curve (C0 curve scaled 0.1), "
                    f"kappa={cfg.kappa}, tol={tol}, targets=sources",
