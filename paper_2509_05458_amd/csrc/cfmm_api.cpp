@@ -1304,7 +1304,7 @@ int cfmm_eval_layer(cfmm_plan_t p, const void* charge, const void* dipole, void*
     HIPCHK(run_l3d_m2l(p, tv, P, 0, st));
     if (v) HIPCHK(l3d_p2x_dip(W + p->off_p2l, p->n_p2l, P, 1, tv, pv, p->d_dre, p->d_dim, p->d_local, st));
     else HIPCHK(l3d_p2l(W + p->off_p2l, p->n_p2l, P, tv, pv, p->d_local, st));
-    for (int l = top + 1; l < nlev; ++l) HIPCHK(l3d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], P, tv, p->d_local, st));
+    for (int l = top; l + 1 < nlev; ++l) HIPCHK(l3d_l2l(W + p->m2m_off[l], p->m2m_cnt[l], P, tv, p->d_local, st));
     if (g) {
         M2PParts m4{p->n_m2p3, p->d_m2p_owner, p->d_m2p_poff4, p->d_m2p_part4};
         HIPCHK(l3d_leaf_far_grad(W + p->off_leaves, p->nleaf, top, tv, pv, p->d_mpole, p->d_local, m4, p->d_ufar,
@@ -1525,8 +1525,8 @@ int eval_on_device(cfmm_plan_s* p, const double* sig, double* out)
         HIPCHK(mark(9));
         HIPCHK(l3d_p2l(W + p->off_p2l, p->n_p2l, P, tv, pv, p->d_local, st));
         HIPCHK(mark(4));
-        for (int l = top + 1; l < nlev; ++l)
-            HIPCHK(l3d_l2l(W + p->l2l_off[l], p->l2l_cnt[l], P, tv, p->d_local, st));
+        for (int l = top; l + 1 < nlev; ++l)
+            HIPCHK(l3d_l2l(W + p->m2m_off[l], p->m2m_cnt[l], P, tv, p->d_local, st));
         HIPCHK(mark(5));
         HIPCHK(l3d_leaf_far(W + p->off_leaves, p->nleaf, top, tv, pv, p->d_mpole, p->d_local,
                             p->m2p_parts(), p->d_ufar, st));

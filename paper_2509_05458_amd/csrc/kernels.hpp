@@ -163,6 +163,8 @@ hipError_t l3d_p2m(const int* boxes, int nb, int P, const TreeView& tv, const Po
                    cplx* mpole, hipStream_t st);
 hipError_t l3d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const PointsView& pv,
                    cplx* local, hipStream_t st);
+// M2M into the nb parents `boxes` from all their children; L2L from the nb
+// parents `parents` into all their children
 hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mpole, hipStream_t st);
 // Source expansion length of an M2L pair by the max-norm distance d of the
 // box centres in box widths: p[min(d, 7)] (Sec. 6.3's rule with the pair's
@@ -201,7 +203,7 @@ hipError_t l3d_m2l(const int* boxes, int nb, int P, const TreeView& tv, const in
 int l3d_pns_max_p();
 hipError_t l3d_m2l_pns(const int* boxes, int nb, int P, const TreeView& tv, const cplx* pc, const int* off,
                        const int4* ent, const cplx* mpole, cplx* local, hipStream_t st);
-hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st);
+hipError_t l3d_l2l(const int* parents, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st);
 hipError_t l3d_leaf_far(const int* leaves, int nleaf, int top, const TreeView& tv,
                         const PointsView& pv, const cplx* mpole, const cplx* local, const M2PParts& m2p,
                         cplx* ufar, hipStream_t st);

@@ -427,9 +427,52 @@ __global__ __launch_bounds__(kL3P2XThreads) void k_l3d_p2x_r(const int* __restri
 }
 
 // ------------------------------------------------------------------ M2M
-// One workgroup per parent; for each child, the table R_l^q(d / w_p) (l <= P)
-// and the child's multipole go to LDS; thread owns outputs (n, m).
-__global__ __launch_bounds__(256) void k_l3d_m2m(const int* __restrict__ boxes, TreeView tv,
+// Coefficient (n, m) of task u when the outputs are taken in falling n and,
+// within a degree, in the order m = 0, 1, -1, 2, -2, ...
+__device__ inline void l3_task_desc(int u, int P, int& n, int& m)
+{
+    int v = (P + 1) * (P + 1) - 1 - u;
+    n = (int)sqrtf((float)v + 0.5f);
+    int i = (n + 1) * (n + 1) - 1 - v;
+    m = (i & 1) ? (i + 1) >> 1 : -(i >> 1);
+}
+
+// The same in rising degree.
+__device__ inline void l3_task_asc(int u, int& n, int& m)
+{
+    n = (int)sqrtf((float)u + 0.5f);
+    int i = u - n * n;
+    m = (i & 1) ? (i + 1) >> 1 : -(i >> 1);
+}
+
+// The table of one child slot: T_l^q = (+-1)^q R_l^q(d / w_p), l <= P, by
+// columns (thread i of nb (2P + 1) builds column q of slot i / (2P + 1)).
+__device__ inline void l3_shift_tables(const TreeView& tv, const cplx* cp, int c0, int nb, int P, double s,
+                                       bool sign, cplx* T)
+{
+    int ncol = 2 * P + 1, nc = (P + 1) * (P + 1);
+    for (int i = threadIdx.x; i < nb * ncol; i += blockDim.x) {
+        int g = i / ncol, q = i - g * ncol - P;
+        cplx cc[3];
+        box_centre(tv, c0 + g, cc);
+        Vec3 d;
+        d.x = (cc[0] - cp[0]) * s; d.y = (cc[1] - cp[1]) * s; d.z = (cc[2] - cp[2]) * s;
+        cplx* Tg = T + g * nc;
+        col_R(d, q, P, sign && (q & 1), [&](int n, cplx v) { Tg[nm(n, q)] = v; });
+    }
+}
+
+// One workgroup of 256 threads per parent.  The children pass through LDS in
+// batches of at most CB <= 4 (CB from the LDS budget): per child slot g the
+// table T_l^q = (-1)^q R_l^q(d / w_p), which folds the sign of the shift into
+// the table, and the child's multipole scaled by 2^-j.  Lane task (u, g) sums
+// the contribution of slot g to output (n, m) = task u, over j <= n and only
+// the orders k with |k - m| <= n - j, where the table entry
+// T_{n-j}^{k-m} exists; the four slots of an output sit in adjacent lanes and
+// meet by two lane exchanges in a fixed order.  Outputs are dealt in falling
+// n and rising |m|, so that the lanes of a wavefront run sums of about the
+// same length.
+__global__ __launch_bounds__(256) void k_l3d_m2m(const int* __restrict__ boxes, TreeView tv, int CB,
                                                  cplx* __restrict__ mpole)
 {
     extern __shared__ cplx sh[];
@@ -437,54 +480,51 @@ __global__ __launch_bounds__(256) void k_l3d_m2m(const int* __restrict__ boxes, 
     int l = tv.level[p];
     int P = tv.P[l];
     int nc = (P + 1) * (P + 1);
-    cplx* Rt = sh;             // nc
-    cplx* Mc = sh + nc;        // nc
+    cplx* sT = sh;             // [CB][nc]
+    cplx* sM = sh + CB * nc;   // [CB][nc]
     double s = tv.rs[l];
     int t = threadIdx.x;
-    cplx acc[4];
-    for (int r = 0; r < 4; ++r) acc[r] = mk(0.0, 0.0);
     cplx cp[3];
     box_centre(tv, p, cp);
-    for (int ci = 0; ci < tv.nchild[p]; ++ci) {
-        int c = tv.child0[p] + ci;
-        __syncthreads();
-        if (t < 2 * P + 1) {
-            cplx cc[3];
-            box_centre(tv, c, cc);
-            Vec3 d;
-            d.x = (cc[0] - cp[0]) * s; d.y = (cc[1] - cp[1]) * s; d.z = (cc[2] - cp[2]) * s;
-            int q = t - P;
-            col_R(d, q, P, false, [&](int n, cplx v) { Rt[nm(n, q)] = v; });
+    int c0 = tv.child0[p], nch = tv.nchild[p];
+    cplx* out = mpole + tv.eoff[p];
+    for (int b0 = 0; b0 < nch; b0 += CB) {
+        int nb = min(CB, nch - b0);
+        if (b0 > 0) __syncthreads();
+        l3_shift_tables(tv, cp, c0 + b0, nb, P, s, true, sT);
+        for (int i = t; i < nb * nc; i += blockDim.x) {
+            int g = i / nc, e = i - g * nc;
+            int j = (int)sqrtf((float)e + 0.5f);
+            sM[g * nc + e] = ldexp(1.0, -j) * mpole[tv.eoff[c0 + b0 + g] + e];
         }
-        for (int i = t; i < nc; i += blockDim.x) Mc[i] = mpole[tv.eoff[c] + i];
         __syncthreads();
-        for (int r = 0; r < 4; ++r) {
-            int o = t + r * blockDim.x;
-            if (o >= nc) break;
-            int n = (int)sqrt((double)o);
-            while (n * n > o) --n;
-            while ((n + 1) * (n + 1) <= o) ++n;
-            int m = o - n * n - n;
+        for (int base = 0; base < 4 * nc; base += blockDim.x) {
+            int u = (base + t) >> 2, g = (base + t) & 3;
+            int n = 0, m = 0;
             cplx a = mk(0.0, 0.0);
-            double h = 1.0;
-            for (int j = 0; j <= n; ++j, h *= 0.5) {
-                int lmax = n - j;
-                cplx aj = mk(0.0, 0.0);
-                for (int k = -j; k <= j; ++k) {
-                    int q = m - k;
-                    if (q > lmax || q < -lmax) continue;
-                    cplx rv = Rt[nm(lmax, -q)];
-                    if (q & 1) rv = -rv;
-                    aj += Mc[nm(j, k)] * rv;
+            if (u < nc) {
+                l3_task_desc(u, P, n, m);
+                if (g < nb) {
+                    const cplx* Mg = sM + g * nc;
+                    const cplx* Tg = sT + g * nc;
+                    for (int j = 0; j <= n; ++j) {
+                        int lr = n - j;
+                        int k0 = max(-j, m - lr), k1 = min(j, m + lr);
+                        const cplx* mr = Mg + j * j + j;
+                        const cplx* tr = Tg + lr * lr + lr - m;
+                        for (int k = k0; k <= k1; ++k) a += mr[k] * tr[k];
+                    }
                 }
-                a += h * aj;
             }
-            acc[r] += a;
+            a.re += __shfl_xor(a.re, 1, 64);
+            a.im += __shfl_xor(a.im, 1, 64);
+            a.re += __shfl_xor(a.re, 2, 64);
+            a.im += __shfl_xor(a.im, 2, 64);
+            if (u < nc && g == 0) {
+                int o = nm(n, m);
+                out[o] = b0 == 0 ? a : out[o] + a;
+            }
         }
-    }
-    for (int r = 0; r < 4; ++r) {
-        int o = t + r * blockDim.x;
-        if (o < nc) mpole[tv.eoff[p] + o] = acc[r];
     }
 }
 
@@ -1130,45 +1170,51 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
 }
 
 // ------------------------------------------------------------------ L2L
-__global__ __launch_bounds__(256) void k_l3d_l2l(const int* __restrict__ boxes, TreeView tv,
+// One workgroup of 256 threads per parent: its local expansion goes to LDS
+// once, and its children pass through in batches of at most CB <= 4, each
+// slot with its table T_l^q = R_l^q(d / w_p).  Lane task (u, g) forms output
+// (j, k) = task u of slot g's child, over n >= j and only the orders m with
+// |m - k| <= n - j; every output of degree j runs a sum of (P - j + 1)^2
+// terms, and the tasks are dealt in rising j, so a wavefront's lanes run
+// sums of the same or neighbouring lengths.
+__global__ __launch_bounds__(256) void k_l3d_l2l(const int* __restrict__ boxes, TreeView tv, int CB,
                                                  cplx* __restrict__ local)
 {
     extern __shared__ cplx sh[];
-    int c = boxes[blockIdx.x];
-    int p = tv.parent[c];
+    int p = boxes[blockIdx.x];
     int lp = tv.level[p];
     int P = tv.P[lp];
     int nc = (P + 1) * (P + 1);
-    cplx* Rt = sh;
-    cplx* Lp = sh + nc;
+    cplx* Lp = sh;             // [nc]
+    cplx* sT = sh + nc;        // [CB][nc]
     double s = tv.rs[lp];
     int t = threadIdx.x;
-    if (t < 2 * P + 1) {
-        cplx cp[3], cc[3];
-        box_centre(tv, p, cp);
-        box_centre(tv, c, cc);
-        Vec3 d;
-        d.x = (cc[0] - cp[0]) * s; d.y = (cc[1] - cp[1]) * s; d.z = (cc[2] - cp[2]) * s;
-        int q = t - P;
-        col_R(d, q, P, false, [&](int n, cplx v) { Rt[nm(n, q)] = v; });
-    }
+    cplx cp[3];
+    box_centre(tv, p, cp);
+    int c0 = tv.child0[p], nch = tv.nchild[p];
     for (int i = t; i < nc; i += blockDim.x) Lp[i] = local[tv.eoff[p] + i];
-    __syncthreads();
-    for (int o = t; o < nc; o += blockDim.x) {
-        int j = (int)sqrt((double)o);
-        while (j * j > o) --j;
-        while ((j + 1) * (j + 1) <= o) ++j;
-        int k = o - j * j - j;
-        cplx a = mk(0.0, 0.0);
-        for (int n = j; n <= P; ++n) {
-            int lmax = n - j;
-            for (int m = -n; m <= n; ++m) {
-                int q = m - k;
-                if (q > lmax || q < -lmax) continue;
-                a += Lp[nm(n, m)] * Rt[nm(lmax, q)];
+    for (int b0 = 0; b0 < nch; b0 += CB) {
+        int nb = min(CB, nch - b0);
+        if (b0 > 0) __syncthreads();
+        l3_shift_tables(tv, cp, c0 + b0, nb, P, s, false, sT);
+        __syncthreads();
+        for (int v = t; v < 4 * nc; v += blockDim.x) {
+            int u = v >> 2, g = v & 3;
+            if (g >= nb) continue;
+            int j, k;
+            l3_task_asc(u, j, k);
+            const cplx* Tg = sT + g * nc;
+            cplx a = mk(0.0, 0.0);
+            for (int n = j; n <= P; ++n) {
+                int lr = n - j;
+                int m0 = max(-n, k - lr), m1 = min(n, k + lr);
+                const cplx* lrow = Lp + n * n + n;
+                const cplx* tr = Tg + lr * lr + lr - k;
+                for (int m = m0; m <= m1; ++m) a += lrow[m] * tr[m];
             }
+            cplx* o = local + tv.eoff[c0 + b0 + g];
+            o[nm(j, k)] += ldexp(1.0, -(j + 1)) * a;
         }
-        local[tv.eoff[c] + o] += ldexp(1.0, -(j + 1)) * a;
     }
 }
 
@@ -1692,10 +1738,18 @@ hipError_t l3d_init_tables(int device)
     return hipMemcpyToSymbol(HIP_SYMBOL(g_pns_c), tc, sizeof(tc));
 }
 
+// children per LDS batch of the M2M and L2L: at most four, within 64 KiB
+static int l3_shift_batch(int P)
+{
+    int nc = (P + 1) * (P + 1);
+    return std::max(1, std::min(4, (int)(65536 / (2 * lds_bytes(nc)))));
+}
+
 hipError_t l3d_m2m(const int* boxes, int nb, int P, const TreeView& tv, cplx* mpole, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    k_l3d_m2m<<<nb, 256, lds_bytes(2 * (P + 1) * (P + 1)), st>>>(boxes, tv, mpole);
+    int CB = l3_shift_batch(P);
+    k_l3d_m2m<<<nb, 256, lds_bytes(2 * CB * (P + 1) * (P + 1)), st>>>(boxes, tv, CB, mpole);
     return hipGetLastError();
 }
 
@@ -1795,10 +1849,11 @@ hipError_t l3d_m2l_pns(const int* boxes, int nb, int P, const TreeView& tv, cons
     return hipGetLastError();
 }
 
-hipError_t l3d_l2l(const int* boxes, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st)
+hipError_t l3d_l2l(const int* parents, int nb, int P, const TreeView& tv, cplx* local, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    k_l3d_l2l<<<nb, 256, lds_bytes(2 * (P + 1) * (P + 1)), st>>>(boxes, tv, local);
+    int CB = l3_shift_batch(P);
+    k_l3d_l2l<<<nb, 256, lds_bytes((1 + CB) * (P + 1) * (P + 1)), st>>>(parents, tv, CB, local);
     return hipGetLastError();
 }
 
