@@ -321,108 +321,212 @@ __global__ __launch_bounds__(kL3P2XThreads) void k_l3d_p2x(const int* __restrict
     }
 }
 
-// The same for P <= PM with each thread's outputs (|m| + k, m), k = 0..P-|m|,
-// accumulated in registers (static index k) instead of LDS: the LDS then
-// holds only the staged points, and the slices meet there once at the end.
-template <bool IRREGULAR, int PM>
-__global__ __launch_bounds__(kL3P2XThreads) void k_l3d_p2x_r(const int* __restrict__ boxes, TreeView tv,
-                                                             PointsView pv, int useL4, cplx* __restrict__ out)
+// The same for P <= 15 with the columns paired for equal work.  Lane slot c
+// of a point stream runs the column |m| = a and then the column
+// b = P + 1 - a of the same sign (P - a + 1 and a steps, P + 1 in all); slot 0
+// runs m = 0 alone, and for odd P the slot a = (P + 1)/2 its column alone, so
+// NL = 2 ceil(P/2) + 1 slots cover the (P + 1)^2 coefficients once.  Step s of
+// a slot is a column's diagonal start, sigma C w^|m| (P2M) or
+// (sigma / rho) C (w / r2)^|m| (P2L), the power by squaring, or one step of
+// the recurrence in n written as
+//   next = alpha_s (A cur) - beta_s (B prev),
+// A = z, B = r2 (P2M) or A = z / r2, B = 1 / r2 (P2L).  Each point's A, B,
+// w+-, w-- (over r2 for P2L) and start factor are formed once, by one thread,
+// into LDS; the step constants once per workgroup.  A wavefront holds
+// floor(64 / NL) point streams with register sums (static step index); they
+// meet by lane exchanges, then the wavefronts in LDS, in fixed orders.
+constexpr int kP2XPairThreads = 256;
+constexpr int kP2XPairChunk = 128;
+constexpr int kP2XPairMaxP = 15;
+
+struct P2XSlot {
+    int sg, a, b, na;   // sign (+1 for m >= 0), first and second column (b < 0: none), steps in column a
+};
+
+__device__ inline P2XSlot p2x_slot(int c, int P)
 {
+    int hp = (P + 1) >> 1;
+    P2XSlot q;
+    q.sg = c <= hp ? 1 : -1;
+    q.a = c <= hp ? c : c - hp;
+    q.b = P + 1 - q.a;
+    if (q.a == 0 || q.b == q.a) q.b = -1;
+    q.na = P - q.a + 1;
+    return q;
+}
+
+// column start factor: the sign (-1)^|m| for m < 0 times 1/(2^|m| |m|!) (P2M)
+// or (2|m| - 1)!! (P2L)
+template <bool IRREGULAR>
+__device__ inline double p2x_start_const(int am, int sg)
+{
+    double c = 1.0;
+    if (IRREGULAR) {
+        for (int k = 1; k <= am; ++k) c *= 2.0 * k - 1.0;
+    } else {
+        for (int k = 1; k <= am; ++k) c *= (double)k;
+        c = ldexp(1.0 / c, -am);
+    }
+    return (sg < 0 && (am & 1)) ? -c : c;
+}
+
+// x^ea and x^eb, 0 <= ea, eb <= 15, by squaring with no data-dependent branch
+__device__ inline void cpow_pair15(cplx x, int ea, int eb, cplx& ra, cplx& rb)
+{
+    cplx one = mk(1.0, 0.0);
+    cplx x2 = x * x, x4 = x2 * x2, x8 = x4 * x4;
+    ra = (ea & 1) ? x : one;
+    rb = (eb & 1) ? x : one;
+    ra = ra * ((ea & 2) ? x2 : one);
+    rb = rb * ((eb & 2) ? x2 : one);
+    ra = ra * ((ea & 4) ? x4 : one);
+    rb = rb * ((eb & 4) ? x4 : one);
+    ra = ra * ((ea & 8) ? x8 : one);
+    rb = rb * ((eb & 8) ? x8 : one);
+}
+
+template <bool IRREGULAR>
+__global__ __launch_bounds__(kP2XPairThreads) void k_l3d_p2x_r(const int* __restrict__ boxes, TreeView tv,
+                                                               PointsView pv, int useL4, cplx* __restrict__ out)
+{
+    constexpr int PM = kP2XPairMaxP, CH = kP2XPairChunk, NW = kP2XPairThreads / 64;
     extern __shared__ cplx sh[];
     int b = boxes[blockIdx.x];
     int l = tv.level[b];
     int P = tv.P[l];
-    int ncol = 2 * P + 1, H = blockDim.x / ncol;
-    double* pts = reinterpret_cast<double*>(sh);          // [8][kP2XChunk]: x,y,z re, x,y,z im, sigma re, im
-    cplx* acc = sh + 4 * kP2XChunk;                      // [H][P+1][ncol], for the final reduction
+    int nc = (P + 1) * (P + 1);
+    int NL = 2 * ((P + 1) >> 1) + 1, SW = 64 / NL;
+    cplx* pt = sh;                                        // [5][CH]: A, B, W(m >= 0), W(m < 0), start
+    cplx* acc = sh + 5 * CH;                              // [NW][nc]
+    double2* coef = reinterpret_cast<double2*>(acc + NW * nc);   // [NL][P + 1]
     double s = tv.rs[l];
-    int t = threadIdx.x, h = t / ncol, col = t % ncol;
-    int m = col - P, am = m < 0 ? -m : m;
-    bool act = h < H;
+    int t = threadIdx.x, wv = t >> 6, ln = t & 63, h = ln / NL, c = ln - h * NL;
+    bool act = h < SW;
+    int nst = NW * SW, st = wv * SW + h;
+    for (int i = t; i < NL * (P + 1); i += blockDim.x) {
+        int cc = i / (P + 1), ss = i - cc * (P + 1);
+        P2XSlot u = p2x_slot(cc, P);
+        int n = -1, am = 0;
+        if (ss < u.na) {
+            n = u.a + ss;
+            am = u.a;
+        } else if (u.b >= 0) {
+            n = u.b + ss - u.na;
+            am = u.b;
+        }
+        double al = 0.0, be = 0.0;
+        if (n > am) {
+            if (IRREGULAR) {
+                al = 2.0 * n - 1.0;
+                be = (double)(n + am - 1) * (double)(n - am - 1);
+            } else if (n == am + 1) {
+                al = 1.0;
+            } else {
+                double d = 1.0 / ((double)(n + am) * (double)(n - am));
+                al = (2.0 * n - 1.0) * d;
+                be = d;
+            }
+        }
+        coef[i] = make_double2(al, be);
+    }
+    P2XSlot q = p2x_slot(act ? c : 0, P);
+    double ca = p2x_start_const<IRREGULAR>(q.a, q.sg);
+    double cb = q.b >= 0 ? p2x_start_const<IRREGULAR>(q.b, q.sg) : 0.0;
+    int eb = q.b >= 0 ? q.b : 0;
+    const cplx* wsel = pt + (q.sg > 0 ? 2 : 3) * CH;
+    const double2* cf = coef + (act ? c : 0) * (P + 1);
     cplx r[PM + 1];
 #pragma unroll
     for (int k = 0; k <= PM; ++k) r[k] = mk(0.0, 0.0);
-    cplx c[3];
-    box_centre(tv, b, c);
-    double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
+    cplx cen[3];
+    box_centre(tv, b, cen);
     int e0 = useL4 ? tv.l4off[b] : 0, e1 = useL4 ? tv.l4off[b + 1] : 1;
     int64_t n = pv.n;
     for (int e = e0; e < e1; ++e) {
         int src = useL4 ? tv.l4idx[e] : b;
-        for (int j0 = tv.pbeg[src]; j0 < tv.pend[src]; j0 += kP2XChunk) {
-            int cnt = min(kP2XChunk, tv.pend[src] - j0);
+        for (int j0 = tv.pbeg[src]; j0 < tv.pend[src]; j0 += CH) {
+            int cnt = min(CH, tv.pend[src] - j0);
             __syncthreads();
             if (t < cnt) {
                 int j = j0 + t;
-                for (int d = 0; d < 3; ++d) {
-                    pts[d * kP2XChunk + t] = (pv.xre[d * n + j] - c[d].re) * s;
-                    pts[(3 + d) * kP2XChunk + t] = (pv.xim[d * n + j] - c[d].im) * s;
+                Vec3 y;
+                y.x = mk((pv.xre[j] - cen[0].re) * s, (pv.xim[j] - cen[0].im) * s);
+                y.y = mk((pv.xre[n + j] - cen[1].re) * s, (pv.xim[n + j] - cen[1].im) * s);
+                y.z = mk((pv.xre[2 * n + j] - cen[2].re) * s, (pv.xim[2 * n + j] - cen[2].im) * s);
+                cplx sig = mk(pv.sre[j], pv.sim[j]);
+                cplx r2 = dot3(y), wm = wminus(y), wp = wplus(y);
+                if (IRREGULAR) {
+                    cplx ir2 = cinv(r2);
+                    pt[t] = y.z * ir2;
+                    pt[CH + t] = ir2;
+                    pt[2 * CH + t] = wm * ir2;
+                    pt[3 * CH + t] = wp * ir2;
+                    pt[4 * CH + t] = sig * cinv(csqrt_p(r2));
+                } else {
+                    pt[t] = y.z;
+                    pt[CH + t] = r2;
+                    pt[2 * CH + t] = wm;
+                    pt[3 * CH + t] = wp;
+                    pt[4 * CH + t] = sig;
                 }
-                pts[6 * kP2XChunk + t] = pv.sre[j];
-                pts[7 * kP2XChunk + t] = pv.sim[j];
             }
             __syncthreads();
             if (!act) continue;
-            for (int q = h; q < cnt; q += H) {
-                Vec3 y;
-                y.x = mk(pts[q], pts[3 * kP2XChunk + q]);
-                y.y = mk(pts[kP2XChunk + q], pts[4 * kP2XChunk + q]);
-                y.z = mk(pts[2 * kP2XChunk + q], pts[5 * kP2XChunk + q]);
-                cplx sig = mk(pts[6 * kP2XChunk + q] * sg, pts[7 * kP2XChunk + q] * sg);
-                cplx w = m >= 0 ? wminus(y) : wplus(y);
-                cplx r2 = dot3(y);
-                if (!IRREGULAR) {
-                    cplx a = sig;
-                    for (int k = 1; k <= am; ++k) a = (a * w) * c_ldg[k];
-                    r[0] += a;
-                    cplx bb = y.z * a;
-                    if (am + 1 <= P) r[1] += bb;
+            for (int p = st; p < cnt; p += nst) {
+                cplx A = pt[p], B = pt[CH + p], S = pt[4 * CH + p];
+                cplx xa, xb;
+                cpow_pair15(wsel[p], q.a, eb, xa, xb);
+                cplx da = (S * xa) * ca, db = (S * xb) * cb;
+                cplx prev = mk(0.0, 0.0), cur = mk(0.0, 0.0);
 #pragma unroll
-                    for (int k = 2; k <= PM; ++k) {
-                        if (am + k <= P) {
-                            int nn = am + k;
-                            cplx cc = (c_lodd[nn] * (y.z * bb) - r2 * a) * c_lrr[nn * kLT + am];
-                            r[k] += cc;
-                            a = bb;
-                            bb = cc;
-                        }
-                    }
-                } else {
-                    cplx ir2 = cinv(r2), u = w * ir2, zi = y.z * ir2;
-                    cplx a = sig * cinv(csqrt_p(r2));
-                    for (int k = 1; k <= am; ++k) a = (a * u) * c_lodd[k];
-                    r[0] += a;
-                    cplx bb = c_lodd[am + 1] * (zi * a);
-                    if (am + 1 <= P) r[1] += bb;
-#pragma unroll
-                    for (int k = 2; k <= PM; ++k) {
-                        if (am + k <= P) {
-                            int nn = am + k;
-                            cplx cc = c_lodd[nn] * (zi * bb) - c_lka[nn * kLT + am] * (ir2 * a);
-                            r[k] += cc;
-                            a = bb;
-                            bb = cc;
-                        }
+                for (int k = 0; k <= PM; ++k) {
+                    if (k <= P) {
+                        double2 ab = cf[k];
+                        cplx x = A * cur, yv = B * prev;
+                        cplx rec = mk(fma(ab.x, x.re, -ab.y * yv.re), fma(ab.x, x.im, -ab.y * yv.im));
+                        cplx v = k == 0 ? da : (k == q.na ? db : rec);
+                        r[k] += v;
+                        prev = cur;
+                        cur = v;
                     }
                 }
             }
         }
     }
-    __syncthreads();
-    if (act) {
+    // the streams of a wavefront: slot c of stream 0 adds streams 1.. in order
 #pragma unroll
-        for (int k = 0; k <= PM; ++k)
-            if (am + k <= P) acc[(h * (P + 1) + k) * ncol + col] = r[k];
+    for (int k = 0; k <= PM; ++k) {
+        cplx v = r[k];
+        for (int hh = 1; hh < SW; ++hh) {
+            int from = min(ln + hh * NL, 63);
+            v.re += __shfl(r[k].re, from, 64);
+            v.im += __shfl(r[k].im, from, 64);
+        }
+        r[k] = v;
+    }
+    if (h == 0) {
+#pragma unroll
+        for (int k = 0; k <= PM; ++k) {
+            if (k <= P) {
+                int nn = -1, am = 0;
+                if (k < q.na) {
+                    nn = q.a + k;
+                    am = q.a;
+                } else if (q.b >= 0) {
+                    nn = q.b + k - q.na;
+                    am = q.b;
+                }
+                if (nn >= 0) acc[wv * nc + nm(nn, q.sg > 0 ? am : -am)] = r[k];
+            }
+        }
     }
     __syncthreads();
-    if (h == 0) {
-        cplx* o = out + tv.eoff[b];
-        for (int k = 0; am + k <= P; ++k) {
-            cplx v = acc[k * ncol + col];
-            for (int hh = 1; hh < H; ++hh) v += acc[(hh * (P + 1) + k) * ncol + col];
-            if (useL4) o[nm(am + k, m)] += v;
-            else o[nm(am + k, m)] = v;
-        }
+    cplx* o = out + tv.eoff[b];
+    for (int i = t; i < nc; i += blockDim.x) {
+        cplx v = acc[i];
+        for (int w = 1; w < NW; ++w) v += acc[w * nc + i];
+        if (useL4) o[i] += v;
+        else o[i] = v;
     }
 }
 
@@ -1652,6 +1756,13 @@ __global__ void k_gather_dipole(const double* __restrict__ dip, IoMap io, int64_
 // ---------------------------------------------------------------- launchers
 static size_t lds_bytes(int nelem) { return (size_t)nelem * sizeof(cplx); }
 
+static size_t p2x_pair_lds(int P)
+{
+    int NL = 2 * ((P + 1) / 2) + 1;
+    return lds_bytes(5 * kP2XPairChunk + (kP2XPairThreads / 64) * (P + 1) * (P + 1)) +
+           (size_t)NL * (P + 1) * 2 * sizeof(double);
+}
+
 static size_t p2x_lds(int P)
 {
     int ncol = 2 * P + 1;
@@ -1662,7 +1773,7 @@ hipError_t l3d_p2m(const int* boxes, int nb, int P, const TreeView& tv, const Po
                    cplx* mpole, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    if (P <= 15) k_l3d_p2x_r<false, 15><<<nb, kL3P2XThreads, p2x_lds(P), st>>>(boxes, tv, pv, 0, mpole);
+    if (P <= kP2XPairMaxP) k_l3d_p2x_r<false><<<nb, kP2XPairThreads, p2x_pair_lds(P), st>>>(boxes, tv, pv, 0, mpole);
     else k_l3d_p2x<false><<<nb, kL3P2XThreads, p2x_lds(P), st>>>(boxes, tv, pv, 0, mpole);
     return hipGetLastError();
 }
@@ -1671,7 +1782,7 @@ hipError_t l3d_p2l(const int* boxes, int nb, int P, const TreeView& tv, const Po
                    cplx* local, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    if (P <= 15) k_l3d_p2x_r<true, 15><<<nb, kL3P2XThreads, p2x_lds(P), st>>>(boxes, tv, pv, 1, local);
+    if (P <= kP2XPairMaxP) k_l3d_p2x_r<true><<<nb, kP2XPairThreads, p2x_pair_lds(P), st>>>(boxes, tv, pv, 1, local);
     else k_l3d_p2x<true><<<nb, kL3P2XThreads, p2x_lds(P), st>>>(boxes, tv, pv, 1, local);
     return hipGetLastError();
 }
