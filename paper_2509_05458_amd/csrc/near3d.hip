@@ -301,73 +301,90 @@ __device__ inline void tile_pair(const Tile& sh, int R, int C, bool self, const 
     ci_out = ci.val();
 }
 
-// The same rotation for a tile of C sources against two rows of targets per
-// lane (lane l holds targets l and 64 + l of a 128-target block; R0 >= R1
-// of them are valid): each step reads one source from LDS for two
-// evaluations, and the travelling column sum takes both.  Period
-// L = max(R0, C).
+// Cyclic travel of a tile of C <= 64 points (Y, in LDS) past two rows of
+// points held in the lanes (X: lane l holds rows 0 and 1, R0 >= R1 valid):
+// at step s lane l pairs with tile point (s + l) mod C, so every lane is busy
+// at every step whatever C and the rows' fill.  The lane sums (each X point
+// against all of Y) stay in the lane; the sum of each Y point travels one
+// lane down per step, with the point it belongs to.  The value leaving lane 0
+// at step s is complete for Y point s and goes to flush[s]; lane 0 restarts
+// from zero, which reaches lane 63.  After C steps lane l (< 63) holds a last
+// segment of Y point l mod C, put in seg[l]; Y point j's sum is flush[j] plus
+// seg[j], seg[j + C], ... in that order.
 template <int KIND, int PREC>
-__device__ inline void tile_pair2(const Tile& sh, int R0, int R1, int C, const double (&x)[2][3],
-                                  const double (&y)[2][3], const double (&wr)[2], const double (&wi)[2],
-                                  double kappa, double (&ar)[2], double (&ai)[2], double& cr_out,
-                                  double& ci_out)
+__device__ inline void cyc_pass(const Tile& ty, int C, int R0, int R1, const double (&x)[2][3],
+                                const double (&y)[2][3], const double (&wr)[2], const double (&wi)[2],
+                                double kappa, double (&ar)[2], double (&ai)[2], double2* flush, double2* seg)
 {
     typedef typename Acc<PREC>::T T;
     int t = threadIdx.x;
-    int L = max(R0, C);
-    int nxt = t < L ? (t + 1 == L ? 0 : t + 1) : t;
+    int nxt = (t + 1) & 63;
     Sum<T> rr[2], ri[2], cr, ci;
     T fwr[2] = {(T)wr[0], (T)wr[1]}, fwi[2] = {(T)wi[0], (T)wi[1]};
-    int q = t;
-    for (int step = 0; step < L; ++step) {
-        if (q < C) {
-            double sxr[3], sxi[3];
-            for (int d = 0; d < 3; ++d) {
-                sxr[d] = sh.xr[d][q];
-                sxi[d] = sh.xi[d][q];
-            }
-            T sr = (T)sh.sr[q], si = (T)sh.si[q];
+    int q = t % C;
+    for (int step = 0; step < C; ++step) {
+        double sxr[3], sxi[3];
+        for (int d = 0; d < 3; ++d) {
+            sxr[d] = ty.xr[d][q];
+            sxi[d] = ty.xi[d][q];
+        }
+        T sr = (T)ty.sr[q], si = (T)ty.si[q];
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                if (t < (r ? R1 : R0)) {
-                    double dr[3], di[3];
-                    for (int d = 0; d < 3; ++d) {
-                        dr[d] = x[r][d] - sxr[d];
-                        di[d] = y[r][d] - sxi[d];
-                    }
-                    T gr, gi;
-                    // distinct leaves: s != 0, so FP64 skips the zero test
-                    if constexpr (PREC == 0) Kernel<KIND, PREC>::template eval<false>(dr, di, kappa, gr, gi);
-                    else Kernel<KIND, PREC>::eval(dr, di, kappa, gr, gi);
-                    rr[r].add2(gr, sr, -gi, si);
-                    ri[r].add2(gr, si, gi, sr);
-                    cr.add2(gr, fwr[r], -gi, fwi[r]);
-                    ci.add2(gr, fwi[r], gi, fwr[r]);
+        for (int r = 0; r < 2; ++r) {
+            if (t < (r ? R1 : R0)) {
+                double dr[3], di[3];
+                for (int d = 0; d < 3; ++d) {
+                    dr[d] = x[r][d] - sxr[d];
+                    di[d] = y[r][d] - sxi[d];
                 }
+                T gr, gi;
+                // distinct leaves: s != 0, so FP64 skips the zero test
+                if constexpr (PREC == 0) Kernel<KIND, PREC>::template eval<false>(dr, di, kappa, gr, gi);
+                else Kernel<KIND, PREC>::eval(dr, di, kappa, gr, gi);
+                rr[r].add2(gr, sr, -gi, si);
+                ri[r].add2(gr, si, gi, sr);
+                cr.add2(gr, fwr[r], -gi, fwi[r]);
+                ci.add2(gr, fwi[r], gi, fwr[r]);
             }
+        }
+        if (t == 0) {
+            flush[step] = make_double2(cr.val(), ci.val());
+            cr = Sum<T>();
+            ci = Sum<T>();
         }
         cr.shfl(nxt);
         ci.shfl(nxt);
-        if (++q >= L) q -= L;
+        if (++q == C) q = 0;
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         ar[r] += rr[r].val();
         ai[r] += ri[r].val();
     }
-    cr_out = cr.val();
-    ci_out = ci.val();
+    seg[t] = make_double2(cr.val(), ci.val());
+}
+
+// Y point j's total after cyc_pass (the caller synchronises first).
+__device__ inline cplx cyc_total(const double2* flush, const double2* seg, int C, int j)
+{
+    cplx v = mk(flush[j].x, flush[j].y);
+    for (int l = j; l < 64; l += C) v += mk(seg[l].x, seg[l].y);
+    return v;
 }
 
 // Neighbour items (a < b): rows into C[e], columns into C[partner e].  b's
-// targets are cut into the fewest row sets of at most 64, all of one size R,
-// taken two per lane; a's sources into the fewest tiles of at most 64, of one
-// size, so a ragged leaf does not leave most lanes idle for a whole period.
+// targets go through the lanes in passes of 128 (two rows of 64) against a's
+// sources in tiles of at most 64 (cyclic travel).  A remainder of r <= 64
+// targets after the full passes runs with the roles swapped when that takes
+// fewer steps (ceil(na / 128) r < na): a's points in the lanes, 128 per pass,
+// the r targets travelling; so a leaf of 132 points costs 128 + 4 steps per
+// 64 lanes instead of two half-filled passes.
 template <int KIND, int PREC>
 __global__ __launch_bounds__(64) void k_near3_pair(const int* __restrict__ items, Near3Map mp, TreeView tv,
                                                    PointsView pv, double kappa)
 {
     __shared__ Tile sh;
+    __shared__ double2 flush[64], seg[64];
     int e = items[blockIdx.x];
     int b = mp.row_of[e], a = tv.l1idx[e], ep = mp.partner[e];
     int64_t n = pv.n;
@@ -376,39 +393,72 @@ __global__ __launch_bounds__(64) void k_near3_pair(const int* __restrict__ items
     cplx* Crow = mp.C + mp.coff[e];
     cplx* Ccol = mp.C + mp.coff[ep];
     int nt = pb1 - pb0, na = pa1 - pa0;
-    int kt = (nt + 63) / 64, R = (nt + kt - 1) / kt;      // row sets of R <= 64 targets
     int kc = (na + 63) / 64, Cs = (na + kc - 1) / kc;     // source tiles of Cs <= 64
-    for (int rs = 0; rs < kt; rs += 2) {
-        double x[2][3], y[2][3], wr[2], wi[2], ar[2] = {0.0, 0.0}, ai[2] = {0.0, 0.0};
-        int Rn[2];
+    int nfull = nt / 128, rem = nt - 128 * nfull;
+    bool swap = rem > 0 && rem <= 64 && ((na + 127) / 128) * rem < na;
+    int npass = nfull + (rem > 0 && !swap ? 1 : 0);
+    // lane rows of points p0 + t and p0 + 64 + t (counts R0, R1)
+    auto load_rows = [&](int p0, int R0, int R1, double (&x)[2][3], double (&y)[2][3], double (&wr)[2],
+                         double (&wi)[2]) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-            Rn[r] = rs + r < kt ? min(R, nt - (rs + r) * R) : 0;
-            int i = pb0 + (rs + r) * R + t;
-            bool tok = t < Rn[r];
+            int i = p0 + 64 * r + t;
+            bool ok = t < (r ? R1 : R0);
             for (int d = 0; d < 3; ++d) {
-                x[r][d] = tok ? pv.xre[d * n + i] : 0.0;
-                y[r][d] = tok ? pv.xim[d * n + i] : 0.0;
+                x[r][d] = ok ? pv.xre[d * n + i] : 0.0;
+                y[r][d] = ok ? pv.xim[d * n + i] : 0.0;
             }
-            wr[r] = tok ? pv.sre[i] : 0.0;
-            wi[r] = tok ? pv.sim[i] : 0.0;
+            wr[r] = ok ? pv.sre[i] : 0.0;
+            wi[r] = ok ? pv.sim[i] : 0.0;
         }
+    };
+    for (int ps = 0; ps < npass; ++ps) {
+        int left = nt - 128 * ps;
+        int R0 = min(64, left), R1 = max(0, min(64, left - 64));
+        double x[2][3], y[2][3], wr[2], wi[2], ar[2] = {0.0, 0.0}, ai[2] = {0.0, 0.0};
+        load_rows(pb0 + 128 * ps, R0, R1, x, y, wr, wi);
         for (int j0 = pa0; j0 < pa1; j0 += Cs) {
             int cnt = min(Cs, pa1 - j0);
             __syncthreads();
             load_tile(sh, pv, j0, cnt, t);
             __syncthreads();
-            double cr, ci;
-            tile_pair2<KIND, PREC>(sh, Rn[0], Rn[1], cnt, x, y, wr, wi, kappa, ar, ai, cr, ci);
+            cyc_pass<KIND, PREC>(sh, cnt, R0, R1, x, y, wr, wi, kappa, ar, ai, flush, seg);
+            __syncthreads();
             if (t < cnt) {
+                cplx v = cyc_total(flush, seg, cnt, t);
                 cplx* cc = Ccol + (j0 - pa0) + t;
-                if (rs == 0) *cc = mk(cr, ci);
-                else *cc = *cc + mk(cr, ci);
+                *cc = ps == 0 ? v : *cc + v;
             }
         }
 #pragma unroll
         for (int r = 0; r < 2; ++r)
-            if (t < Rn[r]) Crow[(rs + r) * R + t] = mk(ar[r], ai[r]);
+            if (t < (r ? R1 : R0)) Crow[128 * ps + 64 * r + t] = mk(ar[r], ai[r]);
+    }
+    if (swap) {
+        int i0 = 128 * nfull;
+        __syncthreads();
+        load_tile(sh, pv, pb0 + i0, rem, t);
+        for (int p0 = 0; p0 < na; p0 += 128) {
+            int left = na - p0;
+            int R0 = min(64, left), R1 = max(0, min(64, left - 64));
+            double x[2][3], y[2][3], wr[2], wi[2], ar[2] = {0.0, 0.0}, ai[2] = {0.0, 0.0};
+            load_rows(pa0 + p0, R0, R1, x, y, wr, wi);
+            __syncthreads();
+            cyc_pass<KIND, PREC>(sh, rem, R0, R1, x, y, wr, wi, kappa, ar, ai, flush, seg);
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                if (t < (r ? R1 : R0)) {
+                    cplx* cc = Ccol + p0 + 64 * r + t;
+                    *cc = npass == 0 ? mk(ar[r], ai[r]) : *cc + mk(ar[r], ai[r]);
+                }
+            }
+            __syncthreads();
+            if (t < rem) {
+                cplx v = cyc_total(flush, seg, rem, t);
+                cplx* cr = Crow + i0 + t;
+                *cr = p0 == 0 ? v : *cr + v;
+            }
+        }
     }
 }
 
