@@ -51,8 +51,11 @@ __device__ inline double rsq_nr(double x)
 
 // 1/r (principal r): (t - i Im s/(2t)) / |s|, t = sqrt((|s| + Re s)/2).
 // The FP32 forms use the hardware reciprocal square root directly.
-// With u = 1/|s| and v = 1/t from rsq_nr: |s| = |s|^2 u, t = h v
-// (h = (|s| + Re s)/2), 1/r = (t u, -Im s u v / 2); no division.
+// With u = 1/|s| from rsq_nr, h = |s| + Re s = |s|^2 u + Re s and
+// v = 1/sqrt(h): t = sqrt(1/2) h v and 1/(2t) = sqrt(1/2) v, so
+// 1/r = sqrt(1/2) (h u v, -Im s u v); no division.  The Laplace kernels
+// return 1/r without the factor sqrt(1/2), which the final pass applies once
+// per target.
 // s = (x - y).(x - y) from the FP64 differences dr + i di, started from the
 // first product (an accumulation started from zero costs a register copy per
 // evaluation: fma(a, b, +0) is not a * b when the product is -0).
@@ -95,10 +98,10 @@ struct Kernel<0, 0> {
         if (G && sr == 0.0 && si == 0.0) { gr = gi = 0.0; return; }
         double q = sr * sr + si * si;
         double u = rsq_nr(q);
-        double h = 0.5 * (q * u + sr);
-        double v = rsq_nr(h);
-        gr = (h * v) * u;
-        gi = -0.5 * si * (u * v);
+        double h = fma(q, u, sr);
+        double uv = u * rsq_nr(h);
+        gr = h * uv;
+        gi = -si * uv;
     }
 };
 template <>
@@ -110,10 +113,10 @@ struct Kernel<0, 1> {
         if (sr == 0.0f && si == 0.0f) { gr = gi = 0.0f; return; }
         float q = sr * sr + si * si;
         float u = __builtin_amdgcn_rsqf(q);
-        float h = 0.5f * (q * u + sr);
-        float v = __builtin_amdgcn_rsqf(h);
-        gr = (h * v) * u;
-        gi = -0.5f * si * (u * v);
+        float h = fmaf(q, u, sr);
+        float uv = u * __builtin_amdgcn_rsqf(h);
+        gr = h * uv;
+        gi = -si * uv;
     }
 };
 // e^{i kappa r}/r = e^{-kappa Im r}(cos + i sin)(kappa Re r) conj(r)/|s|, with
@@ -524,6 +527,7 @@ __global__ __launch_bounds__(64) void k_near3_final(const int* __restrict__ leav
         if (p < 0) continue;            // a source that is not a target
         cplx u = mk(0.0, 0.0);
         for (int e = e0; e < e1; ++e) u += mp.C[mp.coff[e] + (i - p0)];
+        if (KIND == 0) u = sqrt(0.5) * u;   // the Laplace kernels' omitted factor
         cplx f = ufar[i];
         if (KIND == 1) f = mk(-kappa * f.im, kappa * f.re);
         double vr = k * (u.re + f.re), vi = k * (u.im + f.im);
