@@ -314,7 +314,7 @@ __device__ inline void tile_pair(const Tile& sh, int R, int C, bool self, const 
 // from zero, which reaches lane 63.  After C steps lane l (< 63) holds a last
 // segment of Y point l mod C, put in seg[l]; Y point j's sum is flush[j] plus
 // seg[j], seg[j + C], ... in that order.
-template <int KIND, int PREC>
+template <int KIND, int PREC, bool FULL>
 __device__ inline void cyc_pass(const Tile& ty, int C, int R0, int R1, const double (&x)[2][3],
                                 const double (&y)[2][3], const double (&wr)[2], const double (&wi)[2],
                                 double kappa, double (&ar)[2], double (&ai)[2], double2* flush, double2* seg)
@@ -332,22 +332,45 @@ __device__ inline void cyc_pass(const Tile& ty, int C, int R0, int R1, const dou
             sxi[d] = ty.xi[d][q];
         }
         T sr = (T)ty.sr[q], si = (T)ty.si[q];
+        if constexpr (FULL) {
+            // every lane holds two targets: the two evaluations run without
+            // a branch, so their dependency chains interleave
+            T gr[2], gi[2];
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            if (t < (r ? R1 : R0)) {
+            for (int r = 0; r < 2; ++r) {
                 double dr[3], di[3];
                 for (int d = 0; d < 3; ++d) {
                     dr[d] = x[r][d] - sxr[d];
                     di[d] = y[r][d] - sxi[d];
                 }
-                T gr, gi;
-                // distinct leaves: s != 0, so FP64 skips the zero test
-                if constexpr (PREC == 0) Kernel<KIND, PREC>::template eval<false>(dr, di, kappa, gr, gi);
-                else Kernel<KIND, PREC>::eval(dr, di, kappa, gr, gi);
-                rr[r].add2(gr, sr, -gi, si);
-                ri[r].add2(gr, si, gi, sr);
-                cr.add2(gr, fwr[r], -gi, fwi[r]);
-                ci.add2(gr, fwi[r], gi, fwr[r]);
+                if constexpr (PREC == 0) Kernel<KIND, PREC>::template eval<false>(dr, di, kappa, gr[r], gi[r]);
+                else Kernel<KIND, PREC>::eval(dr, di, kappa, gr[r], gi[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                rr[r].add2(gr[r], sr, -gi[r], si);
+                ri[r].add2(gr[r], si, gi[r], sr);
+                cr.add2(gr[r], fwr[r], -gi[r], fwi[r]);
+                ci.add2(gr[r], fwi[r], gi[r], fwr[r]);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                if (t < (r ? R1 : R0)) {
+                    double dr[3], di[3];
+                    for (int d = 0; d < 3; ++d) {
+                        dr[d] = x[r][d] - sxr[d];
+                        di[d] = y[r][d] - sxi[d];
+                    }
+                    T gr, gi;
+                    // distinct leaves: s != 0, so FP64 skips the zero test
+                    if constexpr (PREC == 0) Kernel<KIND, PREC>::template eval<false>(dr, di, kappa, gr, gi);
+                    else Kernel<KIND, PREC>::eval(dr, di, kappa, gr, gi);
+                    rr[r].add2(gr, sr, -gi, si);
+                    ri[r].add2(gr, si, gi, sr);
+                    cr.add2(gr, fwr[r], -gi, fwi[r]);
+                    ci.add2(gr, fwi[r], gi, fwr[r]);
+                }
             }
         }
         if (t == 0) {
@@ -425,7 +448,8 @@ __global__ __launch_bounds__(64) void k_near3_pair(const int* __restrict__ items
             __syncthreads();
             load_tile(sh, pv, j0, cnt, t);
             __syncthreads();
-            cyc_pass<KIND, PREC>(sh, cnt, R0, R1, x, y, wr, wi, kappa, ar, ai, flush, seg);
+            if (R1 == 64) cyc_pass<KIND, PREC, true>(sh, cnt, R0, R1, x, y, wr, wi, kappa, ar, ai, flush, seg);
+            else cyc_pass<KIND, PREC, false>(sh, cnt, R0, R1, x, y, wr, wi, kappa, ar, ai, flush, seg);
             __syncthreads();
             if (t < cnt) {
                 cplx v = cyc_total(flush, seg, cnt, t);
@@ -447,7 +471,8 @@ __global__ __launch_bounds__(64) void k_near3_pair(const int* __restrict__ items
             double x[2][3], y[2][3], wr[2], wi[2], ar[2] = {0.0, 0.0}, ai[2] = {0.0, 0.0};
             load_rows(pa0 + p0, R0, R1, x, y, wr, wi);
             __syncthreads();
-            cyc_pass<KIND, PREC>(sh, rem, R0, R1, x, y, wr, wi, kappa, ar, ai, flush, seg);
+            if (R1 == 64) cyc_pass<KIND, PREC, true>(sh, rem, R0, R1, x, y, wr, wi, kappa, ar, ai, flush, seg);
+            else cyc_pass<KIND, PREC, false>(sh, rem, R0, R1, x, y, wr, wi, kappa, ar, ai, flush, seg);
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 if (t < (r ? R1 : R0)) {
