@@ -314,7 +314,9 @@ __device__ inline void tile_pair(const Tile& sh, int R, int C, bool self, const 
 // from zero, which reaches lane 63.  After C steps lane l (< 63) holds a last
 // segment of Y point l mod C, put in seg[l]; Y point j's sum is flush[j] plus
 // seg[j], seg[j + C], ... in that order.
-template <int KIND, int PREC, bool FULL>
+// ZG keeps the test for s = 0 in the FP64 kernels (tiles of one leaf, which
+// may hold coincident points).
+template <int KIND, int PREC, bool FULL, bool ZG = false>
 __device__ inline void cyc_pass(const Tile& ty, int C, int R0, int R1, const double (&x)[2][3],
                                 const double (&y)[2][3], const double (&wr)[2], const double (&wi)[2],
                                 double kappa, double (&ar)[2], double (&ai)[2], double2* flush, double2* seg)
@@ -343,7 +345,7 @@ __device__ inline void cyc_pass(const Tile& ty, int C, int R0, int R1, const dou
                     dr[d] = x[r][d] - sxr[d];
                     di[d] = y[r][d] - sxi[d];
                 }
-                if constexpr (PREC == 0) Kernel<KIND, PREC>::template eval<false>(dr, di, kappa, gr[r], gi[r]);
+                if constexpr (PREC == 0) Kernel<KIND, PREC>::template eval<ZG>(dr, di, kappa, gr[r], gi[r]);
                 else Kernel<KIND, PREC>::eval(dr, di, kappa, gr[r], gi[r]);
             }
 #pragma unroll
@@ -364,7 +366,7 @@ __device__ inline void cyc_pass(const Tile& ty, int C, int R0, int R1, const dou
                     }
                     T gr, gi;
                     // distinct leaves: s != 0, so FP64 skips the zero test
-                    if constexpr (PREC == 0) Kernel<KIND, PREC>::template eval<false>(dr, di, kappa, gr, gi);
+                    if constexpr (PREC == 0) Kernel<KIND, PREC>::template eval<ZG>(dr, di, kappa, gr, gi);
                     else Kernel<KIND, PREC>::eval(dr, di, kappa, gr, gi);
                     rr[r].add2(gr, sr, -gi, si);
                     ri[r].add2(gr, si, gi, sr);
@@ -490,13 +492,17 @@ __global__ __launch_bounds__(64) void k_near3_pair(const int* __restrict__ items
     }
 }
 
-// Diagonal items (a = b): tile pairs (T, S) with T <= S of the leaf; both
-// rows and columns land in C[e].  The block first clears its region.
+// Diagonal items (a = b): tile pairs (T, S) with T <= S of the leaf's tiles
+// of 64; both rows and columns land in C[e].  A tile against itself takes the
+// half rotation, a pair of distinct tiles the cyclic travel (so a short last
+// tile costs as many steps as it has points).  The block first clears its
+// region.
 template <int KIND, int PREC>
 __global__ __launch_bounds__(64) void k_near3_diag(const int* __restrict__ items, Near3Map mp, TreeView tv,
                                                    PointsView pv, double kappa)
 {
     __shared__ Tile sh;
+    __shared__ double2 flush[64], seg[64];
     int e = items[blockIdx.x];
     int b = mp.row_of[e];
     int64_t n = pv.n;
@@ -519,16 +525,25 @@ __global__ __launch_bounds__(64) void k_near3_diag(const int* __restrict__ items
             __syncthreads();
             load_tile(sh, pv, j0, cnt, t);
             __syncthreads();
-            double cr, ci;
-            bool self = j0 == i0;
-            tile_pair<KIND, PREC>(sh, min(64, p1 - i0), cnt, self, x, y, wr, wi, kappa, ar, ai, cr, ci);
-            if (self) {
+            if (j0 == i0) {
+                double cr, ci;
+                tile_pair<KIND, PREC>(sh, min(64, p1 - i0), cnt, true, x, y, wr, wi, kappa, ar, ai, cr, ci);
                 ar += cr;   // the column sums of the same tile are this lane's own point
                 ai += ci;
-            } else if (t < cnt) {
-                // written by this wavefront only; earlier tiles' rows never touch it
-                cplx* cc = Cb + (j0 - p0) + t;
-                *cc = *cc + mk(cr, ci);
+            } else {
+                double xx[2][3] = {{x[0], x[1], x[2]}, {0.0, 0.0, 0.0}};
+                double yy[2][3] = {{y[0], y[1], y[2]}, {0.0, 0.0, 0.0}};
+                double wwr[2] = {wr, 0.0}, wwi[2] = {wi, 0.0}, aar[2] = {ar, 0.0}, aai[2] = {ai, 0.0};
+                cyc_pass<KIND, PREC, false, true>(sh, cnt, min(64, p1 - i0), 0, xx, yy, wwr, wwi, kappa, aar, aai,
+                                                  flush, seg);
+                ar = aar[0];
+                ai = aai[0];
+                __syncthreads();
+                if (t < cnt) {
+                    // written by this wavefront only; earlier tiles' rows never touch it
+                    cplx* cc = Cb + (j0 - p0) + t;
+                    *cc = *cc + cyc_total(flush, seg, cnt, t);
+                }
             }
         }
         if (tok) Cb[i - p0] = Cb[i - p0] + mk(ar, ai);
