@@ -1037,34 +1037,44 @@ __device__ inline cplx cpow_small(cplx z, int q)
     return r;
 }
 
-// The even and odd halves (in s) of sum_s yc[s] x_{s-n}, yc[s] = Y^n_{s-n, m}
-// (zero past s = 2n), x at xs[s].  Steps run in blocks of eight up to the
-// wavefront's largest 2n (nw, uniform) with no per-lane branch: a lane's
-// steps past 2n read finite entries of the next degrees and multiply them by
-// zero, so the block's loads issue together.  With the symmetries of
-// d^n(pi/2), Y_{m' -m} = (-1)^{n+m'} Y_{m' m} and Y_{m m'} = (-1)^{m-m'} Y_{m' m},
-// both orders +m and -m of both products follow from the two halves E, O:
-//   (Y^T x)_{+m} = E + O,  (Y^T x)_{-m} = E - O,
-//   (Y x)_{+m} = (-1)^{m+n} (E - O),  (Y x)_{-m} = (-1)^{m+n} (E + O).
+// A rotation of degree n over a folded row: with the symmetries of d^n(pi/2),
+// Y_{m' -m} = (-1)^{n+m'} Y_{m' m}, Y_{m m'} = (-1)^{m-m'} Y_{m' m} and so
+// Y_{-k, m} = (-1)^{n+m} Y_{k m},
+// the lane of order m >= 0 needs only V_k = x_k + (-1)^{n+m} x_{-k} (k > 0,
+// V_0 = x_0) and its column yc[k] = Y^n_{k m}, k = 0..n (zero past n).  With
+// E and O the sums over even and odd k,
+//   (Y^T x)_{+m} = E + O,          (Y^T x)_{-m} = (-1)^n (E - O),
+//   (Y x)_{+m} = (-1)^m (E - O),   (Y x)_{-m} = (-1)^{n+m} (E + O),
+// for n + 1 reads instead of 2n + 1.  Steps run in blocks of eight up to the
+// wavefront's largest degree nw (uniform) with no per-lane branch: a lane's
+// steps past n read finite entries of the next rows and multiply them by
+// zero, so the block's loads issue together.
 template <int PM>
-__device__ inline void pns_halves(const double (&yc)[2 * PM + 1], const cplx* xs, int nw, cplx& E, cplx& O)
+__device__ inline void pns_halves_v(const double (&yc)[PM + 1], const cplx* vs, int nw, cplx& E, cplx& O)
 {
-    // two accumulation chains, by the parity of s
     cplx a[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
 #pragma unroll
-    for (int s0 = 0; s0 <= 2 * PM; s0 += 8) {
-        if (s0 <= 2 * nw) {
+    for (int k0 = 0; k0 <= PM; k0 += 8) {
+        if (k0 <= nw) {
 #pragma unroll
-            for (int s = s0; s < s0 + 8 && s <= 2 * PM; ++s) {
-                cplx x = xs[s];
-                a[s & 1].re = fma(yc[s], x.re, a[s & 1].re);
-                a[s & 1].im = fma(yc[s], x.im, a[s & 1].im);
+            for (int k = k0; k < k0 + 8 && k <= PM; ++k) {
+                cplx x = vs[k];
+                a[k & 1].re = fma(yc[k], x.re, a[k & 1].re);
+                a[k & 1].im = fma(yc[k], x.im, a[k & 1].im);
             }
         }
     }
     E = a[0];
     O = a[1];
 }
+
+// Folded rows in the stage buffers: V with + (S) of degree n at
+// pns_vbase(n, 0), with - (D) at pns_vbase(n, 1), n + 1 entries each.  At a
+// step the lanes of a sixteen-lane quarter wave read at most twelve rows,
+// whose bases are distinct modulo 16 (2n + p), so their sixteen-byte reads
+// fall in distinct groups of four banks.
+__host__ __device__ constexpr int pns_vbase(int n, int p) { return 34 * n + 17 * p; }
+constexpr int kPnsBufV = 544;                 // pns_vbase(15, 1) + 16 <= 544
 
 // Phase tables of one pair: tEa[q + P] = (-i)^q e^{iqa}, tEb[q + P] = e^{iqb}
 // (|q| <= P), tR[i] = rho^-i (i <= P + 1), from this lane's prefetched
@@ -1120,7 +1130,7 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
                                                                  const cplx* __restrict__ mpole,
                                                                  cplx* __restrict__ local)
 {
-    __shared__ cplx buf[2][kPnsBuf];
+    __shared__ cplx buf[2][kPnsBufV];
     __shared__ cplx tEa[2][2 * PM + 1], tEb[2][2 * PM + 1], tR[2][PM + 2];
     int b = boxes[xcd_contiguous(blockIdx.x, nboxes)];
     int P = tv.P[tv.level[b]];
@@ -1131,18 +1141,30 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
     int m = t - n * (n + 1) / 2;
     bool on = n <= P;
     int gp = n * n + n + m, gm = n * n + n - m;   // coefficients (n, +m), (n, -m) in the expansions
-    int bn = pns_base(n), ip = bn + n + m, im = bn + n - m;   // and in the stage buffers
+    int bn = pns_base(n), ip = bn + n + m, im = bn + n - m;   // natural layout, for the coaxial step
+    // folded rows: this lane reads row V of its parity and writes entry m of both
+    int vr = pns_vbase(n, (n + m) & 1), vs0 = pns_vbase(n, 0) + m, vd0 = pns_vbase(n, 1) + m;
     bool two = on && m > 0;
-    double sg = ((m + n) & 1) ? -1.0 : 1.0;
+    double sg = ((m + n) & 1) ? -1.0 : 1.0, sgm = (m & 1) ? -1.0 : 1.0, sgn = (n & 1) ? -1.0 : 1.0;
     // the largest degree among this wavefront's lanes (uniform)
     int tw = min((t | 63), (P + 1) * (P + 2) / 2 - 1);
     int nw = (int)((sqrtf(8.0f * tw + 1.0f) - 1.0f) * 0.5f);
     while (nw * (nw + 1) / 2 > tw) --nw;
     while ((nw + 1) * (nw + 2) / 2 <= tw) ++nw;
     nw = __builtin_amdgcn_readfirstlane(nw);
-    double yc[2 * PM + 1];
+    double yc[PM + 1];   // Y^n_{k m}, k = 0..n
 #pragma unroll
-    for (int s = 0; s <= 2 * PM; ++s) yc[s] = (on && s <= 2 * n) ? g_pns_y[pns_ybase(n) + (m + n) * (2 * n + 1) + s] : 0.0;
+    for (int k = 0; k <= PM; ++k) yc[k] = (on && k <= n) ? g_pns_y[pns_ybase(n) + (m + n) * (2 * n + 1) + n + k] : 0.0;
+    // a lane's two values +m, -m into the folded rows (m = 0: V_0 = x_0 in both)
+    auto put = [&](cplx* B, cplx vp, cplx vm) {
+        if (m == 0) {
+            B[vs0] = vp;
+            B[vd0] = vp;
+        } else {
+            B[vs0] = vp + vm;
+            B[vd0] = vp - vm;
+        }
+    };
     double cn = on ? g_pns_c[gp] : 0.0;
     // coaxial factors Zh^m_{n n'} = (-1)^{n+m} (n+n')! / (c_n^m c_n'^m): stage
     // 3 divides by the source coefficient's own c, the coaxial step takes
@@ -1153,7 +1175,7 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
     cplx accp = mk(0.0, 0.0), accm = mk(0.0, 0.0);
     // every entry a stage may read stays finite: zero at the start, and the
     // degrees past a pair's source length are zeroed before the coaxial step
-    for (int i = t; i < kPnsBuf; i += blockDim.x) {
+    for (int i = t; i < kPnsBufV; i += blockDim.x) {
         buf[0][i] = mk(0.0, 0.0);
         buf[1][i] = mk(0.0, 0.0);
     }
@@ -1183,14 +1205,11 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
         // A: the previous pair's last stage (reads buf[qp], slot qp), then
         // this pair's first stage (writes X)
         if (k > k0 && on) {
-            pns_halves<PM>(yc, buf[qp] + bn, nw, E, O);
-            accp += (sg * (E - O)) * tEa[qp][P - m];
+            pns_halves_v<PM>(yc, buf[qp] + vr, nw, E, O);
+            accp += (sgm * (E - O)) * tEa[qp][P - m];
             accm += (sg * (E + O)) * tEa[qp][P + m];
         }
-        if (src_on) {
-            X[ip] = tEa[q][m + P] * (cn * mvp);
-            X[im] = tEa[q][P - m] * (cn * mvm);
-        }
+        if (src_on) put(X, tEa[q][m + P] * (cn * mvp), tEa[q][P - m] * (cn * mvm));
         cplx np = mk(0.0, 0.0), nm_ = mk(0.0, 0.0);
         if (k + 1 < k1) {
             if (on && n <= nxt.z) {
@@ -1202,19 +1221,17 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
         __syncthreads();
         // B: x1 = Y^T x0, x2 = e^{imb} x1
         if (src_on) {
-            pns_halves<PM>(yc, X + bn, min(nw, Ps), E, O);
-            Y[ip] = (E + O) * tEb[q][P + m];
-            Y[im] = (E - O) * tEb[q][P - m];
+            pns_halves_v<PM>(yc, X + vr, min(nw, Ps), E, O);
+            put(Y, (E + O) * tEb[q][P + m], (sgn * (E - O)) * tEb[q][P - m]);
         }
         __syncthreads();
         // C: x3 = Y x2, times rho^-n / c_n^m; degrees past Ps zeroed
         if (on) {
             cplx vp = mk(0.0, 0.0), vm = mk(0.0, 0.0);
             if (src_on) {
-                pns_halves<PM>(yc, Y + bn, min(nw, Ps), E, O);
-                double r = sg * icn;
-                vp = (r * (E - O)) * tR[q][n];
-                vm = (r * (E + O)) * tR[q][n];
+                pns_halves_v<PM>(yc, Y + vr, min(nw, Ps), E, O);
+                vp = ((sgm * icn) * (E - O)) * tR[q][n];
+                vm = ((sg * icn) * (E + O)) * tR[q][n];
             }
             X[ip] = vp;
             X[im] = vm;
@@ -1245,15 +1262,13 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
                 ++nn;
             }
             cplx z = tR[q][n + 1] * zsg;
-            Y[ip] = vp * z;
-            Y[im] = vm * z;
+            put(Y, vp * z, vm * z);
         }
         __syncthreads();
         // E: y1 = Y^T y0, y2 = e^{-imb} y1; the next pair's tables
         if (on) {
-            pns_halves<PM>(yc, Y + bn, nw, E, O);
-            X[ip] = (E + O) * tEb[q][P - m];
-            X[im] = (E - O) * tEb[q][P + m];
+            pns_halves_v<PM>(yc, Y + vr, nw, E, O);
+            put(X, (E + O) * tEb[q][P - m], (sgn * (E - O)) * tEb[q][P + m]);
         }
         if (k + 1 < k1) pns_tables(t, P, ka, kb, tEa[q ^ 1], tEb[q ^ 1], tR[q ^ 1]);
         __syncthreads();
@@ -1263,8 +1278,8 @@ __global__ __launch_bounds__(pns_threads<PM>(), 3) void k_l3d_m2l_pns(const int*
         mvm = nm_;
     }
     if (k1 > k0 && on) {
-        pns_halves<PM>(yc, buf[qp] + bn, nw, E, O);
-        accp += (sg * (E - O)) * tEa[qp][P - m];
+        pns_halves_v<PM>(yc, buf[qp] + vr, nw, E, O);
+        accp += (sgm * (E - O)) * tEa[qp][P - m];
         accm += (sg * (E + O)) * tEa[qp][P + m];
     }
     if (on) {
