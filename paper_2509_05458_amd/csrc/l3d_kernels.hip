@@ -1054,10 +1054,10 @@ __device__ inline void pns_halves_v(const double (&yc)[PM + 1], const cplx* vs, 
 {
     cplx a[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
 #pragma unroll
-    for (int k0 = 0; k0 <= PM; k0 += 8) {
+    for (int k0 = 0; k0 <= PM; k0 += 4) {
         if (k0 <= nw) {
 #pragma unroll
-            for (int k = k0; k < k0 + 8 && k <= PM; ++k) {
+            for (int k = k0; k < k0 + 4 && k <= PM; ++k) {
                 cplx x = vs[k];
                 a[k & 1].re = fma(yc[k], x.re, a[k & 1].re);
                 a[k & 1].im = fma(yc[k], x.im, a[k & 1].im);
