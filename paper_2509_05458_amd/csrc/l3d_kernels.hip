@@ -175,14 +175,22 @@ __device__ inline cplx reg_sum(const Vec3& x, int P, const cplx* __restrict__ C)
         cplx bp = z * ap, bm = z * am;
         cfma(acc, C[nm(m + 1, m)], bp);
         if (m > 0) cfma(acc, C[nm(m + 1, -m)], bm);
+        // the coefficients and constants of step n are loaded during step
+        // n - 1 (uniform: scalar registers), so no step waits on its loads
+        int n1 = min(m + 2, P);
+        double o = c_lodd[n1], f = c_lrr[n1 * kLT + m];
+        cplx kp = C[nm(n1, m)], km = C[nm(n1, -m)];
         for (int n = m + 2; n <= P; ++n) {
-            double o = c_lodd[n], f = c_lrr[n * kLT + m];
+            int nx = min(n + 1, P);
+            double o2 = c_lodd[nx], f2 = c_lrr[nx * kLT + m];
+            cplx kp2 = C[nm(nx, m)], km2 = C[nm(nx, -m)];
             cplx cp = (o * (z * bp) - r2 * ap) * f;
             cplx cm = (o * (z * bm) - r2 * am) * f;
-            cfma(acc, C[nm(n, m)], cp);
-            if (m > 0) cfma(acc, C[nm(n, -m)], cm);
+            cfma(acc, kp, cp);
+            if (m > 0) cfma(acc, km, cm);
             ap = bp; bp = cp;
             am = bm; bm = cm;
+            o = o2; f = f2; kp = kp2; km = km2;
         }
     }
     return acc;
