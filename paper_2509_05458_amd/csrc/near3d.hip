@@ -9,13 +9,15 @@
 // C[partner e] (columns), a diagonal item writes C[e].  A final pass adds, per
 // target, its entries' partials in list order, so results are reproducible.
 //
-// Inside an item a wavefront holds up to 64 targets (one per lane) and a tile
-// of up to 64 sources in LDS.  With L the larger of the two counts, at step s
-// lane l pairs its target with source (l + s) mod L: the row sum stays in the
-// lane and the source's column sum travels with the source, one lane down per
-// step, so after L steps lane l holds the column sum of source l.  A tile
-// against itself takes steps 1..L/2 only (at step L/2 just lanes l < L/2 when
-// L is even), which covers each unordered pair once.
+// Inside an item a wavefront holds targets in its lanes and a tile of up to
+// 64 sources in LDS, and the source's column sum travels with the source,
+// one lane down per step, while the row sums stay in the lanes.  Neighbour
+// items hold two rows of 64 targets per lane and travel cyclically: at step
+// s lane l pairs with source (s + l) mod C of a tile of C, so every lane is
+// busy at every step (cyc_pass).  Diagonal items take the leaf's tiles of 64
+// in pairs: a tile against itself by rotation with period L, steps 1..L/2
+// only (at step L/2 just lanes l < L/2 when L is even), which covers each
+// unordered pair once; two distinct tiles by cyclic travel.
 //
 // Precision: FP64, or MIXED (differences formed in FP64 and cast to FP32, the
 // kernel in FP32, each tile's sums accumulated in FP32 with Kahan compensation
