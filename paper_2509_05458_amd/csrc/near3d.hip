@@ -315,7 +315,9 @@ __device__ inline void tile_pair(const Tile& sh, int R, int C, bool self, const 
 // at step s is complete for Y point s and goes to flush[s]; lane 0 restarts
 // from zero, which reaches lane 63.  After C steps lane l (< 63) holds a last
 // segment of Y point l mod C, put in seg[l]; Y point j's sum is flush[j] plus
-// seg[j], seg[j + C], ... in that order.
+// seg[j], seg[j + C], ... in that order.  When C divides 64 the value leaving
+// lane 0 reaches lane 63, which pairs with the same Y point at the next step,
+// so nothing is flushed (flush[j] counts as zero).
 // ZG keeps the test for s = 0 in the FP64 kernels (tiles of one leaf, which
 // may hold coincident points).
 template <int KIND, int PREC, bool FULL, bool ZG = false>
@@ -329,6 +331,7 @@ __device__ inline void cyc_pass(const Tile& ty, int C, int R0, int R1, const dou
     Sum<T> rr[2], ri[2], cr, ci;
     T fwr[2] = {(T)wr[0], (T)wr[1]}, fwi[2] = {(T)wi[0], (T)wi[1]};
     int q = t % C;
+    bool wrap = (64 % C) == 0;
     for (int step = 0; step < C; ++step) {
         double sxr[3], sxi[3];
         for (int d = 0; d < 3; ++d) {
@@ -377,7 +380,7 @@ __device__ inline void cyc_pass(const Tile& ty, int C, int R0, int R1, const dou
                 }
             }
         }
-        if (t == 0) {
+        if (!wrap && t == 0) {
             flush[step] = make_double2(cr.val(), ci.val());
             cr = Sum<T>();
             ci = Sum<T>();
@@ -397,14 +400,14 @@ __device__ inline void cyc_pass(const Tile& ty, int C, int R0, int R1, const dou
 // Y point j's total after cyc_pass (the caller synchronises first).
 __device__ inline cplx cyc_total(const double2* flush, const double2* seg, int C, int j)
 {
-    cplx v = mk(flush[j].x, flush[j].y);
+    cplx v = (64 % C) == 0 ? mk(0.0, 0.0) : mk(flush[j].x, flush[j].y);
     for (int l = j; l < 64; l += C) v += mk(seg[l].x, seg[l].y);
     return v;
 }
 
 // Neighbour items (a < b): rows into C[e], columns into C[partner e].  b's
 // targets go through the lanes in passes of 128 (two rows of 64) against a's
-// sources in tiles of at most 64 (cyclic travel).  A remainder of r <= 64
+// sources in tiles of 64 and a last tile of the rest (cyclic travel).  A remainder of r <= 64
 // targets after the full passes runs with the roles swapped when that takes
 // fewer steps (ceil(na / 128) r < na): a's points in the lanes, 128 per pass,
 // the r targets travelling; so a leaf of 132 points costs 128 + 4 steps per
@@ -423,7 +426,7 @@ __global__ __launch_bounds__(64) void k_near3_pair(const int* __restrict__ items
     cplx* Crow = mp.C + mp.coff[e];
     cplx* Ccol = mp.C + mp.coff[ep];
     int nt = pb1 - pb0, na = pa1 - pa0;
-    int kc = (na + 63) / 64, Cs = (na + kc - 1) / kc;     // source tiles of Cs <= 64
+    const int Cs = 64;                                    // source tiles of 64, the last one shorter
     int nfull = nt / 128, rem = nt - 128 * nfull;
     bool swap = rem > 0 && rem <= 64 && ((na + 127) / 128) * rem < na;
     int npass = nfull + (rem > 0 && !swap ? 1 : 0);
